@@ -1,0 +1,153 @@
+"""FP64 oracle: RotorMap's brute-force mapping (§3.1) and its metrics.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+§3.1: windows of length N slide over the reference with a step; each window
+is encoded, forming the index.  A read's head (its first N letters) is
+encoded and its fidelity with every window is computed; the best-scoring
+windows are the candidate locations.
+
+Here: window starts j = 0, sigma, 2 sigma, ... up to G-N, so there are
+W = floor((G-N)/sigma) + 1 windows; F(r, j) = |<x_r|c_j>|^2 / (X_r C_j) with
+F = 0 when either vector is degenerate; the top-k list of a read is ordered by
+F descending, then by the window's position in the index ascending.
+
+Windows are processed in chunks to bound memory.  The top-k of a union of
+chunks is the top-k of the union of the chunks' top-k lists, so merging the
+per-chunk lists is the same selection as one pass over all windows.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import rope
+
+TIE_TAU = 1e-5  # fidelity gap under which two candidates count as tied
+
+
+def n_windows(G: int, N: int, stride: int = 1) -> int:
+    if G < N:
+        return 0
+    return (G - N) // stride + 1
+
+
+def window_starts(G: int, N: int, stride: int = 1) -> np.ndarray:
+    return np.arange(n_windows(G, N, stride), dtype=np.int64) * stride
+
+
+def window_letters(ref: np.ndarray, starts: np.ndarray, N: int) -> np.ndarray:
+    return ref[starts[:, None] + np.arange(N)[None, :]]
+
+
+def read_heads(seq: np.ndarray, offsets: np.ndarray, N: int) -> np.ndarray:
+    """First N letters of every read, [R, N]; a read shorter than N is an error."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    if np.any(np.diff(offsets) < N):
+        raise ValueError("a read is shorter than the window length")
+    return seq[offsets[:-1, None] + np.arange(N)[None, :]]
+
+
+def normalized_rows(C: np.ndarray, N: int):
+    """Normalise each row; degenerate rows become zero.  Returns (rows, sq_norms)."""
+    n2 = np.sum(np.abs(C) ** 2, axis=1)
+    ok = n2 >= rope.DEGENERATE_REL * N
+    out = np.zeros_like(C)
+    out[ok] = C[ok] / np.sqrt(n2[ok])[:, None]
+    return out, n2
+
+
+def fidelity_matrix(Xn: np.ndarray, Cn: np.ndarray) -> np.ndarray:
+    """F[r, j] = |<x_r|c_j>|^2 for unit (or zero) rows."""
+    return np.abs(np.conj(Xn) @ Cn.T) ** 2
+
+
+def topk_rows(F: np.ndarray, ids: np.ndarray, k: int):
+    """Per row, the k best (F desc, id asc); returns (ids [R,k], F [R,k])."""
+    order = np.lexsort((np.broadcast_to(ids, F.shape), -F), axis=1)[:, :k]
+    return np.take_along_axis(np.broadcast_to(ids, F.shape), order, 1), np.take_along_axis(F, order, 1)
+
+
+def map_reads(ref: np.ndarray, heads: np.ndarray, N: int, m: int = 32, k: int = 8,
+              stride: int = 1, schedule: str = "default", chunk: int = 65536,
+              window_range=None):
+    """Exact top-k windows of every read head by brute force over all windows.
+
+    Returns (idx [R,k] int64 window ids, F [R,k] float64).  `window_range`
+    restricts the scan to window ids [lo, hi) (used to time a bounded sample)."""
+    W = n_windows(ref.shape[0], N, stride)
+    lo, hi = (0, W) if window_range is None else window_range
+    Xn, _ = normalized_rows(rope.encode_many(heads, N, m, schedule), N)
+    R = Xn.shape[0]
+    best_i = np.full((R, 0), -1, dtype=np.int64)
+    best_f = np.zeros((R, 0))
+    for a in range(lo, hi, chunk):
+        b = min(hi, a + chunk)
+        ids = np.arange(a, b, dtype=np.int64)
+        Cn, _ = normalized_rows(rope.encode_many(window_letters(ref, ids * stride, N), N, m, schedule), N)
+        F = fidelity_matrix(Xn, Cn)
+        allF = np.concatenate([best_f, F], axis=1)
+        allI = np.concatenate([best_i, np.broadcast_to(ids, F.shape)], axis=1)
+        order = np.lexsort((allI, -allF), axis=1)[:, :k]
+        best_i = np.take_along_axis(allI, order, 1)
+        best_f = np.take_along_axis(allF, order, 1)
+    return best_i, best_f
+
+
+def pair_fidelity(ref: np.ndarray, head: np.ndarray, j: int, N: int, m: int = 32,
+                  stride: int = 1, schedule: str = "default") -> float:
+    """F(read head, window j), one pair at a time."""
+    s = j * stride
+    return rope.fidelity(rope.encode_raw(head, N, m, schedule),
+                         rope.encode_raw(ref[s:s + N], N, m, schedule), N)
+
+
+def pair_fidelities(ref: np.ndarray, heads: np.ndarray, idx: np.ndarray, N: int, m: int = 32,
+                    stride: int = 1, schedule: str = "default") -> np.ndarray:
+    """F(head r, window idx[r, i]) for every entry of idx [R, c] (entries < 0 give nan)."""
+    R, c = idx.shape
+    Xn, _ = normalized_rows(rope.encode_many(heads, N, m, schedule), N)
+    safe = np.clip(idx, 0, None).reshape(-1)
+    Cn, _ = normalized_rows(rope.encode_many(window_letters(ref, safe * stride, N), N, m, schedule), N)
+    F = np.abs(np.sum(np.conj(np.repeat(Xn, c, axis=0)) * Cn, axis=1)) ** 2
+    F = F.reshape(R, c)
+    F[idx < 0] = np.nan
+    return F
+
+
+def recall_at_k(got: np.ndarray, ref_idx: np.ndarray, ref_F: np.ndarray, got_true_F: np.ndarray,
+                tau: float = TIE_TAU) -> float:
+    """Mean over reads of |{j in got_r : j in oracle top-k or F(j) >= F_(k) - tau}| / k.
+
+    got [R,k] are a path's window ids; ref_idx/ref_F the oracle's top-k;
+    got_true_F the oracle's fidelity of each of `got`'s entries.  Duplicate ids
+    count once."""
+    R, k = ref_idx.shape
+    total = 0.0
+    for r in range(R):
+        seen = set()
+        hits = 0
+        kth = ref_F[r, k - 1]
+        oracle = set(int(v) for v in ref_idx[r])
+        for i in range(k):
+            j = int(got[r, i])
+            if j in seen or j < 0:
+                continue
+            seen.add(j)
+            if j in oracle or got_true_F[r, i] >= kth - tau:
+                hits += 1
+        total += hits / k
+    return total / R
+
+
+def same_up_to_ties(got: np.ndarray, ref_F: np.ndarray, got_true_F: np.ndarray,
+                    tau: float = TIE_TAU) -> np.ndarray:
+    """Per read: the path's list equals the oracle's rank by rank, up to swaps among
+    candidates whose oracle fidelities differ by at most tau, with no duplicates."""
+    R, k = got.shape
+    ok = np.ones(R, dtype=bool)
+    for r in range(R):
+        if len(set(int(v) for v in got[r])) != k or np.any(got[r] < 0):
+            ok[r] = False
+            continue
+        ok[r] = bool(np.all(np.abs(got_true_F[r] - ref_F[r]) <= tau))
+    return ok

@@ -1,0 +1,100 @@
+"""Pins of the FP64 mapping oracle: brute force on tiny inputs, exact substrings,
+tie order, recall metrics."""
+import numpy as np
+import pytest
+
+from oracle import mapping, rope
+from synth import make_reference, simulate_reads
+
+
+def _brute_topk(ref, head, N, m, k, stride):
+    W = mapping.n_windows(ref.shape[0], N, stride)
+    x = rope.encode_raw(head, N, m)
+    scored = []
+    for j in range(W):
+        c = rope.encode_raw(ref[j * stride:j * stride + N], N, m)
+        scored.append((-rope.fidelity(x, c, N), j))
+    scored.sort()
+    return [j for _, j in scored[:k]], [-f for f, _ in scored[:k]]
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_map_reads_matches_pairwise_brute_force(stride):
+    rng = np.random.default_rng(10)
+    ref = rng.integers(0, 4, 400).astype(np.uint8)
+    # a repeated block makes exact ties between identical windows
+    ref[300:340] = ref[100:140]
+    N, m, k = 30, 8, 6
+    heads = np.stack([ref[s:s + N] for s in (0, 100, 257)] + [rng.integers(0, 4, N).astype(np.uint8)])
+    idx, F = mapping.map_reads(ref, heads, N, m, k, stride, chunk=7)
+    for r in range(heads.shape[0]):
+        bi, bf = _brute_topk(ref, heads[r], N, m, k, stride)
+        assert list(idx[r]) == bi
+        assert np.allclose(F[r], bf, atol=1e-12)
+
+
+def test_exact_substring_scores_one_and_ties_order_by_index():
+    rng = np.random.default_rng(11)
+    ref = rng.integers(0, 4, 1000).astype(np.uint8)
+    ref[600:700] = ref[200:300]          # window 200 == window 600 for N <= 100
+    N = 80
+    heads = np.stack([ref[200:200 + N], ref[33:33 + N]])
+    idx, F = mapping.map_reads(ref, heads, N, 32, 4)
+    assert idx[0, 0] == 200 and idx[0, 1] == 600
+    assert abs(F[0, 0] - 1) < 1e-12 and abs(F[0, 1] - 1) < 1e-12
+    assert idx[1, 0] == 33 and abs(F[1, 0] - 1) < 1e-12
+
+
+def test_degenerate_window_scores_zero():
+    ref = np.concatenate([np.zeros(150, np.uint8), np.arange(150, dtype=np.uint8) % 4])
+    head = (np.arange(150) % 4).astype(np.uint8)
+    F = mapping.pair_fidelities(ref, head[None], np.array([[0, 150]]), 150)
+    assert F[0, 0] == 0.0 and abs(F[0, 1] - 1) < 1e-12
+
+
+def test_pair_fidelities_match_full_scan():
+    ref = make_reference(3000, seed=0, uniform=True)
+    reads = simulate_reads(ref, np.full(5, 150), 0.01, 0.005, 0.005, seed=3)
+    heads = mapping.read_heads(reads.seq, reads.offsets, 150)
+    idx, F = mapping.map_reads(ref, heads, 150, 32, 8, chunk=1000)
+    F2 = mapping.pair_fidelities(ref, heads, idx, 150)
+    assert np.allclose(F, F2, atol=1e-12)
+    for r in range(5):
+        assert abs(mapping.pair_fidelity(ref, heads[r], int(idx[r, 0]), 150) - F[r, 0]) < 1e-12
+
+
+def test_true_location_is_found_for_low_error_reads():
+    # Qualitative: on a uniform random reference reads at 2% error map to their
+    # true start (the paper reports all true matches on a random reference).
+    ref = make_reference(20_000, seed=0, uniform=True)
+    reads = simulate_reads(ref, np.full(40, 150), 0.01, 0.005, 0.005, seed=101)
+    heads = mapping.read_heads(reads.seq, reads.offsets, 150)
+    idx, _ = mapping.map_reads(ref, heads, 150, 32, 8)
+    assert np.mean(np.abs(idx[:, 0] - reads.truth) <= 3) >= 0.95
+
+
+def test_recall_and_tie_metrics():
+    ref_idx = np.array([[5, 7, 9]])
+    ref_F = np.array([[0.9, 0.5, 0.3]])
+    # exact
+    assert mapping.recall_at_k(ref_idx, ref_idx, ref_F, ref_F) == 1.0
+    # a tie member (F within tau of the 3rd) replacing the 3rd counts as correct
+    got = np.array([[5, 7, 11]])
+    assert mapping.recall_at_k(got, ref_idx, ref_F, np.array([[0.9, 0.5, 0.3 - 1e-6]])) == 1.0
+    assert mapping.same_up_to_ties(got, ref_F, np.array([[0.9, 0.5, 0.3 - 1e-6]]))[0]
+    # a clearly worse window does not
+    assert abs(mapping.recall_at_k(got, ref_idx, ref_F, np.array([[0.9, 0.5, 0.2]])) - 2 / 3) < 1e-12
+    assert not mapping.same_up_to_ties(got, ref_F, np.array([[0.9, 0.5, 0.2]]))[0]
+    # duplicates count once
+    dup = np.array([[5, 5, 7]])
+    assert abs(mapping.recall_at_k(dup, ref_idx, ref_F, np.array([[0.9, 0.9, 0.5]])) - 2 / 3) < 1e-12
+    # swapped order is not "same", unless tied
+    sw = np.array([[7, 5, 9]])
+    assert not mapping.same_up_to_ties(sw, ref_F, np.array([[0.5, 0.9, 0.3]]))[0]
+
+
+def test_window_count():
+    assert mapping.n_windows(20_000, 150, 1) == 19_851
+    assert mapping.n_windows(10_000_000, 150, 1) == 9_999_851
+    assert mapping.n_windows(1000, 100, 7) == 129
+    assert mapping.n_windows(99, 100, 1) == 0
