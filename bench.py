@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Benchmark of RotorMap's hot path on one MI355X.
+
+One step = one pass of the whole path over the batch: build the window index
+of the reference (rolling encoder), encode every read head, score every read
+against every window on MFMA with the fused top-k, merge, and rescore the
+candidates in FP32.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0).  Default workload: the precision workload
+(10 Mbp synthetic reference with 41% GC and 5% repeats, 100,000 reads of
+150 bp at 2% error, every stride-1 window, top-8 from 16 candidates
+rescored in FP32, FP16 embeddings).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("reads mapped/sec at ≥99% top-k recall vs FP64 oracle; window scores/sec")
+PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "fp8": 5000.0}   # dense MFMA, MI355X
+FLOPS_PER_SCORE = 1024  # two 256-long real dot products (Re and Im rows), 2 flops each
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="precision")
+    ap.add_argument("--precision", default=None, help="fp32 | fp16 | fp8 (default: the workload's)")
+    ap.add_argument("--reads", type=int, default=None, help="use only the first R reads")
+    ap.add_argument("--k-fetch", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
+    ap.add_argument("--cpu-reads", type=int, default=8)
+    ap.add_argument("--cpu-windows", type=int, default=1_000_000)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures one GPU's share of the "
+              "work (the multi-GPU sharding is described in DESIGN.md, not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2603_22245_amd import mapper, _lib as L
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    precision = args.precision or w.precision
+    k, k_fetch = w.k, max(w.k, args.k_fetch)
+
+    t0 = time.time()
+    ref = w.reference()
+    reads = w.reads(ref)
+    if args.reads is not None and args.reads < reads.n:
+        n = args.reads
+        reads = synth.Reads(reads.seq[:reads.offsets[n]], reads.offsets[:n + 1], reads.truth[:n])
+    R = reads.n
+    log(f"workload {w.name}: G={ref.shape[0]:,} R={R:,} generated in {time.time() - t0:.1f}s")
+
+    index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision=precision,
+                               reanchor=w.reanchor)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, R, k, k_fetch)
+    torch.cuda.synchronize()
+    W = index.n_windows
+    log(f"index: W={W:,} precision={precision}; buffers ready")
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ref_len = int(ref.shape[0])
+
+    def step():
+        ev[0].record()
+        L.rm_encode_reference(index.ref, ref_len, index.params, index.buf, index.buf.numel())
+        ev[1].record()
+        mapper.encode_reads(index, rb)
+        ev[2].record()
+        mapper.score_topk(index, rb, bufs)
+        ev[3].record()
+        mapper.rescore(index, rb, bufs)
+        ev[4].record()
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    parts = np.zeros(4)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        parts += [ev[j].elapsed_time(ev[j + 1]) for j in range(4)]
+        log(f"step {i + 1}/{args.steps}: {sum(ev[j].elapsed_time(ev[j + 1]) for j in range(4)):.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / args.steps
+    parts /= args.steps
+    value = R / (ms_per_step / 1e3)
+
+    top_idx = bufs.top_idx.cpu().numpy()
+    top_score = bufs.top_score.cpu().numpy()
+    cand_idx = bufs.cand_idx.cpu().numpy()
+    cand_score = bufs.cand_score.cpu().numpy()
+
+    # ---- accuracy against the FP64 oracle
+    acc = accuracy(w, ref, reads, top_idx, top_score, cand_idx, cand_score, k, R)
+
+    # ---- dominant kernel: the scoring product (+ its small merge), HIP events
+    score_s = parts[2] / 1e3
+    achieved = R * W * FLOPS_PER_SCORE / score_s / 1e12
+    peak = PEAK_TFLOPS[precision]
+    enc_bytes = W * (256 * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "score_topk_kernel (+merge_kernel)",
+                "algorithmic": f"{FLOPS_PER_SCORE} flops per (read, window) score x {R} x {W}"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "reads/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16", "fp8": "fp8e4m3"}[precision],
+        "data": "synthetic",
+        "config": {"workload": describe(w, precision, k, k_fetch, R), "reads": R, "windows": W,
+                   "window_len": w.window_len, "n_freq": w.n_freq, "stride": w.stride,
+                   "k": k, "k_fetch": k_fetch, "precision": precision},
+        "window_scores_per_s": float(f"{R * W / score_s:.4g}"),
+        "breakdown_ms": {"encode_reference": round(parts[0], 3), "encode_reads": round(parts[1], 3),
+                         "score_topk": round(parts[2], 3), "rescore": round(parts[3], 3)},
+        "encoder_gbs": round(enc_bytes / (parts[0] / 1e3) / 1e9, 1),
+        "accuracy": acc,
+        "roofline": roofline,
+    }
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+
+    if not args.no_fp32 and precision != "fp32":
+        out["fp32_path"] = fp32_path(w, ref, reads, k, k_fetch, value)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, ref, reads, W, args.cpu_reads, args.cpu_windows)
+    print(json.dumps(out), flush=True)
+
+
+def describe(w, precision, k, k_fetch, R):
+    return (f"{w.name}: {w.G / 1e6:g} Mbp synthetic reference ({int(w.gc * 100)}% GC, "
+            f"{int(w.repeat_frac * 100)}% repeats), {R:,} reads of {w.read_len} bp, N={w.window_len}, "
+            f"m={w.n_freq}, stride {w.stride}, {precision} index, top-{k} of {k_fetch} rescored in FP32")
+
+
+def accuracy(w, ref, reads, top_idx, top_score, cand_idx, cand_score, k, R):
+    """Recall@k and score errors on the oracle's stored sample; true-location rate."""
+    from oracle import mapping
+    res = {}
+    # true location: the read's sampled start within a few windows of the top-1
+    truth_win = reads.truth // w.stride
+    res["top1_within_8_of_truth"] = round(float(np.mean(np.abs(top_idx[:, 0] - truth_win) <= 8)), 5)
+    gold = os.path.join(ROOT, "tests", "golden", f"{w.name}_top16_sample64.npz")
+    if not os.path.exists(gold):
+        res["recall_at_k"] = None
+        return res
+    g = np.load(gold)
+    pick = g["reads"]
+    if pick.max() >= R:
+        res["recall_at_k"] = None
+        return res
+    o_idx, o_F = g["idx"][:, :k], g["F"][:, :k]
+    heads = mapping.read_heads(reads.seq, reads.offsets, w.window_len)[pick]
+    got = top_idx[pick]
+    got_F = mapping.pair_fidelities(ref, heads, got, w.window_len, w.n_freq, w.stride)
+    res["recall_at_k"] = round(mapping.recall_at_k(got, o_idx, o_F, got_F), 5)
+    res["exact_lists_up_to_ties"] = round(float(mapping.same_up_to_ties(got, o_F, got_F).mean()), 5)
+    res["rescore_max_abs_err"] = float(f"{np.nanmax(np.abs(top_score[pick] - got_F)):.3g}")
+    c = cand_idx[pick]
+    c_F = mapping.pair_fidelities(ref, heads, c, w.window_len, w.n_freq, w.stride)
+    err = np.abs(cand_score[pick] - c_F)
+    best = o_F[:, :1]
+    res["product_max_abs_err"] = float(f"{np.nanmax(err):.3g}")
+    res["product_max_rel_err_vs_best"] = float(f"{np.nanmax(err / np.maximum(c_F, best)):.3g}")
+    res["sample_reads"] = int(pick.shape[0])
+    return res
+
+
+def fp32_path(w, ref, reads, k, k_fetch, value_lowp):
+    """One timed step of the plain FP32 path (FP32 index and FP32 MFMA product)."""
+    import torch
+    from paper_2603_22245_amd import mapper
+    index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision="fp32",
+                               reanchor=w.reanchor)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
+    mapper.map_reads(index, rb, bufs)  # warm-up / first launch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mapper.map_reads(index, rb, bufs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    v = reads.n / dt
+    log(f"fp32 path: {dt * 1e3:.1f} ms per pass")
+    W = index.n_windows
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+    return {"value": round(v, 1), "unit": "reads/s", "ms_per_step": round(dt * 1e3, 2),
+            "tflops": round(reads.n * W * FLOPS_PER_SCORE / dt / 1e12, 2),
+            "speedup_of_low_precision": round(value_lowp / v, 2),
+            "note": "read encoding + FP32 MFMA product + top-k + FP32 rescore, prebuilt FP32 index"}
+
+
+def cpu_baseline(w, ref, reads, W, n_reads, n_windows):
+    """The FP64 oracle mapping a bounded sample: n_reads read heads against the first
+    n_windows windows (direct encoding + brute-force scan), scaled to all windows."""
+    from oracle import mapping
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    nw = min(n_windows, W)
+    heads = mapping.read_heads(reads.seq, reads.offsets, w.window_len)[:n_reads]
+    t = time.perf_counter()
+    mapping.map_reads(ref, heads, w.window_len, w.n_freq, w.k, w.stride, window_range=(0, nw))
+    dt = time.perf_counter() - t
+    v = n_reads / dt * (nw / W)
+    log(f"cpu baseline: {n_reads} reads x {nw:,} windows in {dt:.1f}s")
+    return {"value": float(f"{v:.4g}"), "unit": "reads/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_reads} read heads x first {nw:,} of {W:,} windows (FP64 encoding + "
+                      f"brute-force scan, {dt:.1f} s), scaled by {nw:,}/{W:,}",
+            "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

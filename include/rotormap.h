@@ -1,0 +1,167 @@
+/* rotormap.h -- C ABI of the RotorMap hot path on AMD MI355X (gfx950).
+ *
+ * What is computed (RotorMap paper, arXiv 2603.22245):
+ *  - §3 (the mapping problem): given a reference and reads, find for each read
+ *    the reference positions it most likely comes from;
+ *  - §3.1 (basic idea): windows of N letters slide over the reference with a
+ *    step; each window's RoPE encoding is stored in an index; each read's head
+ *    (its first N letters) is encoded; the fidelity of the head with every
+ *    window is computed (a matrix product at its core) and the best windows are
+ *    kept;
+ *  - §2.1-§2.3 (the encoding, tokens of one letter, s = 1): component (k, L) of
+ *    a string is the sum over the locations p of letter L of omega^(f_k p),
+ *    omega = exp(2 pi i / N), k = 1..m (§2.2 eq. mult-factor: f_k = k; §3.3 eq.
+ *    mult-factor-finetune: f_k = 2(k-1)/(m-1)+1), ordered (k-1)*4 + L as in the
+ *    D^loc form of §2.10, then normalised;
+ *  - §2.4: fidelity F = |<x|c>|^2 / (|x|^2 |c|^2);
+ *  - §3.4: the window encoding is updated letter by letter as the window slides
+ *    (rotate by omega^-f_k, remove the outgoing letter, add the incoming one).
+ *
+ * Conventions shared by every call:
+ *  - Letters are uint8 codes A,C,G,T = 0,1,2,3.  Any other code contributes no
+ *    token (it is skipped, as a letter of unknown identity with no weight).
+ *  - Every pointer named d_* is DEVICE memory owned by the caller.  The library
+ *    never allocates or frees device memory and keeps no state between calls.
+ *  - Calls that take `stream` (a hipStream_t; NULL = the null stream) only
+ *    enqueue work on it and return; results are ready once the stream is
+ *    synchronised.  Faults inside a kernel surface at that synchronisation.
+ *  - Every argument is validated on the host before anything is enqueued; a
+ *    call that returns anything but RM_OK has enqueued nothing.  A HIP launch
+ *    error after validation returns RM_EHIP.
+ *  - A window or read whose squared norm (before normalisation) is below
+ *    1e-4 * N in FP32 is degenerate (e.g. one letter repeated, or a period that
+ *    divides N, §3.3): it is stored as the zero vector and its fidelity with
+ *    anything is 0.
+ *  - Candidate lists are ordered by fidelity descending, then by window id
+ *    ascending.  Window id j is the window starting at reference position
+ *    j * stride.
+ */
+#ifndef ROTORMAP_H
+#define ROTORMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define RM_OK 0
+#define RM_EINVAL (-1)        /* a null pointer, a bad enum or an inconsistent argument */
+#define RM_ESIZE (-2)         /* a size out of range or a buffer that is too small */
+#define RM_EUNSUPPORTED (-3)  /* a parameter combination the kernels do not implement */
+#define RM_EHIP (-4)          /* a HIP runtime error when enqueuing */
+
+/* ---- enums --------------------------------------------------------------- */
+#define RM_FP32 0      /* embeddings stored as float32 */
+#define RM_FP16 1      /* embeddings stored as IEEE binary16, round to nearest even */
+#define RM_FP8_E4M3 2  /* embeddings stored as OCP FP8 e4m3 codes of v / 2^e (RNE;
+                          2^e the smallest power of two with max|v| / 2^e <= 448)
+                          plus one FP32 scale per window / per read chosen so
+                          that code * scale has unit norm */
+
+#define RM_SCHED_DEFAULT 0    /* f_k = k            (§2.2 eq. mult-factor) */
+#define RM_SCHED_FINETUNED 1  /* f_k = 2(k-1)/(m-1)+1 (§3.3 eq. mult-factor-finetune) */
+
+#define RM_DIM 32          /* supported number of factors m: 4*m = 128 complex components */
+#define RM_MAX_WINDOW 16384 /* largest supported N */
+#define RM_MAX_KFETCH 32   /* largest candidate list per read */
+
+/* Parameters of an index.  Plain data; zero-initialise and fill. */
+typedef struct rm_params {
+  int32_t window_len; /* N: letters per window and per read head, 1..RM_MAX_WINDOW */
+  int32_t stride;     /* window step (>= 1); window j starts at j * stride */
+  int32_t n_freq;     /* m; must be RM_DIM */
+  int32_t schedule;   /* RM_SCHED_* */
+  int32_t precision;  /* RM_FP32, RM_FP16 or RM_FP8_E4M3 */
+  int32_t reanchor;   /* window starts between two FP64 re-computations of the
+                         rolling state (>= 1), or 0: chosen by the library,
+                         at most 4096 */
+} rm_params;
+
+/* Descriptor of an index living in a caller-owned device buffer.  Filled by
+ * rm_encode_reference; the pointers point into that buffer.  Plain data: it may
+ * be copied, and stays valid while the buffer lives. */
+typedef struct rm_index {
+  rm_params p;
+  int64_t ref_len;     /* G, letters in the reference */
+  int64_t n_windows;   /* W = floor((G - N) / stride) + 1 */
+  void* d_emb;         /* [W][256] embeddings (re, im interleaved per component) */
+  float* d_scale;      /* [W] FP8 dequantisation scale per window (1.0 for FP32/FP16) */
+  float* d_norm2;      /* [W] squared norm of each window's vector before normalising */
+  double* d_phase64;   /* [N][m] complex omega^(f_k p), FP64 (re, im) */
+  float* d_phase32;    /* [N][m] the same rounded to FP32 */
+  float* d_step32;     /* [m][4] FP32 omega^-f_k (re, im) and omega^(f_k (N-1)) (re, im) */
+} rm_index;
+
+/* Human-readable text of a status code (static storage). */
+const char* rm_status_str(int status);
+
+/* Library version string (static storage). */
+const char* rm_version(void);
+
+/* Number of windows for (ref_len, p), or -1 if the parameters are invalid. */
+int64_t rm_num_windows(int64_t ref_len, const rm_params* p);
+
+/* Bytes of the device buffer rm_encode_reference needs, or 0 if the
+ * parameters are invalid.  The buffer must be 256-byte aligned. */
+size_t rm_index_bytes(int64_t ref_len, const rm_params* p);
+
+/* Build the index (§3.1) of the reference d_ref[0..ref_len) into d_buf:
+ * FP64 angle tables, then every window's encoding by the rolling update of
+ * §3.4 in FP32 with an FP64 re-computation every p->reanchor starts,
+ * normalised and stored in p->precision.  Fills *out.
+ * Errors: RM_EINVAL (null pointer, bad enum), RM_ESIZE (ref_len < N, N out of
+ * range, stride < 1, buf_bytes < rm_index_bytes, more than 2^31-1 windows),
+ * RM_EUNSUPPORTED (n_freq != RM_DIM). */
+int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
+                        void* d_buf, size_t buf_bytes, rm_index* out, void* stream);
+
+/* Bytes of the read-embedding buffer for n_reads reads: [n_reads][2][256]
+ * elements of the index precision (row 2r holds (Re x, Im x) per component and
+ * row 2r+1 holds (-Im x, Re x), so that one real product of the two rows with a
+ * window row gives Re and Im of <x|c>).  0 if invalid. */
+size_t rm_read_emb_bytes(int32_t n_reads, const rm_params* p);
+
+/* Encode the head (first N letters) of every read (§3.1): FP64 direct sum,
+ * normalised, stored in the index precision.  Read r is
+ * d_seq[d_off[r] .. d_off[r+1]) (d_off: n_reads+1 int64, device).  A read
+ * shorter than N is encoded as the zero vector.  d_read_scale [n_reads]
+ * receives the FP8 scale per read (1.0 otherwise); it may be NULL unless the
+ * precision is FP8.  Errors: RM_EINVAL, RM_ESIZE (n_reads < 1). */
+int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
+                    int32_t n_reads, void* d_read_emb, float* d_read_scale, void* stream);
+
+/* Bytes of the workspace rm_score_topk needs. 0 if invalid. */
+size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_fetch);
+
+/* Score every read against every window and keep, per read, the k_fetch best
+ * windows (§3.1: fidelities of the read's encoding with all index vectors as a
+ * matrix product, then the best locations).  The product runs on MFMA in the
+ * index precision with FP32 accumulation; the full score matrix is never
+ * stored.  Outputs [n_reads][k_fetch]: window ids (int32) and fidelities
+ * (float, computed from the stored embeddings).  Ties are broken by lower
+ * window id, exactly.  If W < k_fetch the tail is filled with id -1, score -1.
+ * d_read_scale may be NULL unless the precision is FP8.
+ * Errors: RM_EINVAL, RM_ESIZE (k_fetch outside 1..RM_MAX_KFETCH, ws too small). */
+int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
+                  int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx, float* d_cand_score,
+                  void* d_ws, size_t ws_bytes, void* stream);
+
+/* Rescore the candidates in FP32 and keep the k best (the refinement idea of
+ * §3.4 applied to the candidates): each candidate window's encoding and the
+ * read head's encoding are recomputed directly from the letters with the
+ * FP32 angle table (never from the stored low-precision index), F =
+ * |<x|c>|^2 / (X C) in FP32, sorted by (F desc, window id asc).  Candidates
+ * with id < 0 are skipped; missing entries are filled with id -1, score -1.
+ * Errors: RM_EINVAL, RM_ESIZE (k < 1 or k > k_fetch). */
+int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
+               const int64_t* d_off, int32_t n_reads, int32_t k_fetch,
+               const int32_t* d_cand_idx, int32_t k, int32_t* d_top_idx, float* d_top_score,
+               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROTORMAP_H */

@@ -22,7 +22,11 @@ import numpy as np
 
 from . import rope
 
-TIE_TAU = 1e-5  # fidelity gap under which two candidates count as tied
+TIE_TAU = 1e-5  # fidelity gap under which two candidates count as tied in metrics
+# Scores closer than this are equal for ranking: FP64 summation order (which
+# a matrix product may vary with a row's position in a batch) moves F by
+# ~1e-16, so equal windows must not be ordered by rounding noise.
+RANK_EPS = 1e-12
 
 
 def n_windows(G: int, N: int, stride: int = 1) -> int:
@@ -49,7 +53,7 @@ def read_heads(seq: np.ndarray, offsets: np.ndarray, N: int) -> np.ndarray:
 
 def normalized_rows(C: np.ndarray, N: int):
     """Normalise each row; degenerate rows become zero.  Returns (rows, sq_norms)."""
-    n2 = np.sum(np.abs(C) ** 2, axis=1)
+    n2 = np.sum(C.real ** 2 + C.imag ** 2, axis=1)
     ok = n2 >= rope.DEGENERATE_REL * N
     out = np.zeros_like(C)
     out[ok] = C[ok] / np.sqrt(n2[ok])[:, None]
@@ -61,10 +65,32 @@ def fidelity_matrix(Xn: np.ndarray, Cn: np.ndarray) -> np.ndarray:
     return np.abs(np.conj(Xn) @ Cn.T) ** 2
 
 
+def rank_order(F: np.ndarray, ids: np.ndarray) -> np.ndarray:
+    """Order of candidates by F descending, then id ascending, where scores that
+    differ by at most RANK_EPS from their neighbour in F order form one tie group."""
+    o = np.argsort(-F, kind="stable")
+    Fs = F[o]
+    group = np.cumsum(np.r_[True, (Fs[:-1] - Fs[1:]) > RANK_EPS])
+    return o[np.lexsort((ids[o], group))]
+
+
 def topk_rows(F: np.ndarray, ids: np.ndarray, k: int):
-    """Per row, the k best (F desc, id asc); returns (ids [R,k], F [R,k])."""
-    order = np.lexsort((np.broadcast_to(ids, F.shape), -F), axis=1)[:, :k]
-    return np.take_along_axis(np.broadcast_to(ids, F.shape), order, 1), np.take_along_axis(F, order, 1)
+    """Per row, the k best by `rank_order`; returns (ids [R,k], F [R,k]).
+
+    Every entry within RANK_EPS of the row's k-th largest F or above is a
+    candidate, so all members of a boundary tie group take part."""
+    R, n = F.shape
+    ids = np.broadcast_to(ids, F.shape)
+    kk = min(k, n)
+    kth = -np.partition(-F, kk - 1, axis=1)[:, kk - 1]
+    out_i = np.empty((R, kk), dtype=np.int64)
+    out_f = np.empty((R, kk))
+    for r in range(R):
+        cand = np.nonzero(F[r] >= kth[r] - RANK_EPS)[0]
+        order = rank_order(F[r, cand], ids[r, cand])[:kk]
+        out_i[r] = ids[r, cand[order]]
+        out_f[r] = F[r, cand[order]]
+    return out_i, out_f
 
 
 def map_reads(ref: np.ndarray, heads: np.ndarray, N: int, m: int = 32, k: int = 8,
@@ -87,9 +113,7 @@ def map_reads(ref: np.ndarray, heads: np.ndarray, N: int, m: int = 32, k: int = 
         F = fidelity_matrix(Xn, Cn)
         allF = np.concatenate([best_f, F], axis=1)
         allI = np.concatenate([best_i, np.broadcast_to(ids, F.shape)], axis=1)
-        order = np.lexsort((allI, -allF), axis=1)[:, :k]
-        best_i = np.take_along_axis(allI, order, 1)
-        best_f = np.take_along_axis(allF, order, 1)
+        best_i, best_f = topk_rows(allF, allI, k)
     return best_i, best_f
 
 

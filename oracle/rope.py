@@ -138,10 +138,11 @@ def encode_many(strings: np.ndarray, N: int, m: int = 32, schedule: str = "defau
     strings = np.asarray(strings)
     B, n = strings.shape
     E = unit_phases(N, m, np.arange(n), schedule)       # [n, m]
+    Er, Ei = np.ascontiguousarray(E.real), np.ascontiguousarray(E.imag)
     out = np.empty((B, m, N_LETTERS), dtype=np.complex128)
     for L in range(N_LETTERS):
         ind = (strings == L).astype(np.float64)          # [B, n]
-        out[:, :, L] = (ind @ E.real) + 1j * (ind @ E.imag)
+        out[:, :, L] = (ind @ Er) + 1j * (ind @ Ei)
     return out.reshape(B, m * N_LETTERS)
 
 

@@ -1,0 +1,185 @@
+// Host side of the C ABI: argument validation (always before anything is
+// enqueued), the layout of the caller's index buffer, and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include "rm_internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool params_ok(const rm_params* p, int* why) {
+  if (p == nullptr) return (*why = RM_EINVAL), false;
+  if (p->n_freq != RM_DIM) return (*why = RM_EUNSUPPORTED), false;
+  if (p->schedule != RM_SCHED_DEFAULT && p->schedule != RM_SCHED_FINETUNED)
+    return (*why = RM_EINVAL), false;
+  if (p->precision != RM_FP32 && p->precision != RM_FP16 && p->precision != RM_FP8_E4M3)
+    return (*why = RM_EINVAL), false;
+  if (p->window_len < 1 || p->window_len > RM_MAX_WINDOW) return (*why = RM_ESIZE), false;
+  if (p->stride < 1) return (*why = RM_ESIZE), false;
+  if (p->reanchor < 0) return (*why = RM_ESIZE), false;
+  return true;
+}
+
+int64_t windows_of(int64_t ref_len, const rm_params* p) {
+  if (ref_len < p->window_len) return -1;
+  return (ref_len - p->window_len) / p->stride + 1;
+}
+
+struct Layout {
+  size_t emb, scale, norm2, phase64, phase32, step32, total;
+};
+
+Layout layout(int64_t W, const rm_params* p) {
+  Layout L{};
+  size_t off = 0;
+  L.emb = off;
+  off = align_up(off + (size_t)W * rm::kReal * rm::elem_bytes(p->precision));
+  L.scale = off;
+  off = align_up(off + (size_t)W * sizeof(float));
+  L.norm2 = off;
+  off = align_up(off + (size_t)W * sizeof(float));
+  L.phase64 = off;
+  off = align_up(off + (size_t)p->window_len * p->n_freq * 2 * sizeof(double));
+  L.phase32 = off;
+  off = align_up(off + (size_t)p->window_len * p->n_freq * 2 * sizeof(float));
+  L.step32 = off;
+  off = align_up(off + (size_t)p->n_freq * 4 * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+int index_ok(const rm_index* idx) {
+  if (idx == nullptr) return RM_EINVAL;
+  int why = RM_OK;
+  if (!params_ok(&idx->p, &why)) return why;
+  int64_t W = windows_of(idx->ref_len, &idx->p);
+  if (W < 1 || W != idx->n_windows) return RM_EINVAL;
+  if (!idx->d_emb || !idx->d_scale || !idx->d_norm2 || !idx->d_phase64 || !idx->d_phase32 ||
+      !idx->d_step32)
+    return RM_EINVAL;
+  return RM_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? RM_OK : RM_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* rm_status_str(int status) {
+  switch (status) {
+    case RM_OK: return "ok";
+    case RM_EINVAL: return "invalid argument";
+    case RM_ESIZE: return "size out of range or buffer too small";
+    case RM_EUNSUPPORTED: return "unsupported parameters";
+    case RM_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* rm_version(void) { return "rotormap-gfx950 0.1"; }
+
+int64_t rm_num_windows(int64_t ref_len, const rm_params* p) {
+  int why = RM_OK;
+  if (!params_ok(p, &why)) return -1;
+  return windows_of(ref_len, p);
+}
+
+size_t rm_index_bytes(int64_t ref_len, const rm_params* p) {
+  int why = RM_OK;
+  if (!params_ok(p, &why)) return 0;
+  int64_t W = windows_of(ref_len, p);
+  if (W < 1 || W > INT32_MAX) return 0;
+  return layout(W, p).total;
+}
+
+int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p, void* d_buf,
+                        size_t buf_bytes, rm_index* out, void* stream) {
+  int why = RM_OK;
+  if (!params_ok(p, &why)) return why;
+  if (d_ref == nullptr || d_buf == nullptr || out == nullptr) return RM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(d_buf) % kAlign != 0) return RM_EINVAL;
+  int64_t W = windows_of(ref_len, p);
+  if (W < 1 || W > INT32_MAX) return RM_ESIZE;
+  Layout L = layout(W, p);
+  if (buf_bytes < L.total) return RM_ESIZE;
+
+  uint8_t* base = static_cast<uint8_t*>(d_buf);
+  rm_index idx{};
+  idx.p = *p;
+  idx.ref_len = ref_len;
+  idx.n_windows = W;
+  idx.d_emb = base + L.emb;
+  idx.d_scale = reinterpret_cast<float*>(base + L.scale);
+  idx.d_norm2 = reinterpret_cast<float*>(base + L.norm2);
+  idx.d_phase64 = reinterpret_cast<double*>(base + L.phase64);
+  idx.d_phase32 = reinterpret_cast<float*>(base + L.phase32);
+  idx.d_step32 = reinterpret_cast<float*>(base + L.step32);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = hip_status(rm::launch_tables(*p, idx.d_phase64, idx.d_phase32, idx.d_step32, s));
+  if (st != RM_OK) return st;
+  st = hip_status(rm::launch_encode_reference(d_ref, W, *p, idx.d_phase64, idx.d_step32, idx.d_emb,
+                                              idx.d_scale, idx.d_norm2, s));
+  if (st != RM_OK) return st;
+  *out = idx;
+  return RM_OK;
+}
+
+size_t rm_read_emb_bytes(int32_t n_reads, const rm_params* p) {
+  int why = RM_OK;
+  if (!params_ok(p, &why) || n_reads < 1) return 0;
+  return (size_t)n_reads * 2 * rm::kReal * rm::elem_bytes(p->precision);
+}
+
+int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
+                    int32_t n_reads, void* d_read_emb, float* d_read_scale, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_seq == nullptr || d_off == nullptr || d_read_emb == nullptr) return RM_EINVAL;
+  if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
+  if (n_reads < 1) return RM_ESIZE;
+  return hip_status(rm::launch_encode_reads(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
+                                            d_read_emb, d_read_scale,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_fetch) {
+  if (index_ok(idx) != RM_OK || n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return 0;
+  return rm::plan_score(idx->p.precision, idx->n_windows, n_reads, k_fetch).ws_bytes;
+}
+
+int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
+                  int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx, float* d_cand_score,
+                  void* d_ws, size_t ws_bytes, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_read_emb == nullptr || d_cand_idx == nullptr || d_cand_score == nullptr || d_ws == nullptr)
+    return RM_EINVAL;
+  if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
+  if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return RM_ESIZE;
+  rm::ScorePlan plan = rm::plan_score(idx->p.precision, idx->n_windows, n_reads, k_fetch);
+  if (ws_bytes < plan.ws_bytes) return RM_ESIZE;
+  return hip_status(rm::launch_score_topk(*idx, plan, d_read_emb, d_read_scale, n_reads, k_fetch,
+                                          d_cand_idx, d_cand_score, d_ws,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
+               const int64_t* d_off, int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx,
+               int32_t k, int32_t* d_top_idx, float* d_top_score, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_ref == nullptr || d_seq == nullptr || d_off == nullptr || d_cand_idx == nullptr ||
+      d_top_idx == nullptr || d_top_score == nullptr)
+    return RM_EINVAL;
+  if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || k < 1 || k > k_fetch)
+    return RM_ESIZE;
+  return hip_status(rm::launch_rescore(*idx, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, k,
+                                       d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

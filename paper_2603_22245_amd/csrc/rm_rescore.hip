@@ -1,0 +1,111 @@
+// FP32 rescore of each read's candidate windows.
+//
+// The candidates come from the low-precision product; their fidelities are
+// recomputed from the letters -- never from the stored index -- in FP32: the
+// read head's and each candidate window's RoPE vector are direct sums of the
+// FP32-rounded angle table (§2.1-§2.2), and F = |<x|c>|^2 / (X C) (§2.4).
+// The candidates are then ordered by (F desc, window id asc) and the k best
+// kept.  One wavefront per read; lane layout as in the encoders (lane l owns
+// factor l/2 and letters 2(l&1), 2(l&1)+1).
+#include "rm_internal.h"
+
+namespace rm {
+
+namespace {
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
+  uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
+  uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// FP32 direct sum over letters [0, n) for this lane's two components.
+__device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, int n,
+                                             const float2* __restrict__ phase32, int lane,
+                                             float2& a0, float2& a1) {
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+  a0 = make_float2(0.f, 0.f);
+  a1 = make_float2(0.f, 0.f);
+  for (int pb = 0; pb < n; pb += 64) {
+    int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
+    int cnt = min(64, n - pb);
+
+    for (int i = 0; i < cnt; ++i) {
+      int L = __builtin_amdgcn_readlane(mine, i);
+      float2 e = phase32[(int64_t)(pb + i) * kM + k];
+      a0.x += (L == L0) ? e.x : 0.f;
+      a0.y += (L == L0) ? e.y : 0.f;
+      a1.x += (L == L1) ? e.x : 0.f;
+      a1.y += (L == L1) ? e.y : 0.f;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void rescore_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride,
+    const float2* __restrict__ phase32, const uint8_t* __restrict__ seq,
+    const int64_t* __restrict__ off, int32_t R, int k_fetch, const int32_t* __restrict__ cand,
+    int k, int32_t* __restrict__ top_idx, float* __restrict__ top_score) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
+  if (len >= N) direct_sum32(seq + start, N, phase32, lane, x0, x1);
+  float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
+  const bool xdeg = X < kDegenerateRel * (float)N;
+
+  // lane e (< k_fetch) ends up holding candidate e's key
+  uint64_t key = 0;
+  for (int e = 0; e < k_fetch; ++e) {
+    int32_t j = cand[r * k_fetch + e];
+    if (j < 0 || j >= W) continue;  // uniform per wavefront
+    float2 c0, c1;
+    direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
+    float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+    // <x|c> = sum conj(x) c
+    float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
+    float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
+    bool deg = xdeg || C < kDegenerateRel * (float)N;
+    float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+    if (lane == e) {
+      uint32_t hi = __float_as_uint(F) + 1u;
+      key = ((uint64_t)hi << 32) | (0xffffffffu - (uint32_t)j);
+    }
+  }
+  // bitonic sort of the 64 lanes' keys, descending (empty keys are 0)
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+    for (int d = kk >> 1; d > 0; d >>= 1) {
+      uint64_t other = shfl_xor64(key, d);
+      bool desc_block = (lane & kk) == 0;
+      bool lower = (lane & d) == 0;
+      uint64_t mx = key > other ? key : other;
+      uint64_t mn = key > other ? other : key;
+      key = (lower == desc_block) ? mx : mn;
+    }
+  }
+  if (lane < k) {
+    uint32_t hi = (uint32_t)(key >> 32);
+    top_idx[r * k + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
+    top_score[r * k + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
+                          const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                          const int32_t* cand_idx, int32_t k, int32_t* top_idx, float* top_score,
+                          hipStream_t s) {
+  unsigned blocks = (unsigned)(((int64_t)n_reads + 3) / 4);
+  hipLaunchKernelGGL(rescore_kernel, dim3(blocks), dim3(256), 0, s, ref, idx.n_windows,
+                     idx.p.window_len, idx.p.stride, reinterpret_cast<const float2*>(idx.d_phase32),
+                     seq, off, n_reads, k_fetch, cand_idx, k, top_idx, top_score);
+  return hipGetLastError();
+}
+
+}  // namespace rm

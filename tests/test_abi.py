@@ -1,0 +1,117 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad
+arguments on the host before enqueuing anything (no GPU needed)."""
+import ctypes
+
+import pytest
+
+from paper_2603_22245_amd import _lib as L
+
+
+def test_library_exports_every_declared_function():
+    lib = L.lib()
+    names = L.header_functions()
+    assert {"rm_encode_reference", "rm_encode_reads", "rm_score_topk", "rm_rescore"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings_and_version():
+    assert L.status_str(L.RM_OK) == "ok"
+    for s in (L.RM_EINVAL, L.RM_ESIZE, L.RM_EUNSUPPORTED, L.RM_EHIP):
+        assert L.status_str(s) not in ("ok", "unknown status")
+    assert "gfx950" in L.rm_version()
+
+
+def test_window_counts_and_sizes():
+    p = L.make_params(150, 1, 32, "default", "fp16")
+    assert L.rm_num_windows(20_000, p) == 19_851
+    assert L.rm_num_windows(149, p) == -1
+    assert L.rm_index_bytes(20_000, p) >= 19_851 * 256 * 2
+    p8 = L.make_params(150, 1, 32, "default", "fp8")
+    p32 = L.make_params(150, 1, 32, "default", "fp32")
+    assert L.rm_index_bytes(10**7, p8) < L.rm_index_bytes(10**7, p) < L.rm_index_bytes(10**7, p32)
+    assert L.rm_read_emb_bytes(10, p) == 10 * 2 * 256 * 2
+    assert L.rm_read_emb_bytes(0, p) == 0
+    p3 = L.make_params(150, 7, 32, "default", "fp16")
+    assert L.rm_num_windows(1000, p3) == (1000 - 150) // 7 + 1
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n_freq", 16, L.RM_EUNSUPPORTED),
+    ("window_len", 0, L.RM_ESIZE),
+    ("window_len", L.RM_MAX_WINDOW + 1, L.RM_ESIZE),
+    ("stride", 0, L.RM_ESIZE),
+    ("precision", 7, L.RM_EINVAL),
+    ("schedule", 5, L.RM_EINVAL),
+    ("reanchor", -1, L.RM_ESIZE),
+])
+def test_bad_params_rejected(field, value, status):
+    p = L.make_params(150, 1, 32, "default", "fp16")
+    setattr(p, field, value)
+    assert L.rm_index_bytes(20_000, p) == 0
+    out = L.rm_index()
+    st = L.lib().rm_encode_reference(0x1000, 20_000, ctypes.byref(p), 0x10000, 1 << 30,
+                                     ctypes.byref(out), None)
+    assert st == status
+
+
+def test_encode_reference_validation():
+    lib = L.lib()
+    p = L.make_params(150, 1, 32, "default", "fp16")
+    out = L.rm_index()
+    need = L.rm_index_bytes(20_000, p)
+    enc = lambda ref, n, buf, nb: lib.rm_encode_reference(ref, n, ctypes.byref(p), buf, nb,
+                                                          ctypes.byref(out), None)
+    assert enc(None, 20_000, 0x10000, need) == L.RM_EINVAL
+    assert enc(0x1000, 20_000, None, need) == L.RM_EINVAL
+    assert enc(0x1000, 20_000, 0x10010, need) == L.RM_EINVAL      # misaligned buffer
+    assert enc(0x1000, 20_000, 0x10000, need - 1) == L.RM_ESIZE
+    assert enc(0x1000, 149, 0x10000, need) == L.RM_ESIZE           # shorter than a window
+    assert lib.rm_encode_reference(0x1000, 20_000, None, 0x10000, need, ctypes.byref(out), None) \
+        == L.RM_EINVAL
+    huge = L.make_params(1, 1, 32, "default", "fp8")
+    assert L.rm_index_bytes(2**31 + 5, huge) == 0                  # more than 2^31-1 windows
+
+
+def _fake_index(precision="fp16", W_ref=20_000):
+    p = L.make_params(150, 1, 32, "default", precision)
+    idx = L.rm_index()
+    idx.p = p
+    idx.ref_len = W_ref
+    idx.n_windows = L.rm_num_windows(W_ref, p)
+    for f in ("d_emb", "d_scale", "d_norm2", "d_phase64", "d_phase32", "d_step32"):
+        setattr(idx, f, 0x100000)
+    return idx
+
+
+def test_read_score_rescore_validation():
+    lib = L.lib()
+    idx = _fake_index()
+    R = ctypes.byref
+    # encode reads
+    assert lib.rm_encode_reads(None, 1, 1, 10, 1, 1, None) == L.RM_EINVAL
+    assert lib.rm_encode_reads(R(idx), None, 1, 10, 1, 1, None) == L.RM_EINVAL
+    assert lib.rm_encode_reads(R(idx), 1, 1, 0, 1, 1, None) == L.RM_ESIZE
+    bad = _fake_index()
+    bad.n_windows += 1                                             # inconsistent descriptor
+    assert lib.rm_encode_reads(R(bad), 1, 1, 10, 1, 1, None) == L.RM_EINVAL
+    idx8 = _fake_index("fp8")
+    assert lib.rm_encode_reads(R(idx8), 1, 1, 10, 1, None, None) == L.RM_EINVAL  # scale needed
+    # score
+    ws = L.rm_score_workspace_bytes(idx, 100, 8)
+    assert ws > 0
+    assert L.rm_score_workspace_bytes(idx, 100, 0) == 0
+    assert L.rm_score_workspace_bytes(idx, 100, L.RM_MAX_KFETCH + 1) == 0
+    sc = lambda i, n, kf, nb: lib.rm_score_topk(R(i), 1, 1, n, kf, 1, 1, 1, nb, None)
+    assert sc(idx, 100, 8, ws - 1) == L.RM_ESIZE
+    assert sc(idx, 100, 0, ws) == L.RM_ESIZE
+    assert sc(idx, 100, 33, ws) == L.RM_ESIZE
+    assert sc(idx, 0, 8, ws) == L.RM_ESIZE
+    assert lib.rm_score_topk(R(idx), None, 1, 100, 8, 1, 1, 1, ws, None) == L.RM_EINVAL
+    assert lib.rm_score_topk(R(idx8), 1, None, 100, 8, 1, 1, 1, 1 << 30, None) == L.RM_EINVAL
+    # rescore
+    rs = lambda n, kf, k: lib.rm_rescore(R(idx), 1, 1, 1, n, kf, 1, k, 1, 1, None)
+    assert rs(10, 8, 9) == L.RM_ESIZE                              # k > k_fetch
+    assert rs(10, 8, 0) == L.RM_ESIZE
+    assert rs(0, 8, 8) == L.RM_ESIZE
+    assert lib.rm_rescore(R(idx), None, 1, 1, 10, 8, 1, 8, 1, 1, None) == L.RM_EINVAL

@@ -1,0 +1,324 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Sizes: the plain workload (20,000 bp uniform reference, 200 reads of 150 bp)
+spans many 32-window tiles, several window chunks and a ragged tail
+(W = 19,851); other cases cover strides, the fine-tuned schedule, long
+re-anchor segments and the edge cases."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mapping, rope
+from tests.gpu_helpers import (emb_to_complex, fp8_bound, oracle_heads, oracle_windows,
+                               read_rows, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+PLAIN = synth.WORKLOADS["plain"]
+# Score tolerance of the low-precision product against the FP64 oracle.
+# FP32/FP16: |dF| <= tol * max(F, best F of the read).  FP8: |dF| <= 1e-2 in
+# fidelity units (F lies in [0, 1]); e4m3's 3 mantissa bits leave an absolute
+# error floor of a few 1e-3 on every score, which the relative form cannot
+# meet for reads whose best score is low.  The fraction of FP8 scores inside
+# the relative form is printed.
+TOL = {"fp32": 1e-5, "fp16": 1e-3, "fp8": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def plain_data():
+    ref = PLAIN.reference()
+    reads = PLAIN.reads(ref)
+    heads = mapping.read_heads(reads.seq, reads.offsets, 150)
+    return ref, reads, heads
+
+
+@pytest.fixture(scope="module")
+def plain_oracle(plain_data):
+    ref, reads, heads = plain_data
+    Cn, n2 = oracle_windows(ref, 150)
+    Xn, _ = oracle_heads(heads, 150)
+    F = np.abs(np.conj(Xn) @ Cn.T) ** 2          # [200, 19851]
+    return Cn, n2, Xn, F
+
+
+def _build(ref, precision, **kw):
+    from paper_2603_22245_amd import mapper
+    torch_cuda()
+    return mapper.build_index(ref, precision=precision, **kw)
+
+
+def _map(index, reads, k, k_fetch):
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
+    mapper.map_reads(index, rb, bufs)
+    torch.cuda.synchronize()
+    return rb, bufs
+
+
+def test_angle_tables_fp64():
+    torch = torch_cuda()
+    ref = synth.make_reference(1000, seed=1, uniform=True)
+    for sched in ("default", "finetuned"):
+        for N in (150, 37):
+            index = _build(ref, "fp32", window_len=N, schedule=sched)
+            torch.cuda.synchronize()
+            off = index.idx.d_phase64 - index.buf.data_ptr()
+            ph = index.buf[off: off + N * 32 * 16].view(torch.float64).cpu().numpy()
+            ph = ph[0::2] + 1j * ph[1::2]
+            want = rope.unit_phases(N, 32, np.arange(N), sched).reshape(-1)
+            assert np.max(np.abs(ph - want)) < 1e-14
+
+
+@pytest.mark.parametrize("N,stride,sched", [(150, 1, "default"), (150, 3, "default"),
+                                            (150, 1, "finetuned"), (32, 1, "default"),
+                                            (1000, 7, "default")])
+def test_rolling_encoder_fp32(N, stride, sched):
+    torch = torch_cuda()
+    ref = synth.make_reference(30_000, gc=0.45, repeat_frac=0.05, seed=7)
+    index = _build(ref, "fp32", window_len=N, stride=stride, schedule=sched)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    Cn, n2 = oracle_windows(ref, N, stride, schedule=sched)
+    assert got.shape == Cn.shape
+    ok = n2 >= 1e-3 * N                                   # far from degenerate
+    err = np.max(np.abs(got[ok] - Cn[ok]))
+    assert err < 5e-5, err
+    gn2 = index.norms2().cpu().numpy()
+    assert np.max(np.abs(gn2[ok] - n2[ok]) / n2[ok]) < 1e-4
+
+
+def test_rolling_drift_over_long_segments():
+    # 65,536 starts per FP64 re-anchor: the FP32 recurrence's error after the
+    # longest segment stays far below FP16 rounding of a unit vector.
+    torch = torch_cuda()
+    ref = synth.make_reference(140_000, seed=8, uniform=True)
+    index = _build(ref, "fp32", reanchor=65_536)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    Cn, n2 = oracle_windows(ref, 150)
+    err = np.abs(got - Cn).max(axis=1)
+    first = err[:1000].max()
+    last = err[64_000:65_536].max()
+    print(f"drift: max |d| first 1000 starts {first:.2e}, starts 64000-65535 {last:.2e}")
+    assert last < 2e-4
+    assert err[65_536] < 1e-5                               # re-anchored
+
+
+def test_letter_sum_identity_on_device():
+    # For integer factors sum_L c_{k,L} = 0 in every full window.
+    torch = torch_cuda()
+    ref = synth.make_reference(20_000, seed=9, uniform=True)
+    index = _build(ref, "fp32")
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch).reshape(-1, 32, 4)
+    assert np.max(np.abs(got.sum(axis=2))) < 5e-5
+
+
+@pytest.mark.parametrize("precision", ["fp16", "fp8"])
+def test_quantised_encodings(precision, plain_data, plain_oracle):
+    torch = torch_cuda()
+    ref, _, _ = plain_data
+    Cn, n2, _, _ = plain_oracle
+    index = _build(ref, precision)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    if precision == "fp16":
+        # half an FP16 ulp (2^-11 relative) plus the FP32 rolling error
+        assert np.all(np.abs(got.real - Cn.real) <= 2.0 ** -11 * np.abs(Cn.real) + 2e-5)
+        assert np.all(np.abs(got.imag - Cn.imag) <= 2.0 ** -11 * np.abs(Cn.imag) + 2e-5)
+    else:
+        scale = index.scales().cpu().numpy()
+        s = np.exp2(np.round(np.log2(scale)))[:, None]    # the power of two of the codes
+        nz = np.abs(got).sum(axis=1) > 0
+        # dequantised rows are unit length (norm folded into the FP32 scale)
+        assert np.max(np.abs(np.linalg.norm(got[nz], axis=1) - 1)) < 1e-5
+        assert np.max(np.abs(scale[nz] / s[nz, 0] - 1)) < 0.05
+        corr = 0.05
+        assert np.all(np.abs(got.real - Cn.real) <= fp8_bound(np.abs(Cn.real), s) + corr * np.abs(Cn.real))
+        assert np.all(np.abs(got.imag - Cn.imag) <= fp8_bound(np.abs(Cn.imag), s) + corr * np.abs(Cn.imag))
+        # the codes' power of two is the smallest bringing the largest component to <= 448
+        maxabs = np.maximum(np.abs(Cn.real), np.abs(Cn.imag)).max(axis=1)
+        s1 = s[:, 0]
+        okw = maxabs > 0
+        assert np.all(maxabs[okw] / s1[okw] <= 448 * (1 + 1e-5))
+        assert np.all(maxabs[okw] / s1[okw] > 224 * (1 - 1e-4))
+        # bytes equal torch's RNE cast of the oracle value, up to one code where
+        # the FP32 rolling value and the FP64 value straddle a rounding boundary
+        q = index.embeddings().cpu().numpy().astype(np.int32)
+        inter = np.empty((Cn.shape[0], 256))
+        inter[:, 0::2], inter[:, 1::2] = Cn.real, Cn.imag
+        import torch as T
+        want = T.from_numpy(np.clip(inter / s, -448, 448)).to(T.float8_e4m3fn).view(T.uint8)
+        want = want.numpy().astype(np.int32)
+        # signed ordinal of a code: codes adjacent in value differ by one
+        ord_g = np.where(q >> 7, -(q & 127), q & 127)
+        ord_w = np.where(want >> 7, -(want & 127), want & 127)
+        diff = np.abs(ord_g - ord_w)
+        print(f"fp8 codes: {np.mean(diff == 0):.6f} equal, {np.mean(diff == 1):.2e} one apart, "
+              f"max {diff.max()}")
+        assert diff.max() <= 1
+        assert np.mean(diff == 0) > 0.999
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp8"])
+def test_read_encoder(precision, plain_data):
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    index = _build(ref, precision)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    mapper.encode_reads(index, rb)
+    torch.cuda.synchronize()
+    re_row, im_row = read_rows(rb, precision, torch)
+    Xn, _ = oracle_heads(heads, 150)
+    want_re = np.empty((reads.n, 256))
+    want_re[:, 0::2], want_re[:, 1::2] = Xn.real, Xn.imag
+    want_im = np.empty((reads.n, 256))
+    want_im[:, 0::2], want_im[:, 1::2] = -Xn.imag, Xn.real
+    s = np.exp2(np.round(np.log2(rb.scale.cpu().numpy())))[:, None]
+
+    def bound(w):
+        if precision == "fp32":
+            return 1e-6
+        if precision == "fp16":
+            return 2.0 ** -11 * np.abs(w) + 1e-7
+        return fp8_bound(np.abs(w), s) + 0.05 * np.abs(w)   # plus the norm correction
+
+    assert np.all(np.abs(re_row - want_re) <= bound(want_re))
+    assert np.all(np.abs(im_row - want_im) <= bound(want_im))
+
+
+def _check_candidates(idx, score, F, tol, absolute=False):
+    R, kf = idx.shape
+    best = F.max(axis=1)
+    inside = []
+    for r in range(R):
+        ids = idx[r]
+        assert len(set(ids.tolist())) == kf and ids.min() >= 0
+        assert np.all(np.diff(score[r]) <= 0)             # sorted by the path's score
+        f_or = F[r, ids]
+        err = np.abs(score[r] - f_or)
+        rel_ok = err <= tol * np.maximum(f_or, best[r]) + 1e-7
+        inside.append(rel_ok)
+        assert np.all(err <= tol + 1e-7) if absolute else np.all(rel_ok), r
+    frac = float(np.mean(inside))
+    print(f"scores within {tol} x max(F, best F): {frac:.5f}; max |dF| "
+          f"{np.max(np.abs(score - np.take_along_axis(F, idx, 1))):.2e}")
+    return frac
+
+
+@pytest.mark.parametrize("precision,k_fetch", [("fp32", 8), ("fp16", 8), ("fp16", 16),
+                                               ("fp8", 16), ("fp8", 32), ("fp32", 32)])
+def test_score_topk_and_rescore(precision, k_fetch, plain_data, plain_oracle):
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    _, _, _, F = plain_oracle
+    index = _build(ref, precision)
+    k = 8
+    rb, bufs = _map(index, reads, k, k_fetch)
+    cidx = bufs.cand_idx.cpu().numpy()
+    csc = bufs.cand_score.cpu().numpy()
+    _check_candidates(cidx, csc, F, TOL[precision], absolute=precision == "fp8")
+    # oracle top-k_fetch and top-k with ties ordered by index
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    o_idx = order[:, :k]
+    o_F = np.take_along_axis(F, o_idx, 1)
+    cand_F = np.take_along_axis(F, cidx, 1)
+    rec_c = mapping.recall_at_k(cidx[:, :k], o_idx, o_F, cand_F[:, :k])
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    top_F = np.take_along_axis(F, tidx, 1)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, top_F)
+    exact = mapping.same_up_to_ties(tidx, o_F, top_F)
+    print(f"{precision} k_fetch={k_fetch}: candidate recall@8 {rec_c:.4f}, "
+          f"rescored recall@8 {rec:.4f}, exact lists {exact.mean():.4f}")
+    assert np.max(np.abs(tsc - top_F)) < 2e-6            # FP32 rescore vs FP64
+    if precision == "fp32":
+        assert exact.all()
+    else:
+        assert rec >= 0.99
+        assert exact.mean() >= 0.97
+
+
+def test_more_reads_than_one_tile_and_many_chunks():
+    torch = torch_cuda()
+    ref = synth.make_reference(60_000, gc=0.41, repeat_frac=0.05, seed=11)
+    reads = synth.simulate_reads(ref, np.full(700, 150), 0.01, 0.005, 0.005, seed=12)
+    heads = mapping.read_heads(reads.seq, reads.offsets, 150)
+    index = _build(ref, "fp16")
+    rb, bufs = _map(index, reads, 8, 16)
+    Cn, _ = oracle_windows(ref, 150)
+    Xn, _ = oracle_heads(heads, 150)
+    F = np.abs(np.conj(Xn) @ Cn.T) ** 2
+    _check_candidates(bufs.cand_idx.cpu().numpy(), bufs.cand_score.cpu().numpy(), F, TOL["fp16"])
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    o_idx = order[:, :8]
+    tidx = bufs.top_idx.cpu().numpy()
+    rec = mapping.recall_at_k(tidx, o_idx, np.take_along_axis(F, o_idx, 1),
+                              np.take_along_axis(F, tidx, 1))
+    assert rec >= 0.999
+
+
+def test_hamming_closed_form_on_device():
+    # N = m = 32 integer factors: the fidelity of equal-length strings is
+    # ((N - d)/N)^2 with d the Hamming distance (§1), exactly.
+    torch = torch_cuda()
+    rng = np.random.default_rng(13)
+    ref = rng.integers(0, 4, 4000).astype(np.uint8)
+    starts = rng.integers(0, 4000 - 32, 64)
+    ds = rng.integers(0, 12, 64)
+    seqs = []
+    for s, d in zip(starts, ds):
+        w = ref[s:s + 32].copy()
+        pos = rng.choice(32, d, replace=False)
+        w[pos] = (w[pos] + rng.integers(1, 4, d)) % 4
+        seqs.append(w)
+    reads = synth.Reads(np.concatenate(seqs), np.arange(65, dtype=np.int64) * 32, starts)
+    index = _build(ref, "fp32", window_len=32)
+    rb, bufs = _map(index, reads, 8, 8)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    for r in range(64):
+        w = seqs[r]
+        for i in range(8):
+            j = int(tidx[r, i])
+            d = int(np.sum(ref[j:j + 32] != w))
+            assert abs(tsc[r, i] - ((32 - d) / 32) ** 2) < 2e-6
+
+
+def test_edge_cases():
+    torch = torch_cuda()
+    rng = np.random.default_rng(14)
+    # tiny reference: fewer windows (6) than k_fetch (8)
+    ref = rng.integers(0, 4, 155).astype(np.uint8)
+    reads = synth.Reads(ref[:150].copy(), np.array([0, 150], dtype=np.int64), np.array([0]))
+    index = _build(ref, "fp16")
+    rb, bufs = _map(index, reads, 8, 8)
+    tidx = bufs.top_idx.cpu().numpy()[0]
+    assert tidx[0] == 0 and list(tidx[6:]) == [-1, -1]
+    assert sorted(tidx[:6].tolist()) == list(range(6))
+    assert np.all(bufs.top_score.cpu().numpy()[0][6:] == -1)
+    # degenerate windows (a run of one letter), an exact duplicate block, and a
+    # read shorter than N (zero vector: every window scores 0, ids 0..k-1)
+    ref = rng.integers(0, 4, 5000).astype(np.uint8)
+    ref[1000:1400] = 0
+    ref[3000:3300] = ref[2000:2300]
+    good = ref[2050:2200].copy()
+    seq = np.concatenate([good, ref[1100:1250], rng.integers(0, 4, 100).astype(np.uint8)])
+    off = np.array([0, 150, 300, 400], dtype=np.int64)
+    reads = synth.Reads(seq, off, np.array([2050, 1100, 0]))
+    for prec in ("fp32", "fp16", "fp8"):
+        index = _build(ref, prec)
+        rb, bufs = _map(index, reads, 8, 16)
+        tidx = bufs.top_idx.cpu().numpy()
+        tsc = bufs.top_score.cpu().numpy()
+        assert tidx[0, 0] == 2050 and tidx[0, 1] == 3050, prec   # tie: lower id first
+        assert abs(tsc[0, 0] - 1) < 1e-5 and abs(tsc[0, 1] - 1) < 1e-5
+        assert np.all(tsc[1] == 0.0) and list(tidx[1]) == list(range(8)), prec  # degenerate read
+        assert np.all(tsc[2] == 0.0) and list(tidx[2]) == list(range(8)), prec  # short read
+        e = emb_to_complex(index, torch)
+        assert np.all(e[1000:1251] == 0)                   # windows inside the run

@@ -8,14 +8,31 @@ from synth import make_reference, simulate_reads
 
 
 def _brute_topk(ref, head, N, m, k, stride):
+    # every window scored one pair at a time; ranked by F descending, scores
+    # within RANK_EPS counting as equal and ordered by window id
     W = mapping.n_windows(ref.shape[0], N, stride)
     x = rope.encode_raw(head, N, m)
-    scored = []
-    for j in range(W):
-        c = rope.encode_raw(ref[j * stride:j * stride + N], N, m)
-        scored.append((-rope.fidelity(x, c, N), j))
-    scored.sort()
-    return [j for _, j in scored[:k]], [-f for f, _ in scored[:k]]
+    F = np.array([rope.fidelity(x, rope.encode_raw(ref[j * stride:j * stride + N], N, m), N)
+                  for j in range(W)])
+    order = sorted(range(W), key=lambda j: -F[j])
+    groups, cur = [], [order[0]]
+    for a, b in zip(order, order[1:]):
+        if F[a] - F[b] > mapping.RANK_EPS:
+            groups.append(cur)
+            cur = []
+        cur.append(b)
+    groups.append(cur)
+    ranked = [j for g in groups for j in sorted(g)][:k]
+    return ranked, [F[j] for j in ranked]
+
+
+def test_rank_order_ties_by_index():
+    F = np.array([0.5, 0.9, 0.5 + 1e-14, 0.7, 0.9 - 3e-13, 0.1])
+    ids = np.array([10, 3, 2, 8, 5, 1])
+    o = mapping.rank_order(F, ids)
+    assert list(ids[o]) == [3, 5, 8, 2, 10, 1]
+    F2 = np.array([0.5, 0.5 + 1e-9])                 # a real difference is kept
+    assert list(mapping.rank_order(F2, np.array([0, 1]))) == [1, 0]
 
 
 @pytest.mark.parametrize("stride", [1, 3])
