@@ -47,7 +47,21 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
     ap.add_argument("--cpu-reads", type=int, default=8)
     ap.add_argument("--cpu-windows", type=int, default=1_000_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: 1 GiB read + 1 GiB written, three times."""
+    import torch
+    n = 1 << 30
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
 
 
 def main():
@@ -61,6 +75,10 @@ def main():
     import torch
     import synth
     from paper_2603_22245_amd import mapper, _lib as L
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)

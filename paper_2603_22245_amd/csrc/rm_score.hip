@@ -31,6 +31,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTileW = 32;  // windows per B tile (the MFMA N dimension)
+// The register test re^2 + im^2 - t > 0 is computed with fused multiply-adds,
+// which round differently from the F stored in a key; lowering t by 2^-20
+// relative sends every candidate within rounding of the k-th best to the exact
+// key comparison instead of dropping it.  (t < 0 for a list that is not full.)
+constexpr float kLoose = 1.0f - 1.0f / 1048576.0f;
 
 __device__ __forceinline__ uint64_t make_key(float F, int32_t j) {
   uint32_t hi = __float_as_uint(F) + 1u;  // F >= 0
@@ -87,18 +92,49 @@ struct Prec<RM_FP8_E4M3> {
   static constexpr int esize = 1;
 };
 
+// LDS byte offset of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const void*)p);
+}
+
+// Asynchronous copy from global memory straight into LDS (gfx950
+// global_load_lds_*): lane l writes 16 (dma16) or 4 (dma4) bytes at LDS
+// offset lds + l * size.  Written as inline assembly, with no output register,
+// so that the compiler does not drain every outstanding copy (vmcnt(0)) before
+// each LDS read; completion is awaited explicitly with wait_vmcnt<N>(), which
+// counts this wavefront's vector-memory operations in issue order.
+__device__ __forceinline__ void dma16(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
+               : "memory");
+}
+__device__ __forceinline__ void dma4(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(lds)
+               : "memory");
+}
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// B tiles in LDS: row r (one window, RB bytes) stores its logical 16-byte chunk
+// c at position c ^ (r & 15).  A lane reading chunk c of row `col` therefore
+// reads byte offset col*RB + 16 (c ^ (col & 15)); the 16 lanes of one LDS
+// access cycle (consecutive col, same c) hit 16 different bank groups.
+//
 // One 32x32 output block per fragment over the full K = 256.  `a[f]` holds
 // this lane's 128 K-elements of fragment f (K range [128 g, 128 g + 128),
-// g = lane / 32); `b` points at the same K range of this lane's window row in
-// LDS.  Any assignment of K indices to (lane group, register slot) works as
-// long as A and B use the same one, which they do here.
+// g = lane / 32, in natural order); `row` points at this lane's window row in
+// the current LDS stage and kx = (byte offset of the lane's K half) ^
+// 16 (col & 15), so logical byte offset o is found at row + (kx ^ o).  Any
+// assignment of K indices to (lane group, register slot) works as long as A
+// and B use the same one, which they do here.
 template <int PREC, int NF, int AU4>
-__device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8_t* b,
-                                          f32x16 (&acc)[NF]) {
+__device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8_t* row,
+                                          uint32_t kx, f32x16 (&acc)[NF]) {
   if constexpr (PREC == RM_FP16) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      uint4 bv = *reinterpret_cast<const uint4*>(b + 16 * s);
+      uint4 bv = *reinterpret_cast<const uint4*>(row + (kx ^ (16u * s)));
       half8 bh = __builtin_bit_cast(half8, bv);
 #pragma unroll
       for (int f = 0; f < NF; ++f)
@@ -108,8 +144,8 @@ __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8
   } else if constexpr (PREC == RM_FP8_E4M3) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      uint4 b0 = *reinterpret_cast<const uint4*>(b + 32 * s);
-      uint4 b1 = *reinterpret_cast<const uint4*>(b + 32 * s + 16);
+      uint4 b0 = *reinterpret_cast<const uint4*>(row + (kx ^ (32u * s)));
+      uint4 b1 = *reinterpret_cast<const uint4*>(row + (kx ^ (32u * s + 16u)));
       i32x8 bb = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
                   (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
 #pragma unroll
@@ -125,7 +161,7 @@ __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8
   } else {
 #pragma unroll
     for (int s4 = 0; s4 < 32; ++s4) {
-      uint4 bv = *reinterpret_cast<const uint4*>(b + 16 * s4);
+      uint4 bv = *reinterpret_cast<const uint4*>(row + (kx ^ (16u * s4)));
       float bf[4] = {__uint_as_float(bv.x), __uint_as_float(bv.y), __uint_as_float(bv.z),
                      __uint_as_float(bv.w)};
 #pragma unroll
@@ -141,28 +177,32 @@ __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8
   }
 }
 
-template <int PREC, int NF, int WAVES, int KP, int ENT>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
 struct ScoreKernel {
   static constexpr int esize = Prec<PREC>::esize;
-  static constexpr int RB = kReal * esize;          // bytes per embedding row
-  static constexpr int RS = RB + 16;                // padded LDS row stride
+  static constexpr int RB = kReal * esize;              // bytes per embedding row
+  static constexpr int CPR = RB / 16;                   // 16-byte chunks per row
   static constexpr int AU4 = (kReal / 2) * esize / 16;  // uint4 per lane per fragment
-  static constexpr int READS = WAVES * NF * 16;     // reads per block
+  static constexpr int READS = WAVES * NF * 16;         // reads per block
   static constexpr int THREADS = WAVES * 64;
-  static constexpr int TILE_U4 = kTileW * RB / 16;  // uint4 per B tile
-  static constexpr int CPT = TILE_U4 / THREADS;     // uint4 per thread per tile
-  static constexpr int CB = ENT - KP;               // buffer slots per read
-  static_assert(CPT >= 1 && TILE_U4 % THREADS == 0, "tile/threads");
+  static constexpr int TILE = kTileW * RB;              // bytes per B tile
+  static constexpr int L = TILE / 1024 / WAVES;         // 1 KB copies per wave per tile
+  static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 1 : 0);  // + the window scales
+  static constexpr int CB = ENT - KP;                   // buffer slots per read
+  static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
   static_assert(CB >= 1, "buffer");
+  static_assert(STAGES >= 2, "stages");
 };
 
-template <int PREC, int NF, int WAVES, int KP, int ENT>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
 __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
     const uint8_t* __restrict__ index, const float* __restrict__ win_scale, int64_t W,
     const uint8_t* __restrict__ reads, const float* __restrict__ read_scale, int32_t R,
     int read_tiles, int64_t chunk_windows, int P, uint64_t* __restrict__ ws) {
-  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT>;
-  __shared__ __align__(16) uint8_t btile[2][kTileW * K::RS];
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES>;
+  constexpr bool kFp8 = PREC == RM_FP8_E4M3;
+  __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
+  __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * 32 : 4];
   __shared__ uint64_t lst[K::READS][ENT];
   __shared__ int cnt[K::READS];
   __shared__ float thr[K::READS];
@@ -201,44 +241,67 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
       for (int u = 0; u < K::AU4; ++u) a[f][u] = make_uint4(0, 0, 0, 0);
     }
   }
-
-  // per (fragment, slot) read index within the block, thresholds, read scales
-  float th[NF][8];
-  float rs2[NF][8];
+  // per (fragment, slot): s_r^2 and its inverse (FP8; 1 otherwise)
+  float rs2[NF][8], irs2[NF][8];
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      th[f][q] = -1.f;
       rs2[f][q] = 1.f;
-      if constexpr (PREC == RM_FP8_E4M3) {
+      irs2[f][q] = 1.f;
+      if constexpr (kFp8) {
         int64_t r = read0 + (wave * NF + f) * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
         float s = r < R ? read_scale[r] : 0.f;
         rs2[f][q] = s * s;
+        irs2[f][q] = rs2[f][q] > 0.f ? 1.f / rs2[f][q] : 0.f;
       }
     }
+  // Wait for these loads here, before the tile loop: otherwise the compiler's
+  // wait-count state from them reaches into the loop.
+  {
+    uint32_t any = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int u = 0; u < K::AU4; ++u) any |= a[f][u].x | a[f][u].w;
+    __builtin_amdgcn_s_waitcnt(0);
+    if (any == 0xdeadbeefu && R < 0) ws[0] = any;  // never true; keeps the use
+  }
 
-  // ---- B tile loader
-  uint4 breg[K::CPT];
-  auto load_tile = [&](int t) {
-    const int64_t base = wbeg + (int64_t)t * kTileW;
+  // thresholds in the product's units: F-threshold / s_r^2 (further divided by
+  // s_j^2 per window in the epilogue), lowered by kLoose
+  float th[NF][8];
 #pragma unroll
-    for (int i = 0; i < K::CPT; ++i) {
-      int c = tid + i * K::THREADS;
-      int row = c / (K::RB / 16);
-      int cu = c % (K::RB / 16);
-      int64_t wrow = base + row;
-      breg[i] = wrow < wend ? reinterpret_cast<const uint4*>(index + wrow * K::RB)[cu]
-                            : make_uint4(0, 0, 0, 0);
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) th[f][q] = -1.f;
+
+  // ---- B tiles: asynchronous copies into an LDS ring of STAGES tiles
+  const uint32_t ring_lds = lds_offset(ring);
+  const uint32_t scale_lds = lds_offset(ring_scale);
+  int drow[K::L];
+  uint32_t doff[K::L];
+#pragma unroll
+  for (int i = 0; i < K::L; ++i) {
+    int pos = (i * WAVES + wave) * 64 + lane;  // physical 16-byte chunk in the tile
+    int r = pos / K::CPR;
+    int c = (pos % K::CPR) ^ (r & 15);          // logical chunk stored there
+    drow[i] = r;
+    doff[i] = (uint32_t)c * 16u;
+  }
+  auto issue = [&](int t) {
+    const int stage = t % STAGES;
+    const int64_t tb = wbeg + (int64_t)t * kTileW;
+#pragma unroll
+    for (int i = 0; i < K::L; ++i) {
+      int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
+      dma16(index + grow * K::RB + doff[i],
+            __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * WAVES + wave) * 1024));
     }
-  };
-  auto store_tile = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < K::CPT; ++i) {
-      int c = tid + i * K::THREADS;
-      int row = c / (K::RB / 16);
-      int cu = c % (K::RB / 16);
-      *reinterpret_cast<uint4*>(&btile[buf][row * K::RS + cu * 16]) = breg[i];
+    if constexpr (kFp8) {
+      if (lane < 32)
+        dma4(win_scale + min(tb + lane, wend - 1),
+             __builtin_amdgcn_readfirstlane(scale_lds + (stage * WAVES + wave) * 128));
     }
   };
 
@@ -269,50 +332,75 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) th[f][q] = thr[rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1)];
+      for (int q = 0; q < 8; ++q)
+        th[f][q] = thr[rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1)] * irs2[f][q] * kLoose;
   };
 
-  __syncthreads();
-  if (ntiles > 0) {
-    load_tile(0);
-    store_tile(0);
-  }
-  __syncthreads();
+  // lane's B row offset and K-half key (see mfma_tile)
+  const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
+
+#pragma unroll
+  for (int t = 0; t < STAGES - 1; ++t)
+    if (t < ntiles) issue(t);
 
   for (int t = 0; t < ntiles; ++t) {
-    const int buf = t & 1;
+    const int stage = t % STAGES;
     const int64_t tbase = wbeg + (int64_t)t * kTileW;
-    if (t + 1 < ntiles) load_tile(t + 1);
-    float sj2 = 1.f;
-    if constexpr (PREC == RM_FP8_E4M3) {
-      float s = (tbase + col < wend) ? win_scale[tbase + col] : 0.f;
-      sj2 = s * s;
-    }
+    // this wavefront's copies of tile t are complete once at most the copies of
+    // the tiles issued after it (up to STAGES-2 of them) are outstanding
+    if (ntiles - 1 - t >= STAGES - 2)
+      wait_vmcnt<(STAGES - 2) * K::LT>();
+    else
+      wait_vmcnt<0>();
+    __syncthreads();  // every wavefront's copies landed; stage (t-1) % STAGES is free
+    if (t + STAGES - 1 < ntiles) issue(t + STAGES - 1);
 
     f32x16 acc[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = f32x16{};
-    mfma_tile<PREC, NF, K::AU4>(a, &btile[buf][col * K::RS + g * (K::RB / 2)], acc);
+    mfma_tile<PREC, NF, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
 
-    // ---- epilogue: F per (read slot, window col); hits against thresholds
+    // ---- epilogue: re^2 + im^2 - threshold per (read slot, window col),
+    // reduced with max; only a positive maximum anywhere in the wavefront
+    // leads to the (rare) per-score test below.
     const int32_t j = (int32_t)(tbase + col);
     const bool colok = tbase + col < wend;
-    uint32_t pend = 0;
-    float Fv[NF][8];
+    float sj2 = 1.f, isj2 = 1.f;
+    if constexpr (kFp8) {
+      float s = ring_scale[(stage * WAVES + wave) * 32 + col];
+      sj2 = s * s;
+      isj2 = sj2 > 0.f ? 1.f / sj2 : 0.f;
+    }
+    float ex = -1.f;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         float re = acc[f][2 * q], im = acc[f][2 * q + 1];
-        float F = re * re + im * im;
-        if constexpr (PREC == RM_FP8_E4M3) F = F * (rs2[f][q] * sj2);
-        Fv[f][q] = F;
-        pend |= (uint32_t)(colok && F > th[f][q]) << (f * 8 + q);
+        float tq = th[f][q];
+        if constexpr (kFp8) tq = tq * isj2;
+        ex = fmaxf(ex, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)));
       }
+    if (!colok) ex = -1.f;
 
-    if (__ballot(pend != 0)) {
-      // slow path (rare after the first tiles): append every hit, merging reads
-      // whose buffer is full, until nothing is pending.
+    if (__ballot(ex > 0.f)) {
+      uint32_t pend = 0;
+      float Fv[NF][8];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float re = acc[f][2 * q], im = acc[f][2 * q + 1];
+          float F = re * re + im * im;
+          if constexpr (kFp8) F = F * (rs2[f][q] * sj2);
+          Fv[f][q] = F;
+          float tq = th[f][q];
+          if constexpr (kFp8) tq = tq * isj2;
+          pend |= (uint32_t)(colok && __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)) > 0.f)
+                  << (f * 8 + q);
+        }
+      // append every hit, merging reads whose buffer is full, until nothing
+      // is pending
       while (true) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -335,9 +423,6 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
         if (!__ballot(pend != 0)) break;
       }
     }
-
-    if (t + 1 < ntiles) store_tile(buf ^ 1);
-    __syncthreads();
   }
 
   // ---- final merge and write-out of this chunk's lists
@@ -406,31 +491,40 @@ Shape shape_for(int precision, int k_fetch) {
   return {nf, waves, kp, ent};
 }
 
-template <int PREC, int NF, int WAVES, int KP, int ENT>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
 hipError_t launch_one(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
                       const float* read_scale, int32_t R, void* ws, hipStream_t s) {
   unsigned blocks = (unsigned)plan.read_tiles * (unsigned)plan.chunks;
-  hipLaunchKernelGGL((score_topk_kernel<PREC, NF, WAVES, KP, ENT>), dim3(blocks), dim3(WAVES * 64),
-                     0, s, static_cast<const uint8_t*>(idx.d_emb), idx.d_scale, idx.n_windows,
-                     static_cast<const uint8_t*>(read_emb), read_scale, R, plan.read_tiles,
-                     plan.chunk_windows, plan.chunks, static_cast<uint64_t*>(ws));
+  hipLaunchKernelGGL((score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES>), dim3(blocks),
+                     dim3(WAVES * 64), 0, s, static_cast<const uint8_t*>(idx.d_emb), idx.d_scale,
+                     idx.n_windows, static_cast<const uint8_t*>(read_emb), read_scale, R,
+                     plan.read_tiles, plan.chunk_windows, plan.chunks, static_cast<uint64_t*>(ws));
   return hipGetLastError();
 }
 
+// LDS per block: ring STAGES x 32 rows + lists READS x ENT x 8 B (+ FP8 scales),
+// kept within 160 KB.
 template <int PREC>
 hipError_t dispatch_kp(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
                        const float* read_scale, int32_t R, void* ws, hipStream_t s) {
-  constexpr int NF = PREC == RM_FP32 ? 1 : 2;
-  switch (plan.kp) {
-    case 8:
-      return launch_one<PREC, NF, 8, 8, 32>(idx, plan, read_emb, read_scale, R, ws, s);
-    case 16:
-      return launch_one<PREC, NF, 8, 16, 32>(idx, plan, read_emb, read_scale, R, ws, s);
-    default:
-      if constexpr (PREC == RM_FP16)
-        return launch_one<PREC, NF, 4, 32, 64>(idx, plan, read_emb, read_scale, R, ws, s);
-      else
-        return launch_one<PREC, NF, 8, 32, 64>(idx, plan, read_emb, read_scale, R, ws, s);
+  if constexpr (PREC == RM_FP32) {
+    switch (plan.kp) {
+      case 8: return launch_one<PREC, 1, 8, 8, 32, 3>(idx, plan, read_emb, read_scale, R, ws, s);
+      case 16: return launch_one<PREC, 1, 8, 16, 32, 3>(idx, plan, read_emb, read_scale, R, ws, s);
+      default: return launch_one<PREC, 1, 8, 32, 64, 2>(idx, plan, read_emb, read_scale, R, ws, s);
+    }
+  } else if constexpr (PREC == RM_FP16) {
+    switch (plan.kp) {
+      case 8: return launch_one<PREC, 2, 8, 8, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
+      case 16: return launch_one<PREC, 2, 8, 16, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
+      default: return launch_one<PREC, 2, 4, 32, 64, 4>(idx, plan, read_emb, read_scale, R, ws, s);
+    }
+  } else {
+    switch (plan.kp) {
+      case 8: return launch_one<PREC, 2, 8, 8, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
+      case 16: return launch_one<PREC, 2, 8, 16, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
+      default: return launch_one<PREC, 2, 8, 32, 64, 3>(idx, plan, read_emb, read_scale, R, ws, s);
+    }
   }
 }
 
