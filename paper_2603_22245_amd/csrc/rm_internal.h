@@ -85,6 +85,7 @@ struct ScorePlan {
   int chunks;          // P: window chunks per read
   int64_t chunk_windows;
   int kp;              // list length kept per (read, chunk): 8, 16 or 32
+  size_t thr_offset;   // byte offset of the shared per-read thresholds in the workspace
   size_t ws_bytes;
 };
 

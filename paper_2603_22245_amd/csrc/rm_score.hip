@@ -198,7 +198,8 @@ template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
 __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
     const uint8_t* __restrict__ index, const float* __restrict__ win_scale, int64_t W,
     const uint8_t* __restrict__ reads, const float* __restrict__ read_scale, int32_t R,
-    int read_tiles, int64_t chunk_windows, int P, uint64_t* __restrict__ ws) {
+    int read_tiles, int64_t chunk_windows, int P, uint64_t* __restrict__ ws,
+    uint32_t* __restrict__ gthr) {
   using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES>;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
   __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
@@ -289,9 +290,9 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
     drow[i] = r;
     doff[i] = (uint32_t)c * 16u;
   }
-  auto issue = [&](int t) {
-    const int stage = t % STAGES;
-    const int64_t tb = wbeg + (int64_t)t * kTileW;
+  // copy window tile `tsrc` into ring stage `stage`
+  auto issue_into = [&](int tsrc, int stage) {
+    const int64_t tb = wbeg + (int64_t)tsrc * kTileW;
 #pragma unroll
     for (int i = 0; i < K::L; ++i) {
       int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
@@ -303,6 +304,21 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
         dma4(win_scale + min(tb + lane, wend - 1),
              __builtin_amdgcn_readfirstlane(scale_lds + (stage * WAVES + wave) * 128));
     }
+  };
+
+  // ---- thresholds: the larger of this chunk's k-th best and the best k-th
+  // best any chunk has published for the read (0 = none yet)
+  auto refresh_thresholds = [&]() {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+        int64_t r = read0 + rb;
+        uint32_t gk = r < R ? __hip_atomic_load(&gthr[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        float gt = gk ? __uint_as_float(gk - 1u) : -1.f;
+        th[f][q] = fmaxf(thr[rb], gt) * irs2[f][q] * kLoose;
+      }
   };
 
   // ---- merge a read's buffer into its list (whole wavefront, uniform call)
@@ -324,53 +340,55 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
         uint64_t key = (id < KP + n) ? lst[rb][id] : 0;
         key = sort_desc<ENT>(key, lane);
         if (id < KP) lst[rb][id] = key;
-        if (id == KP - 1) thr[rb] = key_score(key);
+        if (id == KP - 1) {
+          float kth = key_score(key);
+          thr[rb] = kth;
+          // publish this chunk's k-th best: no window scoring below it can be
+          // in the read's final list, whichever chunk holds it
+          if (kth >= 0.f && read0 + rb < R) atomicMax(&gthr[read0 + rb], __float_as_uint(kth) + 1u);
+        }
         if (id == 0) cnt[rb] = 0;
       }
     }
     __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        th[f][q] = thr[rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1)] * irs2[f][q] * kLoose;
+    refresh_thresholds();
   };
 
   // lane's B row offset and K-half key (see mfma_tile)
   const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
 
-#pragma unroll
-  for (int t = 0; t < STAGES - 1; ++t)
-    if (t < ntiles) issue(t);
-
-  for (int t = 0; t < ntiles; ++t) {
+  // Pipeline: the ring always has copies of the next STAGES-2 tiles in flight
+  // (past the last tile the copies repeat the last tile, so every tile step
+  // issues the same number of copies and waits for the same count).  A tile
+  // step waits for its own tile, synchronises the block (every copy landed;
+  // the stage of the previous tile is free), refills that stage and issues
+  // the tile's MFMAs.  The epilogue of tile t runs after the MFMAs of tile t+1
+  // have been issued, in the same basic block, so its VALU work fills the
+  // MFMA pipeline's latency.
+  auto start_tile = [&](int t, f32x16 (&acc)[NF], float& sj2) {
+    wait_vmcnt<(STAGES - 2) * K::LT>();
+    __syncthreads();
     const int stage = t % STAGES;
-    const int64_t tbase = wbeg + (int64_t)t * kTileW;
-    // this wavefront's copies of tile t are complete once at most the copies of
-    // the tiles issued after it (up to STAGES-2 of them) are outstanding
-    if (ntiles - 1 - t >= STAGES - 2)
-      wait_vmcnt<(STAGES - 2) * K::LT>();
-    else
-      wait_vmcnt<0>();
-    __syncthreads();  // every wavefront's copies landed; stage (t-1) % STAGES is free
-    if (t + STAGES - 1 < ntiles) issue(t + STAGES - 1);
-
-    f32x16 acc[NF];
+    if constexpr (kFp8) {
+      float sc = ring_scale[(stage * WAVES + wave) * 32 + col];
+      sj2 = sc * sc;
+    }
+    issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = f32x16{};
     mfma_tile<PREC, NF, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
+  };
 
-    // ---- epilogue: re^2 + im^2 - threshold per (read slot, window col),
-    // reduced with max; only a positive maximum anywhere in the wavefront
-    // leads to the (rare) per-score test below.
+  // re^2 + im^2 - threshold per (read slot, window col), reduced with max;
+  // only a positive maximum anywhere in the wavefront leads to the (rare)
+  // per-score test and appends.
+  auto epilogue = [&](int t, const f32x16 (&acc)[NF], float sj2) {
+    if ((t & 255) == 255) refresh_thresholds();  // pick up other chunks' progress
+    const int64_t tbase = wbeg + (int64_t)t * kTileW;
     const int32_t j = (int32_t)(tbase + col);
     const bool colok = tbase + col < wend;
-    float sj2 = 1.f, isj2 = 1.f;
-    if constexpr (kFp8) {
-      float s = ring_scale[(stage * WAVES + wave) * 32 + col];
-      sj2 = s * s;
-      isj2 = sj2 > 0.f ? 1.f / sj2 : 0.f;
-    }
+    float isj2 = 1.f;
+    if constexpr (kFp8) isj2 = sj2 > 0.f ? 1.f / sj2 : 0.f;
     float ex = -1.f;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -423,7 +441,36 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
         if (!__ballot(pend != 0)) break;
       }
     }
+  };
+
+#pragma unroll
+  for (int t = 0; t < STAGES - 1; ++t) issue_into(min(t, ntiles - 1), t);
+
+  // FP16 keeps one accumulator set: its A fragments take 128 VGPRs and a
+  // second set would spill at two wavefronts per SIMD.
+  constexpr bool kPipe = PREC != RM_FP16;
+  refresh_thresholds();
+  f32x16 accA[NF];
+  float sjA = 1.f;
+  if constexpr (kPipe) {
+    f32x16 accB[NF];
+    float sjB = 1.f;
+    start_tile(0, accA, sjA);
+    for (int t = 0;; t += 2) {
+      start_tile(t + 1, accB, sjB);  // past the end: a repeat of the last tile, unused
+      epilogue(t, accA, sjA);
+      if (t + 1 >= ntiles) break;
+      start_tile(t + 2, accA, sjA);
+      epilogue(t + 1, accB, sjB);
+      if (t + 2 >= ntiles) break;
+    }
+  } else {
+    for (int t = 0; t < ntiles; ++t) {
+      start_tile(t, accA, sjA);
+      epilogue(t, accA, sjA);
+    }
   }
+  wait_vmcnt<0>();  // no copy may still be writing this block's LDS
 
   // ---- final merge and write-out of this chunk's lists
   {
@@ -437,6 +484,12 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
       if (r < R) ws[((int64_t)r * P + chunk) * KP + e] = lst[rb0 + rr][e];
     }
   }
+}
+
+// Shared per-read thresholds start with "no information" (0).
+__global__ void clear_thresholds(uint32_t* __restrict__ gthr, int32_t R) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R) gthr[i] = 0u;
 }
 
 // Merge the P per-chunk lists of each read into its k_fetch best: repeated
@@ -498,7 +551,8 @@ hipError_t launch_one(const rm_index& idx, const ScorePlan& plan, const void* re
   hipLaunchKernelGGL((score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES>), dim3(blocks),
                      dim3(WAVES * 64), 0, s, static_cast<const uint8_t*>(idx.d_emb), idx.d_scale,
                      idx.n_windows, static_cast<const uint8_t*>(read_emb), read_scale, R,
-                     plan.read_tiles, plan.chunk_windows, plan.chunks, static_cast<uint64_t*>(ws));
+                     plan.read_tiles, plan.chunk_windows, plan.chunks, static_cast<uint64_t*>(ws),
+                     reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws) + plan.thr_offset));
   return hipGetLastError();
 }
 
@@ -550,14 +604,20 @@ ScorePlan plan_score(int precision, int64_t W, int32_t n_reads, int32_t k_fetch)
   p.chunk_windows = cw;
   p.chunks = (int)((W + cw - 1) / cw);
   if (p.chunks < 1) p.chunks = 1;
-  p.ws_bytes = (size_t)n_reads * (size_t)p.chunks * (size_t)p.kp * sizeof(uint64_t);
+  size_t lists = (size_t)n_reads * (size_t)p.chunks * (size_t)p.kp * sizeof(uint64_t);
+  p.thr_offset = (lists + 255) / 256 * 256;
+  p.ws_bytes = p.thr_offset + (size_t)n_reads * sizeof(uint32_t);
   return p;
 }
 
 hipError_t launch_score_topk(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
                              const float* read_scale, int32_t n_reads, int32_t k_fetch,
                              int32_t* cand_idx, float* cand_score, void* ws, hipStream_t s) {
-  hipError_t e;
+  hipLaunchKernelGGL(clear_thresholds, dim3((unsigned)(((int64_t)n_reads + 255) / 256)), dim3(256),
+                     0, s, reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws) + plan.thr_offset),
+                     n_reads);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (idx.p.precision) {
     case RM_FP32:
       e = dispatch_kp<RM_FP32>(idx, plan, read_emb, read_scale, n_reads, ws, s);
