@@ -161,6 +161,78 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                const int32_t* d_cand_idx, int32_t k, int32_t* d_top_idx, float* d_top_score,
                void* stream);
 
+/* ---- batching: several (index, read batch) groups in one launch -------------
+ * Reads of uneven length are mapped by bucketing them by head length (§2.9:
+ * strings of different lengths are only compared at one window length), one
+ * index per bucket length, and scoring every bucket's reads against its index
+ * in ONE persistent launch (grouped work queue), followed by one merge per
+ * group.  The sequence encode -> score -> rescore may be captured in a HIP
+ * graph with rm_capture_begin / rm_capture_end and replayed with
+ * rm_graph_launch. */
+
+#define RM_MAX_GROUPS 8
+
+/* Tile shape of the scoring kernel; zero fields select the library default. */
+typedef struct rm_tuning {
+  int32_t read_tile;   /* reads per block: 0, 128 or 256 (256 is not available for
+                          FP32, nor for FP16 with k_fetch > 16) */
+  int32_t chunk_tiles; /* 32-window tiles per work item: 0 or >= 1 */
+} rm_tuning;
+
+/* Assign each read to the longest bucket length not above its length (host
+ * memory; a pure CPU helper).  h_off: n_reads+1 offsets; bucket_len: n_buckets
+ * strictly increasing lengths.  Writes h_bucket[n_reads] (the bucket index, or
+ * -1 for a read shorter than bucket_len[0]) and h_count[n_buckets].
+ * Errors: RM_EINVAL (null pointer, lengths not increasing), RM_ESIZE. */
+int rm_bucket_reads(const int64_t* h_off, int32_t n_reads, const int32_t* bucket_len,
+                    int32_t n_buckets, int32_t* h_bucket, int32_t* h_count);
+
+/* Workspace bytes of rm_score_topk_groups; 0 if invalid.  idx and n_reads are
+ * host arrays of n_groups entries; tune may be NULL. */
+size_t rm_score_groups_workspace_bytes(const rm_index* idx, int32_t n_groups,
+                                       const int32_t* n_reads, int32_t k_fetch,
+                                       const rm_tuning* tune);
+
+/* rm_score_topk for n_groups (index, read batch) pairs in one persistent launch
+ * (§3.1 per group).  idx, d_read_emb, d_read_scale, n_reads, d_cand_idx and
+ * d_cand_score are HOST arrays of n_groups entries (the entries are device
+ * pointers); d_read_scale may be NULL unless the precision is FP8.  All groups
+ * share one precision and k_fetch.  Output per group as rm_score_topk.
+ * Errors: RM_EINVAL (null pointer, mixed precisions), RM_ESIZE (n_groups outside
+ * 1..RM_MAX_GROUPS, a group without reads, k_fetch out of range, ws too small),
+ * RM_EUNSUPPORTED (a tuning the kernels do not implement). */
+int rm_score_topk_groups(const rm_index* idx, int32_t n_groups, const void* const* d_read_emb,
+                         const float* const* d_read_scale, const int32_t* n_reads,
+                         int32_t k_fetch, int32_t* const* d_cand_idx,
+                         float* const* d_cand_score, void* d_ws, size_t ws_bytes,
+                         const rm_tuning* tune, void* stream);
+
+/* Autotuner: times candidate tile shapes of rm_score_topk_groups on these very
+ * inputs (each candidate once after a warm-up run, with HIP events; the stream
+ * is synchronised, so do not call it while capturing) and returns the fastest
+ * in *best (and its time in *best_ms if not NULL).  Candidates whose workspace
+ * exceeds ws_bytes are skipped.  If cache_path is not NULL, a previous result
+ * for the same device architecture, precision, k_fetch and group shapes is
+ * returned from that file without timing, and a new result is appended to it
+ * (one JSON object per line).  The outputs hold the last candidate's results.
+ * Errors: as rm_score_topk_groups; RM_EHIP if timing fails. */
+int rm_autotune_score(const rm_index* idx, int32_t n_groups, const void* const* d_read_emb,
+                      const float* const* d_read_scale, const int32_t* n_reads, int32_t k_fetch,
+                      int32_t* const* d_cand_idx, float* const* d_cand_score, void* d_ws,
+                      size_t ws_bytes, const char* cache_path, rm_tuning* best, float* best_ms,
+                      void* stream);
+
+/* HIP graph capture of a sequence of rm_* calls on one stream (which must not
+ * be the null stream).  Between begin and end the calls are recorded, not run;
+ * they enqueue kernels only (no allocation, copy or memset).  rm_capture_end
+ * instantiates the graph; rm_graph_launch replays it on a stream;
+ * rm_graph_destroy frees it (host objects only).  Errors: RM_EINVAL, RM_EHIP. */
+typedef struct rm_graph_s* rm_graph;
+int rm_capture_begin(void* stream);
+int rm_capture_end(void* stream, rm_graph* out);
+int rm_graph_launch(rm_graph graph, void* stream);
+int rm_graph_destroy(rm_graph graph);
+
 #ifdef __cplusplus
 }
 #endif

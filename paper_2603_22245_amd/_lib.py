@@ -36,6 +36,13 @@ class rm_index(ctypes.Structure):
                 ("d_phase32", ctypes.c_void_p), ("d_step32", ctypes.c_void_p)]
 
 
+class rm_tuning(ctypes.Structure):
+    _fields_ = [("read_tile", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32)]
+
+
+RM_MAX_GROUPS = 8
+
+
 class RotorMapError(RuntimeError):
     def __init__(self, status: int, call: str):
         self.status = status
@@ -65,6 +72,17 @@ def lib():
             "rm_score_workspace_bytes": (SZ, [IP, I32, I32]),
             "rm_score_topk": (ctypes.c_int, [IP, P, P, I32, I32, P, P, P, SZ, P]),
             "rm_rescore": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, P, P, P]),
+            "rm_bucket_reads": (ctypes.c_int, [P, I32, P, I32, P, P]),
+            "rm_score_groups_workspace_bytes": (SZ, [IP, I32, P, I32, ctypes.POINTER(rm_tuning)]),
+            "rm_score_topk_groups": (ctypes.c_int, [IP, I32, P, P, P, I32, P, P, P, SZ,
+                                                    ctypes.POINTER(rm_tuning), P]),
+            "rm_autotune_score": (ctypes.c_int, [IP, I32, P, P, P, I32, P, P, P, SZ,
+                                                 ctypes.c_char_p, ctypes.POINTER(rm_tuning),
+                                                 ctypes.POINTER(ctypes.c_float), P]),
+            "rm_capture_begin": (ctypes.c_int, [P]),
+            "rm_capture_end": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_void_p)]),
+            "rm_graph_launch": (ctypes.c_int, [P, P]),
+            "rm_graph_destroy": (ctypes.c_int, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -163,3 +181,78 @@ def rm_rescore(idx: rm_index, d_ref, d_seq, d_off, n_reads: int, k_fetch: int, d
     _check(lib().rm_rescore(ctypes.byref(idx), _ptr(d_ref), _ptr(d_seq), _ptr(d_off), n_reads,
                             k_fetch, _ptr(d_cand_idx), k, _ptr(d_top_idx), _ptr(d_top_score),
                             _stream(stream)), "rm_rescore")
+
+
+# ---------------------------------------------------------------- batching
+
+def rm_bucket_reads(offsets, bucket_len):
+    """Host helper: bucket index per read (-1 if shorter than the first bucket) and
+    per-bucket counts."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    bl = np.ascontiguousarray(bucket_len, dtype=np.int32)
+    n = off.shape[0] - 1
+    bucket = np.empty(n, dtype=np.int32)
+    count = np.empty(bl.shape[0], dtype=np.int32)
+    _check(lib().rm_bucket_reads(off.ctypes.data, n, bl.ctypes.data, bl.shape[0],
+                                 bucket.ctypes.data, count.ctypes.data), "rm_bucket_reads")
+    return bucket, count
+
+
+def _groups(idxs, n_reads):
+    n = len(idxs)
+    arr = (rm_index * n)(*idxs)
+    nr = (ctypes.c_int32 * n)(*[int(v) for v in n_reads])
+    return n, arr, nr
+
+
+def _ptrs(xs):
+    return (ctypes.c_void_p * len(xs))(*[_ptr(x) for x in xs])
+
+
+def rm_score_groups_workspace_bytes(idxs, n_reads, k_fetch, tune=None) -> int:
+    n, arr, nr = _groups(idxs, n_reads)
+    return int(lib().rm_score_groups_workspace_bytes(arr, n, nr, k_fetch,
+                                                     ctypes.byref(tune) if tune else None))
+
+
+def rm_score_topk_groups(idxs, d_read_emb, d_read_scale, n_reads, k_fetch, d_cand_idx,
+                         d_cand_score, d_ws, ws_bytes, tune=None, stream=None) -> None:
+    n, arr, nr = _groups(idxs, n_reads)
+    scales = _ptrs(d_read_scale) if d_read_scale is not None else None
+    _check(lib().rm_score_topk_groups(arr, n, _ptrs(d_read_emb), scales, nr, k_fetch,
+                                      _ptrs(d_cand_idx), _ptrs(d_cand_score), _ptr(d_ws),
+                                      ws_bytes, ctypes.byref(tune) if tune else None,
+                                      _stream(stream)), "rm_score_topk_groups")
+
+
+def rm_autotune_score(idxs, d_read_emb, d_read_scale, n_reads, k_fetch, d_cand_idx, d_cand_score,
+                      d_ws, ws_bytes, cache_path=None, stream=None):
+    n, arr, nr = _groups(idxs, n_reads)
+    scales = _ptrs(d_read_scale) if d_read_scale is not None else None
+    best = rm_tuning()
+    ms = ctypes.c_float(0.0)
+    _check(lib().rm_autotune_score(arr, n, _ptrs(d_read_emb), scales, nr, k_fetch,
+                                   _ptrs(d_cand_idx), _ptrs(d_cand_score), _ptr(d_ws), ws_bytes,
+                                   cache_path.encode() if cache_path else None,
+                                   ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
+           "rm_autotune_score")
+    return best, float(ms.value)
+
+
+def rm_capture_begin(stream) -> None:
+    _check(lib().rm_capture_begin(_stream(stream)), "rm_capture_begin")
+
+
+def rm_capture_end(stream) -> int:
+    g = ctypes.c_void_p()
+    _check(lib().rm_capture_end(_stream(stream), ctypes.byref(g)), "rm_capture_end")
+    return int(g.value)
+
+
+def rm_graph_launch(graph: int, stream=None) -> None:
+    _check(lib().rm_graph_launch(graph, _stream(stream)), "rm_graph_launch")
+
+
+def rm_graph_destroy(graph: int) -> None:
+    _check(lib().rm_graph_destroy(graph), "rm_graph_destroy")

@@ -2,6 +2,8 @@
 // enqueued), the layout of the caller's index buffer, and kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <new>
+
 #include "rm_internal.h"
 
 namespace {
@@ -148,24 +150,14 @@ int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_
 }
 
 size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_fetch) {
-  if (index_ok(idx) != RM_OK || n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return 0;
-  return rm::plan_score(idx->p.precision, idx->n_windows, n_reads, k_fetch).ws_bytes;
+  return rm_score_groups_workspace_bytes(idx, 1, &n_reads, k_fetch, nullptr);
 }
 
 int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
                   int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx, float* d_cand_score,
                   void* d_ws, size_t ws_bytes, void* stream) {
-  int st = index_ok(idx);
-  if (st != RM_OK) return st;
-  if (d_read_emb == nullptr || d_cand_idx == nullptr || d_cand_score == nullptr || d_ws == nullptr)
-    return RM_EINVAL;
-  if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
-  if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return RM_ESIZE;
-  rm::ScorePlan plan = rm::plan_score(idx->p.precision, idx->n_windows, n_reads, k_fetch);
-  if (ws_bytes < plan.ws_bytes) return RM_ESIZE;
-  return hip_status(rm::launch_score_topk(*idx, plan, d_read_emb, d_read_scale, n_reads, k_fetch,
-                                          d_cand_idx, d_cand_score, d_ws,
-                                          static_cast<hipStream_t>(stream)));
+  return rm_score_topk_groups(idx, 1, &d_read_emb, &d_read_scale, &n_reads, k_fetch, &d_cand_idx,
+                              &d_cand_score, d_ws, ws_bytes, nullptr, stream);
 }
 
 int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
@@ -180,6 +172,127 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
     return RM_ESIZE;
   return hip_status(rm::launch_rescore(*idx, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, k,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
+}
+
+// ------------------------------------------------------------------ batching
+
+int rm_bucket_reads(const int64_t* h_off, int32_t n_reads, const int32_t* bucket_len,
+                    int32_t n_buckets, int32_t* h_bucket, int32_t* h_count) {
+  if (!h_off || !bucket_len || !h_bucket || !h_count) return RM_EINVAL;
+  if (n_reads < 0 || n_buckets < 1) return RM_ESIZE;
+  for (int b = 0; b < n_buckets; ++b) {
+    if (bucket_len[b] < 1 || (b > 0 && bucket_len[b] <= bucket_len[b - 1])) return RM_EINVAL;
+    h_count[b] = 0;
+  }
+  for (int32_t r = 0; r < n_reads; ++r) {
+    int64_t len = h_off[r + 1] - h_off[r];
+    int b = -1;
+    while (b + 1 < n_buckets && bucket_len[b + 1] <= len) ++b;
+    h_bucket[r] = b;
+    if (b >= 0) ++h_count[b];
+  }
+  return RM_OK;
+}
+
+static int groups_ok(const rm_index* idx, int32_t n_groups, const int32_t* n_reads,
+                     int32_t k_fetch) {
+  if (idx == nullptr || n_reads == nullptr) return RM_EINVAL;
+  if (n_groups < 1 || n_groups > RM_MAX_GROUPS) return RM_ESIZE;
+  if (k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return RM_ESIZE;
+  for (int i = 0; i < n_groups; ++i) {
+    int st = index_ok(&idx[i]);
+    if (st != RM_OK) return st;
+    if (idx[i].p.precision != idx[0].p.precision) return RM_EINVAL;
+    if (n_reads[i] < 1) return RM_ESIZE;
+  }
+  return RM_OK;
+}
+
+static rm::ScorePlan groups_plan(const rm_index* idx, int32_t n_groups, const int32_t* n_reads,
+                                 int32_t k_fetch, const rm_tuning* tune) {
+  int64_t W[RM_MAX_GROUPS];
+  for (int i = 0; i < n_groups; ++i) W[i] = idx[i].n_windows;
+  rm::Tuning t{tune ? tune->read_tile : 0, tune ? tune->chunk_tiles : 0};
+  return rm::plan_score(idx[0].p.precision, n_groups, W, n_reads, k_fetch, t);
+}
+
+size_t rm_score_groups_workspace_bytes(const rm_index* idx, int32_t n_groups,
+                                       const int32_t* n_reads, int32_t k_fetch,
+                                       const rm_tuning* tune) {
+  if (groups_ok(idx, n_groups, n_reads, k_fetch) != RM_OK) return 0;
+  rm::ScorePlan plan = groups_plan(idx, n_groups, n_reads, k_fetch, tune);
+  return plan.ok ? plan.ws_bytes : 0;
+}
+
+int rm_score_topk_groups(const rm_index* idx, int32_t n_groups, const void* const* d_read_emb,
+                         const float* const* d_read_scale, const int32_t* n_reads,
+                         int32_t k_fetch, int32_t* const* d_cand_idx,
+                         float* const* d_cand_score, void* d_ws, size_t ws_bytes,
+                         const rm_tuning* tune, void* stream) {
+  int st = groups_ok(idx, n_groups, n_reads, k_fetch);
+  if (st != RM_OK) return st;
+  if (!d_read_emb || !d_cand_idx || !d_cand_score || !d_ws) return RM_EINVAL;
+  const bool fp8 = idx[0].p.precision == RM_FP8_E4M3;
+  if (fp8 && !d_read_scale) return RM_EINVAL;
+  for (int i = 0; i < n_groups; ++i) {
+    if (!d_read_emb[i] || !d_cand_idx[i] || !d_cand_score[i]) return RM_EINVAL;
+    if (fp8 && !d_read_scale[i]) return RM_EINVAL;
+  }
+  if (tune && (tune->chunk_tiles < 0 ||
+               (tune->read_tile != 0 && tune->read_tile != 128 && tune->read_tile != 256)))
+    return RM_EUNSUPPORTED;
+  rm::ScorePlan plan = groups_plan(idx, n_groups, n_reads, k_fetch, tune);
+  if (!plan.ok) return tune && tune->read_tile ? RM_EUNSUPPORTED : RM_ESIZE;
+  if (ws_bytes < plan.ws_bytes) return RM_ESIZE;
+  return hip_status(rm::launch_score_topk(idx, plan, d_read_emb, d_read_scale, n_reads, k_fetch,
+                                          d_cand_idx, d_cand_score, d_ws,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+// ------------------------------------------------------------------ graphs
+
+struct rm_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int rm_capture_begin(void* stream) {
+  if (stream == nullptr) return RM_EINVAL;
+  return hip_status(
+      hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
+}
+
+int rm_capture_end(void* stream, rm_graph* out) {
+  if (stream == nullptr || out == nullptr) return RM_EINVAL;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g) != hipSuccess || g == nullptr)
+    return RM_EHIP;
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return RM_EHIP;
+  }
+  rm_graph h = new (std::nothrow) rm_graph_s{g, ex};
+  if (h == nullptr) {
+    hipGraphExecDestroy(ex);
+    hipGraphDestroy(g);
+    return RM_EHIP;
+  }
+  *out = h;
+  return RM_OK;
+}
+
+int rm_graph_launch(rm_graph graph, void* stream) {
+  if (graph == nullptr) return RM_EINVAL;
+  return hip_status(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+}
+
+int rm_graph_destroy(rm_graph graph) {
+  if (graph == nullptr) return RM_EINVAL;
+  hipGraphExecDestroy(graph->exec);
+  hipGraphDestroy(graph->graph);
+  delete graph;
+  return RM_OK;
 }
 
 }  // extern "C"

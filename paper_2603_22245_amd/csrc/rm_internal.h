@@ -79,21 +79,66 @@ hipError_t launch_encode_reads(const rm_params& p, const double* phase64, const 
                                const int64_t* off, int32_t n_reads, void* emb, float* scale,
                                hipStream_t s);
 
-struct ScorePlan {
-  int reads_per_block;
-  int read_tiles;
-  int chunks;          // P: window chunks per read
+constexpr int kMaxGroups = 8;
+
+// One (index, read batch) pair of a scoring launch; passed by value in the
+// kernel arguments.
+struct ScoreGroup {
+  const uint8_t* index;      // [W][256] window embeddings
+  const float* win_scale;    // [W]
+  int64_t W;
+  const uint8_t* reads;      // [R][2][256] read rows
+  const float* read_scale;   // [R]
+  int32_t R;
+  int32_t read_tiles;
   int64_t chunk_windows;
-  int kp;              // list length kept per (read, chunk): 8, 16 or 32
-  size_t thr_offset;   // byte offset of the shared per-read thresholds in the workspace
-  size_t ws_bytes;
+  int32_t P;                 // window chunks
+  int32_t item_begin;        // first work item of this group
+  uint64_t* lists;           // [R][P][kp] keys
+  uint32_t* gthr;            // [R] shared k-th-best per read
 };
 
-ScorePlan plan_score(int precision, int64_t W, int32_t n_reads, int32_t k_fetch);
+struct ScoreLaunch {
+  ScoreGroup g[kMaxGroups];
+  int32_t n_groups;
+  int32_t total_items;
+  int* counter;
+};
 
-hipError_t launch_score_topk(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
-                             const float* read_scale, int32_t n_reads, int32_t k_fetch,
-                             int32_t* cand_idx, float* cand_score, void* ws, hipStream_t s);
+struct Tuning {
+  int read_tile;    // reads per block (128 or 256); 0 = default
+  int chunk_tiles;  // 32-window tiles per work item; 0 = default
+};
+
+struct GroupPlan {
+  int read_tiles;
+  int chunks;
+  int64_t chunk_windows;
+  size_t lists_offset;
+  size_t thr_offset;
+};
+
+struct ScorePlan {
+  int kp;           // list length per (read, chunk): 8, 16 or 32
+  int read_tile;    // reads per block
+  int n_groups;
+  GroupPlan g[kMaxGroups];
+  int64_t total_items;
+  size_t counter_offset;
+  size_t ws_bytes;
+  bool ok;
+};
+
+// Read-tile sizes the kernels implement for a precision and list length.
+bool read_tile_ok(int precision, int kp, int read_tile);
+
+ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_t* R, int k_fetch,
+                     Tuning t);
+
+hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
+                             const void* const* read_emb, const float* const* read_scale,
+                             const int32_t* R, int k_fetch, int32_t* const* cand_idx,
+                             float* const* cand_score, void* ws, hipStream_t s);
 
 hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                           const int64_t* off, int32_t n_reads, int32_t k_fetch,

@@ -194,27 +194,30 @@ struct ScoreKernel {
   static_assert(STAGES >= 2, "stages");
 };
 
+// One work item: read tile `tile` of group G against window chunk `chunk`.
 template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
-__global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
-    const uint8_t* __restrict__ index, const float* __restrict__ win_scale, int64_t W,
-    const uint8_t* __restrict__ reads, const float* __restrict__ read_scale, int32_t R,
-    int read_tiles, int64_t chunk_windows, int P, uint64_t* __restrict__ ws,
-    uint32_t* __restrict__ gthr) {
+__device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int tile,
+                                           uint8_t* ring, float* ring_scale,
+                                           uint64_t (*lst)[ENT], int* cnt, float* thr,
+                                           float* rsq) {
   using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES>;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
-  __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
-  __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * 32 : 4];
-  __shared__ uint64_t lst[K::READS][ENT];
-  __shared__ int cnt[K::READS];
-  __shared__ float thr[K::READS];
+  const uint8_t* __restrict__ index = G.index;
+  const float* __restrict__ win_scale = G.win_scale;
+  const int64_t W = G.W;
+  const uint8_t* __restrict__ reads = G.reads;
+  const float* __restrict__ read_scale = G.read_scale;
+  const int32_t R = G.R;
+  const int64_t chunk_windows = G.chunk_windows;
+  const int P = G.P;
+  uint64_t* __restrict__ ws = G.lists;
+  uint32_t* __restrict__ gthr = G.gthr;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int g = lane >> 5;
   const int col = lane & 31;
-  const int chunk = blockIdx.x / read_tiles;
-  const int tile = blockIdx.x % read_tiles;
   const int64_t read0 = (int64_t)tile * K::READS;
   const int64_t wbeg = (int64_t)chunk * chunk_windows;
   const int64_t wend = min(W, wbeg + chunk_windows);
@@ -242,21 +245,14 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
       for (int u = 0; u < K::AU4; ++u) a[f][u] = make_uint4(0, 0, 0, 0);
     }
   }
-  // per (fragment, slot): s_r^2 and its inverse (FP8; 1 otherwise)
-  float rs2[NF][8], irs2[NF][8];
-#pragma unroll
-  for (int f = 0; f < NF; ++f)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      rs2[f][q] = 1.f;
-      irs2[f][q] = 1.f;
-      if constexpr (kFp8) {
-        int64_t r = read0 + (wave * NF + f) * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
-        float s = r < R ? read_scale[r] : 0.f;
-        rs2[f][q] = s * s;
-        irs2[f][q] = rs2[f][q] > 0.f ? 1.f / rs2[f][q] : 0.f;
-      }
+  // FP8: s_r^2 per read of the block, in LDS (1 otherwise)
+  if constexpr (kFp8) {
+    if (lane < NF * 16) {
+      int64_t r = read0 + rb0 + lane;
+      float sc = r < R ? read_scale[r] : 0.f;
+      rsq[rb0 + lane] = sc * sc;
     }
+  }
   // Wait for these loads here, before the tile loop: otherwise the compiler's
   // wait-count state from them reaches into the loop.
   {
@@ -266,6 +262,7 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
 #pragma unroll
       for (int u = 0; u < K::AU4; ++u) any |= a[f][u].x | a[f][u].w;
     __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
     if (any == 0xdeadbeefu && R < 0) ws[0] = any;  // never true; keeps the use
   }
 
@@ -317,7 +314,12 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
         int64_t r = read0 + rb;
         uint32_t gk = r < R ? __hip_atomic_load(&gthr[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         float gt = gk ? __uint_as_float(gk - 1u) : -1.f;
-        th[f][q] = fmaxf(thr[rb], gt) * irs2[f][q] * kLoose;
+        float t = fmaxf(thr[rb], gt);
+        if constexpr (kFp8) {
+          float r2 = rsq[rb];
+          t = r2 > 0.f ? t / r2 : 0.f;  // F-threshold in units of the product
+        }
+        th[f][q] = t * kLoose;
       }
   };
 
@@ -403,15 +405,11 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
 
     if (__ballot(ex > 0.f)) {
       uint32_t pend = 0;
-      float Fv[NF][8];
 #pragma unroll
       for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           float re = acc[f][2 * q], im = acc[f][2 * q + 1];
-          float F = re * re + im * im;
-          if constexpr (kFp8) F = F * (rs2[f][q] * sj2);
-          Fv[f][q] = F;
           float tq = th[f][q];
           if constexpr (kFp8) tq = tq * isj2;
           pend |= (uint32_t)(colok && __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)) > 0.f)
@@ -429,7 +427,10 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
               int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
               int pos = atomicAdd(&cnt[rb], 1);
               if (pos < K::CB) {
-                lst[rb][KP + pos] = make_key(Fv[f][q], j);
+                float re = acc[f][2 * q], im = acc[f][2 * q + 1];
+                float F = re * re + im * im;
+                if constexpr (kFp8) F = F * (rsq[rb] * sj2);
+                lst[rb][KP + pos] = make_key(F, j);
                 pend &= ~bit;
               }
             }
@@ -486,10 +487,44 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(
   }
 }
 
-// Shared per-read thresholds start with "no information" (0).
-__global__ void clear_thresholds(uint32_t* __restrict__ gthr, int32_t R) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < R) gthr[i] = 0u;
+// Persistent grouped kernel: a grid sized to the chip pulls work items
+// (group, chunk, read tile) from a device counter until all are done.  Items
+// are numbered chunk-major within each group, so concurrently running blocks
+// stream the same windows.  Every block leaves the loop once the counter has
+// passed the last item.
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
+__global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES>;
+  constexpr bool kFp8 = PREC == RM_FP8_E4M3;
+  __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
+  __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * 32 : 4];
+  __shared__ uint64_t lst[K::READS][ENT];
+  __shared__ int cnt[K::READS];
+  __shared__ float thr[K::READS];
+  __shared__ float rsq[kFp8 ? K::READS : 1];
+  __shared__ int s_item;
+  while (true) {
+    __syncthreads();  // the previous item is finished with s_item and all LDS
+    if (threadIdx.x == 0) s_item = atomicAdd(L.counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= L.total_items) break;
+    int gi = 0;
+    while (gi + 1 < L.n_groups && item >= L.g[gi + 1].item_begin) ++gi;
+    const ScoreGroup& G = L.g[gi];
+    const int local = item - G.item_begin;
+    score_item<PREC, NF, WAVES, KP, ENT, STAGES>(G, local / G.read_tiles, local % G.read_tiles,
+                                                  ring, ring_scale, lst, cnt, thr, rsq);
+  }
+}
+
+// Clears the work counter and every group's shared per-read thresholds
+// ("no information" = 0).
+__global__ void clear_state(ScoreLaunch L) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *L.counter = 0;
+  for (int gi = 0; gi < L.n_groups; ++gi)
+    if (i < L.g[gi].R) L.g[gi].gthr[i] = 0u;
 }
 
 // Merge the P per-chunk lists of each read into its k_fetch best: repeated
@@ -531,111 +566,165 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__
   }
 }
 
-struct Shape {
-  int nf, waves, kp, ent;
-};
-
-Shape shape_for(int precision, int k_fetch) {
-  int kp = k_fetch <= 8 ? 8 : k_fetch <= 16 ? 16 : 32;
-  int ent = kp <= 16 ? 32 : 64;
-  int nf = precision == RM_FP32 ? 1 : 2;
-  int waves = 8;
-  if (precision == RM_FP16 && kp == 32) waves = 4;
-  return {nf, waves, kp, ent};
-}
-
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
-hipError_t launch_one(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
-                      const float* read_scale, int32_t R, void* ws, hipStream_t s) {
-  unsigned blocks = (unsigned)plan.read_tiles * (unsigned)plan.chunks;
-  hipLaunchKernelGGL((score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES>), dim3(blocks),
-                     dim3(WAVES * 64), 0, s, static_cast<const uint8_t*>(idx.d_emb), idx.d_scale,
-                     idx.n_windows, static_cast<const uint8_t*>(read_emb), read_scale, R,
-                     plan.read_tiles, plan.chunk_windows, plan.chunks, static_cast<uint64_t*>(ws),
-                     reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws) + plan.thr_offset));
+template <int PREC, int NF, int KP, int ENT, int STAGES>
+hipError_t launch_persistent(const ScoreLaunch& L, hipStream_t s) {
+  constexpr int WAVES = 8;
+  auto kern = score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES>;
+  // resident blocks per CU for this instantiation (LDS and VGPR limited)
+  static int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, WAVES * 64, 0) != hipSuccess || n < 1)
+      n = 1;
+    return n;
+  }();
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  int64_t grid = (int64_t)per_cu * cus;
+  if (grid > L.total_items) grid = L.total_items;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(WAVES * 64), 0, s, L);
   return hipGetLastError();
 }
 
-// LDS per block: ring STAGES x 32 rows + lists READS x ENT x 8 B (+ FP8 scales),
-// kept within 160 KB.
-template <int PREC>
-hipError_t dispatch_kp(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
-                       const float* read_scale, int32_t R, void* ws, hipStream_t s) {
-  if constexpr (PREC == RM_FP32) {
-    switch (plan.kp) {
-      case 8: return launch_one<PREC, 1, 8, 8, 32, 3>(idx, plan, read_emb, read_scale, R, ws, s);
-      case 16: return launch_one<PREC, 1, 8, 16, 32, 3>(idx, plan, read_emb, read_scale, R, ws, s);
-      default: return launch_one<PREC, 1, 8, 32, 64, 2>(idx, plan, read_emb, read_scale, R, ws, s);
+// Instantiations: (precision, reads per block, list length) -> (fragments per
+// wavefront, list+buffer entries, ring stages); LDS stays within 160 KB.
+hipError_t dispatch(int precision, int read_tile, int kp, const ScoreLaunch& L, hipStream_t s) {
+  if (precision == RM_FP32) {
+    switch (kp) {
+      case 8: return launch_persistent<RM_FP32, 1, 8, 32, 3>(L, s);
+      case 16: return launch_persistent<RM_FP32, 1, 16, 32, 3>(L, s);
+      default: return launch_persistent<RM_FP32, 1, 32, 64, 2>(L, s);
     }
-  } else if constexpr (PREC == RM_FP16) {
-    switch (plan.kp) {
-      case 8: return launch_one<PREC, 2, 8, 8, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
-      case 16: return launch_one<PREC, 2, 8, 16, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
-      default: return launch_one<PREC, 2, 4, 32, 64, 4>(idx, plan, read_emb, read_scale, R, ws, s);
+  }
+  if (precision == RM_FP16) {
+    if (read_tile == 256) {
+      switch (kp) {
+        case 8: return launch_persistent<RM_FP16, 2, 8, 32, 4>(L, s);
+        default: return launch_persistent<RM_FP16, 2, 16, 32, 4>(L, s);
+      }
     }
-  } else {
-    switch (plan.kp) {
-      case 8: return launch_one<PREC, 2, 8, 8, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
-      case 16: return launch_one<PREC, 2, 8, 16, 32, 4>(idx, plan, read_emb, read_scale, R, ws, s);
-      default: return launch_one<PREC, 2, 8, 32, 64, 3>(idx, plan, read_emb, read_scale, R, ws, s);
+    switch (kp) {
+      case 8: return launch_persistent<RM_FP16, 1, 8, 32, 4>(L, s);
+      case 16: return launch_persistent<RM_FP16, 1, 16, 32, 4>(L, s);
+      default: return launch_persistent<RM_FP16, 1, 32, 64, 4>(L, s);
     }
+  }
+  if (read_tile == 256) {
+    switch (kp) {
+      case 8: return launch_persistent<RM_FP8_E4M3, 2, 8, 32, 4>(L, s);
+      case 16: return launch_persistent<RM_FP8_E4M3, 2, 16, 32, 4>(L, s);
+      default: return launch_persistent<RM_FP8_E4M3, 2, 32, 64, 3>(L, s);
+    }
+  }
+  switch (kp) {
+    case 8: return launch_persistent<RM_FP8_E4M3, 1, 8, 32, 4>(L, s);
+    case 16: return launch_persistent<RM_FP8_E4M3, 1, 16, 32, 4>(L, s);
+    default: return launch_persistent<RM_FP8_E4M3, 1, 32, 64, 4>(L, s);
   }
 }
 
 }  // namespace
 
-ScorePlan plan_score(int precision, int64_t W, int32_t n_reads, int32_t k_fetch) {
-  Shape sh = shape_for(precision, k_fetch);
+bool read_tile_ok(int precision, int kp, int read_tile) {
+  if (read_tile == 128) return true;
+  if (read_tile == 256) return precision != RM_FP32 && !(precision == RM_FP16 && kp == 32);
+  return false;
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_t* R, int k_fetch,
+                     Tuning t) {
   ScorePlan p{};
-  p.kp = sh.kp;
-  p.reads_per_block = sh.waves * sh.nf * 16;
-  p.read_tiles = (int)(((int64_t)n_reads + p.reads_per_block - 1) / p.reads_per_block);
-  // Enough blocks to fill 256 CUs several times, chunks of at least 64 tiles,
-  // and at most 1024 keys per read for the merge.
-  int64_t target_blocks = 256 * 8;
-  int64_t P = (target_blocks + p.read_tiles - 1) / p.read_tiles;
-  int64_t max_by_len = (W + 64 * kTileW - 1) / (64 * kTileW);
-  if (P > max_by_len) P = max_by_len;
-  if (P > 1024 / sh.kp) P = 1024 / sh.kp;
-  if (P < 1) P = 1;
-  int64_t cw = (W + P - 1) / P;
-  cw = (cw + kTileW - 1) / kTileW * kTileW;
-  if (cw < kTileW) cw = kTileW;
-  p.chunk_windows = cw;
-  p.chunks = (int)((W + cw - 1) / cw);
-  if (p.chunks < 1) p.chunks = 1;
-  size_t lists = (size_t)n_reads * (size_t)p.chunks * (size_t)p.kp * sizeof(uint64_t);
-  p.thr_offset = (lists + 255) / 256 * 256;
-  p.ws_bytes = p.thr_offset + (size_t)n_reads * sizeof(uint32_t);
+  p.kp = k_fetch <= 8 ? 8 : k_fetch <= 16 ? 16 : 32;
+  int rt = t.read_tile;
+  if (rt == 0) rt = read_tile_ok(precision, p.kp, 256) ? 256 : 128;
+  if (!read_tile_ok(precision, p.kp, rt) || n_groups < 1 || n_groups > kMaxGroups) return p;
+  p.read_tile = rt;
+  p.n_groups = n_groups;
+  size_t off = 0;
+  int64_t items = 0;
+  for (int i = 0; i < n_groups; ++i) {
+    GroupPlan& gp = p.g[i];
+    gp.read_tiles = (int)(((int64_t)R[i] + rt - 1) / rt);
+    int64_t tiles = (W[i] + kTileW - 1) / kTileW;
+    int64_t ct = t.chunk_tiles;
+    if (ct <= 0) {
+      // enough items to fill 256 CUs several times, at least 64 tiles each,
+      // at most 1024 keys per read for the merge
+      int64_t P = (256 * 8 + gp.read_tiles - 1) / gp.read_tiles;
+      if (P > (tiles + 63) / 64) P = (tiles + 63) / 64;
+      if (P < 1) P = 1;
+      ct = (tiles + P - 1) / P;
+    }
+    if (ct < 1) ct = 1;
+    int64_t P = (tiles + ct - 1) / ct;
+    if (P > 1024 / p.kp) {  // keep the merge within 1024 keys per read
+      P = 1024 / p.kp;
+      ct = (tiles + P - 1) / P;
+      P = (tiles + ct - 1) / ct;
+    }
+    gp.chunk_windows = ct * kTileW;
+    gp.chunks = (int)P;
+    gp.lists_offset = off;
+    off = align256(off + (size_t)R[i] * (size_t)P * (size_t)p.kp * sizeof(uint64_t));
+    gp.thr_offset = off;
+    off = align256(off + (size_t)R[i] * sizeof(uint32_t));
+    items += (int64_t)gp.read_tiles * P;
+  }
+  p.counter_offset = off;
+  p.ws_bytes = off + 256;
+  p.total_items = items;
+  p.ok = items > 0 && items < INT32_MAX;
   return p;
 }
 
-hipError_t launch_score_topk(const rm_index& idx, const ScorePlan& plan, const void* read_emb,
-                             const float* read_scale, int32_t n_reads, int32_t k_fetch,
-                             int32_t* cand_idx, float* cand_score, void* ws, hipStream_t s) {
-  hipLaunchKernelGGL(clear_thresholds, dim3((unsigned)(((int64_t)n_reads + 255) / 256)), dim3(256),
-                     0, s, reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws) + plan.thr_offset),
-                     n_reads);
+hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
+                             const void* const* read_emb, const float* const* read_scale,
+                             const int32_t* R, int k_fetch, int32_t* const* cand_idx,
+                             float* const* cand_score, void* ws, hipStream_t s) {
+  uint8_t* base = static_cast<uint8_t*>(ws);
+  ScoreLaunch L{};
+  L.n_groups = plan.n_groups;
+  L.total_items = (int32_t)plan.total_items;
+  L.counter = reinterpret_cast<int*>(base + plan.counter_offset);
+  int32_t item = 0;
+  int32_t maxR = 0;
+  for (int i = 0; i < plan.n_groups; ++i) {
+    const GroupPlan& gp = plan.g[i];
+    ScoreGroup& G = L.g[i];
+    G.index = static_cast<const uint8_t*>(idx[i].d_emb);
+    G.win_scale = idx[i].d_scale;
+    G.W = idx[i].n_windows;
+    G.reads = static_cast<const uint8_t*>(read_emb[i]);
+    G.read_scale = read_scale ? read_scale[i] : nullptr;
+    G.R = R[i];
+    G.read_tiles = gp.read_tiles;
+    G.chunk_windows = gp.chunk_windows;
+    G.P = gp.chunks;
+    G.item_begin = item;
+    G.lists = reinterpret_cast<uint64_t*>(base + gp.lists_offset);
+    G.gthr = reinterpret_cast<uint32_t*>(base + gp.thr_offset);
+    item += gp.read_tiles * gp.chunks;
+    if (R[i] > maxR) maxR = R[i];
+  }
+  hipLaunchKernelGGL(clear_state, dim3((unsigned)(((int64_t)maxR + 255) / 256)), dim3(256), 0, s, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  switch (idx.p.precision) {
-    case RM_FP32:
-      e = dispatch_kp<RM_FP32>(idx, plan, read_emb, read_scale, n_reads, ws, s);
-      break;
-    case RM_FP16:
-      e = dispatch_kp<RM_FP16>(idx, plan, read_emb, read_scale, n_reads, ws, s);
-      break;
-    default:
-      e = dispatch_kp<RM_FP8_E4M3>(idx, plan, read_emb, read_scale, n_reads, ws, s);
-      break;
-  }
+  e = dispatch(idx[0].p.precision, plan.read_tile, plan.kp, L, s);
   if (e != hipSuccess) return e;
-  int n_per_read = plan.chunks * plan.kp;
-  unsigned blocks = (unsigned)(((int64_t)n_reads + 3) / 4);
-  hipLaunchKernelGGL(merge_kernel, dim3(blocks), dim3(256), 0, s,
-                     static_cast<const uint64_t*>(ws), n_per_read, n_reads, k_fetch, cand_idx,
-                     cand_score);
-  return hipGetLastError();
+  for (int i = 0; i < plan.n_groups; ++i) {
+    int n_per_read = plan.g[i].chunks * plan.kp;
+    unsigned blocks = (unsigned)(((int64_t)R[i] + 3) / 4);
+    hipLaunchKernelGGL(merge_kernel, dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const uint64_t*>(base + plan.g[i].lists_offset), n_per_read,
+                       R[i], k_fetch, cand_idx[i], cand_score[i]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rm

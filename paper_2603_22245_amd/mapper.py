@@ -129,3 +129,129 @@ def map_reads(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
     encode_reads(index, reads, stream)
     score_topk(index, reads, bufs, stream)
     rescore(index, reads, bufs, stream)
+
+
+# ---------------------------------------------------------------- batching
+
+BUCKETS = (100, 200, 400, 800, 1600, 3200, 6400)
+
+
+@dataclasses.dataclass
+class Bucket:
+    length: int            # head length N_b (the bucket's window length)
+    stride: int
+    read_ids: np.ndarray   # indices of the batch's reads in this bucket
+    index: Index
+    reads: ReadBatch
+    bufs: MapBuffers
+
+
+class BatchMapper:
+    """Reads of uneven length: one index per head length (bucket), every bucket's
+    reads scored against its index in one persistent launch (rm_score_topk_groups),
+    then FP32 rescore per bucket.  Buckets without reads are skipped; reads shorter
+    than the smallest bucket are left unmapped (id -1)."""
+
+    def __init__(self, ref: np.ndarray, seq: np.ndarray, offsets: np.ndarray, k: int = 8,
+                 k_fetch: int = 16, precision: str = "fp16", buckets=BUCKETS,
+                 stride_div: int = 100, device="cuda"):
+        torch = _torch()
+        self.k, self.k_fetch, self.precision = k, k_fetch, precision
+        self.n_reads = int(offsets.shape[0] - 1)
+        bucket_of, count = L.rm_bucket_reads(offsets, buckets)
+        self.bucket_of = bucket_of
+        self.buckets = []
+        for b, n_b in enumerate(buckets):
+            ids = np.nonzero(bucket_of == b)[0]
+            if ids.size == 0:
+                continue
+            stride = max(1, n_b // stride_div)
+            index = build_index(ref, window_len=n_b, stride=stride, precision=precision,
+                                device=device)
+            # this bucket's reads, concatenated (each keeps all its letters)
+            lens = offsets[ids + 1] - offsets[ids]
+            off = np.zeros(ids.size + 1, dtype=np.int64)
+            np.cumsum(lens, out=off[1:])
+            parts = [seq[offsets[i]:offsets[i + 1]] for i in ids]
+            bseq = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+            rb = upload_reads(index, bseq, off, device)
+            bufs = map_buffers(index, ids.size, k, k_fetch, device)
+            self.buckets.append(Bucket(n_b, stride, ids, index, rb, bufs))
+        self.tune = None
+        self.ws_bytes = self._ws_bytes(None)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.graph = None
+
+    def _ws_bytes(self, tune):
+        return L.rm_score_groups_workspace_bytes([b.index.idx for b in self.buckets],
+                                                 [b.reads.n for b in self.buckets],
+                                                 self.k_fetch, tune)
+
+    def _group_args(self):
+        bs = self.buckets
+        return ([b.index.idx for b in bs], [b.reads.emb for b in bs],
+                [b.reads.scale for b in bs], [b.reads.n for b in bs], self.k_fetch,
+                [b.bufs.cand_idx for b in bs], [b.bufs.cand_score for b in bs])
+
+    def autotune(self, cache_path=None, stream=None):
+        """Pick the scoring launch's tile shape by timing candidates on these inputs
+        (reads must be encoded first)."""
+        torch = _torch()
+        # the largest candidate workspace: 128-read tiles and the smallest chunks
+        need = max(self._ws_bytes(L.rm_tuning(rt, ct)) for rt in (128, 256)
+                   for ct in (0, 128, 512, 2048, 8192))
+        if need > self.ws.numel():
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.ws.device)
+        idxs, emb, scale, nr, kf, ci, cs = self._group_args()
+        best, ms = L.rm_autotune_score(idxs, emb, scale, nr, kf, ci, cs, self.ws, self.ws.numel(),
+                                       cache_path, stream)
+        self.tune = best
+        self.ws_bytes = self._ws_bytes(best)
+        return best, ms
+
+    def encode(self, stream=None):
+        for b in self.buckets:
+            encode_reads(b.index, b.reads, stream)
+
+    def score(self, stream=None):
+        idxs, emb, scale, nr, kf, ci, cs = self._group_args()
+        L.rm_score_topk_groups(idxs, emb, scale, nr, kf, ci, cs, self.ws, self.ws_bytes, self.tune,
+                               stream)
+
+    def rescore(self, stream=None):
+        for b in self.buckets:
+            rescore(b.index, b.reads, b.bufs, stream)
+
+    def run(self, stream=None):
+        self.encode(stream)
+        self.score(stream)
+        self.rescore(stream)
+
+    def capture(self, stream):
+        """Record run() on `stream` (not the null stream) into a HIP graph."""
+        if self.graph is not None:
+            L.rm_graph_destroy(self.graph)
+        L.rm_capture_begin(stream)
+        try:
+            self.run(stream)
+        finally:
+            self.graph = L.rm_capture_end(stream)
+        return self.graph
+
+    def replay(self, stream):
+        L.rm_graph_launch(self.graph, stream)
+
+    def results(self):
+        """Top-k window ids and FP32 scores of every read (id -1 for unmapped reads),
+        and each read's bucket index."""
+        ids = np.full((self.n_reads, self.k), -1, dtype=np.int32)
+        sc = np.full((self.n_reads, self.k), -1.0, dtype=np.float32)
+        for b in self.buckets:
+            ids[b.read_ids] = b.bufs.top_idx.cpu().numpy()
+            sc[b.read_ids] = b.bufs.top_score.cpu().numpy()
+        return ids, sc
+
+    def close(self):
+        if self.graph is not None:
+            L.rm_graph_destroy(self.graph)
+            self.graph = None
