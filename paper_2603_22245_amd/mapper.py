@@ -54,12 +54,15 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
                 reanchor=0, stream=None, device="cuda") -> Index:
     torch = _torch()
     p = L.make_params(window_len, stride, L.RM_DIM, schedule, precision, reanchor)
-    d_ref = torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device)
-    nbytes = L.rm_index_bytes(int(ref.shape[0]), p)
+    if isinstance(ref, np.ndarray):
+        d_ref = torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device)
+    else:  # already a device tensor
+        d_ref = ref
+    nbytes = L.rm_index_bytes(int(d_ref.numel()), p)
     if nbytes == 0:
         raise L.RotorMapError(L.RM_ESIZE, "rm_index_bytes")
     buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    idx = L.rm_encode_reference(d_ref, int(ref.shape[0]), p, buf, nbytes, stream)
+    idx = L.rm_encode_reference(d_ref, int(d_ref.numel()), p, buf, nbytes, stream)
     return Index(p, idx, buf, d_ref)
 
 
@@ -161,12 +164,13 @@ class BatchMapper:
         bucket_of, count = L.rm_bucket_reads(offsets, buckets)
         self.bucket_of = bucket_of
         self.buckets = []
+        d_ref = torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device)
         for b, n_b in enumerate(buckets):
             ids = np.nonzero(bucket_of == b)[0]
             if ids.size == 0:
                 continue
             stride = max(1, n_b // stride_div)
-            index = build_index(ref, window_len=n_b, stride=stride, precision=precision,
+            index = build_index(d_ref, window_len=n_b, stride=stride, precision=precision,
                                 device=device)
             # this bucket's reads, concatenated (each keeps all its letters)
             lens = offsets[ids + 1] - offsets[ids]
@@ -209,6 +213,13 @@ class BatchMapper:
         self.ws_bytes = self._ws_bytes(best)
         return best, ms
 
+    def rebuild_indexes(self, stream=None):
+        """Re-encode every bucket's index in place (same buffers)."""
+        for b in self.buckets:
+            idx = L.rm_encode_reference(b.index.ref, int(b.index.ref.numel()), b.index.params,
+                                        b.index.buf, b.index.buf.numel(), stream)
+            b.index.idx = idx
+
     def encode(self, stream=None):
         for b in self.buckets:
             encode_reads(b.index, b.reads, stream)
@@ -227,12 +238,15 @@ class BatchMapper:
         self.score(stream)
         self.rescore(stream)
 
-    def capture(self, stream):
-        """Record run() on `stream` (not the null stream) into a HIP graph."""
+    def capture(self, stream, with_index=False):
+        """Record run() (preceded by the index builds if with_index) on `stream`
+        (not the null stream) into a HIP graph."""
         if self.graph is not None:
             L.rm_graph_destroy(self.graph)
         L.rm_capture_begin(stream)
         try:
+            if with_index:
+                self.rebuild_indexes(stream)
             self.run(stream)
         finally:
             self.graph = L.rm_capture_end(stream)
