@@ -233,6 +233,73 @@ int rm_capture_end(void* stream, rm_graph* out);
 int rm_graph_launch(rm_graph graph, void* stream);
 int rm_graph_destroy(rm_graph graph);
 
+/* ---- learned angle offsets ------------------------------------------------
+ * Not in the paper, which notes that token definitions, initial encodings or
+ * rotations could be altered (§2.10).  Tokens are 9-mers at locations
+ * p = 0..n-9 (s-mer locations, §2.1); the middle letter L selects the
+ * component; the 8 flanking letters, one-hot (32 inputs), feed
+ * o = W2 relu(W1 x + b1) + b2 (128 outputs = 4 letters x 32 factors); the token
+ * adds exp(i (theta_k p + o[L*32 + k])) to component (k, L), theta_k =
+ * 2 pi (k+1) / N with N the nominal length (§2.2).  With W2 = b2 = 0 this is
+ * the plain encoding of w[4 .. n-4).  Parameters: W1 [64][32], b1 [64],
+ * W2 [128][64], b2 [128], row-major FP32 (RM_LEARNED_PARAMS values).
+ * Training: fidelity (§2.4) of string pairs, pairwise logistic ranking loss
+ * softplus(-(F_i - F_j)/0.05) averaged over pairs with Levenshtein label
+ * d_i < d_j (§1), Adam (beta 0.9 / 0.999, eps 1e-8). */
+
+#define RM_LEARNED_PARAMS 10432
+#define RM_LEARNED_MAX_LEN 256    /* letters of a string the learned kernels use */
+#define RM_LEARNED_MAX_PAIRS 1024 /* pairs per training step */
+
+/* Workspace bytes of rm_learned_train_step / rm_learned_gradient for n_pairs
+ * pairs; 0 if n_pairs is outside 2..RM_LEARNED_MAX_PAIRS. */
+size_t rm_learned_workspace_bytes(int32_t n_pairs);
+
+/* Encodings of n_strings strings (string s = d_seq[d_off[s] .. d_off[s+1]),
+ * device memory) into d_c [n_strings][256] floats (component k*4 + letter,
+ * re/im interleaved), FP32, unnormalised.  d_params non-null: the learned
+ * encoding above, of the first RM_LEARNED_MAX_LEN letters.  d_params null: the
+ * plain encoding (§2.2, s = 1, f_k = k) of the whole string, the baseline the
+ * learned one is compared with.  nominal_len is N of the phases.
+ * Errors: RM_EINVAL (null pointer), RM_ESIZE (n_strings < 1, nominal_len < 1). */
+int rm_learned_encode(const float* d_params, const uint8_t* d_seq, const int64_t* d_off,
+                      int32_t n_strings, int32_t nominal_len, float* d_c, void* stream);
+
+/* Fidelity (§2.4) of pairs of encodings: d_F[i] = F(d_ca[i], d_cb[i]), rows of
+ * 256 floats as written by rm_learned_encode; 0 if either vector is zero.
+ * Errors: RM_EINVAL, RM_ESIZE (n_pairs < 1). */
+int rm_pair_fidelity(const float* d_ca, const float* d_cb, int32_t n_pairs, float* d_F,
+                     void* stream);
+
+/* One Adam step of the network on n_pairs pairs (a_i, b_i) = (d_a[d_aoff[i] ..
+ * d_aoff[i+1]), d_b[d_boff[i] .. d_boff[i+1])) with labels d_ld[i] (edit
+ * distances; only their order matters).  d_state = [params | m | v | step],
+ * 3 * RM_LEARNED_PARAMS + 1 floats of device memory owned by the caller (start
+ * with m = v = step = 0); the step count lives there, so a captured sequence
+ * of calls can be replayed.  *d_loss (device) receives the batch loss before
+ * the update.  d_ws: ws_bytes >= rm_learned_workspace_bytes(n_pairs).
+ * Errors: RM_EINVAL (null pointer), RM_ESIZE (n_pairs outside
+ * 2..RM_LEARNED_MAX_PAIRS, nominal_len < 1, workspace too small). */
+int rm_learned_train_step(float* d_state, float lr, const uint8_t* d_a, const int64_t* d_aoff,
+                          const uint8_t* d_b, const int64_t* d_boff, const int32_t* d_ld,
+                          int32_t n_pairs, int32_t nominal_len, void* d_ws, size_t ws_bytes,
+                          float* d_loss, void* stream);
+
+/* The loss and its gradient with respect to the parameters (no update):
+ * d_grad [RM_LEARNED_PARAMS], *d_loss.  Arguments and errors as above. */
+int rm_learned_gradient(const float* d_params, const uint8_t* d_a, const int64_t* d_aoff,
+                        const uint8_t* d_b, const int64_t* d_boff, const int32_t* d_ld,
+                        int32_t n_pairs, int32_t nominal_len, void* d_ws, size_t ws_bytes,
+                        float* d_grad, float* d_loss, void* stream);
+
+/* Exact Levenshtein distance (unit costs) of n pairs (a_i, b_i), device
+ * memory, into d_out[i] (int32): the labels of the ranking loss and the
+ * reference for rank correlations.  Letters must be codes 0..3 (any other code
+ * matches nothing, itself included).  The shorter string of a pair may have at
+ * most 256 letters; a longer one gives -1.  Errors: RM_EINVAL, RM_ESIZE (n < 1). */
+int rm_levenshtein(const uint8_t* d_a, const int64_t* d_aoff, const uint8_t* d_b,
+                   const int64_t* d_boff, int64_t n, int32_t* d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,9 @@ class rm_tuning(ctypes.Structure):
 
 
 RM_MAX_GROUPS = 8
+RM_LEARNED_PARAMS = 10432
+RM_LEARNED_MAX_LEN = 256
+RM_LEARNED_MAX_PAIRS = 1024
 
 
 class RotorMapError(RuntimeError):
@@ -83,6 +86,13 @@ def lib():
             "rm_capture_end": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_void_p)]),
             "rm_graph_launch": (ctypes.c_int, [P, P]),
             "rm_graph_destroy": (ctypes.c_int, [P]),
+            "rm_learned_workspace_bytes": (SZ, [I32]),
+            "rm_learned_encode": (ctypes.c_int, [P, P, P, I32, I32, P, P]),
+            "rm_pair_fidelity": (ctypes.c_int, [P, P, I32, P, P]),
+            "rm_learned_train_step": (ctypes.c_int, [P, ctypes.c_float, P, P, P, P, P, I32, I32,
+                                                     P, SZ, P, P]),
+            "rm_learned_gradient": (ctypes.c_int, [P, P, P, P, P, P, I32, I32, P, SZ, P, P, P]),
+            "rm_levenshtein": (ctypes.c_int, [P, P, P, P, I64, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -256,3 +266,39 @@ def rm_graph_launch(graph: int, stream=None) -> None:
 
 def rm_graph_destroy(graph: int) -> None:
     _check(lib().rm_graph_destroy(graph), "rm_graph_destroy")
+
+
+def rm_learned_workspace_bytes(n_pairs: int) -> int:
+    return int(lib().rm_learned_workspace_bytes(n_pairs))
+
+
+def rm_learned_encode(d_params, d_seq, d_off, n_strings: int, nominal_len: int, d_c,
+                      stream=None) -> None:
+    _check(lib().rm_learned_encode(_ptr(d_params), _ptr(d_seq), _ptr(d_off), n_strings,
+                                   nominal_len, _ptr(d_c), _stream(stream)), "rm_learned_encode")
+
+
+def rm_pair_fidelity(d_ca, d_cb, n_pairs: int, d_F, stream=None) -> None:
+    _check(lib().rm_pair_fidelity(_ptr(d_ca), _ptr(d_cb), n_pairs, _ptr(d_F), _stream(stream)),
+           "rm_pair_fidelity")
+
+
+def rm_learned_train_step(d_state, lr: float, d_a, d_aoff, d_b, d_boff, d_ld, n_pairs: int,
+                          nominal_len: int, d_ws, ws_bytes: int, d_loss, stream=None) -> None:
+    _check(lib().rm_learned_train_step(_ptr(d_state), lr, _ptr(d_a), _ptr(d_aoff), _ptr(d_b),
+                                       _ptr(d_boff), _ptr(d_ld), n_pairs, nominal_len, _ptr(d_ws),
+                                       ws_bytes, _ptr(d_loss), _stream(stream)),
+           "rm_learned_train_step")
+
+
+def rm_learned_gradient(d_params, d_a, d_aoff, d_b, d_boff, d_ld, n_pairs: int, nominal_len: int,
+                        d_ws, ws_bytes: int, d_grad, d_loss, stream=None) -> None:
+    _check(lib().rm_learned_gradient(_ptr(d_params), _ptr(d_a), _ptr(d_aoff), _ptr(d_b),
+                                     _ptr(d_boff), _ptr(d_ld), n_pairs, nominal_len, _ptr(d_ws),
+                                     ws_bytes, _ptr(d_grad), _ptr(d_loss), _stream(stream)),
+           "rm_learned_gradient")
+
+
+def rm_levenshtein(d_a, d_aoff, d_b, d_boff, n: int, d_out, stream=None) -> None:
+    _check(lib().rm_levenshtein(_ptr(d_a), _ptr(d_aoff), _ptr(d_b), _ptr(d_boff), n, _ptr(d_out),
+                                _stream(stream)), "rm_levenshtein")

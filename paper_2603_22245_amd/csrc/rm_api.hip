@@ -249,6 +249,71 @@ int rm_score_topk_groups(const rm_index* idx, int32_t n_groups, const void* cons
                                           static_cast<hipStream_t>(stream)));
 }
 
+// ------------------------------------------------------------------ learned offsets
+
+size_t rm_learned_workspace_bytes(int32_t n_pairs) {
+  if (n_pairs < 2 || n_pairs > RM_LEARNED_MAX_PAIRS) return 0;
+  return rm::learned_workspace_bytes(n_pairs);
+}
+
+int rm_learned_encode(const float* d_params, const uint8_t* d_seq, const int64_t* d_off,
+                      int32_t n_strings, int32_t nominal_len, float* d_c, void* stream) {
+  if (!d_seq || !d_off || !d_c) return RM_EINVAL;
+  if (n_strings < 1 || nominal_len < 1) return RM_ESIZE;
+  return hip_status(rm::launch_learned_encode(d_params, d_seq, d_off, n_strings, nominal_len, d_c,
+                                              static_cast<hipStream_t>(stream)));
+}
+
+int rm_pair_fidelity(const float* d_ca, const float* d_cb, int32_t n_pairs, float* d_F,
+                     void* stream) {
+  if (!d_ca || !d_cb || !d_F) return RM_EINVAL;
+  if (n_pairs < 1) return RM_ESIZE;
+  return hip_status(
+      rm::launch_pair_fidelity(d_ca, d_cb, n_pairs, d_F, static_cast<hipStream_t>(stream)));
+}
+
+static int learned_args_ok(const void* p, const uint8_t* a, const int64_t* aoff, const uint8_t* b,
+                           const int64_t* boff, const int32_t* ld, int32_t n_pairs,
+                           int32_t nominal_len, void* ws, size_t ws_bytes, const float* loss) {
+  if (!p || !a || !aoff || !b || !boff || !ld || !ws || !loss) return RM_EINVAL;
+  if (n_pairs < 2 || n_pairs > RM_LEARNED_MAX_PAIRS || nominal_len < 1) return RM_ESIZE;
+  if (ws_bytes < rm::learned_workspace_bytes(n_pairs)) return RM_ESIZE;
+  return RM_OK;
+}
+
+int rm_learned_train_step(float* d_state, float lr, const uint8_t* d_a, const int64_t* d_aoff,
+                          const uint8_t* d_b, const int64_t* d_boff, const int32_t* d_ld,
+                          int32_t n_pairs, int32_t nominal_len, void* d_ws, size_t ws_bytes,
+                          float* d_loss, void* stream) {
+  int st = learned_args_ok(d_state, d_a, d_aoff, d_b, d_boff, d_ld, n_pairs, nominal_len, d_ws,
+                           ws_bytes, d_loss);
+  if (st != RM_OK) return st;
+  return hip_status(rm::launch_learned_step(d_state, lr, d_a, d_aoff, d_b, d_boff, d_ld, n_pairs,
+                                            nominal_len, d_ws, nullptr, d_loss,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+int rm_learned_gradient(const float* d_params, const uint8_t* d_a, const int64_t* d_aoff,
+                        const uint8_t* d_b, const int64_t* d_boff, const int32_t* d_ld,
+                        int32_t n_pairs, int32_t nominal_len, void* d_ws, size_t ws_bytes,
+                        float* d_grad, float* d_loss, void* stream) {
+  int st = learned_args_ok(d_params, d_a, d_aoff, d_b, d_boff, d_ld, n_pairs, nominal_len, d_ws,
+                           ws_bytes, d_loss);
+  if (st != RM_OK) return st;
+  if (!d_grad) return RM_EINVAL;
+  return hip_status(rm::launch_learned_step(const_cast<float*>(d_params), 0.f, d_a, d_aoff, d_b,
+                                            d_boff, d_ld, n_pairs, nominal_len, d_ws, d_grad,
+                                            d_loss, static_cast<hipStream_t>(stream)));
+}
+
+int rm_levenshtein(const uint8_t* d_a, const int64_t* d_aoff, const uint8_t* d_b,
+                   const int64_t* d_boff, int64_t n, int32_t* d_out, void* stream) {
+  if (!d_a || !d_aoff || !d_b || !d_boff || !d_out) return RM_EINVAL;
+  if (n < 1) return RM_ESIZE;
+  return hip_status(rm::launch_levenshtein(d_a, d_aoff, d_b, d_boff, n, d_out,
+                                           static_cast<hipStream_t>(stream)));
+}
+
 // ------------------------------------------------------------------ graphs
 
 struct rm_graph_s {
@@ -269,13 +334,13 @@ int rm_capture_end(void* stream, rm_graph* out) {
     return RM_EHIP;
   hipGraphExec_t ex = nullptr;
   if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return RM_EHIP;
   }
   rm_graph h = new (std::nothrow) rm_graph_s{g, ex};
   if (h == nullptr) {
-    hipGraphExecDestroy(ex);
-    hipGraphDestroy(g);
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
     return RM_EHIP;
   }
   *out = h;
@@ -289,8 +354,8 @@ int rm_graph_launch(rm_graph graph, void* stream) {
 
 int rm_graph_destroy(rm_graph graph) {
   if (graph == nullptr) return RM_EINVAL;
-  hipGraphExecDestroy(graph->exec);
-  hipGraphDestroy(graph->graph);
+  (void)hipGraphExecDestroy(graph->exec);
+  (void)hipGraphDestroy(graph->graph);
   delete graph;
   return RM_OK;
 }

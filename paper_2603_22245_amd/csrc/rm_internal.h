@@ -140,6 +140,18 @@ hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
                              const int32_t* R, int k_fetch, int32_t* const* cand_idx,
                              float* const* cand_score, void* ws, hipStream_t s);
 
+size_t learned_workspace_bytes(int32_t n_pairs);
+hipError_t launch_learned_encode(const float* params, const uint8_t* seq, const int64_t* off,
+                                 int32_t n_strings, int N, float* out, hipStream_t s);
+hipError_t launch_pair_fidelity(const float* ca, const float* cb, int32_t n_pairs, float* F,
+                                hipStream_t s);
+hipError_t launch_learned_step(float* state, float lr, const uint8_t* a, const int64_t* aoff,
+                               const uint8_t* b, const int64_t* boff, const int32_t* ld,
+                               int32_t n_pairs, int N, void* ws, float* grad_out,
+                               float* loss_out, hipStream_t s);
+hipError_t launch_levenshtein(const uint8_t* a, const int64_t* aoff, const uint8_t* b,
+                              const int64_t* boff, int64_t n, int32_t* out, hipStream_t s);
+
 hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                           const int64_t* off, int32_t n_reads, int32_t k_fetch,
                           const int32_t* cand_idx, int32_t k, int32_t* top_idx, float* top_score,
