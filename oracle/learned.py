@@ -82,19 +82,53 @@ def tokens(w):
     return mid, x
 
 
-def forward_string(params, w, N: int, m: int = 32):
-    """Learned encoding c (complex [4m], order k*4 + letter) and the cache for backward."""
+def bf16_round(x) -> np.ndarray:
+    """Round to the nearest bfloat16 (8 significant bits, ties to even), as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _network(params, x, bf16: bool):
+    """Pre-activations, hidden values and outputs of the network for inputs x [T, 32].
+    bf16: the inference arithmetic -- both weight matrices and the hidden values
+    rounded to bfloat16, biases and sums exact."""
     W1, b1, W2, b2 = unpack(params)
-    mid, x = tokens(w)
+    if bf16:
+        W1, W2 = bf16_round(W1), bf16_round(W2)
     pre = x @ W1.T + b1                      # [T, 64]
     h = np.maximum(pre, 0.0)
+    if bf16:
+        h = bf16_round(h)
     o = h @ W2.T + b2                        # [T, 128]
+    return pre, h, o
+
+
+def select_offsets(mid, o, m: int = 32) -> np.ndarray:
+    """delta [T, m]: the middle letter's m outputs (zero where it is not A,C,G,T)."""
     T = mid.shape[0]
-    theta = 2 * np.pi * rope.frequencies(m) / N
     ok = mid < 4
     rows = np.arange(T)
     delta = np.zeros((T, m))
     delta[ok] = o[rows[ok, None], (mid[ok] * m)[:, None] + np.arange(m)[None, :]]
+    return delta
+
+
+def token_offsets(params, w, bf16: bool = False, m: int = 32):
+    """Middle letters [T] and phase offsets delta [T, m] of the 9-mer tokens of w."""
+    mid, x = tokens(w)
+    _, _, o = _network(params, x, bf16)
+    return mid, select_offsets(mid, o, m)
+
+
+def forward_string(params, w, N: int, m: int = 32):
+    """Learned encoding c (complex [4m], order k*4 + letter) and the cache for backward."""
+    mid, x = tokens(w)
+    pre, h, o = _network(params, x, False)
+    T = mid.shape[0]
+    theta = 2 * np.pi * rope.frequencies(m) / N
+    delta = select_offsets(mid, o, m)
     phi = np.arange(T)[:, None] * theta[None, :] + delta      # [T, m]
     u = np.exp(1j * phi)
     c = np.zeros((m, 4), dtype=np.complex128)
@@ -191,3 +225,93 @@ def pair_fidelities(params, pairs, N: int, m: int = 32) -> np.ndarray:
         cb, _ = forward_string(params, b, N, m)
         out[i] = fidelity_and_grads(ca, cb)[0]
     return out
+
+
+# --------------------------------------------------------------------------
+# Mapping with the learned encoding (inference arithmetic: bf16=True).  A
+# token's offsets depend only on its 9 letters, so the reference's tokens are
+# evaluated once and every window sums its own N-8 tokens: window j (start s)
+# has c_(k,L) = sum over p = 0..N-9 with w[s+p+4] = L of
+# exp(i (theta_k p + delta_(s+p,k))).  A read head is encoded the same way
+# from its first N letters.
+
+
+def window_encodings(params, ref, starts, N: int, bf16: bool = True, m: int = 32,
+                     ref_offsets=None) -> np.ndarray:
+    """Learned encodings [len(starts), 4m] of the windows w[s, s+N)."""
+    mid, delta = ref_offsets if ref_offsets is not None else token_offsets(params, ref, bf16, m)
+    starts = np.asarray(starts, dtype=np.int64)
+    theta = 2 * np.pi * rope.frequencies(m) / N
+    C = np.zeros((starts.shape[0], m, 4), dtype=np.complex128)
+    rows = np.arange(starts.shape[0])
+    for p in range(N - 2 * CTX):
+        t = starts + p
+        u = np.exp(1j * (p * theta[None, :] + delta[t]))          # [W, m]
+        L = mid[t]
+        for letter in range(4):
+            sel = L == letter
+            C[rows[sel], :, letter] += u[sel]
+    return C.reshape(starts.shape[0], 4 * m)
+
+
+def head_encodings(params, heads, N: int, bf16: bool = True, m: int = 32) -> np.ndarray:
+    """Learned encodings [R, 4m] of read heads [R, N] (each its own string)."""
+    out = np.zeros((heads.shape[0], 4 * m), dtype=np.complex128)
+    for r in range(heads.shape[0]):
+        out[r] = window_encodings(params, heads[r], [0], N, bf16, m)[0]
+    return out
+
+
+def map_reads(params, ref, heads, N: int, k: int = 8, bf16: bool = True, m: int = 32,
+              chunk: int = 16384, window_range=None):
+    """Exact top-k windows of every read head under the learned encoding, by
+    brute force over all windows (ranking as in the plain mapping)."""
+    from . import mapping
+    W = mapping.n_windows(ref.shape[0], N)
+    lo, hi = (0, W) if window_range is None else window_range
+    offs = token_offsets(params, ref, bf16, m)
+    Xn, _ = mapping.normalized_rows(head_encodings(params, heads, N, bf16, m), N)
+    R = Xn.shape[0]
+    best_i = np.full((R, 0), -1, dtype=np.int64)
+    best_f = np.zeros((R, 0))
+    for a in range(lo, hi, chunk):
+        b = min(hi, a + chunk)
+        ids = np.arange(a, b, dtype=np.int64)
+        Cn, _ = mapping.normalized_rows(window_encodings(params, ref, ids, N, bf16, m, offs), N)
+        F = mapping.fidelity_matrix(Xn, Cn)
+        allF = np.concatenate([best_f, F], axis=1)
+        allI = np.concatenate([best_i, np.broadcast_to(ids, F.shape)], axis=1)
+        best_i, best_f = mapping.topk_rows(allF, allI, k)
+    return best_i, best_f
+
+
+def head_window_fidelities(params, ref, heads, idx, N: int, bf16: bool = True,
+                           m: int = 32) -> np.ndarray:
+    """F(head r, window idx[r, i]) under the learned encoding (entries < 0 give nan)."""
+    from . import mapping
+    offs = token_offsets(params, ref, bf16, m)
+    Xn, _ = mapping.normalized_rows(head_encodings(params, heads, N, bf16, m), N)
+    out = np.full(idx.shape, np.nan)
+    for r in range(idx.shape[0]):
+        ok = idx[r] >= 0
+        if not ok.any():
+            continue
+        Cn, _ = mapping.normalized_rows(window_encodings(params, ref, idx[r][ok], N, bf16, m, offs), N)
+        out[r, ok] = np.abs(Cn.conj() @ Xn[r]) ** 2
+    return out
+
+
+def offset_error_bound(params, w, u: float = 2.0 ** -8) -> np.ndarray:
+    """Bound [T, 32] on |delta_bf16 - delta_exact| for the tokens of w: with weights
+    and hidden values rounded to bfloat16 (unit roundoff u), the first layer's
+    error is at most u sum_i |W1_ji| x_i per hidden unit, the hidden rounding
+    adds u |h_j|, and the second layer's weight rounding u |W2_kj| |h_j|; relu is
+    1-Lipschitz.  Summation in FP32 adds a relative 2^-20 of the absolute sums."""
+    mid, x = tokens(w)
+    W1, b1, W2, b2 = unpack(params)
+    h = np.maximum(x @ W1.T + b1, 0.0)
+    a = x @ np.abs(W1.T)                                    # sum_i |W1_ji| x_i
+    dh = u * a + u * (h + u * a)                            # |error of bf16 hidden|
+    bound = (np.abs(W2) @ (u * (h + dh) + dh).T).T          # [T, 128]
+    bound += 2.0 ** -20 * ((np.abs(W2) @ (h + dh).T).T + np.abs(b2) + (np.abs(b1) + a) @ np.abs(W2.T))
+    return select_offsets(mid, bound) + 1e-7
