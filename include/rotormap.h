@@ -292,6 +292,50 @@ int rm_learned_gradient(const float* d_params, const uint8_t* d_a, const int64_t
                         int32_t n_pairs, int32_t nominal_len, void* d_ws, size_t ws_bytes,
                         float* d_grad, float* d_loss, void* stream);
 
+/* ---- mapping with the learned encoding --------------------------------------
+ * Inference in BF16 (weights and hidden values rounded to bfloat16, nearest
+ * even; FP32 accumulation and biases).  The token offsets of a letter string
+ * are computed once (a token's offsets depend on its 9 letters only); the
+ * encoders and the FP32 rescore then use them in place of the network.
+ * Window and read-head encodings hold the tokens at locations 0..N-9 of the N
+ * letters (N >= 9); a slide of the rolling encoder (§3.4) removes the token at
+ * the old start and adds the one at location N-9.  The scoring calls
+ * (rm_score_topk, rm_score_topk_groups) are unchanged. */
+
+/* Bytes of the token offsets of a string of n_letters letters:
+ * (n_letters - 8) * 32 floats; 0 if n_letters < 9. */
+size_t rm_delta_bytes(int64_t n_letters);
+
+/* Token offsets d_delta[t][k] (row-major, FP32, 16-byte aligned) for the
+ * tokens t = 0..n_letters-9 of d_seq: the middle letter's 32 network outputs
+ * (0 if it is not a code 0..3).  For a concatenation of reads, rows whose
+ * token crosses a read boundary are computed but never used.
+ * Errors: RM_EINVAL (null or misaligned pointer), RM_ESIZE (n_letters < 9). */
+int rm_mlp_infer(const float* d_params, const uint8_t* d_seq, int64_t n_letters, float* d_delta,
+                 void* stream);
+
+/* As rm_encode_reference, with the learned encoding; d_ref_delta = the token
+ * offsets of d_ref (rm_mlp_infer over the reference), caller-owned, read
+ * during this call only.  Errors as rm_encode_reference, plus RM_EINVAL
+ * (null d_ref_delta) and RM_ESIZE (window_len < 9). */
+int rm_encode_reference_learned(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
+                                const float* d_ref_delta, void* d_buf, size_t buf_bytes,
+                                rm_index* out, void* stream);
+
+/* As rm_encode_reads, with the learned encoding of each read head;
+ * d_read_delta = the token offsets of d_seq (rows indexed by positions in
+ * d_seq).  Errors as rm_encode_reads, plus RM_EINVAL (null d_read_delta). */
+int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
+                            int32_t n_reads, const float* d_read_delta, void* d_read_emb,
+                            float* d_read_scale, void* stream);
+
+/* As rm_rescore, recomputing the fidelities in FP32 from the letters and the
+ * token offsets of the reference and of the reads.  Errors as rm_rescore. */
+int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d_ref_delta,
+                       const uint8_t* d_seq, const int64_t* d_off, const float* d_read_delta,
+                       int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx, int32_t k,
+                       int32_t* d_top_idx, float* d_top_score, void* stream);
+
 /* Exact Levenshtein distance (unit costs) of n pairs (a_i, b_i), device
  * memory, into d_out[i] (int32): the labels of the ranking loss and the
  * reference for rank correlations.  Letters must be codes 0..3 (any other code

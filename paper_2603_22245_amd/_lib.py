@@ -93,6 +93,11 @@ def lib():
                                                      P, SZ, P, P]),
             "rm_learned_gradient": (ctypes.c_int, [P, P, P, P, P, P, I32, I32, P, SZ, P, P, P]),
             "rm_levenshtein": (ctypes.c_int, [P, P, P, P, I64, P, P]),
+            "rm_delta_bytes": (SZ, [I64]),
+            "rm_mlp_infer": (ctypes.c_int, [P, P, I64, P, P]),
+            "rm_encode_reference_learned": (ctypes.c_int, [P, I64, PP, P, P, SZ, IP, P]),
+            "rm_encode_reads_learned": (ctypes.c_int, [IP, P, P, I32, P, P, P, P]),
+            "rm_rescore_learned": (ctypes.c_int, [IP, P, P, P, P, P, I32, I32, P, I32, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -302,3 +307,38 @@ def rm_learned_gradient(d_params, d_a, d_aoff, d_b, d_boff, d_ld, n_pairs: int, 
 def rm_levenshtein(d_a, d_aoff, d_b, d_boff, n: int, d_out, stream=None) -> None:
     _check(lib().rm_levenshtein(_ptr(d_a), _ptr(d_aoff), _ptr(d_b), _ptr(d_boff), n, _ptr(d_out),
                                 _stream(stream)), "rm_levenshtein")
+
+
+def rm_delta_bytes(n_letters: int) -> int:
+    return int(lib().rm_delta_bytes(n_letters))
+
+
+def rm_mlp_infer(d_params, d_seq, n_letters: int, d_delta, stream=None) -> None:
+    _check(lib().rm_mlp_infer(_ptr(d_params), _ptr(d_seq), n_letters, _ptr(d_delta),
+                              _stream(stream)), "rm_mlp_infer")
+
+
+def rm_encode_reference_learned(d_ref, ref_len: int, p: rm_params, d_ref_delta, d_buf,
+                                buf_bytes: int, stream=None) -> rm_index:
+    out = rm_index()
+    _check(lib().rm_encode_reference_learned(_ptr(d_ref), ref_len, ctypes.byref(p),
+                                             _ptr(d_ref_delta), _ptr(d_buf), buf_bytes,
+                                             ctypes.byref(out), _stream(stream)),
+           "rm_encode_reference_learned")
+    return out
+
+
+def rm_encode_reads_learned(idx: rm_index, d_seq, d_off, n_reads: int, d_read_delta, d_read_emb,
+                            d_read_scale=None, stream=None) -> None:
+    _check(lib().rm_encode_reads_learned(ctypes.byref(idx), _ptr(d_seq), _ptr(d_off), n_reads,
+                                         _ptr(d_read_delta), _ptr(d_read_emb), _ptr(d_read_scale),
+                                         _stream(stream)), "rm_encode_reads_learned")
+
+
+def rm_rescore_learned(idx: rm_index, d_ref, d_ref_delta, d_seq, d_off, d_read_delta, n_reads: int,
+                       k_fetch: int, d_cand_idx, k: int, d_top_idx, d_top_score,
+                       stream=None) -> None:
+    _check(lib().rm_rescore_learned(ctypes.byref(idx), _ptr(d_ref), _ptr(d_ref_delta), _ptr(d_seq),
+                                    _ptr(d_off), _ptr(d_read_delta), n_reads, k_fetch,
+                                    _ptr(d_cand_idx), k, _ptr(d_top_idx), _ptr(d_top_score),
+                                    _stream(stream)), "rm_rescore_learned")

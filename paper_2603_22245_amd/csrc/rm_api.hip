@@ -98,8 +98,26 @@ size_t rm_index_bytes(int64_t ref_len, const rm_params* p) {
   return layout(W, p).total;
 }
 
+static int encode_reference_impl(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
+                                 const float* d_delta, void* d_buf, size_t buf_bytes,
+                                 rm_index* out, void* stream);
+
 int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p, void* d_buf,
                         size_t buf_bytes, rm_index* out, void* stream) {
+  return encode_reference_impl(d_ref, ref_len, p, nullptr, d_buf, buf_bytes, out, stream);
+}
+
+int rm_encode_reference_learned(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
+                                const float* d_ref_delta, void* d_buf, size_t buf_bytes,
+                                rm_index* out, void* stream) {
+  if (d_ref_delta == nullptr) return RM_EINVAL;
+  if (p != nullptr && p->window_len < 9) return RM_ESIZE;
+  return encode_reference_impl(d_ref, ref_len, p, d_ref_delta, d_buf, buf_bytes, out, stream);
+}
+
+static int encode_reference_impl(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
+                                 const float* d_delta, void* d_buf, size_t buf_bytes,
+                                 rm_index* out, void* stream) {
   int why = RM_OK;
   if (!params_ok(p, &why)) return why;
   if (d_ref == nullptr || d_buf == nullptr || out == nullptr) return RM_EINVAL;
@@ -124,8 +142,13 @@ int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   int st = hip_status(rm::launch_tables(*p, idx.d_phase64, idx.d_phase32, idx.d_step32, s));
   if (st != RM_OK) return st;
-  st = hip_status(rm::launch_encode_reference(d_ref, W, *p, idx.d_phase64, idx.d_step32, idx.d_emb,
-                                              idx.d_scale, idx.d_norm2, s));
+  if (d_delta == nullptr)
+    st = hip_status(rm::launch_encode_reference(d_ref, W, *p, idx.d_phase64, idx.d_step32,
+                                                idx.d_emb, idx.d_scale, idx.d_norm2, s));
+  else
+    st = hip_status(rm::launch_encode_reference_learned(d_ref, W, *p, idx.d_phase64,
+                                                        idx.d_phase32, idx.d_step32, d_delta,
+                                                        idx.d_emb, idx.d_scale, idx.d_norm2, s));
   if (st != RM_OK) return st;
   *out = idx;
   return RM_OK;
@@ -147,6 +170,20 @@ int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_
   return hip_status(rm::launch_encode_reads(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
                                             d_read_emb, d_read_scale,
                                             static_cast<hipStream_t>(stream)));
+}
+
+int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
+                            int32_t n_reads, const float* d_read_delta, void* d_read_emb,
+                            float* d_read_scale, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_seq == nullptr || d_off == nullptr || d_read_emb == nullptr || d_read_delta == nullptr)
+    return RM_EINVAL;
+  if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
+  if (n_reads < 1 || idx->p.window_len < 9) return RM_ESIZE;
+  return hip_status(rm::launch_encode_reads_learned(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
+                                                    d_read_delta, d_read_emb, d_read_scale,
+                                                    static_cast<hipStream_t>(stream)));
 }
 
 size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_fetch) {
@@ -172,6 +209,38 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
     return RM_ESIZE;
   return hip_status(rm::launch_rescore(*idx, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, k,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
+}
+
+int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d_ref_delta,
+                       const uint8_t* d_seq, const int64_t* d_off, const float* d_read_delta,
+                       int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx, int32_t k,
+                       int32_t* d_top_idx, float* d_top_score, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_ref == nullptr || d_ref_delta == nullptr || d_seq == nullptr || d_off == nullptr ||
+      d_read_delta == nullptr || d_cand_idx == nullptr || d_top_idx == nullptr ||
+      d_top_score == nullptr)
+    return RM_EINVAL;
+  if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || k < 1 || k > k_fetch ||
+      idx->p.window_len < 9)
+    return RM_ESIZE;
+  return hip_status(rm::launch_rescore(*idx, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, k,
+                                       d_top_idx, d_top_score, static_cast<hipStream_t>(stream),
+                                       d_ref_delta, d_read_delta));
+}
+
+size_t rm_delta_bytes(int64_t n_letters) {
+  if (n_letters < 9) return 0;
+  return (size_t)(n_letters - 8) * 32 * sizeof(float);
+}
+
+int rm_mlp_infer(const float* d_params, const uint8_t* d_seq, int64_t n_letters, float* d_delta,
+                 void* stream) {
+  if (d_params == nullptr || d_seq == nullptr || d_delta == nullptr) return RM_EINVAL;
+  if (n_letters < 9) return RM_ESIZE;
+  if (reinterpret_cast<uintptr_t>(d_delta) % 16 != 0) return RM_EINVAL;
+  return hip_status(rm::launch_mlp_infer(d_params, d_seq, n_letters, d_delta,
+                                         static_cast<hipStream_t>(stream)));
 }
 
 // ------------------------------------------------------------------ batching

@@ -177,6 +177,144 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
   if (scale != nullptr && lane == 0) scale[r] = s;
 }
 
+// ---- learned token offsets -------------------------------------------------
+// With learned offsets a window of N letters holds the N-8 tokens at
+// locations p = 0..N-9; token t of the reference (9-mer w[t..t+8]) adds
+// exp(i (theta_k p + delta[t][k])) to component (k, w[t+4]).  One slide moves
+// the window start from s to s+1: every component is multiplied by omega^-f_k,
+// token s leaves (its term, multiplied by omega^-f_k, is subtracted) and token
+// s+N-8 enters at location N-9 (exp(i delta) times omega^(f_k (N-9)) is
+// added).  delta is row-major [tokens][32], FP32.
+
+// FP64 direct sum over the tokens p = 0..N-9 of a string whose token offsets
+// are rows drow[p] (lane's two components).
+__device__ __forceinline__ void direct_sum_learned(const uint8_t* __restrict__ str, int N,
+                                                   const float* __restrict__ drow,
+                                                   const double2* __restrict__ phase64, int lane,
+                                                   double2& a0, double2& a1) {
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+  const int T = N - 8;
+  a0 = make_double2(0.0, 0.0);
+  a1 = make_double2(0.0, 0.0);
+  for (int pb = 0; pb < T; pb += 64) {
+    int mine = (pb + lane < T) ? (int)str[pb + lane + 4] : 255;
+    int cnt = min(64, T - pb);
+    for (int i = 0; i < cnt; ++i) {
+      int L = __builtin_amdgcn_readlane(mine, i);
+      const int p = pb + i;
+      double sn, cs;
+      sincos((double)drow[(int64_t)p * 32 + k], &sn, &cs);
+      const double2 e = phase64[(int64_t)p * kM + k];
+      const double er = e.x * cs - e.y * sn, ei = e.x * sn + e.y * cs;
+      a0.x += (L == L0) ? er : 0.0;
+      a0.y += (L == L0) ? ei : 0.0;
+      a1.x += (L == L1) ? er : 0.0;
+      a1.y += (L == L1) ? ei : 0.0;
+    }
+  }
+}
+
+constexpr int kChunk = 32;  // slides whose token terms are staged in LDS at once
+
+template <int PREC>
+__global__ __launch_bounds__(256) void encode_reference_learned_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,
+    const double2* __restrict__ phase64, const float2* __restrict__ phase32,
+    const float4* __restrict__ step32, const float* __restrict__ delta, void* __restrict__ emb,
+    float* __restrict__ scale, float* __restrict__ norm2) {
+  // per wavefront: exp(i delta) of the outgoing (row 0..31) and incoming
+  // (rows 32..63) tokens of the current chunk of slides
+  __shared__ float2 u_stage[4][2 * kChunk][32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (seg >= n_seg) return;
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+  const int64_t j0 = seg * seg_len;
+  const int64_t j1 = min(W, j0 + seg_len);
+
+  double2 a0, a1;
+  const int64_t s0 = j0 * stride;
+  direct_sum_learned(ref + s0, N, delta + s0 * 32, phase64, lane, a0, a1);
+  float2 c0 = make_float2((float)a0.x, (float)a0.y);
+  float2 c1 = make_float2((float)a1.x, (float)a1.y);
+  emit_window<PREC>(j0, lane, N, c0, c1, emb, scale, norm2);
+
+  const float4 st = step32[k];
+  const float2 rot = make_float2(st.x, st.y);    // omega^-f
+  const float2 inc = phase32[(int64_t)(N - 9) * kM + k];  // omega^(f (N-9))
+  float2(*stage)[32] = u_stage[wave];
+
+  const int64_t n_slides = (j1 - 1 - j0) * stride;
+  int64_t j = j0;
+  int until_emit = stride;
+  for (int64_t tb = 0; tb < n_slides; tb += kChunk) {
+    const int cnt = (int)min<int64_t>(kChunk, n_slides - tb);
+    // stage exp(i delta) of tokens s0+tb+i (out) and s0+tb+i+N-8 (in), i < cnt
+#pragma unroll 4
+    for (int q = 0; q < 2 * kChunk * 32 / 64; ++q) {
+      const int v = q * 64 + lane;
+      const int row = v >> 5, kk = v & 31;
+      const int i = row & (kChunk - 1);
+      if (i < cnt) {
+        const int64_t tok = s0 + tb + i + (row >= kChunk ? N - 8 : 0);
+        float sn, cs;
+        sincosf(delta[tok * 32 + kk], &sn, &cs);
+        stage[row][kk] = make_float2(cs, sn);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // letters: outgoing token middle ref[s0+t+4], incoming ref[s0+t+N-4]
+    const int64_t t = tb + (lane & (kChunk - 1));
+    const bool in_half = lane >= kChunk;
+    int mine = 255;
+    if ((lane & (kChunk - 1)) < cnt) mine = (int)ref[s0 + t + (in_half ? N - 4 : 4)];
+    for (int i = 0; i < cnt; ++i) {
+      const int o = __builtin_amdgcn_readlane(mine, i);
+      const int n = __builtin_amdgcn_readlane(mine, i + kChunk);
+      const float2 uo = cmul(stage[i][k], rot);
+      const float2 ui = cmul(stage[kChunk + i][k], inc);
+      c0 = cmul(c0, rot);
+      c1 = cmul(c1, rot);
+      if (o == L0) { c0.x -= uo.x; c0.y -= uo.y; }
+      if (o == L1) { c1.x -= uo.x; c1.y -= uo.y; }
+      if (n == L0) { c0.x += ui.x; c0.y += ui.y; }
+      if (n == L1) { c1.x += ui.x; c1.y += ui.y; }
+      if (--until_emit == 0) {
+        until_emit = stride;
+        ++j;
+        emit_window<PREC>(j, lane, N, c0, c1, emb, scale, norm2);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // the stage is rewritten by the next chunk
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void encode_reads_learned_kernel(
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
+    const double2* __restrict__ phase64, const float* __restrict__ delta, void* __restrict__ emb,
+    float* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= n_reads) return;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+  if (len >= N) direct_sum_learned(seq + start, N, delta + start * 32, phase64, lane, a0, a1);
+  double X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
+  bool deg = X < (double)kDegenerateRel * N;
+  double inv = deg ? 0.0 : 1.0 / sqrt(X);
+  float xr0 = (float)(a0.x * inv), xi0 = (float)(a0.y * inv);
+  float xr1 = (float)(a1.x * inv), xi1 = (float)(a1.y * inv);
+  Row4 re{{xr0, xi0, xr1, xi1}};
+  Row4 im{{-xi0, xr0, -xi1, xr1}};
+  float s = store_row<PREC>(emb, 2 * r, lane, re);
+  store_row<PREC>(emb, 2 * r + 1, lane, im);
+  if (scale != nullptr && lane == 0) scale[r] = s;
+}
+
 }  // namespace
 
 hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_params& p,
@@ -231,6 +369,68 @@ hipError_t launch_encode_reads(const rm_params& p, const double* phase64, const 
     default:
       hipLaunchKernelGGL(encode_reads_kernel<RM_FP8_E4M3>, dim3((unsigned)blocks), dim3(64 * waves),
                          0, s, seq, off, n_reads, p.window_len, ph, emb, scale);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rm
+
+namespace rm {
+
+hipError_t launch_encode_reference_learned(const uint8_t* ref, int64_t W, const rm_params& p,
+                                           const double* phase64, const float* phase32,
+                                           const float* step32, const float* delta, void* emb,
+                                           float* scale, float* norm2, hipStream_t s) {
+  int64_t seg = p.reanchor;
+  if (seg <= 0) {
+    seg = (W + 8191) / 8192;
+    if (seg < 256) seg = 256;
+    if (seg > 4096) seg = 4096;
+  }
+  int64_t n_seg = (W + seg - 1) / seg;
+  const int waves = 4;
+  int64_t blocks = (n_seg + waves - 1) / waves;
+  auto* ph = reinterpret_cast<const double2*>(phase64);
+  auto* p32 = reinterpret_cast<const float2*>(phase32);
+  auto* st = reinterpret_cast<const float4*>(step32);
+  const dim3 grid((unsigned)blocks), block(64 * waves);
+  switch (p.precision) {
+    case RM_FP32:
+      hipLaunchKernelGGL(encode_reference_learned_kernel<RM_FP32>, grid, block, 0, s, ref, W,
+                         p.window_len, p.stride, seg, n_seg, ph, p32, st, delta, emb, scale, norm2);
+      break;
+    case RM_FP16:
+      hipLaunchKernelGGL(encode_reference_learned_kernel<RM_FP16>, grid, block, 0, s, ref, W,
+                         p.window_len, p.stride, seg, n_seg, ph, p32, st, delta, emb, scale, norm2);
+      break;
+    default:
+      hipLaunchKernelGGL(encode_reference_learned_kernel<RM_FP8_E4M3>, grid, block, 0, s, ref, W,
+                         p.window_len, p.stride, seg, n_seg, ph, p32, st, delta, emb, scale, norm2);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_reads_learned(const rm_params& p, const double* phase64,
+                                       const uint8_t* seq, const int64_t* off, int32_t n_reads,
+                                       const float* delta, void* emb, float* scale,
+                                       hipStream_t s) {
+  const int waves = 4;
+  const dim3 grid((unsigned)(((int64_t)n_reads + waves - 1) / waves)), block(64 * waves);
+  auto* ph = reinterpret_cast<const double2*>(phase64);
+  switch (p.precision) {
+    case RM_FP32:
+      hipLaunchKernelGGL(encode_reads_learned_kernel<RM_FP32>, grid, block, 0, s, seq, off,
+                         n_reads, p.window_len, ph, delta, emb, scale);
+      break;
+    case RM_FP16:
+      hipLaunchKernelGGL(encode_reads_learned_kernel<RM_FP16>, grid, block, 0, s, seq, off,
+                         n_reads, p.window_len, ph, delta, emb, scale);
+      break;
+    default:
+      hipLaunchKernelGGL(encode_reads_learned_kernel<RM_FP8_E4M3>, grid, block, 0, s, seq, off,
+                         n_reads, p.window_len, ph, delta, emb, scale);
       break;
   }
   return hipGetLastError();

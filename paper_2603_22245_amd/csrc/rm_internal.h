@@ -140,6 +140,17 @@ hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
                              const int32_t* R, int k_fetch, int32_t* const* cand_idx,
                              float* const* cand_score, void* ws, hipStream_t s);
 
+hipError_t launch_mlp_infer(const float* params, const uint8_t* seq, int64_t n_letters,
+                            float* delta, hipStream_t s);
+hipError_t launch_encode_reference_learned(const uint8_t* ref, int64_t W, const rm_params& p,
+                                           const double* phase64, const float* phase32,
+                                           const float* step32, const float* delta, void* emb,
+                                           float* scale, float* norm2, hipStream_t s);
+hipError_t launch_encode_reads_learned(const rm_params& p, const double* phase64,
+                                       const uint8_t* seq, const int64_t* off, int32_t n_reads,
+                                       const float* delta, void* emb, float* scale,
+                                       hipStream_t s);
+
 size_t learned_workspace_bytes(int32_t n_pairs);
 hipError_t launch_learned_encode(const float* params, const uint8_t* seq, const int64_t* off,
                                  int32_t n_strings, int N, float* out, hipStream_t s);
@@ -155,6 +166,7 @@ hipError_t launch_levenshtein(const uint8_t* a, const int64_t* aoff, const uint8
 hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                           const int64_t* off, int32_t n_reads, int32_t k_fetch,
                           const int32_t* cand_idx, int32_t k, int32_t* top_idx, float* top_score,
-                          hipStream_t s);
+                          hipStream_t s, const float* ref_delta = nullptr,
+                          const float* read_delta = nullptr);
 
 }  // namespace rm

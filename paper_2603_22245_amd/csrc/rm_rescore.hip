@@ -1,4 +1,4 @@
-// FP32 rescore of each read's candidate windows.
+// FP32 rescore of each read's candidate windows (plain or learned encoding).
 //
 // The candidates come from the low-precision product; their fidelities are
 // recomputed from the letters -- never from the stored index -- in FP32: the
@@ -42,18 +42,56 @@ __device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, in
   }
 }
 
+// FP32 direct sum over the tokens p = 0..N-9 of a string whose token offsets
+// are rows drow[p]: token p adds exp(i (theta_k p + delta)) to component
+// (k, str[p+4]).
+__device__ __forceinline__ void direct_sum32_learned(const uint8_t* __restrict__ str, int N,
+                                                     const float* __restrict__ drow,
+                                                     const float2* __restrict__ phase32, int lane,
+                                                     float2& a0, float2& a1) {
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+  const int T = N - 8;
+  a0 = make_float2(0.f, 0.f);
+  a1 = make_float2(0.f, 0.f);
+  for (int pb = 0; pb < T; pb += 64) {
+    int mine = (pb + lane < T) ? (int)str[pb + lane + 4] : 255;
+    int cnt = min(64, T - pb);
+    for (int i = 0; i < cnt; ++i) {
+      int L = __builtin_amdgcn_readlane(mine, i);
+      const int p = pb + i;
+      float sn, cs;
+      sincosf(drow[(int64_t)p * 32 + k], &sn, &cs);
+      const float2 e = cmul(phase32[(int64_t)p * kM + k], make_float2(cs, sn));
+      a0.x += (L == L0) ? e.x : 0.f;
+      a0.y += (L == L0) ? e.y : 0.f;
+      a1.x += (L == L1) ? e.x : 0.f;
+      a1.y += (L == L1) ? e.y : 0.f;
+    }
+  }
+}
+
+// ref_delta / read_delta null: the plain encoding; else the learned one with
+// the token offsets of the reference (rows = reference positions) and of the
+// reads (rows = positions in seq).
 __global__ __launch_bounds__(256) void rescore_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride,
     const float2* __restrict__ phase32, const uint8_t* __restrict__ seq,
     const int64_t* __restrict__ off, int32_t R, int k_fetch, const int32_t* __restrict__ cand,
-    int k, int32_t* __restrict__ top_idx, float* __restrict__ top_score) {
+    int k, int32_t* __restrict__ top_idx, float* __restrict__ top_score,
+    const float* __restrict__ ref_delta, const float* __restrict__ read_delta) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= R) return;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
   float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
-  if (len >= N) direct_sum32(seq + start, N, phase32, lane, x0, x1);
+  if (len >= N) {
+    if (read_delta != nullptr)
+      direct_sum32_learned(seq + start, N, read_delta + start * 32, phase32, lane, x0, x1);
+    else
+      direct_sum32(seq + start, N, phase32, lane, x0, x1);
+  }
   float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
   const bool xdeg = X < kDegenerateRel * (float)N;
 
@@ -63,7 +101,11 @@ __global__ __launch_bounds__(256) void rescore_kernel(
     int32_t j = cand[r * k_fetch + e];
     if (j < 0 || j >= W) continue;  // uniform per wavefront
     float2 c0, c1;
-    direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
+    if (ref_delta != nullptr)
+      direct_sum32_learned(ref + (int64_t)j * stride, N, ref_delta + (int64_t)j * stride * 32,
+                           phase32, lane, c0, c1);
+    else
+      direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
     float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
     // <x|c> = sum conj(x) c
     float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
@@ -100,11 +142,12 @@ __global__ __launch_bounds__(256) void rescore_kernel(
 hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                           const int64_t* off, int32_t n_reads, int32_t k_fetch,
                           const int32_t* cand_idx, int32_t k, int32_t* top_idx, float* top_score,
-                          hipStream_t s) {
+                          hipStream_t s, const float* ref_delta, const float* read_delta) {
   unsigned blocks = (unsigned)(((int64_t)n_reads + 3) / 4);
   hipLaunchKernelGGL(rescore_kernel, dim3(blocks), dim3(256), 0, s, ref, idx.n_windows,
                      idx.p.window_len, idx.p.stride, reinterpret_cast<const float2*>(idx.d_phase32),
-                     seq, off, n_reads, k_fetch, cand_idx, k, top_idx, top_score);
+                     seq, off, n_reads, k_fetch, cand_idx, k, top_idx, top_score, ref_delta,
+                     read_delta);
   return hipGetLastError();
 }
 

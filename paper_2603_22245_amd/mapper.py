@@ -27,6 +27,8 @@ class Index:
     idx: L.rm_index
     buf: object      # torch uint8 tensor owning the index memory
     ref: object      # torch uint8 tensor, the reference letters on the device
+    learned: object = None  # FP32 network parameters (device) of a learned index
+    delta: object = None    # token offsets of the reference [G-8, 32] (learned index)
 
     @property
     def n_windows(self) -> int:
@@ -50,8 +52,18 @@ class Index:
         return self.buf[off: off + 4 * self.n_windows].view(_torch().float32)
 
 
+def _delta_buffer(n_letters: int, device):
+    torch = _torch()
+    nbytes = L.rm_delta_bytes(n_letters)
+    if nbytes == 0:
+        raise L.RotorMapError(L.RM_ESIZE, "rm_delta_bytes")
+    return torch.empty((nbytes // 128, 32), dtype=torch.float32, device=device)
+
+
 def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", schedule="default",
-                reanchor=0, stream=None, device="cuda") -> Index:
+                reanchor=0, stream=None, device="cuda", learned=None) -> Index:
+    """Encode the reference's windows.  learned: network parameters (10,432
+    FP32 values, numpy or device tensor) for the learned encoding, else plain."""
     torch = _torch()
     p = L.make_params(window_len, stride, L.RM_DIM, schedule, precision, reanchor)
     if isinstance(ref, np.ndarray):
@@ -62,8 +74,16 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
     if nbytes == 0:
         raise L.RotorMapError(L.RM_ESIZE, "rm_index_bytes")
     buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    idx = L.rm_encode_reference(d_ref, int(d_ref.numel()), p, buf, nbytes, stream)
-    return Index(p, idx, buf, d_ref)
+    if learned is None:
+        idx = L.rm_encode_reference(d_ref, int(d_ref.numel()), p, buf, nbytes, stream)
+        return Index(p, idx, buf, d_ref)
+    params = torch.as_tensor(learned, dtype=torch.float32).to(device).contiguous()
+    if params.numel() != L.RM_LEARNED_PARAMS:
+        raise ValueError(f"learned parameters must have {L.RM_LEARNED_PARAMS} values")
+    delta = _delta_buffer(int(d_ref.numel()), device)
+    L.rm_mlp_infer(params, d_ref, int(d_ref.numel()), delta, stream)
+    idx = L.rm_encode_reference_learned(d_ref, int(d_ref.numel()), p, delta, buf, nbytes, stream)
+    return Index(p, idx, buf, d_ref, params, delta)
 
 
 @dataclasses.dataclass
@@ -73,6 +93,7 @@ class ReadBatch:
     off: object
     emb: object
     scale: object
+    delta: object = None  # token offsets of seq (learned index)
 
 
 def upload_reads(index: Index, seq: np.ndarray, offsets: np.ndarray, device="cuda") -> ReadBatch:
@@ -82,7 +103,8 @@ def upload_reads(index: Index, seq: np.ndarray, offsets: np.ndarray, device="cud
     d_off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(device)
     emb = torch.empty(L.rm_read_emb_bytes(n, index.params), dtype=torch.uint8, device=device)
     scale = torch.empty(n, dtype=torch.float32, device=device)
-    return ReadBatch(n, d_seq, d_off, emb, scale)
+    delta = None if index.learned is None else _delta_buffer(int(d_seq.numel()), device)
+    return ReadBatch(n, d_seq, d_off, emb, scale, delta)
 
 
 @dataclasses.dataclass
@@ -114,7 +136,12 @@ def map_buffers(index: Index, n_reads: int, k: int, k_fetch: Optional[int] = Non
 
 
 def encode_reads(index: Index, reads: ReadBatch, stream=None):
-    L.rm_encode_reads(index.idx, reads.seq, reads.off, reads.n, reads.emb, reads.scale, stream)
+    if index.learned is None:
+        L.rm_encode_reads(index.idx, reads.seq, reads.off, reads.n, reads.emb, reads.scale, stream)
+        return
+    L.rm_mlp_infer(index.learned, reads.seq, int(reads.seq.numel()), reads.delta, stream)
+    L.rm_encode_reads_learned(index.idx, reads.seq, reads.off, reads.n, reads.delta, reads.emb,
+                              reads.scale, stream)
 
 
 def score_topk(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
@@ -123,8 +150,13 @@ def score_topk(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
 
 
 def rescore(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
-    L.rm_rescore(index.idx, index.ref, reads.seq, reads.off, reads.n, bufs.k_fetch,
-                 bufs.cand_idx, bufs.k, bufs.top_idx, bufs.top_score, stream)
+    if index.learned is None:
+        L.rm_rescore(index.idx, index.ref, reads.seq, reads.off, reads.n, bufs.k_fetch,
+                     bufs.cand_idx, bufs.k, bufs.top_idx, bufs.top_score, stream)
+        return
+    L.rm_rescore_learned(index.idx, index.ref, index.delta, reads.seq, reads.off, reads.delta,
+                         reads.n, bufs.k_fetch, bufs.cand_idx, bufs.k, bufs.top_idx,
+                         bufs.top_score, stream)
 
 
 def map_reads(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
