@@ -115,11 +115,24 @@ def select_offsets(mid, o, m: int = 32) -> np.ndarray:
     return delta
 
 
-def token_offsets(params, w, bf16: bool = False, m: int = 32):
-    """Middle letters [T] and phase offsets delta [T, m] of the 9-mer tokens of w."""
-    mid, x = tokens(w)
-    _, _, o = _network(params, x, bf16)
-    return mid, select_offsets(mid, o, m)
+def token_offsets(params, w, bf16: bool = False, m: int = 32, block: int = 1 << 18):
+    """Middle letters [T] and phase offsets delta [T, m] of the 9-mer tokens of w
+    (tokens are independent: long strings are taken in blocks of tokens)."""
+    w = np.asarray(w)
+    T = max(w.shape[0] - 2 * CTX, 0)
+    if T <= block:
+        mid, x = tokens(w)
+        _, _, o = _network(params, x, bf16)
+        return mid, select_offsets(mid, o, m)
+    mid = np.empty(T, dtype=np.int64)
+    delta = np.empty((T, m))
+    for a in range(0, T, block):
+        b = min(T, a + block)
+        mb, x = tokens(w[a:b + 2 * CTX])
+        _, _, o = _network(params, x, bf16)
+        mid[a:b] = mb
+        delta[a:b] = select_offsets(mb, o, m)
+    return mid, delta
 
 
 def forward_string(params, w, N: int, m: int = 32):

@@ -177,3 +177,13 @@ def test_learned_mapping_finds_error_free_reads_with_fidelity_one():
     np.testing.assert_array_equal(idx, idx2)
     G = learned.head_window_fidelities(params, ref, heads, idx, N)
     assert np.max(np.abs(G - F)) < 1e-12
+
+
+def test_token_offsets_blocking_changes_nothing():
+    params = _trained_like_params(38)
+    w = np.random.default_rng(39).integers(0, 4, 5000)
+    for bf16 in (False, True):
+        m1, d1 = learned.token_offsets(params, w, bf16)
+        m2, d2 = learned.token_offsets(params, w, bf16, block=333)
+        np.testing.assert_array_equal(m1, m2)
+        np.testing.assert_array_equal(d1, d2)
