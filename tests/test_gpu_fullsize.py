@@ -1,0 +1,262 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times, on outputs the oracle can compute one by one or has stored:
+
+* precision (10 Mbp, 100,000 reads, FP16 index, top-8 of 16): stored oracle
+  top-16 lists of 64 sampled reads; sampled index rows and squared norms;
+* scale (256 Mbp, FP8 index with FP64 re-anchor every 65,536 starts, top-16 of
+  32): sampled index rows (re-anchor boundaries, the last windows), squared
+  norms (rolling drift), rescored scores of sampled reads one window at a time,
+  no sampled window beating a read's 16th result by more than the FP8 product
+  error, true locations;
+* learned (1,000,000 pairs): edit distances bit-exact on a sample, one epoch of
+  training beating the plain encoding's Spearman correlation; the precision
+  workload with the learned encoding against its stored oracle lists;
+* batching (64 Mbp, 20,000 reads of uneven length): stored oracle lists per
+  bucket.
+
+Tolerances as in the smaller parity tests: FP16 rows 2^-11 relative + 2e-5;
+FP8 rows half an e4m3 ulp + the norm correction; squared norms 2e-4 relative
+(FP32 rolling drift over at most 65,535 slides is below 5e-5); FP32 rescore
+1e-4 absolute; the low-precision product 1e-3 (FP16) / 1e-2 (FP8) fidelity
+units.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import learned as OL
+from oracle import lev, mapping, rope
+
+from gpu_helpers import fp8_bound, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+TAU = mapping.TIE_TAU
+
+
+def _rows(index, rows, torch):
+    """Dequantised complex rows [len(rows), 128] of the stored index."""
+    r = torch.from_numpy(np.asarray(rows, dtype=np.int64)).cuda()
+    e = index.embeddings()[r]
+    if e.dtype == torch.uint8:
+        v = e.cpu().view(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+        v *= index.scales()[r].cpu().numpy().astype(np.float64)[:, None]
+    else:
+        v = e.float().cpu().numpy().astype(np.float64)
+    return v[:, 0::2] + 1j * v[:, 1::2]
+
+
+def _oracle_rows(ref, starts, N):
+    C = np.stack([rope.encode_raw(ref[s:s + N], N, 32) for s in starts])
+    return mapping.normalized_rows(C, N)
+
+
+def _check_index_rows(index, ref, rows, N, precision, torch):
+    got = _rows(index, rows, torch)
+    want, n2 = _oracle_rows(ref, rows, N)
+    norms = index.norms2()[torch.from_numpy(np.asarray(rows)).cuda()].cpu().numpy()
+    assert np.max(np.abs(norms / n2 - 1)) <= 2e-4
+    if precision == "fp16":
+        for part in (np.real, np.imag):
+            w = np.abs(part(want))
+            assert np.all(np.abs(part(got) - part(want)) <= 2.0 ** -11 * w + 2e-5)
+    else:
+        scale = index.scales()[torch.from_numpy(np.asarray(rows)).cuda()].cpu().numpy()
+        s = np.exp2(np.round(np.log2(scale)))[:, None]
+        for part in (np.real, np.imag):
+            w = np.abs(part(want))
+            assert np.all(np.abs(part(got) - part(want)) <= fp8_bound(w, s) + 0.05 * w)
+
+
+def _map(index, reads, k, k_fetch):
+    from paper_2603_22245_amd import mapper
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
+    mapper.map_reads(index, rb, bufs)
+    return rb, bufs
+
+
+def _stored_lists(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle sample {name} is missing")
+    return np.load(path)
+
+
+def _check_against_stored(g, top_idx, top_score, k, exact_min):
+    """Recall@k, list agreement up to ties and rescore error against stored
+    oracle lists (longer than k): a window outside a stored list is a miss."""
+    recs, exact, errs = [], [], []
+    for r, oi, of in zip(g["reads"], g["idx"], g["F"]):
+        pos = {int(j): i for i, j in enumerate(oi)}
+        hits, ok = 0, True
+        for rank, j in enumerate(top_idx[r][:k]):
+            j = int(j)
+            if j not in pos:
+                ok = False
+                continue
+            Fj = of[pos[j]]
+            errs.append(abs(float(top_score[r][rank]) - Fj))
+            hits += (pos[j] < k) or (Fj >= of[k - 1] - TAU)
+            ok &= abs(Fj - of[rank]) <= TAU
+        recs.append(hits / k)
+        exact.append(ok)
+    print(f"recall@{k} {np.mean(recs):.5f}, exact lists {np.mean(exact):.4f}, "
+          f"rescore err {max(errs):.2e}")
+    assert np.mean(recs) >= 0.99
+    assert np.mean(exact) >= exact_min
+    assert max(errs) <= 1e-4
+
+
+# ---------------------------------------------------------------- precision
+
+@pytest.mark.parametrize("precision", ["fp16", "fp8"])
+def test_precision_workload_full_size(precision):
+    torch = torch_cuda()
+    from paper_2603_22245_amd import mapper
+    w = synth.WORKLOADS["precision"]
+    ref = w.reference()
+    reads = w.reads(ref)
+    index = mapper.build_index(ref, w.window_len, w.stride, precision, reanchor=w.reanchor)
+    rb, bufs = _map(index, reads, w.k, 16)
+    torch.cuda.synchronize()
+    W = index.n_windows
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, 1, W // 2, W - 2, W - 1], rng.choice(W, 40)]))
+    _check_index_rows(index, ref, rows, w.window_len, precision, torch)
+    g = _stored_lists("precision_top16_sample64.npz")
+    _check_against_stored(g, bufs.top_idx.cpu().numpy(), bufs.top_score.cpu().numpy(), w.k,
+                          exact_min=0.95)
+    # low-precision product scores of candidates in the stored lists
+    ci, cs = bufs.cand_idx.cpu().numpy(), bufs.cand_score.cpu().numpy()
+    tol = {"fp16": 1e-3, "fp8": 1e-2}[precision]
+    for r, oi, of in zip(g["reads"], g["idx"], g["F"]):
+        pos = {int(j): i for i, j in enumerate(oi)}
+        for j, sc in zip(ci[r], cs[r]):
+            if int(j) in pos:
+                assert abs(float(sc) - of[pos[int(j)]]) <= tol
+    truth = reads.truth // w.stride
+    assert np.mean(np.abs(bufs.top_idx.cpu().numpy()[:, 0] - truth) <= 8) >= 0.99
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- scale
+
+def test_scale_workload_full_size_sampled():
+    torch = torch_cuda()
+    from paper_2603_22245_amd import mapper
+    w = synth.WORKLOADS["scale"]
+    N = w.window_len
+    ref = w.reference()
+    reads = w.reads(ref, n=2048)
+    index = mapper.build_index(ref, N, w.stride, w.precision, reanchor=w.reanchor)
+    k, k_fetch = w.k, 32
+    rb, bufs = _map(index, reads, k, k_fetch)
+    torch.cuda.synchronize()
+    W = index.n_windows
+    assert W == 255_999_851
+    seg = w.reanchor
+    rng = np.random.default_rng(11)
+    special = [0, seg - 1, seg, seg + 1, 2 * seg - 1, 1000 * seg - 1, 1000 * seg,
+               (W // seg) * seg - 1, (W // seg) * seg, W - 2, W - 1]
+    rows = np.unique(np.concatenate([special, rng.choice(W, 64)]))
+    _check_index_rows(index, ref, rows, N, "fp8", torch)
+
+    top_i = bufs.top_idx.cpu().numpy().astype(np.int64)
+    top_f = bufs.top_score.cpu().numpy().astype(np.float64)
+    # ordered by F descending, then window id ascending
+    assert np.all((np.diff(top_f, axis=1) < 0) |
+                  ((np.diff(top_f, axis=1) == 0) & (np.diff(top_i, axis=1) > 0)))
+    truth = reads.truth // w.stride
+    hit = np.mean(np.abs(top_i[:, 0] - truth) <= 8)
+    print(f"top-1 within 8 of the true start: {hit:.4f}")
+    assert hit >= 0.97
+    heads = mapping.read_heads(reads.seq, reads.offsets, N)
+    pick = rng.choice(reads.n, 12, replace=False)
+    for r in pick:
+        want = mapping.pair_fidelities(ref, heads[r:r + 1], top_i[r:r + 1], N)[0]
+        assert np.max(np.abs(top_f[r] - want)) <= 1e-4
+        # windows the oracle scores one by one: around the true start and at random
+        probe = np.unique(np.concatenate([np.clip(truth[r] + np.arange(-32, 33), 0, W - 1),
+                                          rng.choice(W, 256)]))
+        pf = mapping.pair_fidelities(ref, heads[r:r + 1], probe[None, :], N)[0]
+        missing = ~np.isin(probe, top_i[r])
+        assert np.all(pf[missing] <= top_f[r, -1] + 1e-2), r
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- learned
+
+def test_learned_workload_full_size():
+    torch = torch_cuda()
+    from paper_2603_22245_amd import learned as LM
+    from scipy.stats import spearmanr
+    P = synth.mutate_pairs(1_000_000, 150, 30, seed=synth.PAIRS_SEED)
+    full = LM.upload_pairs(P.a, P.a_off, P.b, P.b_off)
+    ld = LM.levenshtein(full).cpu().numpy()
+    rng = np.random.default_rng(12)
+    pick = np.sort(rng.choice(P.n, 3000, replace=False))
+    a = [P.pair(i)[0] for i in pick]
+    b = [P.pair(i)[1] for i in pick]
+    ao = np.zeros(len(a) + 1, np.int64); ao[1:] = np.cumsum([len(x) for x in a])
+    bo = np.zeros(len(b) + 1, np.int64); bo[1:] = np.cumsum([len(x) for x in b])
+    want = lev.lev_many(np.concatenate(a), ao, np.concatenate(b), bo)
+    np.testing.assert_array_equal(ld[pick], want)
+    full.ld = torch.from_numpy(ld).cuda()
+    n_tr = 900_000
+    train = LM.PairSet(full.a, full.a_off[:n_tr + 1], full.b, full.b_off[:n_tr + 1], n_tr,
+                       full.ld[:n_tr])
+    held = LM.PairSet(full.a, full.a_off[n_tr:], full.b, full.b_off[n_tr:], P.n - n_tr,
+                      full.ld[n_tr:])
+    t = LM.Trainer(seed=0, batch=1024)
+    losses = t.epoch(train, graph=True).cpu().numpy()
+    assert losses[-32:].mean() < 0.5 * losses[:32].mean()
+    lh = ld[n_tr:]
+    rho_l = spearmanr(LM.pair_fidelity(t.params, held, 150).cpu().numpy(), -lh).correlation
+    rho_p = spearmanr(LM.pair_fidelity(None, held, 150).cpu().numpy(), -lh).correlation
+    print(f"held-out Spearman after one epoch: learned {rho_l:.4f}, plain {rho_p:.4f}")
+    assert rho_l > rho_p + 0.1
+    t.close()
+
+
+def test_precision_workload_learned_encoding_full_size():
+    torch = torch_cuda()
+    from paper_2603_22245_amd import mapper
+    g = _stored_lists("precision_learned_top16_sample64.npz")
+    w = synth.WORKLOADS["precision"]
+    params = np.load(os.path.join(GOLDEN, "learned_weights.npy"))
+    ref = w.reference()
+    reads = w.reads(ref)
+    index = mapper.build_index(ref, w.window_len, w.stride, "fp16", learned=params)
+    rb, bufs = _map(index, reads, w.k, 16)
+    torch.cuda.synchronize()
+    _check_against_stored(g, bufs.top_idx.cpu().numpy(), bufs.top_score.cpu().numpy(), w.k,
+                          exact_min=0.9)
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- batching
+
+def test_batching_workload_full_size():
+    torch = torch_cuda()
+    from paper_2603_22245_amd import mapper
+    g = _stored_lists("batching_top16_per_bucket4.npz")
+    w = synth.WORKLOADS["batching"]
+    ref = w.reference()
+    reads = w.reads(ref)
+    bm = mapper.BatchMapper(ref, reads.seq, reads.offsets, k=w.k, k_fetch=16, precision="fp16")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bm.run(stream)
+        stream.synchronize()
+    ids, sc = bm.results()
+    _check_against_stored(g, ids, sc, w.k, exact_min=0.9)
+    bm.close()
+    torch.cuda.empty_cache()
