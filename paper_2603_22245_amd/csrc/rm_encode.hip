@@ -73,14 +73,20 @@ __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int 
   for (int pb = 0; pb < n; pb += 64) {
     int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
     int cnt = min(64, n - pb);
-
-    for (int i = 0; i < cnt; ++i) {
-      int L = __builtin_amdgcn_readlane(mine, i);
-      double2 e = phase64[(int64_t)(pb + i) * kM + k];
-      a0.x += (L == L0) ? e.x : 0.0;
-      a0.y += (L == L0) ? e.y : 0.0;
-      a1.x += (L == L1) ? e.x : 0.0;
-      a1.y += (L == L1) ? e.y : 0.0;
+    // groups of 8 positions: the 8 table loads are in flight together; a
+    // position past the end re-reads the last row and has letter 255
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      double2 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = phase64[(int64_t)min(pb + i0 + u, n - 1) * kM + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int L = __builtin_amdgcn_readlane(mine, i0 + u);
+        a0.x += (L == L0) ? e[u].x : 0.0;
+        a0.y += (L == L0) ? e[u].y : 0.0;
+        a1.x += (L == L1) ? e[u].x : 0.0;
+        a1.y += (L == L1) ? e[u].y : 0.0;
+      }
     }
   }
 }
@@ -128,11 +134,14 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   const int64_t n_slides = (j1 - 1 - j0) * stride;
   int64_t j = j0;
   int until_emit = stride;
+  // outgoing letter of slide t is ref[s0+t], incoming is ref[s0+t+N]; the
+  // next chunk's letters are loaded while the current chunk rolls
+  int out_l = lane < n_slides ? (int)ref[s0 + lane] : 255;
+  int in_l = lane < n_slides ? (int)ref[s0 + lane + N] : 255;
   for (int64_t tb = 0; tb < n_slides; tb += 64) {
-    // outgoing letter of slide t is ref[s0+t], incoming is ref[s0+t+N]
-    int64_t t = tb + lane;
-    int out_l = (t < n_slides) ? (int)ref[s0 + t] : 255;
-    int in_l = (t < n_slides) ? (int)ref[s0 + t + N] : 255;
+    const int64_t tn = tb + 64 + lane;
+    const int out_next = tn < n_slides ? (int)ref[s0 + tn] : 255;
+    const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
     int cnt = (int)min<int64_t>(64, n_slides - tb);
     for (int i = 0; i < cnt; ++i) {
       int o = __builtin_amdgcn_readlane(out_l, i);
@@ -149,6 +158,8 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
         emit_window<PREC>(j, lane, N, c0, c1, emb, scale, norm2);
       }
     }
+    out_l = out_next;
+    in_l = in_next;
   }
 }
 
@@ -200,17 +211,26 @@ __device__ __forceinline__ void direct_sum_learned(const uint8_t* __restrict__ s
   for (int pb = 0; pb < T; pb += 64) {
     int mine = (pb + lane < T) ? (int)str[pb + lane + 4] : 255;
     int cnt = min(64, T - pb);
-    for (int i = 0; i < cnt; ++i) {
-      int L = __builtin_amdgcn_readlane(mine, i);
-      const int p = pb + i;
-      double sn, cs;
-      sincos((double)drow[(int64_t)p * 32 + k], &sn, &cs);
-      const double2 e = phase64[(int64_t)p * kM + k];
-      const double er = e.x * cs - e.y * sn, ei = e.x * sn + e.y * cs;
-      a0.x += (L == L0) ? er : 0.0;
-      a0.y += (L == L0) ? ei : 0.0;
-      a1.x += (L == L1) ? er : 0.0;
-      a1.y += (L == L1) ? ei : 0.0;
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      double2 e[8];
+      float d[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(pb + i0 + u, T - 1);
+        e[u] = phase64[(int64_t)p * kM + k];
+        d[u] = drow[(int64_t)p * 32 + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int L = __builtin_amdgcn_readlane(mine, i0 + u);
+        double sn, cs;
+        sincos((double)d[u], &sn, &cs);
+        const double er = e[u].x * cs - e[u].y * sn, ei = e[u].x * sn + e[u].y * cs;
+        a0.x += (L == L0) ? er : 0.0;
+        a0.y += (L == L0) ? ei : 0.0;
+        a1.x += (L == L1) ? er : 0.0;
+        a1.y += (L == L1) ? ei : 0.0;
+      }
     }
   }
 }

@@ -188,57 +188,85 @@ __global__ __launch_bounds__(256) void pair_fidelity_kernel(const float* __restr
   if (lane == 0) F[i] = (A > 0.f && B > 0.f) ? (zr * zr + zi * zi) / (A * B) : 0.f;
 }
 
-// Ranking loss over the batch and dLoss/dF_i (one block).
-__global__ __launch_bounds__(1024) void ranking_loss_kernel(const float* __restrict__ F,
-                                                            const int32_t* __restrict__ ld,
-                                                            int32_t n, float* __restrict__ dF,
-                                                            float* __restrict__ loss) {
+// Ranking loss, pass 1: thread (i, part) sums over its eighth of the j's the
+// terms of pair (i, j): loss softplus(z) and count for d_i < d_j (z = -(F_i -
+// F_j) / tau), and the unscaled dLoss/dF_i contributions -sigma(z_ij) (d_i <
+// d_j) and +sigma(z_ji) (d_j < d_i).  The eight parts are summed in a fixed
+// order; per-i results go to g, lossv, cntv.
+constexpr int kRankI = 32, kRankParts = 8;
+
+__global__ __launch_bounds__(kRankI * kRankParts) void ranking_pairs_kernel(
+    const float* __restrict__ F, const int32_t* __restrict__ ld, int32_t n,
+    float* __restrict__ g_out, float* __restrict__ loss_out, int32_t* __restrict__ cnt_out) {
   __shared__ float sF[RM_LEARNED_MAX_PAIRS];
   __shared__ int sL[RM_LEARNED_MAX_PAIRS];
-  __shared__ float red[2][32];
+  __shared__ float rg[kRankParts][kRankI], rl[kRankParts][kRankI];
+  __shared__ int rc[kRankParts][kRankI];
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     sF[i] = F[i];
     sL[i] = ld[i];
   }
   __syncthreads();
-  float my_loss = 0.f, my_cnt = 0.f;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    float g = 0.f;
-    for (int j = 0; j < n; ++j) {
-      if (sL[i] < sL[j]) {  // want F_i > F_j
-        float z = -(sF[i] - sF[j]) / kTau;
-        my_loss += z > 20.f ? z : log1pf(expf(z));
-        my_cnt += 1.f;
+  const int ti = threadIdx.x % kRankI, part = threadIdx.x / kRankI;
+  const int i = blockIdx.x * kRankI + ti;
+  float g = 0.f, l = 0.f;
+  int cnt = 0;
+  if (i < n) {
+    const float Fi = sF[i];
+    const int Li = sL[i];
+    const int per = (n + kRankParts - 1) / kRankParts;
+    const int j0 = part * per, j1 = min(n, j0 + per);
+    for (int j = j0; j < j1; ++j) {
+      const int Lj = sL[j];
+      if (Li < Lj) {  // want F_i > F_j
+        const float z = -(Fi - sF[j]) / kTau;
+        l += z > 20.f ? z : log1pf(expf(z));
+        ++cnt;
         g -= 1.f / (1.f + expf(-z));
-      } else if (sL[j] < sL[i]) {
-        float z = -(sF[j] - sF[i]) / kTau;
+      } else if (Lj < Li) {
+        const float z = -(sF[j] - Fi) / kTau;
         g += 1.f / (1.f + expf(-z));
       }
     }
-    dF[i] = g;  // scaled by 1 / (tau * count) below
   }
-  // block sums of loss and pair count
-  float l = wave_sum(my_loss), c = wave_sum(my_cnt);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-    red[0][wv] = l;
-    red[1][wv] = c;
-  }
+  rg[part][ti] = g;
+  rl[part][ti] = l;
+  rc[part][ti] = cnt;
   __syncthreads();
-  __shared__ float tot[2];
-  if (threadIdx.x == 0) {
-    float L = 0.f, C = 0.f;
-    for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
-      L += red[0][v];
-      C += red[1][v];
+  if (part == 0 && i < n) {
+    for (int q = 1; q < kRankParts; ++q) {
+      g += rg[q][ti];
+      l += rl[q][ti];
+      cnt += rc[q][ti];
     }
-    tot[0] = L;
-    tot[1] = C;
-    *loss = C > 0.f ? L / C : 0.f;
+    g_out[i] = g;
+    loss_out[i] = l;
+    cnt_out[i] = cnt;
   }
+}
+
+// Ranking loss, pass 2 (one block): the loss is the sum of the terms over the
+// number of ordered pairs; dLoss/dF_i = g_i / (tau * count).
+__global__ __launch_bounds__(1024) void ranking_finalize_kernel(
+    float* __restrict__ g, const float* __restrict__ lossv, const int32_t* __restrict__ cntv,
+    int32_t n, float* __restrict__ loss) {
+  __shared__ float sl[1024];
+  __shared__ int sc[1024];
+  const int t = threadIdx.x;
+  sl[t] = t < n ? lossv[t] : 0.f;
+  sc[t] = t < n ? cntv[t] : 0;
   __syncthreads();
-  const float scale = tot[1] > 0.f ? 1.f / (kTau * tot[1]) : 0.f;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dF[i] *= scale;
+  for (int d = 512; d > 0; d >>= 1) {  // fixed-order tree
+    if (t < d) {
+      sl[t] += sl[t + d];
+      sc[t] += sc[t + d];
+    }
+    __syncthreads();
+  }
+  const float C = (float)sc[0];
+  if (t == 0) *loss = sc[0] > 0 ? sl[0] / C : 0.f;
+  const float scale = sc[0] > 0 ? 1.f / (kTau * C) : 0.f;
+  if (t < n) g[t] *= scale;
 }
 
 // Backward: per string, dLoss/dc = dLoss/dF * dF/dc, then through the tokens
@@ -388,15 +416,37 @@ __global__ __launch_bounds__(64 * kWaves, 2) void learned_backward_kernel(
   for (int i = threadIdx.x; i < kOut; i += blockDim.x) out[kB2 + i] = red[kRedB2 + i];
 }
 
-// Sum of the per-block partial gradients; then either the gradient is written
-// (grad != nullptr) or an Adam step is applied to state = [params | m | v | t].
-__global__ __launch_bounds__(256) void reduce_adam_kernel(const float* __restrict__ partial,
-                                                          int n_blocks, float* __restrict__ grad,
-                                                          float* __restrict__ state, float lr) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kParams) return;
+// Sum of the per-block partial gradients (block: 64 parameters x 16 subsets
+// of the partials, summed in a fixed order); then either the gradient is
+// written (grad != nullptr) or an Adam step is applied to state = [params | m
+// | v | t].
+constexpr int kRedParams = 64, kRedParts = 16;
+
+__global__ __launch_bounds__(kRedParams * kRedParts) void reduce_adam_kernel(
+    const float* __restrict__ partial, int n_blocks, float* __restrict__ grad,
+    float* __restrict__ state, float lr) {
+  __shared__ float red[kRedParts][kRedParams];
+  const int tp = threadIdx.x % kRedParams, q = threadIdx.x / kRedParams;
+  const int i = blockIdx.x * kRedParams + tp;
   float g = 0.f;
-  for (int b = 0; b < n_blocks; ++b) g += partial[(int64_t)b * kParams + i];
+  if (i < kParams) {
+    int b = q;
+    for (; b + 3 * kRedParts < n_blocks; b += 4 * kRedParts) {  // 4 loads in flight
+      const float v0 = partial[(int64_t)b * kParams + i];
+      const float v1 = partial[(int64_t)(b + kRedParts) * kParams + i];
+      const float v2 = partial[(int64_t)(b + 2 * kRedParts) * kParams + i];
+      const float v3 = partial[(int64_t)(b + 3 * kRedParts) * kParams + i];
+      g += v0;
+      g += v1;
+      g += v2;
+      g += v3;
+    }
+    for (; b < n_blocks; b += kRedParts) g += partial[(int64_t)b * kParams + i];
+  }
+  red[q][tp] = g;
+  __syncthreads();
+  if (q != 0 || i >= kParams) return;
+  for (int r = 1; r < kRedParts; ++r) g += red[r][tp];
   if (grad != nullptr) {
     grad[i] = g;
     return;
@@ -423,7 +473,7 @@ size_t learned_workspace_bytes(int32_t n_pairs) {
   int64_t blocks = (strings + kWaves - 1) / kWaves;
   size_t bytes = 0;
   bytes += (size_t)strings * 256 * sizeof(float);  // encodings
-  bytes += (size_t)n_pairs * sizeof(float) * 2;    // F, dF
+  bytes += (size_t)n_pairs * sizeof(float) * 4;    // F, dF, per-i loss, per-i count
   bytes += 256;                                    // loss
   bytes += (size_t)blocks * kParams * sizeof(float);
   return (bytes + 255) / 256 * 256 + 1024;
@@ -463,19 +513,24 @@ hipError_t launch_learned_step(float* state, float lr, const uint8_t* a, const i
   float* c = reinterpret_cast<float*>(base);
   float* F = c + strings * 256;
   float* dF = F + n_pairs;
-  float* loss_ws = dF + n_pairs;
+  float* lossv = dF + n_pairs;
+  int32_t* cntv = reinterpret_cast<int32_t*>(lossv + n_pairs);
+  float* loss_ws = reinterpret_cast<float*>(cntv + n_pairs);
   float* partial = reinterpret_cast<float*>(
       (reinterpret_cast<uintptr_t>(loss_ws + 64) + 255) / 256 * 256);
   hipLaunchKernelGGL(learned_encode_kernel, dim3(blocks), dim3(64 * kWaves), 0, s, state, st,
                      (int32_t)strings, N, c);
   hipLaunchKernelGGL(pair_fidelity_kernel, dim3((unsigned)((n_pairs + 3) / 4)), dim3(256), 0, s, c,
                      c + 256, (int64_t)512, n_pairs, F);
-  hipLaunchKernelGGL(ranking_loss_kernel, dim3(1), dim3(1024), 0, s, F, ld, n_pairs, dF,
+  hipLaunchKernelGGL(ranking_pairs_kernel, dim3((unsigned)((n_pairs + kRankI - 1) / kRankI)),
+                     dim3(kRankI * kRankParts), 0, s, F, ld, n_pairs, dF, lossv, cntv);
+  hipLaunchKernelGGL(ranking_finalize_kernel, dim3(1), dim3(1024), 0, s, dF, lossv, cntv, n_pairs,
                      loss_out ? loss_out : loss_ws);
   hipLaunchKernelGGL(learned_backward_kernel, dim3(blocks), dim3(64 * kWaves), 0, s, state, st,
                      n_pairs, N, c, dF, partial);
-  hipLaunchKernelGGL(reduce_adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, partial,
-                     (int)blocks, grad_out, grad_out ? nullptr : state, lr);
+  hipLaunchKernelGGL(reduce_adam_kernel, dim3((kParams + kRedParams - 1) / kRedParams),
+                     dim3(kRedParams * kRedParts), 0, s, partial, (int)blocks, grad_out,
+                     grad_out ? nullptr : state, lr);
   if (grad_out == nullptr)
     hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, s, state);
   return hipGetLastError();

@@ -30,14 +30,19 @@ __device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, in
   for (int pb = 0; pb < n; pb += 64) {
     int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
     int cnt = min(64, n - pb);
-
-    for (int i = 0; i < cnt; ++i) {
-      int L = __builtin_amdgcn_readlane(mine, i);
-      float2 e = phase32[(int64_t)(pb + i) * kM + k];
-      a0.x += (L == L0) ? e.x : 0.f;
-      a0.y += (L == L0) ? e.y : 0.f;
-      a1.x += (L == L1) ? e.x : 0.f;
-      a1.y += (L == L1) ? e.y : 0.f;
+    // groups of 8 positions with their table loads in flight together
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      float2 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = phase32[(int64_t)min(pb + i0 + u, n - 1) * kM + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int L = __builtin_amdgcn_readlane(mine, i0 + u);
+        a0.x += (L == L0) ? e[u].x : 0.f;
+        a0.y += (L == L0) ? e[u].y : 0.f;
+        a1.x += (L == L1) ? e[u].x : 0.f;
+        a1.y += (L == L1) ? e[u].y : 0.f;
+      }
     }
   }
 }
@@ -57,16 +62,26 @@ __device__ __forceinline__ void direct_sum32_learned(const uint8_t* __restrict__
   for (int pb = 0; pb < T; pb += 64) {
     int mine = (pb + lane < T) ? (int)str[pb + lane + 4] : 255;
     int cnt = min(64, T - pb);
-    for (int i = 0; i < cnt; ++i) {
-      int L = __builtin_amdgcn_readlane(mine, i);
-      const int p = pb + i;
-      float sn, cs;
-      sincosf(drow[(int64_t)p * 32 + k], &sn, &cs);
-      const float2 e = cmul(phase32[(int64_t)p * kM + k], make_float2(cs, sn));
-      a0.x += (L == L0) ? e.x : 0.f;
-      a0.y += (L == L0) ? e.y : 0.f;
-      a1.x += (L == L1) ? e.x : 0.f;
-      a1.y += (L == L1) ? e.y : 0.f;
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      float2 ph[8];
+      float d[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(pb + i0 + u, T - 1);
+        ph[u] = phase32[(int64_t)p * kM + k];
+        d[u] = drow[(int64_t)p * 32 + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int L = __builtin_amdgcn_readlane(mine, i0 + u);
+        float sn, cs;
+        sincosf(d[u], &sn, &cs);
+        const float2 e = cmul(ph[u], make_float2(cs, sn));
+        a0.x += (L == L0) ? e.x : 0.f;
+        a0.y += (L == L0) ? e.y : 0.f;
+        a1.x += (L == L1) ? e.x : 0.f;
+        a1.y += (L == L1) ? e.y : 0.f;
+      }
     }
   }
 }

@@ -191,6 +191,8 @@ struct ScoreKernel {
   static constexpr int CB = ENT - KP;                   // buffer slots per read
   static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
   static_assert(CB >= 1, "buffer");
+  static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
+  static_assert(NF * 8 <= 32, "pending hits are 32-bit masks of (fragment, row pair)");
   static_assert(STAGES >= 2, "stages");
 };
 
@@ -324,14 +326,14 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   };
 
   // ---- merge a read's buffer into its list (whole wavefront, uniform call)
-  auto merge_reads = [&](uint32_t mask) {
+  auto merge_reads = [&](uint64_t mask) {
     // ENT == 32: two reads at a time (one per half-wave); ENT == 64: one read.
     while (mask) {
-      int r0 = __builtin_ctz(mask);
+      int r0 = __builtin_ctzll(mask);
       mask &= mask - 1;
       int r1 = -1;
       if (ENT == 32 && mask) {
-        r1 = __builtin_ctz(mask);
+        r1 = __builtin_ctzll(mask);
         mask &= mask - 1;
       }
       int my = (ENT == 32 && lane >= 32) ? r1 : r0;
@@ -437,7 +439,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
           }
         __builtin_amdgcn_wave_barrier();
         bool full = lane < NF * 16 && cnt[rb0 + lane] >= K::CB;
-        uint32_t fm = (uint32_t)__ballot(full);
+        const uint64_t fm = __ballot(full);
         if (fm) merge_reads(fm);
         if (!__ballot(pend != 0)) break;
       }
@@ -476,7 +478,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // ---- final merge and write-out of this chunk's lists
   {
     bool any = lane < NF * 16 && cnt[rb0 + lane] > 0;
-    uint32_t m = (uint32_t)__ballot(any);
+    const uint64_t m = __ballot(any);
     if (m) merge_reads(m);
     __builtin_amdgcn_wave_barrier();
     for (int i = lane; i < NF * 16 * KP; i += 64) {
