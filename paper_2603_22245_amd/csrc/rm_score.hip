@@ -30,7 +30,8 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kTileW = 32;  // windows per B tile (the MFMA N dimension)
+constexpr int kBlkW = 32;   // windows per MFMA column block (the MFMA N dimension)
+constexpr int kPlanW = 64;  // chunk boundaries are multiples of this many windows
 // The register test re^2 + im^2 - t > 0 is computed with fused multiply-adds,
 // which round differently from the F stored in a key; lowering t by 2^-20
 // relative sends every candidate within rounding of the k-th best to the exact
@@ -128,56 +129,74 @@ __device__ __forceinline__ void wait_vmcnt() {
 // 16 (col & 15), so logical byte offset o is found at row + (kx ^ o).  Any
 // assignment of K indices to (lane group, register slot) works as long as A
 // and B use the same one, which they do here.
-template <int PREC, int NF, int AU4>
+template <int PREC, int NF, int NB, int AU4>
 __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8_t* row,
-                                          uint32_t kx, f32x16 (&acc)[NF]) {
+                                          uint32_t kx, f32x16 (&acc)[NF][NB]) {
+  // column block nb of the tile: rows 32 nb + col (same swizzle key: 32 nb
+  // leaves the row's low four bits alone)
+  constexpr int BLK = kBlkW * Prec<PREC>::esize * kReal;
   if constexpr (PREC == RM_FP16) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      uint4 bv = *reinterpret_cast<const uint4*>(row + (kx ^ (16u * s)));
-      half8 bh = __builtin_bit_cast(half8, bv);
+      half8 bh[NB];
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
-        acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a[f][s]), bh,
-                                                        acc[f], 0, 0, 0);
+      for (int nb = 0; nb < NB; ++nb)
+        bh[nb] = __builtin_bit_cast(half8,
+                                    *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (16u * s))));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          acc[f][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a[f][s]),
+                                                              bh[nb], acc[f][nb], 0, 0, 0);
     }
   } else if constexpr (PREC == RM_FP8_E4M3) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      uint4 b0 = *reinterpret_cast<const uint4*>(row + (kx ^ (32u * s)));
-      uint4 b1 = *reinterpret_cast<const uint4*>(row + (kx ^ (32u * s + 16u)));
-      i32x8 bb = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
-                  (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+      i32x8 bb[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        uint4 b0 = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (32u * s)));
+        uint4 b1 = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (32u * s + 16u)));
+        bb[nb] = i32x8{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
+                       (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+      }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const uint4 a0 = a[f][2 * s], a1 = a[f][2 * s + 1];
         i32x8 aa = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
                     (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
         // formats 0/0 = FP8 e4m3 for both operands; E8M0 scales 127 = 1.0
-        acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aa, bb, acc[f], 0, 0, 0, 127, 0,
-                                                                  127);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[f][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aa, bb[nb], acc[f][nb], 0, 0,
+                                                                        0, 127, 0, 127);
       }
     }
   } else {
 #pragma unroll
     for (int s4 = 0; s4 < 32; ++s4) {
-      uint4 bv = *reinterpret_cast<const uint4*>(row + (kx ^ (16u * s4)));
-      float bf[4] = {__uint_as_float(bv.x), __uint_as_float(bv.y), __uint_as_float(bv.z),
-                     __uint_as_float(bv.w)};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int nb = 0; nb < NB; ++nb) {
+        uint4 bv = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (16u * s4)));
+        float bf[4] = {__uint_as_float(bv.x), __uint_as_float(bv.y), __uint_as_float(bv.z),
+                       __uint_as_float(bv.w)};
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const uint4 av = a[f][s4];
-          uint32_t ab = q == 0 ? av.x : q == 1 ? av.y : q == 2 ? av.z : av.w;
-          acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ab), bf[q], acc[f], 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const uint4 av = a[f][s4];
+            uint32_t ab = q == 0 ? av.x : q == 1 ? av.y : q == 2 ? av.z : av.w;
+            acc[f][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ab), bf[q],
+                                                              acc[f][nb], 0, 0, 0);
+          }
         }
       }
     }
   }
 }
 
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
 struct ScoreKernel {
   static constexpr int esize = Prec<PREC>::esize;
   static constexpr int RB = kReal * esize;              // bytes per embedding row
@@ -185,24 +204,26 @@ struct ScoreKernel {
   static constexpr int AU4 = (kReal / 2) * esize / 16;  // uint4 per lane per fragment
   static constexpr int READS = WAVES * NF * 16;         // reads per block
   static constexpr int THREADS = WAVES * 64;
-  static constexpr int TILE = kTileW * RB;              // bytes per B tile
+  static constexpr int TW = kBlkW * NB;                 // windows per B tile
+  static constexpr int TILE = TW * RB;                  // bytes per B tile
   static constexpr int L = TILE / 1024 / WAVES;         // 1 KB copies per wave per tile
   static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 1 : 0);  // + the window scales
   static constexpr int CB = ENT - KP;                   // buffer slots per read
   static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
   static_assert(CB >= 1, "buffer");
   static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
-  static_assert(NF * 8 <= 32, "pending hits are 32-bit masks of (fragment, row pair)");
+  static_assert(NF * NB * 8 <= 64, "pending hits are 64-bit masks of (block, fragment, row pair)");
+  static_assert(kPlanW % TW == 0, "chunks hold whole tiles");
   static_assert(STAGES >= 2, "stages");
 };
 
 // One work item: read tile `tile` of group G against window chunk `chunk`.
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
 __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int tile,
                                            uint8_t* ring, float* ring_scale,
                                            uint64_t (*lst)[ENT], int* cnt, float* thr,
                                            float* rsq) {
-  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES>;
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
   const uint8_t* __restrict__ index = G.index;
   const float* __restrict__ win_scale = G.win_scale;
@@ -217,13 +238,13 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar registers
   const int g = lane >> 5;
   const int col = lane & 31;
   const int64_t read0 = (int64_t)tile * K::READS;
   const int64_t wbeg = (int64_t)chunk * chunk_windows;
   const int64_t wend = min(W, wbeg + chunk_windows);
-  const int ntiles = (int)((wend - wbeg + kTileW - 1) / kTileW);
+  const int ntiles = (int)((wend - wbeg + K::TW - 1) / K::TW);
 
   // ---- per-read state (each wavefront owns its reads)
   const int rb0 = wave * NF * 16;
@@ -291,7 +312,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   }
   // copy window tile `tsrc` into ring stage `stage`
   auto issue_into = [&](int tsrc, int stage) {
-    const int64_t tb = wbeg + (int64_t)tsrc * kTileW;
+    const int64_t tb = wbeg + (int64_t)tsrc * K::TW;
 #pragma unroll
     for (int i = 0; i < K::L; ++i) {
       int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
@@ -299,9 +320,9 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
             __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * WAVES + wave) * 1024));
     }
     if constexpr (kFp8) {
-      if (lane < 32)
+      if (lane < K::TW)
         dma4(win_scale + min(tb + lane, wend - 1),
-             __builtin_amdgcn_readfirstlane(scale_lds + (stage * WAVES + wave) * 128));
+             __builtin_amdgcn_readfirstlane(scale_lds + (stage * WAVES + wave) * K::TW * 4));
     }
   };
 
@@ -369,74 +390,89 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // the tile's MFMAs.  The epilogue of tile t runs after the MFMAs of tile t+1
   // have been issued, in the same basic block, so its VALU work fills the
   // MFMA pipeline's latency.
-  auto start_tile = [&](int t, f32x16 (&acc)[NF], float& sj2) {
+  auto start_tile = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
     wait_vmcnt<(STAGES - 2) * K::LT>();
     __syncthreads();
     const int stage = t % STAGES;
     if constexpr (kFp8) {
-      float sc = ring_scale[(stage * WAVES + wave) * 32 + col];
-      sj2 = sc * sc;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        float sc = ring_scale[(stage * WAVES + wave) * K::TW + nb * kBlkW + col];
+        sj2[nb] = sc * sc;
+      }
     }
     issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = f32x16{};
-    mfma_tile<PREC, NF, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x16{};
+    mfma_tile<PREC, NF, NB, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
   };
 
   // re^2 + im^2 - threshold per (read slot, window col), reduced with max;
   // only a positive maximum anywhere in the wavefront leads to the (rare)
   // per-score test and appends.
-  auto epilogue = [&](int t, const f32x16 (&acc)[NF], float sj2) {
+  auto epilogue = [&](int t, const f32x16 (&acc)[NF][NB], const float (&sj2)[NB]) {
     if ((t & 255) == 255) refresh_thresholds();  // pick up other chunks' progress
-    const int64_t tbase = wbeg + (int64_t)t * kTileW;
-    const int32_t j = (int32_t)(tbase + col);
-    const bool colok = tbase + col < wend;
-    float isj2 = 1.f;
-    if constexpr (kFp8) isj2 = sj2 > 0.f ? 1.f / sj2 : 0.f;
+    const int64_t tbase = wbeg + (int64_t)t * K::TW;
+    bool colok[NB];
+    float isj2[NB];
     float ex = -1.f;
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        float re = acc[f][2 * q], im = acc[f][2 * q + 1];
-        float tq = th[f][q];
-        if constexpr (kFp8) tq = tq * isj2;
-        ex = fmaxf(ex, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)));
-      }
-    if (!colok) ex = -1.f;
-
-    if (__ballot(ex > 0.f)) {
-      uint32_t pend = 0;
+    for (int nb = 0; nb < NB; ++nb) {
+      colok[nb] = tbase + nb * kBlkW + col < wend;
+      isj2[nb] = 1.f;
+      if constexpr (kFp8) isj2[nb] = sj2[nb] > 0.f ? 1.f / sj2[nb] : 0.f;
+      float exb = -1.f;
 #pragma unroll
       for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          float re = acc[f][2 * q], im = acc[f][2 * q + 1];
+          float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
           float tq = th[f][q];
-          if constexpr (kFp8) tq = tq * isj2;
-          pend |= (uint32_t)(colok && __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)) > 0.f)
-                  << (f * 8 + q);
+          if constexpr (kFp8) tq = tq * isj2[nb];
+          exb = fmaxf(exb, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)));
         }
-      // append every hit, merging reads whose buffer is full, until nothing
-      // is pending
-      while (true) {
+      ex = colok[nb] ? fmaxf(ex, exb) : ex;
+    }
+
+    if (__ballot(ex > 0.f)) {
+      uint64_t pend = 0;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            const uint32_t bit = 1u << (f * 8 + q);
-            if (pend & bit) {
-              int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
-              int pos = atomicAdd(&cnt[rb], 1);
-              if (pos < K::CB) {
-                float re = acc[f][2 * q], im = acc[f][2 * q + 1];
-                float F = re * re + im * im;
-                if constexpr (kFp8) F = F * (rsq[rb] * sj2);
-                lst[rb][KP + pos] = make_key(F, j);
-                pend &= ~bit;
+            float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+            float tq = th[f][q];
+            if constexpr (kFp8) tq = tq * isj2[nb];
+            pend |= (uint64_t)(colok[nb] &&
+                               __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)) > 0.f)
+                    << ((nb * NF + f) * 8 + q);
+          }
+      // append every hit, merging reads whose buffer is full, until nothing
+      // is pending
+      while (true) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const uint64_t bit = 1ull << ((nb * NF + f) * 8 + q);
+              if (pend & bit) {
+                int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+                int pos = atomicAdd(&cnt[rb], 1);
+                if (pos < K::CB) {
+                  float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+                  float F = re * re + im * im;
+                  if constexpr (kFp8) F = F * (rsq[rb] * sj2[nb]);
+                  lst[rb][KP + pos] = make_key(F, (int32_t)(tbase + nb * kBlkW + col));
+                  pend &= ~bit;
+                }
               }
             }
-          }
         __builtin_amdgcn_wave_barrier();
         bool full = lane < NF * 16 && cnt[rb0 + lane] >= K::CB;
         const uint64_t fm = __ballot(full);
@@ -450,14 +486,18 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   for (int t = 0; t < STAGES - 1; ++t) issue_into(min(t, ntiles - 1), t);
 
   // FP16 keeps one accumulator set: its A fragments take 128 VGPRs and a
-  // second set would spill at two wavefronts per SIMD.
-  constexpr bool kPipe = PREC != RM_FP16;
+  // second set would spill at two wavefronts per SIMD; so do wide tiles.
+  constexpr bool kPipe = PREC != RM_FP16 && NB == 1;
   refresh_thresholds();
-  f32x16 accA[NF];
-  float sjA = 1.f;
+  f32x16 accA[NF][NB];
+  float sjA[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) sjA[nb] = 1.f;
   if constexpr (kPipe) {
-    f32x16 accB[NF];
-    float sjB = 1.f;
+    f32x16 accB[NF][NB];
+    float sjB[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) sjB[nb] = 1.f;
     start_tile(0, accA, sjA);
     for (int t = 0;; t += 2) {
       start_tile(t + 1, accB, sjB);  // past the end: a repeat of the last tile, unused
@@ -494,12 +534,12 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
 // are numbered chunk-major within each group, so concurrently running blocks
 // stream the same windows.  Every block leaves the loop once the counter has
 // passed the last item.
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
 __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
-  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES>;
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
   __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
-  __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * 32 : 4];
+  __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * K::TW : 4];
   __shared__ uint64_t lst[K::READS][ENT];
   __shared__ int cnt[K::READS];
   __shared__ float thr[K::READS];
@@ -515,8 +555,9 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
     while (gi + 1 < L.n_groups && item >= L.g[gi + 1].item_begin) ++gi;
     const ScoreGroup& G = L.g[gi];
     const int local = item - G.item_begin;
-    score_item<PREC, NF, WAVES, KP, ENT, STAGES>(G, local / G.read_tiles, local % G.read_tiles,
-                                                  ring, ring_scale, lst, cnt, thr, rsq);
+    score_item<PREC, NF, WAVES, KP, ENT, STAGES, NB>(G, local / G.read_tiles,
+                                                      local % G.read_tiles, ring, ring_scale, lst,
+                                                      cnt, thr, rsq);
   }
 }
 
@@ -568,10 +609,10 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__
   }
 }
 
-template <int PREC, int NF, int KP, int ENT, int STAGES>
+template <int PREC, int NF, int KP, int ENT, int STAGES, int NB = 1>
 hipError_t launch_persistent(const ScoreLaunch& L, hipStream_t s) {
   constexpr int WAVES = 8;
-  auto kern = score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES>;
+  auto kern = score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
   // resident blocks per CU for this instantiation (LDS and VGPR limited)
   static int per_cu = [&] {
     int n = 0;
@@ -615,8 +656,8 @@ hipError_t dispatch(int precision, int read_tile, int kp, const ScoreLaunch& L, 
   }
   if (read_tile == 256) {
     switch (kp) {
-      case 8: return launch_persistent<RM_FP8_E4M3, 2, 8, 32, 4>(L, s);
-      case 16: return launch_persistent<RM_FP8_E4M3, 2, 16, 32, 4>(L, s);
+      case 8: return launch_persistent<RM_FP8_E4M3, 2, 8, 32, 4, 2>(L, s);
+      case 16: return launch_persistent<RM_FP8_E4M3, 2, 16, 32, 4, 2>(L, s);
       default: return launch_persistent<RM_FP8_E4M3, 2, 32, 64, 3>(L, s);
     }
   }
@@ -651,7 +692,7 @@ ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_
   for (int i = 0; i < n_groups; ++i) {
     GroupPlan& gp = p.g[i];
     gp.read_tiles = (int)(((int64_t)R[i] + rt - 1) / rt);
-    int64_t tiles = (W[i] + kTileW - 1) / kTileW;
+    int64_t tiles = (W[i] + kPlanW - 1) / kPlanW;
     int64_t ct = t.chunk_tiles;
     if (ct <= 0) {
       // enough items to fill 256 CUs several times, at least 64 tiles each,
@@ -668,7 +709,7 @@ ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_
       ct = (tiles + P - 1) / P;
       P = (tiles + ct - 1) / ct;
     }
-    gp.chunk_windows = ct * kTileW;
+    gp.chunk_windows = ct * kPlanW;
     gp.chunks = (int)P;
     gp.lists_offset = off;
     off = align256(off + (size_t)R[i] * (size_t)P * (size_t)p.kp * sizeof(uint64_t));
