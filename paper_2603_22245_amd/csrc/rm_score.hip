@@ -246,8 +246,12 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   const int64_t wend = min(W, wbeg + chunk_windows);
   const int ntiles = (int)((wend - wbeg + K::TW - 1) / K::TW);
 
-  // ---- per-read state (each wavefront owns its reads)
+  // ---- per-read state (each wavefront owns reads rb0 .. rb0 + NF*16 - 1 of
+  // the tile: rows 32 (wave NF + f) .. +31 for fragment f)
   const int rb0 = wave * NF * 16;
+  auto gread = [&](int i) -> int64_t { return read0 + rb0 + i; };
+  // a wavefront whose rows all lie past the last read has nothing to score
+  const bool wave_active = read0 + rb0 < (int64_t)R;
   for (int i = lane; i < NF * 16 * ENT; i += 64) lst[rb0 + i / ENT][i % ENT] = 0;
   if (lane < NF * 16) {
     cnt[rb0 + lane] = 0;
@@ -271,7 +275,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // FP8: s_r^2 per read of the block, in LDS (1 otherwise)
   if constexpr (kFp8) {
     if (lane < NF * 16) {
-      int64_t r = read0 + rb0 + lane;
+      int64_t r = gread(lane);
       float sc = r < R ? read_scale[r] : 0.f;
       rsq[rb0 + lane] = sc * sc;
     }
@@ -327,14 +331,16 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   };
 
   // ---- thresholds: the larger of this chunk's k-th best and the best k-th
-  // best any chunk has published for the read (0 = none yet)
+  // best any chunk has published for the read (0 = none yet); slots past the
+  // last read get an unreachable threshold
   auto refresh_thresholds = [&]() {
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
-        int64_t r = read0 + rb;
+        const int i = f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+        const int rb = rb0 + i;
+        const int64_t r = gread(i);
         uint32_t gk = r < R ? __hip_atomic_load(&gthr[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         float gt = gk ? __uint_as_float(gk - 1u) : -1.f;
         float t = fmaxf(thr[rb], gt);
@@ -342,7 +348,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
           float r2 = rsq[rb];
           t = r2 > 0.f ? t / r2 : 0.f;  // F-threshold in units of the product
         }
-        th[f][q] = t * kLoose;
+        th[f][q] = r < R ? t * kLoose : 3.0e38f;
       }
   };
 
@@ -370,7 +376,8 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
           thr[rb] = kth;
           // publish this chunk's k-th best: no window scoring below it can be
           // in the read's final list, whichever chunk holds it
-          if (kth >= 0.f && read0 + rb < R) atomicMax(&gthr[read0 + rb], __float_as_uint(kth) + 1u);
+          const int64_t r = gread(my);
+          if (kth >= 0.f && r < R) atomicMax(&gthr[r], __float_as_uint(kth) + 1u);
         }
         if (id == 0) cnt[rb] = 0;
       }
@@ -488,6 +495,19 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // FP16 keeps one accumulator set: its A fragments take 128 VGPRs and a
   // second set would spill at two wavefronts per SIMD; so do wide tiles.
   constexpr bool kPipe = PREC != RM_FP16 && NB == 1;
+  if (!wave_active) {
+    // No read of this wavefront is valid (the tail of the last read tile): it
+    // only copies its share of every tile and joins every tile barrier, as
+    // many as the scoring loop below runs (one more when pipelined).
+    const int steps = kPipe ? ntiles + 1 : ntiles;
+    for (int t = 0; t < steps; ++t) {
+      wait_vmcnt<(STAGES - 2) * K::LT>();
+      __syncthreads();
+      issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
+    }
+    wait_vmcnt<0>();
+    return;  // its reads are all past R: nothing to write
+  }
   refresh_thresholds();
   f32x16 accA[NF][NB];
   float sjA[NB];
@@ -523,7 +543,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     __builtin_amdgcn_wave_barrier();
     for (int i = lane; i < NF * 16 * KP; i += 64) {
       int rr = i / KP, e = i % KP;
-      int64_t r = read0 + rb0 + rr;
+      int64_t r = gread(rr);
       if (r < R) ws[((int64_t)r * P + chunk) * KP + e] = lst[rb0 + rr][e];
     }
   }
