@@ -91,17 +91,62 @@ __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int 
   }
 }
 
+// A window's squared norm and scale wait in lane registers (lane j - jb
+// holds window j) and go out with one store per 64 windows.
+struct SideBuf {
+  int64_t jb;  // first window held
+  int n;       // windows held (uniform)
+  float n2, sc;
+};
+
+__device__ __forceinline__ void side_flush(SideBuf& b, int lane, float* norm2, float* scale) {
+  if (lane < b.n) {
+    norm2[b.jb + lane] = b.n2;
+    scale[b.jb + lane] = b.sc;
+  }
+  b.jb += b.n;
+  b.n = 0;
+}
+
 template <int PREC>
 __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c0, float2 c1,
-                                            void* emb, float* scale, float* norm2) {
+                                            void* emb, SideBuf& side, float* scale,
+                                            float* norm2) {
   float n2 = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
   bool deg = n2 < kDegenerateRel * (float)N;
-  float inv = deg ? 0.f : 1.f / sqrtf(n2);
+  float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
   Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
   float s = store_row<PREC>(emb, j, lane, x);
-  if (lane == 0) {
-    norm2[j] = n2;
-    scale[j] = s;
+  if (lane == side.n) {
+    side.n2 = n2;
+    side.sc = s;
+  }
+  if (++side.n == 64) side_flush(side, lane, norm2, scale);
+}
+
+// One slide of the window state of this lane's components (k, 2h) and
+// (k, 2h+1): rotate by `rot`, remove `uo` from the outgoing letter's component
+// and add `ui` to the incoming one's.  o and n are wavefront-uniform letter
+// codes; codes above 3 touch nothing.
+__device__ __forceinline__ void slide(float2& c0, float2& c1, float2 rot, int o, int n, int h,
+                                      float2 uo, float2 ui) {
+  c0 = cmul(c0, rot);
+  c1 = cmul(c1, rot);
+  if ((o >> 1) != h) uo = make_float2(0.f, 0.f);
+  if ((n >> 1) != h) ui = make_float2(0.f, 0.f);
+  if (o & 1) {
+    c1.x -= uo.x;
+    c1.y -= uo.y;
+  } else {
+    c0.x -= uo.x;
+    c0.y -= uo.y;
+  }
+  if (n & 1) {
+    c1.x += ui.x;
+    c1.y += ui.y;
+  } else {
+    c0.x += ui.x;
+    c0.y += ui.y;
   }
 }
 
@@ -123,7 +168,8 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   direct_sum(ref + j0 * stride, N, phase64, lane, a0, a1);
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
-  emit_window<PREC>(j0, lane, N, c0, c1, emb, scale, norm2);
+  SideBuf side{j0, 0, 0.f, 0.f};
+  emit_window<PREC>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
   const float4 st = step32[k];
   const float2 rot = make_float2(st.x, st.y);   // omega^-f
@@ -144,23 +190,19 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
     const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
     int cnt = (int)min<int64_t>(64, n_slides - tb);
     for (int i = 0; i < cnt; ++i) {
-      int o = __builtin_amdgcn_readlane(out_l, i);
-      int n = __builtin_amdgcn_readlane(in_l, i);
-      c0 = cmul(c0, rot);
-      c1 = cmul(c1, rot);
-      if (o == L0) { c0.x -= rot.x; c0.y -= rot.y; }
-      if (o == L1) { c1.x -= rot.x; c1.y -= rot.y; }
-      if (n == L0) { c0.x += inc.x; c0.y += inc.y; }
-      if (n == L1) { c1.x += inc.x; c1.y += inc.y; }
+      const int o = __builtin_amdgcn_readlane(out_l, i);
+      const int n = __builtin_amdgcn_readlane(in_l, i);
+      slide(c0, c1, rot, o, n, h, rot, inc);
       if (--until_emit == 0) {
         until_emit = stride;
         ++j;
-        emit_window<PREC>(j, lane, N, c0, c1, emb, scale, norm2);
+        emit_window<PREC>(j, lane, N, c0, c1, emb, side, scale, norm2);
       }
     }
     out_l = out_next;
     in_l = in_next;
   }
+  side_flush(side, lane, norm2, scale);
 }
 
 template <int PREC>
@@ -259,7 +301,8 @@ __global__ __launch_bounds__(256) void encode_reference_learned_kernel(
   direct_sum_learned(ref + s0, N, delta + s0 * 32, phase64, lane, a0, a1);
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
-  emit_window<PREC>(j0, lane, N, c0, c1, emb, scale, norm2);
+  SideBuf side{j0, 0, 0.f, 0.f};
+  emit_window<PREC>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
   const float4 st = step32[k];
   const float2 rot = make_float2(st.x, st.y);    // omega^-f
@@ -293,22 +336,16 @@ __global__ __launch_bounds__(256) void encode_reference_learned_kernel(
     for (int i = 0; i < cnt; ++i) {
       const int o = __builtin_amdgcn_readlane(mine, i);
       const int n = __builtin_amdgcn_readlane(mine, i + kChunk);
-      const float2 uo = cmul(stage[i][k], rot);
-      const float2 ui = cmul(stage[kChunk + i][k], inc);
-      c0 = cmul(c0, rot);
-      c1 = cmul(c1, rot);
-      if (o == L0) { c0.x -= uo.x; c0.y -= uo.y; }
-      if (o == L1) { c1.x -= uo.x; c1.y -= uo.y; }
-      if (n == L0) { c0.x += ui.x; c0.y += ui.y; }
-      if (n == L1) { c1.x += ui.x; c1.y += ui.y; }
+      slide(c0, c1, rot, o, n, h, cmul(stage[i][k], rot), cmul(stage[kChunk + i][k], inc));
       if (--until_emit == 0) {
         until_emit = stride;
         ++j;
-        emit_window<PREC>(j, lane, N, c0, c1, emb, scale, norm2);
+        emit_window<PREC>(j, lane, N, c0, c1, emb, side, scale, norm2);
       }
     }
     __builtin_amdgcn_wave_barrier();  // the stage is rewritten by the next chunk
   }
+  side_flush(side, lane, norm2, scale);
 }
 
 template <int PREC>
