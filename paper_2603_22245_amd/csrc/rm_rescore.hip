@@ -5,8 +5,8 @@
 // read head's and each candidate window's RoPE vector are direct sums of the
 // FP32-rounded angle table (§2.1-§2.2), and F = |<x|c>|^2 / (X C) (§2.4).
 // The candidates are then ordered by (F desc, window id asc) and the k best
-// kept.  One wavefront per read; lane layout as in the encoders (lane l owns
-// factor l/2 and letters 2(l&1), 2(l&1)+1).
+// kept.  Four wavefronts per read; lane layout as in the encoders (lane l
+// owns factor l/2 and letters 2(l&1), 2(l&1)+1).
 #include "rm_internal.h"
 
 namespace rm {
@@ -47,16 +47,15 @@ __device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, in
   }
 }
 
-// FP32 direct sum over the tokens p = 0..N-9 of a string whose token offsets
-// are rows drow[p]: token p adds exp(i (theta_k p + delta)) to component
-// (k, str[p+4]).
-__device__ __forceinline__ void direct_sum32_learned(const uint8_t* __restrict__ str, int N,
+// FP32 direct sum over T tokens of a string whose token offsets are rows
+// drow[p]: token p adds phase32[p] exp(i delta) to component (k, str[p+4]).
+// A range of tokens is summed by advancing str, drow and phase32 together.
+__device__ __forceinline__ void direct_sum32_learned(const uint8_t* __restrict__ str, int T,
                                                      const float* __restrict__ drow,
                                                      const float2* __restrict__ phase32, int lane,
                                                      float2& a0, float2& a1) {
   const int k = lane >> 1, h = lane & 1;
   const int L0 = 2 * h, L1 = 2 * h + 1;
-  const int T = N - 8;
   a0 = make_float2(0.f, 0.f);
   a1 = make_float2(0.f, 0.f);
   for (int pb = 0; pb < T; pb += 64) {
@@ -89,50 +88,80 @@ __device__ __forceinline__ void direct_sum32_learned(const uint8_t* __restrict__
 // ref_delta / read_delta null: the plain encoding; else the learned one with
 // the token offsets of the reference (rows = reference positions) and of the
 // reads (rows = positions in seq).
-__global__ __launch_bounds__(256) void rescore_kernel(
+//
+// One block of four wavefronts per read: each wavefront sums a quarter of the
+// read head (the quarters are added in a fixed order), then scores every
+// fourth candidate; wavefront 0 sorts the keys.
+constexpr int kRescoreWaves = 4;
+
+__global__ __launch_bounds__(64 * kRescoreWaves) void rescore_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride,
     const float2* __restrict__ phase32, const uint8_t* __restrict__ seq,
     const int64_t* __restrict__ off, int32_t R, int k_fetch, const int32_t* __restrict__ cand,
     int k, int32_t* __restrict__ top_idx, float* __restrict__ top_score,
     const float* __restrict__ ref_delta, const float* __restrict__ read_delta) {
+  __shared__ float4 part[kRescoreWaves][64];
+  __shared__ uint64_t keys[RM_MAX_KFETCH];
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= R) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r = blockIdx.x;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
+  const bool learned = ref_delta != nullptr;
+  const int T = learned ? N - 8 : N;  // terms of an encoding
+
+  // ---- read head, a quarter per wavefront
   float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
   if (len >= N) {
-    if (read_delta != nullptr)
-      direct_sum32_learned(seq + start, N, read_delta + start * 32, phase32, lane, x0, x1);
+    const int q0 = wave * T / kRescoreWaves, q1 = (wave + 1) * T / kRescoreWaves;
+    if (learned)
+      direct_sum32_learned(seq + start + q0, q1 - q0, read_delta + (start + q0) * 32,
+                           phase32 + (int64_t)q0 * kM, lane, x0, x1);
     else
-      direct_sum32(seq + start, N, phase32, lane, x0, x1);
+      direct_sum32(seq + start + q0, q1 - q0, phase32 + (int64_t)q0 * kM, lane, x0, x1);
   }
-  float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
+  part[wave][lane] = make_float4(x0.x, x0.y, x1.x, x1.y);
+  __syncthreads();
+  {
+    float4 v = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRescoreWaves; ++w) {
+      const float4 u = part[w][lane];
+      v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+    }
+    x0 = make_float2(v.x, v.y);
+    x1 = make_float2(v.z, v.w);
+  }
+  const float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
   const bool xdeg = X < kDegenerateRel * (float)N;
 
-  // lane e (< k_fetch) ends up holding candidate e's key
-  uint64_t key = 0;
-  for (int e = 0; e < k_fetch; ++e) {
-    int32_t j = cand[r * k_fetch + e];
-    if (j < 0 || j >= W) continue;  // uniform per wavefront
-    float2 c0, c1;
-    if (ref_delta != nullptr)
-      direct_sum32_learned(ref + (int64_t)j * stride, N, ref_delta + (int64_t)j * stride * 32,
-                           phase32, lane, c0, c1);
-    else
-      direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
-    float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
-    // <x|c> = sum conj(x) c
-    float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
-    float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
-    bool deg = xdeg || C < kDegenerateRel * (float)N;
-    float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
-    if (lane == e) {
+  // ---- candidates e = wave, wave + 4, ...
+  for (int e = wave; e < k_fetch; e += kRescoreWaves) {
+    const int32_t j = cand[r * k_fetch + e];
+    uint64_t key = 0;
+    if (j >= 0 && j < W) {  // uniform per wavefront
+      float2 c0, c1;
+      if (learned)
+        direct_sum32_learned(ref + (int64_t)j * stride, T, ref_delta + (int64_t)j * stride * 32,
+                             phase32, lane, c0, c1);
+      else
+        direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
+      float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+      // <x|c> = sum conj(x) c
+      float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
+      float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
+      bool deg = xdeg || C < kDegenerateRel * (float)N;
+      float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
       uint32_t hi = __float_as_uint(F) + 1u;
       key = ((uint64_t)hi << 32) | (0xffffffffu - (uint32_t)j);
     }
+    if (lane == 0) keys[e] = key;
   }
-  // bitonic sort of the 64 lanes' keys, descending (empty keys are 0)
+  __syncthreads();
+  if (wave != 0) return;
+
+  // ---- bitonic sort of the keys, descending (empty keys are 0)
+  uint64_t key = lane < k_fetch ? keys[lane] : 0;
 #pragma unroll
   for (int kk = 2; kk <= 64; kk <<= 1) {
 #pragma unroll
@@ -158,8 +187,8 @@ hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t
                           const int64_t* off, int32_t n_reads, int32_t k_fetch,
                           const int32_t* cand_idx, int32_t k, int32_t* top_idx, float* top_score,
                           hipStream_t s, const float* ref_delta, const float* read_delta) {
-  unsigned blocks = (unsigned)(((int64_t)n_reads + 3) / 4);
-  hipLaunchKernelGGL(rescore_kernel, dim3(blocks), dim3(256), 0, s, ref, idx.n_windows,
+  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)n_reads), dim3(64 * kRescoreWaves), 0, s, ref,
+                     idx.n_windows,
                      idx.p.window_len, idx.p.stride, reinterpret_cast<const float2*>(idx.d_phase32),
                      seq, off, n_reads, k_fetch, cand_idx, k, top_idx, top_score, ref_delta,
                      read_delta);
