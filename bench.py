@@ -30,6 +30,36 @@ FLOPS_PER_SCORE = 1024  # two 256-long real dot products (Re and Im rows), 2 flo
 HBM_PEAK_GBS = 8000.0
 
 
+SCORE_SOURCES = ("paper_2603_22245_amd/csrc/rm_score.hip", "paper_2603_22245_amd/csrc/rm_internal.h")
+
+
+def score_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SCORE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per scoring launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE of a rocprofv3 --pmc run of this benchmark,
+    scaled by a plain copy's readings), or None when there is no summary for
+    this precision or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"score_topk_{precision}_precision_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.loads(fh.read().split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    if d.get("source_sha256") != score_source_digest():
+        return None
+    return d.get("bytes_per_launch")
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -162,8 +192,9 @@ def main():
     achieved = R * W * FLOPS_PER_SCORE / score_s / 1e12
     peak = PEAK_TFLOPS[precision]
     enc_bytes = W * (256 * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
+    traffic = measured_traffic(precision) if R == w.n_reads else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "score_topk_kernel (+merge_kernel)",
                 "algorithmic": f"{FLOPS_PER_SCORE} flops per (read, window) score x {R} x {W}"}
 
@@ -177,6 +208,8 @@ def main():
                    "window_len": w.window_len, "n_freq": w.n_freq, "stride": w.stride,
                    "k": k, "k_fetch": k_fetch, "precision": precision},
         "window_scores_per_s": float(f"{R * W / score_s:.4g}"),
+        # the same step on an index built beforehand (reads -> product -> rescore)
+        "reads_per_s_prebuilt_index": round(R / ((parts[1] + parts[2] + parts[3]) / 1e3), 1),
         "breakdown_ms": {"encode_reference": round(parts[0], 3), "encode_reads": round(parts[1], 3),
                          "score_topk": round(parts[2], 3), "rescore": round(parts[3], 3)},
         "encoder_gbs": round(enc_bytes / (parts[0] / 1e3) / 1e9, 1),
@@ -268,6 +301,7 @@ def bench_batching(args):
                    "precision": precision,
                    "tuning": {"read_tile": best.read_tile, "chunk_tiles": best.chunk_tiles}},
         "window_scores_per_s": float(f"{scores / (parts[2] / 1e3):.4g}"),
+        "reads_per_s_prebuilt_index_eager": round(R / ((parts[1] + parts[2] + parts[3]) / 1e3), 1),
         "breakdown_ms_eager": {"encode_references": round(parts[0], 3),
                                "encode_reads": round(parts[1], 3),
                                "score_topk_grouped": round(parts[2], 3),

@@ -715,9 +715,11 @@ ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_
     int64_t tiles = (W[i] + kPlanW - 1) / kPlanW;
     int64_t ct = t.chunk_tiles;
     if (ct <= 0) {
-      // enough items to fill 256 CUs several times, at least 64 tiles each,
-      // at most 1024 keys per read for the merge
-      int64_t P = (256 * 8 + gp.read_tiles - 1) / gp.read_tiles;
+      // about 30 items per CU of a 256-CU chip (a short last round), at least
+      // 64 tile units each, at most 1024 keys per read for the merge; fewer,
+      // longer items leave an uneven last round, more items repeat each
+      // read's top-k warm-up in more chunks
+      int64_t P = (256 * 30 + gp.read_tiles - 1) / gp.read_tiles;
       if (P > (tiles + 63) / 64) P = (tiles + 63) / 64;
       if (P < 1) P = 1;
       ct = (tiles + P - 1) / P;
