@@ -340,7 +340,8 @@ int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d
  * memory, into d_out[i] (int32): the labels of the ranking loss and the
  * reference for rank correlations.  Letters must be codes 0..3 (any other code
  * matches nothing, itself included).  The shorter string of a pair may have at
- * most 256 letters; a longer one gives -1.  Errors: RM_EINVAL, RM_ESIZE (n < 1). */
+ * most 256 letters; a longer one gives -1.  Errors: RM_EINVAL, RM_ESIZE (n < 1 or
+ * n > 2^31 * 256 - 256). */
 int rm_levenshtein(const uint8_t* d_a, const int64_t* d_aoff, const uint8_t* d_b,
                    const int64_t* d_boff, int64_t n, int32_t* d_out, void* stream);
 

@@ -378,7 +378,7 @@ int rm_learned_gradient(const float* d_params, const uint8_t* d_a, const int64_t
 int rm_levenshtein(const uint8_t* d_a, const int64_t* d_aoff, const uint8_t* d_b,
                    const int64_t* d_boff, int64_t n, int32_t* d_out, void* stream) {
   if (!d_a || !d_aoff || !d_b || !d_boff || !d_out) return RM_EINVAL;
-  if (n < 1) return RM_ESIZE;
+  if (n < 1 || n > (int64_t)INT32_MAX * 256) return RM_ESIZE;  // one thread per pair
   return hip_status(rm::launch_levenshtein(d_a, d_aoff, d_b, d_boff, n, d_out,
                                            static_cast<hipStream_t>(stream)));
 }

@@ -115,3 +115,49 @@ def test_read_score_rescore_validation():
     assert rs(10, 8, 0) == L.RM_ESIZE
     assert rs(0, 8, 8) == L.RM_ESIZE
     assert lib.rm_rescore(R(idx), None, 1, 1, 10, 8, 1, 8, 1, 1, None) == L.RM_EINVAL
+
+
+def test_learned_and_edit_distance_validation():
+    """Argument checks of the learned and edit-distance entry points run on the
+    host and return before anything is enqueued."""
+    lib = L.lib()
+    R = ctypes.byref
+    assert L.rm_learned_workspace_bytes(1) == 0
+    assert L.rm_learned_workspace_bytes(L.RM_LEARNED_MAX_PAIRS + 1) == 0
+    ws = L.rm_learned_workspace_bytes(64)
+    assert ws > 64 * 2 * 256 * 4
+    assert L.rm_delta_bytes(8) == 0
+    assert L.rm_delta_bytes(9) == 32 * 4
+    # train step / gradient
+    st = lambda n, ln, nb, loss=1: lib.rm_learned_train_step(1, 1e-3, 1, 1, 1, 1, 1, n, ln, 1, nb,
+                                                             loss, None)
+    assert st(64, 150, ws - 1) == L.RM_ESIZE        # (every call here fails validation)
+    assert st(1, 150, ws) == L.RM_ESIZE
+    assert st(L.RM_LEARNED_MAX_PAIRS + 1, 150, 1 << 40) == L.RM_ESIZE
+    assert st(64, 0, ws) == L.RM_ESIZE
+    assert st(64, 150, ws, loss=None) == L.RM_EINVAL
+    assert lib.rm_learned_gradient(1, 1, 1, 1, 1, 1, 64, 150, 1, ws, None, 1, None) == L.RM_EINVAL
+    # encode, fidelity, inference
+    assert lib.rm_learned_encode(None, None, 1, 4, 150, 1, None) == L.RM_EINVAL
+    assert lib.rm_learned_encode(None, 1, 1, 0, 150, 1, None) == L.RM_ESIZE
+    assert lib.rm_pair_fidelity(1, None, 4, 1, None) == L.RM_EINVAL
+    assert lib.rm_pair_fidelity(1, 1, 0, 1, None) == L.RM_ESIZE
+    assert lib.rm_mlp_infer(1, 1, 8, 0x1000, None) == L.RM_ESIZE
+    assert lib.rm_mlp_infer(1, 1, 100, 0x1004, None) == L.RM_EINVAL        # misaligned offsets
+    assert lib.rm_mlp_infer(None, 1, 100, 0x1000, None) == L.RM_EINVAL
+    # learned mapping calls
+    idx = _fake_index()
+    p = L.make_params(8, 1, 32, "default", "fp16")
+    out = L.rm_index()
+    assert lib.rm_encode_reference_learned(1, 1000, R(p), 1, 0x10000, 1 << 30, R(out), None) \
+        == L.RM_ESIZE                                                       # N < 9
+    p = L.make_params(150, 1, 32, "default", "fp16")
+    assert lib.rm_encode_reference_learned(1, 1000, R(p), None, 0x10000, 1 << 30, R(out), None) \
+        == L.RM_EINVAL
+    assert lib.rm_encode_reads_learned(R(idx), 1, 1, 10, None, 1, 1, None) == L.RM_EINVAL
+    assert lib.rm_rescore_learned(R(idx), 1, None, 1, 1, 1, 10, 8, 1, 8, 1, 1, None) == L.RM_EINVAL
+    assert lib.rm_rescore_learned(R(idx), 1, 1, 1, 1, 1, 10, 8, 1, 9, 1, 1, None) == L.RM_ESIZE
+    # edit distance
+    assert lib.rm_levenshtein(None, 1, 1, 1, 10, 1, None) == L.RM_EINVAL
+    assert lib.rm_levenshtein(1, 1, 1, 1, 0, 1, None) == L.RM_ESIZE
+    assert lib.rm_levenshtein(1, 1, 1, 1, (2**31) * 256, 1, None) == L.RM_ESIZE
