@@ -322,3 +322,67 @@ def test_edge_cases():
         assert np.all(tsc[2] == 0.0) and list(tidx[2]) == list(range(8)), prec  # short read
         e = emb_to_complex(index, torch)
         assert np.all(e[1000:1251] == 0)                   # windows inside the run
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_largest_window_length(precision):
+    """N = RM_MAX_WINDOW: sampled index rows and squared norms against the
+    oracle one window at a time; exact and mutated reads of that length."""
+    from paper_2603_22245_amd import _lib as L
+    torch = torch_cuda()
+    N = L.RM_MAX_WINDOW
+    rng = np.random.default_rng(15)
+    ref = rng.integers(0, 4, 20_000).astype(np.uint8)
+    index = _build(ref, precision, window_len=N)
+    W = index.n_windows
+    assert W == 20_000 - N + 1
+    rows = np.unique(np.r_[0, 1, 255, 256, 257, W // 2, W - 2, W - 1, rng.choice(W, 12)])
+    got = emb_to_complex(index, torch)[rows]
+    want = np.stack([rope.encode_raw(ref[j:j + N], N, 32) for j in rows])
+    wn, n2 = mapping.normalized_rows(want, N)
+    # FP32 rolling error; FP16 adds half an ulp (2^-11 relative)
+    rel = 1e-5 if precision == "fp32" else 2.0 ** -11
+    for part in (np.real, np.imag):
+        assert np.all(np.abs(part(got) - part(wn)) <= rel * np.abs(part(wn)) + 2e-5)
+    norms = index.norms2().cpu().numpy()[rows]
+    assert np.max(np.abs(norms / n2 - 1)) <= 2e-4
+    # reads: exact copies of windows 0, 1234 and W-1, and a mutated copy of 2000
+    mut = ref[2000:2000 + N].copy()
+    pos = rng.choice(N, N // 100, replace=False)
+    mut[pos] = (mut[pos] + rng.integers(1, 4, pos.size)) % 4
+    heads = [ref[0:N], ref[1234:1234 + N], ref[W - 1:W - 1 + N], mut]
+    seq = np.concatenate(heads)
+    off = np.arange(5, dtype=np.int64) * N
+    reads = synth.Reads(seq, off, np.array([0, 1234, W - 1, 2000]))
+    rb, bufs = _map(index, reads, 4, 8)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy().astype(np.float64)
+    assert list(tidx[:3, 0]) == [0, 1234, W - 1]
+    assert np.all(np.abs(tsc[:3, 0] - 1) < 1e-5)
+    F = mapping.pair_fidelities(ref, np.stack(heads), tidx.astype(np.int64), N)
+    assert np.max(np.abs(tsc - F)) <= 1e-4
+    # with 32 frequencies over 16,384 letters neighbouring windows score almost
+    # alike: the mutated read's best must be the oracle's best near its origin
+    near = np.arange(1900, 2101, dtype=np.int64)[None, :]
+    Fn = mapping.pair_fidelities(ref, mut[None, :], near, N)[0]
+    assert abs(int(tidx[3, 0]) - 2000) <= 100
+    assert tsc[3, 0] >= Fn.max() - 1e-4
+
+
+def test_one_letter_windows():
+    """N = 1: a window is one letter (phase 1), so every window holding the
+    read's letter scores 1 and the list is the first k such windows."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(16)
+    ref = rng.integers(0, 4, 3000).astype(np.uint8)
+    index = _build(ref, "fp16", window_len=1)
+    assert index.n_windows == 3000
+    seq = np.array([0, 1, 2, 3], dtype=np.uint8)
+    reads = synth.Reads(seq, np.arange(5, dtype=np.int64), np.zeros(4, np.int64))
+    rb, bufs = _map(index, reads, 8, 16)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    for L in range(4):
+        want = np.nonzero(ref == L)[0][:8]
+        assert list(tidx[L]) == list(want), L
+        assert np.all(np.abs(tsc[L] - 1) < 1e-6)
