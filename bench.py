@@ -30,7 +30,13 @@ FLOPS_PER_SCORE = 1024  # two 256-long real dot products (Re and Im rows), 2 flo
 HBM_PEAK_GBS = 8000.0
 
 
-SCORE_SOURCES = ("paper_2603_22245_amd/csrc/rm_score.hip", "paper_2603_22245_amd/csrc/rm_internal.h")
+SCORE_SOURCES = (
+    "paper_2603_22245_amd/csrc/rm_score.hip",
+    "paper_2603_22245_amd/csrc/rm_score_f16.hip",
+    "paper_2603_22245_amd/csrc/rm_score_kernel.h",
+    "paper_2603_22245_amd/csrc/rm_internal.h",
+    "paper_2603_22245_amd/build.py",
+)
 
 
 def score_source_digest() -> str:

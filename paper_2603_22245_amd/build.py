@@ -2,7 +2,10 @@
 
 Every .hip file under csrc/ is compiled with hipcc for gfx950 and linked into
 paper_2603_22245_amd/librotormap.so.  Packed-FP32 instruction selection is
-turned off for device code.
+turned off for device code.  The FP16 scoring kernel is scheduled with LLVM's
+iterative-ilp machine scheduler, which overlaps the next tile's LDS fragment
+loads with the current tile's MFMAs (about 3% faster at full size; for the FP8
+and FP32 instantiations it is not faster, so they keep the default).
 """
 from __future__ import annotations
 
@@ -25,6 +28,10 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"),
 ]
+# Extra hipcc options per source file.
+FILE_FLAGS = {
+    "rm_score_f16.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
 
 
 def sources():
@@ -33,7 +40,7 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -91,7 +91,7 @@ extern "C" int rm_autotune_score(const rm_index* idx, int32_t n_groups,
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return RM_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return RM_EHIP;
   }
   float best_t = -1.f;
@@ -125,8 +125,8 @@ extern "C" int rm_autotune_score(const rm_index* idx, int32_t n_groups,
       best_c = c;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (status != RM_OK) return status;
   if (best_t < 0.f) return RM_ESIZE;  // no candidate fits the workspace
   *best = best_c;

@@ -1,0 +1,24 @@
+// FP16 instantiations of the scoring kernel.  They live in a translation
+// unit of their own so that they can be scheduled for instruction-level
+// parallelism (the build passes LLVM's iterative-ilp machine scheduler for this
+// file only): with it the compiler overlaps the next tile's B-fragment loads
+// from LDS with the current tile's MFMAs.
+#include "rm_score_kernel.h"
+
+namespace rm {
+
+hipError_t dispatch_score_f16(int read_tile, int kp, const ScoreLaunch& L, hipStream_t s) {
+  if (read_tile == 256) {
+    switch (kp) {
+      case 8: return launch_persistent<RM_FP16, 2, 8, 32, 4>(L, s);
+      default: return launch_persistent<RM_FP16, 2, 16, 32, 4>(L, s);
+    }
+  }
+  switch (kp) {
+    case 8: return launch_persistent<RM_FP16, 1, 8, 32, 4>(L, s);
+    case 16: return launch_persistent<RM_FP16, 1, 16, 32, 4>(L, s);
+    default: return launch_persistent<RM_FP16, 1, 32, 64, 4>(L, s);
+  }
+}
+
+}  // namespace rm

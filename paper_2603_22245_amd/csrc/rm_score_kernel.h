@@ -1,0 +1,617 @@
+// Scoring GEMM with fused per-read top-k, and the merge of per-chunk lists.
+//
+// §3.1 computes the fidelity of every read head with every index vector -- a
+// matrix product -- and keeps the best locations.  With reads stored as two
+// real rows (Re row (xr, xi), Im row (-xi, xr)) and windows as one real row
+// (cr, ci), the real product S = A B^T gives Re<x|c> = S[2r, j] and
+// Im<x|c> = S[2r+1, j] (the complex/real isomorphism of §4), and
+// F = Re^2 + Im^2 for unit vectors (times (s_r s_j)^2 for FP8 scales).
+//
+// Work item = (read tile, window chunk).  A block keeps its read tile in
+// registers (each wavefront owns NF fragments of 32 rows = 16 reads, the full
+// K = 256) and streams the chunk's windows through LDS in tiles of 32
+// (double-buffered).  Per tile every wavefront runs NF x (256/K_mfma) MFMAs
+// on 32x32 output blocks; the epilogue forms F per (read, window) in
+// registers, compares with the read's current k-th best and, only for hits,
+// appends (F, j) to the read's LDS buffer.  Full buffers are merged into the
+// read's sorted list by a bitonic sort across lanes.  The score matrix never
+// leaves registers.
+//
+// List entries are 64-bit keys: high word = float bits of F plus one (0 means
+// empty), low word = ~j; a larger key is a better candidate (F descending,
+// then window id ascending), so one integer comparison orders them exactly.
+//
+// This header holds the kernel templates; each translation unit that
+// includes it instantiates its own precisions (internal linkage), so they can
+// be compiled with different code-generation options.
+#pragma once
+
+#include "rm_internal.h"
+
+namespace rm {
+
+// FP16 instantiations of the scoring kernel (rm_score_f16.hip).
+hipError_t dispatch_score_f16(int read_tile, int kp, const ScoreLaunch& L, hipStream_t s);
+
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBlkW = 32;   // windows per MFMA column block (the MFMA N dimension)
+constexpr int kPlanW = 64;  // chunk boundaries are multiples of this many windows
+// The register test re^2 + im^2 - t > 0 is computed with fused multiply-adds,
+// which round differently from the F stored in a key; lowering t by 2^-20
+// relative sends every candidate within rounding of the k-th best to the exact
+// key comparison instead of dropping it.  (t < 0 for a list that is not full.)
+constexpr float kLoose = 1.0f - 1.0f / 1048576.0f;
+
+__device__ __forceinline__ uint64_t make_key(float F, int32_t j) {
+  uint32_t hi = __float_as_uint(F) + 1u;  // F >= 0
+  uint32_t lo = 0xffffffffu - (uint32_t)j;
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ float key_score(uint64_t key) {
+  uint32_t hi = (uint32_t)(key >> 32);
+  return hi ? __uint_as_float(hi - 1u) : -1.f;
+}
+__device__ __forceinline__ int32_t key_index(uint64_t key) {
+  uint32_t hi = (uint32_t)(key >> 32);
+  return hi ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
+  uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
+  uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sort keys descending within each group of ENT consecutive lanes (bitonic).
+template <int ENT>
+__device__ __forceinline__ uint64_t sort_desc(uint64_t key, int lane) {
+  const int id = lane & (ENT - 1);
+#pragma unroll
+  for (int kk = 2; kk <= ENT; kk <<= 1) {
+#pragma unroll
+    for (int d = kk >> 1; d > 0; d >>= 1) {
+      uint64_t other = shfl_xor64(key, d);
+      bool desc_block = (id & kk) == 0;
+      bool lower = (id & d) == 0;
+      bool keep_max = (lower == desc_block);
+      uint64_t mx = key > other ? key : other;
+      uint64_t mn = key > other ? other : key;
+      key = keep_max ? mx : mn;
+    }
+  }
+  return key;
+}
+
+template <int PREC>
+struct Prec;
+template <>
+struct Prec<RM_FP32> {
+  static constexpr int esize = 4;
+};
+template <>
+struct Prec<RM_FP16> {
+  static constexpr int esize = 2;
+};
+template <>
+struct Prec<RM_FP8_E4M3> {
+  static constexpr int esize = 1;
+};
+
+// LDS byte offset of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const void*)p);
+}
+
+// Asynchronous copy from global memory straight into LDS (gfx950
+// global_load_lds_*): lane l writes 16 (dma16) or 4 (dma4) bytes at LDS
+// offset lds + l * size.  Written as inline assembly, with no output register,
+// so that the compiler does not drain every outstanding copy (vmcnt(0)) before
+// each LDS read; completion is awaited explicitly with wait_vmcnt<N>(), which
+// counts this wavefront's vector-memory operations in issue order.
+__device__ __forceinline__ void dma16(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
+               : "memory");
+}
+__device__ __forceinline__ void dma4(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(lds)
+               : "memory");
+}
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// B tiles in LDS: row r (one window, RB bytes) stores its logical 16-byte chunk
+// c at position c ^ (r & 15).  A lane reading chunk c of row `col` therefore
+// reads byte offset col*RB + 16 (c ^ (col & 15)); the 16 lanes of one LDS
+// access cycle (consecutive col, same c) hit 16 different bank groups.
+//
+// One 32x32 output block per fragment over the full K = 256.  `a[f]` holds
+// this lane's 128 K-elements of fragment f (K range [128 g, 128 g + 128),
+// g = lane / 32, in natural order); `row` points at this lane's window row in
+// the current LDS stage and kx = (byte offset of the lane's K half) ^
+// 16 (col & 15), so logical byte offset o is found at row + (kx ^ o).  Any
+// assignment of K indices to (lane group, register slot) works as long as A
+// and B use the same one, which they do here.
+template <int PREC, int NF, int NB, int AU4>
+__device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8_t* row,
+                                          uint32_t kx, f32x16 (&acc)[NF][NB]) {
+  // column block nb of the tile: rows 32 nb + col (same swizzle key: 32 nb
+  // leaves the row's low four bits alone)
+  constexpr int BLK = kBlkW * Prec<PREC>::esize * kReal;
+  if constexpr (PREC == RM_FP16) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      half8 bh[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bh[nb] = __builtin_bit_cast(half8,
+                                    *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (16u * s))));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          acc[f][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a[f][s]),
+                                                              bh[nb], acc[f][nb], 0, 0, 0);
+    }
+  } else if constexpr (PREC == RM_FP8_E4M3) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      i32x8 bb[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        uint4 b0 = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (32u * s)));
+        uint4 b1 = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (32u * s + 16u)));
+        bb[nb] = i32x8{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
+                       (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const uint4 a0 = a[f][2 * s], a1 = a[f][2 * s + 1];
+        i32x8 aa = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                    (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+        // formats 0/0 = FP8 e4m3 for both operands; E8M0 scales 127 = 1.0
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[f][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aa, bb[nb], acc[f][nb], 0, 0,
+                                                                        0, 127, 0, 127);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s4 = 0; s4 < 32; ++s4) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        uint4 bv = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (16u * s4)));
+        float bf[4] = {__uint_as_float(bv.x), __uint_as_float(bv.y), __uint_as_float(bv.z),
+                       __uint_as_float(bv.w)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const uint4 av = a[f][s4];
+            uint32_t ab = q == 0 ? av.x : q == 1 ? av.y : q == 2 ? av.z : av.w;
+            acc[f][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ab), bf[q],
+                                                              acc[f][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
+struct ScoreKernel {
+  static constexpr int esize = Prec<PREC>::esize;
+  static constexpr int RB = kReal * esize;              // bytes per embedding row
+  static constexpr int CPR = RB / 16;                   // 16-byte chunks per row
+  static constexpr int AU4 = (kReal / 2) * esize / 16;  // uint4 per lane per fragment
+  static constexpr int READS = WAVES * NF * 16;         // reads per block
+  static constexpr int THREADS = WAVES * 64;
+  static constexpr int TW = kBlkW * NB;                 // windows per B tile
+  static constexpr int TILE = TW * RB;                  // bytes per B tile
+  static constexpr int L = TILE / 1024 / WAVES;         // 1 KB copies per wave per tile
+  static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 1 : 0);  // + the window scales
+  static constexpr int CB = ENT - KP;                   // buffer slots per read
+  static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
+  static_assert(CB >= 1, "buffer");
+  static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
+  static_assert(NF * NB * 8 <= 64, "pending hits are 64-bit masks of (block, fragment, row pair)");
+  static_assert(kPlanW % TW == 0, "chunks hold whole tiles");
+  static_assert(STAGES >= 2, "stages");
+};
+
+// One work item: read tile `tile` of group G against window chunk `chunk`.
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
+__device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int tile,
+                                           uint8_t* ring, float* ring_scale,
+                                           uint64_t (*lst)[ENT], int* cnt, float* thr,
+                                           float* rsq) {
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
+  constexpr bool kFp8 = PREC == RM_FP8_E4M3;
+  const uint8_t* __restrict__ index = G.index;
+  const float* __restrict__ win_scale = G.win_scale;
+  const int64_t W = G.W;
+  const uint8_t* __restrict__ reads = G.reads;
+  const float* __restrict__ read_scale = G.read_scale;
+  const int32_t R = G.R;
+  const int64_t chunk_windows = G.chunk_windows;
+  const int P = G.P;
+  uint64_t* __restrict__ ws = G.lists;
+  uint32_t* __restrict__ gthr = G.gthr;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar registers
+  const int g = lane >> 5;
+  const int col = lane & 31;
+  const int64_t read0 = (int64_t)tile * K::READS;
+  const int64_t wbeg = (int64_t)chunk * chunk_windows;
+  const int64_t wend = min(W, wbeg + chunk_windows);
+  const int ntiles = (int)((wend - wbeg + K::TW - 1) / K::TW);
+
+  // ---- per-read state (each wavefront owns reads rb0 .. rb0 + NF*16 - 1 of
+  // the tile: rows 32 (wave NF + f) .. +31 for fragment f)
+  const int rb0 = wave * NF * 16;
+  auto gread = [&](int i) -> int64_t { return read0 + rb0 + i; };
+  // a wavefront whose rows all lie past the last read has nothing to score
+  const bool wave_active = read0 + rb0 < (int64_t)R;
+  for (int i = lane; i < NF * 16 * ENT; i += 64) lst[rb0 + i / ENT][i % ENT] = 0;
+  if (lane < NF * 16) {
+    cnt[rb0 + lane] = 0;
+    thr[rb0 + lane] = -1.f;
+  }
+
+  // ---- A fragments: this lane's K half of row (read tile row) for each fragment
+  uint4 a[NF][K::AU4];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    int64_t row = 2 * read0 + (int64_t)(wave * NF + f) * 32 + col;
+    if (row < 2 * (int64_t)R) {
+      const uint4* src = reinterpret_cast<const uint4*>(reads + row * K::RB + g * (K::RB / 2));
+#pragma unroll
+      for (int u = 0; u < K::AU4; ++u) a[f][u] = src[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < K::AU4; ++u) a[f][u] = make_uint4(0, 0, 0, 0);
+    }
+  }
+  // FP8: s_r^2 per read of the block, in LDS (1 otherwise)
+  if constexpr (kFp8) {
+    if (lane < NF * 16) {
+      int64_t r = gread(lane);
+      float sc = r < R ? read_scale[r] : 0.f;
+      rsq[rb0 + lane] = sc * sc;
+    }
+  }
+  // Wait for these loads here, before the tile loop: otherwise the compiler's
+  // wait-count state from them reaches into the loop.
+  {
+    uint32_t any = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int u = 0; u < K::AU4; ++u) any |= a[f][u].x | a[f][u].w;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (any == 0xdeadbeefu && R < 0) ws[0] = any;  // never true; keeps the use
+  }
+
+  // thresholds in the product's units: F-threshold / s_r^2 (further divided by
+  // s_j^2 per window in the epilogue), lowered by kLoose
+  float th[NF][8];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) th[f][q] = -1.f;
+
+  // ---- B tiles: asynchronous copies into an LDS ring of STAGES tiles
+  const uint32_t ring_lds = lds_offset(ring);
+  const uint32_t scale_lds = lds_offset(ring_scale);
+  int drow[K::L];
+  uint32_t doff[K::L];
+#pragma unroll
+  for (int i = 0; i < K::L; ++i) {
+    int pos = (i * WAVES + wave) * 64 + lane;  // physical 16-byte chunk in the tile
+    int r = pos / K::CPR;
+    int c = (pos % K::CPR) ^ (r & 15);          // logical chunk stored there
+    drow[i] = r;
+    doff[i] = (uint32_t)c * 16u;
+  }
+  // copy window tile `tsrc` into ring stage `stage`
+  auto issue_into = [&](int tsrc, int stage) {
+    const int64_t tb = wbeg + (int64_t)tsrc * K::TW;
+#pragma unroll
+    for (int i = 0; i < K::L; ++i) {
+      int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
+      dma16(index + grow * K::RB + doff[i],
+            __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * WAVES + wave) * 1024));
+    }
+    if constexpr (kFp8) {
+      if (lane < K::TW)
+        dma4(win_scale + min(tb + lane, wend - 1),
+             __builtin_amdgcn_readfirstlane(scale_lds + (stage * WAVES + wave) * K::TW * 4));
+    }
+  };
+
+  // ---- thresholds: the larger of this chunk's k-th best and the best k-th
+  // best any chunk has published for the read (0 = none yet); slots past the
+  // last read get an unreachable threshold
+  auto refresh_thresholds = [&]() {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+        const int rb = rb0 + i;
+        const int64_t r = gread(i);
+        uint32_t gk = r < R ? __hip_atomic_load(&gthr[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        float gt = gk ? __uint_as_float(gk - 1u) : -1.f;
+        float t = fmaxf(thr[rb], gt);
+        if constexpr (kFp8) {
+          float r2 = rsq[rb];
+          t = r2 > 0.f ? t / r2 : 0.f;  // F-threshold in units of the product
+        }
+        th[f][q] = r < R ? t * kLoose : 3.0e38f;
+      }
+  };
+
+  // ---- merge a read's buffer into its list (whole wavefront, uniform call)
+  auto merge_reads = [&](uint64_t mask) {
+    // ENT == 32: two reads at a time (one per half-wave); ENT == 64: one read.
+    while (mask) {
+      int r0 = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      int r1 = -1;
+      if (ENT == 32 && mask) {
+        r1 = __builtin_ctzll(mask);
+        mask &= mask - 1;
+      }
+      int my = (ENT == 32 && lane >= 32) ? r1 : r0;
+      int id = lane & (ENT - 1);
+      if (my >= 0) {
+        int rb = rb0 + my;
+        int n = min(cnt[rb], K::CB);
+        uint64_t key = (id < KP + n) ? lst[rb][id] : 0;
+        key = sort_desc<ENT>(key, lane);
+        if (id < KP) lst[rb][id] = key;
+        if (id == KP - 1) {
+          float kth = key_score(key);
+          thr[rb] = kth;
+          // publish this chunk's k-th best: no window scoring below it can be
+          // in the read's final list, whichever chunk holds it
+          const int64_t r = gread(my);
+          if (kth >= 0.f && r < R) atomicMax(&gthr[r], __float_as_uint(kth) + 1u);
+        }
+        if (id == 0) cnt[rb] = 0;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    refresh_thresholds();
+  };
+
+  // lane's B row offset and K-half key (see mfma_tile)
+  const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
+
+  // Pipeline: the ring always has copies of the next STAGES-2 tiles in flight
+  // (past the last tile the copies repeat the last tile, so every tile step
+  // issues the same number of copies and waits for the same count).  A tile
+  // step waits for its own tile, synchronises the block (every copy landed;
+  // the stage of the previous tile is free), refills that stage and issues
+  // the tile's MFMAs.  The epilogue of tile t runs after the MFMAs of tile t+1
+  // have been issued, in the same basic block, so its VALU work fills the
+  // MFMA pipeline's latency.
+  auto start_tile = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
+    wait_vmcnt<(STAGES - 2) * K::LT>();
+    __syncthreads();
+    const int stage = t % STAGES;
+    if constexpr (kFp8) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        float sc = ring_scale[(stage * WAVES + wave) * K::TW + nb * kBlkW + col];
+        sj2[nb] = sc * sc;
+      }
+    }
+    issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x16{};
+    mfma_tile<PREC, NF, NB, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
+  };
+
+  // re^2 + im^2 - threshold per (read slot, window col), reduced with max;
+  // only a positive maximum anywhere in the wavefront leads to the (rare)
+  // per-score test and appends.
+  auto epilogue = [&](int t, const f32x16 (&acc)[NF][NB], const float (&sj2)[NB]) {
+    if ((t & 255) == 255) refresh_thresholds();  // pick up other chunks' progress
+    const int64_t tbase = wbeg + (int64_t)t * K::TW;
+    bool colok[NB];
+    float isj2[NB];
+    float ex = -1.f;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      colok[nb] = tbase + nb * kBlkW + col < wend;
+      isj2[nb] = 1.f;
+      if constexpr (kFp8) isj2[nb] = sj2[nb] > 0.f ? 1.f / sj2[nb] : 0.f;
+      float exb = -1.f;
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+          float tq = th[f][q];
+          if constexpr (kFp8) tq = tq * isj2[nb];
+          exb = fmaxf(exb, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)));
+        }
+      ex = colok[nb] ? fmaxf(ex, exb) : ex;
+    }
+
+    if (__ballot(ex > 0.f)) {
+      uint64_t pend = 0;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+            float tq = th[f][q];
+            if constexpr (kFp8) tq = tq * isj2[nb];
+            pend |= (uint64_t)(colok[nb] &&
+                               __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)) > 0.f)
+                    << ((nb * NF + f) * 8 + q);
+          }
+      // append every hit, merging reads whose buffer is full, until nothing
+      // is pending
+      while (true) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const uint64_t bit = 1ull << ((nb * NF + f) * 8 + q);
+              if (pend & bit) {
+                int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+                int pos = atomicAdd(&cnt[rb], 1);
+                if (pos < K::CB) {
+                  float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+                  float F = re * re + im * im;
+                  if constexpr (kFp8) F = F * (rsq[rb] * sj2[nb]);
+                  lst[rb][KP + pos] = make_key(F, (int32_t)(tbase + nb * kBlkW + col));
+                  pend &= ~bit;
+                }
+              }
+            }
+        __builtin_amdgcn_wave_barrier();
+        bool full = lane < NF * 16 && cnt[rb0 + lane] >= K::CB;
+        const uint64_t fm = __ballot(full);
+        if (fm) merge_reads(fm);
+        if (!__ballot(pend != 0)) break;
+      }
+    }
+  };
+
+#pragma unroll
+  for (int t = 0; t < STAGES - 1; ++t) issue_into(min(t, ntiles - 1), t);
+
+  // FP16 keeps one accumulator set: its A fragments take 128 VGPRs and a
+  // second set would spill at two wavefronts per SIMD; so do wide tiles.
+  constexpr bool kPipe = PREC != RM_FP16 && NB == 1;
+  if (!wave_active) {
+    // No read of this wavefront is valid (the tail of the last read tile): it
+    // only copies its share of every tile and joins every tile barrier, as
+    // many as the scoring loop below runs (one more when pipelined).
+    const int steps = kPipe ? ntiles + 1 : ntiles;
+    for (int t = 0; t < steps; ++t) {
+      wait_vmcnt<(STAGES - 2) * K::LT>();
+      __syncthreads();
+      issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
+    }
+    wait_vmcnt<0>();
+    return;  // its reads are all past R: nothing to write
+  }
+  refresh_thresholds();
+  f32x16 accA[NF][NB];
+  float sjA[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) sjA[nb] = 1.f;
+  if constexpr (kPipe) {
+    f32x16 accB[NF][NB];
+    float sjB[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) sjB[nb] = 1.f;
+    start_tile(0, accA, sjA);
+    for (int t = 0;; t += 2) {
+      start_tile(t + 1, accB, sjB);  // past the end: a repeat of the last tile, unused
+      epilogue(t, accA, sjA);
+      if (t + 1 >= ntiles) break;
+      start_tile(t + 2, accA, sjA);
+      epilogue(t + 1, accB, sjB);
+      if (t + 2 >= ntiles) break;
+    }
+  } else {
+    for (int t = 0; t < ntiles; ++t) {
+      start_tile(t, accA, sjA);
+      epilogue(t, accA, sjA);
+    }
+  }
+  wait_vmcnt<0>();  // no copy may still be writing this block's LDS
+
+  // ---- final merge and write-out of this chunk's lists
+  {
+    bool any = lane < NF * 16 && cnt[rb0 + lane] > 0;
+    const uint64_t m = __ballot(any);
+    if (m) merge_reads(m);
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < NF * 16 * KP; i += 64) {
+      int rr = i / KP, e = i % KP;
+      int64_t r = gread(rr);
+      if (r < R) ws[((int64_t)r * P + chunk) * KP + e] = lst[rb0 + rr][e];
+    }
+  }
+}
+
+// Persistent grouped kernel: a grid sized to the chip pulls work items
+// (group, chunk, read tile) from a device counter until all are done.  Items
+// are numbered chunk-major within each group, so concurrently running blocks
+// stream the same windows.  Every block leaves the loop once the counter has
+// passed the last item.
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
+__global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
+  constexpr bool kFp8 = PREC == RM_FP8_E4M3;
+  __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
+  __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * K::TW : 4];
+  __shared__ uint64_t lst[K::READS][ENT];
+  __shared__ int cnt[K::READS];
+  __shared__ float thr[K::READS];
+  __shared__ float rsq[kFp8 ? K::READS : 1];
+  __shared__ int s_item;
+  while (true) {
+    __syncthreads();  // the previous item is finished with s_item and all LDS
+    if (threadIdx.x == 0) s_item = atomicAdd(L.counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= L.total_items) break;
+    int gi = 0;
+    while (gi + 1 < L.n_groups && item >= L.g[gi + 1].item_begin) ++gi;
+    const ScoreGroup& G = L.g[gi];
+    const int local = item - G.item_begin;
+    score_item<PREC, NF, WAVES, KP, ENT, STAGES, NB>(G, local / G.read_tiles,
+                                                      local % G.read_tiles, ring, ring_scale, lst,
+                                                      cnt, thr, rsq);
+  }
+}
+
+template <int PREC, int NF, int KP, int ENT, int STAGES, int NB = 1>
+hipError_t launch_persistent(const ScoreLaunch& L, hipStream_t s) {
+  constexpr int WAVES = 8;
+  auto kern = score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
+  // resident blocks per CU for this instantiation (LDS and VGPR limited)
+  static int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, WAVES * 64, 0) != hipSuccess || n < 1)
+      n = 1;
+    return n;
+  }();
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  int64_t grid = (int64_t)per_cu * cus;
+  if (grid > L.total_items) grid = L.total_items;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(WAVES * 64), 0, s, L);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+}  // namespace rm
