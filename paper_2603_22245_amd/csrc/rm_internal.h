@@ -130,7 +130,7 @@ struct ScoreLaunch {
 
 struct Tuning {
   int read_tile;    // reads per block (128 or 256); 0 = default
-  int chunk_tiles;  // 32-window tiles per work item; 0 = default
+  int chunk_tiles;  // 64-window units per work item; 0 = default
 };
 
 struct GroupPlan {

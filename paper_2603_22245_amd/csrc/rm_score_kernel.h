@@ -359,6 +359,11 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         }
         th[f][q] = r < R ? t * kLoose : 3.0e38f;
       }
+    // Settle the threshold loads on every path (vmcnt(0); expcnt and lgkmcnt
+    // not waited): a load whose value one branch leaves unused would otherwise
+    // make the compiler wait for all vector memory -- the tile copies in
+    // flight included -- before the next MFMA that reuses its register.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
   };
 
   // ---- merge a read's buffer into its list (whole wavefront, uniform call)
@@ -406,9 +411,14 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // the tile's MFMAs.  The epilogue of tile t runs after the MFMAs of tile t+1
   // have been issued, in the same basic block, so its VALU work fills the
   // MFMA pipeline's latency.
-  auto start_tile = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
+  auto sync_tile = [&](int t) {
     wait_vmcnt<(STAGES - 2) * K::LT>();
     __syncthreads();
+    issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
+  };
+  // tile t's MFMAs (and, for FP8, its window scales); valid between the
+  // barriers of steps t and t + 1
+  auto mfma_step = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
     const int stage = t % STAGES;
     if constexpr (kFp8) {
 #pragma unroll
@@ -417,12 +427,15 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         sj2[nb] = sc * sc;
       }
     }
-    issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x16{};
     mfma_tile<PREC, NF, NB, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
+  };
+  auto start_tile = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
+    sync_tile(t);
+    mfma_step(t, acc, sj2);
   };
 
   // re^2 + im^2 - threshold per (read slot, window col), reduced with max;
@@ -536,11 +549,26 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
       epilogue(t + 1, accB, sjB);
       if (t + 2 >= ntiles) break;
     }
-  } else {
+  } else if (wave < WAVES / 2) {
+    // one accumulator set: MFMAs of tile t, then its epilogue
     for (int t = 0; t < ntiles; ++t) {
       start_tile(t, accA, sjA);
       epilogue(t, accA, sjA);
     }
+  } else {
+    // The other wavefront of each SIMD (wavefronts w and w + WAVES/2 share
+    // one) runs half a step out of phase: after the barrier of step t it
+    // first finishes the epilogue of tile t-1, then issues tile t's MFMAs, so
+    // one wavefront's epilogue overlaps the other's MFMAs instead of both
+    // leaving the matrix pipe idle together.  Both halves pass the same ntiles
+    // barriers, and each reads tile t only between barriers t and t+1.
+    start_tile(0, accA, sjA);
+    for (int t = 1; t < ntiles; ++t) {
+      sync_tile(t);
+      epilogue(t - 1, accA, sjA);
+      mfma_step(t, accA, sjA);
+    }
+    epilogue(ntiles - 1, accA, sjA);
   }
   wait_vmcnt<0>();  // no copy may still be writing this block's LDS
 
