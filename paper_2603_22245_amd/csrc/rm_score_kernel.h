@@ -218,12 +218,17 @@ struct ScoreKernel {
   static constexpr int L = TILE / 1024 / WAVES;         // 1 KB copies per wave per tile
   static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 1 : 0);  // + the window scales
   static constexpr int CB = ENT - KP;                   // buffer slots per read
+  // one block barrier per GRP tiles; copies run LEAD tiles ahead.  FP8
+  // tiles carry twice the epilogue work per MFMA cycle of FP16 ones, and
+  // halving their barriers pays (2%); for FP16 it costs 2.5%.
+  static constexpr int GRP = PREC == RM_FP8_E4M3 && STAGES >= 4 ? 2 : 1;
+  static constexpr int LEAD = STAGES - GRP;
   static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
   static_assert(CB >= 1, "buffer");
   static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
   static_assert(NF * NB * 8 <= 64, "pending hits are 64-bit masks of (block, fragment, row pair)");
   static_assert(kPlanW % TW == 0, "chunks hold whole tiles");
-  static_assert(STAGES >= 2, "stages");
+  static_assert(STAGES >= 2 && LEAD >= GRP, "stages");
 };
 
 // One work item: read tile `tile` of group G against window chunk `chunk`.
@@ -403,21 +408,25 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // lane's B row offset and K-half key (see mfma_tile)
   const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
 
-  // Pipeline: the ring always has copies of the next STAGES-2 tiles in flight
-  // (past the last tile the copies repeat the last tile, so every tile step
-  // issues the same number of copies and waits for the same count).  A tile
-  // step waits for its own tile, synchronises the block (every copy landed;
-  // the stage of the previous tile is free), refills that stage and issues
-  // the tile's MFMAs.  The epilogue of tile t runs after the MFMAs of tile t+1
-  // have been issued, in the same basic block, so its VALU work fills the
-  // MFMA pipeline's latency.
+  // Pipeline: copies run LEAD tiles ahead of the tile being scored (past the
+  // last tile they repeat the last tile, so every group issues the same
+  // number of copies and waits for the same count).  Every GRP tiles the
+  // block synchronises once: each wavefront first waits for its own copies of
+  // the group's GRP tiles, so after the barrier they are all in LDS, and every
+  // wavefront has issued its MFMAs on the previous group's tiles, whose
+  // stages are then refilled with the tiles LEAD ahead.  When pipelined, the
+  // epilogue of tile t runs after the MFMAs of tile t+1 have been issued, in
+  // the same basic block, so its VALU work fills the MFMA pipeline's latency.
   auto sync_tile = [&](int t) {
-    wait_vmcnt<(STAGES - 2) * K::LT>();
+    if (t % K::GRP) return;
+    wait_vmcnt<(K::LEAD - K::GRP) * K::LT>();
     __syncthreads();
-    issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
+#pragma unroll
+    for (int gi = 0; gi < K::GRP; ++gi)
+      issue_into(min(t + K::LEAD + gi, ntiles - 1), (t + K::LEAD + gi) % STAGES);
   };
-  // tile t's MFMAs (and, for FP8, its window scales); valid between the
-  // barriers of steps t and t + 1
+  // tile t's MFMAs (and, for FP8, its window scales); valid from the barrier
+  // of tile t's group until the barrier after it
   auto mfma_step = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
     const int stage = t % STAGES;
     if constexpr (kFp8) {
@@ -512,21 +521,18 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   };
 
 #pragma unroll
-  for (int t = 0; t < STAGES - 1; ++t) issue_into(min(t, ntiles - 1), t);
+  for (int t = 0; t < K::LEAD; ++t) issue_into(min(t, ntiles - 1), t);
 
   // FP16 keeps one accumulator set: its A fragments take 128 VGPRs and a
   // second set would spill at two wavefronts per SIMD; so do wide tiles.
   constexpr bool kPipe = PREC != RM_FP16 && NB == 1;
   if (!wave_active) {
     // No read of this wavefront is valid (the tail of the last read tile): it
-    // only copies its share of every tile and joins every tile barrier, as
-    // many as the scoring loop below runs (one more when pipelined).
+    // only copies its share of every tile and joins every block barrier, for
+    // as many tile steps as the scoring loop below runs (one more when
+    // pipelined).
     const int steps = kPipe ? ntiles + 1 : ntiles;
-    for (int t = 0; t < steps; ++t) {
-      wait_vmcnt<(STAGES - 2) * K::LT>();
-      __syncthreads();
-      issue_into(min(t + STAGES - 1, ntiles - 1), (t + STAGES - 1) % STAGES);
-    }
+    for (int t = 0; t < steps; ++t) sync_tile(t);
     wait_vmcnt<0>();
     return;  // its reads are all past R: nothing to write
   }
@@ -560,8 +566,9 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     // one) runs half a step out of phase: after the barrier of step t it
     // first finishes the epilogue of tile t-1, then issues tile t's MFMAs, so
     // one wavefront's epilogue overlaps the other's MFMAs instead of both
-    // leaving the matrix pipe idle together.  Both halves pass the same ntiles
-    // barriers, and each reads tile t only between barriers t and t+1.
+    // leaving the matrix pipe idle together.  Both halves pass the same
+    // barriers, and each issues its MFMAs on a tile before the barrier that
+    // lets its stage be refilled.
     start_tile(0, accA, sjA);
     for (int t = 1; t < ntiles; ++t) {
       sync_tile(t);
