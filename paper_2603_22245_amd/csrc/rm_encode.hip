@@ -25,9 +25,11 @@ struct Row4 {
 };
 
 // Write one normalised row (4 reals per lane) in the requested precision.
-// Returns the FP8 scale used (1 for FP32/FP16).
-template <int PREC>
-__device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Row4 x) {
+// Returns the FP8 scale used (1 for FP32/FP16).  With HAVE_MAX (FP8 only) the
+// caller passes the row's largest |real| in `maxabs`.
+template <int PREC, bool HAVE_MAX = false>
+__device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Row4 x,
+                                           float maxabs = 0.f) {
   if constexpr (PREC == RM_FP32) {
     float4* dst = reinterpret_cast<float4*>(static_cast<float*>(base) + row * kReal) + lane;
     *dst = make_float4(x.v[0], x.v[1], x.v[2], x.v[3]);
@@ -43,10 +45,13 @@ __device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Ro
     *dst = make_uint2(lo, hi);
     return 1.f;
   } else {
-    float m = fmaxf(fmaxf(fabsf(x.v[0]), fabsf(x.v[1])), fmaxf(fabsf(x.v[2]), fabsf(x.v[3])));
-    m = wave_max(m);
+    float m = maxabs;
+    if constexpr (!HAVE_MAX) {
+      m = fmaxf(fmaxf(fabsf(x.v[0]), fabsf(x.v[1])), fmaxf(fabsf(x.v[2]), fabsf(x.v[3])));
+      m = wave_max_nonneg(m);
+    }
     float s = fp8_pow2_scale(m);
-    float inv = 1.f / s;  // exact: s is a power of two
+    float inv = pow2_reciprocal(s);  // exact: s is a power of two
     uint32_t w = pack_fp8x2(x.v[0] * inv, x.v[1] * inv) |
                  (pack_fp8x2(x.v[2] * inv, x.v[3] * inv) << 16);
     uint32_t* dst = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(base) + row * kReal) + lane;
@@ -58,7 +63,7 @@ __device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Ro
     // second order).
     float2 d01 = unpack_fp8x2(w), d23 = unpack_fp8x2(w >> 16);
     float q2 = wave_sum(d01.x * d01.x + d01.y * d01.y + d23.x * d23.x + d23.y * d23.y);
-    return q2 > 0.f ? 1.f / sqrtf(q2) : s;
+    return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) : s;  // 1 ulp
   }
 }
 
@@ -113,10 +118,17 @@ __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c
                                             void* emb, SideBuf& side, float* scale,
                                             float* norm2) {
   float n2 = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+  // FP8: the largest |real| of the unnormalised row, reduced alongside n2;
+  // scaling by inv > 0 afterwards gives exactly the normalised row's maximum
+  // (the same product of the same element), without a third dependent
+  // reduction
+  float mraw = 0.f;
+  if constexpr (PREC == RM_FP8_E4M3)
+    mraw = wave_max_nonneg(fmaxf(fmaxf(fabsf(c0.x), fabsf(c0.y)), fmaxf(fabsf(c1.x), fabsf(c1.y))));
   bool deg = n2 < kDegenerateRel * (float)N;
   float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
   Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
-  float s = store_row<PREC>(emb, j, lane, x);
+  float s = store_row<PREC, true>(emb, j, lane, x, mraw * inv);
   if (lane == side.n) {
     side.n2 = n2;
     side.sc = s;

@@ -66,15 +66,46 @@ __device__ __forceinline__ float wave_max(float v) {
   return fmaxf(fmaxf(a, b), fmaxf(c, d));
 }
 
+// Maximum of non-negative floats over the 64 lanes, in every lane.  For
+// non-negative floats the order of the bit patterns as unsigned integers is
+// the numeric order, so the integer maximum needs none of the NaN handling of
+// fmaxf.  Every lane must be active.
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  uint32_t u = __float_as_uint(v);
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xf, 0xf, false));
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x4E, 0xf, 0xf, false));
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x141, 0xf, 0xf, false));
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x140, 0xf, 0xf, false));
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)u, 0);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)u, 16);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)u, 32);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)u, 48);
+  return __uint_as_float(max(max(a, b), max(c, d)));
+}
+
 // Power-of-two scale s with maxabs / s <= 448 (the smallest such power), so that
-// dividing by s is exact and nothing saturates.  maxabs == 0 gives 1.
+// dividing by s is exact and nothing saturates.  maxabs == 0 gives 1.  With
+// maxabs = m 2^E (m in [1, 2)) and 448 = 1.75 2^8, the exponent is E - 8 when
+// m <= 1.75 and E - 7 otherwise: read off the float's bits, no rounding.
 __device__ __forceinline__ float fp8_pow2_scale(float maxabs) {
   if (!(maxabs > 0.f)) return 1.f;
-  int e;
-  float f = frexpf(maxabs / kFp8Max, &e);  // maxabs/448 = f * 2^e, f in [0.5, 1)
-  // 2^(e-1) < maxabs/448 <= 2^e unless f == 0.5 exactly (then maxabs/448 = 2^(e-1))
-  if (f == 0.5f) e -= 1;
-  return ldexpf(1.f, e);
+  const uint32_t b = __float_as_uint(maxabs);
+  const int E = (int)(b >> 23) - 127;
+  const int e = E - 8 + ((b & 0x7fffffu) > 0x600000u ? 1 : 0);
+  if (E == -127 || e < -126 || e > 127) {  // subnormal or huge: the general route
+    int x;
+    float f = frexpf(maxabs / kFp8Max, &x);
+    if (f == 0.5f) x -= 1;
+    return ldexpf(1.f, x);
+  }
+  return __uint_as_float((uint32_t)(e + 127) << 23);
+}
+
+// 1 / s for a power of two s: exact.  Normal s with a normal reciprocal (the
+// scales of unit rows, 2^-12 .. 2^-7) by exponent arithmetic, others by division.
+__device__ __forceinline__ float pow2_reciprocal(float s) {
+  const uint32_t ex = __float_as_uint(s) >> 23;
+  return ex >= 2u && ex <= 252u ? __uint_as_float(0x7f000000u - __float_as_uint(s)) : 1.f / s;
 }
 
 // Two floats -> two OCP e4m3 bytes in the low half of the result, round to

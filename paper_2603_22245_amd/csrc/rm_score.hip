@@ -17,13 +17,42 @@ __global__ void clear_state(ScoreLaunch L) {
     if (i < L.g[gi].R) L.g[gi].gthr[i] = 0u;
 }
 
-// Merge the P per-chunk lists of each read into its k_fetch best: repeated
-// wavefront-wide arg-max over the P*KP keys (keys are unique per read).
+// Merge the P per-chunk lists of each read into its k_fetch best (keys are
+// unique per read).  One wavefront per read (all its lanes active): each lane
+// sorts the EMAX keys it holds (descending), then every round takes the
+// wavefront maximum of the lanes' heads and the lane that held it drops its
+// head.  Lane `out` keeps the
+// round-`out` winner, so the k_fetch results are written with one coalesced
+// store each.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// Maximum over the 64 lanes, in every lane: within rows of 16 by DPP (xor 1,
+// xor 2, half-row mirror, row mirror), then the four row maxima.  Every lane
+// must be active.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  v = max64(v, dpp64<0xB1>(v));
+  v = max64(v, dpp64<0x4E>(v));
+  v = max64(v, dpp64<0x141>(v));
+  v = max64(v, dpp64<0x140>(v));
+  return max64(max64(readlane64(v, 0), readlane64(v, 16)), max64(readlane64(v, 32), readlane64(v, 48)));
+}
+
+template <int EMAX>
 __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__ ws, int n_per_read,
                                                     int32_t R, int k_fetch,
                                                     int32_t* __restrict__ cand_idx,
                                                     float* __restrict__ cand_score) {
-  constexpr int EMAX = 16;
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= R) return;
@@ -34,25 +63,28 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__
     int i = e * 64 + lane;
     mine[e] = i < n_per_read ? src[i] : 0;
   }
+  // odd-even transposition sort, descending (EMAX rounds make it complete)
+#pragma unroll
+  for (int p = 0; p < EMAX; ++p)
+#pragma unroll
+    for (int e = p & 1; e + 1 < EMAX; e += 2) {
+      uint64_t x = mine[e], y = mine[e + 1];
+      mine[e] = x > y ? x : y;
+      mine[e + 1] = x > y ? y : x;
+    }
+  uint64_t res = 0;
   for (int out = 0; out < k_fetch; ++out) {
-    uint64_t best = 0;
+    const uint64_t gbest = wave_max_u64(mine[0]);
+    if (gbest != 0 && mine[0] == gbest) {
 #pragma unroll
-    for (int e = 0; e < EMAX; ++e) best = mine[e] > best ? mine[e] : best;
-    uint64_t gbest = best;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      uint64_t o = shfl_xor64(gbest, d);
-      gbest = o > gbest ? o : gbest;
+      for (int e = 0; e + 1 < EMAX; ++e) mine[e] = mine[e + 1];
+      mine[EMAX - 1] = 0;
     }
-    if (gbest != 0 && best == gbest) {
-#pragma unroll
-      for (int e = 0; e < EMAX; ++e)
-        if (mine[e] == gbest) mine[e] = 0;
-    }
-    if (lane == 0) {
-      cand_idx[r * k_fetch + out] = key_index(gbest);
-      cand_score[r * k_fetch + out] = key_score(gbest);
-    }
+    if (lane == out) res = gbest;
+  }
+  if (lane < k_fetch) {
+    cand_idx[r * k_fetch + lane] = key_index(res);
+    cand_score[r * k_fetch + lane] = key_score(res);
   }
 }
 
@@ -176,7 +208,10 @@ hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
   for (int i = 0; i < plan.n_groups; ++i) {
     int n_per_read = plan.g[i].chunks * plan.kp;
     unsigned blocks = (unsigned)(((int64_t)R[i] + 3) / 4);
-    hipLaunchKernelGGL(merge_kernel, dim3(blocks), dim3(256), 0, s,
+    // n_per_read <= 1024 (plan_score keeps the merge within 1024 keys)
+    auto kern = n_per_read <= 256 ? merge_kernel<4> : n_per_read <= 512 ? merge_kernel<8>
+                                                                        : merge_kernel<16>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s,
                        reinterpret_cast<const uint64_t*>(base + plan.g[i].lists_offset), n_per_read,
                        R[i], k_fetch, cand_idx[i], cand_score[i]);
     e = hipGetLastError();
