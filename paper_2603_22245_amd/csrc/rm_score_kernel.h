@@ -417,34 +417,51 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // stages are then refilled with the tiles LEAD ahead.  When pipelined, the
   // epilogue of tile t runs after the MFMAs of tile t+1 have been issued, in
   // the same basic block, so its VALU work fills the MFMA pipeline's latency.
-  auto sync_tile = [&](int t) {
-    if (t % K::GRP) return;
+  // wait for this wavefront's copies of tile t's group and synchronise the
+  // block; false (nothing done) inside a group
+  auto group_barrier = [&](int t) -> bool {
+    if (t % K::GRP) return false;
     wait_vmcnt<(K::LEAD - K::GRP) * K::LT>();
     __syncthreads();
+    return true;
+  };
+  auto issue_group = [&](int t) {
 #pragma unroll
     for (int gi = 0; gi < K::GRP; ++gi)
       issue_into(min(t + K::LEAD + gi, ntiles - 1), (t + K::LEAD + gi) % STAGES);
   };
-  // tile t's MFMAs (and, for FP8, its window scales); valid from the barrier
-  // of tile t's group until the barrier after it
-  auto mfma_step = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
-    const int stage = t % STAGES;
+  auto sync_tile = [&](int t) {
+    if (group_barrier(t)) issue_group(t);
+  };
+  // FP8: squared window scales of tile t (this wavefront's copy)
+  auto read_scales = [&](int t, float (&sj2)[NB]) {
     if constexpr (kFp8) {
+      const int stage = t % STAGES;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         float sc = ring_scale[(stage * WAVES + wave) * K::TW + nb * kBlkW + col];
         sj2[nb] = sc * sc;
       }
     }
+  };
+  auto mfmas = [&](int t, f32x16 (&acc)[NF][NB]) {
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x16{};
-    mfma_tile<PREC, NF, NB, K::AU4>(a, ring + stage * K::TILE + col * K::RB, kx, acc);
+    mfma_tile<PREC, NF, NB, K::AU4>(a, ring + (t % STAGES) * K::TILE + col * K::RB, kx, acc);
+  };
+  // tile t's scales and MFMAs; its data is valid from the barrier of tile t's
+  // group until the barrier after it
+  auto mfma_step = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
+    read_scales(t, sj2);
+    mfmas(t, acc);
   };
   auto start_tile = [&](int t, f32x16 (&acc)[NF][NB], float (&sj2)[NB]) {
-    sync_tile(t);
-    mfma_step(t, acc, sj2);
+    const bool b = group_barrier(t);
+    read_scales(t, sj2);
+    if (b) issue_group(t);
+    mfmas(t, acc);
   };
 
   // re^2 + im^2 - threshold per (read slot, window col), reduced with max;
