@@ -175,7 +175,7 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
 /* Tile shape of the scoring kernel; zero fields select the library default. */
 typedef struct rm_tuning {
   int32_t read_tile;   /* reads per block: 0, 128 or 256 (256 is not available for
-                          FP32, nor for FP16 with k_fetch > 16) */
+                          FP32) */
   int32_t chunk_tiles; /* 64-window units per work item: 0 or >= 1 */
 } rm_tuning;
 

@@ -103,7 +103,7 @@ hipError_t dispatch(int precision, int read_tile, int kp, const ScoreLaunch& L, 
     switch (kp) {
       case 8: return launch_persistent<RM_FP8_E4M3, 2, 8, 32, 4, 2>(L, s);
       case 16: return launch_persistent<RM_FP8_E4M3, 2, 16, 32, 4, 2>(L, s);
-      default: return launch_persistent<RM_FP8_E4M3, 2, 32, 64, 3>(L, s);
+      default: return launch_persistent<RM_FP8_E4M3, 2, 32, 48, 3, 2>(L, s);
     }
   }
   switch (kp) {
@@ -117,7 +117,7 @@ hipError_t dispatch(int precision, int read_tile, int kp, const ScoreLaunch& L, 
 
 bool read_tile_ok(int precision, int kp, int read_tile) {
   if (read_tile == 128) return true;
-  if (read_tile == 256) return precision != RM_FP32 && !(precision == RM_FP16 && kp == 32);
+  if (read_tile == 256) return precision != RM_FP32;
   return false;
 }
 

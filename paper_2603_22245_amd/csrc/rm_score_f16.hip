@@ -11,7 +11,10 @@ hipError_t dispatch_score_f16(int read_tile, int kp, const ScoreLaunch& L, hipSt
   if (read_tile == 256) {
     switch (kp) {
       case 8: return launch_persistent<RM_FP16, 2, 8, 32, 4>(L, s);
-      default: return launch_persistent<RM_FP16, 2, 16, 32, 4>(L, s);
+      case 16: return launch_persistent<RM_FP16, 2, 16, 32, 4>(L, s);
+      // 32-key lists with a 16-slot buffer: 96 KB of lists leave room for
+      // three 16 KB ring stages
+      default: return launch_persistent<RM_FP16, 2, 32, 48, 3>(L, s);
     }
   }
   switch (kp) {

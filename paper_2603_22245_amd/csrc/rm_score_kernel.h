@@ -218,13 +218,16 @@ struct ScoreKernel {
   static constexpr int L = TILE / 1024 / WAVES;         // 1 KB copies per wave per tile
   static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 1 : 0);  // + the window scales
   static constexpr int CB = ENT - KP;                   // buffer slots per read
+  // lanes of the bitonic merge of one read's list and buffer (ENT rounded up
+  // to a power of two; lanes past ENT sort empty keys)
+  static constexpr int SW = ENT <= 32 ? 32 : 64;
   // one block barrier per GRP tiles; copies run LEAD tiles ahead.  FP8
   // tiles carry twice the epilogue work per MFMA cycle of FP16 ones, and
   // halving their barriers pays (2%); for FP16 it costs 2.5%.
   static constexpr int GRP = PREC == RM_FP8_E4M3 && STAGES >= 4 ? 2 : 1;
   static constexpr int LEAD = STAGES - GRP;
   static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
-  static_assert(CB >= 1, "buffer");
+  static_assert(CB >= 1 && ENT <= 64, "buffer");
   static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
   static_assert(NF * NB * 8 <= 64, "pending hits are 64-bit masks of (block, fragment, row pair)");
   static_assert(kPlanW % TW == 0, "chunks hold whole tiles");
@@ -373,22 +376,22 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
 
   // ---- merge a read's buffer into its list (whole wavefront, uniform call)
   auto merge_reads = [&](uint64_t mask) {
-    // ENT == 32: two reads at a time (one per half-wave); ENT == 64: one read.
+    // SW == 32: two reads at a time (one per half-wave); SW == 64: one read.
     while (mask) {
       int r0 = __builtin_ctzll(mask);
       mask &= mask - 1;
       int r1 = -1;
-      if (ENT == 32 && mask) {
+      if (K::SW == 32 && mask) {
         r1 = __builtin_ctzll(mask);
         mask &= mask - 1;
       }
-      int my = (ENT == 32 && lane >= 32) ? r1 : r0;
-      int id = lane & (ENT - 1);
+      int my = (K::SW == 32 && lane >= 32) ? r1 : r0;
+      int id = lane & (K::SW - 1);
       if (my >= 0) {
         int rb = rb0 + my;
         int n = min(cnt[rb], K::CB);
-        uint64_t key = (id < KP + n) ? lst[rb][id] : 0;
-        key = sort_desc<ENT>(key, lane);
+        uint64_t key = (id < KP + n) ? lst[rb][id] : 0;  // KP + n <= ENT
+        key = sort_desc<K::SW>(key, lane);
         if (id < KP) lst[rb][id] = key;
         if (id == KP - 1) {
           float kth = key_score(key);

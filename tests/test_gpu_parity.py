@@ -210,7 +210,8 @@ def _check_candidates(idx, score, F, tol, absolute=False):
 
 
 @pytest.mark.parametrize("precision,k_fetch", [("fp32", 8), ("fp16", 8), ("fp16", 16),
-                                               ("fp8", 16), ("fp8", 32), ("fp32", 32)])
+                                               ("fp16", 32), ("fp8", 16), ("fp8", 32),
+                                               ("fp32", 32)])
 def test_score_topk_and_rescore(precision, k_fetch, plain_data, plain_oracle):
     torch = torch_cuda()
     ref, reads, heads = plain_data
