@@ -387,3 +387,60 @@ def test_one_letter_windows():
         want = np.nonzero(ref == L)[0][:8]
         assert list(tidx[L]) == list(want), L
         assert np.all(np.abs(tsc[L] - 1) < 1e-6)
+
+
+@pytest.mark.parametrize("k_fetch,k", [(1, 1), (5, 3), (9, 9), (20, 8), (27, 16), (32, 32)])
+def test_rescore_given_candidates(k_fetch, k, plain_data, plain_oracle):
+    """The FP32 rescore alone, on candidate pools that the product did not
+    choose: random windows with some invalid entries (-1 and >= W), every
+    pool-size class of the kernel (1 to 5 blocks of 32 one-hot rows), and a
+    few reads shorter than the window (no head: F = 0 for every candidate).
+    The top-k must be the FP64 oracle's order of the same pool, up to ties."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    _, _, _, F = plain_oracle
+    R, W = F.shape
+    index = _build(ref, "fp32")
+    # reads 0..2 cut to 100 letters: heads shorter than N = 150
+    seq, off = reads.seq.copy(), reads.offsets.copy()
+    short = [0, 1, 2]
+    keep = np.ones(seq.size, bool)
+    for r in short:
+        keep[off[r] + 100:off[r + 1]] = False
+    lens = np.diff(off)
+    lens[short] = 100
+    seq = seq[keep]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    rng = np.random.default_rng(7 + k_fetch)
+    pool = np.stack([rng.choice(W, k_fetch, replace=False) for _ in range(R)]).astype(np.int32)
+    bad = rng.random(pool.shape) < 0.1
+    pool[bad] = np.where(rng.random(bad.sum()) < 0.5, -1, W + 5)
+    rb = mapper.upload_reads(index, seq, off)
+    bufs = mapper.map_buffers(index, R, k, k_fetch)
+    bufs.cand_idx.copy_(torch.from_numpy(pool).cuda())
+    mapper.rescore(index, rb, bufs)
+    torch.cuda.synchronize()
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    for r in range(R):
+        valid = [int(j) for j in pool[r] if 0 <= j < W]
+        if r in short:
+            want_ids = sorted(valid)[:k]      # all F = 0: window id ascending
+            got = [int(j) for j in tidx[r] if j >= 0]
+            assert got == want_ids, r
+            assert np.all(tsc[r][:len(want_ids)] == 0.0), r
+            continue
+        n = min(k, len(valid))
+        if n == 0:                            # every candidate invalid: empty list
+            assert np.all(tidx[r] == -1), r
+            continue
+        fv = np.array([F[r, j] for j in valid])
+        order = np.lexsort((np.array(valid), -fv))
+        want_F = fv[order[:n]]
+        got_ids = tidx[r, :n]
+        assert np.all(got_ids >= 0) and np.all(tidx[r, n:] == -1), r
+        assert len(set(got_ids.tolist())) == n and set(got_ids.tolist()) <= set(valid), r
+        got_true = F[r, got_ids]
+        assert np.all(np.abs(got_true - want_F) <= mapping.TIE_TAU), r
+        assert np.max(np.abs(tsc[r, :n] - got_true)) < 2e-6, r
