@@ -138,6 +138,32 @@ def pair_fidelities(ref: np.ndarray, heads: np.ndarray, idx: np.ndarray, N: int,
     return F
 
 
+def refine_pool(coarse_ids, stride: int, radius: int, W1: int) -> np.ndarray:
+    """§3.4, refinement around found locations: the step-1 window starts within
+    `radius` of a found coarse window's start (coarse id j starts at j*stride),
+    clamped to 0 .. W1-1, each start once.  Negative ids are skipped."""
+    starts = set()
+    for j in coarse_ids:
+        j = int(j)
+        if j < 0:
+            continue
+        c = j * stride
+        for s in range(max(0, c - radius), min(W1 - 1, c + radius) + 1):
+            starts.add(s)
+    return np.array(sorted(starts), dtype=np.int64)
+
+
+def refine_topk(F1_row: np.ndarray, coarse_ids, stride: int, radius: int, k: int):
+    """The k best of the refinement pool of one read, ranked like every list
+    here: F1_row holds the read's fidelities with ALL step-1 windows (an oracle
+    F row); returns (starts, F) of length min(k, pool size)."""
+    pool = refine_pool(coarse_ids, stride, radius, F1_row.shape[0])
+    if pool.size == 0:
+        return np.zeros(0, dtype=np.int64), np.zeros(0)
+    i, f = topk_rows(F1_row[pool][None, :], pool[None, :], k)
+    return i[0], f[0]
+
+
 def recall_at_k(got: np.ndarray, ref_idx: np.ndarray, ref_F: np.ndarray, got_true_F: np.ndarray,
                 tau: float = TIE_TAU) -> float:
     """Mean over reads of |{j in got_r : j in oracle top-k or F(j) >= F_(k) - tau}| / k.

@@ -115,3 +115,53 @@ def test_window_count():
     assert mapping.n_windows(10_000_000, 150, 1) == 9_999_851
     assert mapping.n_windows(1000, 100, 7) == 129
     assert mapping.n_windows(99, 100, 1) == 0
+
+
+def test_refine_pool_clamps_and_deduplicates():
+    # coarse stride 4, radius 3, 50 step-1 windows: neighbourhoods of ids 0, 1
+    # overlap, id 12 (start 48) is clamped at the last start 49, -1 is skipped
+    pool = mapping.refine_pool([0, 1, 12, -1], 4, 3, 50)
+    assert list(pool) == [0, 1, 2, 3, 4, 5, 6, 7] + [45, 46, 47, 48, 49]
+    assert list(mapping.refine_pool([5], 4, 0, 50)) == [20]
+    assert mapping.refine_pool([-1, -3], 4, 3, 50).size == 0
+
+
+@pytest.mark.parametrize("stride", [2, 5])
+def test_refine_with_full_coverage_is_the_step1_brute_force(stride):
+    """Every coarse window with radius stride-1 covers every step-1 start, so
+    the refined top-k must be the brute-force top-k over all step-1 windows."""
+    rng = np.random.default_rng(12 + stride)
+    ref = rng.integers(0, 4, 300).astype(np.uint8)
+    ref[200:240] = ref[50:90]
+    N, m, k = 30, 8, 6
+    heads = np.stack([ref[s:s + N] for s in (0, 51, 203)] + [rng.integers(0, 4, N).astype(np.uint8)])
+    W1 = mapping.n_windows(ref.shape[0], N, 1)
+    Wc = mapping.n_windows(ref.shape[0], N, stride)
+    x = np.stack([rope.encode_raw(h, N, m) for h in heads])
+    C = np.stack([rope.encode_raw(ref[s:s + N], N, m) for s in range(W1)])
+    F1 = np.array([[rope.fidelity(x[r], C[s], N) for s in range(W1)] for r in range(len(heads))])
+    for r in range(len(heads)):
+        got_i, got_f = mapping.refine_topk(F1[r], np.arange(Wc), stride, stride - 1, k)
+        bi, bf = _brute_topk(ref, heads[r], N, m, k, 1)
+        assert list(got_i) == bi
+        assert np.allclose(got_f, bf, atol=1e-12)
+
+
+def test_refine_radius_zero_is_the_coarse_scan_and_finds_off_grid_substrings():
+    rng = np.random.default_rng(14)
+    ref = rng.integers(0, 4, 400).astype(np.uint8)
+    N, m, k, stride = 40, 8, 5, 4
+    W1 = mapping.n_windows(ref.shape[0], N, 1)
+    Wc = mapping.n_windows(ref.shape[0], N, stride)
+    head = ref[101:101 + N]               # start 101: not on the stride-4 grid
+    x = rope.encode_raw(head, N, m)
+    F1 = np.array([rope.fidelity(x, rope.encode_raw(ref[s:s + N], N, m), N) for s in range(W1)])
+    # radius 0: the coarse windows' own scores, ids mapped to their starts
+    got_i, got_f = mapping.refine_topk(F1, np.arange(Wc), stride, 0, k)
+    ci, cf = _brute_topk(ref, head, N, m, k, stride)
+    assert list(got_i) == [stride * j for j in ci]
+    assert np.allclose(got_f, cf, atol=1e-12)
+    # around the nearest coarse window (start 100) radius 2 reaches start 101,
+    # an exact copy of the head: self-fidelity 1, ranked first
+    got_i, got_f = mapping.refine_topk(F1, [25], stride, 2, 3)
+    assert got_i[0] == 101 and abs(got_f[0] - 1.0) < 1e-12
