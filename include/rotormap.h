@@ -161,6 +161,37 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                const int32_t* d_cand_idx, int32_t k, int32_t* d_top_idx, float* d_top_score,
                void* stream);
 
+/* ---- refinement around found locations (§3.4) ------------------------------
+ * With a coarse index (stride sigma > 1) the product finds the coarse window
+ * nearest each good location; rm_refine then scores the step-1 windows whose
+ * starts lie within `radius` of each candidate's start (j * sigma - radius ..
+ * j * sigma + radius, clamped to the reference) exactly in FP32 -- the first
+ * by a direct sum of its letters, the rest by the one-letter slide relations
+ * of §3.4 -- and keeps the k best distinct starts over all of a read's
+ * neighbourhoods, ordered by (F desc, start asc).  F = |<x|c>|^2 / (X C)
+ * (§2.4) with each window's norm recomputed.  Plain encoding only. */
+#define RM_REFINE_MAX_RADIUS 7
+
+/* Bytes of the workspace rm_refine needs (256-byte multiple); 0 if invalid. */
+size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius);
+
+/* Refine the coarse candidates d_cand_idx [n_reads][k_fetch] (window ids of
+ * the coarse index `coarse`, e.g. rm_score_topk's output; ids < 0 or >= W are
+ * skipped) into d_top_idx / d_top_score [n_reads][k]: step-1 window starts
+ * (the window ids of a stride-1 index of the same reference) and their FP32
+ * fidelities; missing entries are id -1, score -1.  d_ref is the coarse
+ * index's reference, d_seq / d_off the reads as in rm_encode_reads (a read
+ * shorter than N scores 0 everywhere).  d_ws: caller-owned device workspace of
+ * rm_refine_workspace_bytes.  Asynchronous on `stream`.
+ * Errors: RM_EINVAL (null pointer, invalid index), RM_ESIZE (n_reads < 1,
+ * k_fetch outside 1..RM_MAX_KFETCH, radius outside 0..RM_REFINE_MAX_RADIUS,
+ * k outside 1..min(RM_MAX_KFETCH, k_fetch (2 radius + 1)), ws too small,
+ * 2^31 or more step-1 windows). */
+int rm_refine(const rm_index* coarse, const uint8_t* d_ref, const uint8_t* d_seq,
+              const int64_t* d_off, int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx,
+              int32_t radius, int32_t k, int32_t* d_top_idx, float* d_top_score, void* d_ws,
+              size_t ws_bytes, void* stream);
+
 /* ---- batching: several (index, read batch) groups in one launch -------------
  * Reads of uneven length are mapped by bucketing them by head length (§2.9:
  * strings of different lengths are only compared at one window length), one

@@ -44,6 +44,7 @@ RM_MAX_GROUPS = 8
 RM_LEARNED_PARAMS = 10432
 RM_LEARNED_MAX_LEN = 256
 RM_LEARNED_MAX_PAIRS = 1024
+RM_REFINE_MAX_RADIUS = 7
 
 
 class RotorMapError(RuntimeError):
@@ -75,6 +76,8 @@ def lib():
             "rm_score_workspace_bytes": (SZ, [IP, I32, I32]),
             "rm_score_topk": (ctypes.c_int, [IP, P, P, I32, I32, P, P, P, SZ, P]),
             "rm_rescore": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, P, P, P]),
+            "rm_refine_workspace_bytes": (SZ, [I32, I32, I32]),
+            "rm_refine": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, I32, P, P, P, SZ, P]),
             "rm_bucket_reads": (ctypes.c_int, [P, I32, P, I32, P, P]),
             "rm_score_groups_workspace_bytes": (SZ, [IP, I32, P, I32, ctypes.POINTER(rm_tuning)]),
             "rm_score_topk_groups": (ctypes.c_int, [IP, I32, P, P, P, I32, P, P, P, SZ,
@@ -196,6 +199,18 @@ def rm_rescore(idx: rm_index, d_ref, d_seq, d_off, n_reads: int, k_fetch: int, d
     _check(lib().rm_rescore(ctypes.byref(idx), _ptr(d_ref), _ptr(d_seq), _ptr(d_off), n_reads,
                             k_fetch, _ptr(d_cand_idx), k, _ptr(d_top_idx), _ptr(d_top_score),
                             _stream(stream)), "rm_rescore")
+
+
+def rm_refine_workspace_bytes(n_reads: int, k_fetch: int, radius: int) -> int:
+    return lib().rm_refine_workspace_bytes(n_reads, k_fetch, radius)
+
+
+def rm_refine(coarse: rm_index, d_ref, d_seq, d_off, n_reads: int, k_fetch: int, d_cand_idx,
+              radius: int, k: int, d_top_idx, d_top_score, d_ws, ws_bytes: int,
+              stream=None) -> None:
+    _check(lib().rm_refine(ctypes.byref(coarse), _ptr(d_ref), _ptr(d_seq), _ptr(d_off), n_reads,
+                           k_fetch, _ptr(d_cand_idx), radius, k, _ptr(d_top_idx),
+                           _ptr(d_top_score), _ptr(d_ws), ws_bytes, _stream(stream)), "rm_refine")
 
 
 # ---------------------------------------------------------------- batching

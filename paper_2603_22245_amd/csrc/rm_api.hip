@@ -211,6 +211,33 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
 }
 
+size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius) {
+  if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || radius < 0 ||
+      radius > RM_REFINE_MAX_RADIUS)
+    return 0;
+  return rm::refine_workspace_bytes(n_reads, k_fetch, radius);
+}
+
+int rm_refine(const rm_index* coarse, const uint8_t* d_ref, const uint8_t* d_seq,
+              const int64_t* d_off, int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx,
+              int32_t radius, int32_t k, int32_t* d_top_idx, float* d_top_score, void* d_ws,
+              size_t ws_bytes, void* stream) {
+  int st = index_ok(coarse);
+  if (st != RM_OK) return st;
+  if (d_ref == nullptr || d_seq == nullptr || d_off == nullptr || d_cand_idx == nullptr ||
+      d_top_idx == nullptr || d_top_score == nullptr || d_ws == nullptr)
+    return RM_EINVAL;
+  if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || radius < 0 ||
+      radius > RM_REFINE_MAX_RADIUS || k < 1 || k > RM_MAX_KFETCH ||
+      (int64_t)k > (int64_t)k_fetch * (2 * radius + 1))
+    return RM_ESIZE;
+  if (ws_bytes < rm::refine_workspace_bytes(n_reads, k_fetch, radius)) return RM_ESIZE;
+  if (coarse->ref_len - coarse->p.window_len + 1 > (int64_t)INT32_MAX) return RM_ESIZE;
+  return hip_status(rm::launch_refine(*coarse, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx,
+                                      radius, k, d_top_idx, d_top_score, d_ws,
+                                      static_cast<hipStream_t>(stream)));
+}
+
 int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d_ref_delta,
                        const uint8_t* d_seq, const int64_t* d_off, const float* d_read_delta,
                        int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx, int32_t k,

@@ -136,32 +136,6 @@ __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c
   if (++side.n == 64) side_flush(side, lane, norm2, scale);
 }
 
-// One slide of the window state of this lane's components (k, 2h) and
-// (k, 2h+1): rotate by `rot`, remove `uo` from the outgoing letter's component
-// and add `ui` to the incoming one's.  o and n are wavefront-uniform letter
-// codes; codes above 3 touch nothing.
-__device__ __forceinline__ void slide(float2& c0, float2& c1, float2 rot, int o, int n, int h,
-                                      float2 uo, float2 ui) {
-  c0 = cmul(c0, rot);
-  c1 = cmul(c1, rot);
-  if ((o >> 1) != h) uo = make_float2(0.f, 0.f);
-  if ((n >> 1) != h) ui = make_float2(0.f, 0.f);
-  if (o & 1) {
-    c1.x -= uo.x;
-    c1.y -= uo.y;
-  } else {
-    c0.x -= uo.x;
-    c0.y -= uo.y;
-  }
-  if (n & 1) {
-    c1.x += ui.x;
-    c1.y += ui.y;
-  } else {
-    c0.x += ui.x;
-    c0.y += ui.y;
-  }
-}
-
 template <int PREC>
 __global__ __launch_bounds__(256) void encode_reference_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,

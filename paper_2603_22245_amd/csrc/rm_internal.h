@@ -120,6 +120,86 @@ __device__ __forceinline__ float2 unpack_fp8x2(uint32_t w) {
   return make_float2(v[0], v[1]);
 }
 
+// ---------------------------------------------------------------- shared device code
+
+// One slide of the window state of this lane's components (k, 2h) and
+// (k, 2h+1): rotate by `rot`, remove `uo` from the outgoing letter's component
+// and add `ui` to the incoming one's.  o and n are wavefront-uniform letter
+// codes; codes above 3 touch nothing.
+__device__ __forceinline__ void slide(float2& c0, float2& c1, float2 rot, int o, int n, int h,
+                                      float2 uo, float2 ui) {
+  c0 = cmul(c0, rot);
+  c1 = cmul(c1, rot);
+  if ((o >> 1) != h) uo = make_float2(0.f, 0.f);
+  if ((n >> 1) != h) ui = make_float2(0.f, 0.f);
+  if (o & 1) {
+    c1.x -= uo.x;
+    c1.y -= uo.y;
+  } else {
+    c0.x -= uo.x;
+    c0.y -= uo.y;
+  }
+  if (n & 1) {
+    c1.x += ui.x;
+    c1.y += ui.y;
+  } else {
+    c0.x += ui.x;
+    c0.y += ui.y;
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// Maximum over the 64 lanes, in every lane: within rows of 16 by DPP (xor 1,
+// xor 2, half-row mirror, row mirror), then the four row maxima.  Every lane
+// must be active.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  v = max64(v, dpp64<0xB1>(v));
+  v = max64(v, dpp64<0x4E>(v));
+  v = max64(v, dpp64<0x141>(v));
+  v = max64(v, dpp64<0x140>(v));
+  return max64(max64(readlane64(v, 0), readlane64(v, 16)), max64(readlane64(v, 32), readlane64(v, 48)));
+}
+
+// FP32 direct sum over letters [0, n) for this lane's two components.
+__device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, int n,
+                                             const float2* __restrict__ phase32, int lane,
+                                             float2& a0, float2& a1) {
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+  a0 = make_float2(0.f, 0.f);
+  a1 = make_float2(0.f, 0.f);
+  for (int pb = 0; pb < n; pb += 64) {
+    int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
+    int cnt = min(64, n - pb);
+    // groups of 8 positions with their table loads in flight together
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      float2 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = phase32[(int64_t)min(pb + i0 + u, n - 1) * kM + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int L = __builtin_amdgcn_readlane(mine, i0 + u);
+        a0.x += (L == L0) ? e[u].x : 0.f;
+        a0.y += (L == L0) ? e[u].y : 0.f;
+        a1.x += (L == L1) ? e[u].x : 0.f;
+        a1.y += (L == L1) ? e[u].y : 0.f;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_tables(const rm_params& p, double* phase64, float* phase32, float* step32,
@@ -216,6 +296,12 @@ hipError_t launch_learned_step(float* state, float lr, const uint8_t* a, const i
                                float* loss_out, hipStream_t s);
 hipError_t launch_levenshtein(const uint8_t* a, const int64_t* aoff, const uint8_t* b,
                               const int64_t* boff, int64_t n, int32_t* out, hipStream_t s);
+
+size_t refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius);
+hipError_t launch_refine(const rm_index& coarse, const uint8_t* ref, const uint8_t* seq,
+                         const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                         const int32_t* cand_idx, int32_t radius, int32_t k, int32_t* top_idx,
+                         float* top_score, void* ws, hipStream_t s);
 
 hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                           const int64_t* off, int32_t n_reads, int32_t k_fetch,

@@ -1,0 +1,140 @@
+// Refinement around found locations (§3.4, "Increasing the accuracy").
+//
+// The product scores the windows of a coarse index (starts j*sigma).  Around
+// each candidate window the step-1 windows with starts j*sigma - h .. j*sigma
+// + h are scored exactly in FP32: the first one as a direct sum over its
+// letters with the FP32 phase table (§2.1-§2.2), the next ones by sliding one
+// letter at a time with the relations of §3.4 (every component turns by
+// omega^-f, the outgoing letter's component loses omega^-f, the incoming
+// letter's gains omega^{f (N-1)}).  The squared norm of each window is
+// recomputed from its components rather than skipped, so every fidelity is
+// the full F = |<x|c>|^2 / (X C) of §2.4.  The k best distinct starts over all
+// of a read's neighbourhoods are kept, ordered by (F desc, start asc).
+//
+// Plain encoding only.  Lane layout as in the encoders (lane l owns factor l/2
+// and letters 2(l&1), 2(l&1)+1).
+#include "rm_internal.h"
+
+namespace rm {
+
+namespace {
+
+// One wavefront per (read, candidate), four per block.  Slot i of the
+// candidate's span in `pool` receives the key of start lo + i; slots past the
+// clamped neighbourhood (or of an invalid candidate) receive 0.
+__global__ __launch_bounds__(256) void refine_kernel(
+    const uint8_t* __restrict__ ref, int64_t W1, int N, int cstride, int64_t Wc,
+    const float2* __restrict__ phase32, const float4* __restrict__ step32,
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t R, int k_fetch,
+    const int32_t* __restrict__ cand, int radius, uint64_t* __restrict__ pool) {
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= (int64_t)R * k_fetch) return;  // whole wavefront
+  const int64_t r = item / k_fetch;
+  const int span = 2 * radius + 1;
+  uint64_t* out = pool + item * span;
+  const int32_t j = cand[item];
+  int64_t lo = 0, hi = -1;
+  if (j >= 0 && j < Wc) {
+    const int64_t c = (int64_t)j * cstride;
+    lo = c - radius < 0 ? 0 : c - radius;
+    hi = c + radius > W1 - 1 ? W1 - 1 : c + radius;
+  }
+  if (lane < span && lo + lane > hi) out[lane] = 0;
+  if (hi < lo) return;
+
+  const int64_t start = off[r];
+  float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
+  if (off[r + 1] - start >= N) direct_sum32(seq + start, N, phase32, lane, x0, x1);
+  const float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
+  const bool xdeg = X < kDegenerateRel * (float)N;
+
+  float2 c0, c1;
+  direct_sum32(ref + lo, N, phase32, lane, c0, c1);
+  const int h = lane & 1;
+  const float4 st = step32[lane >> 1];
+  const float2 rot = make_float2(st.x, st.y);  // omega^-f
+  const float2 inc = make_float2(st.z, st.w);  // omega^(f (N-1))
+  uint64_t mine = 0;
+  for (int64_t s = lo; s <= hi; ++s) {
+    const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+    // <x|c> = sum conj(x) c
+    const float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
+    const float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
+    const bool deg = xdeg || C < kDegenerateRel * (float)N;
+    const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+    if (lane == (int)(s - lo))
+      mine = ((uint64_t)(__float_as_uint(F) + 1u) << 32) | (0xffffffffu - (uint32_t)s);
+    // s + N <= hi - 1 + N <= W1 - 2 + N = ref_len - 1
+    if (s < hi) slide(c0, c1, rot, (int)ref[s], (int)ref[s + N], h, rot, inc);
+  }
+  if (lane <= (int)(hi - lo)) out[lane] = mine;
+}
+
+// One wavefront per read over its k_fetch * span keys (at most 8 per lane):
+// k rounds of a wavefront maximum; every key of the winning start leaves the
+// pool (neighbourhoods of nearby candidates overlap, and their FP32 values of
+// a shared start may differ in the last bits).
+__global__ __launch_bounds__(256) void refine_select_kernel(const uint64_t* __restrict__ pool, int n,
+                                                            int32_t R, int k,
+                                                            int32_t* __restrict__ top_idx,
+                                                            float* __restrict__ top_score) {
+  constexpr int EMAX = 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;  // whole wavefront
+  const uint64_t* src = pool + r * n;
+  uint64_t mine[EMAX];
+#pragma unroll
+  for (int e = 0; e < EMAX; ++e) {
+    const int i = e * 64 + lane;
+    mine[e] = i < n ? src[i] : 0;
+  }
+  uint64_t res = 0;
+  for (int out = 0; out < k; ++out) {
+    uint64_t best = 0;
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e) best = mine[e] > best ? mine[e] : best;
+    const uint64_t g = wave_max_u64(best);
+    if (g != 0) {
+#pragma unroll
+      for (int e = 0; e < EMAX; ++e)
+        if ((uint32_t)mine[e] == (uint32_t)g) mine[e] = 0;
+    }
+    if (lane == out) res = g;
+  }
+  if (lane < k) {
+    const uint32_t hi = (uint32_t)(res >> 32);
+    top_idx[r * k + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)res) : -1;
+    top_score[r * k + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
+  }
+}
+
+}  // namespace
+
+size_t refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius) {
+  return ((size_t)n_reads * (size_t)k_fetch * (size_t)(2 * radius + 1) * sizeof(uint64_t) + 255) /
+         256 * 256;
+}
+
+hipError_t launch_refine(const rm_index& coarse, const uint8_t* ref, const uint8_t* seq,
+                         const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                         const int32_t* cand_idx, int32_t radius, int32_t k, int32_t* top_idx,
+                         float* top_score, void* ws, hipStream_t s) {
+  const int N = coarse.p.window_len;
+  const int64_t W1 = coarse.ref_len - N + 1;  // step-1 windows
+  uint64_t* pool = static_cast<uint64_t*>(ws);
+  const int64_t items = (int64_t)n_reads * k_fetch;
+  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, ref, W1, N,
+                     coarse.p.stride, coarse.n_windows,
+                     reinterpret_cast<const float2*>(coarse.d_phase32),
+                     reinterpret_cast<const float4*>(coarse.d_step32), seq, off, n_reads, k_fetch,
+                     cand_idx, radius, pool);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(refine_select_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256),
+                     0, s, pool, k_fetch * (2 * radius + 1), n_reads, k, top_idx, top_score);
+  return hipGetLastError();
+}
+
+}  // namespace rm

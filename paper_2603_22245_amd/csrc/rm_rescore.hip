@@ -27,34 +27,6 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// FP32 direct sum over letters [0, n) for this lane's two components.
-__device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, int n,
-                                             const float2* __restrict__ phase32, int lane,
-                                             float2& a0, float2& a1) {
-  const int k = lane >> 1, h = lane & 1;
-  const int L0 = 2 * h, L1 = 2 * h + 1;
-  a0 = make_float2(0.f, 0.f);
-  a1 = make_float2(0.f, 0.f);
-  for (int pb = 0; pb < n; pb += 64) {
-    int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
-    int cnt = min(64, n - pb);
-    // groups of 8 positions with their table loads in flight together
-    for (int i0 = 0; i0 < cnt; i0 += 8) {
-      float2 e[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) e[u] = phase32[(int64_t)min(pb + i0 + u, n - 1) * kM + k];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int L = __builtin_amdgcn_readlane(mine, i0 + u);
-        a0.x += (L == L0) ? e[u].x : 0.f;
-        a0.y += (L == L0) ? e[u].y : 0.f;
-        a1.x += (L == L1) ? e[u].x : 0.f;
-        a1.y += (L == L1) ? e[u].y : 0.f;
-      }
-    }
-  }
-}
-
 // FP32 direct sum over T tokens of a string whose token offsets are rows
 // drow[p]: token p adds phase32[p] exp(i delta) to component (k, str[p+4]).
 // A range of tokens is summed by advancing str, drow and phase32 together.

@@ -24,30 +24,6 @@ __global__ void clear_state(ScoreLaunch L) {
 // head.  Lane `out` keeps the
 // round-`out` winner, so the k_fetch results are written with one coalesced
 // store each.
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-
-// Maximum over the 64 lanes, in every lane: within rows of 16 by DPP (xor 1,
-// xor 2, half-row mirror, row mirror), then the four row maxima.  Every lane
-// must be active.
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-  v = max64(v, dpp64<0xB1>(v));
-  v = max64(v, dpp64<0x4E>(v));
-  v = max64(v, dpp64<0x141>(v));
-  v = max64(v, dpp64<0x140>(v));
-  return max64(max64(readlane64(v, 0), readlane64(v, 16)), max64(readlane64(v, 32), readlane64(v, 48)));
-}
-
 template <int EMAX>
 __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__ ws, int n_per_read,
                                                     int32_t R, int k_fetch,

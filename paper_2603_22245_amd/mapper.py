@@ -166,6 +166,30 @@ def map_reads(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
     rescore(index, reads, bufs, stream)
 
 
+def refine(index: Index, reads: ReadBatch, bufs: MapBuffers, radius: int, ws=None, stream=None):
+    """Step-1 refinement around the coarse candidates in bufs.cand_idx (§3.4):
+    writes the k best step-1 window starts and their FP32 fidelities into
+    bufs.top_idx / bufs.top_score.  `index` is the coarse (stride > 1) index;
+    `ws` a device workspace of rm_refine_workspace_bytes (allocated if None)."""
+    if index.learned is not None:
+        raise ValueError("refinement is implemented for the plain encoding only")
+    torch = _torch()
+    need = L.rm_refine_workspace_bytes(reads.n, bufs.k_fetch, radius)
+    if ws is None:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=bufs.cand_idx.device)
+    L.rm_refine(index.idx, index.ref, reads.seq, reads.off, reads.n, bufs.k_fetch, bufs.cand_idx,
+                radius, bufs.k, bufs.top_idx, bufs.top_score, ws, ws.numel(), stream)
+    return ws
+
+
+def map_reads_coarse(index: Index, reads: ReadBatch, bufs: MapBuffers, radius: int, ws=None,
+                     stream=None):
+    """encode heads -> product over the coarse windows -> step-1 refinement."""
+    encode_reads(index, reads, stream)
+    score_topk(index, reads, bufs, stream)
+    return refine(index, reads, bufs, radius, ws, stream)
+
+
 # ---------------------------------------------------------------- batching
 
 BUCKETS = (100, 200, 400, 800, 1600, 3200, 6400)

@@ -161,3 +161,32 @@ def test_learned_and_edit_distance_validation():
     assert lib.rm_levenshtein(None, 1, 1, 1, 10, 1, None) == L.RM_EINVAL
     assert lib.rm_levenshtein(1, 1, 1, 1, 0, 1, None) == L.RM_ESIZE
     assert lib.rm_levenshtein(1, 1, 1, 1, (2**31) * 256, 1, None) == L.RM_ESIZE
+
+
+def test_refine_validation():
+    """rm_refine rejects every bad argument before anything is launched."""
+    lib = L.lib()
+    idx = _fake_index()
+    R = ctypes.byref
+    assert L.rm_refine_workspace_bytes(10, 8, 3) == (10 * 8 * 7 * 8 + 255) // 256 * 256
+    assert L.rm_refine_workspace_bytes(10, 8, L.RM_REFINE_MAX_RADIUS + 1) == 0
+    assert L.rm_refine_workspace_bytes(10, 0, 3) == 0
+    assert L.rm_refine_workspace_bytes(0, 8, 3) == 0
+    ws = L.rm_refine_workspace_bytes(10, 8, 3)
+    rf = lambda n, kf, rad, k, nb, i=idx: lib.rm_refine(R(i), 1, 1, 1, n, kf, 1, rad, k, 1, 1, 1,
+                                                       nb, None)
+    assert rf(10, 8, 3, 8, ws - 1) == L.RM_ESIZE                   # workspace too small
+    assert rf(10, 8, -1, 8, ws) == L.RM_ESIZE
+    assert rf(10, 8, L.RM_REFINE_MAX_RADIUS + 1, 8, 1 << 30) == L.RM_ESIZE
+    assert rf(10, 0, 3, 1, ws) == L.RM_ESIZE
+    assert rf(10, L.RM_MAX_KFETCH + 1, 3, 8, 1 << 30) == L.RM_ESIZE
+    assert rf(0, 8, 3, 8, ws) == L.RM_ESIZE
+    assert rf(10, 8, 3, 0, ws) == L.RM_ESIZE
+    assert rf(10, 8, 3, L.RM_MAX_KFETCH + 1, ws) == L.RM_ESIZE     # k above the list limit
+    assert rf(10, 2, 0, 3, ws) == L.RM_ESIZE                       # k > k_fetch (2 radius + 1)
+    assert lib.rm_refine(None, 1, 1, 1, 10, 8, 1, 3, 8, 1, 1, 1, ws, None) == L.RM_EINVAL
+    assert lib.rm_refine(R(idx), 1, 1, 1, 10, 8, 1, 3, 8, 1, 1, None, ws, None) == L.RM_EINVAL
+    assert lib.rm_refine(R(idx), None, 1, 1, 10, 8, 1, 3, 8, 1, 1, 1, ws, None) == L.RM_EINVAL
+    bad = _fake_index()
+    bad.n_windows += 1
+    assert rf(10, 8, 3, 8, ws, bad) == L.RM_EINVAL

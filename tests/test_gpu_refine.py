@@ -1,0 +1,110 @@
+"""GPU parity of the refinement around found locations (§3.4): a coarse index
+(stride sigma), the product over its windows, then rm_refine over the step-1
+windows near each candidate, checked against the FP64 oracle's refinement of
+the same candidates (oracle.mapping.refine_topk) and, for recall, against the
+oracle's top-k over every step-1 window."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mapping
+from tests.gpu_helpers import oracle_heads, oracle_windows, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+PLAIN = synth.WORKLOADS["plain"]
+K = 8
+TOL_F = 5e-6     # FP32 direct sum plus at most 2 radius one-letter slides
+
+
+@pytest.fixture(scope="module")
+def step1_oracle():
+    ref = PLAIN.reference()
+    reads = PLAIN.reads(ref)
+    heads = mapping.read_heads(reads.seq, reads.offsets, 150)
+    Cn, _ = oracle_windows(ref, 150)
+    Xn, _ = oracle_heads(heads, 150)
+    F1 = np.abs(np.conj(Xn) @ Cn.T) ** 2          # [200, 19851], every step-1 window
+    return ref, reads, F1
+
+
+def _check_against_oracle(tidx, tsc, cand, F1, stride, radius, k):
+    exact = 0
+    for r in range(F1.shape[0]):
+        want_i, want_f = mapping.refine_topk(F1[r], cand[r], stride, radius, k)
+        n = want_i.size
+        got = tidx[r, :n]
+        assert np.all(tidx[r, n:] == -1) and np.all(got >= 0), r
+        assert len(set(got.tolist())) == n, r                       # distinct starts
+        pool = set(mapping.refine_pool(cand[r], stride, radius, F1.shape[1]).tolist())
+        assert set(got.tolist()) <= pool, r                           # only refined starts
+        got_true = F1[r, got]
+        assert np.all(np.abs(got_true - want_f) <= mapping.TIE_TAU), r  # same ranking up to ties
+        assert np.max(np.abs(tsc[r, :n] - got_true)) < TOL_F, r
+        exact += int(np.array_equal(got, want_i))
+    return exact / F1.shape[0]
+
+
+@pytest.mark.parametrize("precision,stride,radius", [("fp32", 2, 1), ("fp16", 4, 3),
+                                                     ("fp16", 8, 7), ("fp8", 4, 2)])
+def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, F1 = step1_oracle
+    index = mapper.build_index(ref, precision=precision, stride=stride)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, K, 16)
+    mapper.map_reads_coarse(index, rb, bufs, radius)
+    torch.cuda.synchronize()
+    cand = bufs.cand_idx.cpu().numpy()
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    same = _check_against_oracle(tidx, tsc, cand, F1, stride, radius, K)
+    # recall of the whole coarse path against every step-1 window
+    W1 = F1.shape[1]
+    o_idx, o_F = mapping.topk_rows(F1, np.arange(W1), K)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, np.take_along_axis(F1, tidx, 1))
+    print(f"{precision} stride {stride} radius {radius}: lists identical to the oracle's "
+          f"refinement {same:.3f}; recall@{K} vs all step-1 windows {rec:.4f}")
+    # the method's own recall (coarse candidates that miss a location cannot be
+    # refined into it, and a radius below stride - 1 leaves gaps): measured
+    # 0.9994, 0.983, 0.897 and 0.937, asserted with margin
+    assert rec >= {2: 0.99, 4: 0.97 if radius == 3 else 0.9, 8: 0.85}[stride]
+
+
+def test_refine_edges_and_invalid_candidates(step1_oracle):
+    """Candidates at both ends of the reference (clamped neighbourhoods),
+    overlapping neighbourhoods, invalid ids, a radius of 0 and a read shorter
+    than the window."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, F1 = step1_oracle
+    stride, radius, kf, k = 4, 5, 6, 12
+    index = mapper.build_index(ref, precision="fp16", stride=stride)
+    Wc = index.n_windows
+    R = 40
+    seq, off = reads.seq[:reads.offsets[R]].copy(), reads.offsets[:R + 1].copy()
+    lens = np.diff(off)
+    lens[0] = 90                                   # read 0: no head
+    keep = np.ones(seq.size, bool)
+    keep[off[0] + 90:off[1]] = False
+    seq = seq[keep]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    rng = np.random.default_rng(5)
+    cand = rng.integers(0, Wc, (R, kf)).astype(np.int32)
+    cand[1] = [0, 1, 2, Wc - 1, Wc - 2, -1]        # both ends, overlaps, one invalid
+    cand[2] = [Wc, -5, 3, 3, 4, 10]                # out of range ids, a repeated id
+    rb = mapper.upload_reads(index, seq, off)
+    for rad, k in ((radius, k), (0, kf)):          # k <= k_fetch (2 radius + 1)
+        bufs = mapper.map_buffers(index, R, k, kf)
+        bufs.cand_idx.copy_(torch.from_numpy(cand).cuda())
+        mapper.refine(index, rb, bufs, rad)
+        torch.cuda.synchronize()
+        tidx = bufs.top_idx.cpu().numpy()
+        tsc = bufs.top_score.cpu().numpy()
+        c = np.where((cand >= 0) & (cand < Wc), cand, -1)
+        # read 0 has no head: every refined start scores 0, ordered by start
+        pool0 = mapping.refine_pool(c[0], stride, rad, F1.shape[1])[:k]
+        assert list(tidx[0, :pool0.size]) == list(pool0)
+        assert np.all(tsc[0, :pool0.size] == 0.0)
+        _check_against_oracle(tidx[1:], tsc[1:], c[1:], F1[1:R], stride, rad, k)
