@@ -79,6 +79,11 @@ def parse():
     ap.add_argument("--precision", default=None, help="fp32 | fp16 | fp8 (default: the workload's)")
     ap.add_argument("--reads", type=int, default=None, help="use only the first R reads")
     ap.add_argument("--k-fetch", type=int, default=16)
+    ap.add_argument("--coarse-stride", type=int, default=None,
+                    help="index at this window stride, then step-1 refinement around the "
+                         "candidates (§3.4) in place of the rescore")
+    ap.add_argument("--radius", type=int, default=None,
+                    help="refinement radius in letters (default: coarse stride - 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
     ap.add_argument("--cpu-reads", type=int, default=8)
@@ -145,10 +150,17 @@ def main():
     R = reads.n
     log(f"workload {w.name}: G={ref.shape[0]:,} R={R:,} generated in {time.time() - t0:.1f}s")
 
-    index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision=precision,
+    coarse = args.coarse_stride is not None and args.coarse_stride > 1
+    stride = args.coarse_stride if coarse else w.stride
+    radius = (args.radius if args.radius is not None else stride - 1) if coarse else 0
+    index = mapper.build_index(ref, window_len=w.window_len, stride=stride, precision=precision,
                                reanchor=w.reanchor)
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
     bufs = mapper.map_buffers(index, R, k, k_fetch)
+    refine_ws = None
+    if coarse:
+        refine_ws = torch.empty(L.rm_refine_workspace_bytes(R, k_fetch, radius), dtype=torch.uint8,
+                                device="cuda")
     torch.cuda.synchronize()
     W = index.n_windows
     log(f"index: W={W:,} precision={precision}; buffers ready")
@@ -164,7 +176,10 @@ def main():
         ev[2].record()
         mapper.score_topk(index, rb, bufs)
         ev[3].record()
-        mapper.rescore(index, rb, bufs)
+        if coarse:
+            mapper.refine(index, rb, bufs, radius, refine_ws)
+        else:
+            mapper.rescore(index, rb, bufs)
         ev[4].record()
 
     for i in range(args.warmup):
@@ -191,14 +206,16 @@ def main():
     cand_score = bufs.cand_score.cpu().numpy()
 
     # ---- accuracy against the FP64 oracle
-    acc = accuracy(w, reads, top_idx, top_score, cand_idx, cand_score, k, R)
+    # coarse candidates compared by their start (window id x stride)
+    cand_start = np.where(cand_idx >= 0, cand_idx.astype(np.int64) * stride, -1)
+    acc = accuracy(w, reads, top_idx, top_score, cand_start, cand_score, k, R)
 
     # ---- dominant kernel: the scoring product (+ its small merge), HIP events
     score_s = parts[2] / 1e3
     achieved = R * W * FLOPS_PER_SCORE / score_s / 1e12
     peak = PEAK_TFLOPS[precision]
     enc_bytes = W * (256 * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
-    traffic = measured_traffic(precision) if R == w.n_reads else None
+    traffic = measured_traffic(precision) if R == w.n_reads and not coarse else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "score_topk_kernel (+merge_kernel)",
@@ -210,14 +227,15 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp16": "f16", "fp8": "fp8e4m3"}[precision],
         "data": "synthetic",
-        "config": {"workload": describe(w, precision, k, k_fetch, R), "reads": R, "windows": W,
-                   "window_len": w.window_len, "n_freq": w.n_freq, "stride": w.stride,
-                   "k": k, "k_fetch": k_fetch, "precision": precision},
+        "config": {"workload": describe(w, precision, k, k_fetch, R, stride, radius), "reads": R,
+                   "windows": W, "window_len": w.window_len, "n_freq": w.n_freq,
+                   "stride": stride, "k": k, "k_fetch": k_fetch, "precision": precision},
         "window_scores_per_s": float(f"{R * W / score_s:.4g}"),
         # the same step on an index built beforehand (reads -> product -> rescore)
         "reads_per_s_prebuilt_index": round(R / ((parts[1] + parts[2] + parts[3]) / 1e3), 1),
         "breakdown_ms": {"encode_reference": round(parts[0], 3), "encode_reads": round(parts[1], 3),
-                         "score_topk": round(parts[2], 3), "rescore": round(parts[3], 3)},
+                         "score_topk": round(parts[2], 3),
+                         ("refine" if coarse else "rescore"): round(parts[3], 3)},
         "encoder_gbs": round(enc_bytes / (parts[0] / 1e3) / 1e9, 1),
         "accuracy": acc,
         "roofline": roofline,
@@ -225,7 +243,7 @@ def main():
     del index, rb, bufs
     torch.cuda.empty_cache()
 
-    if not args.no_fp32 and precision != "fp32":
+    if not args.no_fp32 and precision != "fp32" and not coarse:
         out["fp32_path"] = fp32_path(w, ref, reads, k, k_fetch, value)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, ref, reads, W, args.cpu_reads, args.cpu_windows)
@@ -531,10 +549,15 @@ def batching_accuracy(ref, reads, bm, ids, sc, k):
     return res
 
 
-def describe(w, precision, k, k_fetch, R):
-    return (f"{w.name}: {w.G / 1e6:g} Mbp synthetic reference ({int(w.gc * 100)}% GC, "
+def describe(w, precision, k, k_fetch, R, stride=None, radius=0):
+    stride = w.stride if stride is None else stride
+    head = (f"{w.name}: {w.G / 1e6:g} Mbp synthetic reference ({int(w.gc * 100)}% GC, "
             f"{int(w.repeat_frac * 100)}% repeats), {R:,} reads of {w.read_len} bp, N={w.window_len}, "
-            f"m={w.n_freq}, stride {w.stride}, {precision} index, top-{k} of {k_fetch} rescored in FP32")
+            f"m={w.n_freq}, stride {stride}, {precision} index, ")
+    if stride > w.stride:
+        return head + (f"top-{k_fetch} coarse windows refined in FP32 over the step-1 windows "
+                       f"within {radius} letters, top-{k} kept")
+    return head + f"top-{k} of {k_fetch} rescored in FP32"
 
 
 def accuracy(w, reads, top_idx, top_score, cand_idx, cand_score, k, R, gold_name=None):
