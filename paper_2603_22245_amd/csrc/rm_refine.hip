@@ -12,63 +12,84 @@
 // of a read's neighbourhoods are kept, ordered by (F desc, start asc).
 //
 // Plain encoding only.  Lane layout as in the encoders (lane l owns factor l/2
-// and letters 2(l&1), 2(l&1)+1).
+// and letters 2(l&1), 2(l&1)+1).  The head's encoding is summed once per read
+// in the same order as the rescore's (quarters added in a fixed order).
 #include "rm_internal.h"
 
 namespace rm {
 
 namespace {
 
-// One wavefront per (read, candidate), four per block.  Slot i of the
-// candidate's span in `pool` receives the key of start lo + i; slots past the
-// clamped neighbourhood (or of an invalid candidate) receive 0.
+// One block of four wavefronts per read: the read head is summed once, a
+// quarter per wavefront (the quarters added in a fixed order), then wavefront
+// w refines candidates w, w + 4, ...  Slot i of a candidate's span in `pool`
+// receives the key of start lo + i; slots past the clamped neighbourhood (or
+// of an invalid candidate) receive 0.
 __global__ __launch_bounds__(256) void refine_kernel(
     const uint8_t* __restrict__ ref, int64_t W1, int N, int cstride, int64_t Wc,
     const float2* __restrict__ phase32, const float4* __restrict__ step32,
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t R, int k_fetch,
     const int32_t* __restrict__ cand, int radius, uint64_t* __restrict__ pool) {
+  __shared__ float4 part[4][64];
   const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= (int64_t)R * k_fetch) return;  // whole wavefront
-  const int64_t r = item / k_fetch;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r = blockIdx.x;
   const int span = 2 * radius + 1;
-  uint64_t* out = pool + item * span;
-  const int32_t j = cand[item];
-  int64_t lo = 0, hi = -1;
-  if (j >= 0 && j < Wc) {
-    const int64_t c = (int64_t)j * cstride;
-    lo = c - radius < 0 ? 0 : c - radius;
-    hi = c + radius > W1 - 1 ? W1 - 1 : c + radius;
-  }
-  if (lane < span && lo + lane > hi) out[lane] = 0;
-  if (hi < lo) return;
 
+  // ---- read head, a quarter of its letters per wavefront
   const int64_t start = off[r];
   float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
-  if (off[r + 1] - start >= N) direct_sum32(seq + start, N, phase32, lane, x0, x1);
+  if (off[r + 1] - start >= N) {
+    const int q0 = wave * N / 4, q1 = (wave + 1) * N / 4;
+    direct_sum32(seq + start + q0, q1 - q0, phase32 + (int64_t)q0 * kM, lane, x0, x1);
+  }
+  part[wave][lane] = make_float4(x0.x, x0.y, x1.x, x1.y);
+  __syncthreads();
+  {
+    float4 v = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      const float4 u = part[w][lane];
+      v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+    }
+    x0 = make_float2(v.x, v.y);
+    x1 = make_float2(v.z, v.w);
+  }
   const float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
   const bool xdeg = X < kDegenerateRel * (float)N;
-
-  float2 c0, c1;
-  direct_sum32(ref + lo, N, phase32, lane, c0, c1);
   const int h = lane & 1;
   const float4 st = step32[lane >> 1];
   const float2 rot = make_float2(st.x, st.y);  // omega^-f
   const float2 inc = make_float2(st.z, st.w);  // omega^(f (N-1))
-  uint64_t mine = 0;
-  for (int64_t s = lo; s <= hi; ++s) {
-    const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
-    // <x|c> = sum conj(x) c
-    const float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
-    const float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
-    const bool deg = xdeg || C < kDegenerateRel * (float)N;
-    const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
-    if (lane == (int)(s - lo))
-      mine = ((uint64_t)(__float_as_uint(F) + 1u) << 32) | (0xffffffffu - (uint32_t)s);
-    // s + N <= hi - 1 + N <= W1 - 2 + N = ref_len - 1
-    if (s < hi) slide(c0, c1, rot, (int)ref[s], (int)ref[s + N], h, rot, inc);
+
+  for (int e = wave; e < k_fetch; e += 4) {
+    uint64_t* out = pool + (r * k_fetch + e) * span;
+    const int32_t j = cand[r * k_fetch + e];
+    int64_t lo = 0, hi = -1;
+    if (j >= 0 && j < Wc) {
+      const int64_t c = (int64_t)j * cstride;
+      lo = c - radius < 0 ? 0 : c - radius;
+      hi = c + radius > W1 - 1 ? W1 - 1 : c + radius;
+    }
+    if (lane < span && lo + lane > hi) out[lane] = 0;
+    if (hi < lo) continue;  // uniform
+    float2 c0, c1;
+    direct_sum32(ref + lo, N, phase32, lane, c0, c1);
+    uint64_t mine = 0;
+    for (int64_t s = lo; s <= hi; ++s) {
+      const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+      // <x|c> = sum conj(x) c
+      const float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
+      const float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
+      const bool deg = xdeg || C < kDegenerateRel * (float)N;
+      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+      if (lane == (int)(s - lo))
+        mine = ((uint64_t)(__float_as_uint(F) + 1u) << 32) | (0xffffffffu - (uint32_t)s);
+      // s + N <= hi - 1 + N <= W1 - 2 + N = ref_len - 1
+      if (s < hi) slide(c0, c1, rot, (int)ref[s], (int)ref[s + N], h, rot, inc);
+    }
+    if (lane <= (int)(hi - lo)) out[lane] = mine;
   }
-  if (lane <= (int)(hi - lo)) out[lane] = mine;
 }
 
 // One wavefront per read over its k_fetch * span keys (at most 8 per lane):
@@ -124,8 +145,7 @@ hipError_t launch_refine(const rm_index& coarse, const uint8_t* ref, const uint8
   const int N = coarse.p.window_len;
   const int64_t W1 = coarse.ref_len - N + 1;  // step-1 windows
   uint64_t* pool = static_cast<uint64_t*>(ws);
-  const int64_t items = (int64_t)n_reads * k_fetch;
-  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, ref, W1, N,
+  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)n_reads), dim3(256), 0, s, ref, W1, N,
                      coarse.p.stride, coarse.n_windows,
                      reinterpret_cast<const float2*>(coarse.d_phase32),
                      reinterpret_cast<const float4*>(coarse.d_step32), seq, off, n_reads, k_fetch,
