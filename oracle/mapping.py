@@ -164,6 +164,28 @@ def refine_topk(F1_row: np.ndarray, coarse_ids, stride: int, radius: int, k: int
     return i[0], f[0]
 
 
+def reverse_complement(seq: np.ndarray) -> np.ndarray:
+    """The other strand read 5'->3': reverse the letters and complement them
+    (A=0 <-> T=3, C=1 <-> G=2, i.e. L -> 3 - L)."""
+    return (3 - seq[::-1]).astype(np.uint8)
+
+
+def merge_strands(fwd_idx, fwd_F, rev_idx, rev_F, k: int, min_fidelity: float = 0.0):
+    """Both mapping directions (the paper maps reads in both directions): the k
+    best of a read's forward-strand list and its reverse-complement list, each
+    already ranked (F desc, id asc), ranked the same way with the forward entry
+    first on a full tie; entries with F below min_fidelity are dropped (the
+    threshold regime: only locations whose fidelity passes the threshold are
+    reported; none passing = unmapped).  Returns (ids, F, strands), strand 0 =
+    forward, 1 = reverse; negative ids are skipped."""
+    entries = [(-float(f), int(j), 0) for j, f in zip(fwd_idx, fwd_F) if j >= 0]
+    entries += [(-float(f), int(j), 1) for j, f in zip(rev_idx, rev_F) if j >= 0]
+    entries = sorted(e for e in entries if -e[0] >= min_fidelity)[:k]
+    return (np.array([e[1] for e in entries], dtype=np.int64),
+            np.array([-e[0] for e in entries]),
+            np.array([e[2] for e in entries], dtype=np.int64))
+
+
 def recall_at_k(got: np.ndarray, ref_idx: np.ndarray, ref_F: np.ndarray, got_true_F: np.ndarray,
                 tau: float = TIE_TAU) -> float:
     """Mean over reads of |{j in got_r : j in oracle top-k or F(j) >= F_(k) - tau}| / k.

@@ -165,3 +165,40 @@ def test_refine_radius_zero_is_the_coarse_scan_and_finds_off_grid_substrings():
     # an exact copy of the head: self-fidelity 1, ranked first
     got_i, got_f = mapping.refine_topk(F1, [25], stride, 2, 3)
     assert got_i[0] == 101 and abs(got_f[0] - 1.0) < 1e-12
+
+
+def test_reverse_complement_definition():
+    s = np.array([0, 0, 1, 2, 3, 1], dtype=np.uint8)          # AACGTC
+    assert list(mapping.reverse_complement(s)) == [2, 0, 1, 2, 3, 3]   # GACGTT
+    rng = np.random.default_rng(15)
+    x = rng.integers(0, 4, 200).astype(np.uint8)
+    assert np.array_equal(mapping.reverse_complement(mapping.reverse_complement(x)), x)
+
+
+def test_reverse_strand_read_maps_back_with_fidelity_one():
+    """A read taken from the other strand (the reverse complement of a
+    reference substring) is found by mapping its reverse complement: F = 1 at
+    the substring's start on strand 1, while its forward head scores low."""
+    rng = np.random.default_rng(16)
+    ref = rng.integers(0, 4, 600).astype(np.uint8)
+    N, m, k = 40, 8, 4
+    read = mapping.reverse_complement(ref[250:250 + 60])      # other strand, longer than N
+    fwd_head = read[:N]
+    rev_head = mapping.reverse_complement(read)[:N]          # = ref[250:290]
+    fi, ff = mapping.map_reads(ref, fwd_head[None], N, m, k)
+    ri, rf = mapping.map_reads(ref, rev_head[None], N, m, k)
+    ids, F, strands = mapping.merge_strands(fi[0], ff[0], ri[0], rf[0], k)
+    assert ids[0] == 250 and strands[0] == 1 and abs(F[0] - 1.0) < 1e-12
+    assert ff[0, 0] < 0.5
+
+
+def test_merge_strands_order_ties_and_threshold():
+    ids, F, st = mapping.merge_strands([5, 9, -1], [0.9, 0.4, 0.0], [7, 5], [0.9, 0.6], 4)
+    # equal F: lower id first, then forward before reverse on the same id
+    assert list(ids) == [5, 7, 5, 9] and list(st) == [0, 1, 1, 0]
+    ids, F, st = mapping.merge_strands([5, 9], [0.9, 0.4], [5, 2], [0.9, 0.3], 3)
+    assert list(ids) == [5, 5, 9] and list(st) == [0, 1, 0]
+    ids, F, st = mapping.merge_strands([5, 9], [0.9, 0.4], [7, 2], [0.6, 0.3], 4, min_fidelity=0.5)
+    assert list(ids) == [5, 7] and list(st) == [0, 1]
+    ids, F, st = mapping.merge_strands([5], [0.2], [7], [0.1], 4, min_fidelity=0.5)
+    assert ids.size == 0                                      # unmapped
