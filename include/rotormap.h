@@ -161,6 +161,38 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                const int32_t* d_cand_idx, int32_t k, int32_t* d_top_idx, float* d_top_score,
                void* stream);
 
+/* ---- both strands and the threshold regime ---------------------------------
+ * The paper maps reads in both directions: a read from the other strand
+ * matches the reference after reverse complementing it.  Map the reads and
+ * their reverse complements as one batch (2 n_reads heads), then combine each
+ * read's two lists.  §3.1 takes the fidelities above a threshold as the
+ * matching locations, and §3.5 describes the regime that reports every
+ * location passing it: rm_merge_strands drops entries below min_fidelity, and
+ * a read with none left is unmapped. */
+
+/* Reverse complement of every read: d_out[d_off[r] .. d_off[r+1]) receives
+ * the letters of read r reversed, codes 0..3 (A, C, G, T) mapped to 3 - L
+ * (other codes copied).  d_out has the layout of d_seq (n_letters =
+ * d_off[n_reads] - d_off[0] letters from offset d_off[0]) and must not
+ * overlap it.  Errors: RM_EINVAL (null pointer, d_out == d_seq), RM_ESIZE
+ * (n_reads < 1, n_letters < 1). */
+int rm_reverse_complement(const uint8_t* d_seq, const int64_t* d_off, int32_t n_reads,
+                          int64_t n_letters, uint8_t* d_out, void* stream);
+
+/* Combine, per read, the forward list (d_fwd_idx / d_fwd_score [n_reads][k])
+ * and the reverse-complement list (d_rev_*, same shape), each ranked by
+ * (F desc, window id asc) as rm_rescore returns them, into the k best ranked
+ * the same way, the forward entry first on a full tie; entries with id < 0 or
+ * F < min_fidelity are dropped.  Outputs [n_reads][k]: window ids, F, strand
+ * (int8: 0 forward, 1 reverse complement; -1 with id -1 and F -1 past the
+ * kept entries) and d_n_found [n_reads], the number kept (0 = unmapped).
+ * Errors: RM_EINVAL (null pointer), RM_ESIZE (n_reads < 1, k outside
+ * 1..RM_MAX_KFETCH). */
+int rm_merge_strands(const int32_t* d_fwd_idx, const float* d_fwd_score, const int32_t* d_rev_idx,
+                     const float* d_rev_score, int32_t n_reads, int32_t k, float min_fidelity,
+                     int32_t* d_top_idx, float* d_top_score, int8_t* d_top_strand,
+                     int32_t* d_n_found, void* stream);
+
 /* ---- refinement around found locations (§3.4) ------------------------------
  * With a coarse index (stride sigma > 1) the product finds the coarse window
  * nearest each good location; rm_refine then scores the step-1 windows whose

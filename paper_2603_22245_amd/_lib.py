@@ -77,6 +77,9 @@ def lib():
             "rm_score_topk": (ctypes.c_int, [IP, P, P, I32, I32, P, P, P, SZ, P]),
             "rm_rescore": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, P, P, P]),
             "rm_refine_workspace_bytes": (SZ, [I32, I32, I32]),
+            "rm_reverse_complement": (ctypes.c_int, [P, P, I32, I64, P, P]),
+            "rm_merge_strands": (ctypes.c_int, [P, P, P, P, I32, I32, ctypes.c_float, P, P, P, P,
+                                                P]),
             "rm_refine": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, I32, P, P, P, SZ, P]),
             "rm_bucket_reads": (ctypes.c_int, [P, I32, P, I32, P, P]),
             "rm_score_groups_workspace_bytes": (SZ, [IP, I32, P, I32, ctypes.POINTER(rm_tuning)]),
@@ -199,6 +202,20 @@ def rm_rescore(idx: rm_index, d_ref, d_seq, d_off, n_reads: int, k_fetch: int, d
     _check(lib().rm_rescore(ctypes.byref(idx), _ptr(d_ref), _ptr(d_seq), _ptr(d_off), n_reads,
                             k_fetch, _ptr(d_cand_idx), k, _ptr(d_top_idx), _ptr(d_top_score),
                             _stream(stream)), "rm_rescore")
+
+
+def rm_reverse_complement(d_seq, d_off, n_reads: int, n_letters: int, d_out, stream=None) -> None:
+    _check(lib().rm_reverse_complement(_ptr(d_seq), _ptr(d_off), n_reads, n_letters, _ptr(d_out),
+                                       _stream(stream)), "rm_reverse_complement")
+
+
+def rm_merge_strands(d_fwd_idx, d_fwd_score, d_rev_idx, d_rev_score, n_reads: int, k: int,
+                     min_fidelity: float, d_top_idx, d_top_score, d_top_strand, d_n_found,
+                     stream=None) -> None:
+    _check(lib().rm_merge_strands(_ptr(d_fwd_idx), _ptr(d_fwd_score), _ptr(d_rev_idx),
+                                  _ptr(d_rev_score), n_reads, k, min_fidelity, _ptr(d_top_idx),
+                                  _ptr(d_top_score), _ptr(d_top_strand), _ptr(d_n_found),
+                                  _stream(stream)), "rm_merge_strands")
 
 
 def rm_refine_workspace_bytes(n_reads: int, k_fetch: int, radius: int) -> int:

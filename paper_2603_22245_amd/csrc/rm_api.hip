@@ -211,6 +211,29 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
 }
 
+int rm_reverse_complement(const uint8_t* d_seq, const int64_t* d_off, int32_t n_reads,
+                          int64_t n_letters, uint8_t* d_out, void* stream) {
+  if (d_seq == nullptr || d_off == nullptr || d_out == nullptr || d_out == d_seq) return RM_EINVAL;
+  if (n_reads < 1 || n_letters < 1) return RM_ESIZE;
+  return hip_status(rm::launch_reverse_complement(d_seq, d_off, n_reads, n_letters, d_out,
+                                                  static_cast<hipStream_t>(stream)));
+}
+
+int rm_merge_strands(const int32_t* d_fwd_idx, const float* d_fwd_score, const int32_t* d_rev_idx,
+                     const float* d_rev_score, int32_t n_reads, int32_t k, float min_fidelity,
+                     int32_t* d_top_idx, float* d_top_score, int8_t* d_top_strand,
+                     int32_t* d_n_found, void* stream) {
+  if (d_fwd_idx == nullptr || d_fwd_score == nullptr || d_rev_idx == nullptr ||
+      d_rev_score == nullptr || d_top_idx == nullptr || d_top_score == nullptr ||
+      d_top_strand == nullptr || d_n_found == nullptr)
+    return RM_EINVAL;
+  if (n_reads < 1 || k < 1 || k > RM_MAX_KFETCH) return RM_ESIZE;
+  return hip_status(rm::launch_merge_strands(d_fwd_idx, d_fwd_score, d_rev_idx, d_rev_score,
+                                             n_reads, k, min_fidelity, d_top_idx, d_top_score,
+                                             d_top_strand, d_n_found,
+                                             static_cast<hipStream_t>(stream)));
+}
+
 size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius) {
   if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || radius < 0 ||
       radius > RM_REFINE_MAX_RADIUS)

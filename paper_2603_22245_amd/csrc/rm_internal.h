@@ -297,6 +297,13 @@ hipError_t launch_learned_step(float* state, float lr, const uint8_t* a, const i
 hipError_t launch_levenshtein(const uint8_t* a, const int64_t* aoff, const uint8_t* b,
                               const int64_t* boff, int64_t n, int32_t* out, hipStream_t s);
 
+hipError_t launch_reverse_complement(const uint8_t* seq, const int64_t* off, int32_t n_reads,
+                                     int64_t n_letters, uint8_t* out, hipStream_t s);
+hipError_t launch_merge_strands(const int32_t* fi, const float* ff, const int32_t* ri,
+                                const float* rf, int32_t n_reads, int32_t k, float min_fidelity,
+                                int32_t* top_idx, float* top_score, int8_t* top_strand,
+                                int32_t* n_found, hipStream_t s);
+
 size_t refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius);
 hipError_t launch_refine(const rm_index& coarse, const uint8_t* ref, const uint8_t* seq,
                          const int64_t* off, int32_t n_reads, int32_t k_fetch,

@@ -166,6 +166,53 @@ def map_reads(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
     rescore(index, reads, bufs, stream)
 
 
+@dataclasses.dataclass
+class StrandResult:
+    top_idx: object      # [R][k] window ids
+    top_score: object    # [R][k] FP32 fidelities
+    top_strand: object   # [R][k] int8: 0 forward, 1 reverse complement, -1 empty
+    n_found: object      # [R] entries kept (0 = unmapped)
+
+
+def upload_reads_both_strands(index: Index, seq: np.ndarray, offsets: np.ndarray,
+                              device="cuda", stream=None) -> ReadBatch:
+    """A batch of 2R reads: the R reads, then their reverse complements
+    (computed on the GPU by rm_reverse_complement) with the same lengths."""
+    torch = _torch()
+    n = int(offsets.shape[0] - 1)
+    nl = int(offsets[-1] - offsets[0])
+    off = np.ascontiguousarray(offsets, dtype=np.int64) - int(offsets[0])
+    d_seq = torch.empty(2 * nl, dtype=torch.uint8, device=device)
+    d_seq[:nl].copy_(torch.from_numpy(np.ascontiguousarray(seq[offsets[0]:offsets[-1]],
+                                                           dtype=np.uint8)))
+    off2 = np.concatenate([off, off[1:] + nl])
+    d_off = torch.from_numpy(off2).to(device)
+    L.rm_reverse_complement(d_seq[:nl], d_off[:n + 1], n, nl, d_seq[nl:], stream)
+    emb = torch.empty(L.rm_read_emb_bytes(2 * n, index.params), dtype=torch.uint8, device=device)
+    scale = torch.empty(2 * n, dtype=torch.float32, device=device)
+    delta = None if index.learned is None else _delta_buffer(int(d_seq.numel()), device)
+    return ReadBatch(2 * n, d_seq, d_off, emb, scale, delta)
+
+
+def map_reads_both_strands(index: Index, reads2: ReadBatch, bufs2: MapBuffers,
+                           min_fidelity: float = 0.0, stream=None) -> StrandResult:
+    """Map the 2R-read batch of upload_reads_both_strands (bufs2 sized for 2R
+    reads) and combine each read's forward and reverse-complement lists with
+    rm_merge_strands, keeping entries with F >= min_fidelity."""
+    torch = _torch()
+    map_reads(index, reads2, bufs2, stream)
+    n, k = reads2.n // 2, bufs2.k
+    dev = bufs2.top_idx.device
+    out = StrandResult(torch.empty((n, k), dtype=torch.int32, device=dev),
+                       torch.empty((n, k), dtype=torch.float32, device=dev),
+                       torch.empty((n, k), dtype=torch.int8, device=dev),
+                       torch.empty(n, dtype=torch.int32, device=dev))
+    L.rm_merge_strands(bufs2.top_idx[:n], bufs2.top_score[:n], bufs2.top_idx[n:],
+                       bufs2.top_score[n:], n, k, min_fidelity, out.top_idx, out.top_score,
+                       out.top_strand, out.n_found, stream)
+    return out
+
+
 def refine(index: Index, reads: ReadBatch, bufs: MapBuffers, radius: int, ws=None, stream=None):
     """Step-1 refinement around the coarse candidates in bufs.cand_idx (§3.4):
     writes the k best step-1 window starts and their FP32 fidelities into

@@ -190,3 +190,21 @@ def test_refine_validation():
     bad = _fake_index()
     bad.n_windows += 1
     assert rf(10, 8, 3, 8, ws, bad) == L.RM_EINVAL
+
+
+def test_strand_calls_validation():
+    lib = L.lib()
+    assert lib.rm_reverse_complement(None, 1, 10, 100, 2, None) == L.RM_EINVAL
+    assert lib.rm_reverse_complement(1, None, 10, 100, 2, None) == L.RM_EINVAL
+    assert lib.rm_reverse_complement(1, 1, 10, 100, None, None) == L.RM_EINVAL
+    assert lib.rm_reverse_complement(1, 1, 10, 100, 1, None) == L.RM_EINVAL    # in place
+    assert lib.rm_reverse_complement(1, 1, 0, 100, 2, None) == L.RM_ESIZE
+    assert lib.rm_reverse_complement(1, 1, 10, 0, 2, None) == L.RM_ESIZE
+    ms = lambda n, k, *p: lib.rm_merge_strands(*(p or (1,) * 4), n, k, ctypes.c_float(0.0),
+                                               1, 1, 1, 1, None)
+    assert ms(10, 0) == L.RM_ESIZE
+    assert ms(10, L.RM_MAX_KFETCH + 1) == L.RM_ESIZE
+    assert ms(0, 8) == L.RM_ESIZE
+    assert ms(10, 8, 1, 1, None, 1) == L.RM_EINVAL
+    assert lib.rm_merge_strands(1, 1, 1, 1, 10, 8, ctypes.c_float(0.0), 1, 1, 1, None,
+                                None) == L.RM_EINVAL
