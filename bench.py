@@ -84,6 +84,8 @@ def parse():
                          "candidates (§3.4) in place of the rescore")
     ap.add_argument("--radius", type=int, default=None,
                     help="refinement radius in letters (default: coarse stride - 1)")
+    ap.add_argument("--corr-pairs", type=int, default=100_000,
+                    help="correlation workload: pairs over all mutation rates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
     ap.add_argument("--cpu-reads", type=int, default=8)
@@ -135,6 +137,10 @@ def main():
         return
     if args.workload == "learned":
         out = bench_learned(args)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "correlation":
+        out = bench_correlation(args)
         print(json.dumps(out), flush=True)
         return
     w = synth.WORKLOADS[args.workload]
@@ -341,6 +347,85 @@ def bench_batching(args):
 def _spearman(x, y) -> float:
     from scipy.stats import spearmanr
     return float(spearmanr(x, y).correlation)
+
+
+def correlation_curve(err_levels, fid_by_level):
+    """§2.4, the fitting curve: the points (E_fid(err), err), one per mutation
+    rate, connected (piecewise linear in E_fid).  Returns (E, err) sorted by E
+    ascending, ready for np.interp."""
+    E = np.array([float(np.mean(f)) for f in fid_by_level])
+    e = np.asarray(err_levels, dtype=np.float64)
+    o = np.argsort(E, kind="stable")
+    return E[o], e[o]
+
+
+def prediction_rmse(err_levels, fid_by_level, curve):
+    """§2.4: per mutation rate, the root mean square of the vertical distances
+    between the points (fid, err) of its pairs and the fitting curve, i.e. the
+    error of predicting the rate from an observed fidelity."""
+    E, e = curve
+    return [float(np.sqrt(np.mean((np.interp(np.asarray(f), E, e) - err) ** 2)))
+            for err, f in zip(err_levels, fid_by_level)]
+
+
+def bench_correlation(args):
+    """The correlation protocol of §2.4 on the GPU: random 150 bp strings and
+    companions mutated at rates err evenly spread over (0, 0.5) (edits split
+    evenly between substitutions, insertions and deletions), their fidelities
+    under the plain and the learned encoding, the fitting curve and the RMSE of
+    predicting err from the fidelity."""
+    import torch
+    import synth
+    from paper_2603_22245_amd import learned as LM
+    N, levels = 150, 25
+    per = max(1, args.corr_pairs // levels)
+    err_levels = (np.arange(levels) + 0.5) * 0.5 / levels
+    edits = np.repeat(np.rint(err_levels * N).astype(np.int64), per)
+    t0 = time.time()
+    pairs = synth.mutate_pairs(edits.size, N, int(edits.max()), seed=403, edits=edits)
+    log(f"correlation: {pairs.n:,} pairs at {levels} mutation rates generated in "
+        f"{time.time() - t0:.1f}s")
+    ps = LM.upload_pairs(pairs.a, pairs.a_off, pairs.b, pairs.b_off)
+    weights = np.load(os.path.join(ROOT, "tests", "golden", "learned_weights.npy"))
+    params = torch.from_numpy(weights.astype(np.float32)).cuda()
+    out_F = {}
+    ms = {}
+    for name, prm in (("plain", None), ("learned", params)):
+        LM.pair_fidelity(prm, ps, N)          # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        F = LM.pair_fidelity(prm, ps, N)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1)
+        out_F[name] = F.cpu().numpy().astype(np.float64).reshape(levels, per)
+    res = {}
+    for name, F in out_F.items():
+        curve = correlation_curve(err_levels, list(F))
+        rmse = prediction_rmse(err_levels, list(F), curve)
+        low = err_levels < 0.25
+        res[name] = {"E_fid": [round(float(np.mean(f)), 5) for f in F],
+                     "rmse": [round(r, 5) for r in rmse],
+                     "max_rmse_below_25pct": round(float(np.max(np.asarray(rmse)[low])), 5),
+                     "mean_rmse": round(float(np.mean(rmse)), 5)}
+    value = pairs.n / (ms["plain"] / 1e3)
+    return {
+        "metric": "pair fidelities/s (plain encoding); RMSE of predicting the mutation rate "
+                  "from fidelity (§2.4 protocol)",
+        "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(ms["plain"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"correlation: {pairs.n:,} pairs of a uniform {N} bp string and "
+                               f"its companion after round(err N) edits (substitution, insertion, "
+                               f"deletion uniform), err at {levels} rates evenly over (0, 0.5), "
+                               f"{per} pairs per rate; plain and learned (stored weights) "
+                               f"encodings, m=32",
+                   "pairs": pairs.n, "window_len": N, "levels": levels},
+        "err_levels": [round(float(e), 4) for e in err_levels],
+        "plain": res["plain"], "learned": res["learned"],
+        "learned_ms": round(ms["learned"], 3),
+    }
 
 
 def bench_learned(args):

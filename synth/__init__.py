@@ -184,14 +184,19 @@ class Pairs:
                 self.b[self.b_off[i]:self.b_off[i + 1]])
 
 
-def mutate_pairs(n: int, length: int, max_edits: int, seed: int) -> Pairs:
-    """a uniform of `length`; b = a after e ~ U{0..max_edits} edits, each edit a
-    substitution, insertion or deletion (uniform type) at a uniform position of the
-    current string."""
+def mutate_pairs(n: int, length: int, max_edits: int, seed: int, edits=None) -> Pairs:
+    """a uniform of `length`; b = a after e ~ U{0..max_edits} edits (or the given
+    per-pair counts `edits`, each <= max_edits), each edit a substitution,
+    insertion or deletion (uniform type) at a uniform position of the current
+    string."""
     rng = np.random.default_rng(seed)
     width = length + max_edits + 1
     a = rng.integers(0, 4, size=(n, length), dtype=np.uint8)
-    e = rng.integers(0, max_edits + 1, size=n)
+    if edits is None:
+        e = rng.integers(0, max_edits + 1, size=n)
+    else:
+        e = np.asarray(edits, dtype=np.int64)
+        assert e.shape == (n,) and e.min() >= 0 and e.max() <= max_edits
     buf = np.zeros((n, width), dtype=np.uint8)
     buf[:, :length] = a
     cur = np.full(n, length, dtype=np.int64)
