@@ -172,7 +172,8 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return max64(max64(readlane64(v, 0), readlane64(v, 16)), max64(readlane64(v, 32), readlane64(v, 48)));
 }
 
-// FP32 direct sum over letters [0, n) for this lane's two components.
+// FP32 direct sum over letters [0, n) for this lane's two components (positions
+// past n in the last group of 8 read letter code 255 and add nothing).
 __device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, int n,
                                              const float2* __restrict__ phase32, int lane,
                                              float2& a0, float2& a1) {

@@ -1,4 +1,4 @@
-// FP32 rescore of each read's candidate windows (plain or learned encoding).
+// FP32 rescore of each read's candidate windows (plain and learned encodings).
 //
 // The candidates come from the low-precision product; their fidelities are
 // recomputed from the letters -- never from the stored index -- in FP32: the
@@ -199,9 +199,10 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
   sort_and_write(mykey, lane, r, k, top_idx, top_score);
 }
 
-// ref_delta / read_delta null: the plain encoding; else the learned one with
-// the token offsets of the reference (rows = reference positions) and of the
-// reads (rows = positions in seq).
+// Learned encoding, with the token offsets of the reference (rows = reference
+// positions) and of the reads (rows = positions in seq).  Its phases depend
+// on each string's tokens, so there is no table shared by the strings to
+// contract with: every string is its own direct sum.
 //
 // One block of four wavefronts per read: each wavefront sums a quarter of the
 // read head (the quarters are added in a fixed order), then scores every
@@ -221,18 +222,14 @@ __global__ __launch_bounds__(64 * kRescoreWaves) void rescore_kernel(
   const int64_t r = blockIdx.x;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
-  const bool learned = ref_delta != nullptr;
-  const int T = learned ? N - 8 : N;  // terms of an encoding
+  const int T = N - 8;  // tokens of an encoding
 
   // ---- read head, a quarter per wavefront
   float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
   if (len >= N) {
     const int q0 = wave * T / kRescoreWaves, q1 = (wave + 1) * T / kRescoreWaves;
-    if (learned)
-      direct_sum32_learned(seq + start + q0, q1 - q0, read_delta + (start + q0) * 32,
-                           phase32 + (int64_t)q0 * kM, lane, x0, x1);
-    else
-      direct_sum32(seq + start + q0, q1 - q0, phase32 + (int64_t)q0 * kM, lane, x0, x1);
+    direct_sum32_learned(seq + start + q0, q1 - q0, read_delta + (start + q0) * 32,
+                         phase32 + (int64_t)q0 * kM, lane, x0, x1);
   }
   part[wave][lane] = make_float4(x0.x, x0.y, x1.x, x1.y);
   __syncthreads();
@@ -255,11 +252,8 @@ __global__ __launch_bounds__(64 * kRescoreWaves) void rescore_kernel(
     uint64_t key = 0;
     if (j >= 0 && j < W) {  // uniform per wavefront
       float2 c0, c1;
-      if (learned)
-        direct_sum32_learned(ref + (int64_t)j * stride, T, ref_delta + (int64_t)j * stride * 32,
-                             phase32, lane, c0, c1);
-      else
-        direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
+      direct_sum32_learned(ref + (int64_t)j * stride, T, ref_delta + (int64_t)j * stride * 32,
+                           phase32, lane, c0, c1);
       float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
       // <x|c> = sum conj(x) c
       float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
