@@ -303,3 +303,18 @@ WORKLOADS = {
 }
 
 PAIRS_SEED = 402  # learned-offsets workload: 1,000,000 pairs of 150 bp, 0..30 edits
+
+
+TOKEN_MAP_SEED = 604  # compact token maps: seed = this + s
+
+
+def token_map(s: int, n_class: int, seed: Optional[int] = None) -> np.ndarray:
+    """A seeded 4^s-to-n_class table for the compact token encodings: a
+    uniformly random assignment of the 4^s s-mer codes to n_class classes in
+    which every class receives the same number of s-mers (4^s / n_class, or
+    one more for the first 4^s mod n_class classes).  uint8 [4^s]."""
+    if not 1 <= n_class <= 255:
+        raise ValueError("n_class must be in 1..255")
+    rng = np.random.default_rng(TOKEN_MAP_SEED + s if seed is None else seed)
+    n = 4 ** s
+    return (rng.permutation(n) % n_class).astype(np.uint8)
