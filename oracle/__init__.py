@@ -11,7 +11,7 @@ Modules:
   rope     -- the RoPE-DNA encoding (s = 1), §2.1-§2.3 and §2.10, and the
               sliding-window update of §3.4
   tokens   -- the same with s-mer tokens and compact token maps (§2.1,
-              §2.9, §2.10, §3.4)
+              §2.6, §2.10, §3.4)
   mapping  -- window index, read heads, fidelity, brute-force scoring and
               top-k (§3.1), recall metrics
   lev      -- textbook Levenshtein DP (§1) and a brute-force check

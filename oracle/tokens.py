@@ -13,7 +13,7 @@ Definitions followed (RotorMap paper, arXiv 2603.22245):
   2(k-1)/(m-1)+1 (fine-tuned).
 * §2.3: the default version concatenates the m feature vectors, each indexed
   by the 4^s s-mers, and normalises.
-* §2.9 (compact versions): a 4^s-to-4^t mapping of the s-mers lowers the
+* §2.6 (compact versions): a 4^s-to-4^t mapping of the s-mers lowers the
   dimension; the tokens are then counted by their mapped value (their class).
   Here the mapping is any table `token_map` from s-mer code to class in
   0..C-1, or -1 for an s-mer left out (the variant that keeps only selected
@@ -72,7 +72,7 @@ def encode_raw(w, N: int, s: int, m: int, n_class: int, token_map=None,
                schedule: str = "default") -> np.ndarray:
     """Unnormalised vector c, complex128 [m * n_class]:
     c[(k-1) n_class + cls] = sum over locations loc whose token has class cls
-    of omega^(f_k loc) (§2.1-§2.3, §2.9)."""
+    of omega^(f_k loc) (§2.1-§2.3, §2.6)."""
     cls = token_classes(w, s, token_map)
     E = rope.unit_phases(N, m, np.arange(cls.shape[0]), schedule)   # [n-s+1, m]
     c = np.zeros((m, n_class), dtype=np.complex128)

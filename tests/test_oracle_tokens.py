@@ -2,7 +2,7 @@
 the mathematics fix: the s = 1 case of §2.1-§2.3 (oracle.rope, pinned on its
 own), the §2.10 matrix-power formulation, a closed-form geometric sum, brute
 force over token locations found by string slicing, the §3.4 slide against
-direct encoding, linearity of the compact map (§2.9) and exact-substring
+direct encoding, linearity of the compact map (§2.6) and exact-substring
 mapping (§3.1)."""
 import itertools
 
@@ -102,7 +102,7 @@ def test_slide_matches_direct_encoding(s, m, C, schedule, with_map):
 
 
 def test_compact_map_sums_the_codes_it_merges():
-    """A 4^s-to-C map (§2.9) adds the components of the s-mers it merges:
+    """A 4^s-to-C map (§2.6) adds the components of the s-mers it merges:
     c_map[k, q] = sum over codes with map[code] = q of c_identity[k, code]."""
     s, m, C, N = 4, 8, 16, 150
     w = _rand(N)
