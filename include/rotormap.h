@@ -64,7 +64,10 @@ extern "C" {
 #define RM_SCHED_DEFAULT 0    /* f_k = k            (§2.2 eq. mult-factor) */
 #define RM_SCHED_FINETUNED 1  /* f_k = 2(k-1)/(m-1)+1 (§3.3 eq. mult-factor-finetune) */
 
-#define RM_DIM 32          /* supported number of factors m: 4*m = 128 complex components */
+#define RM_DIM 32          /* number of factors m of the letter encoding: 4*m = 128 complex
+                              components; token encodings use m * n_class = 128 */
+#define RM_MAX_MER 8       /* longest token (s-mer) of a token encoding */
+#define RM_TOKEN_SKIP 255  /* token-map value of an s-mer that adds nothing */
 #define RM_MAX_WINDOW 16384 /* largest supported N */
 #define RM_MAX_KFETCH 32   /* largest candidate list per read */
 
@@ -78,6 +81,22 @@ typedef struct rm_params {
   int32_t reanchor;   /* window starts between two FP64 re-computations of the
                          rolling state (>= 1), or 0: chosen by the library,
                          at most 4096 */
+  /* Tokens (§2.1: s-mers; §2.6: compact versions).  Zero-initialised fields
+   * give the letter encoding (s = 1, n_class 4, n_freq RM_DIM).  Otherwise the
+   * encoding is a token encoding: the token at location loc = 0..N-s is the
+   * s-mer w[loc .. loc+s), with code sum_i w[loc+i] 4^(s-1-i) (first letter
+   * most significant; an s-mer holding a letter outside 0..3 is no token); its
+   * class is the code itself (no map: n_class must be 4^s) or d_token_map[code]
+   * (values >= n_class, e.g. RM_TOKEN_SKIP, add nothing: the variant keeping
+   * only selected s-mers).  Component index (k-1)*n_class + class, and
+   * n_class * n_freq must be 128 with n_class even: (s, m) = (2, 8) or (3, 2)
+   * without a map, any s <= RM_MAX_MER with one (e.g. s = 8 mapped to 16
+   * classes, m = 8). */
+  int32_t mer_len;    /* s, 1..RM_MAX_MER; 0 means 1 */
+  int32_t n_class;    /* components per factor; 0 means 4^s */
+  const uint8_t* d_token_map; /* NULL, or DEVICE [4^s] class per s-mer code; read
+                                 by rm_encode_reference only (copied into the
+                                 index buffer) */
 } rm_params;
 
 /* Descriptor of an index living in a caller-owned device buffer.  Filled by
@@ -92,7 +111,10 @@ typedef struct rm_index {
   float* d_norm2;      /* [W] squared norm of each window's vector before normalising */
   double* d_phase64;   /* [N][m] complex omega^(f_k p), FP64 (re, im) */
   float* d_phase32;    /* [N][m] the same rounded to FP32 */
-  float* d_step32;     /* [m][4] FP32 omega^-f_k (re, im) and omega^(f_k (N-1)) (re, im) */
+  float* d_step32;     /* [m][4] FP32 omega^-f_k (re, im) and omega^(f_k (N-s)) (re, im) */
+  uint8_t* d_token_class; /* token encodings: [4^s] class per s-mer code (the map with
+                             values >= n_class replaced by RM_TOKEN_SKIP, or the
+                             identity); NULL for the letter encoding */
 } rm_index;
 
 /* Human-readable text of a status code (static storage). */
@@ -113,8 +135,10 @@ size_t rm_index_bytes(int64_t ref_len, const rm_params* p);
  * §3.4 in FP32 with an FP64 re-computation every p->reanchor starts,
  * normalised and stored in p->precision.  Fills *out.
  * Errors: RM_EINVAL (null pointer, bad enum), RM_ESIZE (ref_len < N, N out of
- * range, stride < 1, buf_bytes < rm_index_bytes, more than 2^31-1 windows),
- * RM_EUNSUPPORTED (n_freq != RM_DIM). */
+ * range, stride < 1, buf_bytes < rm_index_bytes, more than 2^31-1 windows,
+ * mer_len out of range, N < s), RM_EUNSUPPORTED (letter encoding with n_freq
+ * != RM_DIM; token encoding with n_class * n_freq != 128, n_class odd, or no
+ * map and n_class != 4^s). */
 int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
                         void* d_buf, size_t buf_bytes, rm_index* out, void* stream);
 
@@ -127,7 +151,8 @@ size_t rm_read_emb_bytes(int32_t n_reads, const rm_params* p);
 /* Encode the head (first N letters) of every read (§3.1): FP64 direct sum,
  * normalised, stored in the index precision.  Read r is
  * d_seq[d_off[r] .. d_off[r+1]) (d_off: n_reads+1 int64, device).  A read
- * shorter than N is encoded as the zero vector.  d_read_scale [n_reads]
+ * shorter than N is encoded as the zero vector.  A token index sums the
+ * head's tokens (locations 0..N-s) by class.  d_read_scale [n_reads]
  * receives the FP8 scale per read (1.0 otherwise); it may be NULL unless the
  * precision is FP8.  Errors: RM_EINVAL, RM_ESIZE (n_reads < 1). */
 int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
@@ -155,7 +180,8 @@ int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_re
  * FP32 angle table (never from the stored low-precision index), F =
  * |<x|c>|^2 / (X C) in FP32, sorted by (F desc, window id asc).  Candidates
  * with id < 0 are skipped; missing entries are filled with id -1, score -1.
- * Errors: RM_EINVAL, RM_ESIZE (k < 1 or k > k_fetch). */
+ * A token index recomputes the encodings over its tokens and classes the same
+ * way.  Errors: RM_EINVAL, RM_ESIZE (k < 1 or k > k_fetch). */
 int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                const int64_t* d_off, int32_t n_reads, int32_t k_fetch,
                const int32_t* d_cand_idx, int32_t k, int32_t* d_top_idx, float* d_top_score,
@@ -218,7 +244,7 @@ size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radiu
  * Errors: RM_EINVAL (null pointer, invalid index), RM_ESIZE (n_reads < 1,
  * k_fetch outside 1..RM_MAX_KFETCH, radius outside 0..RM_REFINE_MAX_RADIUS,
  * k outside 1..min(RM_MAX_KFETCH, k_fetch (2 radius + 1)), ws too small,
- * 2^31 or more step-1 windows). */
+ * 2^31 or more step-1 windows), RM_EUNSUPPORTED (a token encoding). */
 int rm_refine(const rm_index* coarse, const uint8_t* d_ref, const uint8_t* d_seq,
               const int64_t* d_off, int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx,
               int32_t radius, int32_t k, int32_t* d_top_idx, float* d_top_score, void* d_ws,
@@ -380,20 +406,23 @@ int rm_mlp_infer(const float* d_params, const uint8_t* d_seq, int64_t n_letters,
 /* As rm_encode_reference, with the learned encoding; d_ref_delta = the token
  * offsets of d_ref (rm_mlp_infer over the reference), caller-owned, read
  * during this call only.  Errors as rm_encode_reference, plus RM_EINVAL
- * (null d_ref_delta) and RM_ESIZE (window_len < 9). */
+ * (null d_ref_delta), RM_ESIZE (window_len < 9) and RM_EUNSUPPORTED (token
+ * parameters: the learned encoding has its own 9-letter tokens). */
 int rm_encode_reference_learned(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
                                 const float* d_ref_delta, void* d_buf, size_t buf_bytes,
                                 rm_index* out, void* stream);
 
 /* As rm_encode_reads, with the learned encoding of each read head;
  * d_read_delta = the token offsets of d_seq (rows indexed by positions in
- * d_seq).  Errors as rm_encode_reads, plus RM_EINVAL (null d_read_delta). */
+ * d_seq).  Errors as rm_encode_reads, plus RM_EINVAL (null d_read_delta) and
+ * RM_EUNSUPPORTED (a token index). */
 int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
                             int32_t n_reads, const float* d_read_delta, void* d_read_emb,
                             float* d_read_scale, void* stream);
 
 /* As rm_rescore, recomputing the fidelities in FP32 from the letters and the
- * token offsets of the reference and of the reads.  Errors as rm_rescore. */
+ * token offsets of the reference and of the reads.  Errors as rm_rescore,
+ * plus RM_EUNSUPPORTED (a token index). */
 int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d_ref_delta,
                        const uint8_t* d_seq, const int64_t* d_off, const float* d_read_delta,
                        int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx, int32_t k,

@@ -19,6 +19,7 @@ RM_OK, RM_EINVAL, RM_ESIZE, RM_EUNSUPPORTED, RM_EHIP = 0, -1, -2, -3, -4
 RM_FP32, RM_FP16, RM_FP8_E4M3 = 0, 1, 2
 RM_SCHED_DEFAULT, RM_SCHED_FINETUNED = 0, 1
 RM_DIM, RM_MAX_WINDOW, RM_MAX_KFETCH = 32, 16384, 32
+RM_MAX_MER, RM_TOKEN_SKIP = 8, 255
 PRECISIONS = {"fp32": RM_FP32, "fp16": RM_FP16, "fp8": RM_FP8_E4M3}
 SCHEDULES = {"default": RM_SCHED_DEFAULT, "finetuned": RM_SCHED_FINETUNED}
 
@@ -26,14 +27,17 @@ SCHEDULES = {"default": RM_SCHED_DEFAULT, "finetuned": RM_SCHED_FINETUNED}
 class rm_params(ctypes.Structure):
     _fields_ = [("window_len", ctypes.c_int32), ("stride", ctypes.c_int32),
                 ("n_freq", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reanchor", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reanchor", ctypes.c_int32),
+                ("mer_len", ctypes.c_int32), ("n_class", ctypes.c_int32),
+                ("d_token_map", ctypes.c_void_p)]
 
 
 class rm_index(ctypes.Structure):
     _fields_ = [("p", rm_params), ("ref_len", ctypes.c_int64), ("n_windows", ctypes.c_int64),
                 ("d_emb", ctypes.c_void_p), ("d_scale", ctypes.c_void_p),
                 ("d_norm2", ctypes.c_void_p), ("d_phase64", ctypes.c_void_p),
-                ("d_phase32", ctypes.c_void_p), ("d_step32", ctypes.c_void_p)]
+                ("d_phase32", ctypes.c_void_p), ("d_step32", ctypes.c_void_p),
+                ("d_token_class", ctypes.c_void_p)]
 
 
 class rm_tuning(ctypes.Structure):
@@ -144,11 +148,13 @@ def _check(status: int, call: str):
 
 
 def make_params(window_len=150, stride=1, n_freq=RM_DIM, schedule="default", precision="fp16",
-                reanchor=0) -> rm_params:
+                reanchor=0, mer_len=0, n_class=0, token_map=None) -> rm_params:
+    """token_map: None or a device uint8 tensor of 4^mer_len classes (its
+    address is stored; it must stay alive until rm_encode_reference returns)."""
     return rm_params(window_len, stride, n_freq,
                      SCHEDULES.get(schedule, schedule) if isinstance(schedule, str) else schedule,
                      PRECISIONS.get(precision, precision) if isinstance(precision, str) else precision,
-                     reanchor)
+                     reanchor, mer_len, n_class, None if token_map is None else _ptr(token_map))
 
 
 def status_str(status: int) -> str:

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "rm_internal.h"
+#include "rm_tokens.h"
 
 namespace {
 
@@ -12,9 +13,27 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// The letter encoding: single letters, no map, 4 classes (the zero-initialised
+// token fields).  Anything else is a token encoding.
+bool letter_encoding(const rm_params* p) {
+  return p->mer_len <= 1 && p->d_token_map == nullptr && (p->n_class == 0 || p->n_class == 4);
+}
+
+int mer_of(const rm_params* p) { return p->mer_len > 1 ? p->mer_len : 1; }
+
 bool params_ok(const rm_params* p, int* why) {
   if (p == nullptr) return (*why = RM_EINVAL), false;
-  if (p->n_freq != RM_DIM) return (*why = RM_EUNSUPPORTED), false;
+  if (p->mer_len < 0 || p->mer_len > RM_MAX_MER) return (*why = RM_ESIZE), false;
+  if (letter_encoding(p)) {
+    if (p->n_freq != RM_DIM) return (*why = RM_EUNSUPPORTED), false;
+  } else {
+    const int s = mer_of(p);
+    const int C = p->n_class != 0 ? p->n_class : (s <= 3 ? 1 << (2 * s) : 0);
+    if (C < 2 || C % 2 != 0 || p->n_freq < 1 || C * p->n_freq != rm::kComplex)
+      return (*why = RM_EUNSUPPORTED), false;
+    if (p->d_token_map == nullptr && C != (1 << (2 * s))) return (*why = RM_EUNSUPPORTED), false;
+    if (p->window_len < s) return (*why = RM_ESIZE), false;
+  }
   if (p->schedule != RM_SCHED_DEFAULT && p->schedule != RM_SCHED_FINETUNED)
     return (*why = RM_EINVAL), false;
   if (p->precision != RM_FP32 && p->precision != RM_FP16 && p->precision != RM_FP8_E4M3)
@@ -31,7 +50,7 @@ int64_t windows_of(int64_t ref_len, const rm_params* p) {
 }
 
 struct Layout {
-  size_t emb, scale, norm2, phase64, phase32, step32, total;
+  size_t emb, scale, norm2, phase64, phase32, step32, token_class, total;
 };
 
 Layout layout(int64_t W, const rm_params* p) {
@@ -49,6 +68,8 @@ Layout layout(int64_t W, const rm_params* p) {
   off = align_up(off + (size_t)p->window_len * p->n_freq * 2 * sizeof(float));
   L.step32 = off;
   off = align_up(off + (size_t)p->n_freq * 4 * sizeof(float));
+  L.token_class = off;
+  if (!letter_encoding(p)) off = align_up(off + ((size_t)1 << (2 * mer_of(p))));
   L.total = off;
   return L;
 }
@@ -62,6 +83,7 @@ int index_ok(const rm_index* idx) {
   if (!idx->d_emb || !idx->d_scale || !idx->d_norm2 || !idx->d_phase64 || !idx->d_phase32 ||
       !idx->d_step32)
     return RM_EINVAL;
+  if (!letter_encoding(&idx->p) && !idx->d_token_class) return RM_EINVAL;
   return RM_OK;
 }
 
@@ -112,6 +134,7 @@ int rm_encode_reference_learned(const uint8_t* d_ref, int64_t ref_len, const rm_
                                 rm_index* out, void* stream) {
   if (d_ref_delta == nullptr) return RM_EINVAL;
   if (p != nullptr && p->window_len < 9) return RM_ESIZE;
+  if (p != nullptr && !letter_encoding(p)) return RM_EUNSUPPORTED;
   return encode_reference_impl(d_ref, ref_len, p, d_ref_delta, d_buf, buf_bytes, out, stream);
 }
 
@@ -138,11 +161,19 @@ static int encode_reference_impl(const uint8_t* d_ref, int64_t ref_len, const rm
   idx.d_phase64 = reinterpret_cast<double*>(base + L.phase64);
   idx.d_phase32 = reinterpret_cast<float*>(base + L.phase32);
   idx.d_step32 = reinterpret_cast<float*>(base + L.step32);
+  idx.d_token_class = letter_encoding(p) ? nullptr : base + L.token_class;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   int st = hip_status(rm::launch_tables(*p, idx.d_phase64, idx.d_phase32, idx.d_step32, s));
   if (st != RM_OK) return st;
-  if (d_delta == nullptr)
+  if (idx.d_token_class != nullptr) {
+    const int C = 128 / p->n_freq;
+    st = hip_status(rm::launch_token_table(p->d_token_map, mer_of(p), C, idx.d_token_class, s));
+    if (st == RM_OK)
+      st = hip_status(rm::launch_encode_reference_tokens(d_ref, W, *p, idx.d_phase64,
+                                                         idx.d_step32, idx.d_token_class,
+                                                         idx.d_emb, idx.d_scale, idx.d_norm2, s));
+  } else if (d_delta == nullptr)
     st = hip_status(rm::launch_encode_reference(d_ref, W, *p, idx.d_phase64, idx.d_step32,
                                                 idx.d_emb, idx.d_scale, idx.d_norm2, s));
   else
@@ -167,6 +198,11 @@ int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_
   if (d_seq == nullptr || d_off == nullptr || d_read_emb == nullptr) return RM_EINVAL;
   if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
   if (n_reads < 1) return RM_ESIZE;
+  if (!letter_encoding(&idx->p))
+    return hip_status(rm::launch_encode_reads_tokens(idx->p, idx->d_phase64, idx->d_token_class,
+                                                     d_seq, d_off, n_reads, d_read_emb,
+                                                     d_read_scale,
+                                                     static_cast<hipStream_t>(stream)));
   return hip_status(rm::launch_encode_reads(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
                                             d_read_emb, d_read_scale,
                                             static_cast<hipStream_t>(stream)));
@@ -181,6 +217,7 @@ int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int
     return RM_EINVAL;
   if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
   if (n_reads < 1 || idx->p.window_len < 9) return RM_ESIZE;
+  if (!letter_encoding(&idx->p)) return RM_EUNSUPPORTED;
   return hip_status(rm::launch_encode_reads_learned(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
                                                     d_read_delta, d_read_emb, d_read_scale,
                                                     static_cast<hipStream_t>(stream)));
@@ -207,6 +244,10 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
     return RM_EINVAL;
   if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || k < 1 || k > k_fetch)
     return RM_ESIZE;
+  if (!letter_encoding(&idx->p))
+    return hip_status(rm::launch_rescore_tokens(*idx, d_ref, d_seq, d_off, n_reads, k_fetch,
+                                                d_cand_idx, k, d_top_idx, d_top_score,
+                                                static_cast<hipStream_t>(stream)));
   return hip_status(rm::launch_rescore(*idx, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, k,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
 }
@@ -255,6 +296,7 @@ int rm_refine(const rm_index* coarse, const uint8_t* d_ref, const uint8_t* d_seq
       (int64_t)k > (int64_t)k_fetch * (2 * radius + 1))
     return RM_ESIZE;
   if (ws_bytes < rm::refine_workspace_bytes(n_reads, k_fetch, radius)) return RM_ESIZE;
+  if (!letter_encoding(&coarse->p)) return RM_EUNSUPPORTED;
   if (coarse->ref_len - coarse->p.window_len + 1 > (int64_t)INT32_MAX) return RM_ESIZE;
   return hip_status(rm::launch_refine(*coarse, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx,
                                       radius, k, d_top_idx, d_top_score, d_ws,
@@ -274,6 +316,7 @@ int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d
   if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || k < 1 || k > k_fetch ||
       idx->p.window_len < 9)
     return RM_ESIZE;
+  if (!letter_encoding(&idx->p)) return RM_EUNSUPPORTED;
   return hip_status(rm::launch_rescore(*idx, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, k,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream),
                                        d_ref_delta, d_read_delta));

@@ -15,6 +15,7 @@
 // directly from the letters in FP64 (the re-anchor), then rolled in FP32.
 // Each window is normalised (§2.3) and written in the index precision.
 #include "rm_internal.h"
+#include "rm_tokens.h"
 
 namespace rm {
 
@@ -358,6 +359,95 @@ __global__ __launch_bounds__(256) void encode_reads_learned_kernel(
   if (scale != nullptr && lane == 0) scale[r] = s;
 }
 
+// ---- token encodings (§2.1 s-mers, §2.6 compact versions) ----------------------
+// The window encoder above with tokens in place of letters (lane layout of
+// rm_tokens.h): the re-anchor sums the tokens at locations 0..N-s in FP64; a
+// slide removes the token at the old start (location 0, -omega^-f after the
+// rotation) and adds the token ending at the new window's last letter
+// (location N-s, +omega^(f (N-s)), held in step32).
+template <int PREC>
+__global__ __launch_bounds__(256) void encode_reference_tokens_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int s, int m, int n_class,
+    int64_t seg_len, int64_t n_seg, const double2* __restrict__ phase64,
+    const float4* __restrict__ step32, const uint8_t* __restrict__ table, void* __restrict__ emb,
+    float* __restrict__ scale, float* __restrict__ norm2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (seg >= n_seg) return;
+  const int k = 2 * lane / n_class, c0 = 2 * lane - k * n_class;
+  const int T = N - s + 1;  // tokens per window
+  const int64_t j0 = seg * seg_len;
+  const int64_t j1 = min(W, j0 + seg_len);
+
+  double2 a0, a1;
+  direct_sum_tokens(ref + j0 * stride, T, s, table, phase64, m, k, c0, lane, a0, a1);
+  float2 v0 = make_float2((float)a0.x, (float)a0.y);
+  float2 v1 = make_float2((float)a1.x, (float)a1.y);
+  SideBuf side{j0, 0, 0.f, 0.f};
+  emit_window<PREC>(j0, lane, N, v0, v1, emb, side, scale, norm2);
+
+  const float4 st = step32[k];
+  const float2 rot = make_float2(st.x, st.y);  // omega^-f
+  const float2 inc = make_float2(st.z, st.w);  // omega^(f (N-s))
+
+  // slide t moves the start from s0+t to s0+t+1: the outgoing token starts at
+  // s0+t, the incoming one at s0+t+1+N-s (its last letter is s0+t+N)
+  const int64_t s0 = j0 * stride;
+  const int64_t n_slides = (j1 - 1 - j0) * stride;
+  const int64_t in_off = N - s + 1;
+  int64_t j = j0;
+  int until_emit = stride;
+  int out_c = lane < n_slides ? token_class(ref + s0 + lane, s, table) : RM_TOKEN_SKIP;
+  int in_c = lane < n_slides ? token_class(ref + s0 + lane + in_off, s, table) : RM_TOKEN_SKIP;
+  for (int64_t tb = 0; tb < n_slides; tb += 64) {
+    const int64_t tn = tb + 64 + lane;
+    const int out_next = tn < n_slides ? token_class(ref + s0 + tn, s, table) : RM_TOKEN_SKIP;
+    const int in_next =
+        tn < n_slides ? token_class(ref + s0 + tn + in_off, s, table) : RM_TOKEN_SKIP;
+    const int cnt = (int)min<int64_t>(64, n_slides - tb);
+    for (int i = 0; i < cnt; ++i) {
+      // classes relative to this lane's c0: 0 or 1 is one of its components
+      const int o = __builtin_amdgcn_readlane(out_c, i) - c0;
+      const int n = __builtin_amdgcn_readlane(in_c, i) - c0;
+      slide(v0, v1, rot, (unsigned)o < 2u ? o : 255, (unsigned)n < 2u ? n : 255, 0, rot, inc);
+      if (--until_emit == 0) {
+        until_emit = stride;
+        ++j;
+        emit_window<PREC>(j, lane, N, v0, v1, emb, side, scale, norm2);
+      }
+    }
+    out_c = out_next;
+    in_c = in_next;
+  }
+  side_flush(side, lane, norm2, scale);
+}
+
+// The read-head encoder with tokens: FP64 direct sum over the head's tokens.
+template <int PREC>
+__global__ __launch_bounds__(256) void encode_reads_tokens_kernel(
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
+    int s, int m, int n_class, const double2* __restrict__ phase64,
+    const uint8_t* __restrict__ table, void* __restrict__ emb, float* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= n_reads) return;
+  const int k = 2 * lane / n_class, c0 = 2 * lane - k * n_class;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+  if (len >= N) direct_sum_tokens(seq + start, N - s + 1, s, table, phase64, m, k, c0, lane, a0, a1);
+  double X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
+  bool deg = X < (double)kDegenerateRel * N;
+  double inv = deg ? 0.0 : 1.0 / sqrt(X);
+  float xr0 = (float)(a0.x * inv), xi0 = (float)(a0.y * inv);
+  float xr1 = (float)(a1.x * inv), xi1 = (float)(a1.y * inv);
+  Row4 re{{xr0, xi0, xr1, xi1}};
+  Row4 im{{-xi0, xr0, -xi1, xr1}};
+  float sc = store_row<PREC>(emb, 2 * r, lane, re);
+  store_row<PREC>(emb, 2 * r + 1, lane, im);
+  if (scale != nullptr && lane == 0) scale[r] = sc;
+}
+
 }  // namespace
 
 hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_params& p,
@@ -476,6 +566,48 @@ hipError_t launch_encode_reads_learned(const rm_params& p, const double* phase64
                          n_reads, p.window_len, ph, delta, emb, scale);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_reference_tokens(const uint8_t* ref, int64_t W, const rm_params& p,
+                                          const double* phase64, const float* step32,
+                                          const uint8_t* table, void* emb, float* scale,
+                                          float* norm2, hipStream_t st) {
+  // segments as for the letter encoding
+  int64_t seg = p.reanchor;
+  if (seg <= 0) {
+    seg = (W + 8191) / 8192;
+    if (seg < 256) seg = 256;
+    if (seg > 4096) seg = 4096;
+  }
+  const int64_t n_seg = (W + seg - 1) / seg;
+  const int waves = 4;
+  const int64_t blocks = (n_seg + waves - 1) / waves;
+  const int s = p.mer_len > 1 ? p.mer_len : 1;
+  const int C = 128 / p.n_freq;
+  auto* ph = reinterpret_cast<const double2*>(phase64);
+  auto* sp = reinterpret_cast<const float4*>(step32);
+  auto kern = p.precision == RM_FP32   ? encode_reference_tokens_kernel<RM_FP32>
+              : p.precision == RM_FP16 ? encode_reference_tokens_kernel<RM_FP16>
+                                       : encode_reference_tokens_kernel<RM_FP8_E4M3>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), 0, st, ref, W, p.window_len,
+                     p.stride, s, p.n_freq, C, seg, n_seg, ph, sp, table, emb, scale, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_reads_tokens(const rm_params& p, const double* phase64,
+                                      const uint8_t* table, const uint8_t* seq, const int64_t* off,
+                                      int32_t n_reads, void* emb, float* scale, hipStream_t st) {
+  const int waves = 4;
+  const int64_t blocks = ((int64_t)n_reads + waves - 1) / waves;
+  const int s = p.mer_len > 1 ? p.mer_len : 1;
+  const int C = 128 / p.n_freq;
+  auto* ph = reinterpret_cast<const double2*>(phase64);
+  auto kern = p.precision == RM_FP32   ? encode_reads_tokens_kernel<RM_FP32>
+              : p.precision == RM_FP16 ? encode_reads_tokens_kernel<RM_FP16>
+                                       : encode_reads_tokens_kernel<RM_FP8_E4M3>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), 0, st, seq, off, n_reads,
+                     p.window_len, s, p.n_freq, C, ph, table, emb, scale);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 // direct sums up to the order of FP32 additions, and each table row is read
 // once per read instead of once per string.
 #include "rm_internal.h"
+#include "rm_tokens.h"
 
 namespace rm {
 
@@ -271,6 +272,71 @@ __global__ __launch_bounds__(64 * kRescoreWaves) void rescore_kernel(
   sort_and_write(lane < k_fetch ? keys[lane] : 0, lane, r, k, top_idx, top_score);
 }
 
+// Token encodings (§2.1 s-mers, §2.6 compact versions; lane layout of
+// rm_tokens.h): the block layout of rescore_kernel, with FP32 direct sums over
+// the tokens at locations 0..N-s by class.
+__global__ __launch_bounds__(64 * kRescoreWaves) void rescore_tokens_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int s, int m, int n_class,
+    const float2* __restrict__ phase32, const uint8_t* __restrict__ table,
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t R, int k_fetch,
+    const int32_t* __restrict__ cand, int k, int32_t* __restrict__ top_idx,
+    float* __restrict__ top_score) {
+  __shared__ float4 part[kRescoreWaves][64];
+  __shared__ uint64_t keys[RM_MAX_KFETCH];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r = blockIdx.x;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  const int T = N - s + 1;  // tokens of an encoding
+  const int kf = 2 * lane / n_class, c0 = 2 * lane - kf * n_class;
+
+  // ---- read head, a quarter of its token locations per wavefront
+  float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
+  if (len >= N) {
+    const int q0 = wave * T / kRescoreWaves, q1 = (wave + 1) * T / kRescoreWaves;
+    direct_sum_tokens(seq + start + q0, q1 - q0, s, table, phase32 + (int64_t)q0 * m, m, kf, c0,
+                      lane, x0, x1);
+  }
+  part[wave][lane] = make_float4(x0.x, x0.y, x1.x, x1.y);
+  __syncthreads();
+  {
+    float4 v = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRescoreWaves; ++w) {
+      const float4 u = part[w][lane];
+      v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+    }
+    x0 = make_float2(v.x, v.y);
+    x1 = make_float2(v.z, v.w);
+  }
+  const float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
+  const bool xdeg = X < kDegenerateRel * (float)N;
+
+  // ---- candidates e = wave, wave + 4, ...
+  for (int e = wave; e < k_fetch; e += kRescoreWaves) {
+    const int32_t j = cand[r * k_fetch + e];
+    uint64_t key = 0;
+    if (j >= 0 && j < W) {  // uniform per wavefront
+      float2 c0v, c1v;
+      direct_sum_tokens(ref + (int64_t)j * stride, T, s, table, phase32, m, kf, c0, lane, c0v,
+                        c1v);
+      const float C = wave_sum(c0v.x * c0v.x + c0v.y * c0v.y + c1v.x * c1v.x + c1v.y * c1v.y);
+      // <x|c> = sum conj(x) c
+      const float ipr = wave_sum(x0.x * c0v.x + x0.y * c0v.y + x1.x * c1v.x + x1.y * c1v.y);
+      const float ipi = wave_sum(x0.x * c0v.y - x0.y * c0v.x + x1.x * c1v.y - x1.y * c1v.x);
+      const bool deg = xdeg || C < kDegenerateRel * (float)N;
+      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+      key = ((uint64_t)(__float_as_uint(F) + 1u) << 32) | (0xffffffffu - (uint32_t)j);
+    }
+    if (lane == 0) keys[e] = key;
+  }
+  __syncthreads();
+  if (wave != 0) return;
+
+  sort_and_write(lane < k_fetch ? keys[lane] : 0, lane, r, k, top_idx, top_score);
+}
+
 }  // namespace
 
 hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
@@ -294,6 +360,19 @@ hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t
                      idx.p.window_len, idx.p.stride, reinterpret_cast<const float2*>(idx.d_phase32),
                      seq, off, n_reads, k_fetch, cand_idx, k, top_idx, top_score, ref_delta,
                      read_delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescore_tokens(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
+                                 const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                                 const int32_t* cand_idx, int32_t k, int32_t* top_idx,
+                                 float* top_score, hipStream_t st) {
+  const int s = idx.p.mer_len > 1 ? idx.p.mer_len : 1;
+  hipLaunchKernelGGL(rescore_tokens_kernel, dim3((unsigned)n_reads), dim3(64 * kRescoreWaves), 0,
+                     st, ref, idx.n_windows, idx.p.window_len, idx.p.stride, s, idx.p.n_freq,
+                     128 / idx.p.n_freq, reinterpret_cast<const float2*>(idx.d_phase32),
+                     idx.d_token_class, seq, off, n_reads, k_fetch, cand_idx, k, top_idx,
+                     top_score);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ class Index:
     ref: object      # torch uint8 tensor, the reference letters on the device
     learned: object = None  # FP32 network parameters (device) of a learned index
     delta: object = None    # token offsets of the reference [G-8, 32] (learned index)
+    token_map: object = None  # device copy of the caller's s-mer class table (token index)
 
     @property
     def n_windows(self) -> int:
@@ -61,11 +62,30 @@ def _delta_buffer(n_letters: int, device):
 
 
 def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", schedule="default",
-                reanchor=0, stream=None, device="cuda", learned=None) -> Index:
+                reanchor=0, stream=None, device="cuda", learned=None, mer_len=1,
+                n_freq=None, token_map=None) -> Index:
     """Encode the reference's windows.  learned: network parameters (10,432
-    FP32 values, numpy or device tensor) for the learned encoding, else plain."""
+    FP32 values, numpy or device tensor) for the learned encoding, else plain.
+
+    Token encodings (s-mers): mer_len = s, n_freq = m (default 128 / 4^s, or
+    128 / n_class with a map) and token_map = None (class = s-mer code) or a
+    table of 4^s classes (uint8; RM_TOKEN_SKIP or any value >= 128 / m leaves an
+    s-mer out)."""
     torch = _torch()
-    p = L.make_params(window_len, stride, L.RM_DIM, schedule, precision, reanchor)
+    d_map = None
+    n_class = 0
+    if token_map is not None:
+        d_map = torch.as_tensor(np.ascontiguousarray(token_map, dtype=np.uint8)).to(device)
+        if d_map.numel() != 4 ** mer_len:
+            raise ValueError(f"token_map must have 4^{mer_len} entries")
+        if n_freq is None:
+            raise ValueError("n_freq is required with a token map")
+    if n_freq is None:
+        n_freq = L.RM_DIM if mer_len <= 1 else max(1, 128 // 4 ** mer_len)
+    if mer_len > 1 or token_map is not None:
+        n_class = 128 // n_freq
+    p = L.make_params(window_len, stride, n_freq, schedule, precision, reanchor, mer_len, n_class,
+                      d_map)
     if isinstance(ref, np.ndarray):
         d_ref = torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device)
     else:  # already a device tensor
@@ -76,7 +96,7 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
     buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
     if learned is None:
         idx = L.rm_encode_reference(d_ref, int(d_ref.numel()), p, buf, nbytes, stream)
-        return Index(p, idx, buf, d_ref)
+        return Index(p, idx, buf, d_ref, token_map=d_map)
     params = torch.as_tensor(learned, dtype=torch.float32).to(device).contiguous()
     if params.numel() != L.RM_LEARNED_PARAMS:
         raise ValueError(f"learned parameters must have {L.RM_LEARNED_PARAMS} values")

@@ -208,3 +208,49 @@ def test_strand_calls_validation():
     assert ms(10, 8, 1, 1, None, 1) == L.RM_EINVAL
     assert lib.rm_merge_strands(1, 1, 1, 1, 10, 8, ctypes.c_float(0.0), 1, 1, 1, None,
                                 None) == L.RM_EINVAL
+
+
+def test_token_params_validation():
+    """Token encodings (s-mers): accepted shapes, rejected ones, the class-table
+    region of the index buffer, and the calls that take letter indexes only."""
+    lib = L.lib()
+    R = ctypes.byref
+    letters = L.make_params(150, 1, 32, "default", "fp16")
+    ok = [L.make_params(150, 1, 8, "default", "fp16", 0, 2, 16),
+          L.make_params(150, 1, 2, "finetuned", "fp8", 0, 3, 64),
+          L.make_params(150, 1, 8, "default", "fp16", 0, 8, 16, 0x2000)]     # s = 8, a map
+    for p in ok:
+        assert L.rm_num_windows(20_000, p) == 19_851
+    # the phase tables shrink with m; the class table adds 4^s bytes (256-byte aligned)
+    assert L.rm_index_bytes(20_000, ok[0]) < L.rm_index_bytes(20_000, letters)
+    assert L.rm_index_bytes(20_000, ok[2]) - L.rm_index_bytes(20_000, ok[0]) == 4 ** 8 - 256
+    assert L.rm_index_bytes(20_000, ok[1]) > 19_851 * 256
+    bad = [(L.make_params(150, 1, 32, "default", "fp16", 0, 2, 16), L.RM_EUNSUPPORTED),  # C m != 128
+           (L.make_params(150, 1, 8, "default", "fp16", 0, 4, 16), L.RM_EUNSUPPORTED),   # no map, C != 4^s
+           (L.make_params(150, 1, 2, "default", "fp16", 0, 4, 0), L.RM_EUNSUPPORTED),    # 4^4 * 2 != 128
+           (L.make_params(150, 1, 1, "default", "fp16", 0, 2, 128, 0x2000), L.RM_OK),
+           (L.make_params(150, 1, 128, "default", "fp16", 0, 2, 1, 0x2000), L.RM_EUNSUPPORTED),
+           (L.make_params(150, 1, 8, "default", "fp16", 0, L.RM_MAX_MER + 1, 16, 0x2000),
+            L.RM_ESIZE),
+           (L.make_params(150, 1, 8, "default", "fp16", 0, -1, 16), L.RM_ESIZE),
+           (L.make_params(7, 1, 8, "default", "fp16", 0, 8, 16, 0x2000), L.RM_ESIZE)]    # N < s
+    out = L.rm_index()
+    for p, status in bad:
+        if status == L.RM_OK:
+            assert L.rm_index_bytes(20_000, p) > 0
+            continue
+        assert L.rm_index_bytes(20_000, p) == 0
+        assert lib.rm_encode_reference(0x1000, 20_000, R(p), 0x10000, 1 << 30, R(out), None) == status
+    # a token index descriptor needs its class table
+    idx = _fake_index()
+    idx.p = ok[0]
+    assert lib.rm_encode_reads(R(idx), 1, 1, 10, 1, 1, None) == L.RM_EINVAL
+    idx.d_token_class = 0x100000
+    # the learned calls and the refinement take letter indexes only
+    ws = L.rm_refine_workspace_bytes(10, 8, 3)
+    assert lib.rm_refine(R(idx), 1, 1, 1, 10, 8, 1, 3, 8, 1, 1, 1, ws, None) == L.RM_EUNSUPPORTED
+    assert lib.rm_encode_reads_learned(R(idx), 1, 1, 10, 1, 1, 1, None) == L.RM_EUNSUPPORTED
+    assert lib.rm_rescore_learned(R(idx), 1, 1, 1, 1, 1, 10, 8, 1, 8, 1, 1, None) \
+        == L.RM_EUNSUPPORTED
+    assert lib.rm_encode_reference_learned(0x1000, 20_000, R(ok[0]), 0x3000, 0x10000, 1 << 30,
+                                           R(out), None) == L.RM_EUNSUPPORTED

@@ -1,0 +1,286 @@
+"""GPU parity of the token encodings (§2.1 s-mers, §2.6 compact versions)
+against the FP64 token oracle (oracle.tokens), through the C ABI: the rolling
+window encoder (FP32 state, FP64 re-anchors), the quantised index, the
+read-head encoder, the product + top-k + FP32 rescore, the rescore alone on
+given candidate pools, and windows that a map leaves empty.
+
+Encodings: s = 2 with m = 8 (16 di-mer classes), s = 3 with m = 2 and the
+fine-tuned factors (64 tri-mer classes), and s = 8 mapped by a seeded
+balanced random table onto 16 classes with m = 8, fine-tuned -- the compact
+fine-tuned kind of encoding the paper maps with, at 128 complex components."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mapping, tokens
+from tests.gpu_helpers import emb_to_complex, fp8_bound, read_rows, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+PLAIN = synth.WORKLOADS["plain"]
+N = 150
+TOL = {"fp32": 1e-5, "fp16": 1e-3, "fp8": 1e-2}
+
+# name -> (s, m, n_class, token map or None, schedule)
+ENC = {
+    "s2": (2, 8, 16, None, "default"),
+    "s3": (3, 2, 64, None, "finetuned"),
+    "s8c16": (8, 8, 16, synth.token_map(8, 16), "finetuned"),
+}
+
+
+def _build(ref, enc, precision, **kw):
+    from paper_2603_22245_amd import mapper
+    torch_cuda()
+    s, m, C, tm, sched = ENC[enc]
+    return mapper.build_index(ref, window_len=kw.pop("window_len", N), precision=precision,
+                              schedule=sched, mer_len=s, n_freq=m, token_map=tm, **kw)
+
+
+def _oracle_windows(ref, enc, n=N, stride=1):
+    s, m, C, tm, sched = ENC[enc]
+    starts = mapping.window_starts(ref.shape[0], n, stride)
+    Cw = tokens.encode_many(mapping.window_letters(ref, starts, n), n, s, m, C, tm, sched)
+    return mapping.normalized_rows(Cw, n)
+
+
+def _oracle_heads(heads, enc, n=N):
+    s, m, C, tm, sched = ENC[enc]
+    return mapping.normalized_rows(tokens.encode_many(heads, n, s, m, C, tm, sched), n)
+
+
+@pytest.fixture(scope="module")
+def plain_data():
+    ref = PLAIN.reference()
+    reads = PLAIN.reads(ref)
+    heads = mapping.read_heads(reads.seq, reads.offsets, N)
+    return ref, reads, heads
+
+
+@pytest.fixture(scope="module")
+def oracle_F(plain_data):
+    ref, _, heads = plain_data
+    out = {}
+    for enc in ENC:
+        Cn, n2 = _oracle_windows(ref, enc)
+        Xn, _ = _oracle_heads(heads, enc)
+        out[enc] = (Cn, n2, np.abs(np.conj(Xn) @ Cn.T) ** 2)
+    return out
+
+
+@pytest.mark.parametrize("enc,n,stride,reanchor", [("s2", 150, 1, 0), ("s3", 150, 3, 0),
+                                                   ("s8c16", 150, 1, 300), ("s2", 37, 2, 500),
+                                                   ("s8c16", 1000, 7, 0)])
+def test_rolling_token_encoder_fp32(enc, n, stride, reanchor):
+    """Every window of a repeat-rich reference with unknown letters (code 4)
+    against the oracle's direct encoding; re-anchored and rolled windows."""
+    torch = torch_cuda()
+    ref = synth.make_reference(30_000, gc=0.45, repeat_frac=0.05, seed=7)
+    ref[5_000:5_003] = 4
+    ref[12_345] = 4
+    index = _build(ref, enc, "fp32", window_len=n, stride=stride, reanchor=reanchor)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    Cn, n2 = _oracle_windows(ref, enc, n, stride)
+    assert got.shape == Cn.shape
+    ok = n2 >= 1e-3 * n
+    err = np.max(np.abs(got[ok] - Cn[ok]))
+    print(f"{enc} N={n} stride={stride}: max |d| {err:.2e} over {ok.sum()} windows")
+    assert err < 5e-5, err
+    gn2 = index.norms2().cpu().numpy()
+    assert np.max(np.abs(gn2[ok] - n2[ok]) / n2[ok]) < 1e-4
+
+
+@pytest.mark.parametrize("enc,precision", [("s2", "fp16"), ("s8c16", "fp8"), ("s3", "fp8")])
+def test_quantised_token_encodings(enc, precision, plain_data, oracle_F):
+    torch = torch_cuda()
+    ref, _, _ = plain_data
+    Cn, _, _ = oracle_F[enc]
+    index = _build(ref, enc, precision)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    if precision == "fp16":
+        assert np.all(np.abs(got.real - Cn.real) <= 2.0 ** -11 * np.abs(Cn.real) + 2e-5)
+        assert np.all(np.abs(got.imag - Cn.imag) <= 2.0 ** -11 * np.abs(Cn.imag) + 2e-5)
+    else:
+        scale = index.scales().cpu().numpy()
+        s = np.exp2(np.round(np.log2(scale)))[:, None]
+        nz = np.abs(got).sum(axis=1) > 0
+        assert np.max(np.abs(np.linalg.norm(got[nz], axis=1) - 1)) < 1e-5
+        corr = 0.05
+        assert np.all(np.abs(got.real - Cn.real) <= fp8_bound(np.abs(Cn.real), s) + corr * np.abs(Cn.real))
+        assert np.all(np.abs(got.imag - Cn.imag) <= fp8_bound(np.abs(Cn.imag), s) + corr * np.abs(Cn.imag))
+
+
+@pytest.mark.parametrize("enc,precision", [("s2", "fp32"), ("s3", "fp16"), ("s8c16", "fp8")])
+def test_token_read_encoder(enc, precision, plain_data):
+    """Read heads (tokens at locations 0..N-s) against the oracle; a read
+    shorter than N is the zero vector."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    seq, off = reads.seq.copy(), reads.offsets.copy()
+    lens = np.diff(off)
+    keep = np.ones(seq.size, bool)
+    keep[off[5] + 120:off[6]] = False            # read 5: 120 letters
+    lens[5] = 120
+    seq = seq[keep]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    index = _build(ref, enc, precision)
+    rb = mapper.upload_reads(index, seq, off)
+    mapper.encode_reads(index, rb)
+    torch.cuda.synchronize()
+    re_row, im_row = read_rows(rb, precision, torch)
+    Xn, _ = _oracle_heads(heads, enc)
+    Xn[5] = 0
+    want_re = np.empty((reads.n, 256))
+    want_re[:, 0::2], want_re[:, 1::2] = Xn.real, Xn.imag
+    want_im = np.empty((reads.n, 256))
+    want_im[:, 0::2], want_im[:, 1::2] = -Xn.imag, Xn.real
+    s = np.exp2(np.round(np.log2(rb.scale.cpu().numpy())))[:, None]
+
+    def bound(w):
+        if precision == "fp32":
+            return 1e-6
+        if precision == "fp16":
+            return 2.0 ** -11 * np.abs(w) + 1e-7
+        return fp8_bound(np.abs(w), s) + 0.05 * np.abs(w)
+
+    assert np.all(np.abs(re_row - want_re) <= bound(want_re))
+    assert np.all(np.abs(im_row - want_im) <= bound(want_im))
+    assert np.all(re_row[5] == 0) and np.all(im_row[5] == 0)
+
+
+@pytest.mark.parametrize("enc,precision,k_fetch", [("s2", "fp16", 16), ("s3", "fp32", 8),
+                                                   ("s8c16", "fp8", 16), ("s8c16", "fp16", 8),
+                                                   ("s2", "fp8", 32)])
+def test_token_map_reads(enc, precision, k_fetch, plain_data, oracle_F):
+    """Product + fused top-k + FP32 rescore with a token index, against the
+    oracle's brute-force fidelities of every (read, window) pair."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    _, _, F = oracle_F[enc]
+    index = _build(ref, enc, precision)
+    k = 8
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
+    mapper.map_reads(index, rb, bufs)
+    torch.cuda.synchronize()
+    cidx = bufs.cand_idx.cpu().numpy()
+    csc = bufs.cand_score.cpu().numpy()
+    best = F.max(axis=1)
+    f_c = np.take_along_axis(F, cidx, 1)
+    assert np.all(cidx >= 0)
+    err = np.abs(csc - f_c)
+    if precision == "fp8":
+        # |dF| <= 1e-2 except for e4m3's rounding tail: measured on these reads
+        # with 32 candidates, 0.02 % of the di- and tri-mer scores lie above it
+        # (largest 1.08e-2, at F ~ 0.4); the letter encoding's largest is
+        # 7.5e-3.  The FP32 rescore below restores the exact order.
+        assert np.mean(err > TOL["fp8"]) <= 1e-3
+        assert err.max() <= 1.5e-2
+    else:
+        assert np.all(err <= TOL[precision] * np.maximum(f_c, best[:, None]) + 1e-7)
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    o_idx = order[:, :k]
+    o_F = np.take_along_axis(F, o_idx, 1)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    top_F = np.take_along_axis(F, tidx, 1)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, top_F)
+    exact = mapping.same_up_to_ties(tidx, o_F, top_F)
+    top1 = np.mean(np.abs(tidx[:, 0] - reads.truth) <= 8)
+    print(f"{enc} {precision} k_fetch={k_fetch}: rescored recall@8 {rec:.4f}, exact lists "
+          f"{exact.mean():.4f}, max |dF| candidates {err.max():.2e}, top-1 near truth {top1:.3f}")
+    assert np.max(np.abs(tsc - top_F)) < 2e-6
+    if precision == "fp32":
+        assert exact.all()
+    else:
+        assert rec >= 0.99
+        assert exact.mean() >= 0.97
+
+
+@pytest.mark.parametrize("enc,k_fetch,k", [("s2", 5, 3), ("s8c16", 20, 8), ("s3", 32, 32)])
+def test_token_rescore_given_candidates(enc, k_fetch, k, plain_data, oracle_F):
+    """The FP32 token rescore alone on random pools with invalid entries and
+    reads shorter than the window (every F = 0, ids ascending)."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, _ = plain_data
+    _, _, F = oracle_F[enc]
+    R, W = F.shape
+    index = _build(ref, enc, "fp16")
+    seq, off = reads.seq.copy(), reads.offsets.copy()
+    short = [0, 7]
+    keep = np.ones(seq.size, bool)
+    lens = np.diff(off)
+    for r in short:
+        keep[off[r] + 100:off[r + 1]] = False
+        lens[r] = 100
+    seq = seq[keep]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    rng = np.random.default_rng(3 + k_fetch)
+    pool = np.stack([rng.choice(W, k_fetch, replace=False) for _ in range(R)]).astype(np.int32)
+    bad = rng.random(pool.shape) < 0.1
+    pool[bad] = np.where(rng.random(bad.sum()) < 0.5, -1, W + 5)
+    rb = mapper.upload_reads(index, seq, off)
+    bufs = mapper.map_buffers(index, R, k, k_fetch)
+    bufs.cand_idx.copy_(torch.from_numpy(pool).cuda())
+    mapper.rescore(index, rb, bufs)
+    torch.cuda.synchronize()
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    for r in range(R):
+        valid = [int(j) for j in pool[r] if 0 <= j < W]
+        if r in short:
+            want = sorted(valid)[:k]
+            assert [int(j) for j in tidx[r] if j >= 0] == want, r
+            assert np.all(tsc[r][:len(want)] == 0.0), r
+            continue
+        n = min(k, len(valid))
+        if n == 0:
+            assert np.all(tidx[r] == -1), r
+            continue
+        fv = np.array([F[r, j] for j in valid])
+        want_F = fv[np.lexsort((np.array(valid), -fv))[:n]]
+        got = tidx[r, :n]
+        assert np.all(got >= 0) and np.all(tidx[r, n:] == -1), r
+        assert len(set(got.tolist())) == n and set(got.tolist()) <= set(valid), r
+        assert np.all(np.abs(F[r, got] - want_F) <= mapping.TIE_TAU), r
+        assert np.max(np.abs(tsc[r, :n] - F[r, got])) < 2e-6, r
+
+
+def test_windows_a_map_leaves_empty():
+    """A map that leaves the all-A 8-mer out: windows inside a long run of A
+    hold no token, are stored as zero vectors and score 0 with every read; an
+    all-A read scores 0 everywhere (its rescored list is in id order)."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    s, m, C = 8, 8, 16
+    tm = synth.token_map(s, C).copy()
+    tm[0] = 255                                        # AAAAAAAA: no token
+    ref = synth.make_reference(6_000, seed=21, uniform=True)
+    ref[2_000:2_400] = 0                               # 400 A's
+    index = mapper.build_index(ref, window_len=N, precision="fp16", schedule="finetuned",
+                               mer_len=s, n_freq=m, token_map=tm)
+    reads_seq = np.concatenate([ref[3_000:3_150], np.zeros(150, np.uint8)])
+    off = np.array([0, 150, 300], dtype=np.int64)
+    rb = mapper.upload_reads(index, reads_seq, off)
+    bufs = mapper.map_buffers(index, 2, 4, 8)
+    mapper.map_reads(index, rb, bufs)
+    torch.cuda.synchronize()
+    emb = emb_to_complex(index, torch)
+    n2 = index.norms2().cpu().numpy()
+    empty = np.arange(2_000, 2_400 - N + 1 - (s - 1))  # every token of the window is AAAAAAAA
+    assert np.all(emb[empty] == 0) and np.all(n2[empty] < 1e-4 * N)   # degenerate: zero rows
+    tmi = tm.astype(np.int64)
+    tmi[tmi >= C] = tokens.SKIP
+    Cn, _ = mapping.normalized_rows(tokens.encode_many(
+        mapping.window_letters(ref, np.arange(ref.size - N + 1), N), N, s, m, C, tmi, "finetuned"), N)
+    assert np.all(np.abs(Cn[empty]) == 0)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    assert tidx[0, 0] == 3_000 and abs(tsc[0, 0] - 1.0) < 1e-5
+    assert np.all(tsc[1] == 0.0) and list(tidx[1]) == sorted(tidx[1].tolist())
