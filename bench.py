@@ -86,6 +86,9 @@ def parse():
                     help="refinement radius in letters (default: coarse stride - 1)")
     ap.add_argument("--corr-pairs", type=int, default=100_000,
                     help="correlation workload: pairs over all mutation rates")
+    ap.add_argument("--tokens", default=None,
+                    help="token encoding (s-mers, compact maps): s2 | s3 | s8c16 "
+                         "(default: the letter encoding)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
     ap.add_argument("--cpu-reads", type=int, default=8)
@@ -159,8 +162,16 @@ def main():
     coarse = args.coarse_stride is not None and args.coarse_stride > 1
     stride = args.coarse_stride if coarse else w.stride
     radius = (args.radius if args.radius is not None else stride - 1) if coarse else 0
+    tok = {}
+    if args.tokens is not None:
+        if coarse:
+            print("--tokens and --coarse-stride do not combine (refinement takes letter indexes)",
+                  file=sys.stderr)
+            sys.exit(2)
+        s_, m_, _, tm_, sched_ = synth.token_encoding(args.tokens)
+        tok = dict(mer_len=s_, n_freq=m_, token_map=tm_, schedule=sched_)
     index = mapper.build_index(ref, window_len=w.window_len, stride=stride, precision=precision,
-                               reanchor=w.reanchor)
+                               reanchor=w.reanchor, **tok)
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
     bufs = mapper.map_buffers(index, R, k, k_fetch)
     refine_ws = None
@@ -214,14 +225,16 @@ def main():
     # ---- accuracy against the FP64 oracle
     # coarse candidates compared by their start (window id x stride)
     cand_start = np.where(cand_idx >= 0, cand_idx.astype(np.int64) * stride, -1)
-    acc = accuracy(w, reads, top_idx, top_score, cand_start, cand_score, k, R)
+    gold = None if args.tokens is None else f"{w.name}_{args.tokens}_top16_sample64.npz"
+    acc = accuracy(w, reads, top_idx, top_score, cand_start, cand_score, k, R, gold)
 
     # ---- dominant kernel: the scoring product (+ its small merge), HIP events
     score_s = parts[2] / 1e3
     achieved = R * W * FLOPS_PER_SCORE / score_s / 1e12
     peak = PEAK_TFLOPS[precision]
     enc_bytes = W * (256 * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
-    traffic = measured_traffic(precision) if R == w.n_reads and not coarse else None
+    traffic = (measured_traffic(precision) if R == w.n_reads and not coarse and not args.tokens
+               else None)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "score_topk_kernel (+merge_kernel)",
@@ -233,8 +246,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp16": "f16", "fp8": "fp8e4m3"}[precision],
         "data": "synthetic",
-        "config": {"workload": describe(w, precision, k, k_fetch, R, stride, radius), "reads": R,
-                   "windows": W, "window_len": w.window_len, "n_freq": w.n_freq,
+        "config": {"workload": describe(w, precision, k, k_fetch, R, stride, radius, args.tokens),
+                   "reads": R, "windows": W, "window_len": w.window_len,
+                   "n_freq": tok.get("n_freq", w.n_freq), "tokens": args.tokens,
                    "stride": stride, "k": k, "k_fetch": k_fetch, "precision": precision},
         "window_scores_per_s": float(f"{R * W / score_s:.4g}"),
         # the same step on an index built beforehand (reads -> product -> rescore)
@@ -250,9 +264,10 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_fp32 and precision != "fp32" and not coarse:
-        out["fp32_path"] = fp32_path(w, ref, reads, k, k_fetch, value)
+        out["fp32_path"] = fp32_path(w, ref, reads, k, k_fetch, value, tok)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, ref, reads, W, args.cpu_reads, args.cpu_windows)
+        out["cpu_baseline"] = cpu_baseline(w, ref, reads, W, args.cpu_reads, args.cpu_windows,
+                                           args.tokens)
     print(json.dumps(out), flush=True)
 
 
@@ -634,11 +649,17 @@ def batching_accuracy(ref, reads, bm, ids, sc, k):
     return res
 
 
-def describe(w, precision, k, k_fetch, R, stride=None, radius=0):
+def describe(w, precision, k, k_fetch, R, stride=None, radius=0, tokens=None):
     stride = w.stride if stride is None else stride
+    enc = f"m={w.n_freq}"
+    if tokens is not None:
+        import synth
+        s, m, C, tm, sched = synth.token_encoding(tokens)
+        enc = (f"{s}-mer tokens" + (f" mapped to {C} classes" if tm is not None else "") +
+               f", m={m}, {sched} factors")
     head = (f"{w.name}: {w.G / 1e6:g} Mbp synthetic reference ({int(w.gc * 100)}% GC, "
             f"{int(w.repeat_frac * 100)}% repeats), {R:,} reads of {w.read_len} bp, N={w.window_len}, "
-            f"m={w.n_freq}, stride {stride}, {precision} index, ")
+            f"{enc}, stride {stride}, {precision} index, ")
     if stride > w.stride:
         return head + (f"top-{k_fetch} coarse windows refined in FP32 over the step-1 windows "
                        f"within {radius} letters, top-{k} kept")
@@ -683,12 +704,12 @@ def accuracy(w, reads, top_idx, top_score, cand_idx, cand_score, k, R, gold_name
     return res
 
 
-def fp32_path(w, ref, reads, k, k_fetch, value_lowp):
+def fp32_path(w, ref, reads, k, k_fetch, value_lowp, tok=None):
     """One timed step of the plain FP32 path (FP32 index and FP32 MFMA product)."""
     import torch
     from paper_2603_22245_amd import mapper
     index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision="fp32",
-                               reanchor=w.reanchor)
+                               reanchor=w.reanchor, **(tok or {}))
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
     bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
     mapper.map_reads(index, rb, bufs)  # warm-up / first launch
@@ -708,10 +729,10 @@ def fp32_path(w, ref, reads, k, k_fetch, value_lowp):
             "note": "read encoding + FP32 MFMA product + top-k + FP32 rescore, prebuilt FP32 index"}
 
 
-def cpu_baseline(w, ref, reads, W, n_reads, n_windows):
+def cpu_baseline(w, ref, reads, W, n_reads, n_windows, tokens_name=None):
     """The FP64 oracle mapping a bounded sample: n_reads read heads against the first
     n_windows windows (direct encoding + brute-force scan), scaled to all windows."""
-    from oracle import mapping
+    from oracle import mapping, tokens
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -720,7 +741,13 @@ def cpu_baseline(w, ref, reads, W, n_reads, n_windows):
     nw = min(n_windows, W)
     heads = mapping.read_heads(reads.seq, reads.offsets, w.window_len)[:n_reads]
     t = time.perf_counter()
-    mapping.map_reads(ref, heads, w.window_len, w.n_freq, w.k, w.stride, window_range=(0, nw))
+    if tokens_name is None:
+        mapping.map_reads(ref, heads, w.window_len, w.n_freq, w.k, w.stride, window_range=(0, nw))
+    else:
+        import synth
+        s, m, C, tm, sched = synth.token_encoding(tokens_name)
+        tokens.map_reads(ref, heads, w.window_len, s, m, C, tm, w.k, w.stride, sched,
+                         window_range=(0, nw))
     dt = time.perf_counter() - t
     v = n_reads / dt * (nw / W)
     log(f"cpu baseline: {n_reads} reads x {nw:,} windows in {dt:.1f}s")

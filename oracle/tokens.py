@@ -129,6 +129,28 @@ def encode_many(strings: np.ndarray, N: int, s: int, m: int, n_class: int, token
     return out.reshape(B, m * n_class)
 
 
+def encode_windows(ref: np.ndarray, starts: np.ndarray, N: int, s: int, m: int, n_class: int,
+                   token_map=None, schedule: str = "default") -> np.ndarray:
+    """Unnormalised encodings of the windows ref[j : j+N] for j in `starts`,
+    complex128 [len(starts), m*n_class]: the token at location p of window j
+    is the reference's token at position j+p, so the reference's token classes
+    are found once and gathered per window (§2.1, §3.1)."""
+    starts = np.asarray(starts, dtype=np.int64)
+    T = N - s + 1
+    if starts.size == 0:
+        return np.zeros((0, m * n_class), dtype=np.complex128)
+    lo, hi = int(starts.min()), int(starts.max()) + N       # the letters the windows cover
+    cls_ref = token_classes(np.asarray(ref)[lo:hi], s, token_map)
+    cls = cls_ref[(starts - lo)[:, None] + np.arange(T)[None, :]]
+    E = rope.unit_phases(N, m, np.arange(T), schedule)
+    Er, Ei = np.ascontiguousarray(E.real), np.ascontiguousarray(E.imag)
+    out = np.empty((cls.shape[0], m, n_class), dtype=np.complex128)
+    for q in range(n_class):
+        ind = (cls == q).astype(np.float64)
+        out[:, :, q] = (ind @ Er) + 1j * (ind @ Ei)
+    return out.reshape(cls.shape[0], m * n_class)
+
+
 def slide(c: np.ndarray, old: int, new: int, N: int, s: int, m: int, n_class: int,
           schedule: str = "default") -> np.ndarray:
     """One-letter slide (§3.4): rotate by omega^-f_k, the outgoing token's class
@@ -162,19 +184,20 @@ def sliding_encodings(ref, N: int, count: int, s: int, m: int, n_class: int, tok
 
 def map_reads(ref: np.ndarray, heads: np.ndarray, N: int, s: int, m: int, n_class: int,
               token_map=None, k: int = 8, stride: int = 1, schedule: str = "default",
-              chunk: int = 32768):
+              chunk: int = 32768, window_range=None):
     """Exact top-k windows of every head by brute force (§3.1) with the token
-    encoding; ordered as in `oracle.mapping`.  Returns (idx [R,k], F [R,k])."""
+    encoding; ordered as in `oracle.mapping`.  Returns (idx [R,k], F [R,k]).
+    `window_range` restricts the scan to window ids [lo, hi)."""
     W = mapping.n_windows(ref.shape[0], N, stride)
+    lo, hi = (0, W) if window_range is None else window_range
     Xn, _ = mapping.normalized_rows(encode_many(heads, N, s, m, n_class, token_map, schedule), N)
     R = Xn.shape[0]
     best_i = np.full((R, 0), -1, dtype=np.int64)
     best_f = np.zeros((R, 0))
-    for a in range(0, W, chunk):
-        b = min(W, a + chunk)
+    for a in range(lo, hi, chunk):
+        b = min(hi, a + chunk)
         ids = np.arange(a, b, dtype=np.int64)
-        Cw = encode_many(mapping.window_letters(ref, ids * stride, N), N, s, m, n_class,
-                         token_map, schedule)
+        Cw = encode_windows(ref, ids * stride, N, s, m, n_class, token_map, schedule)
         Cn, _ = mapping.normalized_rows(Cw, N)
         F = mapping.fidelity_matrix(Xn, Cn)
         best_i, best_f = mapping.topk_rows(np.concatenate([best_f, F], axis=1),

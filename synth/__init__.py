@@ -318,3 +318,19 @@ def token_map(s: int, n_class: int, seed: Optional[int] = None) -> np.ndarray:
     rng = np.random.default_rng(TOKEN_MAP_SEED + s if seed is None else seed)
     n = 4 ** s
     return (rng.permutation(n) % n_class).astype(np.uint8)
+
+
+# Token encodings used by the tests, the stored oracle samples and the
+# benchmark: name -> (s, m, n_class, mapped, schedule).  A mapped encoding
+# takes token_map(s, n_class) as its 4^s-to-n_class table.
+TOKEN_ENCODINGS = {
+    "s2": (2, 8, 16, False, "default"),
+    "s3": (3, 2, 64, False, "finetuned"),
+    "s8c16": (8, 8, 16, True, "finetuned"),
+}
+
+
+def token_encoding(name: str):
+    """(s, m, n_class, table or None, schedule) of a named token encoding."""
+    s, m, C, mapped, sched = TOKEN_ENCODINGS[name]
+    return s, m, C, (token_map(s, C) if mapped else None), sched

@@ -22,11 +22,7 @@ N = 150
 TOL = {"fp32": 1e-5, "fp16": 1e-3, "fp8": 1e-2}
 
 # name -> (s, m, n_class, token map or None, schedule)
-ENC = {
-    "s2": (2, 8, 16, None, "default"),
-    "s3": (3, 2, 64, None, "finetuned"),
-    "s8c16": (8, 8, 16, synth.token_map(8, 16), "finetuned"),
-}
+ENC = {name: synth.token_encoding(name) for name in synth.TOKEN_ENCODINGS}
 
 
 def _build(ref, enc, precision, **kw):

@@ -162,3 +162,17 @@ def test_exact_substring_reads_map_to_their_window(s, m, C, with_map):
     allF = np.array([abs(np.vdot(x, tokens.encode(ref[j:j + N], N, s, m, C, tm))) ** 2
                      for j in range(0, W, 37)])
     assert np.max(allF) <= F[1, 0] + 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(synth.TOKEN_ENCODINGS))
+def test_window_encodings_gathered_from_the_reference(name):
+    """encode_windows (the reference's tokens found once, gathered per window)
+    equals encoding each window's letters, unknown letters included."""
+    s, m, C, tm, sched = synth.token_encoding(name)
+    ref = _rand(2_000)
+    ref[[10, 500, 501, 1999]] = 4
+    N, stride = 60, 3
+    starts = mapping.window_starts(ref.size, N, stride)
+    a = tokens.encode_windows(ref, starts, N, s, m, C, tm, sched)
+    b = tokens.encode_many(mapping.window_letters(ref, starts, N), N, s, m, C, tm, sched)
+    assert np.max(np.abs(a - b)) < 1e-12
