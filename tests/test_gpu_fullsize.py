@@ -2,7 +2,8 @@
 benchmark times, on outputs the oracle can compute one by one or has stored:
 
 * precision (10 Mbp, 100,000 reads, FP16 index, top-8 of 16): stored oracle
-  top-16 lists of 64 sampled reads; sampled index rows and squared norms;
+  top-16 lists of 64 sampled reads; sampled index rows and squared norms; the
+  same with token indexes (2-mers FP16, 8-mers mapped to 16 classes FP8);
 * scale (256 Mbp, FP8 index with FP64 re-anchor every 65,536 starts, top-16 of
   32): sampled index rows (re-anchor boundaries, the last windows), squared
   norms (rolling drift), rescored scores of sampled reads one window at a time,
@@ -139,6 +140,59 @@ def test_precision_workload_full_size(precision):
         for j, sc in zip(ci[r], cs[r]):
             if int(j) in pos:
                 assert abs(float(sc) - of[pos[int(j)]]) <= tol
+    truth = reads.truth // w.stride
+    assert np.mean(np.abs(bufs.top_idx.cpu().numpy()[:, 0] - truth) <= 8) >= 0.99
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("enc,precision", [("s2", "fp16"), ("s8c16", "fp8")])
+def test_precision_workload_token_encoding_full_size(enc, precision):
+    """The precision workload with a token index (§2.1 s-mers, §2.6 compact
+    map), in the benchmark's configuration (top-8 of 16): sampled index rows
+    against the token oracle, and the stored token-oracle lists of 64 reads."""
+    torch = torch_cuda()
+    from oracle import tokens
+    from paper_2603_22245_amd import mapper
+    w = synth.WORKLOADS["precision"]
+    s, m, C, tm, sched = synth.token_encoding(enc)
+    ref = w.reference()
+    reads = w.reads(ref)
+    index = mapper.build_index(ref, w.window_len, w.stride, precision, sched, w.reanchor,
+                               mer_len=s, n_freq=m, token_map=tm)
+    rb, bufs = _map(index, reads, w.k, 16)
+    torch.cuda.synchronize()
+    W = index.n_windows
+    rng = np.random.default_rng(8)
+    rows = np.unique(np.concatenate([[0, 1, W // 2, W - 2, W - 1], rng.choice(W, 40)]))
+    got = _rows(index, rows, torch)
+    want, n2 = mapping.normalized_rows(
+        tokens.encode_windows(ref, rows * w.stride, w.window_len, s, m, C, tm, sched), w.window_len)
+    norms = index.norms2()[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.max(np.abs(norms / n2 - 1)) <= 2e-4
+    for part in (np.real, np.imag):
+        a = np.abs(part(want))
+        if precision == "fp16":
+            assert np.all(np.abs(part(got) - part(want)) <= 2.0 ** -11 * a + 2e-5)
+        else:
+            scale = index.scales()[torch.from_numpy(rows).cuda()].cpu().numpy()
+            sc = np.exp2(np.round(np.log2(scale)))[:, None]
+            assert np.all(np.abs(part(got) - part(want)) <= fp8_bound(a, sc) + 0.05 * a)
+    g = _stored_lists(f"precision_{enc}_top16_sample64.npz")
+    _check_against_stored(g, bufs.top_idx.cpu().numpy(), bufs.top_score.cpu().numpy(), w.k,
+                          exact_min=0.95)
+    ci, cs = bufs.cand_idx.cpu().numpy(), bufs.cand_score.cpu().numpy()
+    errs = []
+    for r, oi, of in zip(g["reads"], g["idx"], g["F"]):
+        pos = {int(j): i for i, j in enumerate(oi)}
+        errs += [abs(float(sc) - of[pos[int(j)]]) for j, sc in zip(ci[r], cs[r]) if int(j) in pos]
+    errs = np.array(errs)
+    tol = {"fp16": 1e-3, "fp8": 1e-2}[precision]
+    print(f"{enc} {precision}: {errs.size} product scores vs stored, max |dF| {errs.max():.2e}, "
+          f"above {tol}: {int(np.sum(errs > tol))}")
+    # FP8: e4m3's rounding tail may put a rare score just above 1e-2
+    assert errs.max() <= (tol if precision == "fp16" else 1.5e-2)
+    assert np.mean(errs > tol) <= 2e-3
     truth = reads.truth // w.stride
     assert np.mean(np.abs(bufs.top_idx.cpu().numpy()[:, 0] - truth) <= 8) >= 0.99
     del index, rb, bufs
