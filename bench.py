@@ -168,8 +168,8 @@ def main():
             print("--tokens and --coarse-stride do not combine (refinement takes letter indexes)",
                   file=sys.stderr)
             sys.exit(2)
-        s_, m_, _, tm_, sched_ = synth.token_encoding(args.tokens)
-        tok = dict(mer_len=s_, n_freq=m_, token_map=tm_, schedule=sched_)
+        s_, m_, c_, tm_, sched_ = synth.token_encoding(args.tokens)
+        tok = dict(mer_len=s_, n_freq=m_, n_class=c_, token_map=tm_, schedule=sched_)
     index = mapper.build_index(ref, window_len=w.window_len, stride=stride, precision=precision,
                                reanchor=w.reanchor, **tok)
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)

@@ -21,6 +21,20 @@ bool letter_encoding(const rm_params* p) {
 
 int mer_of(const rm_params* p) { return p->mer_len > 1 ? p->mer_len : 1; }
 
+// Components per factor: n_class, or 4^s (0 when 4^s exceeds 256).
+int classes_of(const rm_params* p) {
+  const int s = mer_of(p);
+  return p->n_class != 0 ? p->n_class : (s <= 4 ? 1 << (2 * s) : 0);
+}
+
+// A token encoding of 1,024 complex components (FP16 only, own kernels).
+bool wide_encoding(const rm_params* p) {
+  return !letter_encoding(p) && (int64_t)p->n_freq * classes_of(p) == rm::kWideComplex;
+}
+
+// Reals per stored row (and per read-embedding row).
+size_t real_dim(const rm_params* p) { return wide_encoding(p) ? 2 * rm::kWideComplex : rm::kReal; }
+
 bool params_ok(const rm_params* p, int* why) {
   if (p == nullptr) return (*why = RM_EINVAL), false;
   if (p->mer_len < 0 || p->mer_len > RM_MAX_MER) return (*why = RM_ESIZE), false;
@@ -28,9 +42,13 @@ bool params_ok(const rm_params* p, int* why) {
     if (p->n_freq != RM_DIM) return (*why = RM_EUNSUPPORTED), false;
   } else {
     const int s = mer_of(p);
-    const int C = p->n_class != 0 ? p->n_class : (s <= 3 ? 1 << (2 * s) : 0);
-    if (C < 2 || C % 2 != 0 || p->n_freq < 1 || C * p->n_freq != rm::kComplex)
+    const int C = classes_of(p);
+    if (C < 2 || C % 2 != 0 || C > 256 || p->n_freq < 1) return (*why = RM_EUNSUPPORTED), false;
+    if (C * p->n_freq == rm::kWideComplex) {
+      if (C % 16 != 0 || p->precision != RM_FP16) return (*why = RM_EUNSUPPORTED), false;
+    } else if (C * p->n_freq != rm::kComplex) {
       return (*why = RM_EUNSUPPORTED), false;
+    }
     if (p->d_token_map == nullptr && C != (1 << (2 * s))) return (*why = RM_EUNSUPPORTED), false;
     if (p->window_len < s) return (*why = RM_ESIZE), false;
   }
@@ -57,7 +75,7 @@ Layout layout(int64_t W, const rm_params* p) {
   Layout L{};
   size_t off = 0;
   L.emb = off;
-  off = align_up(off + (size_t)W * rm::kReal * rm::elem_bytes(p->precision));
+  off = align_up(off + (size_t)W * real_dim(p) * rm::elem_bytes(p->precision));
   L.scale = off;
   off = align_up(off + (size_t)W * sizeof(float));
   L.norm2 = off;
@@ -167,9 +185,14 @@ static int encode_reference_impl(const uint8_t* d_ref, int64_t ref_len, const rm
   int st = hip_status(rm::launch_tables(*p, idx.d_phase64, idx.d_phase32, idx.d_step32, s));
   if (st != RM_OK) return st;
   if (idx.d_token_class != nullptr) {
-    const int C = 128 / p->n_freq;
+    const bool wide = wide_encoding(p);
+    const int C = (wide ? rm::kWideComplex : rm::kComplex) / p->n_freq;
     st = hip_status(rm::launch_token_table(p->d_token_map, mer_of(p), C, idx.d_token_class, s));
-    if (st == RM_OK)
+    if (st == RM_OK && wide)
+      st = hip_status(rm::launch_encode_reference_wide(d_ref, W, *p, idx.d_phase64, idx.d_step32,
+                                                       idx.d_token_class, idx.d_emb, idx.d_scale,
+                                                       idx.d_norm2, s));
+    else if (st == RM_OK)
       st = hip_status(rm::launch_encode_reference_tokens(d_ref, W, *p, idx.d_phase64,
                                                          idx.d_step32, idx.d_token_class,
                                                          idx.d_emb, idx.d_scale, idx.d_norm2, s));
@@ -188,7 +211,7 @@ static int encode_reference_impl(const uint8_t* d_ref, int64_t ref_len, const rm
 size_t rm_read_emb_bytes(int32_t n_reads, const rm_params* p) {
   int why = RM_OK;
   if (!params_ok(p, &why) || n_reads < 1) return 0;
-  return (size_t)n_reads * 2 * rm::kReal * rm::elem_bytes(p->precision);
+  return (size_t)n_reads * 2 * real_dim(p) * rm::elem_bytes(p->precision);
 }
 
 int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_off,
@@ -198,6 +221,10 @@ int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_
   if (d_seq == nullptr || d_off == nullptr || d_read_emb == nullptr) return RM_EINVAL;
   if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
   if (n_reads < 1) return RM_ESIZE;
+  if (wide_encoding(&idx->p))
+    return hip_status(rm::launch_encode_reads_wide(idx->p, idx->d_phase64, idx->d_token_class,
+                                                   d_seq, d_off, n_reads, d_read_emb, d_read_scale,
+                                                   static_cast<hipStream_t>(stream)));
   if (!letter_encoding(&idx->p))
     return hip_status(rm::launch_encode_reads_tokens(idx->p, idx->d_phase64, idx->d_token_class,
                                                      d_seq, d_off, n_reads, d_read_emb,
@@ -224,12 +251,25 @@ int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int
 }
 
 size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_fetch) {
+  if (idx != nullptr && wide_encoding(&idx->p)) {
+    if (index_ok(idx) != RM_OK || n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return 0;
+    return rm::wide_workspace_bytes(n_reads, idx->n_windows, k_fetch);
+  }
   return rm_score_groups_workspace_bytes(idx, 1, &n_reads, k_fetch, nullptr);
 }
 
 int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
                   int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx, float* d_cand_score,
                   void* d_ws, size_t ws_bytes, void* stream) {
+  if (idx != nullptr && wide_encoding(&idx->p)) {
+    int st = index_ok(idx);
+    if (st != RM_OK) return st;
+    if (!d_read_emb || !d_cand_idx || !d_cand_score || !d_ws) return RM_EINVAL;
+    if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return RM_ESIZE;
+    if (ws_bytes < rm::wide_workspace_bytes(n_reads, idx->n_windows, k_fetch)) return RM_ESIZE;
+    return hip_status(rm::launch_score_wide(*idx, d_read_emb, n_reads, k_fetch, d_cand_idx,
+                                            d_cand_score, d_ws, static_cast<hipStream_t>(stream)));
+  }
   return rm_score_topk_groups(idx, 1, &d_read_emb, &d_read_scale, &n_reads, k_fetch, &d_cand_idx,
                               &d_cand_score, d_ws, ws_bytes, nullptr, stream);
 }
@@ -244,6 +284,10 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
     return RM_EINVAL;
   if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || k < 1 || k > k_fetch)
     return RM_ESIZE;
+  if (wide_encoding(&idx->p))
+    return hip_status(rm::launch_rescore_wide(*idx, d_ref, d_seq, d_off, n_reads, k_fetch,
+                                              d_cand_idx, k, d_top_idx, d_top_score,
+                                              static_cast<hipStream_t>(stream)));
   if (!letter_encoding(&idx->p))
     return hip_status(rm::launch_rescore_tokens(*idx, d_ref, d_seq, d_off, n_reads, k_fetch,
                                                 d_cand_idx, k, d_top_idx, d_top_score,
@@ -365,6 +409,7 @@ static int groups_ok(const rm_index* idx, int32_t n_groups, const int32_t* n_rea
     int st = index_ok(&idx[i]);
     if (st != RM_OK) return st;
     if (idx[i].p.precision != idx[0].p.precision) return RM_EINVAL;
+    if (wide_encoding(&idx[i].p)) return RM_EUNSUPPORTED;  // scored by rm_score_topk only
     if (n_reads[i] < 1) return RM_ESIZE;
   }
   return RM_OK;

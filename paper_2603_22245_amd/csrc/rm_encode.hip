@@ -397,13 +397,13 @@ __global__ __launch_bounds__(256) void encode_reference_tokens_kernel(
   const int64_t in_off = N - s + 1;
   int64_t j = j0;
   int until_emit = stride;
-  int out_c = lane < n_slides ? token_class(ref + s0 + lane, s, table) : RM_TOKEN_SKIP;
-  int in_c = lane < n_slides ? token_class(ref + s0 + lane + in_off, s, table) : RM_TOKEN_SKIP;
+  int out_c = lane < n_slides ? token_class(ref + s0 + lane, s, table) : kNoToken;
+  int in_c = lane < n_slides ? token_class(ref + s0 + lane + in_off, s, table) : kNoToken;
   for (int64_t tb = 0; tb < n_slides; tb += 64) {
     const int64_t tn = tb + 64 + lane;
-    const int out_next = tn < n_slides ? token_class(ref + s0 + tn, s, table) : RM_TOKEN_SKIP;
+    const int out_next = tn < n_slides ? token_class(ref + s0 + tn, s, table) : kNoToken;
     const int in_next =
-        tn < n_slides ? token_class(ref + s0 + tn + in_off, s, table) : RM_TOKEN_SKIP;
+        tn < n_slides ? token_class(ref + s0 + tn + in_off, s, table) : kNoToken;
     const int cnt = (int)min<int64_t>(64, n_slides - tb);
     for (int i = 0; i < cnt; ++i) {
       // classes relative to this lane's c0: 0 or 1 is one of its components

@@ -16,8 +16,13 @@
 
 namespace rm {
 
-// Class of the token starting at p (RM_TOKEN_SKIP if one of its letters is
-// not a code 0..3).
+// "No token here": an s-mer holding a letter outside 0..3, or a location
+// past the end.  Negative, so it matches no component whatever n_class is (a
+// table value >= n_class matches none either; with n_class = 256 every table
+// value is a class).
+constexpr int kNoToken = -1;
+
+// Class of the token starting at p.
 __device__ __forceinline__ int token_class(const uint8_t* __restrict__ p, int s,
                                            const uint8_t* __restrict__ table) {
   uint32_t code = 0;
@@ -27,7 +32,7 @@ __device__ __forceinline__ int token_class(const uint8_t* __restrict__ p, int s,
     ok = ok && L < 4u;
     code = code * 4u + (L & 3u);
   }
-  return ok ? (int)table[code] : RM_TOKEN_SKIP;
+  return ok ? (int)table[code] : kNoToken;
 }
 
 // Direct sum over the tokens at locations 0..T-1 of `str` of this lane's two
@@ -42,7 +47,7 @@ __device__ __forceinline__ void direct_sum_tokens(const uint8_t* __restrict__ st
   a0.x = 0; a0.y = 0;
   a1.x = 0; a1.y = 0;
   for (int pb = 0; pb < T; pb += 64) {
-    const int mine = (pb + lane < T) ? token_class(str + pb + lane, s, table) : RM_TOKEN_SKIP;
+    const int mine = (pb + lane < T) ? token_class(str + pb + lane, s, table) : kNoToken;
     const int cnt = min(64, T - pb);
     // groups of 8 locations with their table loads in flight together; a
     // location past the end re-reads the last row and has no token
@@ -63,7 +68,8 @@ __device__ __forceinline__ void direct_sum_tokens(const uint8_t* __restrict__ st
 }
 
 // table[code] for code < 4^s: the caller's map with values >= n_class set to
-// RM_TOKEN_SKIP, or the identity when map is NULL.
+// RM_TOKEN_SKIP (a value no lane's classes include when n_class <= 128), or the
+// identity when map is NULL.
 hipError_t launch_token_table(const uint8_t* map, int s, int n_class, uint8_t* table,
                               hipStream_t st);
 
@@ -75,6 +81,33 @@ hipError_t launch_encode_reference_tokens(const uint8_t* ref, int64_t W, const r
 hipError_t launch_encode_reads_tokens(const rm_params& p, const double* phase64,
                                       const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                       int32_t n_reads, void* emb, float* scale, hipStream_t st);
+
+// Encodings of 1,024 complex components (16 per lane), FP16 only.
+constexpr int kWideComplex = 1024;
+constexpr int kWideMaxChunks = 16;  // window chunks per read tile (merge reads <= 16 x 32 keys)
+
+struct WidePlan {
+  int n_rt;             // read tiles of 64 reads
+  int64_t n_tiles;      // window tiles of 128
+  int64_t chunk_tiles;  // window tiles per chunk
+  int n_chunks;
+};
+WidePlan plan_wide(int32_t n_reads, int64_t W);
+size_t wide_workspace_bytes(int32_t n_reads, int64_t W, int32_t k_fetch);
+hipError_t launch_encode_reference_wide(const uint8_t* ref, int64_t W, const rm_params& p,
+                                        const double* phase64, const float* step32,
+                                        const uint8_t* table, void* emb, float* scale,
+                                        float* norm2, hipStream_t st);
+hipError_t launch_encode_reads_wide(const rm_params& p, const double* phase64,
+                                    const uint8_t* table, const uint8_t* seq, const int64_t* off,
+                                    int32_t n_reads, void* emb, float* scale, hipStream_t st);
+hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, int32_t n_reads,
+                             int32_t k_fetch, int32_t* cand_idx, float* cand_score, void* ws,
+                             hipStream_t st);
+hipError_t launch_rescore_wide(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
+                               const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                               const int32_t* cand_idx, int32_t k, int32_t* top_idx,
+                               float* top_score, hipStream_t st);
 
 hipError_t launch_rescore_tokens(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                                  const int64_t* off, int32_t n_reads, int32_t k_fetch,

@@ -1,0 +1,570 @@
+// Token encodings with 1,024 complex components (§2.1 s-mers, §2.6 compact
+// versions): e.g. 8-mers mapped to 256 classes with m = 4 -- the encoding the
+// paper maps with (§3.5) -- or 4-mers with m = 4.  FP16 storage only.
+//
+// Lane layout: lane l owns the 16 complex components [16 l, 16 l + 16), i.e.
+// factor k = 16 l / n_class and classes c0 .. c0 + 15 with c0 = 16 l mod
+// n_class (n_class a multiple of 16), stored at reals [32 l, 32 l + 32) of the
+// 2,048-real row (re, im interleaved per component).
+//
+// The product has K = 2,048, too long to keep a read tile in registers as the
+// 256-real scoring kernel does, so here both operands stream through LDS:
+// block tiles of 128 A rows (64 reads) x 128 windows, K in stages of 32
+// (double-buffered), four wavefronts of 64 x 64 outputs on 32x32x16 FP16
+// MFMAs.  Per tile the epilogue writes F = Re^2 + Im^2 of every (read, window)
+// to LDS and each wavefront compares 16 reads' scores with their current
+// k-th best; the (rare) hits are inserted into the read's sorted list held in
+// LDS.  A block walks the window tiles of one chunk and writes each read's
+// list; a merge kernel keeps the k best over the chunks.
+#include "rm_tokens.h"
+
+namespace rm {
+
+namespace {
+
+constexpr int kWC = 16;     // complex components per lane
+constexpr int kWR = 2048;   // reals per row
+constexpr int kTM = 128;    // A rows per block tile (64 reads)
+constexpr int kTN = 128;    // windows per block tile
+constexpr int kTK = 32;     // K (halves) per stage
+constexpr int kRow = kTK + 8;  // LDS row in halves (80 bytes: rows land on different banks)
+constexpr int kStages = kWR / kTK;
+constexpr int kListMax = RM_MAX_KFETCH;
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ---- encoders ---------------------------------------------------------------
+
+// Direct sum over the tokens at locations 0..T-1 of `str`: the lane's 16
+// components (class c0 + q gets phase[loc][k] for every token of that class).
+template <typename T, typename E2>
+__device__ __forceinline__ void wide_direct_sum(const uint8_t* __restrict__ str, int T_, int s,
+                                                const uint8_t* __restrict__ table,
+                                                const E2* __restrict__ phase, int m, int k, int c0,
+                                                int lane, T (&re)[kWC], T (&im)[kWC]) {
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) re[q] = im[q] = 0;
+  for (int pb = 0; pb < T_; pb += 64) {
+    const int mine = (pb + lane < T_) ? token_class(str + pb + lane, s, table) : kNoToken;
+    const int cnt = min(64, T_ - pb);
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      E2 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = phase[(int64_t)min(pb + i0 + u, T_ - 1) * m + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = __builtin_amdgcn_readlane(mine, i0 + u) - c0;
+#pragma unroll
+        for (int q = 0; q < kWC; ++q) {
+          re[q] += (c == q) ? (T)e[u].x : (T)0;
+          im[q] += (c == q) ? (T)e[u].y : (T)0;
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t pack_h2(float a, float b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+}
+
+// One FP16 row: 32 reals per lane (x_q re, im for q = 0..15), 64 bytes.
+__device__ __forceinline__ void store_wide_row(_Float16* __restrict__ base, int64_t row, int lane,
+                                               const float (&re)[kWC], const float (&im)[kWC],
+                                               float mul) {
+  uint4* dst = reinterpret_cast<uint4*>(base + row * kWR) + lane * 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int q = 4 * v;
+    dst[v] = make_uint4(pack_h2(re[q] * mul, im[q] * mul), pack_h2(re[q + 1] * mul, im[q + 1] * mul),
+                        pack_h2(re[q + 2] * mul, im[q + 2] * mul),
+                        pack_h2(re[q + 3] * mul, im[q + 3] * mul));
+  }
+}
+
+__device__ __forceinline__ void emit_wide(int64_t j, int lane, int N, const float (&re)[kWC],
+                                          const float (&im)[kWC], _Float16* __restrict__ emb,
+                                          float* __restrict__ scale, float* __restrict__ norm2) {
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) acc += re[q] * re[q] + im[q] * im[q];
+  const float n2 = wave_sum(acc);
+  const bool deg = n2 < kDegenerateRel * (float)N;
+  const float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);
+  store_wide_row(emb, j, lane, re, im, inv);
+  if (lane == 0) {
+    norm2[j] = n2;
+    scale[j] = 1.f;
+  }
+}
+
+// Rolling window encoder (§3.4) with tokens, as the 128-component token
+// encoder: FP64 re-anchor at each segment start, then one-letter slides in
+// FP32 (rotate by omega^-f, the token at the old start loses omega^-f after
+// the rotation, the token ending at the new last letter gains omega^(f (N-s))).
+__global__ __launch_bounds__(256) void encode_reference_wide_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int s, int m, int n_class,
+    int64_t seg_len, int64_t n_seg, const double2* __restrict__ phase64,
+    const float4* __restrict__ step32, const uint8_t* __restrict__ table,
+    _Float16* __restrict__ emb, float* __restrict__ scale, float* __restrict__ norm2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (seg >= n_seg) return;
+  const int k = kWC * lane / n_class, c0 = kWC * lane - k * n_class;
+  const int T = N - s + 1;
+  const int64_t j0 = seg * seg_len;
+  const int64_t j1 = min(W, j0 + seg_len);
+
+  float re[kWC], im[kWC];
+  {
+    double dr[kWC], di[kWC];
+    wide_direct_sum(ref + j0 * stride, T, s, table, phase64, m, k, c0, lane, dr, di);
+#pragma unroll
+    for (int q = 0; q < kWC; ++q) {
+      re[q] = (float)dr[q];
+      im[q] = (float)di[q];
+    }
+  }
+  emit_wide(j0, lane, N, re, im, emb, scale, norm2);
+
+  const float4 st = step32[k];
+  const float rr = st.x, ri = st.y;  // omega^-f
+  const float ir = st.z, ii = st.w;  // omega^(f (N-s))
+  const int64_t s0 = j0 * stride;
+  const int64_t n_slides = (j1 - 1 - j0) * stride;
+  const int64_t in_off = N - s + 1;
+  int64_t j = j0;
+  int until_emit = stride;
+  int out_c = lane < n_slides ? token_class(ref + s0 + lane, s, table) : kNoToken;
+  int in_c = lane < n_slides ? token_class(ref + s0 + lane + in_off, s, table) : kNoToken;
+  for (int64_t tb = 0; tb < n_slides; tb += 64) {
+    const int64_t tn = tb + 64 + lane;
+    const int out_next = tn < n_slides ? token_class(ref + s0 + tn, s, table) : kNoToken;
+    const int in_next =
+        tn < n_slides ? token_class(ref + s0 + tn + in_off, s, table) : kNoToken;
+    const int cnt = (int)min<int64_t>(64, n_slides - tb);
+    for (int i = 0; i < cnt; ++i) {
+      const int o = __builtin_amdgcn_readlane(out_c, i) - c0;
+      const int n = __builtin_amdgcn_readlane(in_c, i) - c0;
+#pragma unroll
+      for (int q = 0; q < kWC; ++q) {
+        const float a = re[q] * rr - im[q] * ri;
+        const float b = re[q] * ri + im[q] * rr;
+        re[q] = a - (o == q ? rr : 0.f) + (n == q ? ir : 0.f);
+        im[q] = b - (o == q ? ri : 0.f) + (n == q ? ii : 0.f);
+      }
+      if (--until_emit == 0) {
+        until_emit = stride;
+        ++j;
+        emit_wide(j, lane, N, re, im, emb, scale, norm2);
+      }
+    }
+    out_c = out_next;
+    in_c = in_next;
+  }
+}
+
+// Read heads: FP64 direct sum, normalised; rows 2r = (Re x, Im x) and
+// 2r+1 = (-Im x, Re x) per component, as for the 128-component encodings.
+__global__ __launch_bounds__(256) void encode_reads_wide_kernel(
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
+    int s, int m, int n_class, const double2* __restrict__ phase64,
+    const uint8_t* __restrict__ table, _Float16* __restrict__ emb, float* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= n_reads) return;
+  const int k = kWC * lane / n_class, c0 = kWC * lane - k * n_class;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  double dr[kWC], di[kWC];
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) dr[q] = di[q] = 0.0;
+  if (len >= N) wide_direct_sum(seq + start, N - s + 1, s, table, phase64, m, k, c0, lane, dr, di);
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) acc += dr[q] * dr[q] + di[q] * di[q];
+  const double X = wave_sum(acc);
+  const double inv = X < (double)kDegenerateRel * N ? 0.0 : 1.0 / sqrt(X);
+  float xr[kWC], xi[kWC], nxi[kWC];
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) {
+    xr[q] = (float)(dr[q] * inv);
+    xi[q] = (float)(di[q] * inv);
+    nxi[q] = -xi[q];
+  }
+  store_wide_row(emb, 2 * r, lane, xr, xi, 1.f);
+  store_wide_row(emb, 2 * r + 1, lane, nxi, xr, 1.f);
+  if (scale != nullptr && lane == 0) scale[r] = 1.f;
+}
+
+// ---- product + per-read top-k -------------------------------------------------
+
+__device__ __forceinline__ uint64_t wide_key(float F, int64_t j) {
+  return ((uint64_t)(__float_as_uint(F) + 1u) << 32) | (0xffffffffu - (uint32_t)j);
+}
+
+// Work item b = (read tile b % n_rt, window chunk b / n_rt): window tiles
+// [chunk * chunk_tiles, min(n_tiles, (chunk + 1) * chunk_tiles)).  Writes the
+// k_fetch best keys of each of the tile's reads over the chunk to
+// part[read][chunk][0..k_fetch) (0 = empty).
+__global__ __launch_bounds__(256, 2) void score_wide_kernel(
+    const _Float16* __restrict__ A, int32_t n_reads, const _Float16* __restrict__ B, int64_t W,
+    int n_rt, int64_t n_tiles, int64_t chunk_tiles, int n_chunks, int k_fetch,
+    uint64_t* __restrict__ part) {
+  // two stages of A (kTM rows) and B (kTN rows), then reused as the epilogue's
+  // F buffer [64 reads][kTN windows]
+  __shared__ __attribute__((aligned(16))) _Float16 stage[2][kTM + kTN][kRow];
+  __shared__ uint64_t lists[kTM / 2][kListMax];
+  static_assert(sizeof(float) * (kTM / 2) * kTN <= sizeof(_Float16) * 2 * (kTM + kTN) * kRow,
+                "F buffer fits in the stages");
+  float* Fbuf = reinterpret_cast<float*>(&stage[0][0][0]);
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;  // this wavefront's 64 rows x 64 windows
+  const int rt = blockIdx.x % n_rt, chunk = blockIdx.x / n_rt;
+  const int64_t row0 = (int64_t)rt * kTM;  // first A row (= 2 x first read)
+  const int64_t M = 2 * (int64_t)n_reads;
+  const int64_t t0 = (int64_t)chunk * chunk_tiles;
+  const int64_t t1 = min(n_tiles, t0 + chunk_tiles);
+
+  for (int i = tid; i < (kTM / 2) * kListMax; i += 256) (&lists[0][0])[i] = 0;
+
+  // global -> LDS copy assignment: 16-byte piece q = tid + 256 i (i = 0..3) of
+  // a stage; pieces 0..511 are A rows (4 per row), 512..1023 B rows
+  auto load_stage = [&](int64_t tile, int st, uint4 (&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      const int rr = q >> 2, part16 = q & 3;
+      const _Float16* src = nullptr;
+      if (rr < kTM) {
+        const int64_t g = row0 + rr;
+        if (g < M) src = A + g * kWR + st * kTK + part16 * 8;
+      } else {
+        const int64_t g = tile * kTN + (rr - kTM);
+        if (g < W) src = B + g * kWR + st * kTK + part16 * 8;
+      }
+      v[i] = src != nullptr ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto store_stage = [&](int buf, const uint4 (&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&stage[buf][q >> 2][(q & 3) * 8]) = v[i];
+    }
+  };
+
+  for (int64_t tile = t0; tile < t1; ++tile) {
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[f][g][v] = 0.f;
+
+    uint4 pre[4];
+    load_stage(tile, 0, pre);
+    store_stage(0, pre);
+    __syncthreads();
+    for (int st = 0; st < kStages; ++st) {
+      const int buf = st & 1;
+      if (st + 1 < kStages) load_stage(tile, st + 1, pre);
+#pragma unroll
+      for (int ks = 0; ks < kTK / 16; ++ks) {
+        const int kk = ks * 16 + 8 * (lane >> 5);
+        half8 a[2], b[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+          a[f] = *reinterpret_cast<const half8*>(&stage[buf][64 * wr + 32 * f + (lane & 31)][kk]);
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+          b[g] = *reinterpret_cast<const half8*>(
+              &stage[buf][kTM + 64 * wc + 32 * g + (lane & 31)][kk]);
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+          for (int g = 0; g < 2; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[f], b[g], acc[f][g], 0, 0, 0);
+      }
+      if (st + 1 < kStages) store_stage(buf ^ 1, pre);
+      __syncthreads();
+    }
+
+    // ---- epilogue: F of every (read, window) of the tile into LDS.  Output
+    // element v of a 32x32 block is row 8(v/4) + 4(lane/32) + v%4, column
+    // lane%32; rows 2q and 2q+1 (v even, v+1) are a read's Re and Im.
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const int row = 64 * wr + 32 * f + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          const int col = 64 * wc + 32 * g + (lane & 31);
+          const float re = acc[f][g][v], im = acc[f][g][v + 1];
+          Fbuf[(row >> 1) * kTN + col] = re * re + im * im;
+        }
+    __syncthreads();
+
+    // ---- per read: compare with the k-th best, insert the hits (wavefront w
+    // takes reads w, w + 4, ...; two windows per lane)
+    for (int rl = wave; rl < kTM / 2; rl += 4) {
+      const int64_t r = row0 / 2 + rl;
+      if (r >= n_reads) break;  // uniform
+      const uint64_t th = lists[rl][k_fetch - 1];
+      uint64_t key[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = lane + 64 * h;
+        const int64_t j = tile * kTN + col;
+        key[h] = j < W ? wide_key(Fbuf[rl * kTN + col], j) : 0;
+      }
+      uint64_t hit0 = __ballot(key[0] > th), hit1 = __ballot(key[1] > th);
+      if ((hit0 | hit1) == 0) continue;
+      uint64_t cur = lane < k_fetch ? lists[rl][lane] : 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint64_t hits = h == 0 ? hit0 : hit1;
+        while (hits != 0) {
+          const int src = __builtin_ctzll(hits);
+          hits &= hits - 1;
+          const uint64_t kn = __shfl(key[h], src, 64);
+          // position = entries that beat it; shift the rest down one lane
+          const int pos = __popcll(__ballot(lane < k_fetch && cur > kn));
+          if (pos >= k_fetch) continue;  // uniform
+          const uint64_t up = __shfl_up(cur, 1, 64);
+          cur = lane < pos ? cur : (lane == pos ? kn : up);
+        }
+      }
+      if (lane < k_fetch) lists[rl][lane] = cur;
+    }
+    __syncthreads();  // before the next tile's first stage overwrites Fbuf
+  }
+
+  // ---- the chunk's list of every read of the tile
+  for (int rl = wave; rl < kTM / 2; rl += 4) {
+    const int64_t r = row0 / 2 + rl;
+    if (r >= n_reads) break;
+    if (lane < k_fetch) part[(r * n_chunks + chunk) * k_fetch + lane] = lists[rl][lane];
+  }
+}
+
+// One wavefront per read: the k_fetch best of its n_chunks lists (keys are
+// distinct: the chunks hold disjoint windows).
+__global__ __launch_bounds__(256) void merge_wide_kernel(const uint64_t* __restrict__ part,
+                                                         int32_t n_reads, int n, int k_fetch,
+                                                         int32_t* __restrict__ cand_idx,
+                                                         float* __restrict__ cand_score) {
+  constexpr int EMAX = 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n_reads) return;
+  const uint64_t* src = part + r * n;
+  uint64_t mine[EMAX];
+#pragma unroll
+  for (int e = 0; e < EMAX; ++e) {
+    const int i = e * 64 + lane;
+    mine[e] = i < n ? src[i] : 0;
+  }
+  uint64_t res = 0;
+  for (int out = 0; out < k_fetch; ++out) {
+    uint64_t best = 0;
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e) best = mine[e] > best ? mine[e] : best;
+    const uint64_t g = wave_max_u64(best);
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e)
+      if (g != 0 && mine[e] == g) mine[e] = 0;
+    if (lane == out) res = g;
+  }
+  if (lane < k_fetch) {
+    const uint32_t hi = (uint32_t)(res >> 32);
+    cand_idx[r * k_fetch + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)res) : -1;
+    cand_score[r * k_fetch + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
+  }
+}
+
+// ---- FP32 rescore -------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t shfl_xor64w(uint64_t v, int d) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
+  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Four wavefronts per read: the head summed a quarter of its token locations
+// per wavefront (quarters added in a fixed order), the candidates
+// interleaved, every encoding a direct FP32 sum over its tokens; then the
+// keys are sorted and the k best written.
+__global__ __launch_bounds__(256) void rescore_wide_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int s, int m, int n_class,
+    const float2* __restrict__ phase32, const uint8_t* __restrict__ table,
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t R, int k_fetch,
+    const int32_t* __restrict__ cand, int k, int32_t* __restrict__ top_idx,
+    float* __restrict__ top_score) {
+  __shared__ float part[4][2 * kWC][64];
+  __shared__ uint64_t keys[RM_MAX_KFETCH];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r = blockIdx.x;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  const int T = N - s + 1;
+  const int kf = kWC * lane / n_class, c0 = kWC * lane - kf * n_class;
+
+  float xr[kWC], xi[kWC];
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) xr[q] = xi[q] = 0.f;
+  if (len >= N) {
+    const int q0 = wave * T / 4, q1 = (wave + 1) * T / 4;
+    wide_direct_sum(seq + start + q0, q1 - q0, s, table, phase32 + (int64_t)q0 * m, m, kf, c0,
+                    lane, xr, xi);
+  }
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) {
+    part[wave][2 * q][lane] = xr[q];
+    part[wave][2 * q + 1][lane] = xi[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) {
+    xr[q] = ((part[0][2 * q][lane] + part[1][2 * q][lane]) + part[2][2 * q][lane]) +
+            part[3][2 * q][lane];
+    xi[q] = ((part[0][2 * q + 1][lane] + part[1][2 * q + 1][lane]) + part[2][2 * q + 1][lane]) +
+            part[3][2 * q + 1][lane];
+  }
+  float ax = 0.f;
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) ax += xr[q] * xr[q] + xi[q] * xi[q];
+  const float X = wave_sum(ax);
+  const bool xdeg = X < kDegenerateRel * (float)N;
+
+  for (int e = wave; e < k_fetch; e += 4) {
+    const int32_t j = cand[r * k_fetch + e];
+    uint64_t key = 0;
+    if (j >= 0 && j < W) {  // uniform per wavefront
+      float cr[kWC], ci[kWC];
+      wide_direct_sum(ref + (int64_t)j * stride, T, s, table, phase32, m, kf, c0, lane, cr, ci);
+      float ac = 0.f, pr = 0.f, pi = 0.f;
+#pragma unroll
+      for (int q = 0; q < kWC; ++q) {
+        ac += cr[q] * cr[q] + ci[q] * ci[q];
+        pr += xr[q] * cr[q] + xi[q] * ci[q];  // <x|c> = sum conj(x) c
+        pi += xr[q] * ci[q] - xi[q] * cr[q];
+      }
+      const float C = wave_sum(ac), ipr = wave_sum(pr), ipi = wave_sum(pi);
+      const bool deg = xdeg || C < kDegenerateRel * (float)N;
+      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+      key = wide_key(F, j);
+    }
+    if (lane == 0) keys[e] = key;
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  uint64_t key = lane < k_fetch ? keys[lane] : 0;
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+    for (int d = kk >> 1; d > 0; d >>= 1) {
+      const uint64_t other = shfl_xor64w(key, d);
+      const bool desc_block = (lane & kk) == 0;
+      const bool lower = (lane & d) == 0;
+      const uint64_t mx = key > other ? key : other;
+      const uint64_t mn = key > other ? other : key;
+      key = (lower == desc_block) ? mx : mn;
+    }
+  }
+  if (lane < k) {
+    const uint32_t hi = (uint32_t)(key >> 32);
+    top_idx[r * k + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
+    top_score[r * k + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
+  }
+}
+
+}  // namespace
+
+WidePlan plan_wide(int32_t n_reads, int64_t W) {
+  WidePlan p{};
+  p.n_rt = (int)(((int64_t)n_reads * 2 + kTM - 1) / kTM);
+  p.n_tiles = (W + kTN - 1) / kTN;
+  // enough items for two blocks per compute unit several times over
+  int64_t c = (4096 + p.n_rt - 1) / p.n_rt;
+  if (c > kWideMaxChunks) c = kWideMaxChunks;
+  if (c > p.n_tiles) c = p.n_tiles;
+  if (c < 1) c = 1;
+  p.chunk_tiles = (p.n_tiles + c - 1) / c;
+  p.n_chunks = (int)((p.n_tiles + p.chunk_tiles - 1) / p.chunk_tiles);
+  return p;
+}
+
+size_t wide_workspace_bytes(int32_t n_reads, int64_t W, int32_t k_fetch) {
+  const WidePlan p = plan_wide(n_reads, W);
+  return ((size_t)n_reads * p.n_chunks * k_fetch * sizeof(uint64_t) + 255) / 256 * 256;
+}
+
+hipError_t launch_encode_reference_wide(const uint8_t* ref, int64_t W, const rm_params& p,
+                                        const double* phase64, const float* step32,
+                                        const uint8_t* table, void* emb, float* scale,
+                                        float* norm2, hipStream_t st) {
+  int64_t seg = p.reanchor;
+  if (seg <= 0) {
+    seg = (W + 8191) / 8192;
+    if (seg < 256) seg = 256;
+    if (seg > 4096) seg = 4096;
+  }
+  const int64_t n_seg = (W + seg - 1) / seg;
+  const int64_t blocks = (n_seg + 3) / 4;
+  hipLaunchKernelGGL(encode_reference_wide_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ref,
+                     W, p.window_len, p.stride, p.mer_len > 1 ? p.mer_len : 1, p.n_freq,
+                     kWideComplex / p.n_freq, seg, n_seg, reinterpret_cast<const double2*>(phase64),
+                     reinterpret_cast<const float4*>(step32), table,
+                     static_cast<_Float16*>(emb), scale, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_reads_wide(const rm_params& p, const double* phase64,
+                                    const uint8_t* table, const uint8_t* seq, const int64_t* off,
+                                    int32_t n_reads, void* emb, float* scale, hipStream_t st) {
+  hipLaunchKernelGGL(encode_reads_wide_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)),
+                     dim3(256), 0, st, seq, off, n_reads, p.window_len,
+                     p.mer_len > 1 ? p.mer_len : 1, p.n_freq, kWideComplex / p.n_freq,
+                     reinterpret_cast<const double2*>(phase64), table,
+                     static_cast<_Float16*>(emb), scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, int32_t n_reads,
+                             int32_t k_fetch, int32_t* cand_idx, float* cand_score, void* ws,
+                             hipStream_t st) {
+  const WidePlan p = plan_wide(n_reads, idx.n_windows);
+  uint64_t* part = static_cast<uint64_t*>(ws);
+  hipLaunchKernelGGL(score_wide_kernel, dim3((unsigned)((int64_t)p.n_rt * p.n_chunks)), dim3(256),
+                     0, st, static_cast<const _Float16*>(read_emb), n_reads,
+                     static_cast<const _Float16*>(idx.d_emb), idx.n_windows, p.n_rt, p.n_tiles,
+                     p.chunk_tiles, p.n_chunks, k_fetch, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(merge_wide_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0,
+                     st, part, n_reads, p.n_chunks * k_fetch, k_fetch, cand_idx, cand_score);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescore_wide(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
+                               const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                               const int32_t* cand_idx, int32_t k, int32_t* top_idx,
+                               float* top_score, hipStream_t st) {
+  hipLaunchKernelGGL(rescore_wide_kernel, dim3((unsigned)n_reads), dim3(256), 0, st, ref,
+                     idx.n_windows, idx.p.window_len, idx.p.stride,
+                     idx.p.mer_len > 1 ? idx.p.mer_len : 1, idx.p.n_freq,
+                     kWideComplex / idx.p.n_freq, reinterpret_cast<const float2*>(idx.d_phase32),
+                     idx.d_token_class, seq, off, n_reads, k_fetch, cand_idx, k, top_idx,
+                     top_score);
+  return hipGetLastError();
+}
+
+}  // namespace rm

@@ -35,14 +35,20 @@ class Index:
     def n_windows(self) -> int:
         return int(self.idx.n_windows)
 
+    @property
+    def real_dim(self) -> int:
+        """Reals per stored row: 256, or 2 n_class m for a token encoding."""
+        p = self.params
+        return 2 * p.n_class * p.n_freq if p.n_class else 256
+
     def embeddings(self):
-        """The stored [W, 256] embeddings as a torch view (float32/float16/uint8)."""
+        """The stored [W, real_dim] embeddings as a torch view (float32/float16/uint8)."""
         torch = _torch()
-        W = self.n_windows
+        W, D = self.n_windows, self.real_dim
         dt = {L.RM_FP32: torch.float32, L.RM_FP16: torch.float16, L.RM_FP8_E4M3: torch.uint8}
         dtype = dt[self.params.precision]
         esz = torch.tensor([], dtype=dtype).element_size()
-        return self.buf[: W * 256 * esz].view(dtype).view(W, 256)
+        return self.buf[: W * D * esz].view(dtype).view(W, D)
 
     def scales(self):
         off = self.idx.d_scale - self.buf.data_ptr()
@@ -63,27 +69,32 @@ def _delta_buffer(n_letters: int, device):
 
 def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", schedule="default",
                 reanchor=0, stream=None, device="cuda", learned=None, mer_len=1,
-                n_freq=None, token_map=None) -> Index:
+                n_freq=None, token_map=None, n_class=None) -> Index:
     """Encode the reference's windows.  learned: network parameters (10,432
     FP32 values, numpy or device tensor) for the learned encoding, else plain.
 
-    Token encodings (s-mers): mer_len = s, n_freq = m (default 128 / 4^s, or
-    128 / n_class with a map) and token_map = None (class = s-mer code) or a
-    table of 4^s classes (uint8; RM_TOKEN_SKIP or any value >= 128 / m leaves an
-    s-mer out)."""
+    Token encodings (s-mers): mer_len = s, token_map = None (class = s-mer
+    code, n_class = 4^s) or a table of 4^s classes (uint8; a value >= n_class
+    leaves an s-mer out), n_class (default 4^s without a map, 128 / n_freq
+    with one) and n_freq = m (default 128 / n_class, or 1024 / n_class for
+    n_class above 64).  n_class * n_freq is 128 (every precision) or 1,024
+    (FP16)."""
     torch = _torch()
     d_map = None
-    n_class = 0
+    token = mer_len > 1 or token_map is not None or n_class is not None
     if token_map is not None:
         d_map = torch.as_tensor(np.ascontiguousarray(token_map, dtype=np.uint8)).to(device)
         if d_map.numel() != 4 ** mer_len:
             raise ValueError(f"token_map must have 4^{mer_len} entries")
+        if n_freq is None and n_class is None:
+            raise ValueError("n_freq or n_class is required with a token map")
+    if not token:
+        n_class, n_freq = 0, L.RM_DIM if n_freq is None else n_freq
+    else:
+        if n_class is None:
+            n_class = 4 ** mer_len if token_map is None else 128 // n_freq
         if n_freq is None:
-            raise ValueError("n_freq is required with a token map")
-    if n_freq is None:
-        n_freq = L.RM_DIM if mer_len <= 1 else max(1, 128 // 4 ** mer_len)
-    if mer_len > 1 or token_map is not None:
-        n_class = 128 // n_freq
+            n_freq = max(1, (128 if n_class <= 64 else 1024) // n_class)
     p = L.make_params(window_len, stride, n_freq, schedule, precision, reanchor, mer_len, n_class,
                       d_map)
     if isinstance(ref, np.ndarray):

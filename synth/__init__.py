@@ -313,8 +313,8 @@ def token_map(s: int, n_class: int, seed: Optional[int] = None) -> np.ndarray:
     uniformly random assignment of the 4^s s-mer codes to n_class classes in
     which every class receives the same number of s-mers (4^s / n_class, or
     one more for the first 4^s mod n_class classes).  uint8 [4^s]."""
-    if not 1 <= n_class <= 255:
-        raise ValueError("n_class must be in 1..255")
+    if not 1 <= n_class <= 256:
+        raise ValueError("n_class must be in 1..256")
     rng = np.random.default_rng(TOKEN_MAP_SEED + s if seed is None else seed)
     n = 4 ** s
     return (rng.permutation(n) % n_class).astype(np.uint8)
@@ -327,6 +327,11 @@ TOKEN_ENCODINGS = {
     "s2": (2, 8, 16, False, "default"),
     "s3": (3, 2, 64, False, "finetuned"),
     "s8c16": (8, 8, 16, True, "finetuned"),
+    # 1,024 complex components (FP16): 4-mers with m = 4, and 8-mers mapped to
+    # 256 classes with m = 4 and fine-tuned factors (the paper's s = 8, m = 4,
+    # t = 4 shape)
+    "s4m4": (4, 4, 256, False, "default"),
+    "s8c256": (8, 4, 256, True, "finetuned"),
 }
 
 

@@ -14,7 +14,7 @@ def torch_cuda():
 
 
 def emb_to_complex(index, torch):
-    """Stored window embeddings -> dequantised complex [W, 128] (float64)."""
+    """Stored window embeddings -> dequantised complex [W, components] (float64)."""
     e = index.embeddings()
     if e.dtype == torch.uint8:
         vals = e.cpu().view(torch.float8_e4m3fn).to(torch.float32).numpy().astype(np.float64)
@@ -25,14 +25,14 @@ def emb_to_complex(index, torch):
 
 
 def read_rows(reads, precision, torch):
-    """Read-embedding buffer -> (row Re, row Im) as float64 [R, 256] each, dequantised."""
+    """Read-embedding buffer -> (row Re, row Im) as float64 [R, reals per row] each, dequantised."""
     n = reads.n
     if precision == "fp32":
-        v = reads.emb.view(torch.float32).view(n, 2, 256).cpu().numpy().astype(np.float64)
+        v = reads.emb.view(torch.float32).view(n, 2, -1).cpu().numpy().astype(np.float64)
     elif precision == "fp16":
-        v = reads.emb.view(torch.float16).view(n, 2, 256).float().cpu().numpy().astype(np.float64)
+        v = reads.emb.view(torch.float16).view(n, 2, -1).float().cpu().numpy().astype(np.float64)
     else:
-        v = reads.emb.view(n, 2, 256).cpu().view(torch.float8_e4m3fn).to(torch.float32).numpy()
+        v = reads.emb.view(n, 2, -1).cpu().view(torch.float8_e4m3fn).to(torch.float32).numpy()
         v = v.astype(np.float64) * reads.scale.cpu().numpy().astype(np.float64)[:, None, None]
     return v[:, 0], v[:, 1]
 

@@ -159,7 +159,7 @@ def test_precision_workload_token_encoding_full_size(enc, precision):
     ref = w.reference()
     reads = w.reads(ref)
     index = mapper.build_index(ref, w.window_len, w.stride, precision, sched, w.reanchor,
-                               mer_len=s, n_freq=m, token_map=tm)
+                               mer_len=s, n_freq=m, n_class=C, token_map=tm)
     rb, bufs = _map(index, reads, w.k, 16)
     torch.cuda.synchronize()
     W = index.n_windows

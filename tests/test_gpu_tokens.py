@@ -30,7 +30,7 @@ def _build(ref, enc, precision, **kw):
     torch_cuda()
     s, m, C, tm, sched = ENC[enc]
     return mapper.build_index(ref, window_len=kw.pop("window_len", N), precision=precision,
-                              schedule=sched, mer_len=s, n_freq=m, token_map=tm, **kw)
+                              schedule=sched, mer_len=s, n_freq=m, n_class=C, token_map=tm, **kw)
 
 
 def _oracle_windows(ref, enc, n=N, stride=1):
@@ -280,3 +280,143 @@ def test_windows_a_map_leaves_empty():
     tsc = bufs.top_score.cpu().numpy()
     assert tidx[0, 0] == 3_000 and abs(tsc[0, 0] - 1.0) < 1e-5
     assert np.all(tsc[1] == 0.0) and list(tidx[1]) == sorted(tidx[1].tolist())
+
+
+# ---- 1,024 complex components (FP16): the product with K = 2,048 -------------
+
+@pytest.mark.parametrize("enc,n,stride,reanchor", [("s4m4", 150, 1, 0), ("s8c256", 150, 1, 300),
+                                                   ("s8c256", 1000, 7, 0), ("s4m4", 37, 2, 500)])
+def test_rolling_wide_encoder_fp16(enc, n, stride, reanchor):
+    """Every window of a repeat-rich reference with unknown letters against
+    the oracle, for the 1,024-component encodings (16 components per lane)."""
+    torch = torch_cuda()
+    ref = synth.make_reference(30_000, gc=0.45, repeat_frac=0.05, seed=7)
+    ref[5_000:5_003] = 4
+    ref[12_345] = 4
+    index = _build(ref, enc, "fp16", window_len=n, stride=stride, reanchor=reanchor)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    Cn, n2 = _oracle_windows(ref, enc, n, stride)
+    assert got.shape == Cn.shape == (index.n_windows, 1024)
+    ok = n2 >= 1e-3 * n
+    for part in (np.real, np.imag):
+        a = np.abs(part(Cn[ok]))
+        assert np.all(np.abs(part(got[ok]) - part(Cn[ok])) <= 2.0 ** -11 * a + 2e-5)
+    gn2 = index.norms2().cpu().numpy()
+    assert np.max(np.abs(gn2[ok] - n2[ok]) / n2[ok]) < 1e-4
+    print(f"{enc} N={n} stride={stride}: max |d| {np.max(np.abs(got[ok] - Cn[ok])):.2e}")
+
+
+@pytest.mark.parametrize("enc", ["s4m4", "s8c256"])
+def test_wide_read_encoder(enc, plain_data):
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    seq, off = reads.seq.copy(), reads.offsets.copy()
+    lens = np.diff(off)
+    keep = np.ones(seq.size, bool)
+    keep[off[3] + 140:off[4]] = False            # read 3: 140 letters, no head
+    lens[3] = 140
+    seq = seq[keep]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    index = _build(ref, enc, "fp16")
+    rb = mapper.upload_reads(index, seq, off)
+    mapper.encode_reads(index, rb)
+    torch.cuda.synchronize()
+    re_row, im_row = read_rows(rb, "fp16", torch)
+    Xn, _ = _oracle_heads(heads, enc)
+    Xn[3] = 0
+    want_re = np.empty((reads.n, 2048))
+    want_re[:, 0::2], want_re[:, 1::2] = Xn.real, Xn.imag
+    want_im = np.empty((reads.n, 2048))
+    want_im[:, 0::2], want_im[:, 1::2] = -Xn.imag, Xn.real
+    assert np.all(np.abs(re_row - want_re) <= 2.0 ** -11 * np.abs(want_re) + 1e-7)
+    assert np.all(np.abs(im_row - want_im) <= 2.0 ** -11 * np.abs(want_im) + 1e-7)
+    assert np.all(re_row[3] == 0) and np.all(im_row[3] == 0)
+
+
+@pytest.mark.parametrize("enc,k_fetch", [("s4m4", 16), ("s8c256", 16), ("s8c256", 32),
+                                         ("s4m4", 1)])
+def test_wide_map_reads(enc, k_fetch, plain_data, oracle_F):
+    """The K = 2,048 product with its per-read top-k, then the FP32 rescore,
+    against the oracle's fidelities of every (read, window) pair: 200 reads
+    (400 rows: a ragged last tile of 16 rows) x 19,851 windows (a ragged last
+    tile of 11 windows), 16 window chunks."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    _, _, F = oracle_F[enc]
+    index = _build(ref, enc, "fp16")
+    k = min(8, k_fetch)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
+    mapper.map_reads(index, rb, bufs)
+    torch.cuda.synchronize()
+    cidx = bufs.cand_idx.cpu().numpy()
+    csc = bufs.cand_score.cpu().numpy()
+    assert np.all(cidx >= 0) and np.all(np.diff(csc, axis=1) <= 0)
+    assert all(len(set(row.tolist())) == k_fetch for row in cidx)
+    f_c = np.take_along_axis(F, cidx, 1)
+    best = F.max(axis=1)
+    err = np.abs(csc - f_c)
+    assert np.all(err <= 1e-3 * np.maximum(f_c, best[:, None]) + 1e-7)
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    # the product's list is the FP16 top-k_fetch: every oracle window scoring
+    # clearly above the list's last entry is in it
+    for r in range(F.shape[0]):
+        last = f_c[r].min()
+        must = order[r, :k_fetch][F[r, order[r, :k_fetch]] > last + 2e-3 * best[r]]
+        assert set(must.tolist()) <= set(cidx[r].tolist()), r
+    o_idx = order[:, :k]
+    o_F = np.take_along_axis(F, o_idx, 1)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    top_F = np.take_along_axis(F, tidx, 1)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, top_F)
+    exact = mapping.same_up_to_ties(tidx, o_F, top_F)
+    top1 = np.mean(np.abs(tidx[:, 0] - reads.truth) <= 8)
+    print(f"{enc} k_fetch={k_fetch}: recall@{k} {rec:.4f}, exact lists {exact.mean():.4f}, "
+          f"max |dF| candidates {err.max():.2e}, top-1 near truth {top1:.3f}")
+    assert np.max(np.abs(tsc - top_F)) < 2e-6
+    assert rec >= 0.99 and exact.mean() >= 0.97
+
+
+def test_wide_rescore_given_candidates(plain_data, oracle_F):
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, _ = plain_data
+    _, _, F = oracle_F["s8c256"]
+    R, W = F.shape
+    k_fetch, k = 20, 8
+    index = _build(ref, "s8c256", "fp16")
+    rng = np.random.default_rng(17)
+    pool = np.stack([rng.choice(W, k_fetch, replace=False) for _ in range(R)]).astype(np.int32)
+    bad = rng.random(pool.shape) < 0.1
+    pool[bad] = np.where(rng.random(bad.sum()) < 0.5, -1, W + 5)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, R, k, k_fetch)
+    bufs.cand_idx.copy_(torch.from_numpy(pool).cuda())
+    mapper.rescore(index, rb, bufs)
+    torch.cuda.synchronize()
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    for r in range(R):
+        valid = [int(j) for j in pool[r] if 0 <= j < W]
+        n = min(k, len(valid))
+        fv = np.array([F[r, j] for j in valid])
+        want_F = fv[np.lexsort((np.array(valid), -fv))[:n]]
+        got = tidx[r, :n]
+        assert np.all(got >= 0) and np.all(tidx[r, n:] == -1), r
+        assert set(got.tolist()) <= set(valid), r
+        assert np.all(np.abs(F[r, got] - want_F) <= mapping.TIE_TAU), r
+        assert np.max(np.abs(tsc[r, :n] - F[r, got])) < 2e-6, r
+
+
+def test_wide_encodings_are_fp16_only():
+    from paper_2603_22245_amd import _lib as L
+    torch_cuda()
+    ref = synth.make_reference(2_000, seed=3, uniform=True)
+    for precision in ("fp32", "fp8"):
+        with pytest.raises(L.RotorMapError):
+            _build(ref, "s4m4", precision)
