@@ -170,6 +170,13 @@ def main():
             sys.exit(2)
         s_, m_, c_, tm_, sched_ = synth.token_encoding(args.tokens)
         tok = dict(mer_len=s_, n_freq=m_, n_class=c_, token_map=tm_, schedule=sched_)
+        if c_ * m_ != 128 and precision != "fp16":
+            print("encodings of 1,024 components are FP16 only", file=sys.stderr)
+            sys.exit(2)
+    # reals per stored row: 256, or 2,048 for the 1,024-component token encodings
+    real_dim = 2 * tok["n_class"] * tok["n_freq"] if tok else 256
+    wide = real_dim != 256
+    flops_per_score = 4 * real_dim
     index = mapper.build_index(ref, window_len=w.window_len, stride=stride, precision=precision,
                                reanchor=w.reanchor, **tok)
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
@@ -230,15 +237,16 @@ def main():
 
     # ---- dominant kernel: the scoring product (+ its small merge), HIP events
     score_s = parts[2] / 1e3
-    achieved = R * W * FLOPS_PER_SCORE / score_s / 1e12
+    achieved = R * W * flops_per_score / score_s / 1e12
     peak = PEAK_TFLOPS[precision]
-    enc_bytes = W * (256 * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
+    enc_bytes = W * (real_dim * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
     traffic = (measured_traffic(precision) if R == w.n_reads and not coarse and not args.tokens
                else None)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "score_topk_kernel (+merge_kernel)",
-                "algorithmic": f"{FLOPS_PER_SCORE} flops per (read, window) score x {R} x {W}"}
+                "kernel": ("score_wide_kernel (+merge_wide_kernel)" if wide
+                           else "score_topk_kernel (+merge_kernel)"),
+                "algorithmic": f"{flops_per_score} flops per (read, window) score x {R} x {W}"}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "reads/s", "n_gpus": 1,
@@ -263,7 +271,7 @@ def main():
     del index, rb, bufs
     torch.cuda.empty_cache()
 
-    if not args.no_fp32 and precision != "fp32" and not coarse:
+    if not args.no_fp32 and precision != "fp32" and not coarse and not wide:
         out["fp32_path"] = fp32_path(w, ref, reads, k, k_fetch, value, tok)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, ref, reads, W, args.cpu_reads, args.cpu_windows,

@@ -143,11 +143,14 @@ def encode_windows(ref: np.ndarray, starts: np.ndarray, N: int, s: int, m: int, 
     cls_ref = token_classes(np.asarray(ref)[lo:hi], s, token_map)
     cls = cls_ref[(starts - lo)[:, None] + np.arange(T)[None, :]]
     E = rope.unit_phases(N, m, np.arange(T), schedule)
-    Er, Ei = np.ascontiguousarray(E.real), np.ascontiguousarray(E.imag)
-    out = np.empty((cls.shape[0], m, n_class), dtype=np.complex128)
-    for q in range(n_class):
-        ind = (cls == q).astype(np.float64)
-        out[:, :, q] = (ind @ Er) + 1j * (ind @ Ei)
+    # location by location: each window's token at p adds omega^(f_k p) to
+    # its class's component of every factor k (one token per window and p)
+    out = np.zeros((cls.shape[0], m, n_class), dtype=np.complex128)
+    rows = np.arange(cls.shape[0])
+    for p in range(T):
+        c = cls[:, p]
+        ok = (c >= 0) & (c < n_class)
+        out[rows[ok], :, c[ok]] += E[p]
     return out.reshape(cls.shape[0], m * n_class)
 
 

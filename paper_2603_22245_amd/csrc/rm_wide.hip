@@ -9,9 +9,12 @@
 //
 // The product has K = 2,048, too long to keep a read tile in registers as the
 // 256-real scoring kernel does, so here both operands stream through LDS:
-// block tiles of 128 A rows (64 reads) x 128 windows, K in stages of 32
-// (double-buffered), four wavefronts of 64 x 64 outputs on 32x32x16 FP16
-// MFMAs.  Per tile the epilogue writes F = Re^2 + Im^2 of every (read, window)
+// block tiles of 128 A rows (64 reads) x 256 windows, K in stages of 64
+// copied straight from global memory into a ring of three LDS stages (two in
+// flight while one is computed), eight wavefronts of 64 x 64 outputs on
+// 32x32x16 FP16 MFMAs.  (Each block's read rows are re-read for every window
+// tile while the window rows are shared by the blocks of a chunk through L2,
+// hence the wide window tile.)  Per tile the epilogue writes F = Re^2 + Im^2 of every (read, window)
 // to LDS and each wavefront compares 16 reads' scores with their current
 // k-th best; the (rare) hits are inserted into the read's sorted list held in
 // LDS.  A block walks the window tiles of one chunk and writes each read's
@@ -24,12 +27,16 @@ namespace {
 
 constexpr int kWC = 16;     // complex components per lane
 constexpr int kWR = 2048;   // reals per row
-constexpr int kTM = 128;    // A rows per block tile (64 reads)
-constexpr int kTN = 128;    // windows per block tile
-constexpr int kTK = 32;     // K (halves) per stage
-constexpr int kRow = kTK + 8;  // LDS row in halves (80 bytes: rows land on different banks)
+constexpr int kWM = 2;              // wavefronts along the rows
+constexpr int kWN = 4;              // wavefronts along the windows
+constexpr int kWaves = kWM * kWN;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTM = 64 * kWM;       // A rows per block tile (kTM / 2 reads)
+constexpr int kTN = 64 * kWN;       // windows per block tile
+constexpr int kTK = 64;     // K (halves) per stage: one 128-byte line of every row
 constexpr int kStages = kWR / kTK;
 constexpr int kListMax = RM_MAX_KFETCH;
+
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -205,56 +212,95 @@ __device__ __forceinline__ uint64_t wide_key(float F, int64_t j) {
   return ((uint64_t)(__float_as_uint(F) + 1u) << 32) | (0xffffffffu - (uint32_t)j);
 }
 
+// LDS byte offset of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const void*)p);
+}
+
+// Asynchronous copy of 16 bytes per lane from global memory straight into LDS
+// (gfx950 global_load_lds_dwordx4): lane l writes LDS bytes [lds + 16 l,
+// lds + 16 l + 16).  No output register; completion is awaited with
+// wait_vm<N>(), which counts this wavefront's vector-memory operations in
+// issue order.
+__device__ __forceinline__ void dma16w(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
+               : "memory", "m0");
+}
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// A stage in LDS: kTM + kTN rows (the A rows, then the window rows) of 128
+// bytes (64 halves of K); row r keeps its 16-byte chunk c at position
+// c ^ ((r / 2) % 8), so that the rows a group of lanes reads at once (the same
+// chunk of consecutive rows) fall on different banks.
+constexpr int kStageBytes = (kTM + kTN) * kTK * 2;  // 48 KB
+constexpr int kChunks = kTK / 8;                     // 16-byte chunks per row
+constexpr int kRowsPerBankRow = 128 / kTK;           // rows per 256 bytes of LDS banks
+constexpr int kRing = 3;                             // stages in LDS (two in flight)
+constexpr int kDmaPerWave = (kTM + kTN) * kChunks / (64 * kWaves);  // copies per lane per stage
+static_assert(kDmaPerWave * 64 * kWaves == (kTM + kTN) * kChunks, "stage splits into whole copies");
+static_assert((kRing - 2) * kDmaPerWave <= 63, "vmcnt range");
+
+__device__ __forceinline__ int swz(int row) { return (row / kRowsPerBankRow) % kChunks; }
+__device__ __forceinline__ uint32_t chunk_pos(int row, int c) {
+  return (uint32_t)(row * (kTK * 2) + 16 * (c ^ swz(row)));
+}
+
 // Work item b = (read tile b % n_rt, window chunk b / n_rt): window tiles
 // [chunk * chunk_tiles, min(n_tiles, (chunk + 1) * chunk_tiles)).  Writes the
 // k_fetch best keys of each of the tile's reads over the chunk to
 // part[read][chunk][0..k_fetch) (0 = empty).
-__global__ __launch_bounds__(256, 2) void score_wide_kernel(
+__global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
     const _Float16* __restrict__ A, int32_t n_reads, const _Float16* __restrict__ B, int64_t W,
     int n_rt, int64_t n_tiles, int64_t chunk_tiles, int n_chunks, int k_fetch,
     uint64_t* __restrict__ part) {
-  // two stages of A (kTM rows) and B (kTN rows), then reused as the epilogue's
-  // F buffer [64 reads][kTN windows]
-  __shared__ __attribute__((aligned(16))) _Float16 stage[2][kTM + kTN][kRow];
+  // the stage ring, reused by the epilogue as the F buffer [kTM / 2 reads][kTN]
+  __shared__ __attribute__((aligned(1024))) uint8_t ring[kRing][kStageBytes];
   __shared__ uint64_t lists[kTM / 2][kListMax];
-  static_assert(sizeof(float) * (kTM / 2) * kTN <= sizeof(_Float16) * 2 * (kTM + kTN) * kRow,
-                "F buffer fits in the stages");
-  float* Fbuf = reinterpret_cast<float*>(&stage[0][0][0]);
+  static_assert(sizeof(float) * (kTM / 2) * kTN <= sizeof(ring), "F buffer fits in the ring");
+  float* Fbuf = reinterpret_cast<float*>(&ring[0][0]);
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;  // this wavefront's 64 rows x 64 windows
+  const int wr = wave / kWN, wc = wave % kWN;  // this wavefront's 64 rows x 64 windows
   const int rt = blockIdx.x % n_rt, chunk = blockIdx.x / n_rt;
   const int64_t row0 = (int64_t)rt * kTM;  // first A row (= 2 x first read)
   const int64_t M = 2 * (int64_t)n_reads;
   const int64_t t0 = (int64_t)chunk * chunk_tiles;
   const int64_t t1 = min(n_tiles, t0 + chunk_tiles);
+  const uint32_t ring_lds = lds_addr(&ring[0][0]);
 
-  for (int i = tid; i < (kTM / 2) * kListMax; i += 256) (&lists[0][0])[i] = 0;
+  for (int i = tid; i < (kTM / 2) * kListMax; i += kThreads) (&lists[0][0])[i] = 0;
 
-  // global -> LDS copy assignment: 16-byte piece q = tid + 256 i (i = 0..3) of
-  // a stage; pieces 0..511 are A rows (4 per row), 512..1023 B rows
-  auto load_stage = [&](int64_t tile, int st, uint4 (&v)[4]) {
+  // This lane's 16-byte pieces of a stage: piece p = 64 (wave + kWaves i) +
+  // lane lands at LDS position p (row p / kChunks, position p % kChunks) and
+  // holds chunk (p % kChunks) ^ swz(row) of that row.  Rows past the last read or
+  // window re-read the last one (always in bounds); their scores are never
+  // used.
+  int64_t src_off[kDmaPerWave];  // element offset of the piece's row and chunk, K stage 0
+  bool is_b[kDmaPerWave];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + 256 * i;
-      const int rr = q >> 2, part16 = q & 3;
-      const _Float16* src = nullptr;
-      if (rr < kTM) {
-        const int64_t g = row0 + rr;
-        if (g < M) src = A + g * kWR + st * kTK + part16 * 8;
+  for (int i = 0; i < kDmaPerWave; ++i) {
+    const int p = 64 * (wave + kWaves * i) + lane;
+    const int row = p / kChunks;
+    const int c = (p % kChunks) ^ swz(row);
+    is_b[i] = row >= kTM;
+    src_off[i] = (is_b[i] ? (int64_t)(row - kTM) : min(row0 + row, M - 1)) * kWR + c * 8;
+  }
+  auto issue = [&](int64_t tile, int st) {
+    const uint32_t base = ring_lds + (uint32_t)(st % kRing) * kStageBytes;
+#pragma unroll
+    for (int i = 0; i < kDmaPerWave; ++i) {
+      const _Float16* src;
+      if (is_b[i]) {
+        const int64_t g = min(tile * kTN + src_off[i] / kWR, W - 1);
+        src = B + g * kWR + (src_off[i] % kWR) + st * kTK;
       } else {
-        const int64_t g = tile * kTN + (rr - kTM);
-        if (g < W) src = B + g * kWR + st * kTK + part16 * 8;
+        src = A + src_off[i] + st * kTK;
       }
-      v[i] = src != nullptr ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
-    }
-  };
-  auto store_stage = [&](int buf, const uint4 (&v)[4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + 256 * i;
-      *reinterpret_cast<uint4*>(&stage[buf][q >> 2][(q & 3) * 8]) = v[i];
+      dma16w(src, __builtin_amdgcn_readfirstlane(base + 1024 * (wave + kWaves * i)));
     }
   };
 
@@ -267,33 +313,39 @@ __global__ __launch_bounds__(256, 2) void score_wide_kernel(
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[f][g][v] = 0.f;
 
-    uint4 pre[4];
-    load_stage(tile, 0, pre);
-    store_stage(0, pre);
-    __syncthreads();
+    // stages st .. st + kRing - 2 are in flight; one barrier per stage: after
+    // it every wavefront's copies of stage st have landed and every wavefront
+    // has finished reading stage st - 1, whose ring slot the copies of stage
+    // st + kRing - 1 then overwrite
+#pragma unroll
+    for (int u = 0; u < kRing - 1; ++u) issue(tile, u);
     for (int st = 0; st < kStages; ++st) {
-      const int buf = st & 1;
-      if (st + 1 < kStages) load_stage(tile, st + 1, pre);
+      if (st + kRing - 2 < kStages) wait_vm<(kRing - 2) * kDmaPerWave>(); else wait_vm<0>();
+      __syncthreads();
+      if (st + kRing - 1 < kStages) issue(tile, st + kRing - 1);
+      const uint8_t* sb = &ring[st % kRing][0];
 #pragma unroll
       for (int ks = 0; ks < kTK / 16; ++ks) {
-        const int kk = ks * 16 + 8 * (lane >> 5);
+        const int c = 2 * ks + (lane >> 5);  // this lane's 8 halves of the 16-K step
         half8 a[2], b[2];
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
-          a[f] = *reinterpret_cast<const half8*>(&stage[buf][64 * wr + 32 * f + (lane & 31)][kk]);
+        for (int f = 0; f < 2; ++f) {
+          const int row = 64 * wr + 32 * f + (lane & 31);
+          a[f] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
+        }
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-          b[g] = *reinterpret_cast<const half8*>(
-              &stage[buf][kTM + 64 * wc + 32 * g + (lane & 31)][kk]);
+        for (int g = 0; g < 2; ++g) {
+          const int row = kTM + 64 * wc + 32 * g + (lane & 31);
+          b[g] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
+        }
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
           for (int g = 0; g < 2; ++g)
             acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[f], b[g], acc[f][g], 0, 0, 0);
       }
-      if (st + 1 < kStages) store_stage(buf ^ 1, pre);
-      __syncthreads();
     }
+    __syncthreads();  // every wavefront is done with the ring before it becomes the F buffer
 
     // ---- epilogue: F of every (read, window) of the tile into LDS.  Output
     // element v of a 32x32 block is row 8(v/4) + 4(lane/32) + v%4, column
@@ -312,24 +364,26 @@ __global__ __launch_bounds__(256, 2) void score_wide_kernel(
     __syncthreads();
 
     // ---- per read: compare with the k-th best, insert the hits (wavefront w
-    // takes reads w, w + 4, ...; two windows per lane)
-    for (int rl = wave; rl < kTM / 2; rl += 4) {
+    // takes reads w, w + kWaves, ...; kTN / 64 windows per lane)
+    constexpr int kH = kTN / 64;
+    for (int rl = wave; rl < kTM / 2; rl += kWaves) {
       const int64_t r = row0 / 2 + rl;
       if (r >= n_reads) break;  // uniform
       const uint64_t th = lists[rl][k_fetch - 1];
-      uint64_t key[2];
+      uint64_t key[kH], hit[kH], any = 0;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kH; ++h) {
         const int col = lane + 64 * h;
         const int64_t j = tile * kTN + col;
         key[h] = j < W ? wide_key(Fbuf[rl * kTN + col], j) : 0;
+        hit[h] = __ballot(key[h] > th);
+        any |= hit[h];
       }
-      uint64_t hit0 = __ballot(key[0] > th), hit1 = __ballot(key[1] > th);
-      if ((hit0 | hit1) == 0) continue;
+      if (any == 0) continue;
       uint64_t cur = lane < k_fetch ? lists[rl][lane] : 0;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint64_t hits = h == 0 ? hit0 : hit1;
+      for (int h = 0; h < kH; ++h) {
+        uint64_t hits = hit[h];
         while (hits != 0) {
           const int src = __builtin_ctzll(hits);
           hits &= hits - 1;
@@ -347,7 +401,7 @@ __global__ __launch_bounds__(256, 2) void score_wide_kernel(
   }
 
   // ---- the chunk's list of every read of the tile
-  for (int rl = wave; rl < kTM / 2; rl += 4) {
+  for (int rl = wave; rl < kTM / 2; rl += kWaves) {
     const int64_t r = row0 / 2 + rl;
     if (r >= n_reads) break;
     if (lane < k_fetch) part[(r * n_chunks + chunk) * k_fetch + lane] = lists[rl][lane];
@@ -492,8 +546,8 @@ WidePlan plan_wide(int32_t n_reads, int64_t W) {
   WidePlan p{};
   p.n_rt = (int)(((int64_t)n_reads * 2 + kTM - 1) / kTM);
   p.n_tiles = (W + kTN - 1) / kTN;
-  // enough items for two blocks per compute unit several times over
-  int64_t c = (4096 + p.n_rt - 1) / p.n_rt;
+  // enough items for one block per compute unit ten times over
+  int64_t c = (2560 + p.n_rt - 1) / p.n_rt;
   if (c > kWideMaxChunks) c = kWideMaxChunks;
   if (c > p.n_tiles) c = p.n_tiles;
   if (c < 1) c = 1;
@@ -543,7 +597,7 @@ hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, int32_t 
                              hipStream_t st) {
   const WidePlan p = plan_wide(n_reads, idx.n_windows);
   uint64_t* part = static_cast<uint64_t*>(ws);
-  hipLaunchKernelGGL(score_wide_kernel, dim3((unsigned)((int64_t)p.n_rt * p.n_chunks)), dim3(256),
+  hipLaunchKernelGGL(score_wide_kernel, dim3((unsigned)((int64_t)p.n_rt * p.n_chunks)), dim3(kThreads),
                      0, st, static_cast<const _Float16*>(read_emb), n_reads,
                      static_cast<const _Float16*>(idx.d_emb), idx.n_windows, p.n_rt, p.n_tiles,
                      p.chunk_tiles, p.n_chunks, k_fetch, part);
