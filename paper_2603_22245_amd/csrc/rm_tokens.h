@@ -91,6 +91,8 @@ struct WidePlan {
   int64_t n_tiles;      // window tiles of 128
   int64_t chunk_tiles;  // window tiles per chunk
   int n_chunks;
+  int n_quads;          // groups of 4 chunks
+  int64_t n_blocks;     // grid size
 };
 WidePlan plan_wide(int32_t n_reads, int64_t W);
 size_t wide_workspace_bytes(int32_t n_reads, int64_t W, int32_t k_fetch);

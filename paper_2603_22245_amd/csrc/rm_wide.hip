@@ -36,6 +36,8 @@ constexpr int kTN = 64 * kWN;       // windows per block tile
 constexpr int kTK = 64;     // K (halves) per stage: one 128-byte line of every row
 constexpr int kStages = kWR / kTK;
 constexpr int kListMax = RM_MAX_KFETCH;
+constexpr int kGroupTiles = 8;   // read tiles per group of 32 blocks on one XCD
+constexpr int kGroupChunks = 4;  // window chunks per group
 
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -248,13 +250,17 @@ __device__ __forceinline__ uint32_t chunk_pos(int row, int c) {
   return (uint32_t)(row * (kTK * 2) + 16 * (c ^ swz(row)));
 }
 
-// Work item b = (read tile b % n_rt, window chunk b / n_rt): window tiles
-// [chunk * chunk_tiles, min(n_tiles, (chunk + 1) * chunk_tiles)).  Writes the
-// k_fetch best keys of each of the tile's reads over the chunk to
-// part[read][chunk][0..k_fetch) (0 = empty).
+// Work items are (read tile, window chunk); a chunk is the window tiles
+// [chunk * chunk_tiles, min(n_tiles, (chunk + 1) * chunk_tiles)).  Blocks go
+// to the eight XCDs in turn (block b on XCD b % 8), so the 32 blocks i =
+// 32 g' .. 32 g' + 31 of XCD x (i = b / 8) run side by side and share that
+// XCD's L2: they take group G = 8 g' + x of 8 read tiles x 4 chunks, so every
+// read tile's rows are streamed by 4 blocks and every chunk's window rows by 8
+// blocks at about the same time.  Writes the k_fetch best keys of each of the
+// tile's reads over the chunk to part[read][chunk][0..k_fetch) (0 = empty).
 __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
     const _Float16* __restrict__ A, int32_t n_reads, const _Float16* __restrict__ B, int64_t W,
-    int n_rt, int64_t n_tiles, int64_t chunk_tiles, int n_chunks, int k_fetch,
+    int n_rt, int64_t n_tiles, int64_t chunk_tiles, int n_chunks, int n_quads, int k_fetch,
     uint64_t* __restrict__ part) {
   // the stage ring, reused by the epilogue as the F buffer [kTM / 2 reads][kTN]
   __shared__ __attribute__((aligned(1024))) uint8_t ring[kRing][kStageBytes];
@@ -265,7 +271,11 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / kWN, wc = wave % kWN;  // this wavefront's 64 rows x 64 windows
-  const int rt = blockIdx.x % n_rt, chunk = blockIdx.x / n_rt;
+  const int xcd = blockIdx.x % 8, i_x = blockIdx.x / 8;
+  const int group = (i_x / 32) * 8 + xcd, j_g = i_x % 32;
+  const int rt = (group / n_quads) * kGroupTiles + j_g / kGroupChunks;
+  const int chunk = (group % n_quads) * kGroupChunks + j_g % kGroupChunks;
+  if (rt >= n_rt || chunk >= n_chunks) return;  // the whole block, before any barrier
   const int64_t row0 = (int64_t)rt * kTM;  // first A row (= 2 x first read)
   const int64_t M = 2 * (int64_t)n_reads;
   const int64_t t0 = (int64_t)chunk * chunk_tiles;
@@ -546,13 +556,17 @@ WidePlan plan_wide(int32_t n_reads, int64_t W) {
   WidePlan p{};
   p.n_rt = (int)(((int64_t)n_reads * 2 + kTM - 1) / kTM);
   p.n_tiles = (W + kTN - 1) / kTN;
-  // enough items for one block per compute unit ten times over
-  int64_t c = (2560 + p.n_rt - 1) / p.n_rt;
+  // chunks per read tile: one group's worth (4), more when there are few read
+  // tiles (enough items for the 256 compute units several times over)
+  int64_t c = kGroupChunks * ((2560 / p.n_rt + kGroupChunks) / kGroupChunks);
   if (c > kWideMaxChunks) c = kWideMaxChunks;
   if (c > p.n_tiles) c = p.n_tiles;
   if (c < 1) c = 1;
   p.chunk_tiles = (p.n_tiles + c - 1) / c;
   p.n_chunks = (int)((p.n_tiles + p.chunk_tiles - 1) / p.chunk_tiles);
+  p.n_quads = (p.n_chunks + kGroupChunks - 1) / kGroupChunks;
+  const int64_t groups = (int64_t)((p.n_rt + kGroupTiles - 1) / kGroupTiles) * p.n_quads;
+  p.n_blocks = (groups + 7) / 8 * 8 * 32;  // whole rounds of 8 groups (idle blocks return)
   return p;
 }
 
@@ -597,10 +611,10 @@ hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, int32_t 
                              hipStream_t st) {
   const WidePlan p = plan_wide(n_reads, idx.n_windows);
   uint64_t* part = static_cast<uint64_t*>(ws);
-  hipLaunchKernelGGL(score_wide_kernel, dim3((unsigned)((int64_t)p.n_rt * p.n_chunks)), dim3(kThreads),
-                     0, st, static_cast<const _Float16*>(read_emb), n_reads,
+  hipLaunchKernelGGL(score_wide_kernel, dim3((unsigned)p.n_blocks), dim3(kThreads), 0, st,
+                     static_cast<const _Float16*>(read_emb), n_reads,
                      static_cast<const _Float16*>(idx.d_emb), idx.n_windows, p.n_rt, p.n_tiles,
-                     p.chunk_tiles, p.n_chunks, k_fetch, part);
+                     p.chunk_tiles, p.n_chunks, p.n_quads, k_fetch, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(merge_wide_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0,
