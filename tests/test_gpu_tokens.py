@@ -420,3 +420,34 @@ def test_wide_encodings_are_fp16_only():
     for precision in ("fp32", "fp8"):
         with pytest.raises(L.RotorMapError):
             _build(ref, "s4m4", precision)
+
+
+def test_wide_fewer_windows_than_candidates():
+    """A 1,024-component index with 21 windows and k_fetch = 32: every window
+    is a candidate once, the rest of the list is empty (id -1, score -1); a
+    read shorter than N scores 0 everywhere (ids ascending); a one-read batch."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref = synth.make_reference(170, seed=31, uniform=True)
+    s, m, C, tm, sched = ENC["s8c256"]
+    reads_seq = np.concatenate([ref[7:157], ref[0:120], ref[20:170]])
+    off = np.array([0, 150, 270, 420], dtype=np.int64)
+    index = _build(ref, "s8c256", "fp16")
+    W = index.n_windows
+    assert W == 21
+    for n in (3, 1):
+        rb = mapper.upload_reads(index, reads_seq[:off[n]], off[:n + 1])
+        bufs = mapper.map_buffers(index, n, 8, 32)
+        mapper.map_reads(index, rb, bufs)
+        torch.cuda.synchronize()
+        cidx = bufs.cand_idx.cpu().numpy()
+        csc = bufs.cand_score.cpu().numpy()
+        tidx = bufs.top_idx.cpu().numpy()
+        assert np.all(cidx[:, W:] == -1) and np.all(csc[:, W:] == -1)
+        for r in range(n):
+            assert sorted(cidx[r, :W].tolist()) == list(range(W)), r
+        assert tidx[0, 0] == 7                             # exact substring at window 7
+        if n == 3:
+            assert tidx[2, 0] == 20
+            assert list(tidx[1]) == list(range(8))         # no head: F = 0, ids ascending
+            assert np.all(bufs.top_score.cpu().numpy()[1] == 0.0)
