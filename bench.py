@@ -170,8 +170,8 @@ def main():
             sys.exit(2)
         s_, m_, c_, tm_, sched_ = synth.token_encoding(args.tokens)
         tok = dict(mer_len=s_, n_freq=m_, n_class=c_, token_map=tm_, schedule=sched_)
-        if c_ * m_ != 128 and precision != "fp16":
-            print("encodings of 1,024 components are FP16 only", file=sys.stderr)
+        if c_ * m_ != 128 and precision == "fp32":
+            print("encodings of 1,024 components have FP16 and FP8 indexes only", file=sys.stderr)
             sys.exit(2)
     # reals per stored row: 256, or 2,048 for the 1,024-component token encodings
     real_dim = 2 * tok["n_class"] * tok["n_freq"] if tok else 256

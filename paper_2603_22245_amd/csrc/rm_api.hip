@@ -27,7 +27,7 @@ int classes_of(const rm_params* p) {
   return p->n_class != 0 ? p->n_class : (s <= 4 ? 1 << (2 * s) : 0);
 }
 
-// A token encoding of 1,024 complex components (FP16 only, own kernels).
+// A token encoding of 1,024 complex components (FP16 or FP8, own kernels).
 bool wide_encoding(const rm_params* p) {
   return !letter_encoding(p) && (int64_t)p->n_freq * classes_of(p) == rm::kWideComplex;
 }
@@ -45,7 +45,7 @@ bool params_ok(const rm_params* p, int* why) {
     const int C = classes_of(p);
     if (C < 2 || C % 2 != 0 || C > 256 || p->n_freq < 1) return (*why = RM_EUNSUPPORTED), false;
     if (C * p->n_freq == rm::kWideComplex) {
-      if (C % 16 != 0 || p->precision != RM_FP16) return (*why = RM_EUNSUPPORTED), false;
+      if (C % 16 != 0 || p->precision == RM_FP32) return (*why = RM_EUNSUPPORTED), false;
     } else if (C * p->n_freq != rm::kComplex) {
       return (*why = RM_EUNSUPPORTED), false;
     }
@@ -265,10 +265,12 @@ int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_re
     int st = index_ok(idx);
     if (st != RM_OK) return st;
     if (!d_read_emb || !d_cand_idx || !d_cand_score || !d_ws) return RM_EINVAL;
+    if (idx->p.precision == RM_FP8_E4M3 && !d_read_scale) return RM_EINVAL;
     if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return RM_ESIZE;
     if (ws_bytes < rm::wide_workspace_bytes(n_reads, idx->n_windows, k_fetch)) return RM_ESIZE;
-    return hip_status(rm::launch_score_wide(*idx, d_read_emb, n_reads, k_fetch, d_cand_idx,
-                                            d_cand_score, d_ws, static_cast<hipStream_t>(stream)));
+    return hip_status(rm::launch_score_wide(*idx, d_read_emb, d_read_scale, n_reads, k_fetch,
+                                            d_cand_idx, d_cand_score, d_ws,
+                                            static_cast<hipStream_t>(stream)));
   }
   return rm_score_topk_groups(idx, 1, &d_read_emb, &d_read_scale, &n_reads, k_fetch, &d_cand_idx,
                               &d_cand_score, d_ws, ws_bytes, nullptr, stream);

@@ -82,7 +82,7 @@ hipError_t launch_encode_reads_tokens(const rm_params& p, const double* phase64,
                                       const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                       int32_t n_reads, void* emb, float* scale, hipStream_t st);
 
-// Encodings of 1,024 complex components (16 per lane), FP16 only.
+// Encodings of 1,024 complex components (16 per lane), FP16 or FP8.
 constexpr int kWideComplex = 1024;
 constexpr int kWideMaxChunks = 16;  // window chunks per read tile (merge reads <= 16 x 32 keys)
 
@@ -103,9 +103,9 @@ hipError_t launch_encode_reference_wide(const uint8_t* ref, int64_t W, const rm_
 hipError_t launch_encode_reads_wide(const rm_params& p, const double* phase64,
                                     const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                     int32_t n_reads, void* emb, float* scale, hipStream_t st);
-hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, int32_t n_reads,
-                             int32_t k_fetch, int32_t* cand_idx, float* cand_score, void* ws,
-                             hipStream_t st);
+hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, const float* read_scale,
+                             int32_t n_reads, int32_t k_fetch, int32_t* cand_idx,
+                             float* cand_score, void* ws, hipStream_t st);
 hipError_t launch_rescore_wide(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                                const int64_t* off, int32_t n_reads, int32_t k_fetch,
                                const int32_t* cand_idx, int32_t k, int32_t* top_idx,

@@ -1,6 +1,6 @@
 // Token encodings with 1,024 complex components (§2.1 s-mers, §2.6 compact
 // versions): e.g. 8-mers mapped to 256 classes with m = 4 -- the encoding the
-// paper maps with (§3.5) -- or 4-mers with m = 4.  FP16 storage only.
+// paper maps with (§3.5) -- or 4-mers with m = 4.  FP16 or FP8 e4m3 storage.
 //
 // Lane layout: lane l owns the 16 complex components [16 l, 16 l + 16), i.e.
 // factor k = 16 l / n_class and classes c0 .. c0 + 15 with c0 = 16 l mod
@@ -33,8 +33,7 @@ constexpr int kWaves = kWM * kWN;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kTM = 64 * kWM;       // A rows per block tile (kTM / 2 reads)
 constexpr int kTN = 64 * kWN;       // windows per block tile
-constexpr int kTK = 64;     // K (halves) per stage: one 128-byte line of every row
-constexpr int kStages = kWR / kTK;
+constexpr int kLine = 128;  // bytes of every row per K stage (64 FP16 or 128 FP8 elements)
 constexpr int kListMax = RM_MAX_KFETCH;
 constexpr int kGroupTiles = 8;   // read tiles per group of 32 blocks on one XCD
 constexpr int kGroupChunks = 4;  // window chunks per group
@@ -42,6 +41,7 @@ constexpr int kGroupChunks = 4;  // window chunks per group
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // ---- encoders ---------------------------------------------------------------
 
@@ -79,22 +79,53 @@ __device__ __forceinline__ uint32_t pack_h2(float a, float b) {
          ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
 }
 
-// One FP16 row: 32 reals per lane (x_q re, im for q = 0..15), 64 bytes.
-__device__ __forceinline__ void store_wide_row(_Float16* __restrict__ base, int64_t row, int lane,
-                                               const float (&re)[kWC], const float (&im)[kWC],
-                                               float mul) {
-  uint4* dst = reinterpret_cast<uint4*>(base + row * kWR) + lane * 4;
+// One row of 2,048 reals: this lane's 32 (x_q re, im for q = 0..15), each
+// times `mul`.  FP16: 64 bytes per lane, returns 1.  FP8: the codes of the row
+// divided by 2^e, the smallest power of two with max |x| / 2^e <= 448 (32
+// bytes per lane), and returns the scale that makes code x scale exactly unit
+// length (1 / the norm of the codes), as the 128-component encoders do.
+template <int PREC>
+__device__ __forceinline__ float store_wide_row(void* __restrict__ base, int64_t row, int lane,
+                                                const float (&re)[kWC], const float (&im)[kWC],
+                                                float mul) {
+  if constexpr (PREC == RM_FP16) {
+    uint4* dst = reinterpret_cast<uint4*>(static_cast<_Float16*>(base) + row * kWR) + lane * 4;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int q = 4 * v;
-    dst[v] = make_uint4(pack_h2(re[q] * mul, im[q] * mul), pack_h2(re[q + 1] * mul, im[q + 1] * mul),
-                        pack_h2(re[q + 2] * mul, im[q + 2] * mul),
-                        pack_h2(re[q + 3] * mul, im[q + 3] * mul));
+    for (int v = 0; v < 4; ++v) {
+      const int q = 4 * v;
+      dst[v] = make_uint4(pack_h2(re[q] * mul, im[q] * mul),
+                          pack_h2(re[q + 1] * mul, im[q + 1] * mul),
+                          pack_h2(re[q + 2] * mul, im[q + 2] * mul),
+                          pack_h2(re[q + 3] * mul, im[q + 3] * mul));
+    }
+    return 1.f;
+  } else {
+    float m = 0.f;
+#pragma unroll
+    for (int q = 0; q < kWC; ++q) m = fmaxf(m, fmaxf(fabsf(re[q] * mul), fabsf(im[q] * mul)));
+    m = wave_max_nonneg(m);
+    const float s = fp8_pow2_scale(m);
+    const float inv = pow2_reciprocal(s) * mul;  // exact power of two times mul
+    uint32_t w[8];
+    float q2 = 0.f;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int q = 2 * v;
+      w[v] = pack_fp8x2(re[q] * inv, im[q] * inv) | (pack_fp8x2(re[q + 1] * inv, im[q + 1] * inv) << 16);
+      const float2 d0 = unpack_fp8x2(w[v]), d1 = unpack_fp8x2(w[v] >> 16);
+      q2 += d0.x * d0.x + d0.y * d0.y + d1.x * d1.x + d1.y * d1.y;
+    }
+    uint4* dst = reinterpret_cast<uint4*>(static_cast<uint8_t*>(base) + row * kWR) + lane * 2;
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    q2 = wave_sum(q2);
+    return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) : s;
   }
 }
 
+template <int PREC>
 __device__ __forceinline__ void emit_wide(int64_t j, int lane, int N, const float (&re)[kWC],
-                                          const float (&im)[kWC], _Float16* __restrict__ emb,
+                                          const float (&im)[kWC], void* __restrict__ emb,
                                           float* __restrict__ scale, float* __restrict__ norm2) {
   float acc = 0.f;
 #pragma unroll
@@ -102,10 +133,10 @@ __device__ __forceinline__ void emit_wide(int64_t j, int lane, int N, const floa
   const float n2 = wave_sum(acc);
   const bool deg = n2 < kDegenerateRel * (float)N;
   const float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);
-  store_wide_row(emb, j, lane, re, im, inv);
+  const float sc = store_wide_row<PREC>(emb, j, lane, re, im, inv);
   if (lane == 0) {
     norm2[j] = n2;
-    scale[j] = 1.f;
+    scale[j] = sc;
   }
 }
 
@@ -113,11 +144,12 @@ __device__ __forceinline__ void emit_wide(int64_t j, int lane, int N, const floa
 // encoder: FP64 re-anchor at each segment start, then one-letter slides in
 // FP32 (rotate by omega^-f, the token at the old start loses omega^-f after
 // the rotation, the token ending at the new last letter gains omega^(f (N-s))).
+template <int PREC>
 __global__ __launch_bounds__(256) void encode_reference_wide_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int s, int m, int n_class,
     int64_t seg_len, int64_t n_seg, const double2* __restrict__ phase64,
     const float4* __restrict__ step32, const uint8_t* __restrict__ table,
-    _Float16* __restrict__ emb, float* __restrict__ scale, float* __restrict__ norm2) {
+    void* __restrict__ emb, float* __restrict__ scale, float* __restrict__ norm2) {
   const int lane = threadIdx.x & 63;
   const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (seg >= n_seg) return;
@@ -136,7 +168,7 @@ __global__ __launch_bounds__(256) void encode_reference_wide_kernel(
       im[q] = (float)di[q];
     }
   }
-  emit_wide(j0, lane, N, re, im, emb, scale, norm2);
+  emit_wide<PREC>(j0, lane, N, re, im, emb, scale, norm2);
 
   const float4 st = step32[k];
   const float rr = st.x, ri = st.y;  // omega^-f
@@ -167,7 +199,7 @@ __global__ __launch_bounds__(256) void encode_reference_wide_kernel(
       if (--until_emit == 0) {
         until_emit = stride;
         ++j;
-        emit_wide(j, lane, N, re, im, emb, scale, norm2);
+        emit_wide<PREC>(j, lane, N, re, im, emb, scale, norm2);
       }
     }
     out_c = out_next;
@@ -177,10 +209,11 @@ __global__ __launch_bounds__(256) void encode_reference_wide_kernel(
 
 // Read heads: FP64 direct sum, normalised; rows 2r = (Re x, Im x) and
 // 2r+1 = (-Im x, Re x) per component, as for the 128-component encodings.
+template <int PREC>
 __global__ __launch_bounds__(256) void encode_reads_wide_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
     int s, int m, int n_class, const double2* __restrict__ phase64,
-    const uint8_t* __restrict__ table, _Float16* __restrict__ emb, float* __restrict__ scale) {
+    const uint8_t* __restrict__ table, void* __restrict__ emb, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= n_reads) return;
@@ -203,9 +236,10 @@ __global__ __launch_bounds__(256) void encode_reads_wide_kernel(
     xi[q] = (float)(di[q] * inv);
     nxi[q] = -xi[q];
   }
-  store_wide_row(emb, 2 * r, lane, xr, xi, 1.f);
-  store_wide_row(emb, 2 * r + 1, lane, nxi, xr, 1.f);
-  if (scale != nullptr && lane == 0) scale[r] = 1.f;
+  // both rows hold the same magnitudes: the same power of two and scale
+  const float sc = store_wide_row<PREC>(emb, 2 * r, lane, xr, xi, 1.f);
+  store_wide_row<PREC>(emb, 2 * r + 1, lane, nxi, xr, 1.f);
+  if (scale != nullptr && lane == 0) scale[r] = sc;
 }
 
 // ---- product + per-read top-k -------------------------------------------------
@@ -234,12 +268,12 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 // A stage in LDS: kTM + kTN rows (the A rows, then the window rows) of 128
-// bytes (64 halves of K); row r keeps its 16-byte chunk c at position
-// c ^ ((r / 2) % 8), so that the rows a group of lanes reads at once (the same
-// chunk of consecutive rows) fall on different banks.
-constexpr int kStageBytes = (kTM + kTN) * kTK * 2;  // 48 KB
-constexpr int kChunks = kTK / 8;                     // 16-byte chunks per row
-constexpr int kRowsPerBankRow = 128 / kTK;           // rows per 256 bytes of LDS banks
+// bytes of K; row r keeps its 16-byte chunk c at position c ^ ((r / 2) % 8),
+// so that the rows a group of lanes reads at once (the same chunk of
+// consecutive rows) fall on different banks.
+constexpr int kStageBytes = (kTM + kTN) * kLine;  // 48 KB
+constexpr int kChunks = kLine / 16;               // 16-byte chunks per row
+constexpr int kRowsPerBankRow = 256 / kLine;      // rows per 256 bytes of LDS banks
 constexpr int kRing = 3;                             // stages in LDS (two in flight)
 constexpr int kDmaPerWave = (kTM + kTN) * kChunks / (64 * kWaves);  // copies per lane per stage
 static_assert(kDmaPerWave * 64 * kWaves == (kTM + kTN) * kChunks, "stage splits into whole copies");
@@ -247,7 +281,7 @@ static_assert((kRing - 2) * kDmaPerWave <= 63, "vmcnt range");
 
 __device__ __forceinline__ int swz(int row) { return (row / kRowsPerBankRow) % kChunks; }
 __device__ __forceinline__ uint32_t chunk_pos(int row, int c) {
-  return (uint32_t)(row * (kTK * 2) + 16 * (c ^ swz(row)));
+  return (uint32_t)(row * kLine + 16 * (c ^ swz(row)));
 }
 
 // Work items are (read tile, window chunk); a chunk is the window tiles
@@ -258,8 +292,14 @@ __device__ __forceinline__ uint32_t chunk_pos(int row, int c) {
 // read tile's rows are streamed by 4 blocks and every chunk's window rows by 8
 // blocks at about the same time.  Writes the k_fetch best keys of each of the
 // tile's reads over the chunk to part[read][chunk][0..k_fetch) (0 = empty).
+//
+// FP16: 32x32x16 MFMAs, F = Re^2 + Im^2.  FP8: 32x32x64 MFMAs on the e4m3
+// codes, F = (Re^2 + Im^2) (s_r s_j)^2 with the read's and the window's
+// scales.
+template <int PREC>
 __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
-    const _Float16* __restrict__ A, int32_t n_reads, const _Float16* __restrict__ B, int64_t W,
+    const uint8_t* __restrict__ A, const float* __restrict__ a_scale, int32_t n_reads,
+    const uint8_t* __restrict__ B, const float* __restrict__ b_scale, int64_t W,
     int n_rt, int64_t n_tiles, int64_t chunk_tiles, int n_chunks, int n_quads, int k_fetch,
     uint64_t* __restrict__ part) {
   // the stage ring, reused by the epilogue as the F buffer [kTM / 2 reads][kTN]
@@ -267,6 +307,9 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
   __shared__ uint64_t lists[kTM / 2][kListMax];
   static_assert(sizeof(float) * (kTM / 2) * kTN <= sizeof(ring), "F buffer fits in the ring");
   float* Fbuf = reinterpret_cast<float*>(&ring[0][0]);
+  constexpr bool kFp8 = PREC == RM_FP8_E4M3;
+  constexpr int64_t kRowBytes = (int64_t)kWR * (kFp8 ? 1 : 2);
+  constexpr int kStages = (int)(kRowBytes / kLine);
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -284,12 +327,29 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
 
   for (int i = tid; i < (kTM / 2) * kListMax; i += kThreads) (&lists[0][0])[i] = 0;
 
+  // FP8: squared scales of this lane's reads (output rows 2q, 2q+1 of a 32-row
+  // block hold read q; see the epilogue) -- and, per tile, of its windows
+  float sr2[2][8];
+#pragma unroll
+  for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int vv = 0; vv < 8; ++vv) {
+      sr2[f][vv] = 1.f;
+      if constexpr (kFp8) {
+        const int v = 2 * vv;
+        const int row = 64 * wr + 32 * f + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t r = row0 / 2 + (row >> 1);
+        const float sc = r < n_reads ? a_scale[r] : 0.f;
+        sr2[f][vv] = sc * sc;
+      }
+    }
+
   // This lane's 16-byte pieces of a stage: piece p = 64 (wave + kWaves i) +
   // lane lands at LDS position p (row p / kChunks, position p % kChunks) and
   // holds chunk (p % kChunks) ^ swz(row) of that row.  Rows past the last read or
   // window re-read the last one (always in bounds); their scores are never
   // used.
-  int64_t src_off[kDmaPerWave];  // element offset of the piece's row and chunk, K stage 0
+  int64_t src_off[kDmaPerWave];  // byte offset of the piece's row and chunk, K stage 0
   bool is_b[kDmaPerWave];
 #pragma unroll
   for (int i = 0; i < kDmaPerWave; ++i) {
@@ -297,18 +357,18 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
     const int row = p / kChunks;
     const int c = (p % kChunks) ^ swz(row);
     is_b[i] = row >= kTM;
-    src_off[i] = (is_b[i] ? (int64_t)(row - kTM) : min(row0 + row, M - 1)) * kWR + c * 8;
+    src_off[i] = (is_b[i] ? (int64_t)(row - kTM) : min(row0 + row, M - 1)) * kRowBytes + c * 16;
   }
   auto issue = [&](int64_t tile, int st) {
     const uint32_t base = ring_lds + (uint32_t)(st % kRing) * kStageBytes;
 #pragma unroll
     for (int i = 0; i < kDmaPerWave; ++i) {
-      const _Float16* src;
+      const uint8_t* src;
       if (is_b[i]) {
-        const int64_t g = min(tile * kTN + src_off[i] / kWR, W - 1);
-        src = B + g * kWR + (src_off[i] % kWR) + st * kTK;
+        const int64_t g = min(tile * kTN + src_off[i] / kRowBytes, W - 1);
+        src = B + g * kRowBytes + (src_off[i] % kRowBytes) + st * kLine;
       } else {
-        src = A + src_off[i] + st * kTK;
+        src = A + src_off[i] + st * kLine;
       }
       dma16w(src, __builtin_amdgcn_readfirstlane(base + 1024 * (wave + kWaves * i)));
     }
@@ -322,6 +382,15 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
       for (int g = 0; g < 2; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[f][g][v] = 0.f;
+    float sj2[2] = {1.f, 1.f};
+    if constexpr (kFp8) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int64_t j = tile * kTN + 64 * wc + 32 * g + (lane & 31);
+        const float sc = b_scale[min(j, W - 1)];
+        sj2[g] = sc * sc;
+      }
+    }
 
     // stages st .. st + kRing - 2 are in flight; one barrier per stage: after
     // it every wavefront's copies of stage st have landed and every wavefront
@@ -334,25 +403,56 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
       __syncthreads();
       if (st + kRing - 1 < kStages) issue(tile, st + kRing - 1);
       const uint8_t* sb = &ring[st % kRing][0];
+      if constexpr (!kFp8) {
 #pragma unroll
-      for (int ks = 0; ks < kTK / 16; ++ks) {
-        const int c = 2 * ks + (lane >> 5);  // this lane's 8 halves of the 16-K step
-        half8 a[2], b[2];
+        for (int ks = 0; ks < kLine / 32; ++ks) {
+          const int c = 2 * ks + (lane >> 5);  // this lane's 8 halves of the 16-K step
+          half8 a[2], b[2];
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-          const int row = 64 * wr + 32 * f + (lane & 31);
-          a[f] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
+          for (int f = 0; f < 2; ++f) {
+            const int row = 64 * wr + 32 * f + (lane & 31);
+            a[f] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
+          }
+#pragma unroll
+          for (int g = 0; g < 2; ++g) {
+            const int row = kTM + 64 * wc + 32 * g + (lane & 31);
+            b[g] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
+          }
+#pragma unroll
+          for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+              acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[f], b[g], acc[f][g], 0, 0, 0);
         }
+      } else {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          const int row = kTM + 64 * wc + 32 * g + (lane & 31);
-          b[g] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
+        for (int ks = 0; ks < kLine / 64; ++ks) {
+          const int c = 4 * ks + 2 * (lane >> 5);  // this lane's 32 codes of the 64-K step
+          i32x8 a[2], b[2];
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const int row = 64 * wr + 32 * f + (lane & 31);
+            const uint4 u0 = *reinterpret_cast<const uint4*>(sb + chunk_pos(row, c));
+            const uint4 u1 = *reinterpret_cast<const uint4*>(sb + chunk_pos(row, c + 1));
+            a[f] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                         (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+          }
+#pragma unroll
+          for (int g = 0; g < 2; ++g) {
+            const int row = kTM + 64 * wc + 32 * g + (lane & 31);
+            const uint4 u0 = *reinterpret_cast<const uint4*>(sb + chunk_pos(row, c));
+            const uint4 u1 = *reinterpret_cast<const uint4*>(sb + chunk_pos(row, c + 1));
+            b[g] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                         (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+          }
+          // formats 0/0 = FP8 e4m3 for both operands; E8M0 scales 127 = 1.0
+#pragma unroll
+          for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+              acc[f][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[f], b[g], acc[f][g], 0,
+                                                                           0, 0, 127, 0, 127);
         }
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-          for (int g = 0; g < 2; ++g)
-            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[f], b[g], acc[f][g], 0, 0, 0);
       }
     }
     __syncthreads();  // every wavefront is done with the ring before it becomes the F buffer
@@ -369,7 +469,9 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
           const int row = 64 * wr + 32 * f + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
           const int col = 64 * wc + 32 * g + (lane & 31);
           const float re = acc[f][g][v], im = acc[f][g][v + 1];
-          Fbuf[(row >> 1) * kTN + col] = re * re + im * im;
+          float F = re * re + im * im;
+          if constexpr (kFp8) F *= sr2[f][v >> 1] * sj2[g];
+          Fbuf[(row >> 1) * kTN + col] = F;
         }
     __syncthreads();
 
@@ -587,34 +689,38 @@ hipError_t launch_encode_reference_wide(const uint8_t* ref, int64_t W, const rm_
   }
   const int64_t n_seg = (W + seg - 1) / seg;
   const int64_t blocks = (n_seg + 3) / 4;
-  hipLaunchKernelGGL(encode_reference_wide_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ref,
-                     W, p.window_len, p.stride, p.mer_len > 1 ? p.mer_len : 1, p.n_freq,
-                     kWideComplex / p.n_freq, seg, n_seg, reinterpret_cast<const double2*>(phase64),
-                     reinterpret_cast<const float4*>(step32), table,
-                     static_cast<_Float16*>(emb), scale, norm2);
+  auto kern = p.precision == RM_FP8_E4M3 ? encode_reference_wide_kernel<RM_FP8_E4M3>
+                                          : encode_reference_wide_kernel<RM_FP16>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, ref, W, p.window_len,
+                     p.stride, p.mer_len > 1 ? p.mer_len : 1, p.n_freq, kWideComplex / p.n_freq,
+                     seg, n_seg, reinterpret_cast<const double2*>(phase64),
+                     reinterpret_cast<const float4*>(step32), table, emb, scale, norm2);
   return hipGetLastError();
 }
 
 hipError_t launch_encode_reads_wide(const rm_params& p, const double* phase64,
                                     const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                     int32_t n_reads, void* emb, float* scale, hipStream_t st) {
-  hipLaunchKernelGGL(encode_reads_wide_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)),
-                     dim3(256), 0, st, seq, off, n_reads, p.window_len,
-                     p.mer_len > 1 ? p.mer_len : 1, p.n_freq, kWideComplex / p.n_freq,
-                     reinterpret_cast<const double2*>(phase64), table,
-                     static_cast<_Float16*>(emb), scale);
+  auto kern = p.precision == RM_FP8_E4M3 ? encode_reads_wide_kernel<RM_FP8_E4M3>
+                                          : encode_reads_wide_kernel<RM_FP16>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0, st, seq,
+                     off, n_reads, p.window_len, p.mer_len > 1 ? p.mer_len : 1, p.n_freq,
+                     kWideComplex / p.n_freq, reinterpret_cast<const double2*>(phase64), table,
+                     emb, scale);
   return hipGetLastError();
 }
 
-hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, int32_t n_reads,
-                             int32_t k_fetch, int32_t* cand_idx, float* cand_score, void* ws,
-                             hipStream_t st) {
+hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, const float* read_scale,
+                             int32_t n_reads, int32_t k_fetch, int32_t* cand_idx,
+                             float* cand_score, void* ws, hipStream_t st) {
   const WidePlan p = plan_wide(n_reads, idx.n_windows);
   uint64_t* part = static_cast<uint64_t*>(ws);
-  hipLaunchKernelGGL(score_wide_kernel, dim3((unsigned)p.n_blocks), dim3(kThreads), 0, st,
-                     static_cast<const _Float16*>(read_emb), n_reads,
-                     static_cast<const _Float16*>(idx.d_emb), idx.n_windows, p.n_rt, p.n_tiles,
-                     p.chunk_tiles, p.n_chunks, p.n_quads, k_fetch, part);
+  auto kern = idx.p.precision == RM_FP8_E4M3 ? score_wide_kernel<RM_FP8_E4M3>
+                                              : score_wide_kernel<RM_FP16>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)p.n_blocks), dim3(kThreads), 0, st,
+                     static_cast<const uint8_t*>(read_emb), read_scale, n_reads,
+                     static_cast<const uint8_t*>(idx.d_emb), idx.d_scale, idx.n_windows, p.n_rt,
+                     p.n_tiles, p.chunk_tiles, p.n_chunks, p.n_quads, k_fetch, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(merge_wide_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0,

@@ -241,6 +241,17 @@ def test_token_params_validation():
             continue
         assert L.rm_index_bytes(20_000, p) == 0
         assert lib.rm_encode_reference(0x1000, 20_000, R(p), 0x10000, 1 << 30, R(out), None) == status
+    # 1,024 components (K = 2,048): FP16 and FP8 indexes, 4 KB / 2 KB rows; no FP32
+    w16 = L.make_params(150, 1, 4, "default", "fp16", 0, 8, 256, 0x2000)
+    w8 = L.make_params(150, 1, 4, "finetuned", "fp8", 0, 4, 0)      # 4-mers, no map
+    assert L.rm_read_emb_bytes(10, w16) == 10 * 2 * 2048 * 2
+    assert L.rm_read_emb_bytes(10, w8) == 10 * 2 * 2048
+    assert L.rm_index_bytes(20_000, w16) > 19_851 * 4096 > L.rm_index_bytes(20_000, w8) > 19_851 * 2048
+    for bad_p in (L.make_params(150, 1, 4, "default", "fp32", 0, 8, 256, 0x2000),
+                  L.make_params(150, 1, 128, "default", "fp16", 0, 8, 8, 0x2000)):   # 8 classes: not a multiple of 16
+        assert L.rm_index_bytes(20_000, bad_p) == 0
+        assert lib.rm_encode_reference(0x1000, 20_000, R(bad_p), 0x10000, 1 << 30, R(out),
+                                       None) == L.RM_EUNSUPPORTED
     # a token index descriptor needs its class table
     idx = _fake_index()
     idx.p = ok[0]

@@ -4,7 +4,8 @@ benchmark times, on outputs the oracle can compute one by one or has stored:
 * precision (10 Mbp, 100,000 reads, FP16 index, top-8 of 16): stored oracle
   top-16 lists of 64 sampled reads; sampled index rows and squared norms; the
   same with token indexes (2-mers FP16, 8-mers mapped to 16 classes FP8,
-  8-mers mapped to 256 classes with m = 4 on the K = 2,048 product);
+  8-mers mapped to 256 classes with m = 4 on the K = 2,048 product, FP16
+  and FP8);
 * scale (256 Mbp, FP8 index with FP64 re-anchor every 65,536 starts, top-16 of
   32): sampled index rows (re-anchor boundaries, the last windows), squared
   norms (rolling drift), rescored scores of sampled reads one window at a time,
@@ -147,7 +148,8 @@ def test_precision_workload_full_size(precision):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("enc,precision", [("s2", "fp16"), ("s8c16", "fp8"), ("s8c256", "fp16")])
+@pytest.mark.parametrize("enc,precision", [("s2", "fp16"), ("s8c16", "fp8"), ("s8c256", "fp16"),
+                                           ("s8c256", "fp8")])
 def test_precision_workload_token_encoding_full_size(enc, precision):
     """The precision workload with a token index (§2.1 s-mers, §2.6 compact
     map), in the benchmark's configuration (top-8 of 16): sampled index rows
