@@ -9,10 +9,10 @@
 //
 // The product has K = 2,048, too long to keep a read tile in registers as the
 // 256-real scoring kernel does, so here both operands stream through LDS:
-// block tiles of 128 A rows (64 reads) x 256 windows, K in stages of 64
-// copied straight from global memory into a ring of three LDS stages (two in
-// flight while one is computed), eight wavefronts of 64 x 64 outputs on
-// 32x32x16 FP16 MFMAs.  (Each block's read rows are re-read for every window
+// block tiles of 256 A rows (128 reads) x 256 windows, K in 64-byte lines per
+// row copied straight from global memory into a ring of four LDS stages
+// (three in flight while one is computed), eight wavefronts of 64 x 128
+// outputs on 32x32x16 FP16 MFMAs.  (Each block's read rows are re-read for every window
 // tile while the window rows are shared by the blocks of a chunk through L2,
 // hence the wide window tile.)  Per tile the epilogue writes F = Re^2 + Im^2 of every (read, window)
 // to LDS and each wavefront compares 16 reads' scores with their current
@@ -27,13 +27,14 @@ namespace {
 
 constexpr int kWC = 16;     // complex components per lane
 constexpr int kWR = 2048;   // reals per row
-constexpr int kWM = 2;              // wavefronts along the rows
-constexpr int kWN = 4;              // wavefronts along the windows
+constexpr int kWM = 4;              // wavefronts along the rows (64 rows each)
+constexpr int kWN = 2;              // wavefronts along the windows
+constexpr int kGN = 4;              // 32-window column blocks per wavefront
 constexpr int kWaves = kWM * kWN;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kTM = 64 * kWM;       // A rows per block tile (kTM / 2 reads)
-constexpr int kTN = 64 * kWN;       // windows per block tile
-constexpr int kLine = 128;  // bytes of every row per K stage (64 FP16 or 128 FP8 elements)
+constexpr int kTN = 32 * kGN * kWN; // windows per block tile
+constexpr int kLine = 64;   // bytes of every row per K stage (32 FP16 or 64 FP8 elements)
 constexpr int kListMax = RM_MAX_KFETCH;
 constexpr int kGroupTiles = 8;   // read tiles per group of 32 blocks on one XCD
 constexpr int kGroupChunks = 4;  // window chunks per group
@@ -267,14 +268,14 @@ __device__ __forceinline__ void wait_vm() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// A stage in LDS: kTM + kTN rows (the A rows, then the window rows) of 128
-// bytes of K; row r keeps its 16-byte chunk c at position c ^ ((r / 2) % 8),
-// so that the rows a group of lanes reads at once (the same chunk of
+// A stage in LDS: kTM + kTN rows (the A rows, then the window rows) of kLine
+// bytes of K; row r keeps its 16-byte chunk c at position c ^ swz(r), so
+// that the rows a group of lanes reads at once (the same chunk of
 // consecutive rows) fall on different banks.
-constexpr int kStageBytes = (kTM + kTN) * kLine;  // 48 KB
+constexpr int kStageBytes = (kTM + kTN) * kLine;  // 32 KB
 constexpr int kChunks = kLine / 16;               // 16-byte chunks per row
 constexpr int kRowsPerBankRow = 256 / kLine;      // rows per 256 bytes of LDS banks
-constexpr int kRing = 3;                             // stages in LDS (two in flight)
+constexpr int kRing = 4;                             // stages in LDS (three in flight)
 constexpr int kDmaPerWave = (kTM + kTN) * kChunks / (64 * kWaves);  // copies per lane per stage
 static_assert(kDmaPerWave * 64 * kWaves == (kTM + kTN) * kChunks, "stage splits into whole copies");
 static_assert((kRing - 2) * kDmaPerWave <= 63, "vmcnt range");
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave / kWN, wc = wave % kWN;  // this wavefront's 64 rows x 64 windows
+  const int wr = wave / kWN, wc = wave % kWN;  // this wavefront's 64 rows x 32 kGN windows
   const int xcd = blockIdx.x % 8, i_x = blockIdx.x / 8;
   const int group = (i_x / 32) * 8 + xcd, j_g = i_x % 32;
   const int rt = (group / n_quads) * kGroupTiles + j_g / kGroupChunks;
@@ -375,18 +376,20 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
   };
 
   for (int64_t tile = t0; tile < t1; ++tile) {
-    f32x16 acc[2][2];
+    f32x16 acc[2][kGN];
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int g = 0; g < kGN; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[f][g][v] = 0.f;
-    float sj2[2] = {1.f, 1.f};
+    float sj2[kGN];
+#pragma unroll
+    for (int g = 0; g < kGN; ++g) sj2[g] = 1.f;
     if constexpr (kFp8) {
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        const int64_t j = tile * kTN + 64 * wc + 32 * g + (lane & 31);
+      for (int g = 0; g < kGN; ++g) {
+        const int64_t j = tile * kTN + 32 * kGN * wc + 32 * g + (lane & 31);
         const float sc = b_scale[min(j, W - 1)];
         sj2[g] = sc * sc;
       }
@@ -407,28 +410,28 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
 #pragma unroll
         for (int ks = 0; ks < kLine / 32; ++ks) {
           const int c = 2 * ks + (lane >> 5);  // this lane's 8 halves of the 16-K step
-          half8 a[2], b[2];
+          half8 a[2], b[kGN];
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
             const int row = 64 * wr + 32 * f + (lane & 31);
             a[f] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
           }
 #pragma unroll
-          for (int g = 0; g < 2; ++g) {
-            const int row = kTM + 64 * wc + 32 * g + (lane & 31);
+          for (int g = 0; g < kGN; ++g) {
+            const int row = kTM + 32 * kGN * wc + 32 * g + (lane & 31);
             b[g] = *reinterpret_cast<const half8*>(sb + chunk_pos(row, c));
           }
 #pragma unroll
           for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int g = 0; g < 2; ++g)
+            for (int g = 0; g < kGN; ++g)
               acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[f], b[g], acc[f][g], 0, 0, 0);
         }
       } else {
 #pragma unroll
         for (int ks = 0; ks < kLine / 64; ++ks) {
           const int c = 4 * ks + 2 * (lane >> 5);  // this lane's 32 codes of the 64-K step
-          i32x8 a[2], b[2];
+          i32x8 a[2], b[kGN];
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
             const int row = 64 * wr + 32 * f + (lane & 31);
@@ -438,8 +441,8 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
                          (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
           }
 #pragma unroll
-          for (int g = 0; g < 2; ++g) {
-            const int row = kTM + 64 * wc + 32 * g + (lane & 31);
+          for (int g = 0; g < kGN; ++g) {
+            const int row = kTM + 32 * kGN * wc + 32 * g + (lane & 31);
             const uint4 u0 = *reinterpret_cast<const uint4*>(sb + chunk_pos(row, c));
             const uint4 u1 = *reinterpret_cast<const uint4*>(sb + chunk_pos(row, c + 1));
             b[g] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
@@ -449,7 +452,7 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
 #pragma unroll
           for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int g = 0; g < 2; ++g)
+            for (int g = 0; g < kGN; ++g)
               acc[f][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[f], b[g], acc[f][g], 0,
                                                                            0, 0, 127, 0, 127);
         }
@@ -463,11 +466,11 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int g = 0; g < kGN; ++g)
 #pragma unroll
         for (int v = 0; v < 16; v += 2) {
           const int row = 64 * wr + 32 * f + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          const int col = 64 * wc + 32 * g + (lane & 31);
+          const int col = 32 * kGN * wc + 32 * g + (lane & 31);
           const float re = acc[f][g][v], im = acc[f][g][v + 1];
           float F = re * re + im * im;
           if constexpr (kFp8) F *= sr2[f][v >> 1] * sj2[g];
