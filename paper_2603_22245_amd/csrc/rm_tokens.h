@@ -87,7 +87,7 @@ constexpr int kWideComplex = 1024;
 constexpr int kWideMaxChunks = 16;  // window chunks per read tile (merge reads <= 16 x 32 keys)
 
 struct WidePlan {
-  int n_rt;             // read tiles (64 reads each)
+  int n_rt;             // read tiles (128 reads each)
   int64_t n_tiles;      // window tiles of 128
   int64_t chunk_tiles;  // window tiles per chunk
   int n_chunks;

@@ -12,9 +12,9 @@
 // block tiles of 256 A rows (128 reads) x 256 windows, K in 64-byte lines per
 // row copied straight from global memory into a ring of four LDS stages
 // (three in flight while one is computed), eight wavefronts of 64 x 128
-// outputs on 32x32x16 FP16 MFMAs.  (Each block's read rows are re-read for every window
-// tile while the window rows are shared by the blocks of a chunk through L2,
-// hence the wide window tile.)  Per tile the epilogue writes F = Re^2 + Im^2 of every (read, window)
+// outputs on 32x32x16 FP16 (32x32x64 FP8) MFMAs.  The block tile is as large
+// as the 160 KB of LDS allows, since its reuse sets the bytes copied per
+// flop.  Per tile the epilogue writes F = Re^2 + Im^2 of every (read, window)
 // to LDS and each wavefront compares 16 reads' scores with their current
 // k-th best; the (rare) hits are inserted into the read's sorted list held in
 // LDS.  A block walks the window tiles of one chunk and writes each read's
