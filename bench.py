@@ -759,10 +759,52 @@ def cpu_baseline(w, ref, reads, W, n_reads, n_windows, tokens_name=None):
     dt = time.perf_counter() - t
     v = n_reads / dt * (nw / W)
     log(f"cpu baseline: {n_reads} reads x {nw:,} windows in {dt:.1f}s")
-    return {"value": float(f"{v:.4g}"), "unit": "reads/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_reads} read heads x first {nw:,} of {W:,} windows (FP64 encoding + "
-                      f"brute-force scan, {dt:.1f} s), scaled by {nw:,}/{W:,}",
-            "host_cpus": os.cpu_count()}
+    # the same oracle on one thread, over a quarter of the windows
+    nw1 = max(1, nw // 4)
+    v1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t = time.perf_counter()
+            if tokens_name is None:
+                mapping.map_reads(ref, heads, w.window_len, w.n_freq, w.k, w.stride,
+                                  window_range=(0, nw1))
+            else:
+                tokens.map_reads(ref, heads, w.window_len, s, m, C, tm, w.k, w.stride, sched,
+                                 window_range=(0, nw1))
+            v1 = n_reads / (time.perf_counter() - t) * (nw1 / W)
+    except ImportError:
+        pass
+    out = {"value": float(f"{v:.4g}"), "unit": "reads/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_reads} read heads x first {nw:,} of {W:,} windows (FP64 encoding + "
+                     f"brute-force scan, {dt:.1f} s), scaled by {nw:,}/{W:,}",
+           "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(), "ram_gib": _ram_gib()}
+    if v1 is not None:
+        out["single_thread_value"] = float(f"{v1:.4g}")
+        out["single_thread_sample"] = f"the same reads x first {nw1:,} windows on one thread"
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _ram_gib():
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    return round(int(line.split()[1]) / 2**20, 1)
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
