@@ -17,7 +17,8 @@ Definitions followed (RotorMap paper, arXiv 2603.22245):
   dimension; the tokens are then counted by their mapped value (their class).
   Here the mapping is any table `token_map` from s-mer code to class in
   0..C-1, or -1 for an s-mer left out (the variant that keeps only selected
-  s-mers).  With no table the class is the s-mer code and C = 4^s.
+  s-mers, e.g. the reference's most frequent ones: `frequent_map`).  With no
+  table the class is the s-mer code and C = 4^s.
 * §2.10: the same vector is sum_loc D^loc (ones(m) (x) onehot(class(loc))),
   D = Diag((omega^1..omega^m) (x) ones(C)): component index (k-1)*C + class.
 * §3.4: one slide of a window multiplies every component by omega^-f_k,
@@ -65,6 +66,27 @@ def token_classes(w, s: int, token_map=None) -> np.ndarray:
     out = np.full(codes.shape, SKIP, dtype=np.int64)
     ok = codes >= 0
     out[ok] = tm[codes[ok]]
+    return out
+
+
+def mer_counts(ref, s: int) -> np.ndarray:
+    """Occurrences of every s-mer code in `ref` (locations 0..G-s; s-mers with
+    a letter outside 0..3 are not counted), int64 [4^s]."""
+    codes = mer_codes(ref, s)
+    return np.bincount(codes[codes >= 0], minlength=4 ** s).astype(np.int64)
+
+
+def frequent_map(ref, s: int, n_class: int) -> np.ndarray:
+    """The compact context-aware version of §2.6: only the n_class most
+    frequent s-mers of the reference are tokens.  Reading: ranked by count
+    descending, then by code ascending; the kept s-mers take classes 0..n_class-1
+    in code order; every other s-mer maps to SKIP.  int64 [4^s]."""
+    counts = mer_counts(ref, s)
+    codes = np.arange(4 ** s)
+    order = np.lexsort((codes, -counts))          # count desc, code asc
+    keep = np.sort(order[:n_class])
+    out = np.full(4 ** s, SKIP, dtype=np.int64)
+    out[keep] = np.arange(keep.size)
     return out
 
 

@@ -176,3 +176,36 @@ def test_window_encodings_gathered_from_the_reference(name):
     a = tokens.encode_windows(ref, starts, N, s, m, C, tm, sched)
     b = tokens.encode_many(mapping.window_letters(ref, starts, N), N, s, m, C, tm, sched)
     assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_mer_counts_by_slicing_text():
+    """Counts of every s-mer found by sliding over the text, letter code 4
+    breaking the s-mers that contain it."""
+    ref = _rand(300)
+    ref[[40, 41, 200]] = 4
+    text = "".join("ACGTN"[v] for v in ref)
+    for s in (1, 2, 3):
+        got = tokens.mer_counts(ref, s)
+        for code, mer in enumerate(itertools.product("ACGT", repeat=s)):
+            mer = "".join(mer)
+            want = sum(1 for p in range(len(text) - s + 1) if text[p:p + s] == mer)
+            assert got[code] == want, (s, mer)
+
+
+def test_frequent_map_by_hand():
+    """A reference whose 2-mer counts are known: the kept 2-mers are the most
+    frequent, ties broken by the lower code, classes in code order."""
+    # AAAAA: AA x4; then CACACA: AC x1, CA x3, AC x2 (total AC 3); GT once
+    ref = synth.to_codes("AAAAACACACAGT")
+    counts = tokens.mer_counts(ref, 2)
+    code = lambda m: 4 * "ACGT".index(m[0]) + "ACGT".index(m[1])
+    assert counts[code("AA")] == 4 and counts[code("AC")] == 3 and counts[code("CA")] == 3
+    assert counts[code("AG")] == 1 and counts[code("GT")] == 1
+    mp = tokens.frequent_map(ref, 2, 4)
+    # AA (4), AC (3), CA (3), then the lowest code among the count-1 2-mers: AG
+    kept = {m: mp[code(m)] for m in ("AA", "AC", "AG", "CA")}
+    assert kept == {"AA": 0, "AC": 1, "AG": 2, "CA": 3}
+    assert np.sum(mp >= 0) == 4 and mp[code("GT")] == tokens.SKIP
+    # more classes than distinct 2-mers present: unseen codes fill by code order
+    mp = tokens.frequent_map(ref, 2, 8)
+    assert np.sum(mp >= 0) == 8 and sorted(mp[mp >= 0].tolist()) == list(range(8))
