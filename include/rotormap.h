@@ -187,6 +187,31 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                const int32_t* d_cand_idx, int32_t k, int32_t* d_top_idx, float* d_top_score,
                void* stream);
 
+/* ---- the compact context-aware token map (§2.6) ------------------------------
+ * Only the reference's most frequent s-mers are tokens: count every s-mer of
+ * the reference, then keep the n_class first by (count descending, code
+ * ascending) as classes 0..n_class-1 in code order; every other s-mer maps to
+ * RM_TOKEN_SKIP.  The map is then passed as rm_params.d_token_map. */
+#define RM_MAX_FREQUENT 128  /* largest n_class for the selection (RM_TOKEN_SKIP stays free) */
+
+/* Bytes of the count buffer for s-mers of mer_len letters (4^s uint32); 0 if invalid. */
+size_t rm_token_counts_bytes(int32_t mer_len);
+
+/* d_counts[code] = occurrences of the s-mer `code` (code as in rm_params) at
+ * the locations 0..ref_len-s of d_ref; s-mers holding a letter outside 0..3
+ * are not counted.  d_counts: caller-owned device buffer of
+ * rm_token_counts_bytes(mer_len), overwritten.  Errors: RM_EINVAL (null
+ * pointer), RM_ESIZE (mer_len outside 1..RM_MAX_MER, ref_len < mer_len). */
+int rm_token_counts(const uint8_t* d_ref, int64_t ref_len, int32_t mer_len, uint32_t* d_counts,
+                    void* stream);
+
+/* d_map[code] (4^s uint8, device, caller-owned) = the class of the n_class
+ * most frequent s-mers of d_counts, ranked by (count desc, code asc) and
+ * numbered in code order; RM_TOKEN_SKIP for the others.  Errors: RM_EINVAL,
+ * RM_ESIZE (mer_len out of range, n_class outside 1..min(RM_MAX_FREQUENT, 4^s))). */
+int rm_token_map_frequent(const uint32_t* d_counts, int32_t mer_len, int32_t n_class,
+                          uint8_t* d_map, void* stream);
+
 /* ---- both strands and the threshold regime ---------------------------------
  * The paper maps reads in both directions: a read from the other strand
  * matches the reference after reverse complementing it.  Map the reads and

@@ -19,7 +19,7 @@ RM_OK, RM_EINVAL, RM_ESIZE, RM_EUNSUPPORTED, RM_EHIP = 0, -1, -2, -3, -4
 RM_FP32, RM_FP16, RM_FP8_E4M3 = 0, 1, 2
 RM_SCHED_DEFAULT, RM_SCHED_FINETUNED = 0, 1
 RM_DIM, RM_MAX_WINDOW, RM_MAX_KFETCH = 32, 16384, 32
-RM_MAX_MER, RM_TOKEN_SKIP = 8, 255
+RM_MAX_MER, RM_TOKEN_SKIP, RM_MAX_FREQUENT = 8, 255, 128
 PRECISIONS = {"fp32": RM_FP32, "fp16": RM_FP16, "fp8": RM_FP8_E4M3}
 SCHEDULES = {"default": RM_SCHED_DEFAULT, "finetuned": RM_SCHED_FINETUNED}
 
@@ -82,6 +82,9 @@ def lib():
             "rm_rescore": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, P, P, P]),
             "rm_refine_workspace_bytes": (SZ, [I32, I32, I32]),
             "rm_reverse_complement": (ctypes.c_int, [P, P, I32, I64, P, P]),
+            "rm_token_counts_bytes": (ctypes.c_size_t, [I32]),
+            "rm_token_counts": (ctypes.c_int, [P, I64, I32, P, P]),
+            "rm_token_map_frequent": (ctypes.c_int, [P, I32, I32, P, P]),
             "rm_merge_strands": (ctypes.c_int, [P, P, P, P, I32, I32, ctypes.c_float, P, P, P, P,
                                                 P]),
             "rm_refine": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, I32, P, P, P, SZ, P]),
@@ -208,6 +211,20 @@ def rm_rescore(idx: rm_index, d_ref, d_seq, d_off, n_reads: int, k_fetch: int, d
     _check(lib().rm_rescore(ctypes.byref(idx), _ptr(d_ref), _ptr(d_seq), _ptr(d_off), n_reads,
                             k_fetch, _ptr(d_cand_idx), k, _ptr(d_top_idx), _ptr(d_top_score),
                             _stream(stream)), "rm_rescore")
+
+
+def rm_token_counts_bytes(mer_len: int) -> int:
+    return int(lib().rm_token_counts_bytes(mer_len))
+
+
+def rm_token_counts(d_ref, ref_len: int, mer_len: int, d_counts, stream=None) -> None:
+    _check(lib().rm_token_counts(_ptr(d_ref), ref_len, mer_len, _ptr(d_counts), _stream(stream)),
+           "rm_token_counts")
+
+
+def rm_token_map_frequent(d_counts, mer_len: int, n_class: int, d_map, stream=None) -> None:
+    _check(lib().rm_token_map_frequent(_ptr(d_counts), mer_len, n_class, _ptr(d_map),
+                                       _stream(stream)), "rm_token_map_frequent")
 
 
 def rm_reverse_complement(d_seq, d_off, n_reads: int, n_letters: int, d_out, stream=None) -> None:

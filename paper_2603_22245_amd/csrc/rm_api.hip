@@ -298,6 +298,29 @@ int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
                                        d_top_idx, d_top_score, static_cast<hipStream_t>(stream)));
 }
 
+size_t rm_token_counts_bytes(int32_t mer_len) {
+  if (mer_len < 1 || mer_len > RM_MAX_MER) return 0;
+  return ((size_t)1 << (2 * mer_len)) * sizeof(uint32_t);
+}
+
+int rm_token_counts(const uint8_t* d_ref, int64_t ref_len, int32_t mer_len, uint32_t* d_counts,
+                    void* stream) {
+  if (d_ref == nullptr || d_counts == nullptr) return RM_EINVAL;
+  if (mer_len < 1 || mer_len > RM_MAX_MER || ref_len < mer_len) return RM_ESIZE;
+  return hip_status(rm::launch_token_counts(d_ref, ref_len, mer_len, d_counts,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+int rm_token_map_frequent(const uint32_t* d_counts, int32_t mer_len, int32_t n_class,
+                          uint8_t* d_map, void* stream) {
+  if (d_counts == nullptr || d_map == nullptr) return RM_EINVAL;
+  if (mer_len < 1 || mer_len > RM_MAX_MER || n_class < 1 || n_class > RM_MAX_FREQUENT ||
+      (int64_t)n_class > ((int64_t)1 << (2 * mer_len)))
+    return RM_ESIZE;
+  return hip_status(rm::launch_token_select(d_counts, mer_len, n_class, d_map,
+                                            static_cast<hipStream_t>(stream)));
+}
+
 int rm_reverse_complement(const uint8_t* d_seq, const int64_t* d_off, int32_t n_reads,
                           int64_t n_letters, uint8_t* d_out, void* stream) {
   if (d_seq == nullptr || d_off == nullptr || d_out == nullptr || d_out == d_seq) return RM_EINVAL;

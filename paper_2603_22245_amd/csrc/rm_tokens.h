@@ -111,6 +111,13 @@ hipError_t launch_rescore_wide(const rm_index& idx, const uint8_t* ref, const ui
                                const int32_t* cand_idx, int32_t k, int32_t* top_idx,
                                float* top_score, hipStream_t st);
 
+// The reference's s-mer counts (4^s uint32, zeroed here) and the map that
+// keeps its n_class most frequent s-mers (§2.6).
+hipError_t launch_token_counts(const uint8_t* ref, int64_t ref_len, int s, uint32_t* counts,
+                               hipStream_t st);
+hipError_t launch_token_select(const uint32_t* counts, int s, int n_class, uint8_t* map,
+                               hipStream_t st);
+
 hipError_t launch_rescore_tokens(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                                  const int64_t* off, int32_t n_reads, int32_t k_fetch,
                                  const int32_t* cand_idx, int32_t k, int32_t* top_idx,

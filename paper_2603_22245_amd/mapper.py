@@ -83,7 +83,10 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
     d_map = None
     token = mer_len > 1 or token_map is not None or n_class is not None
     if token_map is not None:
-        d_map = torch.as_tensor(np.ascontiguousarray(token_map, dtype=np.uint8)).to(device)
+        if isinstance(token_map, np.ndarray) or not hasattr(token_map, "data_ptr"):
+            d_map = torch.as_tensor(np.ascontiguousarray(token_map, dtype=np.uint8)).to(device)
+        else:  # already a device tensor (e.g. frequent_token_map's)
+            d_map = token_map
         if d_map.numel() != 4 ** mer_len:
             raise ValueError(f"token_map must have 4^{mer_len} entries")
         if n_freq is None and n_class is None:
@@ -115,6 +118,24 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
     L.rm_mlp_infer(params, d_ref, int(d_ref.numel()), delta, stream)
     idx = L.rm_encode_reference_learned(d_ref, int(d_ref.numel()), p, delta, buf, nbytes, stream)
     return Index(p, idx, buf, d_ref, params, delta)
+
+
+def frequent_token_map(ref, mer_len: int, n_class: int, stream=None, device="cuda"):
+    """The compact context-aware map of §2.6 on the device: the n_class most
+    frequent s-mers of `ref` (numpy or device uint8) as classes in code order,
+    the others RM_TOKEN_SKIP.  Returns (map [4^s] uint8, counts [4^s] int32 view
+    of the uint32 counts) as device tensors."""
+    torch = _torch()
+    d_ref = ref if hasattr(ref, "data_ptr") else \
+        torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device)
+    nbytes = L.rm_token_counts_bytes(mer_len)
+    if nbytes == 0:
+        raise L.RotorMapError(L.RM_ESIZE, "rm_token_counts_bytes")
+    counts = torch.empty(nbytes // 4, dtype=torch.int32, device=device)
+    d_map = torch.empty(4 ** mer_len, dtype=torch.uint8, device=device)
+    L.rm_token_counts(d_ref, int(d_ref.numel()), mer_len, counts, stream)
+    L.rm_token_map_frequent(counts, mer_len, n_class, d_map, stream)
+    return d_map, counts
 
 
 @dataclasses.dataclass

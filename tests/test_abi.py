@@ -252,6 +252,17 @@ def test_token_params_validation():
         assert L.rm_index_bytes(20_000, bad_p) == 0
         assert lib.rm_encode_reference(0x1000, 20_000, R(bad_p), 0x10000, 1 << 30, R(out),
                                        None) == L.RM_EUNSUPPORTED
+    # counts and the frequent-s-mer map (§2.6): sizes and validation
+    assert L.rm_token_counts_bytes(8) == 4 ** 8 * 4 and L.rm_token_counts_bytes(9) == 0
+    assert L.rm_token_counts_bytes(0) == 0
+    assert lib.rm_token_counts(None, 100, 4, 1, None) == L.RM_EINVAL
+    assert lib.rm_token_counts(1, 100, 4, None, None) == L.RM_EINVAL
+    assert lib.rm_token_counts(1, 3, 4, 1, None) == L.RM_ESIZE                # shorter than s
+    assert lib.rm_token_counts(1, 100, L.RM_MAX_MER + 1, 1, None) == L.RM_ESIZE
+    assert lib.rm_token_map_frequent(None, 4, 8, 1, None) == L.RM_EINVAL
+    assert lib.rm_token_map_frequent(1, 2, 17, 1, None) == L.RM_ESIZE         # more than 4^s
+    assert lib.rm_token_map_frequent(1, 8, L.RM_MAX_FREQUENT + 1, 1, None) == L.RM_ESIZE
+    assert lib.rm_token_map_frequent(1, 8, 0, 1, None) == L.RM_ESIZE
     # a token index descriptor needs its class table
     idx = _fake_index()
     idx.p = ok[0]

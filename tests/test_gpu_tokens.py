@@ -469,3 +469,62 @@ def test_wide_fewer_windows_than_candidates():
             assert tidx[2, 0] == 20
             assert list(tidx[1]) == list(range(8))         # no head: F = 0, ids ascending
             assert np.all(bufs.top_score.cpu().numpy()[1] == 0.0)
+
+
+# ---- the compact context-aware map of §2.6 (the reference's most frequent s-mers)
+
+@pytest.mark.parametrize("s,n_class,G", [(2, 8, 20_000), (4, 64, 200_000), (6, 128, 200_000),
+                                         (8, 128, 10_000_000)])
+def test_frequent_token_map(s, n_class, G):
+    """s-mer counts bit-exact against the oracle's, and the kept set and its
+    classes equal to oracle.tokens.frequent_map (ties at the boundary count
+    broken by the lower code, classes in code order)."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    if G == 10_000_000:
+        ref = synth.WORKLOADS["precision"].reference()
+    else:
+        ref = synth.make_reference(G, gc=0.45, repeat_frac=0.08, seed=40 + s)
+    ref[[17, 18, G // 2]] = 4
+    d_map, counts = mapper.frequent_token_map(ref, s, n_class)
+    torch.cuda.synchronize()
+    want_counts = tokens.mer_counts(ref, s)
+    assert np.array_equal(counts.cpu().numpy().astype(np.int64), want_counts)
+    want = tokens.frequent_map(ref, s, n_class)
+    want = np.where(want < 0, 255, want).astype(np.uint8)
+    assert np.array_equal(d_map.cpu().numpy(), want)
+
+
+def test_map_reads_with_frequent_map(plain_data):
+    """The 128 most frequent 4-mers of the reference as the token classes
+    (m = 8, 1,024 components): product + top-k + rescore against the oracle
+    with the oracle's own frequent map."""
+    from paper_2603_22245_amd import mapper
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    s, C, m = 4, 128, 8
+    d_map, _ = mapper.frequent_token_map(ref, s, C)
+    index = mapper.build_index(ref, precision="fp16", mer_len=s, n_freq=m, n_class=C,
+                               token_map=d_map)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, 8, 16)
+    mapper.map_reads(index, rb, bufs)
+    torch.cuda.synchronize()
+    tm = tokens.frequent_map(ref, s, C)
+    Cn, _ = mapping.normalized_rows(
+        tokens.encode_windows(ref, np.arange(ref.size - N + 1), N, s, m, C, tm), N)
+    Xn, _ = mapping.normalized_rows(tokens.encode_many(heads, N, s, m, C, tm), N)
+    F = np.abs(np.conj(Xn) @ Cn.T) ** 2
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    o_idx = order[:, :8]
+    o_F = np.take_along_axis(F, o_idx, 1)
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    top_F = np.take_along_axis(F, tidx, 1)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, top_F)
+    exact = mapping.same_up_to_ties(tidx, o_F, top_F)
+    print(f"frequent 4-mers -> 128 classes: recall@8 {rec:.4f}, exact {exact.mean():.4f}, "
+          f"top-1 near truth {np.mean(np.abs(tidx[:, 0] - reads.truth) <= 8):.3f}")
+    assert np.max(np.abs(tsc - top_F)) < 2e-6
+    assert rec >= 0.99 and exact.mean() >= 0.97
