@@ -163,12 +163,18 @@ def main():
     stride = args.coarse_stride if coarse else w.stride
     radius = (args.radius if args.radius is not None else stride - 1) if coarse else 0
     tok = {}
+    token_map_ms = None
     if args.tokens is not None:
         if coarse:
             print("--tokens and --coarse-stride do not combine (refinement takes letter indexes)",
                   file=sys.stderr)
             sys.exit(2)
         s_, m_, c_, tm_, sched_ = synth.token_encoding(args.tokens)
+        if synth.token_map_is_frequent(args.tokens):  # the reference's most frequent s-mers
+            t_map = time.perf_counter()
+            tm_, _ = mapper.frequent_token_map(ref, s_, c_)
+            torch.cuda.synchronize()
+            token_map_ms = (time.perf_counter() - t_map) * 1e3
         tok = dict(mer_len=s_, n_freq=m_, n_class=c_, token_map=tm_, schedule=sched_)
         if c_ * m_ != 128 and precision == "fp32":
             print("encodings of 1,024 components have FP16 and FP8 indexes only", file=sys.stderr)
@@ -265,6 +271,7 @@ def main():
                          "score_topk": round(parts[2], 3),
                          ("refine" if coarse else "rescore"): round(parts[3], 3)},
         "encoder_gbs": round(enc_bytes / (parts[0] / 1e3) / 1e9, 1),
+        "token_map_ms": None if token_map_ms is None else round(token_map_ms, 3),
         "accuracy": acc,
         "roofline": roofline,
     }
@@ -663,8 +670,9 @@ def describe(w, precision, k, k_fetch, R, stride=None, radius=0, tokens=None):
     if tokens is not None:
         import synth
         s, m, C, tm, sched = synth.token_encoding(tokens)
-        enc = (f"{s}-mer tokens" + (f" mapped to {C} classes" if tm is not None else "") +
-               f", m={m}, {sched} factors")
+        kept = (f", the {C} most frequent kept" if synth.token_map_is_frequent(tokens) else
+                f" mapped to {C} classes" if tm is not None else "")
+        enc = f"{s}-mer tokens{kept}, m={m}, {sched} factors"
     head = (f"{w.name}: {w.G / 1e6:g} Mbp synthetic reference ({int(w.gc * 100)}% GC, "
             f"{int(w.repeat_frac * 100)}% repeats), {R:,} reads of {w.read_len} bp, N={w.window_len}, "
             f"{enc}, stride {stride}, {precision} index, ")
@@ -754,6 +762,8 @@ def cpu_baseline(w, ref, reads, W, n_reads, n_windows, tokens_name=None):
     else:
         import synth
         s, m, C, tm, sched = synth.token_encoding(tokens_name)
+        if synth.token_map_is_frequent(tokens_name):
+            tm = tokens.frequent_map(ref, s, C)
         tokens.map_reads(ref, heads, w.window_len, s, m, C, tm, w.k, w.stride, sched,
                          window_range=(0, nw))
     dt = time.perf_counter() - t

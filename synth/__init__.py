@@ -321,8 +321,11 @@ def token_map(s: int, n_class: int, seed: Optional[int] = None) -> np.ndarray:
 
 
 # Token encodings used by the tests, the stored oracle samples and the
-# benchmark: name -> (s, m, n_class, mapped, schedule).  A mapped encoding
-# takes token_map(s, n_class) as its 4^s-to-n_class table.
+# benchmark: name -> (s, m, n_class, mapped, schedule).  mapped = True takes
+# token_map(s, n_class) as its 4^s-to-n_class table; mapped = "frequent" keeps
+# the reference's n_class most frequent s-mers, a table the method itself
+# derives from the reference (the caller builds it; token_encoding returns
+# None for it).
 TOKEN_ENCODINGS = {
     "s2": (2, 8, 16, False, "default"),
     "s3": (3, 2, 64, False, "finetuned"),
@@ -332,10 +335,17 @@ TOKEN_ENCODINGS = {
     # t = 4 shape)
     "s4m4": (4, 4, 256, False, "default"),
     "s8c256": (8, 4, 256, True, "finetuned"),
+    # the reference's 128 most frequent 4-mers, m = 8 (1,024 components)
+    "s4f128": (4, 8, 128, "frequent", "default"),
 }
 
 
 def token_encoding(name: str):
-    """(s, m, n_class, table or None, schedule) of a named token encoding."""
+    """(s, m, n_class, table or None, schedule) of a named token encoding
+    (None also for a frequent-s-mer encoding: see token_map_is_frequent)."""
     s, m, C, mapped, sched = TOKEN_ENCODINGS[name]
-    return s, m, C, (token_map(s, C) if mapped else None), sched
+    return s, m, C, (token_map(s, C) if mapped is True else None), sched
+
+
+def token_map_is_frequent(name: str) -> bool:
+    return TOKEN_ENCODINGS[name][3] == "frequent"

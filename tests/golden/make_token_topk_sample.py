@@ -7,7 +7,8 @@ Writes tests/golden/<workload>_<encoding>_top<k>_sample<n>.npz with arrays
   idx    [n,k]  oracle window ids, ranked (F desc, ties within 1e-12 by id)
   F      [n,k]  oracle fidelities
 computed by oracle.tokens.map_reads over every window of the workload, with
-the named encoding of synth.TOKEN_ENCODINGS.  Only the oracle and the seeded
+the named encoding of synth.TOKEN_ENCODINGS (a frequent-s-mer map is the
+oracle's own, oracle.tokens.frequent_map).  Only the oracle and the seeded
 input generators are used.
 """
 import os
@@ -29,6 +30,8 @@ def main(name: str, enc: str, n: int, k: int):
     w = synth.WORKLOADS[name]
     s, m, C, tm, sched = synth.token_encoding(enc)
     ref = w.reference()
+    if synth.token_map_is_frequent(enc):
+        tm = tokens.frequent_map(ref, s, C)
     reads = w.reads(ref)
     pick = sample_reads(name, n)
     heads = mapping.read_heads(reads.seq, reads.offsets, w.window_len)[pick]

@@ -22,7 +22,8 @@ N = 150
 TOL = {"fp32": 1e-5, "fp16": 1e-3, "fp8": 1e-2}
 
 # name -> (s, m, n_class, token map or None, schedule)
-ENC = {name: synth.token_encoding(name) for name in synth.TOKEN_ENCODINGS}
+ENC = {name: synth.token_encoding(name) for name in synth.TOKEN_ENCODINGS
+       if not synth.token_map_is_frequent(name)}
 
 
 def _build(ref, enc, precision, **kw):
