@@ -5,7 +5,7 @@ benchmark times, on outputs the oracle can compute one by one or has stored:
   top-16 lists of 64 sampled reads; sampled index rows and squared norms; the
   same with token indexes (2-mers FP16, 8-mers mapped to 16 classes FP8,
   8-mers mapped to 256 classes with m = 4 on the K = 2,048 product, FP16
-  and FP8);
+  and FP8, and the 128 most frequent 4-mers with m = 8);
 * scale (256 Mbp, FP8 index with FP64 re-anchor every 65,536 starts, top-16 of
   32): sampled index rows (re-anchor boundaries, the last windows), squared
   norms (rolling drift), rescored scores of sampled reads one window at a time,
@@ -149,7 +149,7 @@ def test_precision_workload_full_size(precision):
 
 
 @pytest.mark.parametrize("enc,precision", [("s2", "fp16"), ("s8c16", "fp8"), ("s8c256", "fp16"),
-                                           ("s8c256", "fp8")])
+                                           ("s8c256", "fp8"), ("s4f128", "fp16")])
 def test_precision_workload_token_encoding_full_size(enc, precision):
     """The precision workload with a token index (§2.1 s-mers, §2.6 compact
     map), in the benchmark's configuration (top-8 of 16): sampled index rows
@@ -161,8 +161,12 @@ def test_precision_workload_token_encoding_full_size(enc, precision):
     s, m, C, tm, sched = synth.token_encoding(enc)
     ref = w.reference()
     reads = w.reads(ref)
+    dev_map = tm
+    if synth.token_map_is_frequent(enc):  # built on the device; the oracle's own for the checks
+        dev_map, _ = mapper.frequent_token_map(ref, s, C)
+        tm = tokens.frequent_map(ref, s, C)
     index = mapper.build_index(ref, w.window_len, w.stride, precision, sched, w.reanchor,
-                               mer_len=s, n_freq=m, n_class=C, token_map=tm)
+                               mer_len=s, n_freq=m, n_class=C, token_map=dev_map)
     rb, bufs = _map(index, reads, w.k, 16)
     torch.cuda.synchronize()
     W = index.n_windows
