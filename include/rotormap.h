@@ -88,10 +88,13 @@ typedef struct rm_params {
    * most significant; an s-mer holding a letter outside 0..3 is no token); its
    * class is the code itself (no map: n_class must be 4^s) or d_token_map[code]
    * (values >= n_class, e.g. RM_TOKEN_SKIP, add nothing: the variant keeping
-   * only selected s-mers).  Component index (k-1)*n_class + class, and
-   * n_class * n_freq must be 128 with n_class even: (s, m) = (2, 8) or (3, 2)
-   * without a map, any s <= RM_MAX_MER with one (e.g. s = 8 mapped to 16
-   * classes, m = 8). */
+   * only selected s-mers, e.g. rm_token_map_frequent's).  Component index
+   * (k-1)*n_class + class, with n_class even and at most 256, and
+   * n_class * n_freq either 128 ((s, m) = (2, 8) or (3, 2) without a map, any
+   * s <= RM_MAX_MER with one, e.g. s = 8 mapped to 16 classes, m = 8; every
+   * precision) or 1,024 (n_class a multiple of 16, e.g. s = 8 mapped to 256
+   * classes with m = 4 -- the paper's s = 8, m = 4, t = 4 shape -- or s = 4,
+   * m = 4; FP16 or FP8 index, 2,048 reals per row). */
   int32_t mer_len;    /* s, 1..RM_MAX_MER; 0 means 1 */
   int32_t n_class;    /* components per factor; 0 means 4^s */
   const uint8_t* d_token_map; /* NULL, or DEVICE [4^s] class per s-mer code; read
@@ -106,7 +109,8 @@ typedef struct rm_index {
   rm_params p;
   int64_t ref_len;     /* G, letters in the reference */
   int64_t n_windows;   /* W = floor((G - N) / stride) + 1 */
-  void* d_emb;         /* [W][256] embeddings (re, im interleaved per component) */
+  void* d_emb;         /* [W][256] embeddings (re, im interleaved per component);
+                          [W][2048] for 1,024-component token encodings */
   float* d_scale;      /* [W] FP8 dequantisation scale per window (1.0 for FP32/FP16) */
   float* d_norm2;      /* [W] squared norm of each window's vector before normalising */
   double* d_phase64;   /* [N][m] complex omega^(f_k p), FP64 (re, im) */
@@ -137,13 +141,15 @@ size_t rm_index_bytes(int64_t ref_len, const rm_params* p);
  * Errors: RM_EINVAL (null pointer, bad enum), RM_ESIZE (ref_len < N, N out of
  * range, stride < 1, buf_bytes < rm_index_bytes, more than 2^31-1 windows,
  * mer_len out of range, N < s), RM_EUNSUPPORTED (letter encoding with n_freq
- * != RM_DIM; token encoding with n_class * n_freq != 128, n_class odd, or no
- * map and n_class != 4^s). */
+ * != RM_DIM; token encoding with n_class odd or above 256, n_class * n_freq
+ * neither 128 nor 1,024, 1,024 components with n_class not a multiple of 16
+ * or an FP32 index, or no map and n_class != 4^s). */
 int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
                         void* d_buf, size_t buf_bytes, rm_index* out, void* stream);
 
 /* Bytes of the read-embedding buffer for n_reads reads: [n_reads][2][256]
- * elements of the index precision (row 2r holds (Re x, Im x) per component and
+ * ([n_reads][2][2048] for 1,024-component token encodings) elements of the
+ * index precision (row 2r holds (Re x, Im x) per component and
  * row 2r+1 holds (-Im x, Re x), so that one real product of the two rows with a
  * window row gives Re and Im of <x|c>).  0 if invalid. */
 size_t rm_read_emb_bytes(int32_t n_reads, const rm_params* p);
@@ -314,7 +320,8 @@ size_t rm_score_groups_workspace_bytes(const rm_index* idx, int32_t n_groups,
  * share one precision and k_fetch.  Output per group as rm_score_topk.
  * Errors: RM_EINVAL (null pointer, mixed precisions), RM_ESIZE (n_groups outside
  * 1..RM_MAX_GROUPS, a group without reads, k_fetch out of range, ws too small),
- * RM_EUNSUPPORTED (a tuning the kernels do not implement). */
+ * RM_EUNSUPPORTED (a tuning the kernels do not implement, or an index of
+ * 1,024 components: those are scored by rm_score_topk only). */
 int rm_score_topk_groups(const rm_index* idx, int32_t n_groups, const void* const* d_read_emb,
                          const float* const* d_read_scale, const int32_t* n_reads,
                          int32_t k_fetch, int32_t* const* d_cand_idx,

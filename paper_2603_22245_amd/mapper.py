@@ -78,7 +78,7 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
     leaves an s-mer out), n_class (default 4^s without a map, 128 / n_freq
     with one) and n_freq = m (default 128 / n_class, or 1024 / n_class for
     n_class above 64).  n_class * n_freq is 128 (every precision) or 1,024
-    (FP16)."""
+    (FP16 or FP8)."""
     torch = _torch()
     d_map = None
     token = mer_len > 1 or token_map is not None or n_class is not None
