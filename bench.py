@@ -118,8 +118,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures one GPU's share of the "
-              "work (the multi-GPU sharding is described in DESIGN.md, not run).", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures one GPU's share of the work; "
+              "sharding the path across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
