@@ -165,10 +165,6 @@ def main():
     tok = {}
     token_map_ms = None
     if args.tokens is not None:
-        if coarse:
-            print("--tokens and --coarse-stride do not combine (refinement takes letter indexes)",
-                  file=sys.stderr)
-            sys.exit(2)
         s_, m_, c_, tm_, sched_ = synth.token_encoding(args.tokens)
         if synth.token_map_is_frequent(args.tokens):  # the reference's most frequent s-mers
             t_map = time.perf_counter()

@@ -258,7 +258,11 @@ int rm_merge_strands(const int32_t* d_fwd_idx, const float* d_fwd_score, const i
  * by a direct sum of its letters, the rest by the one-letter slide relations
  * of §3.4 -- and keeps the k best distinct starts over all of a read's
  * neighbourhoods, ordered by (F desc, start asc).  F = |<x|c>|^2 / (X C)
- * (§2.4) with each window's norm recomputed.  Plain encoding only. */
+ * (§2.4) with each window's norm recomputed.  Every encoding rm_build_index
+ * takes: with tokens (§2.1, §2.6) the first window is a direct sum over its
+ * tokens and a slide turns every component by omega^-f, takes omega^-f off
+ * the class of the token leaving and adds omega^{f (N-s)} to the class of the
+ * token entering. */
 #define RM_REFINE_MAX_RADIUS 7
 
 /* Bytes of the workspace rm_refine needs (256-byte multiple); 0 if invalid. */
@@ -275,7 +279,7 @@ size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radiu
  * Errors: RM_EINVAL (null pointer, invalid index), RM_ESIZE (n_reads < 1,
  * k_fetch outside 1..RM_MAX_KFETCH, radius outside 0..RM_REFINE_MAX_RADIUS,
  * k outside 1..min(RM_MAX_KFETCH, k_fetch (2 radius + 1)), ws too small,
- * 2^31 or more step-1 windows), RM_EUNSUPPORTED (a token encoding). */
+ * 2^31 or more step-1 windows). */
 int rm_refine(const rm_index* coarse, const uint8_t* d_ref, const uint8_t* d_seq,
               const int64_t* d_off, int32_t n_reads, int32_t k_fetch, const int32_t* d_cand_idx,
               int32_t radius, int32_t k, int32_t* d_top_idx, float* d_top_score, void* d_ws,

@@ -365,11 +365,12 @@ int rm_refine(const rm_index* coarse, const uint8_t* d_ref, const uint8_t* d_seq
       (int64_t)k > (int64_t)k_fetch * (2 * radius + 1))
     return RM_ESIZE;
   if (ws_bytes < rm::refine_workspace_bytes(n_reads, k_fetch, radius)) return RM_ESIZE;
-  if (!letter_encoding(&coarse->p)) return RM_EUNSUPPORTED;
   if (coarse->ref_len - coarse->p.window_len + 1 > (int64_t)INT32_MAX) return RM_ESIZE;
-  return hip_status(rm::launch_refine(*coarse, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx,
-                                      radius, k, d_top_idx, d_top_score, d_ws,
-                                      static_cast<hipStream_t>(stream)));
+  auto launch = letter_encoding(&coarse->p) ? rm::launch_refine
+                : wide_encoding(&coarse->p) ? rm::launch_refine_wide
+                                            : rm::launch_refine_tokens;
+  return hip_status(launch(*coarse, d_ref, d_seq, d_off, n_reads, k_fetch, d_cand_idx, radius, k,
+                           d_top_idx, d_top_score, d_ws, static_cast<hipStream_t>(stream)));
 }
 
 int rm_rescore_learned(const rm_index* idx, const uint8_t* d_ref, const float* d_ref_delta,

@@ -118,6 +118,21 @@ hipError_t launch_token_counts(const uint8_t* ref, int64_t ref_len, int s, uint3
 hipError_t launch_token_select(const uint32_t* counts, int s, int n_class, uint8_t* map,
                                hipStream_t st);
 
+// Refinement around coarse candidates (§3.4) for token indexes: each read's
+// k_fetch * (2 radius + 1) keys go to the workspace `ws`, in the layout of the
+// letter refinement, then launch_refine_select keeps the k best distinct starts.
+hipError_t launch_refine_tokens(const rm_index& coarse, const uint8_t* ref, const uint8_t* seq,
+                                const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                                const int32_t* cand_idx, int32_t radius, int32_t k,
+                                int32_t* top_idx, float* top_score, void* ws, hipStream_t st);
+hipError_t launch_refine_wide(const rm_index& coarse, const uint8_t* ref, const uint8_t* seq,
+                              const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                              const int32_t* cand_idx, int32_t radius, int32_t k, int32_t* top_idx,
+                              float* top_score, void* ws, hipStream_t st);
+// The k best distinct starts of each read's n pool keys (key 0 = empty slot).
+hipError_t launch_refine_select(const uint64_t* pool, int n, int32_t n_reads, int32_t k,
+                                int32_t* top_idx, float* top_score, hipStream_t st);
+
 hipError_t launch_rescore_tokens(const rm_index& idx, const uint8_t* ref, const uint8_t* seq,
                                  const int64_t* off, int32_t n_reads, int32_t k_fetch,
                                  const int32_t* cand_idx, int32_t k, int32_t* top_idx,

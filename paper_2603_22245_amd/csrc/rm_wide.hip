@@ -655,6 +655,109 @@ __global__ __launch_bounds__(256) void rescore_wide_kernel(
   }
 }
 
+// Refinement around coarse candidates (§3.4), 1,024 components: the read head
+// as in rescore_wide_kernel, then per candidate (wavefront w takes candidates
+// w, w + 4, ...) the first step-1 window of its neighbourhood as a direct FP32
+// sum over its tokens and the next ones by one-token slides (every component
+// turns by omega^-f, the outgoing token's class loses omega^-f, the incoming
+// token's class gains omega^{f (N-s)}), each scored with its recomputed norm.
+// Slot i of the candidate's span in `pool` receives the key of start lo + i,
+// 0 past the clamped neighbourhood or for an invalid candidate.
+__global__ __launch_bounds__(256) void refine_wide_kernel(
+    const uint8_t* __restrict__ ref, int64_t W1, int N, int cstride, int64_t Wc, int s, int m,
+    int n_class, const float2* __restrict__ phase32, const float4* __restrict__ step32,
+    const uint8_t* __restrict__ table, const uint8_t* __restrict__ seq,
+    const int64_t* __restrict__ off, int32_t R, int k_fetch, const int32_t* __restrict__ cand,
+    int radius, uint64_t* __restrict__ pool) {
+  __shared__ float part[4][2 * kWC][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r = blockIdx.x;
+  const int64_t start = off[r];
+  const int64_t len = off[r + 1] - start;
+  const int span = 2 * radius + 1;
+  const int T = N - s + 1;
+  const int kf = kWC * lane / n_class, c0 = kWC * lane - kf * n_class;
+
+  float xr[kWC], xi[kWC];
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) xr[q] = xi[q] = 0.f;
+  if (len >= N) {
+    const int q0 = wave * T / 4, q1 = (wave + 1) * T / 4;
+    wide_direct_sum(seq + start + q0, q1 - q0, s, table, phase32 + (int64_t)q0 * m, m, kf, c0,
+                    lane, xr, xi);
+  }
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) {
+    part[wave][2 * q][lane] = xr[q];
+    part[wave][2 * q + 1][lane] = xi[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) {
+    xr[q] = ((part[0][2 * q][lane] + part[1][2 * q][lane]) + part[2][2 * q][lane]) +
+            part[3][2 * q][lane];
+    xi[q] = ((part[0][2 * q + 1][lane] + part[1][2 * q + 1][lane]) + part[2][2 * q + 1][lane]) +
+            part[3][2 * q + 1][lane];
+  }
+  float ax = 0.f;
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) ax += xr[q] * xr[q] + xi[q] * xi[q];
+  const float X = wave_sum(ax);
+  const bool xdeg = X < kDegenerateRel * (float)N;
+  const float4 st = step32[kf];
+  const float rr = st.x, ri = st.y;  // omega^-f
+  const float ir = st.z, ii = st.w;  // omega^(f (N-s))
+
+  for (int e = wave; e < k_fetch; e += 4) {
+    uint64_t* out = pool + (r * k_fetch + e) * span;
+    const int32_t j = cand[r * k_fetch + e];
+    int64_t lo = 0, hi = -1;
+    if (j >= 0 && j < Wc) {
+      const int64_t c = (int64_t)j * cstride;
+      lo = c - radius < 0 ? 0 : c - radius;
+      hi = c + radius > W1 - 1 ? W1 - 1 : c + radius;
+    }
+    if (lane < span && lo + lane > hi) out[lane] = 0;
+    if (hi < lo) continue;  // uniform
+    float cr[kWC], ci[kWC];
+    wide_direct_sum(ref + lo, T, s, table, phase32, m, kf, c0, lane, cr, ci);
+    // lane i holds the classes of slide lo + i: the token leaving (at lo + i)
+    // and the one entering (at lo + i + T, whose last letter lo + i + N <=
+    // hi - 1 + N <= W1 - 2 + N = ref_len - 1)
+    const int64_t tl = lo + lane;
+    const int out_c = tl < hi ? token_class(ref + tl, s, table) : kNoToken;
+    const int in_c = tl < hi ? token_class(ref + tl + T, s, table) : kNoToken;
+    uint64_t mine = 0;
+    for (int64_t t = lo; t <= hi; ++t) {
+      float ac = 0.f, pr = 0.f, pi = 0.f;
+#pragma unroll
+      for (int q = 0; q < kWC; ++q) {
+        ac += cr[q] * cr[q] + ci[q] * ci[q];
+        pr += xr[q] * cr[q] + xi[q] * ci[q];  // <x|c> = sum conj(x) c
+        pi += xr[q] * ci[q] - xi[q] * cr[q];
+      }
+      const float C = wave_sum(ac), ipr = wave_sum(pr), ipi = wave_sum(pi);
+      const bool deg = xdeg || C < kDegenerateRel * (float)N;
+      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+      if (lane == (int)(t - lo)) mine = wide_key(F, t);
+      if (t < hi) {
+        const int i = (int)(t - lo);
+        const int o = __builtin_amdgcn_readlane(out_c, i) - c0;
+        const int n = __builtin_amdgcn_readlane(in_c, i) - c0;
+#pragma unroll
+        for (int q = 0; q < kWC; ++q) {
+          const float a = cr[q] * rr - ci[q] * ri;
+          const float b = cr[q] * ri + ci[q] * rr;
+          cr[q] = a - (o == q ? rr : 0.f) + (n == q ? ir : 0.f);
+          ci[q] = b - (o == q ? ri : 0.f) + (n == q ? ii : 0.f);
+        }
+      }
+    }
+    if (lane <= (int)(hi - lo)) out[lane] = mine;
+  }
+}
+
 }  // namespace
 
 WidePlan plan_wide(int32_t n_reads, int64_t W) {
@@ -742,6 +845,26 @@ hipError_t launch_rescore_wide(const rm_index& idx, const uint8_t* ref, const ui
                      idx.d_token_class, seq, off, n_reads, k_fetch, cand_idx, k, top_idx,
                      top_score);
   return hipGetLastError();
+}
+
+hipError_t launch_refine_wide(const rm_index& coarse, const uint8_t* ref, const uint8_t* seq,
+                              const int64_t* off, int32_t n_reads, int32_t k_fetch,
+                              const int32_t* cand_idx, int32_t radius, int32_t k, int32_t* top_idx,
+                              float* top_score, void* ws, hipStream_t st) {
+  const int N = coarse.p.window_len;
+  const int64_t W1 = coarse.ref_len - N + 1;  // step-1 windows
+  uint64_t* pool = static_cast<uint64_t*>(ws);
+  hipLaunchKernelGGL(refine_wide_kernel, dim3((unsigned)n_reads), dim3(256), 0, st, ref, W1, N,
+                     coarse.p.stride, coarse.n_windows,
+                     coarse.p.mer_len > 1 ? coarse.p.mer_len : 1, coarse.p.n_freq,
+                     kWideComplex / coarse.p.n_freq,
+                     reinterpret_cast<const float2*>(coarse.d_phase32),
+                     reinterpret_cast<const float4*>(coarse.d_step32), coarse.d_token_class, seq,
+                     off, n_reads, k_fetch, cand_idx, radius, pool);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_refine_select(pool, k_fetch * (2 * radius + 1), n_reads, k, top_idx, top_score,
+                              st);
 }
 
 }  // namespace rm

@@ -271,7 +271,7 @@ def refine(index: Index, reads: ReadBatch, bufs: MapBuffers, radius: int, ws=Non
     bufs.top_idx / bufs.top_score.  `index` is the coarse (stride > 1) index;
     `ws` a device workspace of rm_refine_workspace_bytes (allocated if None)."""
     if index.learned is not None:
-        raise ValueError("refinement is implemented for the plain encoding only")
+        raise ValueError("refinement is implemented for the plain and token encodings")
     torch = _torch()
     need = L.rm_refine_workspace_bytes(reads.n, bufs.k_fetch, radius)
     if ws is None:

@@ -53,3 +53,24 @@ def fp8_bound(x_abs, scale):
     # half an e4m3 ulp relative (2^-4) for normal values, half the smallest
     # subnormal step (2^-10 * scale) near zero, plus FP32 rolling error
     return 2.0 ** -4 * x_abs + 2.0 ** -10 * scale + 2e-5
+
+
+def check_refined_lists(tidx, tsc, cand, F1, stride, radius, k, tol):
+    """Refined lists [R, k] against the oracle's refinement (mapping.refine_topk)
+    of the same coarse candidates, F1 [R, W1] the oracle's fidelities with every
+    step-1 window: distinct starts from the read's pool, the same ranking up to
+    ties, scores within tol.  Returns the fraction of identical lists."""
+    exact = 0
+    for r in range(F1.shape[0]):
+        want_i, want_f = mapping.refine_topk(F1[r], cand[r], stride, radius, k)
+        n = want_i.size
+        got = tidx[r, :n]
+        assert np.all(tidx[r, n:] == -1) and np.all(got >= 0), r
+        assert len(set(got.tolist())) == n, r                       # distinct starts
+        pool = set(mapping.refine_pool(cand[r], stride, radius, F1.shape[1]).tolist())
+        assert set(got.tolist()) <= pool, r                           # only refined starts
+        got_true = F1[r, got]
+        assert np.all(np.abs(got_true - want_f) <= mapping.TIE_TAU), r  # same ranking up to ties
+        assert np.max(np.abs(tsc[r, :n] - got_true)) < tol, r
+        exact += int(np.array_equal(got, want_i))
+    return exact / F1.shape[0]

@@ -268,9 +268,12 @@ def test_token_params_validation():
     idx.p = ok[0]
     assert lib.rm_encode_reads(R(idx), 1, 1, 10, 1, 1, None) == L.RM_EINVAL
     idx.d_token_class = 0x100000
-    # the learned calls and the refinement take letter indexes only
+    # the refinement takes token indexes with the same validation (every call
+    # here fails before a launch); the learned calls take letter indexes only
     ws = L.rm_refine_workspace_bytes(10, 8, 3)
-    assert lib.rm_refine(R(idx), 1, 1, 1, 10, 8, 1, 3, 8, 1, 1, 1, ws, None) == L.RM_EUNSUPPORTED
+    assert lib.rm_refine(R(idx), 1, 1, 1, 10, 8, 1, 3, 8, 1, 1, 1, ws - 256, None) == L.RM_ESIZE
+    assert lib.rm_refine(R(idx), 1, 1, 1, 10, 8, 1, 8, 8, 1, 1, 1, ws, None) == L.RM_ESIZE
+    assert lib.rm_refine(R(idx), 1, 1, None, 10, 8, 1, 3, 8, 1, 1, 1, ws, None) == L.RM_EINVAL
     assert lib.rm_encode_reads_learned(R(idx), 1, 1, 10, 1, 1, 1, None) == L.RM_EUNSUPPORTED
     assert lib.rm_rescore_learned(R(idx), 1, 1, 1, 1, 1, 10, 8, 1, 8, 1, 1, None) \
         == L.RM_EUNSUPPORTED

@@ -8,7 +8,7 @@ import pytest
 
 import synth
 from oracle import mapping
-from tests.gpu_helpers import oracle_heads, oracle_windows, torch_cuda
+from tests.gpu_helpers import check_refined_lists, oracle_heads, oracle_windows, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -28,23 +28,6 @@ def step1_oracle():
     return ref, reads, F1
 
 
-def _check_against_oracle(tidx, tsc, cand, F1, stride, radius, k):
-    exact = 0
-    for r in range(F1.shape[0]):
-        want_i, want_f = mapping.refine_topk(F1[r], cand[r], stride, radius, k)
-        n = want_i.size
-        got = tidx[r, :n]
-        assert np.all(tidx[r, n:] == -1) and np.all(got >= 0), r
-        assert len(set(got.tolist())) == n, r                       # distinct starts
-        pool = set(mapping.refine_pool(cand[r], stride, radius, F1.shape[1]).tolist())
-        assert set(got.tolist()) <= pool, r                           # only refined starts
-        got_true = F1[r, got]
-        assert np.all(np.abs(got_true - want_f) <= mapping.TIE_TAU), r  # same ranking up to ties
-        assert np.max(np.abs(tsc[r, :n] - got_true)) < TOL_F, r
-        exact += int(np.array_equal(got, want_i))
-    return exact / F1.shape[0]
-
-
 @pytest.mark.parametrize("precision,stride,radius", [("fp32", 2, 1), ("fp16", 4, 3),
                                                      ("fp16", 8, 7), ("fp8", 4, 2)])
 def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
@@ -59,7 +42,7 @@ def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
     cand = bufs.cand_idx.cpu().numpy()
     tidx = bufs.top_idx.cpu().numpy()
     tsc = bufs.top_score.cpu().numpy()
-    same = _check_against_oracle(tidx, tsc, cand, F1, stride, radius, K)
+    same = check_refined_lists(tidx, tsc, cand, F1, stride, radius, K, TOL_F)
     # recall of the whole coarse path against every step-1 window
     W1 = F1.shape[1]
     o_idx, o_F = mapping.topk_rows(F1, np.arange(W1), K)
@@ -107,4 +90,4 @@ def test_refine_edges_and_invalid_candidates(step1_oracle):
         pool0 = mapping.refine_pool(c[0], stride, rad, F1.shape[1])[:k]
         assert list(tidx[0, :pool0.size]) == list(pool0)
         assert np.all(tsc[0, :pool0.size] == 0.0)
-        _check_against_oracle(tidx[1:], tsc[1:], c[1:], F1[1:R], stride, rad, k)
+        check_refined_lists(tidx[1:], tsc[1:], c[1:], F1[1:R], stride, rad, k, TOL_F)
