@@ -655,21 +655,46 @@ __global__ __launch_bounds__(256) void rescore_wide_kernel(
   }
 }
 
+// Sums of FP32 phases in 64-bit fixed point with 2^-40 units: an FP32 value of
+// magnitude 2^-17 or more is a whole number of units, a smaller one is off by
+// less than one unit, and integer addition gives the same total whatever order
+// the lanes' atomics land in.  |sum| <= N <= 2^14 keeps it below 2^54.
+constexpr float kFixScale = 1099511627776.0f;  // 2^40
+constexpr double kFixUnit = 1.0 / 1099511627776.0;
+constexpr int kAccLen = kWideComplex + kWideComplex / kWC;  // one pad slot per lane's 16
+
+// Accumulator slot of component `comp`: lane l's components 16l..16l+15 sit at
+// a stride of 17 slots, so the lanes' read-back spreads over the banks.
+__device__ __forceinline__ int acc_slot(int comp) { return comp + comp / kWC; }
+
+// Orders this wavefront's LDS accesses (a compiler barrier plus a wait on them);
+// no other wavefront is waited for.
+__device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 // Refinement around coarse candidates (§3.4), 1,024 components: the read head
 // as in rescore_wide_kernel, then per candidate (wavefront w takes candidates
-// w, w + 4, ...) the first step-1 window of its neighbourhood as a direct FP32
-// sum over its tokens and the next ones by one-token slides (every component
-// turns by omega^-f, the outgoing token's class loses omega^-f, the incoming
-// token's class gains omega^{f (N-s)}), each scored with its recomputed norm.
-// Slot i of the candidate's span in `pool` receives the key of start lo + i,
-// 0 past the clamped neighbourhood or for an invalid candidate.
+// w, w + 4, ...) the first step-1 window of its neighbourhood summed over its
+// tokens and the next ones by one-token slides (every component turns by
+// omega^-f, the outgoing token's class loses omega^-f, the incoming token's
+// class gains omega^{f (N-s)}), each scored with its recomputed norm.  The
+// first window's sum is scattered rather than gathered: each lane takes every
+// 64th token and adds phase[loc][k] to component k * n_class + class for each
+// factor k in the wavefront's fixed-point accumulator (64-bit LDS atomics),
+// which holds the exact sum of the FP32 phases; each lane then reads back its
+// 16 components rounded to FP32.  Slot i of the candidate's span in `pool`
+// receives the key of start lo + i, 0 past the clamped neighbourhood or for
+// an invalid candidate.
 __global__ __launch_bounds__(256) void refine_wide_kernel(
     const uint8_t* __restrict__ ref, int64_t W1, int N, int cstride, int64_t Wc, int s, int m,
     int n_class, const float2* __restrict__ phase32, const float4* __restrict__ step32,
     const uint8_t* __restrict__ table, const uint8_t* __restrict__ seq,
     const int64_t* __restrict__ off, int32_t R, int k_fetch, const int32_t* __restrict__ cand,
     int radius, uint64_t* __restrict__ pool) {
-  __shared__ float part[4][2 * kWC][64];
+  // four wavefronts' accumulators (real and imaginary planes); the head's
+  // partial sums use the front of the same memory before them
+  __shared__ __attribute__((aligned(16))) unsigned long long acc[4][2][kAccLen];
+  static_assert(sizeof(acc) >= 4 * 2 * kWC * 64 * sizeof(float), "head partials fit");
+  auto part = reinterpret_cast<float (*)[2 * kWC][64]>(&acc[0][0][0]);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r = blockIdx.x;
@@ -700,6 +725,9 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     xi[q] = ((part[0][2 * q + 1][lane] + part[1][2 * q + 1][lane]) + part[2][2 * q + 1][lane]) +
             part[3][2 * q + 1][lane];
   }
+  __syncthreads();  // every wavefront has read the partials before any accumulator is cleared
+  unsigned long long* accR = acc[wave][0];
+  unsigned long long* accI = acc[wave][1];
   float ax = 0.f;
 #pragma unroll
   for (int q = 0; q < kWC; ++q) ax += xr[q] * xr[q] + xi[q] * xi[q];
@@ -720,8 +748,30 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     }
     if (lane < span && lo + lane > hi) out[lane] = 0;
     if (hi < lo) continue;  // uniform
+    // the first window: clear this lane's components, scatter the tokens, read back
+#pragma unroll
+    for (int q = 0; q < kWC; ++q) {
+      accR[acc_slot(kWC * lane + q)] = 0;
+      accI[acc_slot(kWC * lane + q)] = 0;
+    }
+    lds_order();
+    for (int loc = lane; loc < T; loc += 64) {
+      const int c = token_class(ref + lo + loc, s, table);
+      if (c < 0 || c >= n_class) continue;  // no token, or a class no component has
+      for (int kk = 0; kk < m; ++kk) {
+        const float2 e = phase32[(int64_t)loc * m + kk];
+        const int slot = acc_slot(kk * n_class + c);
+        atomicAdd(&accR[slot], (unsigned long long)(long long)(e.x * kFixScale));
+        atomicAdd(&accI[slot], (unsigned long long)(long long)(e.y * kFixScale));
+      }
+    }
+    lds_order();
     float cr[kWC], ci[kWC];
-    wide_direct_sum(ref + lo, T, s, table, phase32, m, kf, c0, lane, cr, ci);
+#pragma unroll
+    for (int q = 0; q < kWC; ++q) {
+      cr[q] = (float)((double)(long long)accR[acc_slot(kWC * lane + q)] * kFixUnit);
+      ci[q] = (float)((double)(long long)accI[acc_slot(kWC * lane + q)] * kFixUnit);
+    }
     // lane i holds the classes of slide lo + i: the token leaving (at lo + i)
     // and the one entering (at lo + i + T, whose last letter lo + i + N <=
     // hi - 1 + N <= W1 - 2 + N = ref_len - 1)
