@@ -5,7 +5,9 @@ benchmark times, on outputs the oracle can compute one by one or has stored:
   top-16 lists of 64 sampled reads; sampled index rows and squared norms; the
   same with token indexes (2-mers FP16, 8-mers mapped to 16 classes FP8,
   8-mers mapped to 256 classes with m = 4 on the K = 2,048 product, FP16
-  and FP8, and the 128 most frequent 4-mers with m = 8);
+  and FP8, and the 128 most frequent 4-mers with m = 8); coarse indexes
+  (letters at stride 3, the 256-class tokens at stride 8) with step-1
+  refinement against the oracle's refinement of the same candidates;
 * scale (256 Mbp, FP8 index with FP64 re-anchor every 65,536 starts, top-16 of
   32): sampled index rows (re-anchor boundaries, the last windows), squared
   norms (rolling drift), rescored scores of sampled reads one window at a time,
@@ -204,6 +206,72 @@ def test_precision_workload_token_encoding_full_size(enc, precision):
     assert np.mean(np.abs(bufs.top_idx.cpu().numpy()[:, 0] - truth) <= 8) >= 0.99
     del index, rb, bufs
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("enc,precision,stride,radius", [(None, "fp16", 3, 2),
+                                                         ("s8c256", "fp8", 8, 7)])
+def test_precision_workload_coarse_refine_full_size(enc, precision, stride, radius):
+    """The precision workload on a coarse index with step-1 refinement (§3.4)
+    in the benchmark's configuration (`--coarse-stride`, 32 candidates, top 8):
+    for the 64 stored sample reads the refined lists equal the oracle's
+    refinement of the same coarse candidates (the oracle's fidelities over each
+    read's pool of step-1 starts), scores within 5e-6; with the 8-mer ->
+    256-class tokens (recall 1.0) also the stored step-1 token-oracle lists."""
+    torch = torch_cuda()
+    from oracle import tokens
+    from paper_2603_22245_amd import mapper
+    w = synth.WORKLOADS["precision"]
+    ref = w.reference()
+    reads = w.reads(ref)
+    N, k, k_fetch = w.window_len, w.k, 32
+    if enc is None:
+        index = mapper.build_index(ref, N, stride, precision, reanchor=w.reanchor)
+        g = _stored_lists("precision_top16_sample64.npz")
+    else:
+        s, m, C, tm, sched = synth.token_encoding(enc)
+        index = mapper.build_index(ref, N, stride, precision, sched, w.reanchor, mer_len=s,
+                                   n_freq=m, n_class=C, token_map=tm)
+        g = _stored_lists(f"precision_{enc}_top16_sample64.npz")
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
+    mapper.map_reads_coarse(index, rb, bufs, radius)
+    torch.cuda.synchronize()
+    cand = bufs.cand_idx.cpu().numpy()
+    tidx = bufs.top_idx.cpu().numpy()
+    tsc = bufs.top_score.cpu().numpy()
+    del index, rb, bufs
+    torch.cuda.empty_cache()
+
+    W1 = ref.shape[0] - N + 1
+    pick = np.asarray(g["reads"])
+    heads = mapping.read_heads(reads.seq, reads.offsets, N)[pick]
+    pools = [mapping.refine_pool(cand[r], stride, radius, W1) for r in pick]
+    idx = np.full((pick.size, max(p.size for p in pools)), -1, dtype=np.int64)
+    for i, p in enumerate(pools):
+        idx[i, :p.size] = p
+    if enc is None:
+        F = mapping.pair_fidelities(ref, heads, idx, N)
+    else:
+        F = tokens.pair_fidelities(ref, heads, idx, N, s, m, C, tm, schedule=sched)
+    exact, err = 0, 0.0
+    for i, r in enumerate(pick):
+        p = pools[i]
+        want_i, want_f = mapping.topk_rows(F[i, :p.size][None, :], p[None, :], k)
+        want_i, want_f = want_i[0], want_f[0]
+        n = want_i.size
+        got = tidx[r, :n]
+        assert np.all(tidx[r, n:] == -1) and len(set(got.tolist())) == n, r
+        where = {int(j): c for c, j in enumerate(p)}
+        assert all(int(j) in where for j in got), r                    # only refined starts
+        got_true = np.array([F[i, where[int(j)]] for j in got])
+        assert np.all(np.abs(got_true - want_f) <= TAU), r             # same ranking up to ties
+        err = max(err, float(np.max(np.abs(tsc[r, :n] - got_true))))
+        exact += int(np.array_equal(got, want_i))
+    print(f"{enc or 'letters'} {precision} stride {stride} radius {radius}: lists identical to "
+          f"the oracle's refinement {exact / pick.size:.3f}, max |dF| {err:.2e}")
+    assert err < 5e-6 and exact / pick.size >= 0.95
+    if enc is not None:
+        _check_against_stored(g, tidx, tsc, k, exact_min=0.95)
 
 
 # ---------------------------------------------------------------- scale
