@@ -39,21 +39,36 @@ SCORE_SOURCES = (
 )
 
 
-def score_source_digest() -> str:
+# sources of the 1,024-component product (K = 2,048)
+WIDE_SOURCES = (
+    "paper_2603_22245_amd/csrc/rm_wide.hip",
+    "paper_2603_22245_amd/csrc/rm_tokens.h",
+    "paper_2603_22245_amd/csrc/rm_internal.h",
+    "paper_2603_22245_amd/build.py",
+)
+
+
+def score_source_digest(sources=SCORE_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in SCORE_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, tokens=None):
     """HBM bytes per scoring launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE of a rocprofv3 --pmc run of this benchmark,
     scaled by a plain copy's readings), or None when there is no summary for
-    this precision or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"score_topk_{precision}_precision_traffic.txt")
+    this precision and encoding or the kernel sources changed since it was
+    taken.  tokens: None (letters, score_topk_kernel) or the name of a
+    1,024-component token encoding (score_wide_kernel)."""
+    if tokens is None:
+        name, sources = f"score_topk_{precision}_precision_traffic.txt", SCORE_SOURCES
+    else:
+        name, sources = f"score_wide_{precision}_{tokens}_precision_traffic.txt", WIDE_SOURCES
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
@@ -61,7 +76,7 @@ def measured_traffic(precision: str):
             d = json.loads(fh.read().split("```json", 1)[1].split("```", 1)[0])
     except (IndexError, ValueError):
         return None
-    if d.get("source_sha256") != score_source_digest():
+    if d.get("source_sha256") != score_source_digest(sources):
         return None
     return d.get("bytes_per_launch")
 
@@ -87,8 +102,8 @@ def parse():
     ap.add_argument("--corr-pairs", type=int, default=100_000,
                     help="correlation workload: pairs over all mutation rates")
     ap.add_argument("--tokens", default=None,
-                    help="token encoding (s-mers, compact maps): s2 | s3 | s8c16 "
-                         "(default: the letter encoding)")
+                    help="token encoding (s-mers, compact maps): s2 | s3 | s8c16 | s4m4 | "
+                         "s8c256 | s4f128 (default: the letter encoding)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
     ap.add_argument("--cpu-reads", type=int, default=8)
@@ -242,8 +257,9 @@ def main():
     achieved = R * W * flops_per_score / score_s / 1e12
     peak = PEAK_TFLOPS[precision]
     enc_bytes = W * (real_dim * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
-    traffic = (measured_traffic(precision) if R == w.n_reads and not coarse and not args.tokens
-               else None)
+    traffic = None
+    if R == w.n_reads and not coarse and (args.tokens is None or wide):
+        traffic = measured_traffic(precision, args.tokens)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": ("score_wide_kernel (+merge_wide_kernel)" if wide
