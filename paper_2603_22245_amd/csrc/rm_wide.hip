@@ -360,16 +360,20 @@ __global__ __launch_bounds__(kThreads, 1) void score_wide_kernel(
     is_b[i] = row >= kTM;
     src_off[i] = (is_b[i] ? (int64_t)(row - kTM) : min(row0 + row, M - 1)) * kRowBytes + c * 16;
   }
+  // Stage st of a tile holds K line st, or line kStages - 1 - st on every
+  // other tile of the chunk: a tile then starts on the read rows' lines the
+  // previous one ended on, which the XCD's L2 still holds.
   auto issue = [&](int64_t tile, int st) {
     const uint32_t base = ring_lds + (uint32_t)(st % kRing) * kStageBytes;
+    const int64_t kl = (int64_t)(((tile - t0) & 1) ? kStages - 1 - st : st) * kLine;
 #pragma unroll
     for (int i = 0; i < kDmaPerWave; ++i) {
       const uint8_t* src;
       if (is_b[i]) {
         const int64_t g = min(tile * kTN + src_off[i] / kRowBytes, W - 1);
-        src = B + g * kRowBytes + (src_off[i] % kRowBytes) + st * kLine;
+        src = B + g * kRowBytes + (src_off[i] % kRowBytes) + kl;
       } else {
-        src = A + src_off[i] + st * kLine;
+        src = A + src_off[i] + kl;
       }
       dma16w(src, __builtin_amdgcn_readfirstlane(base + 1024 * (wave + kWaves * i)));
     }
