@@ -675,19 +675,22 @@ __device__ __forceinline__ int acc_slot(int comp) { return comp + comp / kWC; }
 // no other wavefront is waited for.
 __device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-// Refinement around coarse candidates (§3.4), 1,024 components: the read head
-// as in rescore_wide_kernel, then per candidate (wavefront w takes candidates
-// w, w + 4, ...) the first step-1 window of its neighbourhood summed over its
-// tokens and the next ones by one-token slides (every component turns by
-// omega^-f, the outgoing token's class loses omega^-f, the incoming token's
-// class gains omega^{f (N-s)}), each scored with its recomputed norm.  The
-// first window's sum is scattered rather than gathered: each lane takes every
-// 64th token and adds phase[loc][k] to component k * n_class + class for each
-// factor k in the wavefront's fixed-point accumulator (64-bit LDS atomics),
-// which holds the exact sum of the FP32 phases; each lane then reads back its
-// 16 components rounded to FP32.  Slot i of the candidate's span in `pool`
-// receives the key of start lo + i, 0 past the clamped neighbourhood or for
-// an invalid candidate.
+// Refinement around coarse candidates (§3.4), 1,024 components, with the
+// rolling inner product: O(m) work per one-token slide.  The read head as in
+// rescore_wide_kernel; then per candidate (wavefront w takes candidates w,
+// w + 4, ...) the first step-1 window of its neighbourhood is summed over its
+// tokens with locations counted from that window's start lo: each lane takes
+// every 64th token and adds phase[loc][k] to component k * n_class + class for
+// each factor k in the wavefront's fixed-point accumulator u (64-bit LDS
+// atomics; the exact sum of the FP32 phases).  Window lo + i is then
+// omega^(-f_k i) u_i, where u_i has lost omega^(f i) at the class of each
+// token that left and gained omega^(f (i + T)) at the class of each token
+// that entered, so with P_k = sum over factor k's components of conj(x) u
+// (lane k) and S = |u|^2 (rotation keeps norms), <x|c> = sum_k
+// omega^(-f_k i) P_k and |c|^2 = S: a slide changes two components per factor
+// and updates P_k and S by their changes (FP64).  Slot i of the candidate's
+// span in `pool` receives the key of start lo + i, 0 past the clamped
+// neighbourhood or for an invalid candidate.
 __global__ __launch_bounds__(256) void refine_wide_kernel(
     const uint8_t* __restrict__ ref, int64_t W1, int N, int cstride, int64_t Wc, int s, int m,
     int n_class, const float2* __restrict__ phase32, const float4* __restrict__ step32,
@@ -697,6 +700,7 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
   // four wavefronts' accumulators (real and imaginary planes); the head's
   // partial sums use the front of the same memory before them
   __shared__ __attribute__((aligned(16))) unsigned long long acc[4][2][kAccLen];
+  __shared__ float2 xs[kWideComplex];  // the read head's components
   static_assert(sizeof(acc) >= 4 * 2 * kWC * 64 * sizeof(float), "head partials fit");
   auto part = reinterpret_cast<float (*)[2 * kWC][64]>(&acc[0][0][0]);
   const int lane = threadIdx.x & 63;
@@ -729,7 +733,13 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     xi[q] = ((part[0][2 * q + 1][lane] + part[1][2 * q + 1][lane]) + part[2][2 * q + 1][lane]) +
             part[3][2 * q + 1][lane];
   }
-  __syncthreads();  // every wavefront has read the partials before any accumulator is cleared
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < kWC; ++q) xs[kWC * lane + q] = make_float2(xr[q], xi[q]);
+  }
+  // every wavefront has read the partials before any accumulator is cleared,
+  // and the head's components are in xs
+  __syncthreads();
   unsigned long long* accR = acc[wave][0];
   unsigned long long* accI = acc[wave][1];
   float ax = 0.f;
@@ -737,9 +747,12 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
   for (int q = 0; q < kWC; ++q) ax += xr[q] * xr[q] + xi[q] * xi[q];
   const float X = wave_sum(ax);
   const bool xdeg = X < kDegenerateRel * (float)N;
-  const float4 st = step32[kf];
-  const float rr = st.x, ri = st.y;  // omega^-f
-  const float ir = st.z, ii = st.w;  // omega^(f (N-s))
+  // lanes k < m carry factor k: omega^f, and omega^(f T) (T = N - s + 1)
+  const int G = n_class / kWC;  // lanes per factor; m * G = 64
+  const bool fl = lane < m;
+  const float4 st = step32[fl ? lane : 0];
+  const float2 fwd = make_float2(st.x, -st.y);             // omega^f
+  const float2 adv = cmul(fwd, make_float2(st.z, st.w));  // omega^f omega^(f (N-s))
 
   for (int e = wave; e < k_fetch; e += 4) {
     uint64_t* out = pool + (r * k_fetch + e) * span;
@@ -752,7 +765,9 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     }
     if (lane < span && lo + lane > hi) out[lane] = 0;
     if (hi < lo) continue;  // uniform
-    // the first window: clear this lane's components, scatter the tokens, read back
+    // the first window, locations relative to lo: clear this lane's
+    // components, scatter the tokens
+    lds_order();
 #pragma unroll
     for (int q = 0; q < kWC; ++q) {
       accR[acc_slot(kWC * lane + q)] = 0;
@@ -770,12 +785,26 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
       }
     }
     lds_order();
-    float cr[kWC], ci[kWC];
+    // u = that window's components: P_k = sum over factor k's components of
+    // conj(x) u (lane k), S = |u|^2
+    double pr = 0.0, pi = 0.0, sq = 0.0;
 #pragma unroll
     for (int q = 0; q < kWC; ++q) {
-      cr[q] = (float)((double)(long long)accR[acc_slot(kWC * lane + q)] * kFixUnit);
-      ci[q] = (float)((double)(long long)accI[acc_slot(kWC * lane + q)] * kFixUnit);
+      const double ur = (double)(long long)accR[acc_slot(kWC * lane + q)] * kFixUnit;
+      const double ui = (double)(long long)accI[acc_slot(kWC * lane + q)] * kFixUnit;
+      pr += (double)xr[q] * ur + (double)xi[q] * ui;
+      pi += (double)xr[q] * ui - (double)xi[q] * ur;
+      sq += ur * ur + ui * ui;
     }
+    for (int d = 1; d < G; d <<= 1) {  // a factor's G lanes are contiguous and aligned
+      pr += __shfl_xor(pr, d, 64);
+      pi += __shfl_xor(pi, d, 64);
+    }
+    double Pr = __shfl(pr, fl ? lane * G : 0, 64), Pi = __shfl(pi, fl ? lane * G : 0, 64);
+    if (!fl) Pr = Pi = 0.0;
+    double S = wave_sum(sq);
+    float2 wt = make_float2(1.f, 0.f);  // omega^(f_k i) at slide i, lanes k < m
+
     // lane i holds the classes of slide lo + i: the token leaving (at lo + i)
     // and the one entering (at lo + i + T, whose last letter lo + i + N <=
     // hi - 1 + N <= W1 - 2 + N = ref_len - 1)
@@ -784,28 +813,36 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     const int in_c = tl < hi ? token_class(ref + tl + T, s, table) : kNoToken;
     uint64_t mine = 0;
     for (int64_t t = lo; t <= hi; ++t) {
-      float ac = 0.f, pr = 0.f, pi = 0.f;
-#pragma unroll
-      for (int q = 0; q < kWC; ++q) {
-        ac += cr[q] * cr[q] + ci[q] * ci[q];
-        pr += xr[q] * cr[q] + xi[q] * ci[q];  // <x|c> = sum conj(x) c
-        pi += xr[q] * ci[q] - xi[q] * cr[q];
-      }
-      const float C = wave_sum(ac), ipr = wave_sum(pr), ipi = wave_sum(pi);
-      const bool deg = xdeg || C < kDegenerateRel * (float)N;
-      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+      // window t's components are omega^(-f_k (t - lo)) u: <x|c> = sum_k conj(wt_k) P_k
+      const double ipr = wave_sum((double)wt.x * Pr + (double)wt.y * Pi);
+      const double ipi = wave_sum((double)wt.x * Pi - (double)wt.y * Pr);
+      const bool deg = xdeg || S < (double)kDegenerateRel * N;
+      const float F = deg ? 0.f : (float)((ipr * ipr + ipi * ipi) / ((double)X * S));
       if (lane == (int)(t - lo)) mine = wide_key(F, t);
       if (t < hi) {
         const int i = (int)(t - lo);
-        const int o = __builtin_amdgcn_readlane(out_c, i) - c0;
-        const int n = __builtin_amdgcn_readlane(in_c, i) - c0;
-#pragma unroll
-        for (int q = 0; q < kWC; ++q) {
-          const float a = cr[q] * rr - ci[q] * ri;
-          const float b = cr[q] * ri + ci[q] * rr;
-          cr[q] = a - (o == q ? rr : 0.f) + (n == q ? ir : 0.f);
-          ci[q] = b - (o == q ? ri : 0.f) + (n == q ? ii : 0.f);
-        }
+        const int oc = __builtin_amdgcn_readlane(out_c, i);
+        const int ic = __builtin_amdgcn_readlane(in_c, i);
+        double dS = 0.0;
+        // lane k changes component k * n_class + class of each token by d:
+        // P_k += conj(x) d, S += 2 Re(conj(u) d) + |d|^2, u += d (exactly)
+        auto change = [&](int cls, float2 d) {
+          const int comp = lane * n_class + cls;
+          const int sl = acc_slot(comp);
+          const double ur = (double)(long long)accR[sl] * kFixUnit;
+          const double ui = (double)(long long)accI[sl] * kFixUnit;
+          const float2 xv = xs[comp];
+          Pr += (double)xv.x * d.x + (double)xv.y * d.y;
+          Pi += (double)xv.x * d.y - (double)xv.y * d.x;
+          dS += 2.0 * (ur * d.x + ui * d.y) + (double)d.x * d.x + (double)d.y * d.y;
+          accR[sl] += (unsigned long long)(long long)(d.x * kFixScale);
+          accI[sl] += (unsigned long long)(long long)(d.y * kFixScale);
+        };
+        // leaving: relative location i, omega^(f i); entering: i + T
+        if (fl && oc >= 0 && oc < n_class) change(oc, make_float2(-wt.x, -wt.y));
+        if (fl && ic >= 0 && ic < n_class) change(ic, cmul(wt, adv));
+        S += wave_sum(dS);
+        wt = cmul(wt, fwd);
       }
     }
     if (lane <= (int)(hi - lo)) out[lane] = mine;
