@@ -1,8 +1,8 @@
 """Pins of the s-mer token oracle (oracle.tokens) against what the paper and
 the mathematics fix: the s = 1 case of §2.1-§2.3 (oracle.rope, pinned on its
 own), the §2.10 matrix-power formulation, a closed-form geometric sum, brute
-force over token locations found by string slicing, the §3.4 slide against
-direct encoding, linearity of the compact map (§2.6) and exact-substring
+force over token locations found by string slicing, the §3.4 slide and the
+rolling inner product against direct encoding, linearity of the compact map (§2.6) and exact-substring
 mapping (§3.1)."""
 import itertools
 
@@ -209,3 +209,35 @@ def test_frequent_map_by_hand():
     # more classes than distinct 2-mers present: unseen codes fill by code order
     mp = tokens.frequent_map(ref, 2, 8)
     assert np.sum(mp >= 0) == 8 and sorted(mp[mp >= 0].tolist()) == list(range(8))
+
+
+@pytest.mark.parametrize("name", ["s8c256", "s4m4"])
+def test_rolling_inner_product_over_slides(name):
+    """§3.4's rolling inner product, the form the 1,024-component refinement
+    uses: with u the first window's components (locations counted from its
+    start), u losing omega^(f i) at the class of each token that leaves and
+    gaining omega^(f (i + T)) at the class of each token that enters, window i
+    is omega^(-f i) u, so <x|c_i> = sum_k omega^(-f_k i) P_k with P_k the
+    factor-k part of <x|u>, and |c_i|^2 = |u|^2.  Checked against the direct
+    encodings of every window for 14 slides."""
+    s, m, C, tm, sched = synth.token_encoding(name)
+    N = 150
+    T = N - s + 1
+    rng = np.random.default_rng(21)
+    ref = _rand(600, rng)
+    x = tokens.encode_raw(_rand(N, rng), N, s, m, C, tm, sched).reshape(m, C)
+    lo = 200
+    u = tokens.encode_raw(ref[lo:lo + N], N, s, m, C, tm, sched).reshape(m, C)
+    cls = tokens.token_classes(ref, s, tm)
+    step = rope.unit_phases(N, m, np.array([1]), sched)[0]      # omega^(f_k)
+    for i in range(15):
+        c = tokens.encode_raw(ref[lo + i:lo + i + N], N, s, m, C, tm, sched).reshape(m, C)
+        wt = step ** i
+        P = np.sum(np.conj(x) * u, axis=1)
+        assert np.isclose(np.sum(np.conj(wt) * P), np.vdot(x, c), rtol=0, atol=1e-9)
+        assert np.isclose(np.sum(np.abs(u) ** 2), np.sum(np.abs(c) ** 2), rtol=1e-12)
+        o, n = cls[lo + i], cls[lo + i + T]
+        if 0 <= o < C:
+            u[:, o] -= wt
+        if 0 <= n < C:
+            u[:, n] += wt * step ** T
