@@ -442,7 +442,7 @@ REFINE_TOL = 5e-6  # FP32 direct sum over the tokens plus at most 2 radius one-t
 
 @pytest.mark.parametrize("enc,precision,stride,radius", [
     ("s2", "fp16", 4, 3), ("s3", "fp32", 2, 1), ("s8c16", "fp8", 8, 7),
-    ("s8c256", "fp16", 4, 3), ("s8c256", "fp8", 8, 7)])
+    ("s8c256", "fp16", 4, 3), ("s8c256", "fp8", 8, 7), ("s4m4", "fp16", 2, 1)])
 def test_token_coarse_index_then_refine(enc, precision, stride, radius, plain_data, oracle_F):
     """A coarse token index (stride sigma), the product over its windows, then
     rm_refine over the step-1 windows near each candidate: the refined lists
