@@ -26,8 +26,11 @@ b2 [128], row-major.
 
 Pins: W2 = b2 = 0 reduces to the plain encoding (exact); the analytic gradient
 equals central finite differences; the loss's gradient w.r.t. F matches finite
-differences.  The Spearman gain of a trained network over the plain encoding
-has no paper value: parity unpinned.
+differences; the loss and its gradient on a hand-worked batch of four pairs
+(one pair ranked the wrong way, one label tie); Adam on hand-worked two-step
+scalar examples and its constant-gradient invariant (m_hat = g, v_hat = g^2).
+The Spearman gain of a trained network over the plain encoding has no paper
+value: parity unpinned.
 """
 from __future__ import annotations
 
@@ -181,6 +184,29 @@ def ranking_loss(F, ld, tau: float = TAU):
     return loss, dF
 
 
+ADAM_BETA1, ADAM_BETA2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def adam_step(params, m, v, t: int, grad, lr: float, beta1: float = ADAM_BETA1,
+              beta2: float = ADAM_BETA2, eps: float = ADAM_EPS):
+    """One Adam update (Kingma and Ba, "Adam: a method for stochastic
+    optimization", ICLR 2015, Algorithm 1), the optimiser the training uses.
+
+    t is the number of updates already applied (0 before the first).  The
+    first and second moment estimates decay by beta1 and beta2, each is
+    divided by its bias-correction factor 1 - beta^(t+1), and the parameters
+    move by lr * m_hat / (sqrt(v_hat) + eps).  Returns (params, m, v, t + 1)
+    as new arrays."""
+    params = np.asarray(params, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    t = int(t) + 1
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return params - lr * m_hat / (np.sqrt(v_hat) + eps), m, v, t
+
+
 def backward_string(params, cache, G, m: int = 32):
     """Gradient of a real function of c w.r.t. the parameters, given G = its gradient
     w.r.t. c (convention of `fidelity_and_grads`).  c_{k,L} gains i exp(i phi) per
@@ -295,7 +321,7 @@ def map_reads(params, ref, heads, N: int, k: int = 8, bf16: bool = True, m: int 
         allF = np.concatenate([best_f, F], axis=1)
         allI = np.concatenate([best_i, np.broadcast_to(ids, F.shape)], axis=1)
         best_i, best_f = mapping.topk_rows(allF, allI, k)
-    return best_i, best_f
+    return mapping.no_location(best_i, best_f), best_f
 
 
 def head_window_fidelities(params, ref, heads, idx, N: int, bf16: bool = True,

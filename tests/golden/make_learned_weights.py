@@ -5,7 +5,7 @@ Writes tests/golden/learned_weights.npy (10,432 float32 values, the layout of
 oracle.learned) trained on the first n pairs of the learned-offsets workload
 (synth.mutate_pairs, 150 bp, 0..30 edits, seed synth.PAIRS_SEED), labels by the
 oracle's edit distance, loss and gradient by oracle.learned.batch_loss_and_grad,
-Adam (beta 0.9 / 0.999, eps 1e-8, lr 3e-3), batches of 256 in order.  These
+oracle.learned.adam_step (beta 0.9 / 0.999, eps 1e-8, lr 3e-3), batches of 256 in order.  These
 weights give the mapping tests and the learned-encoding mapping sample a
 trained network that no GPU code produced.  Only the oracle and the seeded
 input generators are used.
@@ -37,10 +37,7 @@ def main(n: int, epochs: int, batch: int = 256, lr: float = 3e-3):
     for ep in range(epochs):
         for i in range(0, n - batch + 1, batch):
             loss, g, _ = learned.batch_loss_and_grad(params, pairs[i:i + batch], ld[i:i + batch], N)
-            t += 1
-            m = 0.9 * m + 0.1 * g
-            v = 0.999 * v + 0.001 * g * g
-            params = params - lr * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+            params, m, v, t = learned.adam_step(params, m, v, t, g, lr)
         held = pairs[n:]
         Fl = learned.pair_fidelities(params, held, N)
         Fp = learned.pair_fidelities(learned.init_params(0), held, N)

@@ -187,3 +187,82 @@ def test_token_offsets_blocking_changes_nothing():
         m2, d2 = learned.token_offsets(params, w, bf16, block=333)
         np.testing.assert_array_equal(m1, m2)
         np.testing.assert_array_equal(d1, d2)
+
+
+# ---- hand-worked values of the loss and of the optimiser ----------------------
+
+def test_ranking_loss_hand_worked_four_pairs():
+    """F = (0.9, 0.5, 0.4, 0.6), labels (1, 3, 2, 3).  The ordered pairs with
+    d_i < d_j are (0,1), (0,2), (0,3), (2,1), (2,3); (1,3) is a label tie and
+    does not count, and (2,1) is ranked the wrong way (F_2 < F_1 although
+    d_2 < d_1).  F_i - F_j = 0.4, 0.5, 0.3, -0.1, -0.2, so with tau = 0.05 the
+    softplus arguments -(F_i - F_j)/tau are -8, -10, -6, 2, 4 and
+      loss = (ln(1+e^-8) + ln(1+e^-10) + ln(1+e^-6) + ln(1+e^2) + ln(1+e^4)) / 5
+           = (0.000335406 + 0.0000453989 + 0.00247569 + 2.12692801 + 4.01814993) / 5
+           = 1.22958688587.
+    dloss/dF_i sums sigma(z)/(tau * 5) with sign -1 where i is the lower-label
+    member of a pair and +1 where it is the higher one:
+      dF_0 = -(sigma(-8) + sigma(-10) + sigma(-6)) / 0.25 = -0.0114134846
+      dF_1 = (sigma(-8) + sigma(2)) / 0.25             =  3.52452971
+      dF_2 = (sigma(-10) - sigma(2) - sigma(4)) / 0.25  = -7.45106188
+      dF_3 = (sigma(-6) + sigma(4)) / 0.25             =  3.93794565
+    A flipped sign or a reversed label mask gives 4.83; counting the tie adds
+    a sixth pair."""
+    loss, dF = learned.ranking_loss(np.array([0.9, 0.5, 0.4, 0.6]), np.array([1, 3, 2, 3]))
+    assert abs(loss - 1.2295868858741251) < 1e-13
+    np.testing.assert_allclose(dF, [-0.011413484623214747, 3.5245297124333957,
+                                    -7.451061880588354, 3.9379456527781729],
+                               rtol=1e-12, atol=1e-15)
+
+
+def test_ranking_loss_no_ordered_pair_is_zero():
+    loss, dF = learned.ranking_loss(np.array([0.3, 0.8, 0.1]), np.array([2, 2, 2]))
+    assert loss == 0.0 and np.all(dF == 0.0)
+
+
+def test_adam_two_steps_hand_worked_default_constants():
+    """theta_0 = 1, lr = 0.1, gradients 0.5 then -1 (beta 0.9 / 0.999, eps 1e-8).
+    Step 1: m = 0.05, v = 0.00025, m_hat = 0.05/0.1 = 0.5, v_hat =
+    0.00025/0.001 = 0.25, theta_1 = 1 - 0.1 * 0.5 / (0.5 + 1e-8) = 0.900000002.
+    Step 2: m = 0.045 - 0.1 = -0.055, v = 0.00024975 + 0.001 = 0.00124975,
+    m_hat = -0.055/0.19 = -0.289473684, v_hat = 0.00124975/0.001999 =
+    0.625187594, theta_2 = theta_1 + 0.1 * 0.289473684 / 0.790688 = 0.936610354."""
+    th, m, v, t = learned.adam_step(np.array([1.0]), np.zeros(1), np.zeros(1), 0,
+                                    np.array([0.5]), 0.1)
+    assert t == 1 and abs(m[0] - 0.05) < 1e-16 and abs(v[0] - 0.00025) < 1e-18
+    assert abs(th[0] - 0.90000000199999996) < 1e-15
+    th, m, v, t = learned.adam_step(th, m, v, t, np.array([-1.0]), 0.1)
+    assert t == 2 and abs(m[0] + 0.055) < 1e-16 and abs(v[0] - 0.00124975) < 1e-17
+    assert abs(th[0] - 0.93661035424056560) < 1e-14
+
+
+def test_adam_two_steps_hand_worked_closed_form():
+    """beta1 = beta2 = 0.5, eps = 0, lr = 1, theta_0 = 0, gradients 2 then 4.
+    Step 1: m = 1, v = 2, m_hat = 2, v_hat = 4: theta_1 = -2/2 = -1.
+    Step 2: m = 0.5 + 2 = 2.5, v = 1 + 8 = 9, m_hat = 2.5/0.75 = 10/3,
+    v_hat = 9/0.75 = 12: theta_2 = -1 - (10/3)/sqrt(12) = -1 - 5 sqrt(3)/9.
+    Without the bias corrections step 2 would move by 2.5/3 instead."""
+    kw = dict(beta1=0.5, beta2=0.5, eps=0.0)
+    th, m, v, t = learned.adam_step(np.zeros(1), np.zeros(1), np.zeros(1), 0, np.array([2.0]),
+                                    1.0, **kw)
+    assert th[0] == -1.0 and m[0] == 1.0 and v[0] == 2.0
+    th, m, v, t = learned.adam_step(th, m, v, t, np.array([4.0]), 1.0, **kw)
+    assert m[0] == 2.5 and v[0] == 9.0 and t == 2
+    assert abs(th[0] - (-1.0 - 5.0 * np.sqrt(3.0) / 9.0)) < 1e-15
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With the same gradient g at every step the bias-corrected moments are
+    exactly m_hat = g and v_hat = g^2, so each step moves every parameter by
+    lr * g / (|g| + eps), whatever the step count."""
+    rng = np.random.default_rng(40)
+    g = rng.normal(size=50) * np.exp(rng.uniform(-5, 5, 50))
+    th = rng.normal(size=50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    t = 0
+    for step in range(1, 8):
+        prev = th
+        th, m, v, t = learned.adam_step(th, m, v, t, g, 0.01)
+        np.testing.assert_allclose(prev - th, 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+        assert t == step
