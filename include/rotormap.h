@@ -35,6 +35,12 @@
  *  - Candidate lists are ordered by fidelity descending, then by window id
  *    ascending.  Window id j is the window starting at reference position
  *    j * stride.
+ *  - §3 asks for a read's position only if one exists.  An entry whose
+ *    fidelity is 0 (the read head or the window is the zero vector: a
+ *    degenerate string, or a read shorter than N) is no location and is
+ *    written as id -1 with score 0; so is a slot left empty because there
+ *    are fewer candidates than slots.  A read with no location has id -1,
+ *    score 0 in every slot.
  */
 #ifndef ROTORMAP_H
 #define ROTORMAP_H
@@ -154,7 +160,8 @@ int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* 
  * window row gives Re and Im of <x|c>).  0 if invalid. */
 size_t rm_read_emb_bytes(int32_t n_reads, const rm_params* p);
 
-/* Encode the head (first N letters) of every read (§3.1): FP64 direct sum,
+/* Encode the head (first N letters) of every read (§3.1): FP32 direct sum of the
+ * FP32 angle table (rounded from the FP64 one) over the head's letters,
  * normalised, stored in the index precision.  Read r is
  * d_seq[d_off[r] .. d_off[r+1]) (d_off: n_reads+1 int64, device).  A read
  * shorter than N is encoded as the zero vector.  A token index sums the
@@ -173,7 +180,8 @@ size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_
  * index precision with FP32 accumulation; the full score matrix is never
  * stored.  Outputs [n_reads][k_fetch]: window ids (int32) and fidelities
  * (float, computed from the stored embeddings).  Ties are broken by lower
- * window id, exactly.  If W < k_fetch the tail is filled with id -1, score -1.
+ * window id, exactly.  If W < k_fetch the tail is filled with id -1, score 0;
+ * a read with no location (see the conventions) has id -1, score 0 throughout.
  * d_read_scale may be NULL unless the precision is FP8.
  * Errors: RM_EINVAL, RM_ESIZE (k_fetch outside 1..RM_MAX_KFETCH, ws too small). */
 int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
@@ -185,7 +193,8 @@ int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_re
  * read head's encoding are recomputed directly from the letters with the
  * FP32 angle table (never from the stored low-precision index), F =
  * |<x|c>|^2 / (X C) in FP32, sorted by (F desc, window id asc).  Candidates
- * with id < 0 are skipped; missing entries are filled with id -1, score -1.
+ * with id < 0 are skipped; missing entries and entries with F = 0 are id -1,
+ * score 0 (a read shorter than N, or with a degenerate head, has no location).
  * A token index recomputes the encodings over its tokens and classes the same
  * way.  Errors: RM_EINVAL, RM_ESIZE (k < 1 or k > k_fetch). */
 int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,
@@ -241,7 +250,7 @@ int rm_reverse_complement(const uint8_t* d_seq, const int64_t* d_off, int32_t n_
  * (F desc, window id asc) as rm_rescore returns them, into the k best ranked
  * the same way, the forward entry first on a full tie; entries with id < 0 or
  * F < min_fidelity are dropped.  Outputs [n_reads][k]: window ids, F, strand
- * (int8: 0 forward, 1 reverse complement; -1 with id -1 and F -1 past the
+ * (int8: 0 forward, 1 reverse complement; -1 with id -1 and F 0 past the
  * kept entries) and d_n_found [n_reads], the number kept (0 = unmapped).
  * Errors: RM_EINVAL (null pointer), RM_ESIZE (n_reads < 1, k outside
  * 1..RM_MAX_KFETCH). */
@@ -272,9 +281,10 @@ size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radiu
  * the coarse index `coarse`, e.g. rm_score_topk's output; ids < 0 or >= W are
  * skipped) into d_top_idx / d_top_score [n_reads][k]: step-1 window starts
  * (the window ids of a stride-1 index of the same reference) and their FP32
- * fidelities; missing entries are id -1, score -1.  d_ref is the coarse
- * index's reference, d_seq / d_off the reads as in rm_encode_reads (a read
- * shorter than N scores 0 everywhere).  d_ws: caller-owned device workspace of
+ * fidelities; missing entries and entries with F = 0 are id -1, score 0.
+ * d_ref is the coarse index's reference, d_seq / d_off the reads as in
+ * rm_encode_reads (a read shorter than N scores 0 everywhere, so it has no
+ * location).  d_ws: caller-owned device workspace of
  * rm_refine_workspace_bytes.  Asynchronous on `stream`.
  * Errors: RM_EINVAL (null pointer, invalid index), RM_ESIZE (n_reads < 1,
  * k_fetch outside 1..RM_MAX_KFETCH, radius outside 0..RM_REFINE_MAX_RADIUS,

@@ -10,7 +10,8 @@ windows are the candidate locations.
 Here: window starts j = 0, sigma, 2 sigma, ... up to G-N, so there are
 W = floor((G-N)/sigma) + 1 windows; F(r, j) = |<x_r|c_j>|^2 / (X_r C_j) with
 F = 0 when either vector is degenerate; the top-k list of a read is ordered by
-F descending, then by the window's position in the index ascending.
+F descending, then by the window's position in the index ascending, and an
+entry with F = 0 is no location (id -1, score 0).
 
 Windows are processed in chunks to bound memory.  The top-k of a union of
 chunks is the top-k of the union of the chunks' top-k lists, so merging the
@@ -43,12 +44,30 @@ def window_letters(ref: np.ndarray, starts: np.ndarray, N: int) -> np.ndarray:
     return ref[starts[:, None] + np.arange(N)[None, :]]
 
 
+NO_LETTER = 4  # a code outside A,C,G,T: it adds nothing to any encoding
+
+
 def read_heads(seq: np.ndarray, offsets: np.ndarray, N: int) -> np.ndarray:
-    """First N letters of every read, [R, N]; a read shorter than N is an error."""
+    """First N letters of every read, [R, N] (§3.1 encodes a read's head).  A
+    read shorter than N has no head of length N: its row is all NO_LETTER,
+    which encodes as the zero vector, so it scores 0 with every window and has
+    no location."""
     offsets = np.asarray(offsets, dtype=np.int64)
-    if np.any(np.diff(offsets) < N):
-        raise ValueError("a read is shorter than the window length")
-    return seq[offsets[:-1, None] + np.arange(N)[None, :]]
+    short = np.diff(offsets) < N
+    pos = np.where(short[:, None], 0, offsets[:-1, None] + np.arange(N)[None, :])
+    heads = np.asarray(seq)[pos].astype(np.uint8)
+    heads[short] = NO_LETTER
+    return heads
+
+
+def no_location(ids: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """§3 asks for a read's position only if one exists.  A fidelity of exactly
+    0 means the read head or the window is the zero vector (degenerate, or a
+    read shorter than N), so that window is no location: its id becomes -1
+    (its score stays 0).  Returns the new ids."""
+    ids = np.array(ids, copy=True)
+    ids[np.asarray(F) == 0] = -1
+    return ids
 
 
 def normalized_rows(C: np.ndarray, N: int):
@@ -114,7 +133,7 @@ def map_reads(ref: np.ndarray, heads: np.ndarray, N: int, m: int = 32, k: int = 
         allF = np.concatenate([best_f, F], axis=1)
         allI = np.concatenate([best_i, np.broadcast_to(ids, F.shape)], axis=1)
         best_i, best_f = topk_rows(allF, allI, k)
-    return best_i, best_f
+    return no_location(best_i, best_f), best_f
 
 
 def pair_fidelity(ref: np.ndarray, head: np.ndarray, j: int, N: int, m: int = 32,
@@ -161,7 +180,7 @@ def refine_topk(F1_row: np.ndarray, coarse_ids, stride: int, radius: int, k: int
     if pool.size == 0:
         return np.zeros(0, dtype=np.int64), np.zeros(0)
     i, f = topk_rows(F1_row[pool][None, :], pool[None, :], k)
-    return i[0], f[0]
+    return no_location(i[0], f[0]), f[0]
 
 
 def reverse_complement(seq: np.ndarray) -> np.ndarray:

@@ -228,7 +228,7 @@ def map_reads(ref: np.ndarray, heads: np.ndarray, N: int, s: int, m: int, n_clas
         best_i, best_f = mapping.topk_rows(np.concatenate([best_f, F], axis=1),
                                            np.concatenate([best_i, np.broadcast_to(ids, F.shape)],
                                                           axis=1), k)
-    return best_i, best_f
+    return mapping.no_location(best_i, best_f), best_f
 
 
 def pair_fidelities(ref: np.ndarray, heads: np.ndarray, idx: np.ndarray, N: int, s: int, m: int,

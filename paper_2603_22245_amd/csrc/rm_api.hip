@@ -222,15 +222,15 @@ int rm_encode_reads(const rm_index* idx, const uint8_t* d_seq, const int64_t* d_
   if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
   if (n_reads < 1) return RM_ESIZE;
   if (wide_encoding(&idx->p))
-    return hip_status(rm::launch_encode_reads_wide(idx->p, idx->d_phase64, idx->d_token_class,
+    return hip_status(rm::launch_encode_reads_wide(idx->p, idx->d_phase32, idx->d_token_class,
                                                    d_seq, d_off, n_reads, d_read_emb, d_read_scale,
                                                    static_cast<hipStream_t>(stream)));
   if (!letter_encoding(&idx->p))
-    return hip_status(rm::launch_encode_reads_tokens(idx->p, idx->d_phase64, idx->d_token_class,
+    return hip_status(rm::launch_encode_reads_tokens(idx->p, idx->d_phase32, idx->d_token_class,
                                                      d_seq, d_off, n_reads, d_read_emb,
                                                      d_read_scale,
                                                      static_cast<hipStream_t>(stream)));
-  return hip_status(rm::launch_encode_reads(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
+  return hip_status(rm::launch_encode_reads(idx->p, idx->d_phase32, d_seq, d_off, n_reads,
                                             d_read_emb, d_read_scale,
                                             static_cast<hipStream_t>(stream)));
 }
@@ -245,7 +245,7 @@ int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int
   if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
   if (n_reads < 1 || idx->p.window_len < 9) return RM_ESIZE;
   if (!letter_encoding(&idx->p)) return RM_EUNSUPPORTED;
-  return hip_status(rm::launch_encode_reads_learned(idx->p, idx->d_phase64, d_seq, d_off, n_reads,
+  return hip_status(rm::launch_encode_reads_learned(idx->p, idx->d_phase32, d_seq, d_off, n_reads,
                                                     d_read_delta, d_read_emb, d_read_scale,
                                                     static_cast<hipStream_t>(stream)));
 }

@@ -192,29 +192,39 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   side_flush(side, lane, norm2, scale);
 }
 
+// Normalise a read head (this lane's two components, FP32 sums; a squared
+// norm below kDegenerateRel * N gives the zero vector) and store its two real
+// rows: 2r = (Re x, Im x) per component, 2r+1 = (-Im x, Re x).  A window row
+// (Re c, Im c) dotted with them gives Re and Im of sum conj(x) c.
+template <int PREC>
+__device__ __forceinline__ void emit_head(float2 a0, float2 a1, int N, int64_t r, int lane,
+                                          void* __restrict__ emb, float* __restrict__ scale) {
+  const float X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
+  const float inv = X < kDegenerateRel * N ? 0.f : 1.f / sqrtf(X);
+  const float xr0 = a0.x * inv, xi0 = a0.y * inv;
+  const float xr1 = a1.x * inv, xi1 = a1.y * inv;
+  Row4 re{{xr0, xi0, xr1, xi1}};
+  Row4 im{{-xi0, xr0, -xi1, xr1}};
+  const float s = store_row<PREC>(emb, 2 * r, lane, re);
+  store_row<PREC>(emb, 2 * r + 1, lane, im);
+  if (scale != nullptr && lane == 0) scale[r] = s;
+}
+
+// Read heads (§3.1: the first N letters of each read): an FP32 direct sum of
+// the FP32 phase table over the head's letters, one wavefront per read.  A
+// read shorter than N is the zero vector.
 template <int PREC>
 __global__ __launch_bounds__(256) void encode_reads_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
-    const double2* __restrict__ phase64, void* __restrict__ emb, float* __restrict__ scale) {
+    const float2* __restrict__ phase32, void* __restrict__ emb, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= n_reads) return;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
-  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
-  if (len >= N) direct_sum(seq + start, N, phase64, lane, a0, a1);
-  double X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
-  bool deg = X < (double)kDegenerateRel * N;
-  double inv = deg ? 0.0 : 1.0 / sqrt(X);
-  float xr0 = (float)(a0.x * inv), xi0 = (float)(a0.y * inv);
-  float xr1 = (float)(a1.x * inv), xi1 = (float)(a1.y * inv);
-  // row 2r: (Re x, Im x) per component; row 2r+1: (-Im x, Re x).  A window row
-  // (Re c, Im c) dotted with them gives Re and Im of sum conj(x) c.
-  Row4 re{{xr0, xi0, xr1, xi1}};
-  Row4 im{{-xi0, xr0, -xi1, xr1}};
-  float s = store_row<PREC>(emb, 2 * r, lane, re);
-  store_row<PREC>(emb, 2 * r + 1, lane, im);
-  if (scale != nullptr && lane == 0) scale[r] = s;
+  float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  if (len >= N) direct_sum32(seq + start, N, phase32, lane, a0, a1);
+  emit_head<PREC>(a0, a1, N, r, lane, emb, scale);
 }
 
 // ---- learned token offsets -------------------------------------------------
@@ -335,28 +345,57 @@ __global__ __launch_bounds__(256) void encode_reference_learned_kernel(
   side_flush(side, lane, norm2, scale);
 }
 
+// The same sum in FP32 with the FP32 table (read heads): each term is the
+// table entry omega^(f_k p) turned by exp(i delta).
+__device__ __forceinline__ void direct_sum_learned32(const uint8_t* __restrict__ str, int N,
+                                                     const float* __restrict__ drow,
+                                                     const float2* __restrict__ phase32, int lane,
+                                                     float2& a0, float2& a1) {
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+  const int T = N - 8;
+  a0 = make_float2(0.f, 0.f);
+  a1 = make_float2(0.f, 0.f);
+  for (int pb = 0; pb < T; pb += 64) {
+    int mine = (pb + lane < T) ? (int)str[pb + lane + 4] : 255;
+    int cnt = min(64, T - pb);
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      float2 e[8];
+      float d[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(pb + i0 + u, T - 1);
+        e[u] = phase32[(int64_t)p * kM + k];
+        d[u] = drow[(int64_t)p * 32 + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int L = __builtin_amdgcn_readlane(mine, i0 + u);
+        float sn, cs;
+        sincosf(d[u], &sn, &cs);
+        const float er = e[u].x * cs - e[u].y * sn, ei = e[u].x * sn + e[u].y * cs;
+        a0.x += (L == L0) ? er : 0.f;
+        a0.y += (L == L0) ? ei : 0.f;
+        a1.x += (L == L1) ? er : 0.f;
+        a1.y += (L == L1) ? ei : 0.f;
+      }
+    }
+  }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void encode_reads_learned_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
-    const double2* __restrict__ phase64, const float* __restrict__ delta, void* __restrict__ emb,
+    const float2* __restrict__ phase32, const float* __restrict__ delta, void* __restrict__ emb,
     float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= n_reads) return;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
-  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
-  if (len >= N) direct_sum_learned(seq + start, N, delta + start * 32, phase64, lane, a0, a1);
-  double X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
-  bool deg = X < (double)kDegenerateRel * N;
-  double inv = deg ? 0.0 : 1.0 / sqrt(X);
-  float xr0 = (float)(a0.x * inv), xi0 = (float)(a0.y * inv);
-  float xr1 = (float)(a1.x * inv), xi1 = (float)(a1.y * inv);
-  Row4 re{{xr0, xi0, xr1, xi1}};
-  Row4 im{{-xi0, xr0, -xi1, xr1}};
-  float s = store_row<PREC>(emb, 2 * r, lane, re);
-  store_row<PREC>(emb, 2 * r + 1, lane, im);
-  if (scale != nullptr && lane == 0) scale[r] = s;
+  float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  if (len >= N) direct_sum_learned32(seq + start, N, delta + start * 32, phase32, lane, a0, a1);
+  emit_head<PREC>(a0, a1, N, r, lane, emb, scale);
 }
 
 // ---- token encodings (§2.1 s-mers, §2.6 compact versions) ----------------------
@@ -422,11 +461,11 @@ __global__ __launch_bounds__(256) void encode_reference_tokens_kernel(
   side_flush(side, lane, norm2, scale);
 }
 
-// The read-head encoder with tokens: FP64 direct sum over the head's tokens.
+// The read-head encoder with tokens: FP32 direct sum over the head's tokens.
 template <int PREC>
 __global__ __launch_bounds__(256) void encode_reads_tokens_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
-    int s, int m, int n_class, const double2* __restrict__ phase64,
+    int s, int m, int n_class, const float2* __restrict__ phase32,
     const uint8_t* __restrict__ table, void* __restrict__ emb, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -434,18 +473,9 @@ __global__ __launch_bounds__(256) void encode_reads_tokens_kernel(
   const int k = 2 * lane / n_class, c0 = 2 * lane - k * n_class;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
-  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
-  if (len >= N) direct_sum_tokens(seq + start, N - s + 1, s, table, phase64, m, k, c0, lane, a0, a1);
-  double X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
-  bool deg = X < (double)kDegenerateRel * N;
-  double inv = deg ? 0.0 : 1.0 / sqrt(X);
-  float xr0 = (float)(a0.x * inv), xi0 = (float)(a0.y * inv);
-  float xr1 = (float)(a1.x * inv), xi1 = (float)(a1.y * inv);
-  Row4 re{{xr0, xi0, xr1, xi1}};
-  Row4 im{{-xi0, xr0, -xi1, xr1}};
-  float sc = store_row<PREC>(emb, 2 * r, lane, re);
-  store_row<PREC>(emb, 2 * r + 1, lane, im);
-  if (scale != nullptr && lane == 0) scale[r] = sc;
+  float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  if (len >= N) direct_sum_tokens(seq + start, N - s + 1, s, table, phase32, m, k, c0, lane, a0, a1);
+  emit_head<PREC>(a0, a1, N, r, lane, emb, scale);
 }
 
 }  // namespace
@@ -484,12 +514,12 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
   return hipGetLastError();
 }
 
-hipError_t launch_encode_reads(const rm_params& p, const double* phase64, const uint8_t* seq,
+hipError_t launch_encode_reads(const rm_params& p, const float* phase32, const uint8_t* seq,
                                const int64_t* off, int32_t n_reads, void* emb, float* scale,
                                hipStream_t s) {
   const int waves = 4;
   int64_t blocks = ((int64_t)n_reads + waves - 1) / waves;
-  auto* ph = reinterpret_cast<const double2*>(phase64);
+  auto* ph = reinterpret_cast<const float2*>(phase32);
   switch (p.precision) {
     case RM_FP32:
       hipLaunchKernelGGL(encode_reads_kernel<RM_FP32>, dim3((unsigned)blocks), dim3(64 * waves), 0, s,
@@ -545,13 +575,13 @@ hipError_t launch_encode_reference_learned(const uint8_t* ref, int64_t W, const 
   return hipGetLastError();
 }
 
-hipError_t launch_encode_reads_learned(const rm_params& p, const double* phase64,
+hipError_t launch_encode_reads_learned(const rm_params& p, const float* phase32,
                                        const uint8_t* seq, const int64_t* off, int32_t n_reads,
                                        const float* delta, void* emb, float* scale,
                                        hipStream_t s) {
   const int waves = 4;
   const dim3 grid((unsigned)(((int64_t)n_reads + waves - 1) / waves)), block(64 * waves);
-  auto* ph = reinterpret_cast<const double2*>(phase64);
+  auto* ph = reinterpret_cast<const float2*>(phase32);
   switch (p.precision) {
     case RM_FP32:
       hipLaunchKernelGGL(encode_reads_learned_kernel<RM_FP32>, grid, block, 0, s, seq, off,
@@ -595,14 +625,14 @@ hipError_t launch_encode_reference_tokens(const uint8_t* ref, int64_t W, const r
   return hipGetLastError();
 }
 
-hipError_t launch_encode_reads_tokens(const rm_params& p, const double* phase64,
+hipError_t launch_encode_reads_tokens(const rm_params& p, const float* phase32,
                                       const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                       int32_t n_reads, void* emb, float* scale, hipStream_t st) {
   const int waves = 4;
   const int64_t blocks = ((int64_t)n_reads + waves - 1) / waves;
   const int s = p.mer_len > 1 ? p.mer_len : 1;
   const int C = 128 / p.n_freq;
-  auto* ph = reinterpret_cast<const double2*>(phase64);
+  auto* ph = reinterpret_cast<const float2*>(phase32);
   auto kern = p.precision == RM_FP32   ? encode_reads_tokens_kernel<RM_FP32>
               : p.precision == RM_FP16 ? encode_reads_tokens_kernel<RM_FP16>
                                        : encode_reads_tokens_kernel<RM_FP8_E4M3>;

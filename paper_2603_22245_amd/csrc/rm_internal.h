@@ -172,6 +172,20 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return max64(max64(readlane64(v, 0), readlane64(v, 16)), max64(readlane64(v, 32), readlane64(v, 48)));
 }
 
+// One entry of a ranked list from its 64-bit key (high word = float bits of F
+// plus one, low word = ~window id).  Key 0 is an empty slot (fewer candidates
+// than slots).  F = 0 means the read head or the window is the zero vector (a
+// degenerate string, or a read shorter than N): that window is no location of
+// the read (§3 asks for the read's position only if one exists).  Both are
+// written as id -1 with score 0.
+__device__ __forceinline__ void write_list_entry(uint64_t key, int32_t* __restrict__ idx,
+                                                 float* __restrict__ score) {
+  const uint32_t hi = (uint32_t)(key >> 32);
+  const bool loc = hi > 1u;
+  *idx = loc ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
+  *score = loc ? __uint_as_float(hi - 1u) : 0.f;
+}
+
 // FP32 direct sum over letters [0, n) for this lane's two components (positions
 // past n in the last group of 8 read letter code 255 and add nothing).
 __device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, int n,
@@ -210,7 +224,7 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
                                    const double* phase64, const float* step32, void* emb,
                                    float* scale, float* norm2, hipStream_t s);
 
-hipError_t launch_encode_reads(const rm_params& p, const double* phase64, const uint8_t* seq,
+hipError_t launch_encode_reads(const rm_params& p, const float* phase32, const uint8_t* seq,
                                const int64_t* off, int32_t n_reads, void* emb, float* scale,
                                hipStream_t s);
 
@@ -281,7 +295,7 @@ hipError_t launch_encode_reference_learned(const uint8_t* ref, int64_t W, const 
                                            const double* phase64, const float* phase32,
                                            const float* step32, const float* delta, void* emb,
                                            float* scale, float* norm2, hipStream_t s);
-hipError_t launch_encode_reads_learned(const rm_params& p, const double* phase64,
+hipError_t launch_encode_reads_learned(const rm_params& p, const float* phase32,
                                        const uint8_t* seq, const int64_t* off, int32_t n_reads,
                                        const float* delta, void* emb, float* scale,
                                        hipStream_t s);

@@ -213,11 +213,7 @@ __global__ __launch_bounds__(256) void refine_select_kernel(const uint64_t* __re
     }
     if (lane == out) res = g;
   }
-  if (lane < k) {
-    const uint32_t hi = (uint32_t)(res >> 32);
-    top_idx[r * k + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)res) : -1;
-    top_score[r * k + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
-  }
+  if (lane < k) write_list_entry(res, &top_idx[r * k + lane], &top_score[r * k + lane]);
 }
 
 }  // namespace

@@ -69,7 +69,7 @@ __device__ __forceinline__ void direct_sum32_learned(const uint8_t* __restrict__
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Bitonic sort of one key per lane, descending over the 64 lanes, then the
-// first k keys as (window id, F) -- empty keys give (-1, -1).
+// first k keys as (window id, F) -- empty keys and F = 0 give (-1, 0).
 __device__ __forceinline__ void sort_and_write(uint64_t key, int lane, int64_t r, int k,
                                                int32_t* __restrict__ top_idx,
                                                float* __restrict__ top_score) {
@@ -85,11 +85,7 @@ __device__ __forceinline__ void sort_and_write(uint64_t key, int lane, int64_t r
       key = (lower == desc_block) ? mx : mn;
     }
   }
-  if (lane < k) {
-    uint32_t hi = (uint32_t)(key >> 32);
-    top_idx[r * k + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
-    top_score[r * k + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
-  }
+  if (lane < k) write_list_entry(key, &top_idx[r * k + lane], &top_score[r * k + lane]);
 }
 
 // Plain rescore, one wavefront per read (four per block).  Strings: s = 0 is

@@ -59,8 +59,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__
     if (lane == out) res = gbest;
   }
   if (lane < k_fetch) {
-    cand_idx[r * k_fetch + lane] = key_index(res);
-    cand_score[r * k_fetch + lane] = key_score(res);
+    write_list_entry(res, &cand_idx[r * k_fetch + lane], &cand_score[r * k_fetch + lane]);
   }
 }
 

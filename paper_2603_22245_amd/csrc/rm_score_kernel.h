@@ -56,10 +56,6 @@ __device__ __forceinline__ float key_score(uint64_t key) {
   uint32_t hi = (uint32_t)(key >> 32);
   return hi ? __uint_as_float(hi - 1u) : -1.f;
 }
-__device__ __forceinline__ int32_t key_index(uint64_t key) {
-  uint32_t hi = (uint32_t)(key >> 32);
-  return hi ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
-}
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
   uint32_t lo = __shfl_xor((uint32_t)v, d, 64);

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void merge_strands_kernel(
   n_found[r] = n;
   for (int e = n; e < k; ++e) {
     top_idx[r * k + e] = -1;
-    top_score[r * k + e] = -1.f;
+    top_score[r * k + e] = 0.f;
     top_strand[r * k + e] = -1;
   }
 }

@@ -78,7 +78,7 @@ hipError_t launch_encode_reference_tokens(const uint8_t* ref, int64_t W, const r
                                           const uint8_t* table, void* emb, float* scale,
                                           float* norm2, hipStream_t st);
 
-hipError_t launch_encode_reads_tokens(const rm_params& p, const double* phase64,
+hipError_t launch_encode_reads_tokens(const rm_params& p, const float* phase32,
                                       const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                       int32_t n_reads, void* emb, float* scale, hipStream_t st);
 
@@ -100,7 +100,7 @@ hipError_t launch_encode_reference_wide(const uint8_t* ref, int64_t W, const rm_
                                         const double* phase64, const float* step32,
                                         const uint8_t* table, void* emb, float* scale,
                                         float* norm2, hipStream_t st);
-hipError_t launch_encode_reads_wide(const rm_params& p, const double* phase64,
+hipError_t launch_encode_reads_wide(const rm_params& p, const float* phase32,
                                     const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                     int32_t n_reads, void* emb, float* scale, hipStream_t st);
 hipError_t launch_score_wide(const rm_index& idx, const void* read_emb, const float* read_scale,

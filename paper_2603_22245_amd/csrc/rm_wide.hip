@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void encode_reference_wide_kernel(
 template <int PREC>
 __global__ __launch_bounds__(256) void encode_reads_wide_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
-    int s, int m, int n_class, const double2* __restrict__ phase64,
+    int s, int m, int n_class, const float2* __restrict__ phase32,
     const uint8_t* __restrict__ table, void* __restrict__ emb, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -221,20 +221,19 @@ __global__ __launch_bounds__(256) void encode_reads_wide_kernel(
   const int k = kWC * lane / n_class, c0 = kWC * lane - k * n_class;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
-  double dr[kWC], di[kWC];
-#pragma unroll
-  for (int q = 0; q < kWC; ++q) dr[q] = di[q] = 0.0;
-  if (len >= N) wide_direct_sum(seq + start, N - s + 1, s, table, phase64, m, k, c0, lane, dr, di);
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < kWC; ++q) acc += dr[q] * dr[q] + di[q] * di[q];
-  const double X = wave_sum(acc);
-  const double inv = X < (double)kDegenerateRel * N ? 0.0 : 1.0 / sqrt(X);
   float xr[kWC], xi[kWC], nxi[kWC];
 #pragma unroll
+  for (int q = 0; q < kWC; ++q) xr[q] = xi[q] = 0.f;
+  if (len >= N) wide_direct_sum(seq + start, N - s + 1, s, table, phase32, m, k, c0, lane, xr, xi);
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kWC; ++q) acc += xr[q] * xr[q] + xi[q] * xi[q];
+  const float X = wave_sum(acc);
+  const float inv = X < kDegenerateRel * N ? 0.f : 1.f / sqrtf(X);
+#pragma unroll
   for (int q = 0; q < kWC; ++q) {
-    xr[q] = (float)(dr[q] * inv);
-    xi[q] = (float)(di[q] * inv);
+    xr[q] *= inv;
+    xi[q] *= inv;
     nxi[q] = -xi[q];
   }
   // both rows hold the same magnitudes: the same power of two and scale
@@ -555,11 +554,8 @@ __global__ __launch_bounds__(256) void merge_wide_kernel(const uint64_t* __restr
       if (g != 0 && mine[e] == g) mine[e] = 0;
     if (lane == out) res = g;
   }
-  if (lane < k_fetch) {
-    const uint32_t hi = (uint32_t)(res >> 32);
-    cand_idx[r * k_fetch + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)res) : -1;
-    cand_score[r * k_fetch + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
-  }
+  if (lane < k_fetch)
+    write_list_entry(res, &cand_idx[r * k_fetch + lane], &cand_score[r * k_fetch + lane]);
 }
 
 // ---- FP32 rescore -------------------------------------------------------------
@@ -652,11 +648,7 @@ __global__ __launch_bounds__(256) void rescore_wide_kernel(
       key = (lower == desc_block) ? mx : mn;
     }
   }
-  if (lane < k) {
-    const uint32_t hi = (uint32_t)(key >> 32);
-    top_idx[r * k + lane] = hi ? (int32_t)(0xffffffffu - (uint32_t)key) : -1;
-    top_score[r * k + lane] = hi ? __uint_as_float(hi - 1u) : -1.f;
-  }
+  if (lane < k) write_list_entry(key, &top_idx[r * k + lane], &top_score[r * k + lane]);
 }
 
 // Sums of FP32 phases in 64-bit fixed point with 2^-40 units: an FP32 value of
@@ -664,12 +656,26 @@ __global__ __launch_bounds__(256) void rescore_wide_kernel(
 // less than one unit, and integer addition gives the same total whatever order
 // the lanes' atomics land in.  |sum| <= N <= 2^14 keeps it below 2^54.
 constexpr float kFixScale = 1099511627776.0f;  // 2^40
-constexpr double kFixUnit = 1.0 / 1099511627776.0;
+constexpr float kFixUnit = 1.0f / 1099511627776.0f;  // 2^-40
 constexpr int kAccLen = kWideComplex + kWideComplex / kWC;  // one pad slot per lane's 16
 
 // Accumulator slot of component `comp`: lane l's components 16l..16l+15 sit at
 // a stride of 17 slots, so the lanes' read-back spreads over the banks.
 __device__ __forceinline__ int acc_slot(int comp) { return comp + comp / kWC; }
+
+// A running FP32 sum with its rounding error carried alongside (Knuth's
+// TwoSum: hi + e equals a + b exactly), so many small additions to a large
+// value lose nothing beyond the final rounding of hi + lo.
+struct CompSum {
+  float hi, lo;
+  __device__ __forceinline__ void add(float b) {
+    const float s = hi + b;
+    const float bb = s - hi;
+    lo += (hi - (s - bb)) + (b - bb);
+    hi = s;
+  }
+  __device__ __forceinline__ float value() const { return hi + lo; }
+};
 
 // Orders this wavefront's LDS accesses (a compiler barrier plus a wait on them);
 // no other wavefront is waited for.
@@ -688,7 +694,7 @@ __device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SE
 // that entered, so with P_k = sum over factor k's components of conj(x) u
 // (lane k) and S = |u|^2 (rotation keeps norms), <x|c> = sum_k
 // omega^(-f_k i) P_k and |c|^2 = S: a slide changes two components per factor
-// and updates P_k and S by their changes (FP64).  Slot i of the candidate's
+// and updates P_k and S by their changes (FP32, compensated sums).  Slot i of the candidate's
 // span in `pool` receives the key of start lo + i, 0 past the clamped
 // neighbourhood or for an invalid candidate.
 __global__ __launch_bounds__(256) void refine_wide_kernel(
@@ -786,23 +792,25 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     }
     lds_order();
     // u = that window's components: P_k = sum over factor k's components of
-    // conj(x) u (lane k), S = |u|^2
-    double pr = 0.0, pi = 0.0, sq = 0.0;
+    // conj(x) u (lane k), S = |u|^2, FP32 sums
+    float pr = 0.f, pi = 0.f, sq = 0.f;
 #pragma unroll
     for (int q = 0; q < kWC; ++q) {
-      const double ur = (double)(long long)accR[acc_slot(kWC * lane + q)] * kFixUnit;
-      const double ui = (double)(long long)accI[acc_slot(kWC * lane + q)] * kFixUnit;
-      pr += (double)xr[q] * ur + (double)xi[q] * ui;
-      pi += (double)xr[q] * ui - (double)xi[q] * ur;
+      const float ur = (float)(long long)accR[acc_slot(kWC * lane + q)] * kFixUnit;
+      const float ui = (float)(long long)accI[acc_slot(kWC * lane + q)] * kFixUnit;
+      pr += xr[q] * ur + xi[q] * ui;
+      pi += xr[q] * ui - xi[q] * ur;
       sq += ur * ur + ui * ui;
     }
     for (int d = 1; d < G; d <<= 1) {  // a factor's G lanes are contiguous and aligned
       pr += __shfl_xor(pr, d, 64);
       pi += __shfl_xor(pi, d, 64);
     }
-    double Pr = __shfl(pr, fl ? lane * G : 0, 64), Pi = __shfl(pi, fl ? lane * G : 0, 64);
-    if (!fl) Pr = Pi = 0.0;
-    double S = wave_sum(sq);
+    // the slides' changes are added to P_k and S with compensated sums, so the
+    // running values carry no more error than the first window's sums
+    CompSum Pr{__shfl(pr, fl ? lane * G : 0, 64), 0.f}, Pi{__shfl(pi, fl ? lane * G : 0, 64), 0.f};
+    if (!fl) Pr.hi = Pi.hi = 0.f;
+    CompSum S{wave_sum(sq), 0.f};
     float2 wt = make_float2(1.f, 0.f);  // omega^(f_k i) at slide i, lanes k < m
 
     // lane i holds the classes of slide lo + i: the token leaving (at lo + i)
@@ -814,34 +822,35 @@ __global__ __launch_bounds__(256) void refine_wide_kernel(
     uint64_t mine = 0;
     for (int64_t t = lo; t <= hi; ++t) {
       // window t's components are omega^(-f_k (t - lo)) u: <x|c> = sum_k conj(wt_k) P_k
-      const double ipr = wave_sum((double)wt.x * Pr + (double)wt.y * Pi);
-      const double ipi = wave_sum((double)wt.x * Pi - (double)wt.y * Pr);
-      const bool deg = xdeg || S < (double)kDegenerateRel * N;
-      const float F = deg ? 0.f : (float)((ipr * ipr + ipi * ipi) / ((double)X * S));
+      const float pr_t = Pr.value(), pi_t = Pi.value(), S_t = S.value();
+      const float ipr = wave_sum(wt.x * pr_t + wt.y * pi_t);
+      const float ipi = wave_sum(wt.x * pi_t - wt.y * pr_t);
+      const bool deg = xdeg || S_t < kDegenerateRel * N;
+      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * S_t);
       if (lane == (int)(t - lo)) mine = wide_key(F, t);
       if (t < hi) {
         const int i = (int)(t - lo);
         const int oc = __builtin_amdgcn_readlane(out_c, i);
         const int ic = __builtin_amdgcn_readlane(in_c, i);
-        double dS = 0.0;
+        float dS = 0.f;
         // lane k changes component k * n_class + class of each token by d:
         // P_k += conj(x) d, S += 2 Re(conj(u) d) + |d|^2, u += d (exactly)
         auto change = [&](int cls, float2 d) {
           const int comp = lane * n_class + cls;
           const int sl = acc_slot(comp);
-          const double ur = (double)(long long)accR[sl] * kFixUnit;
-          const double ui = (double)(long long)accI[sl] * kFixUnit;
+          const float ur = (float)(long long)accR[sl] * kFixUnit;
+          const float ui = (float)(long long)accI[sl] * kFixUnit;
           const float2 xv = xs[comp];
-          Pr += (double)xv.x * d.x + (double)xv.y * d.y;
-          Pi += (double)xv.x * d.y - (double)xv.y * d.x;
-          dS += 2.0 * (ur * d.x + ui * d.y) + (double)d.x * d.x + (double)d.y * d.y;
+          Pr.add(xv.x * d.x + xv.y * d.y);
+          Pi.add(xv.x * d.y - xv.y * d.x);
+          dS += 2.f * (ur * d.x + ui * d.y) + (d.x * d.x + d.y * d.y);
           accR[sl] += (unsigned long long)(long long)(d.x * kFixScale);
           accI[sl] += (unsigned long long)(long long)(d.y * kFixScale);
         };
         // leaving: relative location i, omega^(f i); entering: i + T
         if (fl && oc >= 0 && oc < n_class) change(oc, make_float2(-wt.x, -wt.y));
         if (fl && ic >= 0 && ic < n_class) change(ic, cmul(wt, adv));
-        S += wave_sum(dS);
+        S.add(wave_sum(dS));
         wt = cmul(wt, fwd);
       }
     }
@@ -895,14 +904,14 @@ hipError_t launch_encode_reference_wide(const uint8_t* ref, int64_t W, const rm_
   return hipGetLastError();
 }
 
-hipError_t launch_encode_reads_wide(const rm_params& p, const double* phase64,
+hipError_t launch_encode_reads_wide(const rm_params& p, const float* phase32,
                                     const uint8_t* table, const uint8_t* seq, const int64_t* off,
                                     int32_t n_reads, void* emb, float* scale, hipStream_t st) {
   auto kern = p.precision == RM_FP8_E4M3 ? encode_reads_wide_kernel<RM_FP8_E4M3>
                                           : encode_reads_wide_kernel<RM_FP16>;
   hipLaunchKernelGGL(kern, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0, st, seq,
                      off, n_reads, p.window_len, p.mer_len > 1 ? p.mer_len : 1, p.n_freq,
-                     kWideComplex / p.n_freq, reinterpret_cast<const double2*>(phase64), table,
+                     kWideComplex / p.n_freq, reinterpret_cast<const float2*>(phase32), table,
                      emb, scale);
   return hipGetLastError();
 }

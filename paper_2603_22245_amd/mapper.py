@@ -411,10 +411,10 @@ class BatchMapper:
         L.rm_graph_launch(self.graph, stream)
 
     def results(self):
-        """Top-k window ids and FP32 scores of every read (id -1 for unmapped reads),
+        """Top-k window ids and FP32 scores of every read (id -1, score 0 for no location),
         and each read's bucket index."""
         ids = np.full((self.n_reads, self.k), -1, dtype=np.int32)
-        sc = np.full((self.n_reads, self.k), -1.0, dtype=np.float32)
+        sc = np.zeros((self.n_reads, self.k), dtype=np.float32)
         for b in self.buckets:
             ids[b.read_ids] = b.bufs.top_idx.cpu().numpy()
             sc[b.read_ids] = b.bufs.top_score.cpu().numpy()

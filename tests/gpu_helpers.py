@@ -63,9 +63,10 @@ def check_refined_lists(tidx, tsc, cand, F1, stride, radius, k, tol):
     exact = 0
     for r in range(F1.shape[0]):
         want_i, want_f = mapping.refine_topk(F1[r], cand[r], stride, radius, k)
-        n = want_i.size
+        n = int(np.sum(want_i >= 0))            # entries with F = 0 are no location
+        want_i, want_f = want_i[:n], want_f[:n]
         got = tidx[r, :n]
-        assert np.all(tidx[r, n:] == -1) and np.all(got >= 0), r
+        assert np.all(tidx[r, n:] == -1) and np.all(tsc[r, n:] == 0) and np.all(got >= 0), r
         assert len(set(got.tolist())) == n, r                       # distinct starts
         pool = set(mapping.refine_pool(cand[r], stride, radius, F1.shape[1]).tolist())
         assert set(got.tolist()) <= pool, r                           # only refined starts
@@ -74,3 +75,16 @@ def check_refined_lists(tidx, tsc, cand, F1, stride, radius, k, tol):
         assert np.max(np.abs(tsc[r, :n] - got_true)) < tol, r
         exact += int(np.array_equal(got, want_i))
     return exact / F1.shape[0]
+
+
+def assert_lists_exact(exact, rec, k_fetch, k, precision):
+    """Rescored lists against the oracle's.  When the product scores in FP32,
+    or over-fetches (k_fetch > k), every list must equal the oracle's up to
+    ties.  With k_fetch == k in FP16 or FP8, a window the product ranks just
+    below the k-th best is never rescored, so a few lists may differ: recall
+    >= 0.99 and at least 97 % identical lists."""
+    bad = np.nonzero(~np.asarray(exact))[0]
+    if precision == "fp32" or k_fetch > k:
+        assert bad.size == 0, f"lists differing from the oracle's: reads {bad.tolist()}"
+    else:
+        assert rec >= 0.99 and np.mean(exact) >= 0.97, (rec, bad.tolist())

@@ -73,7 +73,7 @@ def test_both_strands_against_the_oracle(strand_case, min_fidelity):
         lo = sum(1 for f in wf if f >= min_fidelity + mapping.TIE_TAU)
         assert lo <= n <= wi.size + sum(1 for f in np.r_[ff[r], rf[r]]
                                         if min_fidelity - mapping.TIE_TAU <= f < min_fidelity), r
-        assert np.all(ti[r, n:] == -1) and np.all(tst[r, n:] == -1), r
+        assert np.all(ti[r, n:] == -1) and np.all(tst[r, n:] == -1) and np.all(ts[r, n:] == 0), r
         got_true = np.where(tst[r, :n] == 0, Ff[r, np.maximum(ti[r, :n], 0)],
                             Fr[r, np.maximum(ti[r, :n], 0)])
         m = min(n, wi.size)

@@ -69,6 +69,31 @@ def test_degenerate_window_scores_zero():
     assert F[0, 0] == 0.0 and abs(F[0, 1] - 1) < 1e-12
 
 
+def test_no_location_when_every_fidelity_is_zero():
+    """§3: a read's position is reported only if one exists.  Reference: 160
+    A's then one C (N = 150, W = 12).  Windows 0..10 are all A, the zero
+    vector (every factor sums a full turn of roots of unity), so every read
+    scores 0 with them; only window 11 holds the C.  A read of 100 letters
+    (shorter than N) and a read of 150 A's are zero vectors too."""
+    ref = np.r_[np.zeros(160, np.uint8), np.ones(1, np.uint8)]
+    rng = np.random.default_rng(12)
+    reads = [rng.integers(0, 4, 150).astype(np.uint8), rng.integers(0, 4, 100).astype(np.uint8),
+             np.zeros(150, np.uint8), ref[11:161].copy()]
+    off = np.r_[0, np.cumsum([len(x) for x in reads])]
+    heads = mapping.read_heads(np.concatenate(reads), off, 150)
+    assert np.all(heads[1] == mapping.NO_LETTER)
+    np.testing.assert_array_equal(heads[0], reads[0])
+    idx, F = mapping.map_reads(ref, heads, 150, 32, 8)
+    # brute force, pair by pair: only (read 0, window 11) and (read 3, window 11) are > 0
+    for r in range(4):
+        for j in range(12):
+            f = mapping.pair_fidelity(ref, heads[r], j, 150)
+            assert (f > 0) == (r in (0, 3) and j == 11), (r, j, f)
+    assert idx[0, 0] == 11 and F[0, 0] > 0 and idx[3, 0] == 11 and abs(F[3, 0] - 1) < 1e-12
+    assert np.all(idx[:, 1:] == -1) and np.all(F[:, 1:] == 0)
+    assert np.all(idx[1:3] == -1) and np.all(F[1:3] == 0)
+
+
 def test_pair_fidelities_match_full_scan():
     ref = make_reference(3000, seed=0, uniform=True)
     reads = simulate_reads(ref, np.full(5, 150), 0.01, 0.005, 0.005, seed=3)
