@@ -71,14 +71,16 @@ def test_traffic_is_read_only_for_the_current_kernel_sources(tmp_path, monkeypat
         d.mkdir(parents=True, exist_ok=True)
         (tmp_path / f).write_text("kernel v1")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("fp16") is None            # no summary
+    assert bench.measured_traffic("precision", "fp16") is None   # no summary
     digest = bench.score_source_digest()
     body = {"bytes_per_launch": 123, "source_sha256": digest}
     (prof / "score_topk_fp16_precision_traffic.txt").write_text(
         "# summary\n\n```json\n" + json.dumps(body) + "\n```\n")
-    assert bench.measured_traffic("fp16") == 123
+    assert bench.measured_traffic("precision", "fp16") == 123
+    assert bench.measured_traffic("scale", "fp16") is None       # another workload's summary
+    assert bench.measured_traffic("precision", "fp8") is None    # another precision's
     (tmp_path / bench.SCORE_SOURCES[0]).write_text("kernel v2")
-    assert bench.measured_traffic("fp16") is None            # kernel changed
+    assert bench.measured_traffic("precision", "fp16") is None   # kernel changed
 
 
 def test_correlation_curve_and_rmse():
