@@ -243,11 +243,12 @@ def main():
     if (not args.no_batching and args.workload == "precision" and args.tokens is None
             and not coarse and args.reads is None):
         del reads
-        b = bench_batching(args, fp32=not args.no_fp32)
+        b = bench_batching(args, fp32=not args.no_fp32, low=("fp16", "fp8"))
         out["batched_path"] = {key: b[key] for key in
                                ("value", "unit", "ms_per_step", "steps", "config",
-                                "window_scores_per_s", "breakdown_ms_eager", "accuracy",
-                                "roofline", "fp32_path") if key in b}
+                                "window_scores_per_s", "reads_per_s_prebuilt_index_eager",
+                                "breakdown_ms_eager", "accuracy", "roofline", "fp8_path",
+                                "fp32_path") if key in b}
     print(json.dumps(out), flush=True)
 
 
@@ -389,16 +390,17 @@ def _batched_pass(ref, reads, k, k_fetch, precision, steps, warmup):
     return bm, wall * 1e3 / steps, parts, best
 
 
-def bench_batching(args, fp32: bool = None):
+def bench_batching(args, fp32: bool = None, low=None):
     """Reads of uneven length: bucket indexes, one grouped persistent scoring launch,
     the whole step replayed from a HIP graph; then the same step with FP32
-    indexes and the FP32 product (the plain FP32 path) for comparison."""
+    indexes and the FP32 product (the plain FP32 path) for comparison.  `low`:
+    (headline precision, another low precision run as a second leg)."""
     import torch
     import synth
     w = synth.WORKLOADS["batching"]
     precision = args.precision or w.precision
-    if args.workload != "batching":
-        precision = w.precision
+    if low is not None:
+        precision = low[0]
     k, k_fetch = w.k, max(w.k, args.k_fetch)
     fp32 = (not args.no_fp32) if fp32 is None else fp32
     t0 = time.time()
@@ -447,6 +449,33 @@ def bench_batching(args, fp32: bool = None):
                      "kernel": "score_topk_kernel (grouped, persistent) + merges",
                      "algorithmic": f"{FLOPS_PER_SCORE} flops x {scores} (read, window) scores"},
     }
+    prebuilt = {precision: parts[1] + parts[2] + parts[3]}
+    step_ms = {precision: ms_per_step}
+    if low is not None and len(low) > 1:
+        p2 = low[1]
+        bm2, ms2, parts2, best2 = _batched_pass(ref, reads, k, k_fetch, p2, args.steps, 1)
+        ids2, sc2 = bm2.results()
+        acc2 = batching_accuracy(ref, reads, bm2, ids2, sc2, k)
+        bm2.close()
+        del bm2
+        torch.cuda.empty_cache()
+        prebuilt[p2] = parts2[1] + parts2[2] + parts2[3]
+        step_ms[p2] = ms2
+        out[f"{p2}_path"] = {
+            "value": round(R / (ms2 / 1e3), 1), "unit": "reads/s", "ms_per_step": round(ms2, 3),
+            "reads_per_s_prebuilt_index_eager": round(R / (prebuilt[p2] / 1e3), 1),
+            "breakdown_ms_eager": {"encode_references": round(parts2[0], 3),
+                                   "encode_reads": round(parts2[1], 3),
+                                   "score_topk_grouped": round(parts2[2], 3),
+                                   "rescore": round(parts2[3], 3)},
+            "accuracy": acc2,
+            "roofline": {"bound": "mfma",
+                         "achieved": round(scores * FLOPS_PER_SCORE / (parts2[2] / 1e3) / 1e12, 2),
+                         "peak": PEAK_TFLOPS[p2], "unit": "TFLOP/s",
+                         "frac": round(scores * FLOPS_PER_SCORE / (parts2[2] / 1e3) / 1e12
+                                       / PEAK_TFLOPS[p2], 4), "traffic": None},
+            "note": f"the same graph-replayed step with {p2} indexes and read heads "
+                    f"(tuning read_tile={best2.read_tile}, chunk_tiles={best2.chunk_tiles})"}
     if fp32 and precision != "fp32":
         bm32, ms32, parts32, best32 = _batched_pass(ref, reads, k, k_fetch, "fp32", 1, 1)
         ids32, sc32 = bm32.results()
@@ -463,7 +492,10 @@ def bench_batching(args, fp32: bool = None):
                                    "score_topk_grouped": round(parts32[2], 3),
                                    "rescore": round(parts32[3], 3)},
             "accuracy": acc32,
-            "speedup_of_low_precision": round(value / v32, 2),
+            "speedup_of_low_precision": {p: round(ms32 / t, 2) for p, t in step_ms.items()},
+            "speedup_of_low_precision_prebuilt_index": {
+                p: round((parts32[1] + parts32[2] + parts32[3]) / t, 2)
+                for p, t in prebuilt.items()},
             "note": "the same graph-replayed step with FP32 indexes and the FP32 MFMA product "
                     f"(tuning read_tile={best32.read_tile}, chunk_tiles={best32.chunk_tiles})"}
     return out
@@ -474,25 +506,6 @@ def _spearman(x, y) -> float:
     return float(spearmanr(x, y).correlation)
 
 
-def correlation_curve(err_levels, fid_by_level):
-    """§2.4, the fitting curve: the points (E_fid(err), err), one per mutation
-    rate, connected (piecewise linear in E_fid).  Returns (E, err) sorted by E
-    ascending, ready for np.interp."""
-    E = np.array([float(np.mean(f)) for f in fid_by_level])
-    e = np.asarray(err_levels, dtype=np.float64)
-    o = np.argsort(E, kind="stable")
-    return E[o], e[o]
-
-
-def prediction_rmse(err_levels, fid_by_level, curve):
-    """§2.4: per mutation rate, the root mean square of the vertical distances
-    between the points (fid, err) of its pairs and the fitting curve, i.e. the
-    error of predicting the rate from an observed fidelity."""
-    E, e = curve
-    return [float(np.sqrt(np.mean((np.interp(np.asarray(f), E, e) - err) ** 2)))
-            for err, f in zip(err_levels, fid_by_level)]
-
-
 def bench_correlation(args):
     """The correlation protocol of §2.4 on the GPU: random 150 bp strings and
     companions mutated at rates err evenly spread over (0, 0.5) (edits split
@@ -501,7 +514,7 @@ def bench_correlation(args):
     predicting err from the fidelity."""
     import torch
     import synth
-    from paper_2603_22245_amd import learned as LM
+    from paper_2603_22245_amd import correlation as CR, learned as LM
     N, levels = 150, 25
     per = max(1, args.corr_pairs // levels)
     err_levels = (np.arange(levels) + 0.5) * 0.5 / levels
@@ -516,23 +529,21 @@ def bench_correlation(args):
     out_F = {}
     ms = {}
     for name, prm in (("plain", None), ("learned", params)):
-        LM.pair_fidelity(prm, ps, N)          # warm-up
+        CR.run(ps, err_levels, N, prm)          # warm-up
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        F = LM.pair_fidelity(prm, ps, N)
+        F, E, rmse = CR.run(ps, err_levels, N, prm)
         e1.record()
         torch.cuda.synchronize()
         ms[name] = e0.elapsed_time(e1)
-        out_F[name] = F.cpu().numpy().astype(np.float64).reshape(levels, per)
+        out_F[name] = (E.cpu().numpy().astype(np.float64), rmse.cpu().numpy().astype(np.float64))
     res = {}
-    for name, F in out_F.items():
-        curve = correlation_curve(err_levels, list(F))
-        rmse = prediction_rmse(err_levels, list(F), curve)
+    for name, (E, rmse) in out_F.items():
         low = err_levels < 0.25
-        res[name] = {"E_fid": [round(float(np.mean(f)), 5) for f in F],
-                     "rmse": [round(r, 5) for r in rmse],
-                     "max_rmse_below_25pct": round(float(np.max(np.asarray(rmse)[low])), 5),
+        res[name] = {"E_fid": [round(float(v), 5) for v in E],
+                     "rmse": [round(float(r), 5) for r in rmse],
+                     "max_rmse_below_25pct": round(float(np.max(rmse[low])), 5),
                      "mean_rmse": round(float(np.mean(rmse)), 5)}
     value = pairs.n / (ms["plain"] / 1e3)
     return {

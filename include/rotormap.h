@@ -259,6 +259,22 @@ int rm_merge_strands(const int32_t* d_fwd_idx, const float* d_fwd_score, const i
                      int32_t* d_top_idx, float* d_top_score, int8_t* d_top_strand,
                      int32_t* d_n_found, void* stream);
 
+/* ---- the correlation score (§2.4) -------------------------------------------
+ * How well fidelity predicts the mutation rate: pairs (dna, mut) are sampled at
+ * mutation rates err; per rate, E_fid is the mean fidelity of its pairs; the
+ * points (E_fid(err), err), joined in order of E_fid, form the fitting curve
+ * (extended flat past its ends); per rate, the RMSE is the root mean square of
+ * the vertical distances curve(fid) - err of its pairs' points.  Fidelities
+ * come from rm_pair_fidelity (plain or learned encoding). */
+#define RM_CORR_MAX_RATES 256
+
+/* From d_F [n_rates][per_rate] (FP32 fidelities, rate-major) and d_err
+ * [n_rates] (the rates), write d_E [n_rates] (E_fid) and d_rmse [n_rates].
+ * All device memory, caller-owned; FP32 sums.  Errors: RM_EINVAL (null
+ * pointer), RM_ESIZE (n_rates outside 1..RM_CORR_MAX_RATES, per_rate < 1). */
+int rm_correlation_score(const float* d_F, const float* d_err, int32_t n_rates, int32_t per_rate,
+                         float* d_E, float* d_rmse, void* stream);
+
 /* ---- refinement around found locations (§3.4) ------------------------------
  * With a coarse index (stride sigma > 1) the product finds the coarse window
  * nearest each good location; rm_refine then scores the step-1 windows whose

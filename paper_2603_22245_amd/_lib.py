@@ -49,6 +49,7 @@ RM_LEARNED_PARAMS = 10432
 RM_LEARNED_MAX_LEN = 256
 RM_LEARNED_MAX_PAIRS = 1024
 RM_REFINE_MAX_RADIUS = 7
+RM_CORR_MAX_RATES = 256
 
 
 class RotorMapError(RuntimeError):
@@ -106,6 +107,7 @@ def lib():
                                                      P, SZ, P, P]),
             "rm_learned_gradient": (ctypes.c_int, [P, P, P, P, P, P, I32, I32, P, SZ, P, P, P]),
             "rm_levenshtein": (ctypes.c_int, [P, P, P, P, I64, P, P]),
+            "rm_correlation_score": (ctypes.c_int, [P, P, I32, I32, P, P, P]),
             "rm_delta_bytes": (SZ, [I64]),
             "rm_mlp_infer": (ctypes.c_int, [P, P, I64, P, P]),
             "rm_encode_reference_learned": (ctypes.c_int, [P, I64, PP, P, P, SZ, IP, P]),
@@ -397,3 +399,9 @@ def rm_rescore_learned(idx: rm_index, d_ref, d_ref_delta, d_seq, d_off, d_read_d
                                     _ptr(d_off), _ptr(d_read_delta), n_reads, k_fetch,
                                     _ptr(d_cand_idx), k, _ptr(d_top_idx), _ptr(d_top_score),
                                     _stream(stream)), "rm_rescore_learned")
+
+
+def rm_correlation_score(d_F, d_err, n_rates: int, per_rate: int, d_E, d_rmse,
+                         stream=None) -> None:
+    _check(lib().rm_correlation_score(_ptr(d_F), _ptr(d_err), n_rates, per_rate, _ptr(d_E),
+                                      _ptr(d_rmse), _stream(stream)), "rm_correlation_score")

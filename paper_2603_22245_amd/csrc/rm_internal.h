@@ -312,6 +312,9 @@ hipError_t launch_learned_step(float* state, float lr, const uint8_t* a, const i
 hipError_t launch_levenshtein(const uint8_t* a, const int64_t* aoff, const uint8_t* b,
                               const int64_t* boff, int64_t n, int32_t* out, hipStream_t s);
 
+hipError_t launch_correlation_score(const float* F, const float* err, int32_t n_rates,
+                                    int32_t per, float* E, float* rmse, hipStream_t s);
+
 hipError_t launch_reverse_complement(const uint8_t* seq, const int64_t* off, int32_t n_reads,
                                      int64_t n_letters, uint8_t* out, hipStream_t s);
 hipError_t launch_merge_strands(const int32_t* fi, const float* ff, const int32_t* ri,

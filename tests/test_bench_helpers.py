@@ -81,24 +81,3 @@ def test_traffic_is_read_only_for_the_current_kernel_sources(tmp_path, monkeypat
     assert bench.measured_traffic("precision", "fp8") is None    # another precision's
     (tmp_path / bench.SCORE_SOURCES[0]).write_text("kernel v2")
     assert bench.measured_traffic("precision", "fp16") is None   # kernel changed
-
-
-def test_correlation_curve_and_rmse():
-    """The §2.4 metric: with fidelities that are an exact decreasing function
-    of the rate the curve passes through every level's mean and the RMSE is 0;
-    with spread around it the RMSE is the spread mapped through the curve's
-    slope (a hand-computed linear case)."""
-    import numpy as np
-    import bench
-    err = np.array([0.1, 0.2, 0.3, 0.4])
-    fid = [np.full(5, (1 - 2 * e) ** 2) for e in err]
-    curve = bench.correlation_curve(err, fid)
-    assert list(curve[1]) == [0.4, 0.3, 0.2, 0.1]                     # sorted by E ascending
-    assert np.allclose(bench.prediction_rmse(err, fid, curve), 0.0)
-    # linear curve E = 1 - e (E in 0.6..0.9); fidelities E +- 0.05 at every level:
-    # predictions err -+ 0.05 (inside the curve's range) -> RMSE 0.05
-    E = 1 - err
-    fid = [np.array([x - 0.05, x + 0.05]) for x in E]
-    curve = (E[::-1].copy(), err[::-1].copy())
-    r = bench.prediction_rmse(err, fid, curve)
-    assert np.allclose(r[1:3], 0.05)
