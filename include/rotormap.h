@@ -259,6 +259,68 @@ int rm_merge_strands(const int32_t* d_fwd_idx, const float* d_fwd_score, const i
                      int32_t* d_top_idx, float* d_top_score, int8_t* d_top_strand,
                      int32_t* d_n_found, void* stream);
 
+/* ---- per-fragment thresholds and the threshold regime (§3.3, §3.5) ----------
+ * §3.3 closes by noting that, for a target mutation rate, the fidelity
+ * expected of each reference fragment can be estimated and used as that
+ * fragment's cutting threshold; §3.5 describes the regime that reports every
+ * location whose fidelity passes its fragment's precomputed threshold (many
+ * for some reads, none for others).  Estimate used here: window j is mutated
+ * `copies` times at rate err by a streaming mutator (walking the reference
+ * from the window's start, each step an insertion, a deletion or a
+ * substitution with probability err/3 each, else a match, until N letters are
+ * out; a step that needs a letter past the reference's end inserts; at most
+ * 8 N + 64 steps), and its threshold is the `rank`-th smallest fidelity
+ * (0 = the smallest) of the window with its copies, in FP32.  The draws come
+ * from the counter-based generator Philox4x32-10 (Salmon et al., SC 2011):
+ * step t of copy c of window j uses the four words of counter (j mod 2^32,
+ * j >> 32, c, t) under key (seed, 0); word 0 below 1x / 2x / 3x
+ * floor(err / 3 * 2^32) is an insertion / deletion / substitution (err as the
+ * FP32 value converted to double), word 1 & 3 an inserted letter and
+ * 1 + word 2 mod 3 a substitution's shift ((old + shift) mod 4).  Letter
+ * encoding only. */
+#define RM_THRESH_MAX_COPIES 64
+
+typedef struct rm_threshold_params {
+  float err;       /* target mutation rate, 0 <= err < 1 */
+  int32_t copies;  /* mutated copies per window, 1..RM_THRESH_MAX_COPIES */
+  int32_t rank;    /* order statistic of the copies' fidelities, 0..copies-1 */
+  uint32_t seed;   /* the generator's key word 0 */
+} rm_threshold_params;
+
+/* d_thr [W] (device, caller-owned, FP32) = the threshold of every window of
+ * idx (d_ref its reference).  Errors: RM_EINVAL (null pointer, invalid index,
+ * err outside [0, 1)), RM_ESIZE (copies or rank out of range),
+ * RM_EUNSUPPORTED (a token index). */
+int rm_window_thresholds(const rm_index* idx, const uint8_t* d_ref,
+                         const rm_threshold_params* tp, float* d_thr, void* stream);
+
+/* Bytes of the workspace rm_score_threshold needs for n_reads reads and a
+ * candidate capacity; 0 if invalid. */
+size_t rm_threshold_workspace_bytes(int32_t n_reads, int64_t capacity);
+
+/* The threshold regime: for every read r, every window j with
+ * F(r, j) >= max(d_thr[j], floor_fidelity) and F(r, j) > 0, F recomputed in
+ * FP32 from the letters (as rm_rescore does), ranked by (F desc, window id
+ * asc).  The product in the index precision (reads from rm_encode_reads of the
+ * same index; d_read_scale as for rm_score_topk) proposes every pair within
+ * the product's error of the cut (2e-2 FP8, 2e-3 FP16, 1e-4 FP32), at most
+ * `capacity` pairs in all.  Output (device, caller-owned): d_hit_off
+ * [n_reads + 1] int64 offsets of each read's span in d_hit_idx / d_hit_score
+ * [capacity] (the spans hold the read's proposals); d_n_found [n_reads] the
+ * hits of each read, at d_hit_idx[d_hit_off[r] ..] ranked, the rest of the
+ * span id -1, score 0; *d_total the number of proposals found.  If *d_total
+ * exceeds capacity, proposals were dropped and the result is incomplete: call
+ * again with a capacity of at least *d_total.  Errors: RM_EINVAL (null
+ * pointer, invalid index, FP8 without read scales, floor_fidelity outside
+ * [0, 1]), RM_ESIZE (n_reads < 1, capacity < 1, workspace too small, 2^31 or
+ * more windows), RM_EUNSUPPORTED (a token index). */
+int rm_score_threshold(const rm_index* idx, const uint8_t* d_ref, const void* d_read_emb,
+                       const float* d_read_scale, const uint8_t* d_seq, const int64_t* d_off,
+                       int32_t n_reads, const float* d_thr, float floor_fidelity,
+                       int64_t capacity, int64_t* d_hit_off, int32_t* d_n_found,
+                       int32_t* d_hit_idx, float* d_hit_score, int64_t* d_total, void* d_ws,
+                       size_t ws_bytes, void* stream);
+
 /* ---- the correlation score (§2.4) -------------------------------------------
  * How well fidelity predicts the mutation rate: pairs (dna, mut) are sampled at
  * mutation rates err; per rate, E_fid is the mean fidelity of its pairs; the

@@ -40,6 +40,11 @@ class rm_index(ctypes.Structure):
                 ("d_token_class", ctypes.c_void_p)]
 
 
+class rm_threshold_params(ctypes.Structure):
+    _fields_ = [("err", ctypes.c_float), ("copies", ctypes.c_int32), ("rank", ctypes.c_int32),
+                ("seed", ctypes.c_uint32)]
+
+
 class rm_tuning(ctypes.Structure):
     _fields_ = [("read_tile", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32)]
 
@@ -50,6 +55,7 @@ RM_LEARNED_MAX_LEN = 256
 RM_LEARNED_MAX_PAIRS = 1024
 RM_REFINE_MAX_RADIUS = 7
 RM_CORR_MAX_RATES = 256
+RM_THRESH_MAX_COPIES = 64
 
 
 class RotorMapError(RuntimeError):
@@ -108,6 +114,11 @@ def lib():
             "rm_learned_gradient": (ctypes.c_int, [P, P, P, P, P, P, I32, I32, P, SZ, P, P, P]),
             "rm_levenshtein": (ctypes.c_int, [P, P, P, P, I64, P, P]),
             "rm_correlation_score": (ctypes.c_int, [P, P, I32, I32, P, P, P]),
+            "rm_window_thresholds": (ctypes.c_int, [IP, P, ctypes.POINTER(rm_threshold_params),
+                                                    P, P]),
+            "rm_threshold_workspace_bytes": (SZ, [I32, I64]),
+            "rm_score_threshold": (ctypes.c_int, [IP, P, P, P, P, P, I32, P, ctypes.c_float, I64,
+                                                  P, P, P, P, P, P, SZ, P]),
             "rm_delta_bytes": (SZ, [I64]),
             "rm_mlp_infer": (ctypes.c_int, [P, P, I64, P, P]),
             "rm_encode_reference_learned": (ctypes.c_int, [P, I64, PP, P, P, SZ, IP, P]),
@@ -405,3 +416,25 @@ def rm_correlation_score(d_F, d_err, n_rates: int, per_rate: int, d_E, d_rmse,
                          stream=None) -> None:
     _check(lib().rm_correlation_score(_ptr(d_F), _ptr(d_err), n_rates, per_rate, _ptr(d_E),
                                       _ptr(d_rmse), _stream(stream)), "rm_correlation_score")
+
+
+def rm_window_thresholds(idx: rm_index, d_ref, err: float, copies: int, rank: int, seed: int,
+                         d_thr, stream=None) -> None:
+    tp = rm_threshold_params(err, copies, rank, seed)
+    _check(lib().rm_window_thresholds(ctypes.byref(idx), _ptr(d_ref), ctypes.byref(tp),
+                                      _ptr(d_thr), _stream(stream)), "rm_window_thresholds")
+
+
+def rm_threshold_workspace_bytes(n_reads: int, capacity: int) -> int:
+    return int(lib().rm_threshold_workspace_bytes(n_reads, capacity))
+
+
+def rm_score_threshold(idx: rm_index, d_ref, d_read_emb, d_read_scale, d_seq, d_off, n_reads: int,
+                       d_thr, floor_fidelity: float, capacity: int, d_hit_off, d_n_found,
+                       d_hit_idx, d_hit_score, d_total, d_ws, ws_bytes: int, stream=None) -> None:
+    _check(lib().rm_score_threshold(ctypes.byref(idx), _ptr(d_ref), _ptr(d_read_emb),
+                                    _ptr(d_read_scale), _ptr(d_seq), _ptr(d_off), n_reads,
+                                    _ptr(d_thr), floor_fidelity, capacity, _ptr(d_hit_off),
+                                    _ptr(d_n_found), _ptr(d_hit_idx), _ptr(d_hit_score),
+                                    _ptr(d_total), _ptr(d_ws), ws_bytes, _stream(stream)),
+           "rm_score_threshold")

@@ -344,6 +344,51 @@ int rm_merge_strands(const int32_t* d_fwd_idx, const float* d_fwd_score, const i
                                              static_cast<hipStream_t>(stream)));
 }
 
+int rm_window_thresholds(const rm_index* idx, const uint8_t* d_ref,
+                         const rm_threshold_params* tp, float* d_thr, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_ref == nullptr || tp == nullptr || d_thr == nullptr) return RM_EINVAL;
+  if (!letter_encoding(&idx->p)) return RM_EUNSUPPORTED;
+  if (!(tp->err >= 0.f && tp->err < 1.f)) return RM_EINVAL;
+  if (tp->copies < 1 || tp->copies > RM_THRESH_MAX_COPIES || tp->rank < 0 ||
+      tp->rank >= tp->copies)
+    return RM_ESIZE;
+  return hip_status(rm::launch_window_thresholds(*idx, d_ref, tp->err, tp->copies, tp->rank,
+                                                 tp->seed, d_thr,
+                                                 static_cast<hipStream_t>(stream)));
+}
+
+size_t rm_threshold_workspace_bytes(int32_t n_reads, int64_t capacity) {
+  if (n_reads < 1 || capacity < 1 || capacity > ((int64_t)1 << 40)) return 0;
+  return rm::threshold_ws_layout(n_reads, capacity).total;
+}
+
+int rm_score_threshold(const rm_index* idx, const uint8_t* d_ref, const void* d_read_emb,
+                       const float* d_read_scale, const uint8_t* d_seq, const int64_t* d_off,
+                       int32_t n_reads, const float* d_thr, float floor_fidelity,
+                       int64_t capacity, int64_t* d_hit_off, int32_t* d_n_found,
+                       int32_t* d_hit_idx, float* d_hit_score, int64_t* d_total, void* d_ws,
+                       size_t ws_bytes, void* stream) {
+  int st = index_ok(idx);
+  if (st != RM_OK) return st;
+  if (d_ref == nullptr || d_read_emb == nullptr || d_seq == nullptr || d_off == nullptr ||
+      d_thr == nullptr || d_hit_off == nullptr || d_n_found == nullptr || d_hit_idx == nullptr ||
+      d_hit_score == nullptr || d_total == nullptr || d_ws == nullptr)
+    return RM_EINVAL;
+  if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
+  if (!letter_encoding(&idx->p)) return RM_EUNSUPPORTED;
+  if (!(floor_fidelity >= 0.f && floor_fidelity <= 1.f)) return RM_EINVAL;
+  if (n_reads < 1 || capacity < 1 || idx->n_windows > INT32_MAX) return RM_ESIZE;
+  const size_t need = rm_threshold_workspace_bytes(n_reads, capacity);
+  if (need == 0 || ws_bytes < need) return RM_ESIZE;
+  return hip_status(rm::launch_score_threshold(*idx, d_ref, d_read_emb, d_read_scale, d_seq,
+                                               d_off, n_reads, d_thr, floor_fidelity,
+                                               d_hit_off, d_n_found, d_hit_idx, d_hit_score,
+                                               d_total, capacity, d_ws,
+                                               static_cast<hipStream_t>(stream)));
+}
+
 size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius) {
   if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH || radius < 0 ||
       radius > RM_REFINE_MAX_RADIUS)

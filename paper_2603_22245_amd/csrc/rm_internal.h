@@ -312,6 +312,21 @@ hipError_t launch_learned_step(float* state, float lr, const uint8_t* a, const i
 hipError_t launch_levenshtein(const uint8_t* a, const int64_t* aoff, const uint8_t* b,
                               const int64_t* boff, int64_t n, int32_t* out, hipStream_t s);
 
+// per-fragment thresholds and the threshold regime (rm_thresh.hip)
+struct ThresholdWs {
+  size_t pool, keys, cand, cnt, fill, pool_n, total;  // byte offsets; total = size
+};
+ThresholdWs threshold_ws_layout(int32_t n_reads, int64_t capacity);
+hipError_t launch_window_thresholds(const rm_index& idx, const uint8_t* ref, float err,
+                                    int copies, int rank, uint32_t seed, float* thr,
+                                    hipStream_t s);
+hipError_t launch_score_threshold(const rm_index& idx, const uint8_t* ref,
+                                  const void* read_emb, const float* read_scale,
+                                  const uint8_t* seq, const int64_t* soff, int32_t R,
+                                  const float* thr, float floor_f, int64_t* hit_off,
+                                  int32_t* n_found, int32_t* hit_idx, float* hit_score,
+                                  int64_t* total, int64_t capacity, void* ws, hipStream_t s);
+
 hipError_t launch_correlation_score(const float* F, const float* err, int32_t n_rates,
                                     int32_t per, float* E, float* rmse, hipStream_t s);
 

@@ -1,0 +1,495 @@
+// Per-fragment fidelity thresholds and the threshold regime.
+//
+// §3.3 (closing paragraph): for a target mutation rate, the fidelity expected
+// of each reference fragment can serve as that fragment's cutting threshold.
+// §3.5: in the threshold regime the mapper reports every location whose
+// fidelity passes its fragment's precomputed threshold, as many as there are.
+//
+// Thresholds: window j is mutated `copies` times at rate err by the streaming
+// mutator the reads are simulated with (per step an insertion, a deletion or
+// a substitution with probability err/3 each, else a match, until N letters
+// are out; a step that needs a letter past the reference's end inserts).  The
+// draws come from Philox4x32-10 (Salmon et al., SC 2011) at counter (j mod
+// 2^32, j >> 32, copy, step) and key (seed, 0): word 0 picks the event by
+// integer comparison, word 1 & 3 is an inserted letter, 1 + word 2 mod 3 a
+// substitution's shift.  The threshold is the `rank`-th smallest fidelity of
+// the window with its copies (FP32 direct sums of the FP32 table).  One
+// wavefront per window; the 64 lanes take 64 consecutive steps of a copy at
+// once, and prefix counts over the lanes give each step's reference position
+// and output position.
+//
+// Regime: a product pass (the index precision on MFMA, read tile in
+// registers, window tiles through LDS) keeps every (read, window) whose
+// product fidelity is within the product's error of max(thr_j, floor) in a
+// pool; the pool is grouped by read (counts, prefix sums, scatter); then one
+// wavefront per read recomputes each candidate's F in FP32 from the letters,
+// keeps those with F >= max(thr_j, floor) and F > 0, and writes them ranked by
+// (F desc, window id asc).
+
+#include "rm_score_kernel.h"
+
+namespace rm {
+namespace {
+
+struct Words4 {
+  uint32_t x, y, z, w;
+};
+
+// Philox4x32-10: ten rounds; a round multiplies words 0 and 2 by the two
+// round constants (64-bit products as high and low halves) and mixes them
+// with words 1 and 3 and the key; the key advances by the Weyl constants
+// between rounds.
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// Number of lanes below this one whose bit is set in `mask`.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ float fidelity32(float2 a0, float2 a1, float A, float2 b0, float2 b1,
+                                            float B, int N) {
+  const float ipr = wave_sum(a0.x * b0.x + a0.y * b0.y + a1.x * b1.x + a1.y * b1.y);
+  const float ipi = wave_sum(a0.x * b0.y - a0.y * b0.x + a1.x * b1.y - a1.y * b1.x);
+  const bool deg = A < kDegenerateRel * N || B < kDegenerateRel * N;
+  return deg ? 0.f : (ipr * ipr + ipi * ipi) / (A * B);
+}
+
+constexpr int kThrWaves = 4;
+
+__global__ __launch_bounds__(64 * kThrWaves) void window_thresholds_kernel(
+    const uint8_t* __restrict__ ref, int64_t G, int64_t W, int N, int stride,
+    const float2* __restrict__ phase32, uint32_t T1, int copies, int rank, uint32_t seed,
+    int max_steps, float* __restrict__ thr) {
+  __shared__ uint8_t emitted[kThrWaves][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * kThrWaves + wave;
+  if (j >= W) return;
+  const int64_t start = j * stride;
+  const int k = lane >> 1, h = lane & 1;
+  const int L0 = 2 * h, L1 = 2 * h + 1;
+
+  float2 c0, c1;
+  direct_sum32(ref + start, N, phase32, lane, c0, c1);
+  const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+  float mine = 3.0e38f;  // lane c keeps copy c's fidelity
+  for (int c = 0; c < copies; ++c) {
+    float2 y0 = make_float2(0.f, 0.f), y1 = make_float2(0.f, 0.f);
+    int64_t pos = start;  // next reference letter
+    int n = 0;            // letters emitted
+    for (int t0 = 0; t0 < max_steps && n < N; t0 += 64) {
+      const int t = t0 + lane;
+      const Words4 d = philox4x32_10((uint32_t)j, (uint32_t)(j >> 32), (uint32_t)c, (uint32_t)t,
+                                     seed, 0u);
+      const bool live = t < max_steps;
+      // 0 insertion, 1 deletion, 2 substitution, 3 match
+      int kind = d.x < T1 ? 0 : d.x < 2u * T1 ? 1 : d.x < 3u * T1 ? 2 : 3;
+      // reference position of each step as if no step ran past the end; once
+      // it reaches G every later step is an insertion, so the positions
+      // before that point are exact
+      const uint64_t consume = __ballot(live && kind != 0);
+      const int64_t p = pos + lanes_below(consume);
+      if (p >= G) kind = 0;
+      const bool emit = live && kind != 1;
+      const uint64_t em = __ballot(emit);
+      const int q = lanes_below(em);  // this step's output index in the group
+      if (emit && n + q < N) {
+        int L;
+        if (kind == 0) {
+          L = (int)(d.y & 3u);
+        } else {
+          const int R0 = ref[p];
+          L = (kind == 3 || R0 > 3) ? R0 : (R0 + 1 + (int)(d.z % 3u)) & 3;
+        }
+        emitted[wave][q] = (uint8_t)L;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int m = min(__popcll(em), N - n);
+      for (int i = 0; i < m; ++i) {
+        const int L = emitted[wave][i];
+        const float2 e = phase32[(int64_t)(n + i) * kM + k];
+        y0.x += (L == L0) ? e.x : 0.f;
+        y0.y += (L == L0) ? e.y : 0.f;
+        y1.x += (L == L1) ? e.x : 0.f;
+        y1.y += (L == L1) ? e.y : 0.f;
+      }
+      __builtin_amdgcn_wave_barrier();  // emitted[] is rewritten by the next group
+      n += m;
+      pos += __popcll(__ballot(live && kind != 0));
+    }
+    const float Y = wave_sum(y0.x * y0.x + y0.y * y0.y + y1.x * y1.x + y1.y * y1.y);
+    const float F = fidelity32(c0, c1, C, y0, y1, Y, N);
+    if (lane == c) mine = F;
+  }
+  // ascending bitonic sort of the copies' fidelities over the 64 lanes
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+    for (int dd = kk >> 1; dd > 0; dd >>= 1) {
+      const float other = __shfl_xor(mine, dd, 64);
+      const bool up = (lane & kk) == 0;
+      const bool lower = (lane & dd) == 0;
+      const float lo = fminf(mine, other), hi = fmaxf(mine, other);
+      mine = (lower == up) ? lo : hi;
+    }
+  }
+  if (lane == rank) thr[j] = mine;
+}
+
+// ---- the regime's product pass
+
+template <int PREC>
+struct ThrK {
+  static constexpr int NF = PREC == RM_FP32 ? 1 : 2;      // fragments (16 reads) per wavefront
+  static constexpr int WAVES = 4;
+  static constexpr int THREADS = WAVES * 64;
+  static constexpr int READS = WAVES * NF * 16;
+  static constexpr int esize = Prec<PREC>::esize;
+  static constexpr int RB = kReal * esize;
+  static constexpr int CPR = RB / 16;
+  static constexpr int AU4 = (kReal / 2) * esize / 16;
+  static constexpr int TW = kBlkW;                          // windows per tile
+  static constexpr int TILE = TW * RB;
+  static constexpr int L = TILE / 1024 / WAVES;             // 1 KB copies per wavefront per tile
+  static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 2 : 1);  // + thresholds (+ window scales)
+  static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile");
+};
+
+// Product pass of the regime.  Block = (read tile, window chunk); the read
+// tile sits in registers, window tiles of 32 are copied straight from global
+// memory into a two-stage LDS ring (rows XOR-swizzled as the top-k product
+// stores them), each wavefront copying its share plus its own copy of the
+// tile's thresholds (and FP8 window scales), and waiting for its own copies
+// before the block barrier.
+template <int PREC>
+__global__ __launch_bounds__(ThrK<PREC>::THREADS) void threshold_scan_kernel(
+    const uint8_t* __restrict__ index, const float* __restrict__ win_scale, int64_t W,
+    const float* __restrict__ thr, float floor_f, float margin, const uint8_t* __restrict__ reads,
+    const float* __restrict__ read_scale, int32_t R, int64_t chunk_windows, int n_chunks,
+    uint64_t* __restrict__ pool, uint64_t pool_cap, unsigned long long* __restrict__ pool_n) {
+  using K = ThrK<PREC>;
+  constexpr bool kFp8 = PREC == RM_FP8_E4M3;
+  __shared__ __attribute__((aligned(16))) uint8_t ring[2][K::TILE];
+  __shared__ float side[2][2][K::WAVES][K::TW];  // [stage][thr, scale][wave][window]
+  __shared__ float rsq[K::READS];  // squared read scale per read slot, 0 past the last read
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 5, col = lane & 31;
+  const int tile_r = blockIdx.x / n_chunks, chunk = blockIdx.x % n_chunks;
+  const int64_t read0 = (int64_t)tile_r * K::READS;
+  const int64_t wbeg = (int64_t)chunk * chunk_windows;
+  const int64_t wend = min(W, wbeg + chunk_windows);
+  if (wbeg >= wend) return;  // uniform over the block
+  const int ntiles = (int)((wend - wbeg + K::TW - 1) / K::TW);
+
+  // A fragments, and each read slot's squared scale
+  uint4 a[K::NF][K::AU4];
+#pragma unroll
+  for (int f = 0; f < K::NF; ++f) {
+    const int64_t row = 2 * read0 + (int64_t)(wave * K::NF + f) * 32 + col;
+    const uint4* src = reinterpret_cast<const uint4*>(reads + row * K::RB + g * (K::RB / 2));
+#pragma unroll
+    for (int u = 0; u < K::AU4; ++u) a[f][u] = row < 2 * (int64_t)R ? src[u] : make_uint4(0, 0, 0, 0);
+  }
+  if (tid < K::READS) {
+    const int64_t r = read0 + tid;
+    float sc = 1.f;
+    if constexpr (kFp8) sc = r < R ? read_scale[r] : 0.f;
+    rsq[tid] = r < R ? sc * sc : 0.f;
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the fragments and scales, before any copy is in flight
+
+  const uint32_t ring_lds = lds_offset(ring);
+  const uint32_t side_lds = lds_offset(side);
+  int drow[K::L];
+  uint32_t doff[K::L];
+#pragma unroll
+  for (int i = 0; i < K::L; ++i) {
+    const int pos = (i * K::WAVES + wave) * 64 + lane;  // physical 16-byte chunk in the tile
+    const int r = pos / K::CPR;
+    drow[i] = r;
+    doff[i] = (uint32_t)((pos % K::CPR) ^ (r & 15)) * 16u;  // the logical chunk stored there
+  }
+  auto issue = [&](int t) {
+    const int stage = t & 1;
+    const int64_t tb = wbeg + (int64_t)t * K::TW;
+#pragma unroll
+    for (int i = 0; i < K::L; ++i) {
+      const int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
+      dma16(index + grow * K::RB + doff[i],
+            __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * K::WAVES + wave) * 1024));
+    }
+    const int64_t jj = min(tb + lane, wend - 1);
+    if (lane < K::TW)
+      dma4(thr + jj, __builtin_amdgcn_readfirstlane(
+                         side_lds + (((stage * 2 + 0) * K::WAVES + wave) * K::TW) * 4));
+    if constexpr (kFp8) {
+      if (lane < K::TW)
+        dma4(win_scale + jj, __builtin_amdgcn_readfirstlane(
+                                 side_lds + (((stage * 2 + 1) * K::WAVES + wave) * K::TW) * 4));
+    }
+  };
+  const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
+
+  issue(0);
+  for (int t = 0; t < ntiles; ++t) {
+    const int stage = t & 1;
+    if (t + 1 < ntiles) {
+      issue(t + 1);          // into the stage every wavefront finished reading before the
+      wait_vmcnt<K::LT>();   // last barrier; then this wavefront's copies of tile t are in
+    } else {
+      wait_vmcnt<0>();
+    }
+    __syncthreads();         // ... and every wavefront's
+    f32x16 acc[K::NF][1];
+#pragma unroll
+    for (int f = 0; f < K::NF; ++f) acc[f][0] = f32x16{};
+    mfma_tile<PREC, K::NF, 1, K::AU4>(a, &ring[stage][col * K::RB], kx, acc);
+    // epilogue: this lane's window column against its cut, less the margin
+    const int64_t j = wbeg + (int64_t)t * K::TW + col;
+    const bool colok = j < wend;
+    const float cut = fmaxf(side[stage][0][wave][col], floor_f) - margin;
+    float sj2 = 1.f;
+    if constexpr (kFp8) {
+      const float sc = side[stage][1][wave][col];
+      sj2 = sc * sc;
+    }
+#pragma unroll
+    for (int f = 0; f < K::NF; ++f)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float re = acc[f][0][2 * q], im = acc[f][0][2 * q + 1];
+        const int slot = wave * K::NF * 16 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+        const float F = (re * re + im * im) * (rsq[slot] * sj2);
+        if (colok && F > 0.f && F >= cut) {
+          const int64_t r = read0 + slot;
+          const unsigned long long p = atomicAdd(pool_n, 1ull);
+          if (p < pool_cap) pool[p] = ((uint64_t)r << 32) | (uint64_t)(uint32_t)j;
+        }
+      }
+    __syncthreads();         // stage `stage` is refilled by the next iteration's copies
+  }
+}
+
+// ---- grouping the pool by read
+
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void zero_counter_kernel(unsigned long long* __restrict__ p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+__global__ void pool_count_kernel(const uint64_t* __restrict__ pool,
+                                  const unsigned long long* __restrict__ pool_n, uint64_t cap,
+                                  uint32_t* __restrict__ cnt) {
+  const uint64_t n = min((uint64_t)*pool_n, cap);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[pool[i] >> 32], 1u);
+}
+
+// Exclusive prefix sums off[0..R] of cnt[0..R) in one block: each thread
+// sums a contiguous segment, the block scans the segment sums, then each
+// thread writes its segment's offsets.  Also writes the untruncated pool size.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(
+    const uint32_t* __restrict__ cnt, int32_t R, int64_t* __restrict__ off,
+    const unsigned long long* __restrict__ pool_n, int64_t* __restrict__ total) {
+  __shared__ int64_t part[kScanThreads];
+  const int t = threadIdx.x;
+  const int64_t seg = ((int64_t)R + kScanThreads - 1) / kScanThreads;
+  const int64_t b = min((int64_t)R, t * seg), e = min((int64_t)R, b + seg);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int64_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == kScanThreads - 1) {
+    off[R] = part[t];
+    *total = (int64_t)*pool_n;
+  }
+}
+
+__global__ void pool_scatter_kernel(const uint64_t* __restrict__ pool,
+                                    const unsigned long long* __restrict__ pool_n, uint64_t cap,
+                                    const int64_t* __restrict__ off, uint32_t* __restrict__ fill,
+                                    int32_t* __restrict__ cand) {
+  const uint64_t n = min((uint64_t)*pool_n, cap);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = (uint32_t)(pool[i] >> 32);
+    const uint32_t at = atomicAdd(&fill[r], 1u);
+    cand[off[r] + at] = (int32_t)(uint32_t)pool[i];
+  }
+}
+
+// One wavefront per read: FP32 F of every candidate from the letters, the
+// hits (F >= max(thr_j, floor), F > 0) as keys, then ranked by repeated
+// wavefront maxima into the read's span of the output.
+__global__ __launch_bounds__(256) void threshold_rescore_kernel(
+    const uint8_t* __restrict__ ref, int N, int stride, const float2* __restrict__ phase32,
+    const uint8_t* __restrict__ seq, const int64_t* __restrict__ soff, int32_t R,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ cand,
+    const float* __restrict__ thr, float floor_f, uint64_t* __restrict__ keys,
+    int32_t* __restrict__ n_found, int32_t* __restrict__ hit_idx, float* __restrict__ hit_score) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;
+  const int64_t b = off[r], e = off[r + 1];
+  const int64_t len = soff[r + 1] - soff[r];
+  float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
+  if (len >= N) direct_sum32(seq + soff[r], N, phase32, lane, x0, x1);
+  const float X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
+  int kept = 0;
+  for (int64_t i = b; i < e; ++i) {
+    const int32_t j = cand[i];
+    float2 c0, c1;
+    direct_sum32(ref + (int64_t)j * stride, N, phase32, lane, c0, c1);
+    const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+    const float F = fidelity32(x0, x1, X, c0, c1, C, N);
+    if (F > 0.f && F >= fmaxf(thr[j], floor_f)) {
+      if (lane == 0) keys[b + kept] = make_key(F, j);
+      ++kept;
+    }
+  }
+  // lane 0's key stores are read back by every lane: make them visible
+  // (stores completed, this compute unit's cache not holding stale lines)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  uint64_t prev = ~0ull;
+  for (int o = 0; o < kept; ++o) {
+    uint64_t best = 0;
+    for (int i = lane; i < kept; i += 64) {
+      const uint64_t v = keys[b + i];
+      best = (v < prev && v > best) ? v : best;
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) write_list_entry(best, &hit_idx[b + o], &hit_score[b + o]);
+    prev = best;
+  }
+  for (int64_t i = b + kept + lane; i < e; i += 64) write_list_entry(0, &hit_idx[i], &hit_score[i]);
+  if (lane == 0) n_found[r] = kept;
+}
+
+}  // namespace
+
+hipError_t launch_window_thresholds(const rm_index& idx, const uint8_t* ref, float err,
+                                    int copies, int rank, uint32_t seed, float* thr,
+                                    hipStream_t s) {
+  const uint32_t T1 = (uint32_t)floor((double)err / 3.0 * 4294967296.0);
+  const int N = idx.p.window_len;
+  const int64_t blocks = (idx.n_windows + kThrWaves - 1) / kThrWaves;
+  hipLaunchKernelGGL(window_thresholds_kernel, dim3((unsigned)blocks), dim3(64 * kThrWaves), 0, s,
+                     ref, idx.ref_len, idx.n_windows, N, idx.p.stride,
+                     reinterpret_cast<const float2*>(idx.d_phase32), T1, copies, rank, seed,
+                     8 * N + 64, thr);
+  return hipGetLastError();
+}
+
+ThresholdWs threshold_ws_layout(int32_t n_reads, int64_t capacity) {
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  ThresholdWs L{};
+  size_t o = 0;
+  L.pool = o;    o += up((size_t)capacity * 8);
+  L.keys = o;    o += up((size_t)capacity * 8);
+  L.cand = o;    o += up((size_t)capacity * 4);
+  L.cnt = o;     o += up((size_t)n_reads * 4);
+  L.fill = o;    o += up((size_t)n_reads * 4);
+  L.pool_n = o;  o += 256;
+  L.total = o;
+  return L;
+}
+
+hipError_t launch_score_threshold(const rm_index& idx, const uint8_t* ref,
+                                  const void* read_emb, const float* read_scale,
+                                  const uint8_t* seq, const int64_t* soff, int32_t R,
+                                  const float* thr, float floor_f, int64_t* hit_off,
+                                  int32_t* n_found, int32_t* hit_idx, float* hit_score,
+                                  int64_t* total, int64_t capacity, void* ws, hipStream_t s) {
+  const ThresholdWs L = threshold_ws_layout(R, capacity);
+  uint8_t* base = static_cast<uint8_t*>(ws);
+  uint64_t* pool = reinterpret_cast<uint64_t*>(base + L.pool);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(base + L.keys);
+  int32_t* cand = reinterpret_cast<int32_t*>(base + L.cand);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+  uint32_t* fill = reinterpret_cast<uint32_t*>(base + L.fill);
+  auto* pool_n = reinterpret_cast<unsigned long long*>(base + L.pool_n);
+  const int prec = idx.p.precision;
+  // the product's largest error in fidelity units (FP16 / FP8 rounding of
+  // unit vectors, FP32 rolling drift), so no pair at or above its cut is lost
+  const float margin = prec == RM_FP8_E4M3 ? 2e-2f : prec == RM_FP16 ? 2e-3f : 1e-4f;
+
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(256), dim3(256), 0, s, cnt, (int64_t)R);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(256), dim3(256), 0, s, fill, (int64_t)R);
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, pool_n);
+
+  const int64_t W = idx.n_windows;
+  auto scan = [&](auto kern, int reads_per_block, int threads) {
+    const int64_t n_rt = ((int64_t)R + reads_per_block - 1) / reads_per_block;
+    int64_t n_chunks = (4096 + n_rt - 1) / n_rt;
+    const int64_t max_chunks = (W + 1023) / 1024;  // at least 1,024 windows per chunk
+    if (n_chunks > max_chunks) n_chunks = max_chunks;
+    if (n_chunks < 1) n_chunks = 1;
+    int64_t cw = (W + n_chunks - 1) / n_chunks;
+    cw = (cw + kBlkW - 1) / kBlkW * kBlkW;
+    n_chunks = (W + cw - 1) / cw;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(n_rt * n_chunks)), dim3(threads), 0, s,
+                       static_cast<const uint8_t*>(idx.d_emb), idx.d_scale, W, thr, floor_f,
+                       margin, static_cast<const uint8_t*>(read_emb), read_scale, R, cw,
+                       (int)n_chunks, pool, (uint64_t)capacity, pool_n);
+  };
+  if (prec == RM_FP32)
+    scan(threshold_scan_kernel<RM_FP32>, ThrK<RM_FP32>::READS, ThrK<RM_FP32>::THREADS);
+  else if (prec == RM_FP16)
+    scan(threshold_scan_kernel<RM_FP16>, ThrK<RM_FP16>::READS, ThrK<RM_FP16>::THREADS);
+  else
+    scan(threshold_scan_kernel<RM_FP8_E4M3>, ThrK<RM_FP8_E4M3>::READS,
+         ThrK<RM_FP8_E4M3>::THREADS);
+
+  hipLaunchKernelGGL(pool_count_kernel, dim3(1024), dim3(256), 0, s, pool, pool_n,
+                     (uint64_t)capacity, cnt);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, cnt, R, hit_off, pool_n,
+                     total);
+  hipLaunchKernelGGL(pool_scatter_kernel, dim3(1024), dim3(256), 0, s, pool, pool_n,
+                     (uint64_t)capacity, hit_off, fill, cand);
+  hipLaunchKernelGGL(threshold_rescore_kernel, dim3((unsigned)(((int64_t)R + 3) / 4)), dim3(256),
+                     0, s, ref, idx.p.window_len, idx.p.stride,
+                     reinterpret_cast<const float2*>(idx.d_phase32), seq, soff, R, hit_off, cand,
+                     thr, floor_f, keys, n_found, hit_idx, hit_score);
+  return hipGetLastError();
+}
+
+}  // namespace rm

@@ -218,6 +218,61 @@ def map_reads(index: Index, reads: ReadBatch, bufs: MapBuffers, stream=None):
     rescore(index, reads, bufs, stream)
 
 
+def window_thresholds(index: Index, err: float, copies: int = 16, rank: int = 1, seed: int = 1,
+                      stream=None):
+    """Per-window cutting thresholds at a target mutation rate (§3.3): the
+    rank-th smallest fidelity of each window with `copies` mutated copies of
+    itself.  Returns a device float32 tensor [W]."""
+    torch = _torch()
+    thr = torch.empty(index.n_windows, dtype=torch.float32, device=index.buf.device)
+    L.rm_window_thresholds(index.idx, index.ref, err, copies, rank, seed, thr, stream)
+    return thr
+
+
+@dataclasses.dataclass
+class ThresholdHits:
+    hit_off: object    # [R+1] int64: read r's span is hit_idx[hit_off[r] : hit_off[r+1]]
+    n_found: object    # [R] int32: hits of read r, ranked at the start of its span
+    hit_idx: object    # [capacity] int32 window ids (-1 past n_found)
+    hit_score: object  # [capacity] FP32 fidelities
+    total: object      # [1] int64: proposals found (> capacity: incomplete)
+    capacity: int
+
+    def lists(self):
+        """Per read, (window ids, F) of its hits as numpy arrays (host)."""
+        off = self.hit_off.cpu().numpy()
+        n = self.n_found.cpu().numpy()
+        idx = self.hit_idx.cpu().numpy()
+        sc = self.hit_score.cpu().numpy()
+        return [(idx[off[r]:off[r] + n[r]], sc[off[r]:off[r] + n[r]]) for r in range(n.size)]
+
+
+def score_threshold(index: Index, reads: ReadBatch, thr, floor: float = 0.0,
+                    capacity: Optional[int] = None, stream=None) -> ThresholdHits:
+    """The threshold regime (§3.5): every window whose FP32 fidelity with the
+    read passes max(its threshold, floor).  The read heads must have been
+    encoded (encode_reads).  If the proposals exceed `capacity` the call is
+    repeated once with the capacity the first pass reported."""
+    torch = _torch()
+    dev = index.buf.device
+    cap = capacity if capacity is not None else max(1024, 64 * reads.n)
+    while True:
+        ws_bytes = L.rm_threshold_workspace_bytes(reads.n, cap)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        h = ThresholdHits(torch.empty(reads.n + 1, dtype=torch.int64, device=dev),
+                          torch.empty(reads.n, dtype=torch.int32, device=dev),
+                          torch.empty(cap, dtype=torch.int32, device=dev),
+                          torch.empty(cap, dtype=torch.float32, device=dev),
+                          torch.empty(1, dtype=torch.int64, device=dev), cap)
+        L.rm_score_threshold(index.idx, index.ref, reads.emb, reads.scale, reads.seq, reads.off,
+                             reads.n, thr, floor, cap, h.hit_off, h.n_found, h.hit_idx,
+                             h.hit_score, h.total, ws, ws_bytes, stream)
+        total = int(h.total.cpu()[0])
+        if total <= cap or capacity is not None:
+            return h
+        cap = total
+
+
 @dataclasses.dataclass
 class StrandResult:
     top_idx: object      # [R][k] window ids

@@ -279,3 +279,38 @@ def test_token_params_validation():
         == L.RM_EUNSUPPORTED
     assert lib.rm_encode_reference_learned(0x1000, 20_000, R(ok[0]), 0x3000, 0x10000, 1 << 30,
                                            R(out), None) == L.RM_EUNSUPPORTED
+
+
+def test_threshold_and_correlation_validation():
+    """Argument checks of the threshold, threshold-regime and correlation
+    entry points (host side, nothing enqueued)."""
+    lib = L.lib()
+    R = ctypes.byref
+    idx = _fake_index()
+    TP = L.rm_threshold_params
+    th = lambda tp: lib.rm_window_thresholds(R(idx), 1, R(tp), 1, None)
+    assert th(TP(1.0, 16, 1, 0)) == L.RM_EINVAL                    # err outside [0, 1)
+    assert th(TP(-0.1, 16, 1, 0)) == L.RM_EINVAL
+    assert th(TP(0.1, 0, 0, 0)) == L.RM_ESIZE
+    assert th(TP(0.1, L.RM_THRESH_MAX_COPIES + 1, 0, 0)) == L.RM_ESIZE
+    assert th(TP(0.1, 16, 16, 0)) == L.RM_ESIZE                    # rank >= copies
+    assert lib.rm_window_thresholds(R(idx), None, R(TP(0.1, 16, 1, 0)), 1, None) == L.RM_EINVAL
+    tok = _fake_index()
+    tok.p.mer_len, tok.p.n_freq, tok.p.n_class, tok.d_token_class = 2, 8, 16, 0x100000
+    assert lib.rm_window_thresholds(R(tok), 1, R(TP(0.1, 16, 1, 0)), 1, None) == L.RM_EUNSUPPORTED
+    assert L.rm_threshold_workspace_bytes(0, 100) == 0
+    assert L.rm_threshold_workspace_bytes(10, 0) == 0
+    ws = L.rm_threshold_workspace_bytes(100, 1000)
+    assert ws >= 1000 * 20 + 100 * 8
+    st = lambda floor, cap, nb, n=100, i=idx, scale=1: lib.rm_score_threshold(
+        R(i), 1, 1, scale, 1, 1, n, 1, floor, cap, 1, 1, 1, 1, 1, 1, nb, None)
+    assert st(0.0, 1000, ws - 1) == L.RM_ESIZE
+    assert st(0.0, 0, ws) == L.RM_ESIZE
+    assert st(0.0, 1000, ws, n=0) == L.RM_ESIZE
+    assert st(1.5, 1000, ws) == L.RM_EINVAL
+    assert st(0.0, 1000, ws, i=_fake_index("fp8"), scale=None) == L.RM_EINVAL
+    assert st(0.0, 1000, ws, i=tok) == L.RM_EUNSUPPORTED
+    cs = lambda n, per: lib.rm_correlation_score(1, 1, n, per, 1, 1, None)
+    assert cs(0, 10) == L.RM_ESIZE and cs(L.RM_CORR_MAX_RATES + 1, 10) == L.RM_ESIZE
+    assert cs(5, 0) == L.RM_ESIZE
+    assert lib.rm_correlation_score(None, 1, 5, 10, 1, 1, None) == L.RM_EINVAL
