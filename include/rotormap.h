@@ -188,6 +188,26 @@ int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_re
                   int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx, float* d_cand_score,
                   void* d_ws, size_t ws_bytes, void* stream);
 
+/* ---- rm_score_topk without a caller workspace ---------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  The same
+ * call as rm_score_topk, with its workspace in a device array the library
+ * owns: RM_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * until the process ends (enough for rm_score_workspace_bytes of 100,000
+ * reads against 10^7 windows with 16 candidates).  The array of the CURRENT
+ * device is used, so call it with the stream's device current.  Its device
+ * address is looked up on the first call on each device; no call allocates or
+ * frees memory.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller; each call clears what must start at zero.
+ * Errors: as rm_score_topk; RM_ESIZE also when rm_score_workspace_bytes
+ * exceeds RM_NOALLOC_SCRATCH_BYTES; RM_EHIP if the array's address cannot be
+ * found; RM_EUNSUPPORTED for a device index of 64 or more. */
+#define RM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int rm_score_topk_noalloc(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
+                          int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx,
+                          float* d_cand_score, void* stream);
+
 /* Rescore the candidates in FP32 and keep the k best (the refinement idea of
  * §3.4 applied to the candidates): each candidate window's encoding and the
  * read head's encoding are recomputed directly from the letters with the

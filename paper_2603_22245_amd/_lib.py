@@ -19,6 +19,7 @@ RM_OK, RM_EINVAL, RM_ESIZE, RM_EUNSUPPORTED, RM_EHIP = 0, -1, -2, -3, -4
 RM_FP32, RM_FP16, RM_FP8_E4M3 = 0, 1, 2
 RM_SCHED_DEFAULT, RM_SCHED_FINETUNED = 0, 1
 RM_DIM, RM_MAX_WINDOW, RM_MAX_KFETCH = 32, 16384, 32
+RM_NOALLOC_SCRATCH_BYTES = 256 << 20
 RM_MAX_MER, RM_TOKEN_SKIP, RM_MAX_FREQUENT = 8, 255, 128
 PRECISIONS = {"fp32": RM_FP32, "fp16": RM_FP16, "fp8": RM_FP8_E4M3}
 SCHEDULES = {"default": RM_SCHED_DEFAULT, "finetuned": RM_SCHED_FINETUNED}
@@ -87,6 +88,7 @@ def lib():
             "rm_score_workspace_bytes": (SZ, [IP, I32, I32]),
             "rm_score_topk": (ctypes.c_int, [IP, P, P, I32, I32, P, P, P, SZ, P]),
             "rm_rescore": (ctypes.c_int, [IP, P, P, P, I32, I32, P, I32, P, P, P]),
+            "rm_score_topk_noalloc": (ctypes.c_int, [IP, P, P, I32, I32, P, P, P]),
             "rm_refine_workspace_bytes": (SZ, [I32, I32, I32]),
             "rm_reverse_complement": (ctypes.c_int, [P, P, I32, I64, P, P]),
             "rm_token_counts_bytes": (ctypes.c_size_t, [I32]),
@@ -217,6 +219,13 @@ def rm_score_topk(idx: rm_index, d_read_emb, d_read_scale, n_reads: int, k_fetch
     _check(lib().rm_score_topk(ctypes.byref(idx), _ptr(d_read_emb), _ptr(d_read_scale), n_reads,
                                k_fetch, _ptr(d_cand_idx), _ptr(d_cand_score), _ptr(d_ws), ws_bytes,
                                _stream(stream)), "rm_score_topk")
+
+
+def rm_score_topk_noalloc(idx: rm_index, d_read_emb, d_read_scale, n_reads: int, k_fetch: int,
+                          d_cand_idx, d_cand_score, stream=None) -> None:
+    _check(lib().rm_score_topk_noalloc(ctypes.byref(idx), _ptr(d_read_emb), _ptr(d_read_scale),
+                                       n_reads, k_fetch, _ptr(d_cand_idx), _ptr(d_cand_score),
+                                       _stream(stream)), "rm_score_topk_noalloc")
 
 
 def rm_rescore(idx: rm_index, d_ref, d_seq, d_off, n_reads: int, k_fetch: int, d_cand_idx, k: int,

@@ -4,6 +4,8 @@
 
 #include <new>
 
+#include <mutex>
+
 #include "rm_internal.h"
 #include "rm_tokens.h"
 
@@ -106,6 +108,31 @@ int index_ok(const rm_index* idx) {
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? RM_OK : RM_EHIP; }
+
+// Workspace of rm_score_topk_noalloc: a device array of the library, one copy
+// per GPU, held until the process ends.  In host code `scratch` names a host
+// stand-in, not device memory; its device address is looked up once per
+// device (with that device current) and only that address is used.
+constexpr size_t kNoallocAlign = 256;
+__device__ __align__(256) static uint8_t scratch[RM_NOALLOC_SCRATCH_BYTES];
+constexpr int kNoallocDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoallocDevices] = {};
+
+// The current device's copy of `scratch`.
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RM_EHIP;
+  if (dev < 0 || dev >= kNoallocDevices) return RM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return RM_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RM_OK;
+}
 
 }  // namespace
 
@@ -274,6 +301,24 @@ int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_re
   }
   return rm_score_topk_groups(idx, 1, &d_read_emb, &d_read_scale, &n_reads, k_fetch, &d_cand_idx,
                               &d_cand_score, d_ws, ws_bytes, nullptr, stream);
+}
+
+int rm_score_topk_noalloc(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
+                          int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx,
+                          float* d_cand_score, void* stream) {
+  if (idx == nullptr || d_read_emb == nullptr || d_cand_idx == nullptr || d_cand_score == nullptr)
+    return RM_EINVAL;
+  if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
+  const size_t need = rm_score_workspace_bytes(idx, n_reads, k_fetch);
+  if (need == 0)  // invalid arguments: rm_score_topk names the error and enqueues nothing
+    return rm_score_topk(idx, d_read_emb, d_read_scale, n_reads, k_fetch, d_cand_idx,
+                         d_cand_score, reinterpret_cast<void*>(kNoallocAlign), 0, stream);
+  if (need > (size_t)RM_NOALLOC_SCRATCH_BYTES) return RM_ESIZE;
+  void* ws = nullptr;
+  const int st = noalloc_scratch(&ws);
+  if (st != RM_OK) return st;
+  return rm_score_topk(idx, d_read_emb, d_read_scale, n_reads, k_fetch, d_cand_idx, d_cand_score,
+                       ws, (size_t)RM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int rm_rescore(const rm_index* idx, const uint8_t* d_ref, const uint8_t* d_seq,

@@ -314,3 +314,18 @@ def test_threshold_and_correlation_validation():
     assert cs(0, 10) == L.RM_ESIZE and cs(L.RM_CORR_MAX_RATES + 1, 10) == L.RM_ESIZE
     assert cs(5, 0) == L.RM_ESIZE
     assert lib.rm_correlation_score(None, 1, 5, 10, 1, 1, None) == L.RM_EINVAL
+
+
+def test_noalloc_validation():
+    """The entry point that allocates nothing validates like rm_score_topk and
+    rejects workspaces above its scratch before touching the device."""
+    lib = L.lib()
+    R = ctypes.byref
+    idx = _fake_index()
+    assert lib.rm_score_topk_noalloc(None, 1, 1, 10, 8, 1, 1, None) == L.RM_EINVAL
+    assert lib.rm_score_topk_noalloc(R(idx), None, 1, 10, 8, 1, 1, None) == L.RM_EINVAL
+    assert lib.rm_score_topk_noalloc(R(idx), 1, 1, 0, 8, 1, 1, None) == L.RM_ESIZE
+    assert lib.rm_score_topk_noalloc(R(idx), 1, 1, 10, 33, 1, 1, None) == L.RM_ESIZE
+    big = 4_000_000
+    assert L.rm_score_workspace_bytes(idx, big, 32) > L.RM_NOALLOC_SCRATCH_BYTES
+    assert lib.rm_score_topk_noalloc(R(idx), 1, 1, big, 32, 1, 1, None) == L.RM_ESIZE
