@@ -370,7 +370,7 @@ int rm_correlation_score(const float* d_F, const float* d_err, int32_t n_rates, 
  * tokens and a slide turns every component by omega^-f, takes omega^-f off
  * the class of the token leaving and adds omega^{f (N-s)} to the class of the
  * token entering. */
-#define RM_REFINE_MAX_RADIUS 7
+#define RM_REFINE_MAX_RADIUS 31  /* 2 radius + 1 <= 63 starts per candidate */
 
 /* Bytes of the workspace rm_refine needs (256-byte multiple); 0 if invalid. */
 size_t rm_refine_workspace_bytes(int32_t n_reads, int32_t k_fetch, int32_t radius);

@@ -54,7 +54,7 @@ RM_MAX_GROUPS = 8
 RM_LEARNED_PARAMS = 10432
 RM_LEARNED_MAX_LEN = 256
 RM_LEARNED_MAX_PAIRS = 1024
-RM_REFINE_MAX_RADIUS = 7
+RM_REFINE_MAX_RADIUS = 31
 RM_CORR_MAX_RATES = 256
 RM_THRESH_MAX_COPIES = 64
 

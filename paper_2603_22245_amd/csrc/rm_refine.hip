@@ -181,15 +181,15 @@ __global__ __launch_bounds__(256) void refine_tokens_kernel(
   }
 }
 
-// One wavefront per read over its k_fetch * span keys (at most 8 per lane):
-// k rounds of a wavefront maximum; every key of the winning start leaves the
-// pool (neighbourhoods of nearby candidates overlap, and their FP32 values of
-// a shared start may differ in the last bits).
+// One wavefront per read over its k_fetch * span keys (at most EMAX per
+// lane): k rounds of a wavefront maximum; every key of the winning start
+// leaves the pool (neighbourhoods of nearby candidates overlap, and their FP32
+// values of a shared start may differ in the last bits).
+template <int EMAX>
 __global__ __launch_bounds__(256) void refine_select_kernel(const uint64_t* __restrict__ pool, int n,
                                                             int32_t R, int k,
                                                             int32_t* __restrict__ top_idx,
                                                             float* __restrict__ top_score) {
-  constexpr int EMAX = 8;
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= R) return;  // whole wavefront
@@ -242,8 +242,11 @@ hipError_t launch_refine(const rm_index& coarse, const uint8_t* ref, const uint8
 
 hipError_t launch_refine_select(const uint64_t* pool, int n, int32_t n_reads, int32_t k,
                                 int32_t* top_idx, float* top_score, hipStream_t s) {
-  hipLaunchKernelGGL(refine_select_kernel, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256),
-                     0, s, pool, n, n_reads, k, top_idx, top_score);
+  // n = k_fetch (2 radius + 1) <= 32 x 63 keys per read
+  auto kern = n <= 512 ? refine_select_kernel<8> : n <= 1024 ? refine_select_kernel<16>
+                                                             : refine_select_kernel<32>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0, s, pool, n,
+                     n_reads, k, top_idx, top_score);
   return hipGetLastError();
 }
 

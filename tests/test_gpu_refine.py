@@ -29,7 +29,9 @@ def step1_oracle():
 
 
 @pytest.mark.parametrize("precision,stride,radius", [("fp32", 2, 1), ("fp16", 4, 3),
-                                                     ("fp16", 8, 7), ("fp8", 4, 2)])
+                                                     ("fp16", 8, 7), ("fp8", 4, 2),
+                                                     ("fp16", 16, 15), ("fp8", 16, 15),
+                                                     ("fp32", 32, 31)])
 def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
     from paper_2603_22245_amd import mapper
     torch = torch_cuda()
@@ -51,8 +53,10 @@ def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
           f"refinement {same:.3f}; recall@{K} vs all step-1 windows {rec:.4f}")
     # the method's own recall (coarse candidates that miss a location cannot be
     # refined into it, and a radius below stride - 1 leaves gaps): measured
-    # 0.9994, 0.983, 0.897 and 0.937, asserted with margin
-    assert rec >= {2: 0.99, 4: 0.97 if radius == 3 else 0.9, 8: 0.85}[stride]
+    # 0.9994, 0.983, 0.897 and 0.937 at strides 2, 4, 8 and 4 (radius 2); at
+    # strides 16 and 32 only the product's sense of the best coarse windows is
+    # tested, so the floor is low
+    assert rec >= {2: 0.99, 4: 0.97 if radius == 3 else 0.9, 8: 0.85, 16: 0.5, 32: 0.3}[stride]
 
 
 def test_refine_edges_and_invalid_candidates(step1_oracle):

@@ -433,7 +433,8 @@ REFINE_TOL = 5e-6  # FP32 direct sum over the tokens plus at most 2 radius one-t
 
 @pytest.mark.parametrize("enc,precision,stride,radius", [
     ("s2", "fp16", 4, 3), ("s3", "fp32", 2, 1), ("s8c16", "fp8", 8, 7),
-    ("s8c256", "fp16", 4, 3), ("s8c256", "fp8", 8, 7), ("s4m4", "fp16", 2, 1)])
+    ("s8c256", "fp16", 4, 3), ("s8c256", "fp8", 8, 7), ("s4m4", "fp16", 2, 1),
+    ("s8c256", "fp8", 16, 15), ("s8c16", "fp16", 16, 15)])
 def test_token_coarse_index_then_refine(enc, precision, stride, radius, plain_data, oracle_F):
     """A coarse token index (stride sigma), the product over its windows, then
     rm_refine over the step-1 windows near each candidate: the refined lists
@@ -457,8 +458,9 @@ def test_token_coarse_index_then_refine(enc, precision, stride, radius, plain_da
     rec = mapping.recall_at_k(tidx, o_idx, o_F, np.take_along_axis(F1, tidx, 1))
     print(f"{enc} {precision} stride {stride} radius {radius}: lists identical to the oracle's "
           f"refinement {same:.3f}; recall@{REFINE_K} vs all step-1 windows {rec:.4f}")
-    # measured 1.0 for every case here (lists identical 0.99-1.0, the rest tied)
-    assert rec >= 0.99 and same >= 0.95
+    # measured 1.0 for every case up to stride 8 (lists identical 0.99-1.0,
+    # the rest tied); at stride 16 the method's recall may fall
+    assert same >= 0.95 and rec >= (0.99 if stride <= 8 else 0.9)
 
 
 @pytest.mark.parametrize("enc", ["s8c16", "s8c256"])
