@@ -110,6 +110,10 @@ def parse():
                     help="skip the FP8 leg of an FP16 run (default workload)")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batched leg of the default run")
+    ap.add_argument("--no-threshold", action="store_true",
+                    help="skip the threshold-regime leg of the default run")
+    ap.add_argument("--threshold-err", type=float, default=0.02,
+                    help="threshold regime: target mutation rate of the per-window thresholds")
     ap.add_argument("--cpu-reads", type=int, default=None,
                     help="oracle baseline: read heads timed (default: 2,000 for the precision "
                          "workload, 1,000 for scale)")
@@ -232,6 +236,8 @@ def main():
                            "note": "the same step with an FP8 e4m3 index and FP8 read heads "
                                    "(per-row FP32 scales), FP32 accumulation and FP32 rescore"}
         low.append(("fp8_path", "fp8", r8["value"]))
+    if (not args.no_threshold and args.workload == "precision" and not tok and not coarse):
+        out["threshold_regime"] = threshold_leg(w, ref, reads, precision, args.threshold_err)
     if not args.no_fp32 and precision != "fp32" and not coarse and not wide:
         fp = fp32_path(w, ref, reads, k, k_fetch, tok)
         fp["speedup_of_low_precision"] = {name: round(v / fp["value"], 2) for name, _, v in low}
@@ -854,6 +860,53 @@ def accuracy(w, reads, top_idx, top_score, cand_idx, cand_score, k, R, gold_name
     res["reference"] = f"oracle top-{g['idx'].shape[1]} lists stored in tests/golden/" \
                        f"{os.path.basename(gold)}"
     return res
+
+
+def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1):
+    """§3.3 / §3.5: per-window thresholds at a target mutation rate (the
+    rank-th smallest fidelity of `copies` mutated copies of each window), then
+    every location whose FP32 fidelity passes its window's threshold, for every
+    read.  Reports locations per read, the share mapped to exactly one, and the
+    share whose locations miss the read's true window (within 8 windows)."""
+    import torch
+    from paper_2603_22245_amd import mapper
+    index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision=precision,
+                               reanchor=w.reanchor)
+    rb = mapper.upload_reads(index, reads.seq, reads.offsets)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    mapper.window_thresholds(index, err, copies, rank, seed)            # warm-up
+    torch.cuda.synchronize()
+    ev[0].record()
+    thr = mapper.window_thresholds(index, err, copies, rank, seed)
+    ev[1].record()
+    mapper.encode_reads(index, rb)
+    h = mapper.score_threshold(index, rb, thr)                          # sizes the capacity
+    torch.cuda.synchronize()
+    ev[2].record()
+    h = mapper.score_threshold(index, rb, thr, capacity=h.capacity)
+    ev[3].record()
+    torch.cuda.synchronize()
+    thr_ms, regime_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    n = h.n_found.cpu().numpy()
+    lists = h.lists()
+    truth = reads.truth // w.stride
+    hit = np.array([np.any(np.abs(ids.astype(np.int64) - t) <= 8) for (ids, _), t in
+                    zip(lists, truth)])
+    thr_h = thr.cpu().numpy()
+    del index, rb, h, thr
+    torch.cuda.empty_cache()
+    log(f"threshold regime: {thr_ms:.1f} ms thresholds, {regime_ms:.1f} ms regime")
+    return {"target_err": err, "copies": copies, "rank": rank, "precision": precision,
+            "thresholds_ms": round(thr_ms, 3), "regime_ms": round(regime_ms, 3),
+            "reads_per_s": round(reads.n / (regime_ms / 1e3), 1),
+            "threshold_median": round(float(np.median(thr_h)), 4),
+            "locations_per_read": round(float(n.mean()), 3),
+            "max_locations": int(n.max()),
+            "mapped_to_one": round(float(np.mean(n == 1)), 4),
+            "unmapped": round(float(np.mean(n == 0)), 4),
+            "missed_true_location": round(float(np.mean(~hit)), 4),
+            "note": "read heads + MFMA proposal pass + grouping + FP32 recompute of the "
+                    "proposals; thresholds timed separately"}
 
 
 def fp32_path(w, ref, reads, k, k_fetch, tok=None):

@@ -62,10 +62,13 @@ extern "C" {
 /* ---- enums --------------------------------------------------------------- */
 #define RM_FP32 0      /* embeddings stored as float32 */
 #define RM_FP16 1      /* embeddings stored as IEEE binary16, round to nearest even */
-#define RM_FP8_E4M3 2  /* embeddings stored as OCP FP8 e4m3 codes of v / 2^e (RNE;
-                          2^e the smallest power of two with max|v| / 2^e <= 448)
+#define RM_FP8_E4M3 2  /* embeddings stored as OCP FP8 e4m3 codes of v / 2^e (RNE)
                           plus one FP32 scale per window / per read chosen so
-                          that code * scale has unit norm */
+                          that code * scale has unit norm; 2^e = 2^-8 for every
+                          window row of 128 complex components (a unit vector's
+                          reals are at most 1, and e4m3's relative precision is
+                          the same across its normal range), else the smallest
+                          power of two with max|v| / 2^e <= 448 */
 
 #define RM_SCHED_DEFAULT 0    /* f_k = k            (§2.2 eq. mult-factor) */
 #define RM_SCHED_FINETUNED 1  /* f_k = 2(k-1)/(m-1)+1 (§3.3 eq. mult-factor-finetune) */
@@ -117,7 +120,10 @@ typedef struct rm_index {
   int64_t n_windows;   /* W = floor((G - N) / stride) + 1 */
   void* d_emb;         /* [W][256] embeddings (re, im interleaved per component);
                           [W][2048] for 1,024-component token encodings */
-  float* d_scale;      /* [W] FP8 dequantisation scale per window (1.0 for FP32/FP16) */
+  float* d_scale;      /* [W] FP8 dequantisation scale per window (1.0 for FP32/FP16);
+                          d_scale[W] = the largest (256 d_scale[j])^2 over the FP8
+                          windows of 128 components (a bound the product's
+                          threshold test uses), else 0 */
   float* d_norm2;      /* [W] squared norm of each window's vector before normalising */
   double* d_phase64;   /* [N][m] complex omega^(f_k p), FP64 (re, im) */
   float* d_phase32;    /* [N][m] the same rounded to FP32 */

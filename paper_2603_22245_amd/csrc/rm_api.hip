@@ -78,8 +78,8 @@ Layout layout(int64_t W, const rm_params* p) {
   size_t off = 0;
   L.emb = off;
   off = align_up(off + (size_t)W * real_dim(p) * rm::elem_bytes(p->precision));
-  L.scale = off;
-  off = align_up(off + (size_t)W * sizeof(float));
+  L.scale = off;  // [W] scales and, at [W], the FP8 windows' scale bound
+  off = align_up(off + (size_t)(W + 1) * sizeof(float));
   L.norm2 = off;
   off = align_up(off + (size_t)W * sizeof(float));
   L.phase64 = off;
@@ -210,6 +210,8 @@ static int encode_reference_impl(const uint8_t* d_ref, int64_t ref_len, const rm
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   int st = hip_status(rm::launch_tables(*p, idx.d_phase64, idx.d_phase32, idx.d_step32, s));
+  if (st == RM_OK)  // the encoders raise d_scale[W] to their windows' largest FP8 scale bound
+    st = hip_status(rm::launch_zero_word(reinterpret_cast<uint32_t*>(idx.d_scale + W), s));
   if (st != RM_OK) return st;
   if (idx.d_token_class != nullptr) {
     const bool wide = wide_encoding(p);

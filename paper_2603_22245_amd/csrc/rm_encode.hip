@@ -26,11 +26,15 @@ struct Row4 {
 };
 
 // Write one normalised row (4 reals per lane) in the requested precision.
-// Returns the FP8 scale used (1 for FP32/FP16).  With HAVE_MAX (FP8 only) the
-// caller passes the row's largest |real| in `maxabs`.
-template <int PREC, bool HAVE_MAX = false>
-__device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Row4 x,
-                                           float maxabs = 0.f) {
+// Returns the FP8 scale used (1 for FP32/FP16).  FP8 codes are RNE(v / 2^e):
+// a read row (WINDOW false) takes the smallest power of two 2^e with
+// max |v| / 2^e <= 448; a window row takes 2^e = 2^-8 for every window (a
+// unit vector's reals are at most 1, so 256 |v| <= 256 stays below 448, and
+// e4m3's relative precision is the same everywhere in its normal range, so
+// nothing is lost for the reals that matter).  The common exponent bounds
+// every window's scale, which the product's threshold test relies on.
+template <int PREC, bool WINDOW = false>
+__device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Row4 x) {
   if constexpr (PREC == RM_FP32) {
     float4* dst = reinterpret_cast<float4*>(static_cast<float*>(base) + row * kReal) + lane;
     *dst = make_float4(x.v[0], x.v[1], x.v[2], x.v[3]);
@@ -46,13 +50,13 @@ __device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Ro
     *dst = make_uint2(lo, hi);
     return 1.f;
   } else {
-    float m = maxabs;
-    if constexpr (!HAVE_MAX) {
-      m = fmaxf(fmaxf(fabsf(x.v[0]), fabsf(x.v[1])), fmaxf(fabsf(x.v[2]), fabsf(x.v[3])));
+    float s = kFp8WindowScale, inv = 1.f / kFp8WindowScale;
+    if constexpr (!WINDOW) {
+      float m = fmaxf(fmaxf(fabsf(x.v[0]), fabsf(x.v[1])), fmaxf(fabsf(x.v[2]), fabsf(x.v[3])));
       m = wave_max_nonneg(m);
+      s = fp8_pow2_scale(m);
+      inv = pow2_reciprocal(s);  // exact: s is a power of two
     }
-    float s = fp8_pow2_scale(m);
-    float inv = pow2_reciprocal(s);  // exact: s is a power of two
     uint32_t w = pack_fp8x2(x.v[0] * inv, x.v[1] * inv) |
                  (pack_fp8x2(x.v[2] * inv, x.v[3] * inv) << 16);
     uint32_t* dst = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(base) + row * kReal) + lane;
@@ -98,20 +102,36 @@ __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int 
 }
 
 // A window's squared norm and scale wait in lane registers (lane j - jb
-// holds window j) and go out with one store per 64 windows.
+// holds window j) and go out with one store per 64 windows.  FP8: each lane
+// keeps the largest (s_j / 2^-8)^2 of the windows it held, and at the end of
+// the wavefront's segment `bound` (the index's d_scale[W]) receives their
+// maximum by one atomic maximum (positive floats order as their bit patterns).
 struct SideBuf {
   int64_t jb;  // first window held
   int n;       // windows held (uniform)
   float n2, sc;
+  float* bound;  // FP8: d_scale[W]; otherwise null
+  float rmax;    // FP8: this lane's largest (s_j / 2^-8)^2 so far
 };
 
 __device__ __forceinline__ void side_flush(SideBuf& b, int lane, float* norm2, float* scale) {
   if (lane < b.n) {
     norm2[b.jb + lane] = b.n2;
     scale[b.jb + lane] = b.sc;
+    const float r = b.sc * (1.f / kFp8WindowScale);
+    b.rmax = fmaxf(b.rmax, r * r);
   }
   b.jb += b.n;
   b.n = 0;
+}
+
+// The segment's last flush, then its share of the index-wide FP8 bound.
+__device__ __forceinline__ void side_finish(SideBuf& b, int lane, float* norm2, float* scale) {
+  side_flush(b, lane, norm2, scale);
+  if (b.bound != nullptr) {
+    const float m = wave_max_nonneg(b.rmax);
+    if (lane == 0) atomicMax(reinterpret_cast<unsigned int*>(b.bound), __float_as_uint(m));
+  }
 }
 
 template <int PREC>
@@ -119,17 +139,10 @@ __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c
                                             void* emb, SideBuf& side, float* scale,
                                             float* norm2) {
   float n2 = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
-  // FP8: the largest |real| of the unnormalised row, reduced alongside n2;
-  // scaling by inv > 0 afterwards gives exactly the normalised row's maximum
-  // (the same product of the same element), without a third dependent
-  // reduction
-  float mraw = 0.f;
-  if constexpr (PREC == RM_FP8_E4M3)
-    mraw = wave_max_nonneg(fmaxf(fmaxf(fabsf(c0.x), fabsf(c0.y)), fmaxf(fabsf(c1.x), fabsf(c1.y))));
   bool deg = n2 < kDegenerateRel * (float)N;
   float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
   Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
-  float s = store_row<PREC, true>(emb, j, lane, x, mraw * inv);
+  float s = store_row<PREC, true>(emb, j, lane, x);
   if (lane == side.n) {
     side.n2 = n2;
     side.sc = s;
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   direct_sum(ref + j0 * stride, N, phase64, lane, a0, a1);
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
-  SideBuf side{j0, 0, 0.f, 0.f};
+  SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
   emit_window<PREC>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
   const float4 st = step32[k];
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
     out_l = out_next;
     in_l = in_next;
   }
-  side_flush(side, lane, norm2, scale);
+  side_finish(side, lane, norm2, scale);
 }
 
 // Normalise a read head (this lane's two components, FP32 sums; a squared
@@ -298,7 +311,7 @@ __global__ __launch_bounds__(256) void encode_reference_learned_kernel(
   direct_sum_learned(ref + s0, N, delta + s0 * 32, phase64, lane, a0, a1);
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
-  SideBuf side{j0, 0, 0.f, 0.f};
+  SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
   emit_window<PREC>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
   const float4 st = step32[k];
@@ -342,7 +355,7 @@ __global__ __launch_bounds__(256) void encode_reference_learned_kernel(
     }
     __builtin_amdgcn_wave_barrier();  // the stage is rewritten by the next chunk
   }
-  side_flush(side, lane, norm2, scale);
+  side_finish(side, lane, norm2, scale);
 }
 
 // The same sum in FP32 with the FP32 table (read heads): each term is the
@@ -422,7 +435,7 @@ __global__ __launch_bounds__(256) void encode_reference_tokens_kernel(
   direct_sum_tokens(ref + j0 * stride, T, s, table, phase64, m, k, c0, lane, a0, a1);
   float2 v0 = make_float2((float)a0.x, (float)a0.y);
   float2 v1 = make_float2((float)a1.x, (float)a1.y);
-  SideBuf side{j0, 0, 0.f, 0.f};
+  SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
   emit_window<PREC>(j0, lane, N, v0, v1, emb, side, scale, norm2);
 
   const float4 st = step32[k];
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(256) void encode_reference_tokens_kernel(
     out_c = out_next;
     in_c = in_next;
   }
-  side_flush(side, lane, norm2, scale);
+  side_finish(side, lane, norm2, scale);
 }
 
 // The read-head encoder with tokens: FP32 direct sum over the head's tokens.

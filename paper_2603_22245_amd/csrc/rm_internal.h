@@ -14,6 +14,14 @@ constexpr int kComplex = kLetters * kM;    // 128 complex components
 constexpr int kReal = 2 * kComplex;        // 256 reals per embedding row
 constexpr float kDegenerateRel = 1e-4f;    // squared norm < this * N -> zero vector
 constexpr float kFp8Max = 448.0f;          // largest finite OCP e4m3 value
+// FP8 window rows of 128 complex components are codes of 256 v (a common
+// power of two).  Their scale s_j = 1 / |codes| then satisfies
+// (256 s_j)^2 <= kFp8WindowBound: e4m3 rounds a normal value to within 2^-4
+// relative and a subnormal one to within 2^-10, so over 256 reals of a unit
+// vector |codes - 256 v| <= 2^-4 256 + 16 2^-10 = 16.015625 and
+// |codes| >= 239.984375; (256 / 239.984375)^2 = 1.13792...
+constexpr float kFp8WindowScale = 1.0f / 256.0f;
+constexpr float kFp8WindowBound = 1.138f;
 
 inline int elem_bytes(int precision) {
   return precision == RM_FP32 ? 4 : precision == RM_FP16 ? 2 : 1;
@@ -219,6 +227,7 @@ __device__ __forceinline__ void direct_sum32(const uint8_t* __restrict__ str, in
 
 hipError_t launch_tables(const rm_params& p, double* phase64, float* phase32, float* step32,
                          hipStream_t s);
+hipError_t launch_zero_word(uint32_t* p, hipStream_t s);
 
 hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_params& p,
                                    const double* phase64, const float* step32, void* emb,

@@ -285,6 +285,15 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
       for (int u = 0; u < K::AU4; ++u) a[f][u] = make_uint4(0, 0, 0, 0);
     }
   }
+  // FP8: the largest s_j^2 of the index's windows: the encoder's record at
+  // win_scale[W] ((256 s_j)^2, typically within a few percent of 1), else the
+  // proven bound kFp8WindowBound
+  float wbound = 1.f;
+  if constexpr (kFp8) {
+    const float rec = win_scale[W];
+    wbound = (rec > 0.f && rec <= kFp8WindowBound ? rec : kFp8WindowBound) *
+             (kFp8WindowScale * kFp8WindowScale);
+  }
   // FP8: s_r^2 per read of the block, in LDS (1 otherwise)
   if constexpr (kFp8) {
     if (lane < NF * 16) {
@@ -358,8 +367,12 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         float gt = gk ? __uint_as_float(gk - 1u) : -1.f;
         float t = fmaxf(thr[rb], gt);
         if constexpr (kFp8) {
-          float r2 = rsq[rb];
-          t = r2 > 0.f ? t / r2 : 0.f;  // F-threshold in units of the product
+          // F = (re^2 + im^2) s_r^2 s_j^2 with s_j^2 <= wbound for every
+          // window of the index: in the product's units the threshold is
+          // divided by s_r^2 and that bound, so no window above it is missed
+          // and the register test needs no per-window factor
+          float r2 = rsq[rb] * wbound;
+          t = r2 > 0.f ? t / r2 : 0.f;
         }
         th[f][q] = r < R ? t * kLoose : 3.0e38f;
       }
@@ -470,22 +483,17 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     if ((t & 255) == 255) refresh_thresholds();  // pick up other chunks' progress
     const int64_t tbase = wbeg + (int64_t)t * K::TW;
     bool colok[NB];
-    float isj2[NB];
     float ex = -1.f;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       colok[nb] = tbase + nb * kBlkW + col < wend;
-      isj2[nb] = 1.f;
-      if constexpr (kFp8) isj2[nb] = sj2[nb] > 0.f ? 1.f / sj2[nb] : 0.f;
       float exb = -1.f;
 #pragma unroll
       for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
-          float tq = th[f][q];
-          if constexpr (kFp8) tq = tq * isj2[nb];
-          exb = fmaxf(exb, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)));
+          exb = fmaxf(exb, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])));
         }
       ex = colok[nb] ? fmaxf(ex, exb) : ex;
     }
@@ -499,10 +507,8 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
-            float tq = th[f][q];
-            if constexpr (kFp8) tq = tq * isj2[nb];
             pend |= (uint64_t)(colok[nb] &&
-                               __builtin_fmaf(re, re, __builtin_fmaf(im, im, -tq)) > 0.f)
+                               __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])) > 0.f)
                     << ((nb * NF + f) * 8 + q);
           }
       // append every hit, merging reads whose buffer is full, until nothing

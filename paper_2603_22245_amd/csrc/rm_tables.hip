@@ -50,6 +50,15 @@ __global__ void tables_kernel(int N, int m, int schedule, int s, double2* __rest
   }
 }
 
+__global__ void zero_word_kernel(uint32_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+}
+
+hipError_t launch_zero_word(uint32_t* p, hipStream_t s) {
+  hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(64), 0, s, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_tables(const rm_params& p, double* phase64, float* phase32, float* step32,
                          hipStream_t s) {
   int64_t total = (int64_t)p.window_len * p.n_freq;
