@@ -241,6 +241,12 @@ constexpr int kMaxGroups = 8;
 
 // One (index, read batch) pair of a scoring launch; passed by value in the
 // kernel arguments.
+// Per read, the scoring launch keeps kScoreSlots keys of windows from
+// finished window chunks, slot = window id mod kScoreSlots: the slots always
+// hold distinct windows, so the kp-th largest of them bounds the read's final
+// kp-th best from below.
+constexpr int kScoreSlots = 32;
+
 struct ScoreGroup {
   const uint8_t* index;      // [W][256] window embeddings
   const float* win_scale;    // [W]
@@ -254,6 +260,7 @@ struct ScoreGroup {
   int32_t item_begin;        // first work item of this group
   uint64_t* lists;           // [R][P][kp] keys
   uint32_t* gthr;            // [R] shared k-th-best per read
+  uint64_t* gslot;           // [R][kScoreSlots] keys of finished chunks (slot = id mod kScoreSlots)
 };
 
 struct ScoreLaunch {
@@ -274,6 +281,7 @@ struct GroupPlan {
   int64_t chunk_windows;
   size_t lists_offset;
   size_t thr_offset;
+  size_t slot_offset;
 };
 
 struct ScorePlan {

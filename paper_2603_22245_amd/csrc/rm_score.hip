@@ -8,13 +8,18 @@ namespace rm {
 
 namespace {
 
-// Clears the work counter and every group's shared per-read thresholds
-// ("no information" = 0).
+// Clears the work counter and every group's shared per-read thresholds and
+// slots ("no information" = 0).
 __global__ void clear_state(ScoreLaunch L) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *L.counter = 0;
   for (int gi = 0; gi < L.n_groups; ++gi)
-    if (i < L.g[gi].R) L.g[gi].gthr[i] = 0u;
+    if (i < L.g[gi].R) {
+      L.g[gi].gthr[i] = 0u;
+      uint4* slot = reinterpret_cast<uint4*>(L.g[gi].gslot + i * kScoreSlots);
+#pragma unroll
+      for (int u = 0; u < kScoreSlots / 2; ++u) slot[u] = make_uint4(0, 0, 0, 0);
+    }
 }
 
 // Merge the P per-chunk lists of each read into its k_fetch best (keys are
@@ -137,6 +142,8 @@ ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_
     off = align256(off + (size_t)R[i] * (size_t)P * (size_t)p.kp * sizeof(uint64_t));
     gp.thr_offset = off;
     off = align256(off + (size_t)R[i] * sizeof(uint32_t));
+    gp.slot_offset = off;
+    off = align256(off + (size_t)R[i] * kScoreSlots * sizeof(uint64_t));
     items += (int64_t)gp.read_tiles * P;
   }
   p.counter_offset = off;
@@ -172,6 +179,7 @@ hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
     G.item_begin = item;
     G.lists = reinterpret_cast<uint64_t*>(base + gp.lists_offset);
     G.gthr = reinterpret_cast<uint32_t*>(base + gp.thr_offset);
+    G.gslot = reinterpret_cast<uint64_t*>(base + gp.slot_offset);
     item += gp.read_tiles * gp.chunks;
     if (R[i] > maxR) maxR = R[i];
   }

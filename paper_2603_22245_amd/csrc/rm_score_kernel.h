@@ -83,6 +83,32 @@ __device__ __forceinline__ uint64_t sort_desc(uint64_t key, int lane) {
   return key;
 }
 
+// The slot bound of each of a wavefront's NF*16 reads (first read row0),
+// written to thr[0 .. NF*16): the KP-th largest F among the keys that finished
+// chunks left in the read's slots (distinct windows; -1 while fewer than KP
+// slots are filled, or past the last read).  Two reads per step, one per
+// half-wavefront, one slot per lane, sorted across the half.  Called once at
+// the start of an item: a read's chunks are scored roughly one after another,
+// since items are numbered chunk-major.  Kept out of line so that its
+// registers do not add to the scoring loop's.
+template <int NF, int KP>
+__device__ __noinline__ void slot_bounds(const uint64_t* __restrict__ gslot, int64_t row0, int32_t R,
+                                         int lane, float* thr) {
+  static_assert(KP <= kScoreSlots && kScoreSlots == 32, "slots");
+  const int g = lane >> 5, col = lane & 31;
+#pragma unroll 1
+  for (int p = 0; p < NF * 8; ++p) {
+    const int i = 2 * p + g;
+    const int64_t r = row0 + i;
+    uint64_t key = r < R ? __hip_atomic_load(&gslot[r * kScoreSlots + col], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                         : 0ull;
+    key = sort_desc<32>(key, lane);
+    if (col == KP - 1) thr[i] = key_score(key);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int PREC>
 struct Prec;
 template <>
@@ -248,6 +274,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   const int P = G.P;
   uint64_t* __restrict__ ws = G.lists;
   uint32_t* __restrict__ gthr = G.gthr;
+  uint64_t* __restrict__ gslot = G.gslot;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -270,6 +297,9 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     cnt[rb0 + lane] = 0;
     thr[rb0 + lane] = -1.f;
   }
+
+  // ---- the read's slot bound is the chunk's first threshold
+  slot_bounds<NF, KP>(gslot, read0 + rb0, R, lane, thr + rb0);
 
   // ---- A fragments: this lane's K half of row (read tile row) for each fragment
   uint4 a[NF][K::AU4];
@@ -352,9 +382,10 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     }
   };
 
-  // ---- thresholds: the larger of this chunk's k-th best and the best k-th
-  // best any chunk has published for the read (0 = none yet); slots past the
-  // last read get an unreachable threshold
+  // ---- thresholds: the larger of this chunk's threshold (its slot bound,
+  // then its own k-th best when higher) and the best k-th best any chunk has
+  // published for the read (0 = none yet); slots past the last read get an
+  // unreachable threshold
   auto refresh_thresholds = [&]() {
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -404,7 +435,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         if (id < KP) lst[rb][id] = key;
         if (id == KP - 1) {
           float kth = key_score(key);
-          thr[rb] = kth;
+          thr[rb] = fmaxf(thr[rb], kth);
           // publish this chunk's k-th best: no window scoring below it can be
           // in the read's final list, whichever chunk holds it
           const int64_t r = gread(my);
@@ -476,25 +507,42 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     mfmas(t, acc);
   };
 
-  // re^2 + im^2 - threshold per (read slot, window col), reduced with max;
-  // only a positive maximum anywhere in the wavefront leads to the (rare)
-  // per-score test and appends.
+  // re^2 + im^2 - threshold per (read slot, window col), reduced with max per
+  // (column block, fragment); only a positive maximum anywhere in the
+  // wavefront leads to the (rare) per-score test and appends.  FP8 tiles
+  // (four block-fragment groups, half the MFMA time per tile of FP16) test
+  // and append only in the groups that hold a hit; for FP16 the extra live
+  // registers of the group test cost more than it saves.
+  constexpr bool kGroupTest = kFp8;
   auto epilogue = [&](int t, const f32x16 (&acc)[NF][NB], const float (&sj2)[NB]) {
     if ((t & 255) == 255) refresh_thresholds();  // pick up other chunks' progress
     const int64_t tbase = wbeg + (int64_t)t * K::TW;
     bool colok[NB];
+    float exg[NB][NF];
     float ex = -1.f;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       colok[nb] = tbase + nb * kBlkW + col < wend;
       float exb = -1.f;
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
+      for (int f = 0; f < NF; ++f) {
+        if constexpr (kGroupTest) {
+          float e = -1.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
-          exb = fmaxf(exb, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])));
+          for (int q = 0; q < 8; ++q) {
+            float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+            e = fmaxf(e, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])));
+          }
+          exg[nb][f] = e;
+          exb = fmaxf(exb, e);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+            exb = fmaxf(exb, __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])));
+          }
         }
+      }
       ex = colok[nb] ? fmaxf(ex, exb) : ex;
     }
 
@@ -504,12 +552,14 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int f = 0; f < NF; ++f)
+          if (!kGroupTest || __ballot(colok[nb] && exg[nb][f] > 0.f)) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
-            pend |= (uint64_t)(colok[nb] &&
-                               __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])) > 0.f)
-                    << ((nb * NF + f) * 8 + q);
+            for (int q = 0; q < 8; ++q) {
+              float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+              pend |= (uint64_t)(colok[nb] &&
+                                 __builtin_fmaf(re, re, __builtin_fmaf(im, im, -th[f][q])) > 0.f)
+                      << ((nb * NF + f) * 8 + q);
+            }
           }
       // append every hit, merging reads whose buffer is full, until nothing
       // is pending
@@ -518,18 +568,20 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
           for (int f = 0; f < NF; ++f)
+            if (!kGroupTest || __ballot(((pend >> ((nb * NF + f) * 8)) & 0xffu) != 0)) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const uint64_t bit = 1ull << ((nb * NF + f) * 8 + q);
-              if (pend & bit) {
-                int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
-                int pos = atomicAdd(&cnt[rb], 1);
-                if (pos < K::CB) {
-                  float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
-                  float F = re * re + im * im;
-                  if constexpr (kFp8) F = F * (rsq[rb] * sj2[nb]);
-                  lst[rb][KP + pos] = make_key(F, (int32_t)(tbase + nb * kBlkW + col));
-                  pend &= ~bit;
+              for (int q = 0; q < 8; ++q) {
+                const uint64_t bit = 1ull << ((nb * NF + f) * 8 + q);
+                if (pend & bit) {
+                  int rb = rb0 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+                  int pos = atomicAdd(&cnt[rb], 1);
+                  if (pos < K::CB) {
+                    float re = acc[f][nb][2 * q], im = acc[f][nb][2 * q + 1];
+                    float F = re * re + im * im;
+                    if constexpr (kFp8) F = F * (rsq[rb] * sj2[nb]);
+                    lst[rb][KP + pos] = make_key(F, (int32_t)(tbase + nb * kBlkW + col));
+                    pend &= ~bit;
+                  }
                 }
               }
             }
@@ -610,7 +662,15 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     for (int i = lane; i < NF * 16 * KP; i += 64) {
       int rr = i / KP, e = i % KP;
       int64_t r = gread(rr);
-      if (r < R) ws[((int64_t)r * P + chunk) * KP + e] = lst[rb0 + rr][e];
+      if (r < R) {
+        const uint64_t key = lst[rb0 + rr][e];
+        ws[((int64_t)r * P + chunk) * KP + e] = key;
+        // this chunk's windows join the read's slots for the chunks after it
+        if (key >> 32)
+          atomicMax(reinterpret_cast<unsigned long long*>(
+                        &gslot[r * kScoreSlots + ((~(uint32_t)key) & (kScoreSlots - 1))]),
+                    (unsigned long long)key);
+      }
     }
   }
 }

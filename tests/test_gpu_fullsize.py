@@ -92,12 +92,17 @@ def _stored_lists(name):
     return np.load(path)
 
 
-def _check_against_stored(g, top_idx, top_score, k, rows=None):
+def _check_against_stored(g, top_idx, top_score, k, rows=None, product_tol=None):
     """Recall@k, list agreement up to ties and rescore error against stored
     oracle lists (longer than k): a window outside a stored list is a miss.
     Sample read g["reads"][i] is row rows[i] of the outputs (default: its read
     index).  Every list must equal the oracle's up to ties (the product
-    over-fetches, so no candidate the FP32 rescore needs is lost)."""
+    over-fetches, so no candidate the FP32 rescore needs is lost) -- except,
+    when product_tol is given, a read whose oracle scores from rank k to the
+    last stored rank all lie within 2 * product_tol * F_best of each other:
+    there the product's own error (|dF| <= product_tol * max(F, F_best)) can
+    reorder the k-th best and the last fetched candidate, and a true top-k
+    window may not be fetched; recall must then still be >= 0.999."""
     recs, exact, errs, bad = [], [], [], []
     rows = g["reads"] if rows is None else rows
     for read, r, oi, of in zip(g["reads"], rows, g["idx"], g["F"]):
@@ -119,6 +124,14 @@ def _check_against_stored(g, top_idx, top_score, k, rows=None):
     print(f"{len(recs)} stored reads: recall@{k} {np.mean(recs):.5f}, exact lists "
           f"{np.mean(exact):.4f}, rescore err {max(errs):.2e}")
     assert np.mean(recs) >= 0.99
+    if product_tol is not None and bad:
+        band = {int(read): float(of[k - 1] - of[-1]) / float(of[0])
+                for read, of in zip(g["reads"], g["F"])}
+        print("differing lists (read: oracle F_k - F_last relative to F_best): " +
+              ", ".join(f"{b}: {band[b]:.4f}" for b in bad))
+        assert all(band[b] <= 2 * product_tol for b in bad), bad
+        assert np.mean(recs) >= 0.999
+        bad = []
     assert not bad, f"lists differing from the stored oracle lists: reads {bad}"
     assert max(errs) <= 1e-4
     return float(np.mean(recs))
@@ -276,7 +289,9 @@ def test_precision_workload_coarse_refine_full_size(enc, precision, stride, radi
         exact += int(np.array_equal(got, want_i))
     print(f"{enc or 'letters'} {precision} stride {stride} radius {radius}: lists identical to "
           f"the oracle's refinement {exact / pick.size:.3f}, max |dF| {err:.2e}")
-    assert err < 5e-6 and exact / pick.size >= 0.95
+    # every list equals the oracle's up to ties (asserted read by read above);
+    # bit-identical including the order of tied windows measured 1.0
+    assert err < 5e-6 and exact / pick.size >= 0.99
     if enc is not None:
         _check_against_stored(g, tidx, tsc, k)
 
@@ -326,7 +341,11 @@ def test_scale_workload_full_size_sampled():
     # ordered by F descending, then window id ascending
     assert np.all((np.diff(top_f, axis=1) < 0) |
                   ((np.diff(top_f, axis=1) == 0) & (np.diff(top_i, axis=1) > 0)))
-    _check_against_stored(g, top_i, top_f, k, rows=rows_of_sample)
+    # FP8 over 256 M windows: the 16th to 32nd best scores of a read can lie
+    # closer together than the product's error (read 537687 of the stored
+    # sample: 0.1633 down to 0.1589, F_best 0.4999), so such a list may miss a
+    # window
+    _check_against_stored(g, top_i, top_f, k, rows=rows_of_sample, product_tol=1e-2)
     truth = reads.truth // w.stride
     hit = np.mean(np.abs(top_i[:, 0] - truth) <= 8)
     print(f"top-1 within 8 of the true start: {hit:.4f}")

@@ -458,9 +458,12 @@ def test_token_coarse_index_then_refine(enc, precision, stride, radius, plain_da
     rec = mapping.recall_at_k(tidx, o_idx, o_F, np.take_along_axis(F1, tidx, 1))
     print(f"{enc} {precision} stride {stride} radius {radius}: lists identical to the oracle's "
           f"refinement {same:.3f}; recall@{REFINE_K} vs all step-1 windows {rec:.4f}")
-    # measured 1.0 for every case up to stride 8 (lists identical 0.99-1.0,
-    # the rest tied); at stride 16 the method's recall may fall
-    assert same >= 0.95 and rec >= (0.99 if stride <= 8 else 0.9)
+    # every list equals the oracle's refinement up to ties (asserted read by
+    # read above); bit-identical including the order of tied windows: 1.0 in
+    # every case but s8c256 FP8 at stride 8 (0.995, one read of 200 with two
+    # windows within the tie tolerance).  Recall against every step-1 window
+    # measured 1.0 in every case; at stride 16 the method itself may lose some.
+    assert same >= 0.99 and rec >= (0.99 if stride <= 8 else 0.9)
 
 
 @pytest.mark.parametrize("enc", ["s8c16", "s8c256"])
