@@ -862,6 +862,16 @@ def accuracy(w, reads, top_idx, top_score, cand_idx, cand_score, k, R, gold_name
     return res
 
 
+def location_clusters(ids, span):
+    """Distinct locations among a read's window ids: windows whose ids differ
+    by at most `span` (windows that overlap the same stretch of reference)
+    form one location.  Returns the number of such clusters."""
+    ids = np.sort(np.asarray(ids, dtype=np.int64))
+    if ids.size == 0:
+        return 0
+    return int(1 + np.count_nonzero(np.diff(ids) > span))
+
+
 def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1):
     """§3.3 / §3.5: per-window thresholds at a target mutation rate (the
     rank-th smallest fidelity of `copies` mutated copies of each window), then
@@ -892,6 +902,11 @@ def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1):
     truth = reads.truth // w.stride
     hit = np.array([np.any(np.abs(ids.astype(np.int64) - t) <= 8) for (ids, _), t in
                     zip(lists, truth)])
+    # at stride 1 a read passes the thresholds of many overlapping windows
+    # around one place; count places: windows overlapping one another (ids
+    # within a window length) are one location
+    span = max(1, w.window_len // w.stride)
+    loc = np.array([location_clusters(ids, span) for ids, _ in lists])
     thr_h = thr.cpu().numpy()
     del index, rb, h, thr
     torch.cuda.empty_cache()
@@ -900,9 +915,11 @@ def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1):
             "thresholds_ms": round(thr_ms, 3), "regime_ms": round(regime_ms, 3),
             "reads_per_s": round(reads.n / (regime_ms / 1e3), 1),
             "threshold_median": round(float(np.median(thr_h)), 4),
-            "locations_per_read": round(float(n.mean()), 3),
-            "max_locations": int(n.max()),
-            "mapped_to_one": round(float(np.mean(n == 1)), 4),
+            "windows_per_read": round(float(n.mean()), 3),
+            "max_windows": int(n.max()),
+            "locations_per_read": round(float(loc.mean()), 3),
+            "max_locations": int(loc.max()),
+            "mapped_to_one_location": round(float(np.mean(loc == 1)), 4),
             "unmapped": round(float(np.mean(n == 0)), 4),
             "missed_true_location": round(float(np.mean(~hit)), 4),
             "note": "read heads + MFMA proposal pass + grouping + FP32 recompute of the "

@@ -81,3 +81,12 @@ def test_traffic_is_read_only_for_the_current_kernel_sources(tmp_path, monkeypat
     assert bench.measured_traffic("precision", "fp8") is None    # another precision's
     (tmp_path / bench.SCORE_SOURCES[0]).write_text("kernel v2")
     assert bench.measured_traffic("precision", "fp16") is None   # kernel changed
+
+
+def test_location_clusters_join_overlapping_windows_only():
+    assert bench.location_clusters([], 150) == 0
+    assert bench.location_clusters([7], 150) == 1
+    # 100..250 overlap one another (ids within 150); 401 is a new place
+    assert bench.location_clusters([250, 100, 180, 401], 150) == 2
+    assert bench.location_clusters([0, 150, 300], 150) == 1      # a chain of overlaps
+    assert bench.location_clusters([0, 151], 150) == 2
