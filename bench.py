@@ -106,6 +106,8 @@ def parse():
                          "s8c256 | s4f128 (default: the letter encoding)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
+    ap.add_argument("--no-fp8-letter-sum", action="store_true",
+                    help="skip the FP8 leg in the letter-sum form")
     ap.add_argument("--no-fp8", action="store_true",
                     help="skip the FP8 leg of an FP16 run (default workload)")
     ap.add_argument("--no-batching", action="store_true",
@@ -214,7 +216,8 @@ def main():
         "config": {"workload": describe(w, precision, k, k_fetch, R, stride, radius, args.tokens),
                    "reads": R, "windows": W, "window_len": w.window_len,
                    "n_freq": tok.get("n_freq", w.n_freq), "tokens": args.tokens,
-                   "stride": stride, "k": k, "k_fetch": k_fetch, "precision": precision},
+                   "stride": stride, "k": k, "k_fetch": k_fetch, "precision": precision,
+                   "row_reals": run["row_reals"]},
         "window_scores_per_s": run["window_scores_per_s"],
         # the same step on an index built beforehand (reads -> product -> rescore)
         "reads_per_s_prebuilt_index": round(R / ((parts[1] + parts[2] + parts[3]) / 1e3), 1),
@@ -232,10 +235,22 @@ def main():
         out["fp8_path"] = {"value": round(r8["value"], 1), "unit": "reads/s",
                            "ms_per_step": round(r8["ms_per_step"], 3),
                            "breakdown_ms": r8["breakdown_ms"], "accuracy": r8["accuracy"],
-                           "roofline": r8["roofline"],
+                           "roofline": r8["roofline"], "row_reals": r8["row_reals"],
                            "note": "the same step with an FP8 e4m3 index and FP8 read heads "
                                    "(per-row FP32 scales), FP32 accumulation and FP32 rescore"}
         low.append(("fp8_path", "fp8", r8["value"]))
+        if not args.no_fp8_letter_sum:
+            r8s = run_map(args, w, ref, reads, "fp8", k, k_fetch, stride, radius, tok,
+                          max(1, args.steps), 1, reduced=True)
+            out["fp8_letter_sum_path"] = {
+                "value": round(r8s["value"], 1), "unit": "reads/s",
+                "ms_per_step": round(r8s["ms_per_step"], 3), "breakdown_ms": r8s["breakdown_ms"],
+                "accuracy": r8s["accuracy"], "roofline": r8s["roofline"],
+                "row_reals": r8s["row_reals"],
+                "note": "the FP8 step with the index and read heads in the letter-sum form "
+                        "(192 reals per row); not the library's FP8 default, since e4m3's "
+                        "error per score grows by about sqrt(4/3) in it"}
+            low.append(("fp8_letter_sum_path", "fp8", r8s["value"]))
     if (not args.no_threshold and args.workload == "precision" and not tok and not coarse):
         out["threshold_regime"] = threshold_leg(w, ref, reads, precision, args.threshold_err)
     if not args.no_fp32 and precision != "fp32" and not coarse and not wide:
@@ -258,19 +273,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_map(args, w, ref, reads, precision, k, k_fetch, stride, radius, tok, steps, warmup):
-    """Build the index, then time `steps` whole steps (index build, read heads,
-    product + top-k, FP32 rescore or refinement) with HIP events on torch's
-    current stream; accuracy against the stored oracle lists."""
+def run_map(args, w, ref, reads, precision, k, k_fetch, stride, radius, tok, steps, warmup,
+            reduced=None):
+    """Build the index (reduced: the letter-sum form; None = the library's
+    choice), then time `steps` whole steps (index build, read heads, product +
+    top-k, FP32 rescore or refinement) with HIP events on torch's current
+    stream; accuracy against the stored oracle lists.  The product's flops are
+    those it executes: 4 per real of a row (K = 256, 192 in the letter-sum form,
+    2,048 for 1,024-component tokens)."""
     import torch
     from paper_2603_22245_amd import mapper, _lib as L
     R = reads.n
     coarse = stride > w.stride
-    real_dim = 2 * tok["n_class"] * tok["n_freq"] if tok else 256
-    wide = real_dim != 256
-    flops_per_score = 4 * real_dim
+    wide = bool(tok) and 2 * tok["n_class"] * tok["n_freq"] != 256
     index = mapper.build_index(ref, window_len=w.window_len, stride=stride, precision=precision,
-                               reanchor=w.reanchor, **tok)
+                               reanchor=w.reanchor, reduced=reduced, **tok)
+    real_dim = index.real_dim
+    flops_per_score = 4 * real_dim
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
     bufs = mapper.map_buffers(index, R, k, k_fetch)
     refine_ws = None
@@ -343,6 +362,7 @@ def run_map(args, w, ref, reads, precision, k, k_fetch, stride, radius, tok, ste
                            else "score_topk_kernel (+merge_kernel)"),
                 "algorithmic": f"{flops_per_score} flops per (read, window) score x {R} x {W}"}
     return {"W": W, "parts": parts, "ms_per_step": ms_per_step, "value": R / (ms_per_step / 1e3),
+            "row_reals": real_dim,
             "window_scores_per_s": float(f"{R * W / score_s:.4g}"),
             "breakdown_ms": {"encode_reference": round(parts[0], 3),
                              "encode_reads": round(parts[1], 3),
@@ -421,8 +441,11 @@ def bench_batching(args, fp32: bool = None, low=None):
                                                  args.warmup)
     value = R / (ms_per_step / 1e3)
     scores = sum(b.reads.n * b.index.n_windows for b in bm.buckets)
+    # flops the product executes: 4 per real of the buckets' rows
+    flops = sum(b.reads.n * b.index.n_windows * 4 * b.index.real_dim for b in bm.buckets)
+    row_reals = sorted({b.index.real_dim for b in bm.buckets})
     peak = PEAK_TFLOPS[precision]
-    achieved = scores * FLOPS_PER_SCORE / (parts[2] / 1e3) / 1e12
+    achieved = flops / (parts[2] / 1e3) / 1e12
     ids, sc = bm.results()
     acc = batching_accuracy(ref, reads, bm, ids, sc, k)
     buckets = [{"N": b.length, "stride": b.stride, "reads": int(b.reads.n),
@@ -453,13 +476,15 @@ def bench_batching(args, fp32: bool = None, low=None):
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": "score_topk_kernel (grouped, persistent) + merges",
-                     "algorithmic": f"{FLOPS_PER_SCORE} flops x {scores} (read, window) scores"},
+                     "algorithmic": f"4 flops per real of rows of {row_reals} reals x {scores} "
+                                    f"(read, window) scores"},
     }
     prebuilt = {precision: parts[1] + parts[2] + parts[3]}
     step_ms = {precision: ms_per_step}
     if low is not None and len(low) > 1:
         p2 = low[1]
         bm2, ms2, parts2, best2 = _batched_pass(ref, reads, k, k_fetch, p2, args.steps, 1)
+        flops2 = sum(b.reads.n * b.index.n_windows * 4 * b.index.real_dim for b in bm2.buckets)
         ids2, sc2 = bm2.results()
         acc2 = batching_accuracy(ref, reads, bm2, ids2, sc2, k)
         bm2.close()
@@ -476,10 +501,10 @@ def bench_batching(args, fp32: bool = None, low=None):
                                    "rescore": round(parts2[3], 3)},
             "accuracy": acc2,
             "roofline": {"bound": "mfma",
-                         "achieved": round(scores * FLOPS_PER_SCORE / (parts2[2] / 1e3) / 1e12, 2),
+                         "achieved": round(flops2 / (parts2[2] / 1e3) / 1e12, 2),
                          "peak": PEAK_TFLOPS[p2], "unit": "TFLOP/s",
-                         "frac": round(scores * FLOPS_PER_SCORE / (parts2[2] / 1e3) / 1e12
-                                       / PEAK_TFLOPS[p2], 4), "traffic": None},
+                         "frac": round(flops2 / (parts2[2] / 1e3) / 1e12 / PEAK_TFLOPS[p2], 4),
+                         "traffic": None},
             "note": f"the same graph-replayed step with {p2} indexes and read heads "
                     f"(tuning read_tile={best2.read_tile}, chunk_tiles={best2.chunk_tiles})"}
     if fp32 and precision != "fp32":
@@ -963,7 +988,8 @@ def fp32_path(w, ref, reads, k, k_fetch, tok=None):
             "tflops": round(reads.n * W * FLOPS_PER_SCORE / dt / 1e12, 2),
             "accuracy": {key: acc.get(key) for key in ("recall_at_k", "exact_lists_up_to_ties",
                                                        "sample_reads")},
-            "note": "index build + read encoding + FP32 MFMA product + top-k + FP32 rescore"}
+            "note": "index build + read encoding + FP32 MFMA product over the full rows "
+                    "(K = 256) + top-k + FP32 rescore"}
 
 
 def cpu_baseline(w, ref, reads, W, n_reads, n_windows, tokens_name=None):

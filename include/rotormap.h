@@ -109,6 +109,20 @@ typedef struct rm_params {
   const uint8_t* d_token_map; /* NULL, or DEVICE [4^s] class per s-mer code; read
                                  by rm_encode_reference only (copied into the
                                  index buffer) */
+  /* Letter-sum form (letter encoding, default schedule, FP16 or FP8 only;
+   * 0 otherwise).  With integer factors f_k = k < N (§2.2) the components of
+   * factor k of a window sum over the four letters to sum_p omega^(k p) = 0,
+   * since each location holds one letter: 1 stores every window and read head
+   * by its coordinates on an orthonormal basis of that 3m-dimensional
+   * subspace (per factor, the letter weights (1,1,-1,-1)/2, (1,-1,1,-1)/2,
+   * (1,-1,-1,1)/2 for A,C,G,T), 96 complex components = 192 reals per row
+   * (re, im interleaved per component, factor-major) instead of 256.  Norms
+   * are taken over all 128 components first, and every fidelity is the same
+   * as with the full rows, provided every reference window holds letters only
+   * (codes 0..3); a window holding another code loses the part of its vector
+   * along the all-letters direction, which matters only against read heads
+   * that hold such codes too. */
+  int32_t reduced;
 } rm_params;
 
 /* Descriptor of an index living in a caller-owned device buffer.  Filled by
@@ -119,7 +133,8 @@ typedef struct rm_index {
   int64_t ref_len;     /* G, letters in the reference */
   int64_t n_windows;   /* W = floor((G - N) / stride) + 1 */
   void* d_emb;         /* [W][256] embeddings (re, im interleaved per component);
-                          [W][2048] for 1,024-component token encodings */
+                          [W][192] in the letter-sum form; [W][2048] for
+                          1,024-component token encodings */
   float* d_scale;      /* [W] FP8 dequantisation scale per window (1.0 for FP32/FP16);
                           d_scale[W] = the largest (256 d_scale[j])^2 over the FP8
                           windows of 128 components (a bound the product's
@@ -155,12 +170,14 @@ size_t rm_index_bytes(int64_t ref_len, const rm_params* p);
  * mer_len out of range, N < s), RM_EUNSUPPORTED (letter encoding with n_freq
  * != RM_DIM; token encoding with n_class odd or above 256, n_class * n_freq
  * neither 128 nor 1,024, 1,024 components with n_class not a multiple of 16
- * or an FP32 index, or no map and n_class != 4^s). */
+ * or an FP32 index, or no map and n_class != 4^s; the letter-sum form with
+ * a token encoding, the fine-tuned schedule or an FP32 index). */
 int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
                         void* d_buf, size_t buf_bytes, rm_index* out, void* stream);
 
 /* Bytes of the read-embedding buffer for n_reads reads: [n_reads][2][256]
- * ([n_reads][2][2048] for 1,024-component token encodings) elements of the
+ * ([n_reads][2][192] in the letter-sum form, [n_reads][2][2048] for
+ * 1,024-component token encodings) elements of the
  * index precision (row 2r holds (Re x, Im x) per component and
  * row 2r+1 holds (-Im x, Re x), so that one real product of the two rows with a
  * window row gives Re and Im of <x|c>).  0 if invalid. */

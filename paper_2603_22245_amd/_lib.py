@@ -30,7 +30,7 @@ class rm_params(ctypes.Structure):
                 ("n_freq", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reanchor", ctypes.c_int32),
                 ("mer_len", ctypes.c_int32), ("n_class", ctypes.c_int32),
-                ("d_token_map", ctypes.c_void_p)]
+                ("d_token_map", ctypes.c_void_p), ("reduced", ctypes.c_int32)]
 
 
 class rm_index(ctypes.Structure):
@@ -166,13 +166,15 @@ def _check(status: int, call: str):
 
 
 def make_params(window_len=150, stride=1, n_freq=RM_DIM, schedule="default", precision="fp16",
-                reanchor=0, mer_len=0, n_class=0, token_map=None) -> rm_params:
+                reanchor=0, mer_len=0, n_class=0, token_map=None, reduced=False) -> rm_params:
     """token_map: None or a device uint8 tensor of 4^mer_len classes (its
-    address is stored; it must stay alive until rm_encode_reference returns)."""
+    address is stored; it must stay alive until rm_encode_reference returns).
+    reduced: store the letter-sum form (rm_params.reduced)."""
     return rm_params(window_len, stride, n_freq,
                      SCHEDULES.get(schedule, schedule) if isinstance(schedule, str) else schedule,
                      PRECISIONS.get(precision, precision) if isinstance(precision, str) else precision,
-                     reanchor, mer_len, n_class, None if token_map is None else _ptr(token_map))
+                     reanchor, mer_len, n_class, None if token_map is None else _ptr(token_map),
+                     int(bool(reduced)))
 
 
 def status_str(status: int) -> str:

@@ -35,7 +35,9 @@ bool wide_encoding(const rm_params* p) {
 }
 
 // Reals per stored row (and per read-embedding row).
-size_t real_dim(const rm_params* p) { return wide_encoding(p) ? 2 * rm::kWideComplex : rm::kReal; }
+size_t real_dim(const rm_params* p) {
+  return wide_encoding(p) ? 2 * rm::kWideComplex : p->reduced ? rm::kRealReduced : rm::kReal;
+}
 
 bool params_ok(const rm_params* p, int* why) {
   if (p == nullptr) return (*why = RM_EINVAL), false;
@@ -61,6 +63,12 @@ bool params_ok(const rm_params* p, int* why) {
   if (p->window_len < 1 || p->window_len > RM_MAX_WINDOW) return (*why = RM_ESIZE), false;
   if (p->stride < 1) return (*why = RM_ESIZE), false;
   if (p->reanchor < 0) return (*why = RM_ESIZE), false;
+  if (p->reduced != 0 && p->reduced != 1) return (*why = RM_EINVAL), false;
+  // the letter-sum form: integer factors (f_k = k < N for every window of at
+  // least RM_DIM + 1 letters), letters, FP16 or FP8
+  if (p->reduced && (!letter_encoding(p) || p->schedule != RM_SCHED_DEFAULT ||
+                     p->precision == RM_FP32 || p->window_len <= RM_DIM))
+    return (*why = RM_EUNSUPPORTED), false;
   return true;
 }
 
@@ -179,7 +187,7 @@ int rm_encode_reference_learned(const uint8_t* d_ref, int64_t ref_len, const rm_
                                 rm_index* out, void* stream) {
   if (d_ref_delta == nullptr) return RM_EINVAL;
   if (p != nullptr && p->window_len < 9) return RM_ESIZE;
-  if (p != nullptr && !letter_encoding(p)) return RM_EUNSUPPORTED;
+  if (p != nullptr && (!letter_encoding(p) || p->reduced)) return RM_EUNSUPPORTED;
   return encode_reference_impl(d_ref, ref_len, p, d_ref_delta, d_buf, buf_bytes, out, stream);
 }
 
@@ -273,7 +281,7 @@ int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int
     return RM_EINVAL;
   if (idx->p.precision == RM_FP8_E4M3 && d_read_scale == nullptr) return RM_EINVAL;
   if (n_reads < 1 || idx->p.window_len < 9) return RM_ESIZE;
-  if (!letter_encoding(&idx->p)) return RM_EUNSUPPORTED;
+  if (!letter_encoding(&idx->p) || idx->p.reduced) return RM_EUNSUPPORTED;
   return hip_status(rm::launch_encode_reads_learned(idx->p, idx->d_phase32, d_seq, d_off, n_reads,
                                                     d_read_delta, d_read_emb, d_read_scale,
                                                     static_cast<hipStream_t>(stream)));

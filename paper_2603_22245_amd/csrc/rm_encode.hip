@@ -72,6 +72,95 @@ __device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Ro
   }
 }
 
+// ---- the letter-sum form (rows of kRealReduced reals)
+// With integer factors (f_k = k < N, §2.2) the components of factor k of a
+// window's vector sum over the four letters to sum_p omega^(k p) = 0 (each of
+// the N locations holds one letter): the vector lies in the subspace
+// orthogonal to the all-letters direction of every factor.  Its coordinates on
+// the orthonormal basis of that subspace given by the three non-constant
+// Walsh-Hadamard rows, (1,1,-1,-1)/2, (1,-1,1,-1)/2 and (1,-1,-1,1)/2 over
+// the letters (A,C,G,T), keep its norm and its inner product with any read
+// (the read's all-letters part meets zero), in 3 components per factor
+// instead of 4.  Lane l holds letters 2h, 2h+1 (h = l & 1) of factor l/2,
+// its partner l^1 the other two; the row's reals 3l .. 3l+2 are the lane's:
+// (y1.re, y1.im, y2.re) for h = 0, (y2.im, y3.re, y3.im) for h = 1.
+struct Row3 {
+  float v[3];
+};
+
+// The lane's three reals of the projected row of (u0, u1) (its two
+// components), and of the matching "Im" row (-Im y, Re y) of a read.
+__device__ __forceinline__ void letter_sum_rows(float2 u0, float2 u1, int h, Row3& re, Row3& im) {
+  const float2 s = make_float2(u0.x + u1.x, u0.y + u1.y);
+  const float2 d = make_float2(u0.x - u1.x, u0.y - u1.y);
+  const float2 sp = make_float2(__shfl_xor(s.x, 1, 64), __shfl_xor(s.y, 1, 64));
+  const float2 dp = make_float2(__shfl_xor(d.x, 1, 64), __shfl_xor(d.y, 1, 64));
+  // y1 = (s01 - s23)/2, y2 = (d01 + d23)/2, y3 = (d01 - d23)/2, letters 0 and 1
+  // being lane h = 0's
+  const float sg = h ? -0.5f : 0.5f;
+  const float2 y1 = make_float2(sg * (s.x - sp.x), sg * (s.y - sp.y));
+  const float2 y2 = make_float2(0.5f * (d.x + dp.x), 0.5f * (d.y + dp.y));
+  const float2 y3 = make_float2(sg * (d.x - dp.x), sg * (d.y - dp.y));
+  if (h) {
+    re = Row3{{y2.y, y3.x, y3.y}};
+    im = Row3{{y2.x, -y3.y, y3.x}};
+  } else {
+    re = Row3{{y1.x, y1.y, y2.x}};
+    im = Row3{{-y1.y, y1.x, -y2.y}};
+  }
+}
+
+// Write the lane's three reals of a letter-sum row (reals 3 lane .. 3 lane + 2)
+// in the requested precision; FP8 codes and the returned scale as for
+// store_row, the scale making the dequantised row exactly as long as the
+// FP32 row.
+template <int PREC, bool WINDOW = false>
+__device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, Row3 x) {
+  const bool odd = lane & 1;
+  if constexpr (PREC == RM_FP32) {
+    float* dst = static_cast<float*>(base) + row * kRealReduced + 3 * lane;
+    dst[0] = x.v[0];
+    dst[1] = x.v[1];
+    dst[2] = x.v[2];
+    return 1.f;
+  } else if constexpr (PREC == RM_FP16) {
+    const uint32_t h0 = __builtin_bit_cast(uint16_t, (_Float16)x.v[0]);
+    const uint32_t h1 = __builtin_bit_cast(uint16_t, (_Float16)x.v[1]);
+    const uint32_t h2 = __builtin_bit_cast(uint16_t, (_Float16)x.v[2]);
+    uint16_t* dst = static_cast<uint16_t*>(base) + row * kRealReduced + 3 * lane;
+    if (!odd) {  // byte offset 6 lane is a multiple of 4
+      *reinterpret_cast<uint32_t*>(dst) = h0 | (h1 << 16);
+      dst[2] = (uint16_t)h2;
+    } else {     // 6 lane + 2 is
+      dst[0] = (uint16_t)h0;
+      *reinterpret_cast<uint32_t*>(dst + 1) = h1 | (h2 << 16);
+    }
+    return 1.f;
+  } else {
+    float s = kFp8WindowScale, inv = 1.f / kFp8WindowScale;
+    if constexpr (!WINDOW) {
+      float m = fmaxf(fmaxf(fabsf(x.v[0]), fabsf(x.v[1])), fabsf(x.v[2]));
+      m = wave_max_nonneg(m);
+      s = fp8_pow2_scale(m);
+      inv = pow2_reciprocal(s);
+    }
+    const uint32_t w01 = pack_fp8x2(x.v[0] * inv, x.v[1] * inv);
+    const uint32_t w2 = pack_fp8x2(x.v[2] * inv, 0.f) & 0xffu;
+    uint8_t* dst = static_cast<uint8_t*>(base) + row * kRealReduced + 3 * lane;
+    if (!odd) {  // byte offset 3 lane is even
+      *reinterpret_cast<uint16_t*>(dst) = (uint16_t)w01;
+      dst[2] = (uint8_t)w2;
+    } else {
+      dst[0] = (uint8_t)(w01 & 0xffu);
+      *reinterpret_cast<uint16_t*>(dst + 1) = (uint16_t)((w01 >> 8) | (w2 << 8));
+    }
+    const float2 d01 = unpack_fp8x2(w01), d2 = unpack_fp8x2(w2);
+    const float q2 = wave_sum(d01.x * d01.x + d01.y * d01.y + d2.x * d2.x);
+    const float y2 = wave_sum(x.v[0] * x.v[0] + x.v[1] * x.v[1] + x.v[2] * x.v[2]);
+    return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) * sqrtf(y2) : s;
+  }
+}
+
 // FP64 direct sum over letters [0, n) of `str` for this lane's two components.
 __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int n,
                                            const double2* __restrict__ phase64, int lane,
@@ -134,15 +223,23 @@ __device__ __forceinline__ void side_finish(SideBuf& b, int lane, float* norm2, 
   }
 }
 
-template <int PREC>
+template <int PREC, bool RED = false>
 __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c0, float2 c1,
                                             void* emb, SideBuf& side, float* scale,
                                             float* norm2) {
   float n2 = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
   bool deg = n2 < kDegenerateRel * (float)N;
   float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
-  Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
-  float s = store_row<PREC, true>(emb, j, lane, x);
+  float s;
+  if constexpr (RED) {  // the letter-sum form of the normalised vector
+    Row3 y, unused;
+    letter_sum_rows(make_float2(c0.x * inv, c0.y * inv), make_float2(c1.x * inv, c1.y * inv),
+                    lane & 1, y, unused);
+    s = store_row3<PREC, true>(emb, j, lane, y);
+  } else {
+    Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
+    s = store_row<PREC, true>(emb, j, lane, x);
+  }
   if (lane == side.n) {
     side.n2 = n2;
     side.sc = s;
@@ -150,7 +247,7 @@ __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c
   if (++side.n == 64) side_flush(side, lane, norm2, scale);
 }
 
-template <int PREC>
+template <int PREC, bool RED>
 __global__ __launch_bounds__(256) void encode_reference_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,
     const double2* __restrict__ phase64, const float4* __restrict__ step32, void* __restrict__ emb,
@@ -169,7 +266,7 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
   SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
-  emit_window<PREC>(j0, lane, N, c0, c1, emb, side, scale, norm2);
+  emit_window<PREC, RED>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
   const float4 st = step32[k];
   const float2 rot = make_float2(st.x, st.y);   // omega^-f
@@ -196,7 +293,7 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
       if (--until_emit == 0) {
         until_emit = stride;
         ++j;
-        emit_window<PREC>(j, lane, N, c0, c1, emb, side, scale, norm2);
+        emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
       }
     }
     out_l = out_next;
@@ -209,24 +306,32 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
 // norm below kDegenerateRel * N gives the zero vector) and store its two real
 // rows: 2r = (Re x, Im x) per component, 2r+1 = (-Im x, Re x).  A window row
 // (Re c, Im c) dotted with them gives Re and Im of sum conj(x) c.
-template <int PREC>
+template <int PREC, bool RED = false>
 __device__ __forceinline__ void emit_head(float2 a0, float2 a1, int N, int64_t r, int lane,
                                           void* __restrict__ emb, float* __restrict__ scale) {
   const float X = wave_sum(a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y);
   const float inv = X < kDegenerateRel * N ? 0.f : 1.f / sqrtf(X);
   const float xr0 = a0.x * inv, xi0 = a0.y * inv;
   const float xr1 = a1.x * inv, xi1 = a1.y * inv;
-  Row4 re{{xr0, xi0, xr1, xi1}};
-  Row4 im{{-xi0, xr0, -xi1, xr1}};
-  const float s = store_row<PREC>(emb, 2 * r, lane, re);
-  store_row<PREC>(emb, 2 * r + 1, lane, im);
+  float s;
+  if constexpr (RED) {  // the letter-sum form (a window's all-letters part is zero)
+    Row3 re, im;
+    letter_sum_rows(make_float2(xr0, xi0), make_float2(xr1, xi1), lane & 1, re, im);
+    s = store_row3<PREC>(emb, 2 * r, lane, re);
+    store_row3<PREC>(emb, 2 * r + 1, lane, im);
+  } else {
+    Row4 re{{xr0, xi0, xr1, xi1}};
+    Row4 im{{-xi0, xr0, -xi1, xr1}};
+    s = store_row<PREC>(emb, 2 * r, lane, re);
+    store_row<PREC>(emb, 2 * r + 1, lane, im);
+  }
   if (scale != nullptr && lane == 0) scale[r] = s;
 }
 
 // Read heads (§3.1: the first N letters of each read): an FP32 direct sum of
 // the FP32 phase table over the head's letters, one wavefront per read.  A
 // read shorter than N is the zero vector.
-template <int PREC>
+template <int PREC, bool RED>
 __global__ __launch_bounds__(256) void encode_reads_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
     const float2* __restrict__ phase32, void* __restrict__ emb, float* __restrict__ scale) {
@@ -237,7 +342,7 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
   const int64_t len = off[r + 1] - start;
   float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
   if (len >= N) direct_sum32(seq + start, N, phase32, lane, a0, a1);
-  emit_head<PREC>(a0, a1, N, r, lane, emb, scale);
+  emit_head<PREC, RED>(a0, a1, N, r, lane, emb, scale);
 }
 
 // ---- learned token offsets -------------------------------------------------
@@ -509,21 +614,14 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
   int64_t blocks = (n_seg + waves - 1) / waves;
   auto* ph = reinterpret_cast<const double2*>(phase64);
   auto* st = reinterpret_cast<const float4*>(step32);
-  switch (p.precision) {
-    case RM_FP32:
-      hipLaunchKernelGGL(encode_reference_kernel<RM_FP32>, dim3((unsigned)blocks), dim3(64 * waves),
-                         0, s, ref, W, p.window_len, p.stride, seg, n_seg, ph, st, emb, scale, norm2);
-      break;
-    case RM_FP16:
-      hipLaunchKernelGGL(encode_reference_kernel<RM_FP16>, dim3((unsigned)blocks), dim3(64 * waves),
-                         0, s, ref, W, p.window_len, p.stride, seg, n_seg, ph, st, emb, scale, norm2);
-      break;
-    default:
-      hipLaunchKernelGGL(encode_reference_kernel<RM_FP8_E4M3>, dim3((unsigned)blocks),
-                         dim3(64 * waves), 0, s, ref, W, p.window_len, p.stride, seg, n_seg, ph, st,
-                         emb, scale, norm2);
-      break;
-  }
+  auto kern = encode_reference_kernel<RM_FP32, false>;
+  if (p.precision == RM_FP16)
+    kern = p.reduced ? encode_reference_kernel<RM_FP16, true> : encode_reference_kernel<RM_FP16, false>;
+  else if (p.precision == RM_FP8_E4M3)
+    kern = p.reduced ? encode_reference_kernel<RM_FP8_E4M3, true>
+                     : encode_reference_kernel<RM_FP8_E4M3, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), 0, s, ref, W, p.window_len,
+                     p.stride, seg, n_seg, ph, st, emb, scale, norm2);
   return hipGetLastError();
 }
 
@@ -533,20 +631,13 @@ hipError_t launch_encode_reads(const rm_params& p, const float* phase32, const u
   const int waves = 4;
   int64_t blocks = ((int64_t)n_reads + waves - 1) / waves;
   auto* ph = reinterpret_cast<const float2*>(phase32);
-  switch (p.precision) {
-    case RM_FP32:
-      hipLaunchKernelGGL(encode_reads_kernel<RM_FP32>, dim3((unsigned)blocks), dim3(64 * waves), 0, s,
-                         seq, off, n_reads, p.window_len, ph, emb, scale);
-      break;
-    case RM_FP16:
-      hipLaunchKernelGGL(encode_reads_kernel<RM_FP16>, dim3((unsigned)blocks), dim3(64 * waves), 0, s,
-                         seq, off, n_reads, p.window_len, ph, emb, scale);
-      break;
-    default:
-      hipLaunchKernelGGL(encode_reads_kernel<RM_FP8_E4M3>, dim3((unsigned)blocks), dim3(64 * waves),
-                         0, s, seq, off, n_reads, p.window_len, ph, emb, scale);
-      break;
-  }
+  auto kern = encode_reads_kernel<RM_FP32, false>;
+  if (p.precision == RM_FP16)
+    kern = p.reduced ? encode_reads_kernel<RM_FP16, true> : encode_reads_kernel<RM_FP16, false>;
+  else if (p.precision == RM_FP8_E4M3)
+    kern = p.reduced ? encode_reads_kernel<RM_FP8_E4M3, true> : encode_reads_kernel<RM_FP8_E4M3, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), 0, s, seq, off, n_reads,
+                     p.window_len, ph, emb, scale);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ constexpr int kLetters = 4;
 constexpr int kM = RM_DIM;                 // factors per encoding (m)
 constexpr int kComplex = kLetters * kM;    // 128 complex components
 constexpr int kReal = 2 * kComplex;        // 256 reals per embedding row
+constexpr int kRealReduced = 2 * 3 * kM;   // 192 reals per row of the letter-sum form
 constexpr float kDegenerateRel = 1e-4f;    // squared norm < this * N -> zero vector
 constexpr float kFp8Max = 448.0f;          // largest finite OCP e4m3 value
 // FP8 window rows of 128 complex components are codes of 256 v (a common
@@ -246,6 +247,9 @@ constexpr int kMaxGroups = 8;
 // hold distinct windows, so the kp-th largest of them bounds the read's final
 // kp-th best from below.
 constexpr int kScoreSlots = 32;
+
+// Rows of the letter-sum form (rm_params.reduced).
+inline bool reduced_rows(const rm_params& p) { return p.reduced != 0; }
 
 struct ScoreGroup {
   const uint8_t* index;      // [W][256] window embeddings

@@ -68,9 +68,27 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* __restrict__
   }
 }
 
-// Instantiations: (precision, reads per block, list length) -> (fragments per
-// wavefront, list+buffer entries, ring stages); LDS stays within 160 KB.
-hipError_t dispatch(int precision, int read_tile, int kp, const ScoreLaunch& L, hipStream_t s) {
+// Instantiations: (precision, reads per block, list length, row format) ->
+// (fragments per wavefront, list+buffer entries, ring stages, column blocks);
+// LDS stays within 160 KB.
+template <int KR>
+hipError_t dispatch_f8(int read_tile, int kp, const ScoreLaunch& L, hipStream_t s) {
+  if (read_tile == 256) {
+    switch (kp) {
+      case 8: return launch_persistent<RM_FP8_E4M3, 2, 8, 32, 4, 2, KR>(L, s);
+      case 16: return launch_persistent<RM_FP8_E4M3, 2, 16, 32, 4, 2, KR>(L, s);
+      default: return launch_persistent<RM_FP8_E4M3, 2, 32, 48, 3, 2, KR>(L, s);
+    }
+  }
+  switch (kp) {
+    case 8: return launch_persistent<RM_FP8_E4M3, 1, 8, 32, 4, 1, KR>(L, s);
+    case 16: return launch_persistent<RM_FP8_E4M3, 1, 16, 32, 4, 1, KR>(L, s);
+    default: return launch_persistent<RM_FP8_E4M3, 1, 32, 64, 4, 1, KR>(L, s);
+  }
+}
+
+hipError_t dispatch(int precision, bool reduced, int read_tile, int kp, const ScoreLaunch& L,
+                    hipStream_t s) {
   if (precision == RM_FP32) {
     switch (kp) {
       case 8: return launch_persistent<RM_FP32, 1, 8, 32, 3>(L, s);
@@ -78,19 +96,9 @@ hipError_t dispatch(int precision, int read_tile, int kp, const ScoreLaunch& L, 
       default: return launch_persistent<RM_FP32, 1, 32, 64, 2>(L, s);
     }
   }
-  if (precision == RM_FP16) return dispatch_score_f16(read_tile, kp, L, s);
-  if (read_tile == 256) {
-    switch (kp) {
-      case 8: return launch_persistent<RM_FP8_E4M3, 2, 8, 32, 4, 2>(L, s);
-      case 16: return launch_persistent<RM_FP8_E4M3, 2, 16, 32, 4, 2>(L, s);
-      default: return launch_persistent<RM_FP8_E4M3, 2, 32, 48, 3, 2>(L, s);
-    }
-  }
-  switch (kp) {
-    case 8: return launch_persistent<RM_FP8_E4M3, 1, 8, 32, 4>(L, s);
-    case 16: return launch_persistent<RM_FP8_E4M3, 1, 16, 32, 4>(L, s);
-    default: return launch_persistent<RM_FP8_E4M3, 1, 32, 64, 4>(L, s);
-  }
+  if (precision == RM_FP16) return dispatch_score_f16(read_tile, kp, reduced, L, s);
+  return reduced ? dispatch_f8<kRealReduced>(read_tile, kp, L, s)
+                 : dispatch_f8<kReal>(read_tile, kp, L, s);
 }
 
 }  // namespace
@@ -186,7 +194,7 @@ hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
   hipLaunchKernelGGL(clear_state, dim3((unsigned)(((int64_t)maxR + 255) / 256)), dim3(256), 0, s, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = dispatch(idx[0].p.precision, plan.read_tile, plan.kp, L, s);
+  e = dispatch(idx[0].p.precision, reduced_rows(idx[0].p), plan.read_tile, plan.kp, L, s);
   if (e != hipSuccess) return e;
   for (int i = 0; i < plan.n_groups; ++i) {
     int n_per_read = plan.g[i].chunks * plan.kp;

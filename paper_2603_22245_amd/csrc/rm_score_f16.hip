@@ -7,21 +7,32 @@
 
 namespace rm {
 
-hipError_t dispatch_score_f16(int read_tile, int kp, const ScoreLaunch& L, hipStream_t s) {
+namespace {
+
+template <int KR>
+hipError_t dispatch_f16(int read_tile, int kp, const ScoreLaunch& L, hipStream_t s) {
   if (read_tile == 256) {
     switch (kp) {
-      case 8: return launch_persistent<RM_FP16, 2, 8, 32, 4>(L, s);
-      case 16: return launch_persistent<RM_FP16, 2, 16, 32, 4>(L, s);
+      case 8: return launch_persistent<RM_FP16, 2, 8, 32, 4, 1, KR>(L, s);
+      case 16: return launch_persistent<RM_FP16, 2, 16, 32, 4, 1, KR>(L, s);
       // 32-key lists with a 16-slot buffer: 96 KB of lists leave room for
-      // three 16 KB ring stages
-      default: return launch_persistent<RM_FP16, 2, 32, 48, 3>(L, s);
+      // three ring stages
+      default: return launch_persistent<RM_FP16, 2, 32, 48, 3, 1, KR>(L, s);
     }
   }
   switch (kp) {
-    case 8: return launch_persistent<RM_FP16, 1, 8, 32, 4>(L, s);
-    case 16: return launch_persistent<RM_FP16, 1, 16, 32, 4>(L, s);
-    default: return launch_persistent<RM_FP16, 1, 32, 64, 4>(L, s);
+    case 8: return launch_persistent<RM_FP16, 1, 8, 32, 4, 1, KR>(L, s);
+    case 16: return launch_persistent<RM_FP16, 1, 16, 32, 4, 1, KR>(L, s);
+    default: return launch_persistent<RM_FP16, 1, 32, 64, 4, 1, KR>(L, s);
   }
+}
+
+}  // namespace
+
+hipError_t dispatch_score_f16(int read_tile, int kp, bool reduced, const ScoreLaunch& L,
+                              hipStream_t s) {
+  return reduced ? dispatch_f16<kRealReduced>(read_tile, kp, L, s)
+                 : dispatch_f16<kReal>(read_tile, kp, L, s);
 }
 
 }  // namespace rm

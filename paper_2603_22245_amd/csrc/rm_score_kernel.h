@@ -31,7 +31,8 @@
 namespace rm {
 
 // FP16 instantiations of the scoring kernel (rm_score_f16.hip).
-hipError_t dispatch_score_f16(int read_tile, int kp, const ScoreLaunch& L, hipStream_t s);
+hipError_t dispatch_score_f16(int read_tile, int kp, bool reduced, const ScoreLaunch& L,
+                              hipStream_t s);
 
 namespace {
 
@@ -148,32 +149,87 @@ __device__ __forceinline__ void wait_vmcnt() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// B tiles in LDS: row r (one window, RB bytes) stores its logical 16-byte chunk
-// c at position c ^ (r & 15).  A lane reading chunk c of row `col` therefore
-// reads byte offset col*RB + 16 (c ^ (col & 15)); the 16 lanes of one LDS
-// access cycle (consecutive col, same c) hit 16 different bank groups.
-//
-// One 32x32 output block per fragment over the full K = 256.  `a[f]` holds
-// this lane's 128 K-elements of fragment f (K range [128 g, 128 g + 128),
-// g = lane / 32, in natural order); `row` points at this lane's window row in
-// the current LDS stage and kx = (byte offset of the lane's K half) ^
-// 16 (col & 15), so logical byte offset o is found at row + (kx ^ o).  Any
-// assignment of K indices to (lane group, register slot) works as long as A
-// and B use the same one, which they do here.
-template <int PREC, int NF, int NB, int AU4>
-__device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8_t* row,
-                                          uint32_t kx, f32x16 (&acc)[NF][NB]) {
-  // column block nb of the tile: rows 32 nb + col (same swizzle key: 32 nb
-  // leaves the row's low four bits alone)
-  constexpr int BLK = kBlkW * Prec<PREC>::esize * kReal;
+// Row formats of the product.  A row holds KR reals: kReal = 256 for the
+// letter encoding (128 complex components), kRealReduced = 192 for its
+// letter-sum form (96 components; FP16 and FP8 only).  B tiles in LDS: row r
+// (one window, RB bytes) stores logical 16-byte chunk c at physical chunk
+// swap(r, c), a permutation keyed by r's low bits that makes the 16 rows read
+// together by one LDS access cycle (16 consecutive rows, the same logical
+// chunk) fall in 16 different bank groups (16-byte units mod 16):
+//  * 256 reals: c ^ (r & 15) (a row is a multiple of 256 B, so its physical
+//    chunk index mod 16 is c ^ (r & 15) itself);
+//  * 192 reals, FP16 (24 chunks = 384 B, rows alternate between bank-group
+//    offsets 0 and 8): chunks 0-15 as c ^ (r & 15), chunks 16-23 as
+//    16 + ((c - 16) ^ ((r >> 1) & 7));
+//  * 192 reals, FP8 (12 chunks = 192 B, rows step the bank-group offset by
+//    12): c ^ ((r >> 2) & 3), which permutes each aligned group of 4 chunks.
+// Each permutation is an involution, so swap() also maps physical to logical.
+// A lane in half g = lane / 32 of a wavefront takes AU4 of the row's chunks,
+// its share of K: register slot u holds logical chunk lane_chunk(g, u), of
+// the read row (A, registers) and of the window row (B, LDS) alike -- any
+// assignment of K indices to (lane half, slot) works as long as A and B use
+// the same one.  keys() gives the lane's LDS byte-offset keys: slot u of the
+// first region is at row + (kx ^ 16 u'), of the second at row + base2 +
+// (kx2 ^ 16 u''), with u', u'' the slot's position inside its region.
+template <int PREC, int KR>
+struct RowFmt {
+  static constexpr int esize = Prec<PREC>::esize;
+  static constexpr int RB = KR * esize;  // bytes per row
+  static constexpr int CPR = RB / 16;    // 16-byte chunks per row
+  static constexpr int AU4 = CPR / 2;    // chunks per lane (uint4 per fragment)
+  static constexpr bool kFull = KR == kReal;
+  static_assert(kFull || (KR == kRealReduced && PREC != RM_FP32), "row format");
+  // slots in the first region, and the byte offset of the second region
+  static constexpr int U1 = kFull ? AU4 : (PREC == RM_FP16 ? 8 : 4);
+  static constexpr int BASE2 = PREC == RM_FP16 ? 256 : 128;
+  __device__ __forceinline__ static int swap(int r, int c) {
+    if constexpr (kFull) return c ^ (r & 15);
+    else if constexpr (PREC == RM_FP16) return c < 16 ? c ^ (r & 15) : 16 + ((c - 16) ^ ((r >> 1) & 7));
+    else return c ^ ((r >> 2) & 3);
+  }
+  __device__ __forceinline__ static int lane_chunk(int g, int u) {
+    if constexpr (kFull) return g * AU4 + u;
+    else if constexpr (PREC == RM_FP16) return u < 8 ? 8 * g + u : 16 + 4 * g + (u - 8);
+    else return u < 4 ? 4 * g + u : 8 + 2 * g + (u - 4);
+  }
+  __device__ __forceinline__ static void keys(int g, int col, uint32_t& kx, uint32_t& kx2) {
+    if constexpr (kFull) {
+      kx = ((uint32_t)g * (RB / 2)) ^ (16u * (uint32_t)(col & 15));
+      kx2 = 0;
+    } else if constexpr (PREC == RM_FP16) {
+      kx = (128u * g) ^ (16u * (uint32_t)(col & 15));
+      kx2 = (64u * g) ^ (16u * (uint32_t)((col >> 1) & 7));
+    } else {
+      kx = (64u * g) ^ (16u * (uint32_t)((col >> 2) & 3));
+      kx2 = (32u * g) ^ (16u * (uint32_t)((col >> 2) & 3));
+    }
+  }
+  // LDS byte offset of slot u (u a compile-time constant after unrolling)
+  __device__ __forceinline__ static uint32_t slot_offset(int u, uint32_t kx, uint32_t kx2) {
+    return u < U1 ? (kx ^ (16u * u)) : BASE2 + (kx2 ^ (16u * (u - U1)));
+  }
+};
+
+// One 32x32 output block per fragment over the row's full K.  `a[f]` holds
+// this lane's AU4 chunks of fragment f's rows (slot order of RowFmt); `row`
+// points at this lane's window row in the current LDS stage and kx, kx2 are
+// its RowFmt keys.
+template <int PREC, int NF, int NB, int KR>
+__device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][RowFmt<PREC, KR>::AU4],
+                                          const uint8_t* row, uint32_t kx, uint32_t kx2,
+                                          f32x16 (&acc)[NF][NB]) {
+  using RF = RowFmt<PREC, KR>;
+  // column block nb of the tile: rows 32 nb + col (same swizzle keys: 32 nb
+  // leaves the row's low five bits alone)
+  constexpr int BLK = kBlkW * RF::RB;
   if constexpr (PREC == RM_FP16) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < RF::AU4; ++s) {
       half8 bh[NB];
+      const uint32_t o = RF::slot_offset(s, kx, kx2);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        bh[nb] = __builtin_bit_cast(half8,
-                                    *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (16u * s))));
+        bh[nb] = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(row + nb * BLK + o));
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -183,12 +239,13 @@ __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8
     }
   } else if constexpr (PREC == RM_FP8_E4M3) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < RF::AU4 / 2; ++s) {
       i32x8 bb[NB];
+      const uint32_t o0 = RF::slot_offset(2 * s, kx, kx2), o1 = RF::slot_offset(2 * s + 1, kx, kx2);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        uint4 b0 = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (32u * s)));
-        uint4 b1 = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (32u * s + 16u)));
+        uint4 b0 = *reinterpret_cast<const uint4*>(row + nb * BLK + o0);
+        uint4 b1 = *reinterpret_cast<const uint4*>(row + nb * BLK + o1);
         bb[nb] = i32x8{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
                        (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
       }
@@ -206,10 +263,10 @@ __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8
     }
   } else {
 #pragma unroll
-    for (int s4 = 0; s4 < 32; ++s4) {
+    for (int s4 = 0; s4 < RF::AU4; ++s4) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        uint4 bv = *reinterpret_cast<const uint4*>(row + nb * BLK + (kx ^ (16u * s4)));
+        uint4 bv = *reinterpret_cast<const uint4*>(row + nb * BLK + RF::slot_offset(s4, kx, kx2));
         float bf[4] = {__uint_as_float(bv.x), __uint_as_float(bv.y), __uint_as_float(bv.z),
                        __uint_as_float(bv.w)};
 #pragma unroll
@@ -227,18 +284,22 @@ __device__ __forceinline__ void mfma_tile(const uint4 (&a)[NF][AU4], const uint8
   }
 }
 
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB, int KR>
 struct ScoreKernel {
-  static constexpr int esize = Prec<PREC>::esize;
-  static constexpr int RB = kReal * esize;              // bytes per embedding row
-  static constexpr int CPR = RB / 16;                   // 16-byte chunks per row
-  static constexpr int AU4 = (kReal / 2) * esize / 16;  // uint4 per lane per fragment
+  using RF = RowFmt<PREC, KR>;
+  static constexpr int RB = RF::RB;                     // bytes per embedding row
+  static constexpr int CPR = RF::CPR;                   // 16-byte chunks per row
+  static constexpr int AU4 = RF::AU4;                   // uint4 per lane per fragment
   static constexpr int READS = WAVES * NF * 16;         // reads per block
   static constexpr int THREADS = WAVES * 64;
   static constexpr int TW = kBlkW * NB;                 // windows per B tile
   static constexpr int TILE = TW * RB;                  // bytes per B tile
-  static constexpr int L = TILE / 1024 / WAVES;         // 1 KB copies per wave per tile
-  static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 1 : 0);  // + the window scales
+  // 1 KB copies per tile: wavefronts w < NH make LH of them, the others LL
+  static constexpr int C = TILE / 1024;
+  static constexpr int LH = (C + WAVES - 1) / WAVES, LL = C / WAVES, NH = C % WAVES;
+  // this wavefront's copies per tile, + the window scales
+  static constexpr int LTH = LH + (PREC == RM_FP8_E4M3 ? 1 : 0);
+  static constexpr int LTL = LL + (PREC == RM_FP8_E4M3 ? 1 : 0);
   static constexpr int CB = ENT - KP;                   // buffer slots per read
   // lanes of the bitonic merge of one read's list and buffer (ENT rounded up
   // to a power of two; lanes past ENT sort empty keys)
@@ -248,7 +309,7 @@ struct ScoreKernel {
   // halving their barriers pays (2%); for FP16 it costs 2.5%.
   static constexpr int GRP = PREC == RM_FP8_E4M3 && STAGES >= 4 ? 2 : 1;
   static constexpr int LEAD = STAGES - GRP;
-  static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile/waves");
+  static_assert(C >= 1 && TILE % 1024 == 0, "tile");
   static_assert(CB >= 1 && ENT <= 64, "buffer");
   static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
   static_assert(NF * NB * 8 <= 64, "pending hits are 64-bit masks of (block, fragment, row pair)");
@@ -257,12 +318,13 @@ struct ScoreKernel {
 };
 
 // One work item: read tile `tile` of group G against window chunk `chunk`.
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB, int KR>
 __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int tile,
                                            uint8_t* ring, float* ring_scale,
                                            uint64_t (*lst)[ENT], int* cnt, float* thr,
                                            float* rsq) {
-  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB, KR>;
+  using RF = typename K::RF;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
   const uint8_t* __restrict__ index = G.index;
   const float* __restrict__ win_scale = G.win_scale;
@@ -307,9 +369,9 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   for (int f = 0; f < NF; ++f) {
     int64_t row = 2 * read0 + (int64_t)(wave * NF + f) * 32 + col;
     if (row < 2 * (int64_t)R) {
-      const uint4* src = reinterpret_cast<const uint4*>(reads + row * K::RB + g * (K::RB / 2));
+      const uint4* src = reinterpret_cast<const uint4*>(reads + row * K::RB);
 #pragma unroll
-      for (int u = 0; u < K::AU4; ++u) a[f][u] = src[u];
+      for (int u = 0; u < K::AU4; ++u) a[f][u] = src[RF::lane_chunk(g, u)];
     } else {
 #pragma unroll
       for (int u = 0; u < K::AU4; ++u) a[f][u] = make_uint4(0, 0, 0, 0);
@@ -356,13 +418,13 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // ---- B tiles: asynchronous copies into an LDS ring of STAGES tiles
   const uint32_t ring_lds = lds_offset(ring);
   const uint32_t scale_lds = lds_offset(ring_scale);
-  int drow[K::L];
-  uint32_t doff[K::L];
+  int drow[K::LH];
+  uint32_t doff[K::LH];
 #pragma unroll
-  for (int i = 0; i < K::L; ++i) {
+  for (int i = 0; i < K::LH; ++i) {
     int pos = (i * WAVES + wave) * 64 + lane;  // physical 16-byte chunk in the tile
-    int r = pos / K::CPR;
-    int c = (pos % K::CPR) ^ (r & 15);          // logical chunk stored there
+    int r = min(pos / K::CPR, K::TW - 1);      // (a wavefront's copy past C is never issued)
+    int c = RF::swap(r, pos % K::CPR);         // logical chunk stored there
     drow[i] = r;
     doff[i] = (uint32_t)c * 16u;
   }
@@ -370,10 +432,12 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   auto issue_into = [&](int tsrc, int stage) {
     const int64_t tb = wbeg + (int64_t)tsrc * K::TW;
 #pragma unroll
-    for (int i = 0; i < K::L; ++i) {
-      int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
-      dma16(index + grow * K::RB + doff[i],
-            __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * WAVES + wave) * 1024));
+    for (int i = 0; i < K::LH; ++i) {
+      if (i < K::LL || wave < K::NH) {
+        int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
+        dma16(index + grow * K::RB + doff[i],
+              __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * WAVES + wave) * 1024));
+      }
     }
     if constexpr (kFp8) {
       if (lane < K::TW)
@@ -448,8 +512,9 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     refresh_thresholds();
   };
 
-  // lane's B row offset and K-half key (see mfma_tile)
-  const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
+  // lane's LDS keys (see RowFmt)
+  uint32_t kx, kx2;
+  RF::keys(g, col, kx, kx2);
 
   // Pipeline: copies run LEAD tiles ahead of the tile being scored (past the
   // last tile they repeat the last tile, so every group issues the same
@@ -464,7 +529,10 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   // block; false (nothing done) inside a group
   auto group_barrier = [&](int t) -> bool {
     if (t % K::GRP) return false;
-    wait_vmcnt<(K::LEAD - K::GRP) * K::LT>();
+    if (K::NH == 0 || wave < K::NH)
+      wait_vmcnt<(K::LEAD - K::GRP) * K::LTH>();
+    else
+      wait_vmcnt<(K::LEAD - K::GRP) * K::LTL>();
     __syncthreads();
     return true;
   };
@@ -492,7 +560,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x16{};
-    mfma_tile<PREC, NF, NB, K::AU4>(a, ring + (t % STAGES) * K::TILE + col * K::RB, kx, acc);
+    mfma_tile<PREC, NF, NB, KR>(a, ring + (t % STAGES) * K::TILE + col * K::RB, kx, kx2, acc);
   };
   // tile t's scales and MFMAs; its data is valid from the barrier of tile t's
   // group until the barrier after it
@@ -680,9 +748,9 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
 // are numbered chunk-major within each group, so concurrently running blocks
 // stream the same windows.  Every block leaves the loop once the counter has
 // passed the last item.
-template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB>
+template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB, int KR>
 __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
-  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
+  using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB, KR>;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
   __shared__ __align__(1024) uint8_t ring[STAGES * K::TILE];
   __shared__ __align__(16) float ring_scale[kFp8 ? STAGES * WAVES * K::TW : 4];
@@ -701,16 +769,16 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
     while (gi + 1 < L.n_groups && item >= L.g[gi + 1].item_begin) ++gi;
     const ScoreGroup& G = L.g[gi];
     const int local = item - G.item_begin;
-    score_item<PREC, NF, WAVES, KP, ENT, STAGES, NB>(G, local / G.read_tiles,
+    score_item<PREC, NF, WAVES, KP, ENT, STAGES, NB, KR>(G, local / G.read_tiles,
                                                       local % G.read_tiles, ring, ring_scale, lst,
                                                       cnt, thr, rsq);
   }
 }
 
-template <int PREC, int NF, int KP, int ENT, int STAGES, int NB = 1>
+template <int PREC, int NF, int KP, int ENT, int STAGES, int NB = 1, int KR = kReal>
 hipError_t launch_persistent(const ScoreLaunch& L, hipStream_t s) {
   constexpr int WAVES = 8;
-  auto kern = score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES, NB>;
+  auto kern = score_topk_kernel<PREC, NF, WAVES, KP, ENT, STAGES, NB, KR>;
   // resident blocks per CU for this instantiation (LDS and VGPR limited)
   static int per_cu = [&] {
     int n = 0;

@@ -156,21 +156,25 @@ __global__ __launch_bounds__(64 * kThrWaves) void window_thresholds_kernel(
 
 // ---- the regime's product pass
 
-template <int PREC>
+template <int PREC, int KR>
 struct ThrK {
+  using RF = RowFmt<PREC, KR>;
   static constexpr int NF = PREC == RM_FP32 ? 1 : 2;      // fragments (16 reads) per wavefront
   static constexpr int WAVES = 4;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int READS = WAVES * NF * 16;
-  static constexpr int esize = Prec<PREC>::esize;
-  static constexpr int RB = kReal * esize;
-  static constexpr int CPR = RB / 16;
-  static constexpr int AU4 = (kReal / 2) * esize / 16;
+  static constexpr int RB = RF::RB;
+  static constexpr int CPR = RF::CPR;
+  static constexpr int AU4 = RF::AU4;
   static constexpr int TW = kBlkW;                          // windows per tile
   static constexpr int TILE = TW * RB;
-  static constexpr int L = TILE / 1024 / WAVES;             // 1 KB copies per wavefront per tile
-  static constexpr int LT = L + (PREC == RM_FP8_E4M3 ? 2 : 1);  // + thresholds (+ window scales)
-  static_assert(L >= 1 && TILE % (1024 * WAVES) == 0, "tile");
+  // 1 KB copies per tile: wavefronts w < NH make LH of them, the others LL;
+  // each also copies the tile's thresholds (and FP8 window scales)
+  static constexpr int C = TILE / 1024;
+  static constexpr int LH = (C + WAVES - 1) / WAVES, LL = C / WAVES, NH = C % WAVES;
+  static constexpr int EXTRA = PREC == RM_FP8_E4M3 ? 2 : 1;
+  static constexpr int LTH = LH + EXTRA, LTL = LL + EXTRA;
+  static_assert(C >= 1 && TILE % 1024 == 0, "tile");
 };
 
 // Product pass of the regime.  Block = (read tile, window chunk); the read
@@ -179,13 +183,14 @@ struct ThrK {
 // stores them), each wavefront copying its share plus its own copy of the
 // tile's thresholds (and FP8 window scales), and waiting for its own copies
 // before the block barrier.
-template <int PREC>
-__global__ __launch_bounds__(ThrK<PREC>::THREADS) void threshold_scan_kernel(
+template <int PREC, int KR>
+__global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kernel(
     const uint8_t* __restrict__ index, const float* __restrict__ win_scale, int64_t W,
     const float* __restrict__ thr, float floor_f, float margin, const uint8_t* __restrict__ reads,
     const float* __restrict__ read_scale, int32_t R, int64_t chunk_windows, int n_chunks,
     uint64_t* __restrict__ pool, uint64_t pool_cap, unsigned long long* __restrict__ pool_n) {
-  using K = ThrK<PREC>;
+  using K = ThrK<PREC, KR>;
+  using RF = typename K::RF;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
   __shared__ __attribute__((aligned(16))) uint8_t ring[2][K::TILE];
   __shared__ float side[2][2][K::WAVES][K::TW];  // [stage][thr, scale][wave][window]
@@ -205,9 +210,10 @@ __global__ __launch_bounds__(ThrK<PREC>::THREADS) void threshold_scan_kernel(
 #pragma unroll
   for (int f = 0; f < K::NF; ++f) {
     const int64_t row = 2 * read0 + (int64_t)(wave * K::NF + f) * 32 + col;
-    const uint4* src = reinterpret_cast<const uint4*>(reads + row * K::RB + g * (K::RB / 2));
+    const uint4* src = reinterpret_cast<const uint4*>(reads + row * K::RB);
 #pragma unroll
-    for (int u = 0; u < K::AU4; ++u) a[f][u] = row < 2 * (int64_t)R ? src[u] : make_uint4(0, 0, 0, 0);
+    for (int u = 0; u < K::AU4; ++u)
+      a[f][u] = row < 2 * (int64_t)R ? src[RF::lane_chunk(g, u)] : make_uint4(0, 0, 0, 0);
   }
   if (tid < K::READS) {
     const int64_t r = read0 + tid;
@@ -219,23 +225,26 @@ __global__ __launch_bounds__(ThrK<PREC>::THREADS) void threshold_scan_kernel(
 
   const uint32_t ring_lds = lds_offset(ring);
   const uint32_t side_lds = lds_offset(side);
-  int drow[K::L];
-  uint32_t doff[K::L];
+  int drow[K::LH];
+  uint32_t doff[K::LH];
 #pragma unroll
-  for (int i = 0; i < K::L; ++i) {
+  for (int i = 0; i < K::LH; ++i) {
     const int pos = (i * K::WAVES + wave) * 64 + lane;  // physical 16-byte chunk in the tile
-    const int r = pos / K::CPR;
+    const int r = min(pos / K::CPR, K::TW - 1);  // (a wavefront's copy past C is never issued)
     drow[i] = r;
-    doff[i] = (uint32_t)((pos % K::CPR) ^ (r & 15)) * 16u;  // the logical chunk stored there
+    doff[i] = (uint32_t)RF::swap(r, pos % K::CPR) * 16u;  // the logical chunk stored there
   }
   auto issue = [&](int t) {
     const int stage = t & 1;
     const int64_t tb = wbeg + (int64_t)t * K::TW;
 #pragma unroll
-    for (int i = 0; i < K::L; ++i) {
-      const int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
-      dma16(index + grow * K::RB + doff[i],
-            __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE + (i * K::WAVES + wave) * 1024));
+    for (int i = 0; i < K::LH; ++i) {
+      if (i < K::LL || wave < K::NH) {
+        const int64_t grow = min(tb + drow[i], wend - 1);  // rows past the chunk: any valid row
+        dma16(index + grow * K::RB + doff[i],
+              __builtin_amdgcn_readfirstlane(ring_lds + stage * K::TILE +
+                                             (i * K::WAVES + wave) * 1024));
+      }
     }
     const int64_t jj = min(tb + lane, wend - 1);
     if (lane < K::TW)
@@ -247,14 +256,18 @@ __global__ __launch_bounds__(ThrK<PREC>::THREADS) void threshold_scan_kernel(
                                  side_lds + (((stage * 2 + 1) * K::WAVES + wave) * K::TW) * 4));
     }
   };
-  const uint32_t kx = ((uint32_t)g * (K::RB / 2)) ^ (16u * (uint32_t)(col & 15));
+  uint32_t kx, kx2;
+  RF::keys(g, col, kx, kx2);
 
   issue(0);
   for (int t = 0; t < ntiles; ++t) {
     const int stage = t & 1;
     if (t + 1 < ntiles) {
       issue(t + 1);          // into the stage every wavefront finished reading before the
-      wait_vmcnt<K::LT>();   // last barrier; then this wavefront's copies of tile t are in
+      if (K::NH == 0 || wave < K::NH)  // last barrier; then this wavefront's copies of tile t are in
+        wait_vmcnt<K::LTH>();
+      else
+        wait_vmcnt<K::LTL>();
     } else {
       wait_vmcnt<0>();
     }
@@ -262,7 +275,7 @@ __global__ __launch_bounds__(ThrK<PREC>::THREADS) void threshold_scan_kernel(
     f32x16 acc[K::NF][1];
 #pragma unroll
     for (int f = 0; f < K::NF; ++f) acc[f][0] = f32x16{};
-    mfma_tile<PREC, K::NF, 1, K::AU4>(a, &ring[stage][col * K::RB], kx, acc);
+    mfma_tile<PREC, K::NF, 1, KR>(a, &ring[stage][col * K::RB], kx, kx2, acc);
     // epilogue: this lane's window column against its cut, less the margin
     const int64_t j = wbeg + (int64_t)t * K::TW + col;
     const bool colok = j < wend;
@@ -471,13 +484,22 @@ hipError_t launch_score_threshold(const rm_index& idx, const uint8_t* ref,
                        margin, static_cast<const uint8_t*>(read_emb), read_scale, R, cw,
                        (int)n_chunks, pool, (uint64_t)capacity, pool_n);
   };
+  const bool red = reduced_rows(idx.p);
   if (prec == RM_FP32)
-    scan(threshold_scan_kernel<RM_FP32>, ThrK<RM_FP32>::READS, ThrK<RM_FP32>::THREADS);
+    scan(threshold_scan_kernel<RM_FP32, kReal>, ThrK<RM_FP32, kReal>::READS,
+         ThrK<RM_FP32, kReal>::THREADS);
+  else if (prec == RM_FP16 && red)
+    scan(threshold_scan_kernel<RM_FP16, kRealReduced>, ThrK<RM_FP16, kRealReduced>::READS,
+         ThrK<RM_FP16, kRealReduced>::THREADS);
   else if (prec == RM_FP16)
-    scan(threshold_scan_kernel<RM_FP16>, ThrK<RM_FP16>::READS, ThrK<RM_FP16>::THREADS);
+    scan(threshold_scan_kernel<RM_FP16, kReal>, ThrK<RM_FP16, kReal>::READS,
+         ThrK<RM_FP16, kReal>::THREADS);
+  else if (red)
+    scan(threshold_scan_kernel<RM_FP8_E4M3, kRealReduced>, ThrK<RM_FP8_E4M3, kRealReduced>::READS,
+         ThrK<RM_FP8_E4M3, kRealReduced>::THREADS);
   else
-    scan(threshold_scan_kernel<RM_FP8_E4M3>, ThrK<RM_FP8_E4M3>::READS,
-         ThrK<RM_FP8_E4M3>::THREADS);
+    scan(threshold_scan_kernel<RM_FP8_E4M3, kReal>, ThrK<RM_FP8_E4M3, kReal>::READS,
+         ThrK<RM_FP8_E4M3, kReal>::THREADS);
 
   hipLaunchKernelGGL(pool_count_kernel, dim3(1024), dim3(256), 0, s, pool, pool_n,
                      (uint64_t)capacity, cnt);

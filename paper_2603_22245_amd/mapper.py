@@ -37,9 +37,10 @@ class Index:
 
     @property
     def real_dim(self) -> int:
-        """Reals per stored row: 256, or 2 n_class m for a token encoding."""
+        """Reals per stored row: 256 (192 in the letter-sum form), or
+        2 n_class m for a token encoding."""
         p = self.params
-        return 2 * p.n_class * p.n_freq if p.n_class else 256
+        return 2 * p.n_class * p.n_freq if p.n_class else (192 if p.reduced else 256)
 
     def embeddings(self):
         """The stored [W, real_dim] embeddings as a torch view (float32/float16/uint8)."""
@@ -67,11 +68,30 @@ def _delta_buffer(n_letters: int, device):
     return torch.empty((nbytes // 128, 32), dtype=torch.float32, device=device)
 
 
+def letter_sum_applies(ref, window_len, precision, schedule="default", token=False,
+                       learned=None) -> bool:
+    """Whether build_index stores an index in the letter-sum form
+    (rm_params.reduced) by default: the plain letter encoding with integer
+    factors, windows longer than m, an FP16 index and a reference of letters
+    only (codes 0..3).  FP8 indexes can take the form too (reduced=True), but
+    not by default: in it e4m3's error per score grows by about sqrt(4/3)
+    (fewer, larger components of the same unit vector)."""
+    if token or learned is not None or schedule != "default" or window_len <= L.RM_DIM:
+        return False
+    if precision not in ("fp16", L.RM_FP16):
+        return False
+    if isinstance(ref, np.ndarray):
+        return ref.size == 0 or int(ref.max()) < 4
+    return ref.numel() == 0 or int(ref.max().item()) < 4
+
+
 def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", schedule="default",
                 reanchor=0, stream=None, device="cuda", learned=None, mer_len=1,
-                n_freq=None, token_map=None, n_class=None) -> Index:
+                n_freq=None, token_map=None, n_class=None, reduced=None) -> Index:
     """Encode the reference's windows.  learned: network parameters (10,432
     FP32 values, numpy or device tensor) for the learned encoding, else plain.
+    reduced: store the letter-sum form (192 reals per row); None chooses it
+    wherever it applies (letter_sum_applies).
 
     Token encodings (s-mers): mer_len = s, token_map = None (class = s-mer
     code, n_class = 4^s) or a table of 4^s classes (uint8; a value >= n_class
@@ -98,8 +118,10 @@ def build_index(ref: np.ndarray, window_len=150, stride=1, precision="fp16", sch
             n_class = 4 ** mer_len if token_map is None else 128 // n_freq
         if n_freq is None:
             n_freq = max(1, (128 if n_class <= 64 else 1024) // n_class)
+    if reduced is None:
+        reduced = letter_sum_applies(ref, window_len, precision, schedule, token, learned)
     p = L.make_params(window_len, stride, n_freq, schedule, precision, reanchor, mer_len, n_class,
-                      d_map)
+                      d_map, reduced)
     if isinstance(ref, np.ndarray):
         d_ref = torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device)
     else:  # already a device tensor

@@ -24,6 +24,29 @@ def emb_to_complex(index, torch):
     return vals[:, 0::2] + 1j * vals[:, 1::2]
 
 
+# The letter-sum form an FP16/FP8 letter index stores by default
+# (rm_params.reduced): per factor, the coordinates y_m = sum_L LETTER_SUM[m, L]
+# x_L on the three non-constant Walsh-Hadamard rows over the letters (A,C,G,T).
+LETTER_SUM = np.array([[1, 1, -1, -1], [1, -1, 1, -1], [1, -1, -1, 1]], dtype=np.float64) / 2.0
+
+
+def stored_form(C, index):
+    """Oracle vectors C [n, 128] (component (k-1)*4 + letter) in the form the
+    index stores them: C itself, or [n, 96] letter-sum coordinates (component
+    (k-1)*3 + m) when the index is in the letter-sum form."""
+    C = np.asarray(C)
+    if not index.params.reduced:
+        return C
+    return np.einsum("nkl,ml->nkm", C.reshape(C.shape[0], -1, 4), LETTER_SUM).reshape(C.shape[0], -1)
+
+
+def interleave(C):
+    """Complex [n, c] -> reals [n, 2c] (re, im interleaved per component)."""
+    out = np.empty((C.shape[0], 2 * C.shape[1]))
+    out[:, 0::2], out[:, 1::2] = C.real, C.imag
+    return out
+
+
 def read_rows(reads, precision, torch):
     """Read-embedding buffer -> (row Re, row Im) as float64 [R, reals per row] each, dequantised."""
     n = reads.n

@@ -329,3 +329,35 @@ def test_noalloc_validation():
     big = 4_000_000
     assert L.rm_score_workspace_bytes(idx, big, 32) > L.RM_NOALLOC_SCRATCH_BYTES
     assert lib.rm_score_topk_noalloc(R(idx), 1, 1, big, 32, 1, 1, None) == L.RM_ESIZE
+
+
+def test_letter_sum_form_params():
+    """The letter-sum form (rm_params.reduced): 192 reals per row for FP16 and
+    FP8 letter indexes with integer factors and N > m; refused elsewhere."""
+    lib = L.lib()
+    R = ctypes.byref
+    out = L.rm_index()
+    for prec, esize in (("fp16", 2), ("fp8", 1)):
+        full = L.make_params(150, 1, 32, "default", prec)
+        red = L.make_params(150, 1, 32, "default", prec, reduced=True)
+        assert L.rm_read_emb_bytes(10, red) == 10 * 2 * 192 * esize
+        assert L.rm_read_emb_bytes(10, full) == 10 * 2 * 256 * esize
+        # rows shrink by a quarter; the rest of the buffer is the same
+        assert L.rm_index_bytes(20_000, full) - L.rm_index_bytes(20_000, red) >= \
+            19_851 * 64 * esize - 256
+    bad = [L.make_params(150, 1, 32, "default", "fp32", reduced=True),          # FP32
+           L.make_params(150, 1, 32, "finetuned", "fp16", reduced=True),        # non-integer factors
+           L.make_params(32, 1, 32, "default", "fp16", reduced=True),           # N = m: f_m = N
+           L.make_params(150, 1, 8, "default", "fp16", 0, 2, 16, reduced=True)]  # tokens
+    for p in bad:
+        assert L.rm_index_bytes(20_000, p) == 0
+        assert lib.rm_encode_reference(0x1000, 20_000, R(p), 0x10000, 1 << 30, R(out), None) \
+            == L.RM_EUNSUPPORTED
+    p = L.make_params(150, 1, 32, "default", "fp16")
+    p.reduced = 2
+    assert lib.rm_encode_reference(0x1000, 20_000, R(p), 0x10000, 1 << 30, R(out), None) \
+        == L.RM_EINVAL
+    # the learned encoding has no letter-sum form
+    red = L.make_params(150, 1, 32, "default", "fp16", reduced=True)
+    assert lib.rm_encode_reference_learned(0x1000, 20_000, R(red), 0x3000, 0x10000, 1 << 30,
+                                           R(out), None) == L.RM_EUNSUPPORTED

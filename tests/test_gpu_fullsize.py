@@ -34,7 +34,7 @@ import synth
 from oracle import learned as OL
 from oracle import lev, mapping, rope
 
-from gpu_helpers import fp8_bound, torch_cuda
+from gpu_helpers import fp8_bound, stored_form, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +44,7 @@ TAU = mapping.TIE_TAU
 
 
 def _rows(index, rows, torch):
-    """Dequantised complex rows [len(rows), 128] of the stored index."""
+    """Dequantised complex rows [len(rows), components] of the stored index."""
     r = torch.from_numpy(np.asarray(rows, dtype=np.int64)).cuda()
     e = index.embeddings()[r]
     if e.dtype == torch.uint8:
@@ -63,6 +63,8 @@ def _oracle_rows(ref, starts, N):
 def _check_index_rows(index, ref, rows, N, precision, torch):
     got = _rows(index, rows, torch)
     want, n2 = _oracle_rows(ref, rows, N)
+    want = stored_form(want, index)
+    assert got.shape == want.shape
     norms = index.norms2()[torch.from_numpy(np.asarray(rows)).cuda()].cpu().numpy()
     assert np.max(np.abs(norms / n2 - 1)) <= 2e-4
     if precision == "fp16":

@@ -9,8 +9,8 @@ import pytest
 
 import synth
 from oracle import mapping, rope
-from tests.gpu_helpers import (assert_lists_exact, emb_to_complex, fp8_bound, oracle_heads, oracle_windows,
-                               read_rows, torch_cuda)
+from tests.gpu_helpers import (assert_lists_exact, emb_to_complex, fp8_bound, interleave,
+                               oracle_heads, oracle_windows, read_rows, stored_form, torch_cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -116,14 +116,21 @@ def test_letter_sum_identity_on_device():
     assert np.max(np.abs(got.sum(axis=2))) < 5e-5
 
 
-@pytest.mark.parametrize("precision", ["fp16", "fp8"])
-def test_quantised_encodings(precision, plain_data, plain_oracle):
+@pytest.mark.parametrize("precision,reduced", [("fp16", False), ("fp16", True), ("fp8", False),
+                                               ("fp8", True)])
+def test_quantised_encodings(precision, reduced, plain_data, plain_oracle):
+    """Stored FP16/FP8 window rows against the oracle's vectors, in the full
+    form and in the letter-sum form (the oracle's vectors projected on the
+    letter-sum basis)."""
     torch = torch_cuda()
     ref, _, _ = plain_data
     Cn, n2, _, _ = plain_oracle
-    index = _build(ref, precision)
+    index = _build(ref, precision, reduced=reduced)
     torch.cuda.synchronize()
+    assert bool(index.params.reduced) == reduced
     got = emb_to_complex(index, torch)
+    Cn = stored_form(Cn, index)
+    assert got.shape == Cn.shape
     if precision == "fp16":
         # half an FP16 ulp (2^-11 relative) plus the FP32 rolling error
         assert np.all(np.abs(got.real - Cn.real) <= 2.0 ** -11 * np.abs(Cn.real) + 2e-5)
@@ -151,8 +158,7 @@ def test_quantised_encodings(precision, plain_data, plain_oracle):
         # bytes equal torch's RNE cast of the oracle value, up to one code where
         # the FP32 rolling value and the FP64 value straddle a rounding boundary
         q = index.embeddings().cpu().numpy().astype(np.int32)
-        inter = np.empty((Cn.shape[0], 256))
-        inter[:, 0::2], inter[:, 1::2] = Cn.real, Cn.imag
+        inter = interleave(Cn)
         import torch as T
         want = T.from_numpy(np.clip(inter / s, -448, 448)).to(T.float8_e4m3fn).view(T.uint8)
         want = want.numpy().astype(np.int32)
@@ -166,21 +172,22 @@ def test_quantised_encodings(precision, plain_data, plain_oracle):
         assert np.mean(diff == 0) > 0.999
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp8"])
-def test_read_encoder(precision, plain_data):
+@pytest.mark.parametrize("precision,reduced", [("fp32", False), ("fp16", False), ("fp16", True),
+                                               ("fp8", False), ("fp8", True)])
+def test_read_encoder(precision, reduced, plain_data):
     from paper_2603_22245_amd import mapper
     torch = torch_cuda()
     ref, reads, heads = plain_data
-    index = _build(ref, precision)
+    index = _build(ref, precision, reduced=reduced)
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
     mapper.encode_reads(index, rb)
     torch.cuda.synchronize()
     re_row, im_row = read_rows(rb, precision, torch)
     Xn, _ = oracle_heads(heads, 150)
-    want_re = np.empty((reads.n, 256))
-    want_re[:, 0::2], want_re[:, 1::2] = Xn.real, Xn.imag
-    want_im = np.empty((reads.n, 256))
-    want_im[:, 0::2], want_im[:, 1::2] = -Xn.imag, Xn.real
+    Xn = stored_form(Xn, index)
+    want_re = interleave(Xn)
+    want_im = interleave(1j * Xn)           # (-Im x, Re x) per component
+    assert re_row.shape == want_re.shape
     s = np.exp2(np.round(np.log2(rb.scale.cpu().numpy())))[:, None]
 
     def bound(w):
@@ -213,14 +220,19 @@ def _check_candidates(idx, score, F, tol, absolute=False):
     return frac
 
 
-@pytest.mark.parametrize("precision,k_fetch", [("fp32", 8), ("fp16", 8), ("fp16", 16),
-                                               ("fp16", 32), ("fp8", 16), ("fp8", 32),
-                                               ("fp32", 32)])
-def test_score_topk_and_rescore(precision, k_fetch, plain_data, plain_oracle):
+@pytest.mark.parametrize("precision,k_fetch,reduced", [
+    ("fp32", 8, None), ("fp16", 8, None), ("fp16", 16, None), ("fp16", 32, None), ("fp8", 16, None),
+    ("fp8", 32, None), ("fp32", 32, None), ("fp16", 16, False), ("fp16", 32, False),
+    ("fp8", 16, True), ("fp8", 32, True)])
+def test_score_topk_and_rescore(precision, k_fetch, reduced, plain_data, plain_oracle):
+    """The product's candidates and the rescored lists against the oracle; FP16
+    and FP8 indexes in the letter-sum form (FP16's default for letters) and in
+    the full form (FP8's default)."""
     torch = torch_cuda()
     ref, reads, heads = plain_data
     _, _, _, F = plain_oracle
-    index = _build(ref, precision)
+    index = _build(ref, precision, reduced=reduced)
+    assert bool(index.params.reduced) == (reduced is True or (reduced is None and precision == "fp16"))
     k = 8
     rb, bufs = _map(index, reads, k, k_fetch)
     cidx = bufs.cand_idx.cpu().numpy()
@@ -347,6 +359,7 @@ def test_largest_window_length(precision):
     got = emb_to_complex(index, torch)[rows]
     want = np.stack([rope.encode_raw(ref[j:j + N], N, 32) for j in rows])
     wn, n2 = mapping.normalized_rows(want, N)
+    wn = stored_form(wn, index)
     # FP32 rolling error; FP16 adds half an ulp (2^-11 relative)
     rel = 1e-5 if precision == "fp32" else 2.0 ** -11
     for part in (np.real, np.imag):
