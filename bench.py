@@ -57,13 +57,15 @@ def score_source_digest(sources=SCORE_SOURCES) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, precision: str, tokens=None):
+def measured_traffic(workload: str, precision: str, tokens=None, row_reals=None):
     """HBM bytes per scoring launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE of a rocprofv3 --pmc run of this benchmark on
     this workload, scaled by a plain copy's readings), or None when there is no
-    summary for this workload, precision and encoding, or the kernel sources
-    changed since it was taken.  tokens: None (letters, score_topk_kernel) or
-    the name of a 1,024-component token encoding (score_wide_kernel)."""
+    summary for this workload, precision and encoding, the summary was taken
+    with another row length (row_reals, when given: 256, or 192 for the
+    letter-sum form), or the kernel sources changed since it was taken.
+    tokens: None (letters, score_topk_kernel) or the name of a 1,024-component
+    token encoding (score_wide_kernel)."""
     if tokens is None:
         name, sources = f"score_topk_{precision}_{workload}_traffic.txt", SCORE_SOURCES
     else:
@@ -77,6 +79,8 @@ def measured_traffic(workload: str, precision: str, tokens=None):
     except (IndexError, ValueError):
         return None
     if d.get("source_sha256") != score_source_digest(sources):
+        return None
+    if row_reals is not None and d.get("row_reals", 256) != row_reals:
         return None
     return d.get("bytes_per_launch")
 
@@ -106,6 +110,9 @@ def parse():
                          "s8c256 | s4f128 (default: the letter encoding)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison step")
+    ap.add_argument("--letter-sum", choices=("auto", "on", "off"), default="auto",
+                    help="row form of the headline index: the library's choice (the "
+                         "letter-sum form for FP16 letter indexes), or forced on / off")
     ap.add_argument("--no-fp8-letter-sum", action="store_true",
                     help="skip the FP8 leg in the letter-sum form")
     ap.add_argument("--no-fp8", action="store_true",
@@ -205,7 +212,8 @@ def main():
     wide = bool(tok) and tok["n_class"] * tok["n_freq"] != 128
 
     run = run_map(args, w, ref, reads, precision, k, k_fetch, stride, radius, tok,
-                  args.steps, args.warmup)
+                  args.steps, args.warmup,
+                  reduced={"auto": None, "on": True, "off": False}[args.letter_sum])
     W, parts, ms_per_step, value = run["W"], run["parts"], run["ms_per_step"], run["value"]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "reads/s", "n_gpus": 1,
@@ -355,7 +363,8 @@ def run_map(args, w, ref, reads, precision, k, k_fetch, stride, radius, tok, ste
     enc_bytes = W * (real_dim * {"fp32": 4, "fp16": 2, "fp8": 1}[precision] + 8) + ref_len
     traffic = None
     if R == w.n_reads and not coarse and (not tok or wide):
-        traffic = measured_traffic(w.name, precision, args.tokens)
+        traffic = measured_traffic(w.name, precision, args.tokens,
+                                   None if args.tokens else real_dim)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": ("score_wide_kernel (+merge_wide_kernel)" if wide

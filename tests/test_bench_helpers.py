@@ -79,6 +79,8 @@ def test_traffic_is_read_only_for_the_current_kernel_sources(tmp_path, monkeypat
     assert bench.measured_traffic("precision", "fp16") == 123
     assert bench.measured_traffic("scale", "fp16") is None       # another workload's summary
     assert bench.measured_traffic("precision", "fp8") is None    # another precision's
+    assert bench.measured_traffic("precision", "fp16", row_reals=256) == 123  # summaries default to 256
+    assert bench.measured_traffic("precision", "fp16", row_reals=192) is None  # another row form
     (tmp_path / bench.SCORE_SOURCES[0]).write_text("kernel v2")
     assert bench.measured_traffic("precision", "fp16") is None   # kernel changed
 
