@@ -78,7 +78,8 @@ extern "C" {
 #define RM_MAX_MER 8       /* longest token (s-mer) of a token encoding */
 #define RM_TOKEN_SKIP 255  /* token-map value of an s-mer that adds nothing */
 #define RM_MAX_WINDOW 16384 /* largest supported N */
-#define RM_MAX_KFETCH 32   /* largest candidate list per read */
+#define RM_MAX_KFETCH 64   /* largest candidate list per read */
+#define RM_WIDE_MAX_KFETCH 32  /* ... with a 1,024-component token encoding */
 
 /* Parameters of an index.  Plain data; zero-initialise and fill. */
 typedef struct rm_params {

@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rotormap.h")
 RM_OK, RM_EINVAL, RM_ESIZE, RM_EUNSUPPORTED, RM_EHIP = 0, -1, -2, -3, -4
 RM_FP32, RM_FP16, RM_FP8_E4M3 = 0, 1, 2
 RM_SCHED_DEFAULT, RM_SCHED_FINETUNED = 0, 1
-RM_DIM, RM_MAX_WINDOW, RM_MAX_KFETCH = 32, 16384, 32
+RM_DIM, RM_MAX_WINDOW, RM_MAX_KFETCH, RM_WIDE_MAX_KFETCH = 32, 16384, 64, 32
 RM_NOALLOC_SCRATCH_BYTES = 256 << 20
 RM_MAX_MER, RM_TOKEN_SKIP, RM_MAX_FREQUENT = 8, 255, 128
 PRECISIONS = {"fp32": RM_FP32, "fp16": RM_FP16, "fp8": RM_FP8_E4M3}

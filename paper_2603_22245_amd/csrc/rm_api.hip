@@ -289,7 +289,8 @@ int rm_encode_reads_learned(const rm_index* idx, const uint8_t* d_seq, const int
 
 size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_fetch) {
   if (idx != nullptr && wide_encoding(&idx->p)) {
-    if (index_ok(idx) != RM_OK || n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return 0;
+    if (index_ok(idx) != RM_OK || n_reads < 1 || k_fetch < 1 || k_fetch > RM_WIDE_MAX_KFETCH)
+      return 0;
     return rm::wide_workspace_bytes(n_reads, idx->n_windows, k_fetch);
   }
   return rm_score_groups_workspace_bytes(idx, 1, &n_reads, k_fetch, nullptr);
@@ -303,7 +304,7 @@ int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_re
     if (st != RM_OK) return st;
     if (!d_read_emb || !d_cand_idx || !d_cand_score || !d_ws) return RM_EINVAL;
     if (idx->p.precision == RM_FP8_E4M3 && !d_read_scale) return RM_EINVAL;
-    if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_MAX_KFETCH) return RM_ESIZE;
+    if (n_reads < 1 || k_fetch < 1 || k_fetch > RM_WIDE_MAX_KFETCH) return RM_ESIZE;
     if (ws_bytes < rm::wide_workspace_bytes(n_reads, idx->n_windows, k_fetch)) return RM_ESIZE;
     return hip_status(rm::launch_score_wide(*idx, d_read_emb, d_read_scale, n_reads, k_fetch,
                                             d_cand_idx, d_cand_score, d_ws,

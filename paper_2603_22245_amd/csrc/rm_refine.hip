@@ -242,9 +242,11 @@ hipError_t launch_refine(const rm_index& coarse, const uint8_t* ref, const uint8
 
 hipError_t launch_refine_select(const uint64_t* pool, int n, int32_t n_reads, int32_t k,
                                 int32_t* top_idx, float* top_score, hipStream_t s) {
-  // n = k_fetch (2 radius + 1) <= 32 x 63 keys per read
-  auto kern = n <= 512 ? refine_select_kernel<8> : n <= 1024 ? refine_select_kernel<16>
-                                                             : refine_select_kernel<32>;
+  // n = k_fetch (2 radius + 1) <= 64 x 63 keys per read
+  auto kern = n <= 512    ? refine_select_kernel<8>
+              : n <= 1024 ? refine_select_kernel<16>
+              : n <= 2048 ? refine_select_kernel<32>
+                          : refine_select_kernel<64>;
   hipLaunchKernelGGL(kern, dim3((unsigned)(((int64_t)n_reads + 3) / 4)), dim3(256), 0, s, pool, n,
                      n_reads, k, top_idx, top_score);
   return hipGetLastError();

@@ -89,8 +89,10 @@ __device__ __forceinline__ void sort_and_write(uint64_t key, int lane, int64_t r
 }
 
 // Plain rescore, one wavefront per read (four per block).  Strings: s = 0 is
-// the read head, s = 1 .. k_fetch the candidates; RB blocks of 32 rows hold
-// the rows (s, L), row = 4 s + L, for s < 8 RB.  Per step of two positions
+// the read head, s = 1 .. k_fetch the candidates, taken in passes of 8 RB:
+// RB blocks of 32 rows hold the rows (s, L), row = 4 (s - s0) + L, of the
+// pass's strings s0 .. s0 + 8 RB - 1 (the head, in the first pass, stays in
+// registers for the later ones).  Per step of two positions
 // p, p+1 a lane contributes A[row = lane % 32][p + lane / 32] = [letter == L]
 // and B[p + lane / 32][col = lane % 32] = table reals (2 factor + re/im), for
 // the two 32-column blocks of the 64 table reals.
@@ -109,90 +111,94 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
   if (r >= R) return;  // whole wavefront
   uint8_t(*letters)[64] = letters_all[wave];
   float(*mat)[2 * kM + 1] = mat_all[wave];
-  const int S = 1 + k_fetch;  // <= SMAX
+  const int S = 1 + k_fetch;
   const int64_t start = off[r];
   const bool head_ok = off[r + 1] - start >= N;
   const int half = lane >> 5, col = lane & 31;
-
-  f32x16 acc[RB][2];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = f32x16{};
-
-  for (int pb = 0; pb < N; pb += 64) {
-    // stage the 64 letters of every string at positions pb .. pb+63 (255 =
-    // none: past N, a short head or an invalid candidate)
-    for (int sx = 0; sx < S; ++sx) {
-      const uint8_t* base = nullptr;
-      if (sx == 0) {
-        if (head_ok) base = seq + start;
-      } else {
-        const int32_t j = cand[r * k_fetch + sx - 1];
-        if (j >= 0 && j < W) base = ref + (int64_t)j * stride;
-      }
-      letters[sx][lane] = (base != nullptr && pb + lane < N) ? base[pb + lane] : (uint8_t)255;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int steps = min(32, (N - pb + 1) >> 1);
-    for (int t = 0; t < steps; ++t) {
-      const int pl = 2 * t + half;
-      const int pos = pb + pl;
-      const bool inb = pos < N;
-      float b[2];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) b[cb] = inb ? tab[(int64_t)pos * (2 * kM) + cb * 32 + col] : 0.f;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int row = rb * 32 + col;
-        const int sx = row >> 2;
-        const float a = (sx < S && letters[sx][pl] == (row & 3)) ? 1.f : 0.f;
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[cb], acc[rb][cb], 0, 0, 0);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();  // every lane is done with this chunk's letters
-  }
-
-  // ---- per string: components of this lane (factor kf, letters 2h, 2h+1)
   const int kf = lane >> 1, h = lane & 1;
   float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
   float X = 0.f;
   bool xdeg = true;
   uint64_t mykey = 0;
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    // result block: lane holds column cb*32 + col of rows 8 (v/4) + 4 half + v%4
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) mat[8 * (v >> 2) + 4 * half + (v & 3)][cb * 32 + col] = acc[rb][cb][v];
-    __builtin_amdgcn_wave_barrier();
-    for (int sl = 0; sl < 8; ++sl) {
-      const int sx = rb * 8 + sl;
-      if (sx >= S) break;
-      const float2 c0 = make_float2(mat[4 * sl + 2 * h][2 * kf], mat[4 * sl + 2 * h][2 * kf + 1]);
-      const float2 c1 = make_float2(mat[4 * sl + 2 * h + 1][2 * kf], mat[4 * sl + 2 * h + 1][2 * kf + 1]);
-      if (sx == 0) {
-        x0 = c0;
-        x1 = c1;
-        X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
-        xdeg = X < kDegenerateRel * (float)N;
-        continue;
+
+  for (int s0 = 0; s0 < S; s0 += SMAX) {
+    const int SP = min(SMAX, S - s0);  // strings of this pass
+    f32x16 acc[RB][2];
+  #pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = f32x16{};
+
+    for (int pb = 0; pb < N; pb += 64) {
+      // stage the 64 letters of every string at positions pb .. pb+63 (255 =
+      // none: past N, a short head or an invalid candidate)
+      for (int sl = 0; sl < SP; ++sl) {
+        const int sx = s0 + sl;
+        const uint8_t* base = nullptr;
+        if (sx == 0) {
+          if (head_ok) base = seq + start;
+        } else {
+          const int32_t j = cand[r * k_fetch + sx - 1];
+          if (j >= 0 && j < W) base = ref + (int64_t)j * stride;
+        }
+        letters[sl][lane] = (base != nullptr && pb + lane < N) ? base[pb + lane] : (uint8_t)255;
       }
-      const int e = sx - 1;
-      const int32_t j = cand[r * k_fetch + e];
-      if (j < 0 || j >= W) continue;  // uniform: stays an empty key
-      const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
-      // <x|c> = sum conj(x) c
-      const float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
-      const float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
-      const bool deg = xdeg || C < kDegenerateRel * (float)N;
-      const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
-      const uint32_t hi = __float_as_uint(F) + 1u;
-      if (lane == e) mykey = ((uint64_t)hi << 32) | (0xffffffffu - (uint32_t)j);
+      __builtin_amdgcn_wave_barrier();
+      const int steps = min(32, (N - pb + 1) >> 1);
+      for (int t = 0; t < steps; ++t) {
+        const int pl = 2 * t + half;
+        const int pos = pb + pl;
+        const bool inb = pos < N;
+        float b[2];
+  #pragma unroll
+        for (int cb = 0; cb < 2; ++cb) b[cb] = inb ? tab[(int64_t)pos * (2 * kM) + cb * 32 + col] : 0.f;
+  #pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int row = rb * 32 + col;
+          const int sl = row >> 2;
+          const float a = (sl < SP && letters[sl][pl] == (row & 3)) ? 1.f : 0.f;
+  #pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[cb], acc[rb][cb], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();  // every lane is done with this chunk's letters
     }
-    __builtin_amdgcn_wave_barrier();  // before the next block overwrites mat
-  }
+
+    // ---- per string: components of this lane (factor kf, letters 2h, 2h+1)
+  #pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      // result block: lane holds column cb*32 + col of rows 8 (v/4) + 4 half + v%4
+  #pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+  #pragma unroll
+        for (int v = 0; v < 16; ++v) mat[8 * (v >> 2) + 4 * half + (v & 3)][cb * 32 + col] = acc[rb][cb][v];
+      __builtin_amdgcn_wave_barrier();
+      for (int sl = 0; sl < 8; ++sl) {
+        const int sx = s0 + rb * 8 + sl;
+        if (rb * 8 + sl >= SP) break;
+        const float2 c0 = make_float2(mat[4 * sl + 2 * h][2 * kf], mat[4 * sl + 2 * h][2 * kf + 1]);
+        const float2 c1 = make_float2(mat[4 * sl + 2 * h + 1][2 * kf], mat[4 * sl + 2 * h + 1][2 * kf + 1]);
+        if (sx == 0) {
+          x0 = c0;
+          x1 = c1;
+          X = wave_sum(x0.x * x0.x + x0.y * x0.y + x1.x * x1.x + x1.y * x1.y);
+          xdeg = X < kDegenerateRel * (float)N;
+          continue;
+        }
+        const int e = sx - 1;
+        const int32_t j = cand[r * k_fetch + e];
+        if (j < 0 || j >= W) continue;  // uniform: stays an empty key
+        const float C = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+        // <x|c> = sum conj(x) c
+        const float ipr = wave_sum(x0.x * c0.x + x0.y * c0.y + x1.x * c1.x + x1.y * c1.y);
+        const float ipi = wave_sum(x0.x * c0.y - x0.y * c0.x + x1.x * c1.y - x1.y * c1.x);
+        const bool deg = xdeg || C < kDegenerateRel * (float)N;
+        const float F = deg ? 0.f : (ipr * ipr + ipi * ipi) / (X * C);
+        const uint32_t hi = __float_as_uint(F) + 1u;
+        if (lane == e) mykey = ((uint64_t)hi << 32) | (0xffffffffu - (uint32_t)j);
+      }
+      __builtin_amdgcn_wave_barrier();  // before the next block overwrites mat
+    }
+  }  // passes
   sort_and_write(mykey, lane, r, k, top_idx, top_score);
 }
 
@@ -340,8 +346,8 @@ hipError_t launch_rescore(const rm_index& idx, const uint8_t* ref, const uint8_t
                           const int32_t* cand_idx, int32_t k, int32_t* top_idx, float* top_score,
                           hipStream_t s, const float* ref_delta, const float* read_delta) {
   if (ref_delta == nullptr) {
-    // rows 4 (1 + k_fetch) in blocks of 32; k_fetch <= RM_MAX_KFETCH = 32
-    const int rb = (1 + k_fetch + 7) / 8;
+    // rows 4 (1 + k_fetch) in blocks of 32, at most 5 blocks (40 strings) a pass
+    const int rb = min(5, (1 + k_fetch + 7) / 8);
     auto kern = rb <= 1 ? rescore_mfma_kernel<1> : rb == 2 ? rescore_mfma_kernel<2>
               : rb == 3 ? rescore_mfma_kernel<3> : rb == 4 ? rescore_mfma_kernel<4>
                                                   : rescore_mfma_kernel<5>;

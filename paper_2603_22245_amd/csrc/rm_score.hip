@@ -83,7 +83,9 @@ hipError_t dispatch_f8(int read_tile, int kp, const ScoreLaunch& L, hipStream_t 
   switch (kp) {
     case 8: return launch_persistent<RM_FP8_E4M3, 1, 8, 32, 4, 1, KR>(L, s);
     case 16: return launch_persistent<RM_FP8_E4M3, 1, 16, 32, 4, 1, KR>(L, s);
-    default: return launch_persistent<RM_FP8_E4M3, 1, 32, 64, 4, 1, KR>(L, s);
+    case 32: return launch_persistent<RM_FP8_E4M3, 1, 32, 64, 4, 1, KR>(L, s);
+    // 64-key lists with a 32-slot buffer: 96 KB of lists
+    default: return launch_persistent<RM_FP8_E4M3, 1, 64, 96, 4, 1, KR>(L, s);
   }
 }
 
@@ -93,7 +95,9 @@ hipError_t dispatch(int precision, bool reduced, int read_tile, int kp, const Sc
     switch (kp) {
       case 8: return launch_persistent<RM_FP32, 1, 8, 32, 3>(L, s);
       case 16: return launch_persistent<RM_FP32, 1, 16, 32, 3>(L, s);
-      default: return launch_persistent<RM_FP32, 1, 32, 64, 2>(L, s);
+      case 32: return launch_persistent<RM_FP32, 1, 32, 64, 2>(L, s);
+      // 64-key lists with a 16-slot buffer (80 KB) and two 32 KB stages
+      default: return launch_persistent<RM_FP32, 1, 64, 80, 2>(L, s);
     }
   }
   if (precision == RM_FP16) return dispatch_score_f16(read_tile, kp, reduced, L, s);
@@ -105,7 +109,7 @@ hipError_t dispatch(int precision, bool reduced, int read_tile, int kp, const Sc
 
 bool read_tile_ok(int precision, int kp, int read_tile) {
   if (read_tile == 128) return true;
-  if (read_tile == 256) return precision != RM_FP32;
+  if (read_tile == 256) return precision != RM_FP32 && kp <= 32;  // 64-key lists: 128 reads
   return false;
 }
 
@@ -114,7 +118,7 @@ static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_t* R, int k_fetch,
                      Tuning t) {
   ScorePlan p{};
-  p.kp = k_fetch <= 8 ? 8 : k_fetch <= 16 ? 16 : 32;
+  p.kp = k_fetch <= 8 ? 8 : k_fetch <= 16 ? 16 : k_fetch <= 32 ? 32 : 64;
   int rt = t.read_tile;
   if (rt == 0) rt = read_tile_ok(precision, p.kp, 256) ? 256 : 128;
   if (!read_tile_ok(precision, p.kp, rt) || n_groups < 1 || n_groups > kMaxGroups) return p;

@@ -23,7 +23,10 @@ hipError_t dispatch_f16(int read_tile, int kp, const ScoreLaunch& L, hipStream_t
   switch (kp) {
     case 8: return launch_persistent<RM_FP16, 1, 8, 32, 4, 1, KR>(L, s);
     case 16: return launch_persistent<RM_FP16, 1, 16, 32, 4, 1, KR>(L, s);
-    default: return launch_persistent<RM_FP16, 1, 32, 64, 4, 1, KR>(L, s);
+    case 32: return launch_persistent<RM_FP16, 1, 32, 64, 4, 1, KR>(L, s);
+    // 64-key lists with a 32-slot buffer: 96 KB of lists leave room for three
+    // stages
+    default: return launch_persistent<RM_FP16, 1, 64, 96, 3, 1, KR>(L, s);
   }
 }
 

@@ -110,6 +110,33 @@ __device__ __noinline__ void slot_bounds(const uint64_t* __restrict__ gslot, int
   __builtin_amdgcn_wave_barrier();
 }
 
+// Sort 128 keys descending, two per lane: element lane + 64 e is k[e] (the
+// same bitonic network over 128 elements; its distance-64 steps compare the
+// lane's own two keys).
+__device__ __forceinline__ void sort_desc128(uint64_t& k0, uint64_t& k1, int lane) {
+#pragma unroll
+  for (int kk = 2; kk <= 128; kk <<= 1) {
+#pragma unroll
+    for (int d = kk >> 1; d > 0; d >>= 1) {
+      if (d == 64) {  // only at kk = 128, where every block is descending
+        const uint64_t mx = k0 > k1 ? k0 : k1, mn = k0 > k1 ? k1 : k0;
+        k0 = mx;
+        k1 = mn;
+        continue;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        uint64_t& key = e ? k1 : k0;
+        const int i = lane + 64 * e;
+        const uint64_t other = shfl_xor64(key, d);
+        const bool keep_max = ((i & d) == 0) == ((i & kk) == 0);
+        const uint64_t mx = key > other ? key : other, mn = key > other ? other : key;
+        key = keep_max ? mx : mn;
+      }
+    }
+  }
+}
+
 template <int PREC>
 struct Prec;
 template <>
@@ -303,14 +330,14 @@ struct ScoreKernel {
   static constexpr int CB = ENT - KP;                   // buffer slots per read
   // lanes of the bitonic merge of one read's list and buffer (ENT rounded up
   // to a power of two; lanes past ENT sort empty keys)
-  static constexpr int SW = ENT <= 32 ? 32 : 64;
+  static constexpr int SW = ENT <= 32 ? 32 : ENT <= 64 ? 64 : 128;
   // one block barrier per GRP tiles; copies run LEAD tiles ahead.  FP8
   // tiles carry twice the epilogue work per MFMA cycle of FP16 ones, and
   // halving their barriers pays (2%); for FP16 it costs 2.5%.
   static constexpr int GRP = PREC == RM_FP8_E4M3 && STAGES >= 4 ? 2 : 1;
   static constexpr int LEAD = STAGES - GRP;
   static_assert(C >= 1 && TILE % 1024 == 0, "tile");
-  static_assert(CB >= 1 && ENT <= 64, "buffer");
+  static_assert(CB >= 1 && ENT <= 128 && KP <= 64, "buffer");
   static_assert(NF * 16 <= 64, "a wavefront's reads are addressed by 64-bit lane masks");
   static_assert(NF * NB * 8 <= 64, "pending hits are 64-bit masks of (block, fragment, row pair)");
   static_assert(kPlanW % TW == 0, "chunks hold whole tiles");
@@ -361,7 +388,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
   }
 
   // ---- the read's slot bound is the chunk's first threshold
-  slot_bounds<NF, KP>(gslot, read0 + rb0, R, lane, thr + rb0);
+  if constexpr (KP <= kScoreSlots) slot_bounds<NF, KP>(gslot, read0 + rb0, R, lane, thr + rb0);
 
   // ---- A fragments: this lane's K half of row (read tile row) for each fragment
   uint4 a[NF][K::AU4];
@@ -478,8 +505,37 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
     __builtin_amdgcn_s_waitcnt(0x0F70);
   };
 
+  // the merged list's k-th best becomes the chunk's threshold and is published:
+  // no window scoring below it can be in the read's final list, whichever
+  // chunk holds it
+  auto take_kth = [&](int my, uint64_t key) {
+    const int rb = rb0 + my;
+    float kth = key_score(key);
+    thr[rb] = fmaxf(thr[rb], kth);
+    const int64_t r = gread(my);
+    if (kth >= 0.f && r < R) atomicMax(&gthr[r], __float_as_uint(kth) + 1u);
+  };
+
   // ---- merge a read's buffer into its list (whole wavefront, uniform call)
   auto merge_reads = [&](uint64_t mask) {
+    if constexpr (K::SW == 128) {  // one read at a time, two keys per lane
+      while (mask) {
+        const int my = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int rb = rb0 + my;
+        const int n = min(cnt[rb], K::CB);
+        uint64_t k0 = lane < KP + n ? lst[rb][lane] : 0;  // KP + n <= ENT
+        uint64_t k1 = lane + 64 < KP + n ? lst[rb][lane + 64] : 0;
+        sort_desc128(k0, k1, lane);
+        if (lane < KP) lst[rb][lane] = k0;
+        if (lane + 64 < KP) lst[rb][lane + 64] = k1;
+        if (lane == (KP - 1) % 64) take_kth(my, KP > 64 ? k1 : k0);
+        if (lane == 0) cnt[rb] = 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      refresh_thresholds();
+      return;
+    }
     // SW == 32: two reads at a time (one per half-wave); SW == 64: one read.
     while (mask) {
       int r0 = __builtin_ctzll(mask);
@@ -497,14 +553,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         uint64_t key = (id < KP + n) ? lst[rb][id] : 0;  // KP + n <= ENT
         key = sort_desc<K::SW>(key, lane);
         if (id < KP) lst[rb][id] = key;
-        if (id == KP - 1) {
-          float kth = key_score(key);
-          thr[rb] = fmaxf(thr[rb], kth);
-          // publish this chunk's k-th best: no window scoring below it can be
-          // in the read's final list, whichever chunk holds it
-          const int64_t r = gread(my);
-          if (kth >= 0.f && r < R) atomicMax(&gthr[r], __float_as_uint(kth) + 1u);
-        }
+        if (id == KP - 1) take_kth(my, key);
         if (id == 0) cnt[rb] = 0;
       }
     }
@@ -734,7 +783,7 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
         const uint64_t key = lst[rb0 + rr][e];
         ws[((int64_t)r * P + chunk) * KP + e] = key;
         // this chunk's windows join the read's slots for the chunks after it
-        if (key >> 32)
+        if (KP <= kScoreSlots && (key >> 32))
           atomicMax(reinterpret_cast<unsigned long long*>(
                         &gslot[r * kScoreSlots + ((~(uint32_t)key) & (kScoreSlots - 1))]),
                     (unsigned long long)key);

@@ -35,7 +35,7 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kTM = 64 * kWM;       // A rows per block tile (kTM / 2 reads)
 constexpr int kTN = 32 * kGN * kWN; // windows per block tile
 constexpr int kLine = 64;   // bytes of every row per K stage (32 FP16 or 64 FP8 elements)
-constexpr int kListMax = RM_MAX_KFETCH;
+constexpr int kListMax = RM_WIDE_MAX_KFETCH;
 constexpr int kGroupTiles = 8;   // read tiles per group of 32 blocks on one XCD
 constexpr int kGroupChunks = 4;  // window chunks per group
 

@@ -105,8 +105,16 @@ def test_read_score_rescore_validation():
     sc = lambda i, n, kf, nb: lib.rm_score_topk(R(i), 1, 1, n, kf, 1, 1, 1, nb, None)
     assert sc(idx, 100, 8, ws - 1) == L.RM_ESIZE
     assert sc(idx, 100, 0, ws) == L.RM_ESIZE
-    assert sc(idx, 100, 33, ws) == L.RM_ESIZE
+    assert sc(idx, 100, L.RM_MAX_KFETCH + 1, 1 << 40) == L.RM_ESIZE
+    assert L.rm_score_workspace_bytes(idx, 100, L.RM_MAX_KFETCH) > ws   # 64 candidates
     assert sc(idx, 0, 8, ws) == L.RM_ESIZE
+    # 1,024-component token encodings keep at most RM_WIDE_MAX_KFETCH candidates
+    wide = _fake_index()
+    wide.p = L.make_params(150, 1, 4, "default", "fp16", 0, 8, 256, 0x2000)
+    wide.d_token_class = 0x100000
+    assert L.rm_score_workspace_bytes(wide, 100, L.RM_WIDE_MAX_KFETCH) > 0
+    assert L.rm_score_workspace_bytes(wide, 100, L.RM_WIDE_MAX_KFETCH + 1) == 0
+    assert sc(wide, 100, L.RM_WIDE_MAX_KFETCH + 1, 1 << 40) == L.RM_ESIZE
     assert lib.rm_score_topk(R(idx), None, 1, 100, 8, 1, 1, 1, ws, None) == L.RM_EINVAL
     assert lib.rm_score_topk(R(idx8), 1, None, 100, 8, 1, 1, 1, 1 << 30, None) == L.RM_EINVAL
     # rescore
@@ -325,7 +333,7 @@ def test_noalloc_validation():
     assert lib.rm_score_topk_noalloc(None, 1, 1, 10, 8, 1, 1, None) == L.RM_EINVAL
     assert lib.rm_score_topk_noalloc(R(idx), None, 1, 10, 8, 1, 1, None) == L.RM_EINVAL
     assert lib.rm_score_topk_noalloc(R(idx), 1, 1, 0, 8, 1, 1, None) == L.RM_ESIZE
-    assert lib.rm_score_topk_noalloc(R(idx), 1, 1, 10, 33, 1, 1, None) == L.RM_ESIZE
+    assert lib.rm_score_topk_noalloc(R(idx), 1, 1, 10, L.RM_MAX_KFETCH + 1, 1, 1, None) == L.RM_ESIZE
     big = 4_000_000
     assert L.rm_score_workspace_bytes(idx, big, 32) > L.RM_NOALLOC_SCRATCH_BYTES
     assert lib.rm_score_topk_noalloc(R(idx), 1, 1, big, 32, 1, 1, None) == L.RM_ESIZE

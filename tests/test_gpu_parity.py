@@ -223,7 +223,8 @@ def _check_candidates(idx, score, F, tol, absolute=False):
 @pytest.mark.parametrize("precision,k_fetch,reduced", [
     ("fp32", 8, None), ("fp16", 8, None), ("fp16", 16, None), ("fp16", 32, None), ("fp8", 16, None),
     ("fp8", 32, None), ("fp32", 32, None), ("fp16", 16, False), ("fp16", 32, False),
-    ("fp8", 16, True), ("fp8", 32, True)])
+    ("fp8", 16, True), ("fp8", 32, True), ("fp16", 64, None), ("fp8", 64, None),
+    ("fp32", 64, None), ("fp16", 48, False), ("fp8", 64, True)])
 def test_score_topk_and_rescore(precision, k_fetch, reduced, plain_data, plain_oracle):
     """The product's candidates and the rescored lists against the oracle; FP16
     and FP8 indexes in the letter-sum form (FP16's default for letters) and in
@@ -253,6 +254,42 @@ def test_score_topk_and_rescore(precision, k_fetch, reduced, plain_data, plain_o
     print(f"{precision} k_fetch={k_fetch}: candidate recall@8 {rec_c:.4f}, "
           f"rescored recall@8 {rec:.4f}, exact lists {exact.mean():.4f}")
     assert np.max(np.abs(tsc - top_F)) < 2e-6            # FP32 rescore vs FP64
+    assert_lists_exact(exact, rec, k_fetch, k, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp8"])
+def test_sixty_four_candidates_and_long_lists(precision, plain_data, plain_oracle):
+    """64 product candidates (lists of 64 keys per chunk, merged two keys per
+    lane) rescored into top-48 lists (top-32 for FP8, whose product error needs
+    the usual two-fold over-fetch: with 48 of 64, 5 of the 200 lists missed a
+    window near rank 48): candidates are the product's own top-64, rescored
+    lists equal the oracle's up to ties."""
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    _, _, _, F = plain_oracle
+    index = _build(ref, precision)
+    k, k_fetch = (32 if precision == "fp8" else 48), 64
+    rb, bufs = _map(index, reads, k, k_fetch)
+    cidx = bufs.cand_idx.cpu().numpy()
+    csc = bufs.cand_score.cpu().numpy()
+    _check_candidates(cidx, csc, F, TOL[precision], absolute=precision == "fp8")
+    # every window the oracle scores clearly above the product's 64th entry is
+    # in the list (clearly: by more than twice the product's error)
+    f_c = np.take_along_axis(F, cidx, 1)
+    margin = {"fp32": 2e-5, "fp16": 2e-3, "fp8": 3e-2}[precision]
+    for r in range(F.shape[0]):
+        above = np.nonzero(F[r] > f_c[r].min() + margin)[0]
+        assert set(above.tolist()) <= set(cidx[r].tolist()), r
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    o_idx = order[:, :k]
+    o_F = np.take_along_axis(F, o_idx, 1)
+    tidx = bufs.top_idx.cpu().numpy()
+    top_F = np.take_along_axis(F, tidx, 1)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, top_F)
+    exact = mapping.same_up_to_ties(tidx, o_F, top_F)
+    print(f"{precision} top-{k} of {k_fetch}: recall {rec:.4f}, exact lists {exact.mean():.4f}")
+    assert np.max(np.abs(bufs.top_score.cpu().numpy() - top_F)) < 2e-6
     assert_lists_exact(exact, rec, k_fetch, k, precision)
 
 

@@ -28,17 +28,20 @@ def step1_oracle():
     return ref, reads, F1
 
 
-@pytest.mark.parametrize("precision,stride,radius", [("fp32", 2, 1), ("fp16", 4, 3),
-                                                     ("fp16", 8, 7), ("fp8", 4, 2),
-                                                     ("fp16", 16, 15), ("fp8", 16, 15),
-                                                     ("fp32", 32, 31)])
-def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
+@pytest.mark.parametrize("precision,stride,radius,k_fetch", [
+    ("fp32", 2, 1, 16), ("fp16", 4, 3, 16), ("fp16", 8, 7, 16), ("fp8", 4, 2, 16),
+    ("fp16", 16, 15, 16), ("fp8", 16, 15, 16), ("fp32", 32, 31, 16), ("fp16", 8, 7, 64),
+    ("fp16", 16, 15, 64), ("fp8", 16, 15, 64), ("fp16", 32, 31, 64), ("fp32", 16, 15, 48)])
+def test_coarse_index_then_refine(precision, stride, radius, k_fetch, step1_oracle):
+    """The refined lists of k_fetch coarse candidates (up to 64: pools of up
+    to 64 x 63 step-1 starts per read) against the oracle's refinement of the
+    same candidates; recall against every step-1 window."""
     from paper_2603_22245_amd import mapper
     torch = torch_cuda()
     ref, reads, F1 = step1_oracle
     index = mapper.build_index(ref, precision=precision, stride=stride)
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
-    bufs = mapper.map_buffers(index, reads.n, K, 16)
+    bufs = mapper.map_buffers(index, reads.n, K, k_fetch)
     mapper.map_reads_coarse(index, rb, bufs, radius)
     torch.cuda.synchronize()
     cand = bufs.cand_idx.cpu().numpy()
@@ -49,8 +52,8 @@ def test_coarse_index_then_refine(precision, stride, radius, step1_oracle):
     W1 = F1.shape[1]
     o_idx, o_F = mapping.topk_rows(F1, np.arange(W1), K)
     rec = mapping.recall_at_k(tidx, o_idx, o_F, np.take_along_axis(F1, tidx, 1))
-    print(f"{precision} stride {stride} radius {radius}: lists identical to the oracle's "
-          f"refinement {same:.3f}; recall@{K} vs all step-1 windows {rec:.4f}")
+    print(f"{precision} stride {stride} radius {radius} k_fetch {k_fetch}: lists identical to "
+          f"the oracle's refinement {same:.3f}; recall@{K} vs all step-1 windows {rec:.4f}")
     # the method's own recall (coarse candidates that miss a location cannot be
     # refined into it, and a radius below stride - 1 leaves gaps): measured
     # 0.9994, 0.983, 0.897 and 0.937 at strides 2, 4, 8 and 4 (radius 2); at
