@@ -207,7 +207,8 @@ size_t rm_score_workspace_bytes(const rm_index* idx, int32_t n_reads, int32_t k_
  * window id, exactly.  If W < k_fetch the tail is filled with id -1, score 0;
  * a read with no location (see the conventions) has id -1, score 0 throughout.
  * d_read_scale may be NULL unless the precision is FP8.
- * Errors: RM_EINVAL, RM_ESIZE (k_fetch outside 1..RM_MAX_KFETCH, ws too small). */
+ * Errors: RM_EINVAL, RM_ESIZE (k_fetch outside 1..RM_MAX_KFETCH -- 1..RM_WIDE_MAX_KFETCH
+ * for 1,024-component token encodings -- ws too small). */
 int rm_score_topk(const rm_index* idx, const void* d_read_emb, const float* d_read_scale,
                   int32_t n_reads, int32_t k_fetch, int32_t* d_cand_idx, float* d_cand_score,
                   void* d_ws, size_t ws_bytes, void* stream);
