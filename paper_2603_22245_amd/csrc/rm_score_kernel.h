@@ -8,14 +8,14 @@
 // F = Re^2 + Im^2 for unit vectors (times (s_r s_j)^2 for FP8 scales).
 //
 // Work item = (read tile, window chunk).  A block keeps its read tile in
-// registers (each wavefront owns NF fragments of 32 rows = 16 reads, the full
-// K = 256) and streams the chunk's windows through LDS in tiles of 32
-// (double-buffered).  Per tile every wavefront runs NF x (256/K_mfma) MFMAs
-// on 32x32 output blocks; the epilogue forms F per (read, window) in
-// registers, compares with the read's current k-th best and, only for hits,
-// appends (F, j) to the read's LDS buffer.  Full buffers are merged into the
-// read's sorted list by a bitonic sort across lanes.  The score matrix never
-// leaves registers.
+// registers (each wavefront owns NF fragments of 32 rows = 16 reads, over the
+// row's full K: 256 reals, or 192 in the letter-sum form) and streams the
+// chunk's windows through an LDS ring in tiles of 32 or 64.  Per tile every
+// wavefront runs NF x NB x (K/K_mfma) MFMAs on 32x32 output blocks; the
+// epilogue forms F per (read, window) in registers, compares with the read's
+// current k-th best and, only for hits, appends (F, j) to the read's LDS
+// buffer.  Full buffers are merged into the read's sorted list by a bitonic
+// sort across lanes.  The score matrix never leaves registers.
 //
 // List entries are 64-bit keys: high word = float bits of F plus one (0 means
 // empty), low word = ~j; a larger key is a better candidate (F descending,
