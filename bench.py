@@ -113,6 +113,8 @@ def parse():
     ap.add_argument("--letter-sum", choices=("auto", "on", "off"), default="auto",
                     help="row form of the headline index: the library's choice (the "
                          "letter-sum form for FP16 letter indexes), or forced on / off")
+    ap.add_argument("--no-fp32-letter-sum", action="store_true",
+                    help="skip the FP32 leg in the letter-sum form")
     ap.add_argument("--no-fp8-letter-sum", action="store_true",
                     help="skip the FP8 leg in the letter-sum form")
     ap.add_argument("--no-fp8", action="store_true",
@@ -121,6 +123,9 @@ def parse():
                     help="skip the batched leg of the default run")
     ap.add_argument("--no-threshold", action="store_true",
                     help="skip the threshold-regime leg of the default run")
+    ap.add_argument("--threshold-floor", type=float, default=0.1,
+                    help="second run of the threshold regime with this fidelity floor "
+                         "(the first has none)")
     ap.add_argument("--threshold-err", type=float, default=0.02,
                     help="threshold regime: target mutation rate of the per-window thresholds")
     ap.add_argument("--cpu-reads", type=int, default=None,
@@ -260,11 +265,18 @@ def main():
                         "error per score grows by about sqrt(4/3) in it"}
             low.append(("fp8_letter_sum_path", "fp8", r8s["value"]))
     if (not args.no_threshold and args.workload == "precision" and not tok and not coarse):
-        out["threshold_regime"] = threshold_leg(w, ref, reads, precision, args.threshold_err)
+        out["threshold_regime"] = threshold_leg(w, ref, reads, precision, args.threshold_err,
+                                                floors=(0.0, args.threshold_floor))
     if not args.no_fp32 and precision != "fp32" and not coarse and not wide:
         fp = fp32_path(w, ref, reads, k, k_fetch, tok)
         fp["speedup_of_low_precision"] = {name: round(v / fp["value"], 2) for name, _, v in low}
         out["fp32_path"] = fp
+        if not tok and not args.no_fp32_letter_sum:
+            # the same algorithm in FP32: the letter-sum rows the FP16 headline uses
+            fs = fp32_path(w, ref, reads, k, k_fetch, tok, reduced=True)
+            fs["speedup_of_low_precision"] = {name: round(v / fs["value"], 2)
+                                              for name, _, v in low}
+            out["fp32_letter_sum_path"] = fs
     if not args.no_cpu_baseline:
         n_cpu = args.cpu_reads or {"scale": 1000}.get(w.name, 2000)
         out["cpu_baseline"] = cpu_baseline(w, ref, reads, W, n_cpu, args.cpu_windows,
@@ -906,12 +918,15 @@ def location_clusters(ids, span):
     return int(1 + np.count_nonzero(np.diff(ids) > span))
 
 
-def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1):
+def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1, floors=(0.0,)):
     """§3.3 / §3.5: per-window thresholds at a target mutation rate (the
     rank-th smallest fidelity of `copies` mutated copies of each window), then
-    every location whose FP32 fidelity passes its window's threshold, for every
-    read.  Reports locations per read, the share mapped to exactly one, and the
-    share whose locations miss the read's true window (within 8 windows)."""
+    every location whose FP32 fidelity passes max(its window's threshold,
+    floor), for every read, once per floor.  Reports, per floor, windows and
+    distinct places per read, the share of reads with exactly one place, and the
+    share whose windows miss the read's true window (within 8 windows); and the
+    thresholds' low percentiles (a window whose mutated copies can lose their
+    alignment to net indels gets a threshold near 0, and every read passes it)."""
     import torch
     from paper_2603_22245_amd import mapper
     index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision=precision,
@@ -924,50 +939,60 @@ def threshold_leg(w, ref, reads, precision, err, copies=16, rank=1, seed=1):
     thr = mapper.window_thresholds(index, err, copies, rank, seed)
     ev[1].record()
     mapper.encode_reads(index, rb)
-    h = mapper.score_threshold(index, rb, thr)                          # sizes the capacity
     torch.cuda.synchronize()
-    ev[2].record()
-    h = mapper.score_threshold(index, rb, thr, capacity=h.capacity)
-    ev[3].record()
-    torch.cuda.synchronize()
-    thr_ms, regime_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
-    n = h.n_found.cpu().numpy()
-    lists = h.lists()
+    thr_ms = ev[0].elapsed_time(ev[1])
+    thr_h = thr.cpu().numpy()
     truth = reads.truth // w.stride
-    hit = np.array([np.any(np.abs(ids.astype(np.int64) - t) <= 8) for (ids, _), t in
-                    zip(lists, truth)])
     # at stride 1 a read passes the thresholds of many overlapping windows
     # around one place; count places: windows overlapping one another (ids
     # within a window length) are one location
     span = max(1, w.window_len // w.stride)
-    loc = np.array([location_clusters(ids, span) for ids, _ in lists])
-    thr_h = thr.cpu().numpy()
-    del index, rb, h, thr
+    runs = []
+    for floor in floors:
+        h = mapper.score_threshold(index, rb, thr, floor)                # sizes the capacity
+        torch.cuda.synchronize()
+        ev[2].record()
+        h = mapper.score_threshold(index, rb, thr, floor, capacity=h.capacity)
+        ev[3].record()
+        torch.cuda.synchronize()
+        regime_ms = ev[2].elapsed_time(ev[3])
+        n = h.n_found.cpu().numpy()
+        lists = h.lists()
+        hit = np.array([np.any(np.abs(ids.astype(np.int64) - t) <= 8) for (ids, _), t in
+                        zip(lists, truth)])
+        loc = np.array([location_clusters(ids, span) for ids, _ in lists])
+        del h
+        log(f"threshold regime, floor {floor}: {regime_ms:.1f} ms")
+        runs.append({"floor": floor, "regime_ms": round(regime_ms, 3),
+                     "reads_per_s": round(reads.n / (regime_ms / 1e3), 1),
+                     "windows_per_read": round(float(n.mean()), 3),
+                     "max_windows": int(n.max()),
+                     "locations_per_read": round(float(loc.mean()), 3),
+                     "max_locations": int(loc.max()),
+                     "mapped_to_one_location": round(float(np.mean(loc == 1)), 4),
+                     "unmapped": round(float(np.mean(n == 0)), 4),
+                     "missed_true_location": round(float(np.mean(~hit)), 4)})
+    del index, rb, thr
     torch.cuda.empty_cache()
-    log(f"threshold regime: {thr_ms:.1f} ms thresholds, {regime_ms:.1f} ms regime")
+    log(f"threshold regime: {thr_ms:.1f} ms thresholds")
     return {"target_err": err, "copies": copies, "rank": rank, "precision": precision,
-            "thresholds_ms": round(thr_ms, 3), "regime_ms": round(regime_ms, 3),
-            "reads_per_s": round(reads.n / (regime_ms / 1e3), 1),
-            "threshold_median": round(float(np.median(thr_h)), 4),
-            "windows_per_read": round(float(n.mean()), 3),
-            "max_windows": int(n.max()),
-            "locations_per_read": round(float(loc.mean()), 3),
-            "max_locations": int(loc.max()),
-            "mapped_to_one_location": round(float(np.mean(loc == 1)), 4),
-            "unmapped": round(float(np.mean(n == 0)), 4),
-            "missed_true_location": round(float(np.mean(~hit)), 4),
-            "note": "read heads + MFMA proposal pass + grouping + FP32 recompute of the "
-                    "proposals; thresholds timed separately"}
+            "thresholds_ms": round(thr_ms, 3),
+            "threshold_percentiles": {str(q): round(float(np.percentile(thr_h, q)), 4)
+                                      for q in (0.1, 1, 5, 50)},
+            "runs": runs,
+            "note": "regime: read heads encoded beforehand; MFMA proposal pass + grouping + "
+                    "FP32 recompute of the proposals; thresholds timed separately"}
 
 
-def fp32_path(w, ref, reads, k, k_fetch, tok=None):
+def fp32_path(w, ref, reads, k, k_fetch, tok=None, reduced=False):
     """Timed whole steps of the plain FP32 path: the same step (index build,
     read heads, product + top-k, FP32 rescore) with an FP32 index and the FP32
-    MFMA product."""
+    MFMA product; full rows, or with reduced=True the letter-sum form."""
     import torch
     from paper_2603_22245_amd import mapper, _lib as L
     index = mapper.build_index(ref, window_len=w.window_len, stride=w.stride, precision="fp32",
-                               reanchor=w.reanchor, **(tok or {}))
+                               reanchor=w.reanchor, reduced=reduced, **(tok or {}))
+    row_reals = index.real_dim
     rb = mapper.upload_reads(index, reads.seq, reads.offsets)
     bufs = mapper.map_buffers(index, reads.n, k, k_fetch)
     ref_len = int(ref.shape[0])
@@ -994,11 +1019,12 @@ def fp32_path(w, ref, reads, k, k_fetch, tok=None):
     acc = accuracy(w, reads, top_idx, top_score, cand_idx, cand_score, k, reads.n,
                    precision="fp32")
     return {"value": round(v, 1), "unit": "reads/s", "ms_per_step": round(dt * 1e3, 2),
-            "tflops": round(reads.n * W * FLOPS_PER_SCORE / dt / 1e12, 2),
+            "row_reals": row_reals,
+            "tflops": round(reads.n * W * 4 * row_reals / dt / 1e12, 2),
             "accuracy": {key: acc.get(key) for key in ("recall_at_k", "exact_lists_up_to_ties",
                                                        "sample_reads")},
-            "note": "index build + read encoding + FP32 MFMA product over the full rows "
-                    "(K = 256) + top-k + FP32 rescore"}
+            "note": f"index build + read encoding + FP32 MFMA product over rows of "
+                    f"{row_reals} reals + top-k + FP32 rescore (tflops over the whole step)"}
 
 
 def cpu_baseline(w, ref, reads, W, n_reads, n_windows, tokens_name=None):

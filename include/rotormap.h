@@ -110,8 +110,8 @@ typedef struct rm_params {
   const uint8_t* d_token_map; /* NULL, or DEVICE [4^s] class per s-mer code; read
                                  by rm_encode_reference only (copied into the
                                  index buffer) */
-  /* Letter-sum form (letter encoding, default schedule, FP16 or FP8 only;
-   * 0 otherwise).  With integer factors f_k = k < N (§2.2) the components of
+  /* Letter-sum form (letter encoding, default schedule, N > RM_DIM; 0
+   * otherwise).  With integer factors f_k = k < N (§2.2) the components of
    * factor k of a window sum over the four letters to sum_p omega^(k p) = 0,
    * since each location holds one letter: 1 stores every window and read head
    * by its coordinates on an orthonormal basis of that 3m-dimensional
@@ -172,7 +172,7 @@ size_t rm_index_bytes(int64_t ref_len, const rm_params* p);
  * != RM_DIM; token encoding with n_class odd or above 256, n_class * n_freq
  * neither 128 nor 1,024, 1,024 components with n_class not a multiple of 16
  * or an FP32 index, or no map and n_class != 4^s; the letter-sum form with
- * a token encoding, the fine-tuned schedule or an FP32 index). */
+ * a token encoding, the fine-tuned schedule or N <= RM_DIM). */
 int rm_encode_reference(const uint8_t* d_ref, int64_t ref_len, const rm_params* p,
                         void* d_buf, size_t buf_bytes, rm_index* out, void* stream);
 

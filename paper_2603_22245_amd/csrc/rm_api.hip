@@ -65,9 +65,9 @@ bool params_ok(const rm_params* p, int* why) {
   if (p->reanchor < 0) return (*why = RM_ESIZE), false;
   if (p->reduced != 0 && p->reduced != 1) return (*why = RM_EINVAL), false;
   // the letter-sum form: integer factors (f_k = k < N for every window of at
-  // least RM_DIM + 1 letters), letters, FP16 or FP8
+  // least RM_DIM + 1 letters), letters
   if (p->reduced && (!letter_encoding(p) || p->schedule != RM_SCHED_DEFAULT ||
-                     p->precision == RM_FP32 || p->window_len <= RM_DIM))
+                     p->window_len <= RM_DIM))
     return (*why = RM_EUNSUPPORTED), false;
   return true;
 }

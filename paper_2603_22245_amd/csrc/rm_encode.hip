@@ -614,7 +614,7 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
   int64_t blocks = (n_seg + waves - 1) / waves;
   auto* ph = reinterpret_cast<const double2*>(phase64);
   auto* st = reinterpret_cast<const float4*>(step32);
-  auto kern = encode_reference_kernel<RM_FP32, false>;
+  auto kern = p.reduced ? encode_reference_kernel<RM_FP32, true> : encode_reference_kernel<RM_FP32, false>;
   if (p.precision == RM_FP16)
     kern = p.reduced ? encode_reference_kernel<RM_FP16, true> : encode_reference_kernel<RM_FP16, false>;
   else if (p.precision == RM_FP8_E4M3)
@@ -631,7 +631,7 @@ hipError_t launch_encode_reads(const rm_params& p, const float* phase32, const u
   const int waves = 4;
   int64_t blocks = ((int64_t)n_reads + waves - 1) / waves;
   auto* ph = reinterpret_cast<const float2*>(phase32);
-  auto kern = encode_reads_kernel<RM_FP32, false>;
+  auto kern = p.reduced ? encode_reads_kernel<RM_FP32, true> : encode_reads_kernel<RM_FP32, false>;
   if (p.precision == RM_FP16)
     kern = p.reduced ? encode_reads_kernel<RM_FP16, true> : encode_reads_kernel<RM_FP16, false>;
   else if (p.precision == RM_FP8_E4M3)

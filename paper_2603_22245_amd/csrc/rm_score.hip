@@ -89,17 +89,21 @@ hipError_t dispatch_f8(int read_tile, int kp, const ScoreLaunch& L, hipStream_t 
   }
 }
 
+template <int KR>
+hipError_t dispatch_f32(int kp, const ScoreLaunch& L, hipStream_t s) {
+  switch (kp) {
+    case 8: return launch_persistent<RM_FP32, 1, 8, 32, 3, 1, KR>(L, s);
+    case 16: return launch_persistent<RM_FP32, 1, 16, 32, 3, 1, KR>(L, s);
+    case 32: return launch_persistent<RM_FP32, 1, 32, 64, 2, 1, KR>(L, s);
+    // 64-key lists with a 16-slot buffer (80 KB) and two stages of at most 32 KB
+    default: return launch_persistent<RM_FP32, 1, 64, 80, 2, 1, KR>(L, s);
+  }
+}
+
 hipError_t dispatch(int precision, bool reduced, int read_tile, int kp, const ScoreLaunch& L,
                     hipStream_t s) {
-  if (precision == RM_FP32) {
-    switch (kp) {
-      case 8: return launch_persistent<RM_FP32, 1, 8, 32, 3>(L, s);
-      case 16: return launch_persistent<RM_FP32, 1, 16, 32, 3>(L, s);
-      case 32: return launch_persistent<RM_FP32, 1, 32, 64, 2>(L, s);
-      // 64-key lists with a 16-slot buffer (80 KB) and two 32 KB stages
-      default: return launch_persistent<RM_FP32, 1, 64, 80, 2>(L, s);
-    }
-  }
+  if (precision == RM_FP32)
+    return reduced ? dispatch_f32<kRealReduced>(kp, L, s) : dispatch_f32<kReal>(kp, L, s);
   if (precision == RM_FP16) return dispatch_score_f16(read_tile, kp, reduced, L, s);
   return reduced ? dispatch_f8<kRealReduced>(read_tile, kp, L, s)
                  : dispatch_f8<kReal>(read_tile, kp, L, s);

@@ -178,13 +178,13 @@ __device__ __forceinline__ void wait_vmcnt() {
 
 // Row formats of the product.  A row holds KR reals: kReal = 256 for the
 // letter encoding (128 complex components), kRealReduced = 192 for its
-// letter-sum form (96 components; FP16 and FP8 only).  B tiles in LDS: row r
+// letter-sum form (96 components).  B tiles in LDS: row r
 // (one window, RB bytes) stores logical 16-byte chunk c at physical chunk
 // swap(r, c), a permutation keyed by r's low bits that makes the 16 rows read
 // together by one LDS access cycle (16 consecutive rows, the same logical
 // chunk) fall in 16 different bank groups (16-byte units mod 16):
-//  * 256 reals: c ^ (r & 15) (a row is a multiple of 256 B, so its physical
-//    chunk index mod 16 is c ^ (r & 15) itself);
+//  * 256 reals, and 192 reals in FP32 (768 B): c ^ (r & 15) (a row is a
+//    multiple of 256 B, so its physical chunk index mod 16 is c ^ (r & 15));
 //  * 192 reals, FP16 (24 chunks = 384 B, rows alternate between bank-group
 //    offsets 0 and 8): chunks 0-15 as c ^ (r & 15), chunks 16-23 as
 //    16 + ((c - 16) ^ ((r >> 1) & 7));
@@ -205,17 +205,18 @@ struct RowFmt {
   static constexpr int CPR = RB / 16;    // 16-byte chunks per row
   static constexpr int AU4 = CPR / 2;    // chunks per lane (uint4 per fragment)
   static constexpr bool kFull = KR == kReal;
-  static_assert(kFull || (KR == kRealReduced && PREC != RM_FP32), "row format");
+  static_assert(kFull || KR == kRealReduced, "row format");
   // slots in the first region, and the byte offset of the second region
-  static constexpr int U1 = kFull ? AU4 : (PREC == RM_FP16 ? 8 : 4);
-  static constexpr int BASE2 = PREC == RM_FP16 ? 256 : 128;
+  static constexpr int U1 = kFull ? AU4 : (PREC == RM_FP32 ? 16 : PREC == RM_FP16 ? 8 : 4);
+  static constexpr int BASE2 = PREC == RM_FP32 ? 512 : PREC == RM_FP16 ? 256 : 128;
   __device__ __forceinline__ static int swap(int r, int c) {
-    if constexpr (kFull) return c ^ (r & 15);
+    if constexpr (kFull || PREC == RM_FP32) return c ^ (r & 15);
     else if constexpr (PREC == RM_FP16) return c < 16 ? c ^ (r & 15) : 16 + ((c - 16) ^ ((r >> 1) & 7));
     else return c ^ ((r >> 2) & 3);
   }
   __device__ __forceinline__ static int lane_chunk(int g, int u) {
     if constexpr (kFull) return g * AU4 + u;
+    else if constexpr (PREC == RM_FP32) return u < 16 ? 16 * g + u : 32 + 8 * g + (u - 16);
     else if constexpr (PREC == RM_FP16) return u < 8 ? 8 * g + u : 16 + 4 * g + (u - 8);
     else return u < 4 ? 4 * g + u : 8 + 2 * g + (u - 4);
   }
@@ -223,6 +224,9 @@ struct RowFmt {
     if constexpr (kFull) {
       kx = ((uint32_t)g * (RB / 2)) ^ (16u * (uint32_t)(col & 15));
       kx2 = 0;
+    } else if constexpr (PREC == RM_FP32) {
+      kx = (256u * g) ^ (16u * (uint32_t)(col & 15));
+      kx2 = (128u * g) ^ (16u * (uint32_t)(col & 15));
     } else if constexpr (PREC == RM_FP16) {
       kx = (128u * g) ^ (16u * (uint32_t)(col & 15));
       kx2 = (64u * g) ^ (16u * (uint32_t)((col >> 1) & 7));

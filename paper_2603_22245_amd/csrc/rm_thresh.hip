@@ -485,7 +485,10 @@ hipError_t launch_score_threshold(const rm_index& idx, const uint8_t* ref,
                        (int)n_chunks, pool, (uint64_t)capacity, pool_n);
   };
   const bool red = reduced_rows(idx.p);
-  if (prec == RM_FP32)
+  if (prec == RM_FP32 && red)
+    scan(threshold_scan_kernel<RM_FP32, kRealReduced>, ThrK<RM_FP32, kRealReduced>::READS,
+         ThrK<RM_FP32, kRealReduced>::THREADS);
+  else if (prec == RM_FP32)
     scan(threshold_scan_kernel<RM_FP32, kReal>, ThrK<RM_FP32, kReal>::READS,
          ThrK<RM_FP32, kReal>::THREADS);
   else if (prec == RM_FP16 && red)

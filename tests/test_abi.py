@@ -340,8 +340,9 @@ def test_noalloc_validation():
 
 
 def test_letter_sum_form_params():
-    """The letter-sum form (rm_params.reduced): 192 reals per row for FP16 and
-    FP8 letter indexes with integer factors and N > m; refused elsewhere."""
+    """The letter-sum form (rm_params.reduced): 192 reals per row for letter
+    indexes with integer factors and N > m, in every precision; refused
+    elsewhere."""
     lib = L.lib()
     R = ctypes.byref
     out = L.rm_index()
@@ -353,8 +354,9 @@ def test_letter_sum_form_params():
         # rows shrink by a quarter; the rest of the buffer is the same
         assert L.rm_index_bytes(20_000, full) - L.rm_index_bytes(20_000, red) >= \
             19_851 * 64 * esize - 256
-    bad = [L.make_params(150, 1, 32, "default", "fp32", reduced=True),          # FP32
-           L.make_params(150, 1, 32, "finetuned", "fp16", reduced=True),        # non-integer factors
+    fp32 = L.make_params(150, 1, 32, "default", "fp32", reduced=True)
+    assert L.rm_read_emb_bytes(10, fp32) == 10 * 2 * 192 * 4
+    bad = [L.make_params(150, 1, 32, "finetuned", "fp16", reduced=True),        # non-integer factors
            L.make_params(32, 1, 32, "default", "fp16", reduced=True),           # N = m: f_m = N
            L.make_params(150, 1, 8, "default", "fp16", 0, 2, 16, reduced=True)]  # tokens
     for p in bad:

@@ -106,6 +106,23 @@ def test_rolling_drift_over_long_segments():
     assert err[65_536] < 1e-5                               # re-anchored
 
 
+def test_fp32_letter_sum_rows(plain_data, plain_oracle):
+    """FP32 windows in the letter-sum form: the oracle's normalised vectors
+    projected on the letter-sum basis, to the FP32 rolling error."""
+    torch = torch_cuda()
+    ref, _, _ = plain_data
+    Cn, n2, _, _ = plain_oracle
+    index = _build(ref, "fp32", reduced=True)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    want = stored_form(Cn, index)
+    assert got.shape == want.shape == (Cn.shape[0], 96)
+    ok = n2 >= 1e-3 * 150
+    assert np.max(np.abs(got[ok] - want[ok])) < 5e-5
+    # the projection keeps the norm: letter-only windows stay unit vectors
+    assert np.max(np.abs(np.linalg.norm(got[ok], axis=1) - 1)) < 1e-5
+
+
 def test_letter_sum_identity_on_device():
     # For integer factors sum_L c_{k,L} = 0 in every full window.
     torch = torch_cuda()
@@ -172,8 +189,8 @@ def test_quantised_encodings(precision, reduced, plain_data, plain_oracle):
         assert np.mean(diff == 0) > 0.999
 
 
-@pytest.mark.parametrize("precision,reduced", [("fp32", False), ("fp16", False), ("fp16", True),
-                                               ("fp8", False), ("fp8", True)])
+@pytest.mark.parametrize("precision,reduced", [("fp32", False), ("fp32", True), ("fp16", False),
+                                               ("fp16", True), ("fp8", False), ("fp8", True)])
 def test_read_encoder(precision, reduced, plain_data):
     from paper_2603_22245_amd import mapper
     torch = torch_cuda()
@@ -224,7 +241,8 @@ def _check_candidates(idx, score, F, tol, absolute=False):
     ("fp32", 8, None), ("fp16", 8, None), ("fp16", 16, None), ("fp16", 32, None), ("fp8", 16, None),
     ("fp8", 32, None), ("fp32", 32, None), ("fp16", 16, False), ("fp16", 32, False),
     ("fp8", 16, True), ("fp8", 32, True), ("fp16", 64, None), ("fp8", 64, None),
-    ("fp32", 64, None), ("fp16", 48, False), ("fp8", 64, True)])
+    ("fp32", 64, None), ("fp16", 48, False), ("fp8", 64, True), ("fp32", 16, True),
+    ("fp32", 64, True)])
 def test_score_topk_and_rescore(precision, k_fetch, reduced, plain_data, plain_oracle):
     """The product's candidates and the rescored lists against the oracle; FP16
     and FP8 indexes in the letter-sum form (FP16's default for letters) and in
