@@ -162,14 +162,14 @@ __device__ __forceinline__ uint32_t lds_offset(const void* p) {
 // offset lds + l * size.  Written as inline assembly, with no output register,
 // so that the compiler does not drain every outstanding copy (vmcnt(0)) before
 // each LDS read; completion is awaited explicitly with wait_vmcnt<N>(), which
-// counts this wavefront's vector-memory operations in issue order.
+// counts this wavefront's vector-memory operations in issue order.  The LDS
+// base goes in through an m0 operand, so the compiler itself sets m0 and
+// knows that it holds the value.
 __device__ __forceinline__ void dma16(const void* src, uint32_t lds) {
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
-               : "memory");
+  asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(lds) : "memory");
 }
 __device__ __forceinline__ void dma4(const void* src, uint32_t lds) {
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(lds)
-               : "memory");
+  asm volatile("global_load_lds_dword %0, off" ::"v"(src), "{m0}"(lds) : "memory");
 }
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {

@@ -257,10 +257,9 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
 // (gfx950 global_load_lds_dwordx4): lane l writes LDS bytes [lds + 16 l,
 // lds + 16 l + 16).  No output register; completion is awaited with
 // wait_vm<N>(), which counts this wavefront's vector-memory operations in
-// issue order.
+// issue order.  The LDS base goes in through an m0 operand.
 __device__ __forceinline__ void dma16w(const void* src, uint32_t lds) {
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
-               : "memory", "m0");
+  asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(lds) : "memory");
 }
 template <int N>
 __device__ __forceinline__ void wait_vm() {
