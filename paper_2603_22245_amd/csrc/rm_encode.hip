@@ -7,10 +7,14 @@
 // (component index k*4 + letter, re/im interleaved).  One wavefront therefore
 // writes a whole row with one coalesced store.
 //
-// Window encoder (§3.4): window j (start j*stride) follows from window j-1 by
-// `stride` one-letter slides; a slide multiplies every component by omega^-f_k,
-// subtracts omega^-f_k from the outgoing letter's component and adds
-// omega^(f_k (N-1)) to the incoming letter's component.  Each wavefront walks a
+// Window encoder (§3.4): window j (start j*stride) follows from window j-1.
+// With stride 1 a slide takes 1 from the outgoing letter's component, turns
+// every component by omega^-f_k and adds omega^(f_k (N-1)) to the incoming
+// letter's component.  A larger stride (up to kBlockMax, and at most N) moves
+// a block at a time: E_{j+1} = omega^(-f s) (E_j - O_j + omega^(f N) I_j), where
+// O_j and I_j add omega^(f q) over the s letters leaving (starts j s + q) and
+// entering (j s + N + q), q < s -- one turn per window instead of one per
+// letter.  Longer strides slide letter by letter.  Each wavefront walks a
 // segment of consecutive windows; at the segment start the state is computed
 // directly from the letters in FP64 (the re-anchor), then rolled in FP32.
 // Each window is normalised (§2.3) and written in the index precision.
@@ -24,6 +28,51 @@ namespace {
 struct Row4 {
   float v[4];
 };
+
+// Cross-lane move (DPP) with full row and bank masks; lanes without a source
+// read 0.  Every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ float mdpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+
+// Sum over the 64 lanes as a wavefront-uniform value: row sums of 16 lanes by
+// DPP (xor 1, xor 2, half-row mirror, row mirror), then each row adds the
+// previous row's sum (row_bcast:15) and rows 2 and 3 add row 1's
+// (row_bcast:31); lane 63 ends with (r3 + r2) + (r1 + r0), which is the
+// (r0 + r1) + (r2 + r3) of wave_sum, since each addition is commutative.
+// Every lane must be active.
+__device__ __forceinline__ float wave_total(float v) {
+  v += mdpp<0xB1>(v);
+  v += mdpp<0x4E>(v);
+  v += mdpp<0x141>(v);
+  v += mdpp<0x140>(v);
+  v += mdpp<0x142>(v);
+  v += mdpp<0x143>(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Multipliers that put a letter's term on a lane's components: m0 = 1 where
+// letter L is the lane's component 0 (L == 2h), m1 = 1 where it is component
+// 1 (L == 2h + 1), both 0 otherwise.  The kernels keep the ten entries
+// [h][min(L, 4)] in LDS (entry 4: codes above 3, no letter), so that a
+// wavefront-uniform letter costs one LDS read and no branch or select.
+struct LetterMul {
+  float m0, m1;
+};
+__device__ __forceinline__ LetterMul letter_mul_entry(int hh, int L) {
+  return LetterMul{(L < 4 && L == 2 * hh) ? 1.f : 0.f, (L < 4 && L == 2 * hh + 1) ? 1.f : 0.f};
+}
+// c += a m t on the lane's two components.
+__device__ __forceinline__ void letter_fma(float2& c0, float2& c1, LetterMul w, float a,
+                                           float2 t) {
+  const float m0 = a * w.m0, m1 = a * w.m1;
+  c0.x = fmaf(m0, t.x, c0.x);
+  c0.y = fmaf(m0, t.y, c0.y);
+  c1.x = fmaf(m1, t.x, c1.x);
+  c1.y = fmaf(m1, t.y, c1.y);
+}
 
 // Write one normalised row (4 reals per lane) in the requested precision.
 // Returns the FP8 scale used (1 for FP32/FP16).  FP8 codes are RNE(v / 2^e):
@@ -67,7 +116,7 @@ __device__ __forceinline__ float store_row(void* base, int64_t row, int lane, Ro
     // quantisation; renormalising removes it (phase errors only enter F at
     // second order).
     float2 d01 = unpack_fp8x2(w), d23 = unpack_fp8x2(w >> 16);
-    float q2 = wave_sum(d01.x * d01.x + d01.y * d01.y + d23.x * d23.x + d23.y * d23.y);
+    float q2 = wave_total(d01.x * d01.x + d01.y * d01.y + d23.x * d23.x + d23.y * d23.y);
     return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) : s;  // 1 ulp
   }
 }
@@ -93,8 +142,9 @@ struct Row3 {
 __device__ __forceinline__ void letter_sum_rows(float2 u0, float2 u1, int h, Row3& re, Row3& im) {
   const float2 s = make_float2(u0.x + u1.x, u0.y + u1.y);
   const float2 d = make_float2(u0.x - u1.x, u0.y - u1.y);
-  const float2 sp = make_float2(__shfl_xor(s.x, 1, 64), __shfl_xor(s.y, 1, 64));
-  const float2 dp = make_float2(__shfl_xor(d.x, 1, 64), __shfl_xor(d.y, 1, 64));
+  // the partner lane's values (lane ^ 1), by DPP quad_perm [1,0,3,2]
+  const float2 sp = make_float2(dpp<0xB1>(s.x), dpp<0xB1>(s.y));
+  const float2 dp = make_float2(dpp<0xB1>(d.x), dpp<0xB1>(d.y));
   // y1 = (s01 - s23)/2, y2 = (d01 + d23)/2, y3 = (d01 - d23)/2, letters 0 and 1
   // being lane h = 0's
   const float sg = h ? -0.5f : 0.5f;
@@ -116,7 +166,6 @@ __device__ __forceinline__ void letter_sum_rows(float2 u0, float2 u1, int h, Row
 // FP32 row.
 template <int PREC, bool WINDOW = false>
 __device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, Row3 x) {
-  const bool odd = lane & 1;
   if constexpr (PREC == RM_FP32) {
     float* dst = static_cast<float*>(base) + row * kRealReduced + 3 * lane;
     dst[0] = x.v[0];
@@ -127,14 +176,12 @@ __device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, R
     const uint32_t h0 = __builtin_bit_cast(uint16_t, (_Float16)x.v[0]);
     const uint32_t h1 = __builtin_bit_cast(uint16_t, (_Float16)x.v[1]);
     const uint32_t h2 = __builtin_bit_cast(uint16_t, (_Float16)x.v[2]);
-    uint16_t* dst = static_cast<uint16_t*>(base) + row * kRealReduced + 3 * lane;
-    if (!odd) {  // byte offset 6 lane is a multiple of 4
-      *reinterpret_cast<uint32_t*>(dst) = h0 | (h1 << 16);
-      dst[2] = (uint16_t)h2;
-    } else {     // 6 lane + 2 is
-      dst[0] = (uint16_t)h0;
-      *reinterpret_cast<uint32_t*>(dst + 1) = h1 | (h2 << 16);
-    }
+    // uniform row start plus a 32-bit lane offset
+    char* rowp = static_cast<char*>(base) + row * (int64_t)(kRealReduced * sizeof(uint16_t));
+    uint16_t* dst = reinterpret_cast<uint16_t*>(rowp + 6 * lane);
+    dst[0] = (uint16_t)h0;
+    dst[1] = (uint16_t)h1;
+    dst[2] = (uint16_t)h2;
     return 1.f;
   } else {
     float s = kFp8WindowScale, inv = 1.f / kFp8WindowScale;
@@ -147,47 +194,53 @@ __device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, R
     const uint32_t w01 = pack_fp8x2(x.v[0] * inv, x.v[1] * inv);
     const uint32_t w2 = pack_fp8x2(x.v[2] * inv, 0.f) & 0xffu;
     uint8_t* dst = static_cast<uint8_t*>(base) + row * kRealReduced + 3 * lane;
-    if (!odd) {  // byte offset 3 lane is even
-      *reinterpret_cast<uint16_t*>(dst) = (uint16_t)w01;
-      dst[2] = (uint8_t)w2;
-    } else {
-      dst[0] = (uint8_t)(w01 & 0xffu);
-      *reinterpret_cast<uint16_t*>(dst + 1) = (uint16_t)((w01 >> 8) | (w2 << 8));
-    }
+    dst[0] = (uint8_t)(w01 & 0xffu);
+    dst[1] = (uint8_t)(w01 >> 8);
+    dst[2] = (uint8_t)w2;
     const float2 d01 = unpack_fp8x2(w01), d2 = unpack_fp8x2(w2);
-    const float q2 = wave_sum(d01.x * d01.x + d01.y * d01.y + d2.x * d2.x);
-    const float y2 = wave_sum(x.v[0] * x.v[0] + x.v[1] * x.v[1] + x.v[2] * x.v[2]);
+    const float q2 = wave_total(d01.x * d01.x + d01.y * d01.y + d2.x * d2.x);
+    const float y2 = wave_total(x.v[0] * x.v[0] + x.v[1] * x.v[1] + x.v[2] * x.v[2]);
     return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) * sqrtf(y2) : s;
   }
 }
 
-// FP64 direct sum over letters [0, n) of `str` for this lane's two components.
+// FP64 direct sum over letters [0, n) of `str` for this lane's two components
+// (letters 2h, 2h+1 of factor k).  The phase omega^(f_k p) is read from the FP64
+// table at every 64th position and advanced in between by FP64 multiplication
+// with omega^(f_k) (at most 63 products, relative error below 2^-45).  The
+// letter is the same for the whole wavefront, so each position adds the phase
+// to one of four per-letter sums by a uniform branch; the lane keeps the two
+// sums of its own letters.  Codes above 3 add nothing.
 __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int n,
                                            const double2* __restrict__ phase64, int lane,
                                            double2& a0, double2& a1) {
   const int k = lane >> 1, h = lane & 1;
-  const int L0 = 2 * h, L1 = 2 * h + 1;
-  a0 = make_double2(0.0, 0.0);
-  a1 = make_double2(0.0, 0.0);
+  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+  const double2 w = phase64[(n > 1 ? kM : 0) + k];  // omega^(f_k)
   for (int pb = 0; pb < n; pb += 64) {
-    int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
-    int cnt = min(64, n - pb);
-    // groups of 8 positions: the 8 table loads are in flight together; a
-    // position past the end re-reads the last row and has letter 255
-    for (int i0 = 0; i0 < cnt; i0 += 8) {
-      double2 e[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) e[u] = phase64[(int64_t)min(pb + i0 + u, n - 1) * kM + k];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int L = __builtin_amdgcn_readlane(mine, i0 + u);
-        a0.x += (L == L0) ? e[u].x : 0.0;
-        a0.y += (L == L0) ? e[u].y : 0.0;
-        a1.x += (L == L1) ? e[u].x : 0.0;
-        a1.y += (L == L1) ? e[u].y : 0.0;
+    const int mine = (pb + lane < n) ? (int)str[pb + lane] : 255;
+    const int cnt = min(64, n - pb);
+    double2 t = phase64[(int64_t)pb * kM + k];
+    for (int i = 0; i < cnt; ++i) {
+      const int L = __builtin_amdgcn_readlane(mine, i);
+      if (L == 0) {
+        s0.x += t.x;
+        s0.y += t.y;
+      } else if (L == 1) {
+        s1.x += t.x;
+        s1.y += t.y;
+      } else if (L == 2) {
+        s2.x += t.x;
+        s2.y += t.y;
+      } else if (L == 3) {
+        s3.x += t.x;
+        s3.y += t.y;
       }
+      t = make_double2(t.x * w.x - t.y * w.y, t.x * w.y + t.y * w.x);
     }
   }
+  a0 = h ? s2 : s0;
+  a1 = h ? s3 : s1;
 }
 
 // A window's squared norm and scale wait in lane registers (lane j - jb
@@ -227,14 +280,24 @@ template <int PREC, bool RED = false>
 __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c0, float2 c1,
                                             void* emb, SideBuf& side, float* scale,
                                             float* norm2) {
-  float n2 = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
-  bool deg = n2 < kDegenerateRel * (float)N;
-  float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
+  const float n2 = wave_total(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+  const bool deg = n2 < kDegenerateRel * (float)N;
+  const float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
   float s;
-  if constexpr (RED) {  // the letter-sum form of the normalised vector
-    Row3 y, unused;
-    letter_sum_rows(make_float2(c0.x * inv, c0.y * inv), make_float2(c1.x * inv, c1.y * inv),
-                    lane & 1, y, unused);
+  if constexpr (RED) {
+    // The letter-sum row of the normalised vector: the combinations of
+    // letter_sum_rows taken on (c0, c1), the basis' factor 1/2 folded into
+    // the normalisation.
+    const float g = 0.5f * inv;
+    const float2 sm = make_float2(c0.x + c1.x, c0.y + c1.y);
+    const float2 df = make_float2(c0.x - c1.x, c0.y - c1.y);
+    const float spx = mdpp<0xB1>(sm.x), spy = mdpp<0xB1>(sm.y);  // partner lane (lane ^ 1)
+    const float dpx = mdpp<0xB1>(df.x), dpy = mdpp<0xB1>(df.y);
+    Row3 y;
+    if (lane & 1)  // (y2.im, y3.re, y3.im)
+      y = Row3{{g * (df.y + dpy), g * (dpx - df.x), g * (dpy - df.y)}};
+    else           // (y1.re, y1.im, y2.re)
+      y = Row3{{g * (sm.x - spx), g * (sm.y - spy), g * (df.x + dpx)}};
     s = store_row3<PREC, true>(emb, j, lane, y);
   } else {
     Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
@@ -247,16 +310,36 @@ __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c
   if (++side.n == 64) side_flush(side, lane, norm2, scale);
 }
 
+// Strides up to this roll block by block; the table of omega^(f_k q), q < stride,
+// sits in LDS (at most 64 x 32 complex FP32 = 16 KB per block of wavefronts).
+constexpr int kBlockMax = 64;
+
+__device__ __forceinline__ double2 cmul64(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
 template <int PREC, bool RED>
 __global__ __launch_bounds__(256) void encode_reference_kernel(
-    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,
-    const double2* __restrict__ phase64, const float4* __restrict__ step32, void* __restrict__ emb,
-    float* __restrict__ scale, float* __restrict__ norm2) {
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int unit_z, int64_t seg_len,
+    int64_t n_seg, const double2* __restrict__ phase64, const float4* __restrict__ step32,
+    void* __restrict__ emb, float* __restrict__ scale, float* __restrict__ norm2) {
+  extern __shared__ float2 tq[];  // [stride][kM] omega^(f_k q): block rolling only
+  __shared__ LetterMul ltab[2][5];
+  const bool blockwise = stride > 1 && stride <= kBlockMax && stride <= N;
+  if (blockwise) {
+    for (int v = threadIdx.x; v < stride * kM; v += blockDim.x) {
+      const double2 e = phase64[v];
+      tq[v] = make_float2((float)e.x, (float)e.y);
+    }
+  }
+  if (threadIdx.x < 10) ltab[threadIdx.x / 5][threadIdx.x % 5] = letter_mul_entry(threadIdx.x / 5, threadIdx.x % 5);
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // wavefront-uniform, so that the segment's bookkeeping stays in scalar registers
+  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (seg >= n_seg) return;
   const int k = lane >> 1, h = lane & 1;
-  const int L0 = 2 * h, L1 = 2 * h + 1;
   const int64_t j0 = seg * seg_len;
   const int64_t j1 = min(W, j0 + seg_len);
 
@@ -268,36 +351,83 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
   emit_window<PREC, RED>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
-  const float4 st = step32[k];
-  const float2 rot = make_float2(st.x, st.y);   // omega^-f
-  const float2 inc = make_float2(st.z, st.w);   // omega^(f (N-1))
-
-  // Slides t = 0 .. n_slides-1 move the window start from j0*stride+t to +1.
+  // Letter t = 0 .. n_slides-1 of the segment leaves at start s0 + t + 1 (it
+  // is ref[s0 + t]) while ref[s0 + t + N] enters; the letters of the next 64
+  // are loaded while the current 64 roll.
   const int64_t s0 = j0 * stride;
   const int64_t n_slides = (j1 - 1 - j0) * stride;
   int64_t j = j0;
-  int until_emit = stride;
-  // outgoing letter of slide t is ref[s0+t], incoming is ref[s0+t+N]; the
-  // next chunk's letters are loaded while the current chunk rolls
   int out_l = lane < n_slides ? (int)ref[s0 + lane] : 255;
   int in_l = lane < n_slides ? (int)ref[s0 + lane + N] : 255;
-  for (int64_t tb = 0; tb < n_slides; tb += 64) {
-    const int64_t tn = tb + 64 + lane;
-    const int out_next = tn < n_slides ? (int)ref[s0 + tn] : 255;
-    const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
-    int cnt = (int)min<int64_t>(64, n_slides - tb);
-    for (int i = 0; i < cnt; ++i) {
-      const int o = __builtin_amdgcn_readlane(out_l, i);
-      const int n = __builtin_amdgcn_readlane(in_l, i);
-      slide(c0, c1, rot, o, n, h, rot, inc);
-      if (--until_emit == 0) {
-        until_emit = stride;
-        ++j;
-        emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
+  if (blockwise) {
+    // omega^(f N) and omega^(-f stride) from the FP64 table, rounded once
+    const double2 zN = cmul64(phase64[(int64_t)(N - 1) * kM + k], phase64[kM + k]);
+    const double2 ws = stride < N ? phase64[(int64_t)stride * kM + k] : zN;
+    const float2 R = make_float2((float)ws.x, -(float)ws.y);
+    const float2 z = make_float2((float)zN.x, (float)zN.y);
+    float2 i0 = make_float2(0.f, 0.f), i1 = i0;  // I_j (O_j is taken from the state at once)
+    int q = 0;
+    for (int64_t tb = 0; tb < n_slides; tb += 64) {
+      const int64_t tn = tb + 64 + lane;
+      const int out_next = tn < n_slides ? (int)ref[s0 + tn] : 255;
+      const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
+      const int cnt = (int)min<int64_t>(64, n_slides - tb);
+      for (int i = 0; i < cnt; ++i) {
+        const int o = __builtin_amdgcn_readlane(out_l, i);
+        const int n = __builtin_amdgcn_readlane(in_l, i);
+        const float2 t = tq[q * kM + k];
+        letter_fma(c0, c1, ltab[h][min(o, 4)], -1.f, t);
+        if (unit_z)  // integer factors: omega^(f N) = 1
+          letter_fma(c0, c1, ltab[h][min(n, 4)], 1.f, t);
+        else
+          letter_fma(i0, i1, ltab[h][min(n, 4)], 1.f, t);
+        if (++q == stride) {
+          q = 0;
+          if (!unit_z) {
+            const float2 u0 = cmul(z, i0), u1 = cmul(z, i1);
+            c0 = make_float2(c0.x + u0.x, c0.y + u0.y);
+            c1 = make_float2(c1.x + u1.x, c1.y + u1.y);
+            i0 = make_float2(0.f, 0.f);
+            i1 = i0;
+          }
+          c0 = cmul(c0, R);
+          c1 = cmul(c1, R);
+          ++j;
+          emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
+        }
       }
+      out_l = out_next;
+      in_l = in_next;
     }
-    out_l = out_next;
-    in_l = in_next;
+  } else {
+    // one letter at a time: E <- omega^-f (E - [out]) + omega^(f (N-1)) [in]
+    const float4 st = step32[k];
+    const float2 rot = make_float2(st.x, st.y);  // omega^-f
+    const float2 inc = make_float2(st.z, st.w);  // omega^(f (N-1))
+    int until_emit = stride;
+    for (int64_t tb = 0; tb < n_slides; tb += 64) {
+      const int64_t tn = tb + 64 + lane;
+      const int out_next = tn < n_slides ? (int)ref[s0 + tn] : 255;
+      const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
+      const int cnt = (int)min<int64_t>(64, n_slides - tb);
+      for (int i = 0; i < cnt; ++i) {
+        const int o = __builtin_amdgcn_readlane(out_l, i);
+        const int n = __builtin_amdgcn_readlane(in_l, i);
+        const LetterMul wo = ltab[h][min(o, 4)];
+        c0.x -= wo.m0;
+        c1.x -= wo.m1;
+        c0 = cmul(c0, rot);
+        c1 = cmul(c1, rot);
+        letter_fma(c0, c1, ltab[h][min(n, 4)], 1.f, inc);
+        if (--until_emit == 0) {
+          until_emit = stride;
+          ++j;
+          emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
+        }
+      }
+      out_l = out_next;
+      in_l = in_next;
+    }
   }
   side_finish(side, lane, norm2, scale);
 }
@@ -336,7 +466,8 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
     const uint8_t* __restrict__ seq, const int64_t* __restrict__ off, int32_t n_reads, int N,
     const float2* __restrict__ phase32, void* __restrict__ emb, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (r >= n_reads) return;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
@@ -403,7 +534,7 @@ __global__ __launch_bounds__(256) void encode_reference_learned_kernel(
   // per wavefront: exp(i delta) of the outgoing (row 0..31) and incoming
   // (rows 32..63) tokens of the current chunk of slides
   __shared__ float2 u_stage[4][2 * kChunk][32];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (seg >= n_seg) return;
   const int k = lane >> 1, h = lane & 1;
@@ -507,7 +638,8 @@ __global__ __launch_bounds__(256) void encode_reads_learned_kernel(
     const float2* __restrict__ phase32, const float* __restrict__ delta, void* __restrict__ emb,
     float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (r >= n_reads) return;
   const int64_t start = off[r];
   const int64_t len = off[r + 1] - start;
@@ -529,7 +661,8 @@ __global__ __launch_bounds__(256) void encode_reference_tokens_kernel(
     const float4* __restrict__ step32, const uint8_t* __restrict__ table, void* __restrict__ emb,
     float* __restrict__ scale, float* __restrict__ norm2) {
   const int lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (seg >= n_seg) return;
   const int k = 2 * lane / n_class, c0 = 2 * lane - k * n_class;
   const int T = N - s + 1;  // tokens per window
@@ -586,7 +719,8 @@ __global__ __launch_bounds__(256) void encode_reads_tokens_kernel(
     int s, int m, int n_class, const float2* __restrict__ phase32,
     const uint8_t* __restrict__ table, void* __restrict__ emb, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (r >= n_reads) return;
   const int k = 2 * lane / n_class, c0 = 2 * lane - k * n_class;
   const int64_t start = off[r];
@@ -620,8 +754,13 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
   else if (p.precision == RM_FP8_E4M3)
     kern = p.reduced ? encode_reference_kernel<RM_FP8_E4M3, true>
                      : encode_reference_kernel<RM_FP8_E4M3, false>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), 0, s, ref, W, p.window_len,
-                     p.stride, seg, n_seg, ph, st, emb, scale, norm2);
+  // block rolling (stride 2 .. kBlockMax, at most N) takes the table of
+  // omega^(f q), q < stride, in LDS; integer factors make omega^(f N) = 1
+  const bool blockwise = p.stride > 1 && p.stride <= kBlockMax && p.stride <= p.window_len;
+  const size_t lds = blockwise ? (size_t)p.stride * kM * sizeof(float2) : 0;
+  const int unit_z = p.schedule == RM_SCHED_DEFAULT ? 1 : 0;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, s, ref, W, p.window_len,
+                     p.stride, unit_z, seg, n_seg, ph, st, emb, scale, norm2);
   return hipGetLastError();
 }
 

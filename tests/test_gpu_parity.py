@@ -73,7 +73,14 @@ def test_angle_tables_fp64():
 
 @pytest.mark.parametrize("N,stride,sched", [(150, 1, "default"), (150, 3, "default"),
                                             (150, 1, "finetuned"), (32, 1, "default"),
-                                            (1000, 7, "default")])
+                                            (1000, 7, "default"),
+                                            # block rolling with omega^(f N) != 1, the
+                                            # largest block, a block of N letters, and
+                                            # strides rolled letter by letter (above
+                                            # the largest block, and above N)
+                                            (150, 3, "finetuned"), (150, 64, "default"),
+                                            (40, 40, "default"), (150, 100, "default"),
+                                            (32, 48, "finetuned")])
 def test_rolling_encoder_fp32(N, stride, sched):
     torch = torch_cuda()
     ref = synth.make_reference(30_000, gc=0.45, repeat_frac=0.05, seed=7)
