@@ -64,6 +64,17 @@ struct LetterMul {
 __device__ __forceinline__ LetterMul letter_mul_entry(int hh, int L) {
   return LetterMul{(L < 4 && L == 2 * hh) ? 1.f : 0.f, (L < 4 && L == 2 * hh + 1) ? 1.f : 0.f};
 }
+// With omega^(f N) = 1 (integer factors) a step adds the incoming letter's term
+// and removes the outgoing one's with the same factor, so one entry serves both:
+// [h][5 min(out, 4) + min(in, 4)] = multipliers of `in` minus those of `out`.
+__device__ __forceinline__ LetterMul letter_pair_entry(int hh, int out, int in) {
+  const LetterMul a = letter_mul_entry(hh, out), b = letter_mul_entry(hh, in);
+  return LetterMul{b.m0 - a.m0, b.m1 - a.m1};
+}
+__device__ __forceinline__ int letter_pair_index(int packed) {  // out | in << 8
+  return 5 * min(packed & 0xff, 4) + min(packed >> 8, 4);
+}
+
 // c += a m t on the lane's two components.
 __device__ __forceinline__ void letter_fma(float2& c0, float2& c1, LetterMul w, float a,
                                            float2 t) {
@@ -318,6 +329,115 @@ __device__ __forceinline__ double2 cmul64(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+struct RollState {
+  float2 c0, c1;
+  int64_t j;  // last window emitted
+};
+
+// Byte offset of entry [0][i] in a table of LetterMul (lane h adds its row).
+__device__ __forceinline__ const LetterMul& tab_entry(const LetterMul* row, int byte_off) {
+  return *reinterpret_cast<const LetterMul*>(reinterpret_cast<const char*>(row) + byte_off);
+}
+
+// Roll a segment from its first window: `n_slides` letters t leave (ref[s0 + t])
+// while ref[s0 + t + N] enters, 64 at a time (the next 64 are loaded while the
+// current ones roll; each lane holds the table offsets of one letter, read out
+// as wavefront-uniform values).  UZ: integer factors (omega^(f N) = 1), so the
+// entering and leaving letters share one table entry.  BLOCK: strides 2..64 (at
+// most N), one turn per window; otherwise one turn per letter, emitting every
+// stride-th window.
+template <int PREC, bool RED, bool UZ, bool BLOCK>
+__device__ __forceinline__ void roll(const uint8_t* __restrict__ ref, int64_t s0, int64_t n_slides,
+                                     int N, int stride, int k, int lane,
+                                     const double2* __restrict__ phase64,
+                                     const float4* __restrict__ step32, const float2* tq,
+                                     const LetterMul (*ltab)[5], const LetterMul (*ptab)[25],
+                                     RollState& st, SideBuf& side, void* emb, float* scale,
+                                     float* norm2) {
+  const int h = lane & 1;
+  const LetterMul* lrow = ltab[h];
+  const LetterMul* prow = ptab[h];
+  float2 c0 = st.c0, c1 = st.c1;
+  int64_t j = st.j;
+  float2 rot, inc, z = make_float2(1.f, 0.f);
+  if constexpr (BLOCK) {
+    // omega^(f N) and omega^(-f stride) from the FP64 table, rounded once
+    const double2 zN = cmul64(phase64[(int64_t)(N - 1) * kM + k], phase64[kM + k]);
+    const double2 ws = stride < N ? phase64[(int64_t)stride * kM + k] : zN;
+    rot = make_float2((float)ws.x, -(float)ws.y);
+    z = make_float2((float)zN.x, (float)zN.y);
+  } else {
+    const float4 sv = step32[k];
+    rot = make_float2(sv.x, sv.y);  // omega^-f
+    inc = make_float2(sv.z, sv.w);  // omega^(f (N-1))
+  }
+  // per-lane letter offsets: UZ one pair entry, else the leaving and the
+  // entering letter's entries (byte offsets into a table row)
+  auto offsets = [&](int64_t t) -> int {
+    const int o = t < n_slides ? (int)ref[s0 + t] : 255;
+    const int n = t < n_slides ? (int)ref[s0 + t + N] : 255;
+    if constexpr (UZ)
+      return 8 * letter_pair_index(o | (n << 8));
+    else
+      return 8 * min(o, 4) | ((8 * min(n, 4)) << 8);
+  };
+  float2 i0 = make_float2(0.f, 0.f), i1 = i0;  // I_j (BLOCK, not UZ)
+  int q = 0, until_emit = stride;
+  int off_l = offsets(lane);
+  for (int64_t tb = 0; tb < n_slides; tb += 64) {
+    const int off_next = offsets(tb + 64 + lane);
+    const int cnt = (int)min<int64_t>(64, n_slides - tb);
+    for (int i = 0; i < cnt; ++i) {
+      const int off = __builtin_amdgcn_readlane(off_l, i);
+      if constexpr (BLOCK) {
+        const float2 t = tq[q * kM + k];
+        if constexpr (UZ) {
+          letter_fma(c0, c1, tab_entry(prow, off), 1.f, t);
+        } else {
+          letter_fma(c0, c1, tab_entry(lrow, off & 0xff), -1.f, t);
+          letter_fma(i0, i1, tab_entry(lrow, off >> 8), 1.f, t);
+        }
+        if (++q == stride) {
+          q = 0;
+          if constexpr (!UZ) {
+            const float2 u0 = cmul(z, i0), u1 = cmul(z, i1);
+            c0 = make_float2(c0.x + u0.x, c0.y + u0.y);
+            c1 = make_float2(c1.x + u1.x, c1.y + u1.y);
+            i0 = make_float2(0.f, 0.f);
+            i1 = i0;
+          }
+          c0 = cmul(c0, rot);
+          c1 = cmul(c1, rot);
+          ++j;
+          emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
+        }
+      } else {
+        if constexpr (UZ) {  // omega^-f (E + [in] - [out])
+          const LetterMul d = tab_entry(prow, off);
+          c0.x += d.m0;
+          c1.x += d.m1;
+          c0 = cmul(c0, rot);
+          c1 = cmul(c1, rot);
+        } else {  // omega^-f (E - [out]) + omega^(f (N-1)) [in]
+          const LetterMul wo = tab_entry(lrow, off & 0xff);
+          c0.x -= wo.m0;
+          c1.x -= wo.m1;
+          c0 = cmul(c0, rot);
+          c1 = cmul(c1, rot);
+          letter_fma(c0, c1, tab_entry(lrow, off >> 8), 1.f, inc);
+        }
+        if (--until_emit == 0) {
+          until_emit = stride;
+          ++j;
+          emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
+        }
+      }
+    }
+    off_l = off_next;
+  }
+  st = RollState{c0, c1, j};
+}
+
 template <int PREC, bool RED>
 __global__ __launch_bounds__(256) void encode_reference_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int unit_z, int64_t seg_len,
@@ -325,6 +445,7 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
     void* __restrict__ emb, float* __restrict__ scale, float* __restrict__ norm2) {
   extern __shared__ float2 tq[];  // [stride][kM] omega^(f_k q): block rolling only
   __shared__ LetterMul ltab[2][5];
+  __shared__ LetterMul ptab[2][25];
   const bool blockwise = stride > 1 && stride <= kBlockMax && stride <= N;
   if (blockwise) {
     for (int v = threadIdx.x; v < stride * kM; v += blockDim.x) {
@@ -333,6 +454,10 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
     }
   }
   if (threadIdx.x < 10) ltab[threadIdx.x / 5][threadIdx.x % 5] = letter_mul_entry(threadIdx.x / 5, threadIdx.x % 5);
+  if (threadIdx.x < 50) {
+    const int hh = threadIdx.x / 25, e = threadIdx.x % 25;
+    ptab[hh][e] = letter_pair_entry(hh, e / 5, e % 5);
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   // wavefront-uniform, so that the segment's bookkeeping stays in scalar registers
@@ -352,82 +477,24 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
   emit_window<PREC, RED>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
   // Letter t = 0 .. n_slides-1 of the segment leaves at start s0 + t + 1 (it
-  // is ref[s0 + t]) while ref[s0 + t + N] enters; the letters of the next 64
-  // are loaded while the current 64 roll.
+  // is ref[s0 + t]) while ref[s0 + t + N] enters.
   const int64_t s0 = j0 * stride;
   const int64_t n_slides = (j1 - 1 - j0) * stride;
-  int64_t j = j0;
-  int out_l = lane < n_slides ? (int)ref[s0 + lane] : 255;
-  int in_l = lane < n_slides ? (int)ref[s0 + lane + N] : 255;
+  RollState st{c0, c1, j0};
   if (blockwise) {
-    // omega^(f N) and omega^(-f stride) from the FP64 table, rounded once
-    const double2 zN = cmul64(phase64[(int64_t)(N - 1) * kM + k], phase64[kM + k]);
-    const double2 ws = stride < N ? phase64[(int64_t)stride * kM + k] : zN;
-    const float2 R = make_float2((float)ws.x, -(float)ws.y);
-    const float2 z = make_float2((float)zN.x, (float)zN.y);
-    float2 i0 = make_float2(0.f, 0.f), i1 = i0;  // I_j (O_j is taken from the state at once)
-    int q = 0;
-    for (int64_t tb = 0; tb < n_slides; tb += 64) {
-      const int64_t tn = tb + 64 + lane;
-      const int out_next = tn < n_slides ? (int)ref[s0 + tn] : 255;
-      const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
-      const int cnt = (int)min<int64_t>(64, n_slides - tb);
-      for (int i = 0; i < cnt; ++i) {
-        const int o = __builtin_amdgcn_readlane(out_l, i);
-        const int n = __builtin_amdgcn_readlane(in_l, i);
-        const float2 t = tq[q * kM + k];
-        letter_fma(c0, c1, ltab[h][min(o, 4)], -1.f, t);
-        if (unit_z)  // integer factors: omega^(f N) = 1
-          letter_fma(c0, c1, ltab[h][min(n, 4)], 1.f, t);
-        else
-          letter_fma(i0, i1, ltab[h][min(n, 4)], 1.f, t);
-        if (++q == stride) {
-          q = 0;
-          if (!unit_z) {
-            const float2 u0 = cmul(z, i0), u1 = cmul(z, i1);
-            c0 = make_float2(c0.x + u0.x, c0.y + u0.y);
-            c1 = make_float2(c1.x + u1.x, c1.y + u1.y);
-            i0 = make_float2(0.f, 0.f);
-            i1 = i0;
-          }
-          c0 = cmul(c0, R);
-          c1 = cmul(c1, R);
-          ++j;
-          emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
-        }
-      }
-      out_l = out_next;
-      in_l = in_next;
-    }
+    if (unit_z)
+      roll<PREC, RED, true, true>(ref, s0, n_slides, N, stride, k, lane, phase64, step32, tq, ltab,
+                                  ptab, st, side, emb, scale, norm2);
+    else
+      roll<PREC, RED, false, true>(ref, s0, n_slides, N, stride, k, lane, phase64, step32, tq, ltab,
+                                   ptab, st, side, emb, scale, norm2);
   } else {
-    // one letter at a time: E <- omega^-f (E - [out]) + omega^(f (N-1)) [in]
-    const float4 st = step32[k];
-    const float2 rot = make_float2(st.x, st.y);  // omega^-f
-    const float2 inc = make_float2(st.z, st.w);  // omega^(f (N-1))
-    int until_emit = stride;
-    for (int64_t tb = 0; tb < n_slides; tb += 64) {
-      const int64_t tn = tb + 64 + lane;
-      const int out_next = tn < n_slides ? (int)ref[s0 + tn] : 255;
-      const int in_next = tn < n_slides ? (int)ref[s0 + tn + N] : 255;
-      const int cnt = (int)min<int64_t>(64, n_slides - tb);
-      for (int i = 0; i < cnt; ++i) {
-        const int o = __builtin_amdgcn_readlane(out_l, i);
-        const int n = __builtin_amdgcn_readlane(in_l, i);
-        const LetterMul wo = ltab[h][min(o, 4)];
-        c0.x -= wo.m0;
-        c1.x -= wo.m1;
-        c0 = cmul(c0, rot);
-        c1 = cmul(c1, rot);
-        letter_fma(c0, c1, ltab[h][min(n, 4)], 1.f, inc);
-        if (--until_emit == 0) {
-          until_emit = stride;
-          ++j;
-          emit_window<PREC, RED>(j, lane, N, c0, c1, emb, side, scale, norm2);
-        }
-      }
-      out_l = out_next;
-      in_l = in_next;
-    }
+    if (unit_z)
+      roll<PREC, RED, true, false>(ref, s0, n_slides, N, stride, k, lane, phase64, step32, tq, ltab,
+                                   ptab, st, side, emb, scale, norm2);
+    else
+      roll<PREC, RED, false, false>(ref, s0, n_slides, N, stride, k, lane, phase64, step32, tq,
+                                    ltab, ptab, st, side, emb, scale, norm2);
   }
   side_finish(side, lane, norm2, scale);
 }
