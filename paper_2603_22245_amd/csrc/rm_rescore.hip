@@ -12,9 +12,10 @@
 // of its candidate windows are one matrix product: rows (string, letter) of
 // one-hot indicators [letter at position p], times the FP32 phase table
 // [p][factor] (§2.1-§2.2: component (k, L) sums the phases of the positions
-// holding L).  The indicators are exact in FP32, so the FP32 MFMA reproduces the
-// direct sums up to the order of FP32 additions, and each table row is read
-// once per read instead of once per string.
+// holding L).  The table is split exactly into three bfloat16 parts (x = hi +
+// mid + lo) and the indicators are exact in bfloat16, so three bf16 MFMAs with
+// FP32 accumulation reproduce the FP32 direct sums up to the order of FP32
+// additions; each table row is read once per read instead of once per string.
 #include "rm_internal.h"
 #include "rm_tokens.h"
 
@@ -88,14 +89,35 @@ __device__ __forceinline__ void sort_and_write(uint64_t key, int lane, int64_t r
   if (lane < k) write_list_entry(key, &top_idx[r * k + lane], &top_score[r * k + lane]);
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Exact split of an FP32 value into three bfloat16 bit patterns, x = hi + mid +
+// lo: hi keeps the sign, exponent and top 7 stored mantissa bits of x
+// (truncated), so x - hi is exact and has at most 16 significant bits; mid
+// keeps the top 8 of those, and the exact remainder has at most 8 (bfloat16
+// has the exponent range of FP32, so no part underflows).
+__device__ __forceinline__ void split_bf16x3(float x, uint32_t& hi, uint32_t& mid, uint32_t& lo) {
+  const uint32_t h = __float_as_uint(x) & 0xffff0000u;
+  const float r1 = x - __uint_as_float(h);
+  const uint32_t m = __float_as_uint(r1) & 0xffff0000u;
+  const float r2 = r1 - __uint_as_float(m);
+  hi = h >> 16;
+  mid = m >> 16;
+  lo = __float_as_uint(r2) >> 16;
+}
+
 // Plain rescore, one wavefront per read (four per block).  Strings: s = 0 is
 // the read head, s = 1 .. k_fetch the candidates, taken in passes of 8 RB:
 // RB blocks of 32 rows hold the rows (s, L), row = 4 (s - s0) + L, of the
 // pass's strings s0 .. s0 + 8 RB - 1 (the head, in the first pass, stays in
-// registers for the later ones).  Per step of two positions
-// p, p+1 a lane contributes A[row = lane % 32][p + lane / 32] = [letter == L]
-// and B[p + lane / 32][col = lane % 32] = table reals (2 factor + re/im), for
-// the two 32-column blocks of the 64 table reals.
+// registers for the later ones).  Positions go 64 at a time: the block splits
+// that chunk of the table into its three bfloat16 parts in LDS, each wavefront
+// stages its strings' letters, then four steps of 16 positions take
+// 32x32x16 bf16 MFMAs: A[row = lane % 32][p] = 2 [letter == L] for the eight
+// positions p = 16 st + 8 (lane / 32) + 0..7 (2 keeps one byte of the bf16
+// pattern; the sums are halved at the end, exactly), B the table part's
+// [p][col = lane % 32] for the two 32-column blocks of the 64 table reals.
 template <int RB>
 __global__ __launch_bounds__(256) void rescore_mfma_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride,
@@ -103,19 +125,25 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
     const int64_t* __restrict__ off, int32_t R, int k_fetch, const int32_t* __restrict__ cand,
     int k, int32_t* __restrict__ top_idx, float* __restrict__ top_score) {
   constexpr int SMAX = 8 * RB;
-  __shared__ uint8_t letters_all[4][SMAX][64];
+  // letters 0..3, 4 for none (past N, a short head, an invalid candidate, a code above 3)
+  __shared__ __attribute__((aligned(16))) uint8_t letters_all[4][SMAX][64];
+  // the table chunk's parts: [part][column block][8 positions][column] of 8 bf16
+  __shared__ u32x4 tparts[3][2][8][32];
   __shared__ float mat_all[4][32][2 * kM + 1];  // one row block of the product
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r = (int64_t)blockIdx.x * 4 + wave;
-  if (r >= R) return;  // whole wavefront
+  const bool active = r < R;  // inactive wavefronts still stage the table
   uint8_t(*letters)[64] = letters_all[wave];
   float(*mat)[2 * kM + 1] = mat_all[wave];
   const int S = 1 + k_fetch;
-  const int64_t start = off[r];
-  const bool head_ok = off[r + 1] - start >= N;
+  const int64_t start = active ? off[r] : 0;
+  const bool head_ok = active && off[r + 1] - start >= N;
   const int half = lane >> 5, col = lane & 31;
   const int kf = lane >> 1, h = lane & 1;
+  // byte lookup: letter b -> 0x40 (the high byte of bf16 2.0) when b is this
+  // lane's row letter (row & 3 = col & 3), else 0
+  const uint32_t onehot_tab = 0x40u << (8 * (col & 3));
   float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);
   float X = 0.f;
   bool xdeg = true;
@@ -124,53 +152,88 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
   for (int s0 = 0; s0 < S; s0 += SMAX) {
     const int SP = min(SMAX, S - s0);  // strings of this pass
     f32x16 acc[RB][2];
-  #pragma unroll
+#pragma unroll
     for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = f32x16{};
 
     for (int pb = 0; pb < N; pb += 64) {
-      // stage the 64 letters of every string at positions pb .. pb+63 (255 =
-      // none: past N, a short head or an invalid candidate)
-      for (int sl = 0; sl < SP; ++sl) {
-        const int sx = s0 + sl;
-        const uint8_t* base = nullptr;
-        if (sx == 0) {
-          if (head_ok) base = seq + start;
-        } else {
-          const int32_t j = cand[r * k_fetch + sx - 1];
-          if (j >= 0 && j < W) base = ref + (int64_t)j * stride;
+      __syncthreads();  // the previous chunk's table parts and letters are read
+      // table parts: thread t builds the fragments (column block cb, positions
+      // 8 pg .. 8 pg + 7, column col) for two (cb, pg) pairs
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int f = (threadIdx.x >> 5) + 8 * u;  // 0..15
+        const int cb = f >> 3, pg = f & 7, c = threadIdx.x & 31;
+        uint32_t hi[8], mid[8], lo[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+          const int pos = pb + 8 * pg + jj;
+          const float x = pos < N ? tab[(int64_t)pos * (2 * kM) + cb * 32 + c] : 0.f;
+          split_bf16x3(x, hi[jj], mid[jj], lo[jj]);
         }
-        letters[sl][lane] = (base != nullptr && pb + lane < N) ? base[pb + lane] : (uint8_t)255;
+        tparts[0][cb][pg][c] = u32x4{hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16,
+                                     hi[6] | hi[7] << 16};
+        tparts[1][cb][pg][c] = u32x4{mid[0] | mid[1] << 16, mid[2] | mid[3] << 16,
+                                     mid[4] | mid[5] << 16, mid[6] | mid[7] << 16};
+        tparts[2][cb][pg][c] = u32x4{lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16,
+                                     lo[6] | lo[7] << 16};
       }
-      __builtin_amdgcn_wave_barrier();
-      const int steps = min(32, (N - pb + 1) >> 1);
-      for (int t = 0; t < steps; ++t) {
-        const int pl = 2 * t + half;
-        const int pos = pb + pl;
-        const bool inb = pos < N;
-        float b[2];
-  #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) b[cb] = inb ? tab[(int64_t)pos * (2 * kM) + cb * 32 + col] : 0.f;
-  #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int row = rb * 32 + col;
-          const int sl = row >> 2;
-          const float a = (sl < SP && letters[sl][pl] == (row & 3)) ? 1.f : 0.f;
-  #pragma unroll
-          for (int cb = 0; cb < 2; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[cb], acc[rb][cb], 0, 0, 0);
+      // this wavefront's strings: the 64 letters at positions pb .. pb+63
+      if (active) {
+        for (int sl = 0; sl < SMAX; ++sl) {
+          const int sx = s0 + sl;
+          const uint8_t* base = nullptr;
+          if (sl < SP) {
+            if (sx == 0) {
+              if (head_ok) base = seq + start;
+            } else {
+              const int32_t j = cand[r * k_fetch + sx - 1];
+              if (j >= 0 && j < W) base = ref + (int64_t)j * stride;
+            }
+          }
+          const int L = (base != nullptr && pb + lane < N) ? (int)base[pb + lane] : 4;
+          letters[sl][lane] = (uint8_t)min(L, 4);
         }
       }
-      __builtin_amdgcn_wave_barrier();  // every lane is done with this chunk's letters
+      __syncthreads();
+      if (active) {
+        const int steps = min(4, (N - pb + 15) >> 4);
+        for (int st = 0; st < steps; ++st) {
+          bf16x8 b[3][2];
+#pragma unroll
+          for (int pt = 0; pt < 3; ++pt)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              b[pt][cb] = __builtin_bit_cast(bf16x8, tparts[pt][cb][2 * st + half][col]);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            // row rb*32 + col: string rb*8 + col/4, letter col & 3
+            const uint2 w = *reinterpret_cast<const uint2*>(&letters[rb * 8 + (col >> 2)][16 * st + 8 * half]);
+            const uint32_t h0 = __builtin_amdgcn_perm(0u, onehot_tab, w.x);  // 4 bytes 0x40 / 0
+            const uint32_t h1 = __builtin_amdgcn_perm(0u, onehot_tab, w.y);
+            const u32x4 av{__builtin_amdgcn_perm(0u, h0, 0x010c000cu), __builtin_amdgcn_perm(0u, h0, 0x030c020cu),
+                           __builtin_amdgcn_perm(0u, h1, 0x010c000cu), __builtin_amdgcn_perm(0u, h1, 0x030c020cu)};
+            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+              for (int pt = 2; pt >= 0; --pt)  // small parts first
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[pt][cb], acc[rb][cb], 0, 0, 0);
+          }
+        }
+      }
     }
 
+    if (!active) continue;  // (no barrier below)
     // ---- per string: components of this lane (factor kf, letters 2h, 2h+1)
-  #pragma unroll
+#pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-      // result block: lane holds column cb*32 + col of rows 8 (v/4) + 4 half + v%4
-  #pragma unroll
+      // result block: lane holds column cb*32 + col of rows 8 (v/4) + 4 half + v%4;
+      // the indicators were 2, so the sums are halved (exactly)
+#pragma unroll
       for (int cb = 0; cb < 2; ++cb)
-  #pragma unroll
-        for (int v = 0; v < 16; ++v) mat[8 * (v >> 2) + 4 * half + (v & 3)][cb * 32 + col] = acc[rb][cb][v];
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          mat[8 * (v >> 2) + 4 * half + (v & 3)][cb * 32 + col] = 0.5f * acc[rb][cb][v];
       __builtin_amdgcn_wave_barrier();
       for (int sl = 0; sl < 8; ++sl) {
         const int sx = s0 + rb * 8 + sl;
@@ -199,7 +262,7 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
       __builtin_amdgcn_wave_barrier();  // before the next block overwrites mat
     }
   }  // passes
-  sort_and_write(mykey, lane, r, k, top_idx, top_score);
+  if (active) sort_and_write(mykey, lane, r, k, top_idx, top_score);
 }
 
 // Learned encoding, with the token offsets of the reference (rows = reference
