@@ -160,7 +160,7 @@ template <int PREC, int KR>
 struct ThrK {
   using RF = RowFmt<PREC, KR>;
   static constexpr int NF = PREC == RM_FP32 ? 1 : 2;      // fragments (16 reads) per wavefront
-  static constexpr int WAVES = 4;
+  static constexpr int WAVES = 8;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int READS = WAVES * NF * 16;
   static constexpr int RB = RF::RB;
@@ -168,6 +168,7 @@ struct ThrK {
   static constexpr int AU4 = RF::AU4;
   static constexpr int TW = kBlkW;                          // windows per tile
   static constexpr int TILE = TW * RB;
+  static constexpr int STAGES = TILE <= 16384 ? 4 : 2;     // LDS ring
   // 1 KB copies per tile: wavefronts w < NH make LH of them, the others LL;
   // each also copies the tile's thresholds (and FP8 window scales)
   static constexpr int C = TILE / 1024;
@@ -177,12 +178,31 @@ struct ThrK {
   static_assert(C >= 1 && TILE % 1024 == 0, "tile");
 };
 
+// Wait until at most `later` tiles' copies of this wavefront (issued after the
+// tile being waited for) are in flight.
+template <int LT, int STAGES>
+__device__ __forceinline__ void wait_tiles(int later) {
+  if constexpr (STAGES >= 4) {
+    if (later >= 2) {
+      wait_vmcnt<2 * LT>();
+      return;
+    }
+  }
+  if (later >= 1)
+    wait_vmcnt<LT>();
+  else
+    wait_vmcnt<0>();
+}
+
 // Product pass of the regime.  Block = (read tile, window chunk); the read
-// tile sits in registers, window tiles of 32 are copied straight from global
-// memory into a two-stage LDS ring (rows XOR-swizzled as the top-k product
-// stores them), each wavefront copying its share plus its own copy of the
-// tile's thresholds (and FP8 window scales), and waiting for its own copies
-// before the block barrier.
+// tile sits in registers (eight wavefronts), window tiles of 32 are copied
+// straight from global memory into a ring of LDS stages (rows XOR-swizzled as
+// the top-k product stores them), each wavefront copying its share plus its
+// own copy of the tile's thresholds (and FP8 window scales).  One barrier per
+// tile: after it every wavefront's copies of the tile are in, and the stage
+// read before it is free for the copies STAGES - 1 tiles ahead.  A lane holds
+// one window column, so its 16 scores share one cut: their maximum is tested
+// first, and only a passing lane's scores are tested one by one.
 template <int PREC, int KR>
 __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kernel(
     const uint8_t* __restrict__ index, const float* __restrict__ win_scale, int64_t W,
@@ -192,9 +212,9 @@ __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kern
   using K = ThrK<PREC, KR>;
   using RF = typename K::RF;
   constexpr bool kFp8 = PREC == RM_FP8_E4M3;
-  __shared__ __attribute__((aligned(16))) uint8_t ring[2][K::TILE];
-  __shared__ float side[2][2][K::WAVES][K::TW];  // [stage][thr, scale][wave][window]
-  __shared__ float rsq[K::READS];  // squared read scale per read slot, 0 past the last read
+  constexpr int S = K::STAGES;
+  __shared__ __attribute__((aligned(16))) uint8_t ring[S][K::TILE];
+  __shared__ float side[S][2][K::WAVES][K::TW];  // [stage][thr, scale][wave][window]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 5, col = lane & 31;
@@ -205,7 +225,8 @@ __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kern
   if (wbeg >= wend) return;  // uniform over the block
   const int ntiles = (int)((wend - wbeg + K::TW - 1) / K::TW);
 
-  // A fragments, and each read slot's squared scale
+  // A fragments (rows past the last read are zero, so their F is 0), and for
+  // FP8 the squared read scale of each of this lane's 16 score slots
   uint4 a[K::NF][K::AU4];
 #pragma unroll
   for (int f = 0; f < K::NF; ++f) {
@@ -215,12 +236,16 @@ __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kern
     for (int u = 0; u < K::AU4; ++u)
       a[f][u] = row < 2 * (int64_t)R ? src[RF::lane_chunk(g, u)] : make_uint4(0, 0, 0, 0);
   }
-  if (tid < K::READS) {
-    const int64_t r = read0 + tid;
-    float sc = 1.f;
-    if constexpr (kFp8) sc = r < R ? read_scale[r] : 0.f;
-    rsq[tid] = r < R ? sc * sc : 0.f;
-  }
+  float rsq[K::NF][8];
+#pragma unroll
+  for (int f = 0; f < K::NF; ++f)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t r = read0 + wave * K::NF * 16 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+      float sc = 1.f;
+      if constexpr (kFp8) sc = r < R ? read_scale[r] : 0.f;
+      rsq[f][q] = sc * sc;
+    }
   __builtin_amdgcn_s_waitcnt(0);  // the fragments and scales, before any copy is in flight
 
   const uint32_t ring_lds = lds_offset(ring);
@@ -235,7 +260,7 @@ __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kern
     doff[i] = (uint32_t)RF::swap(r, pos % K::CPR) * 16u;  // the logical chunk stored there
   }
   auto issue = [&](int t) {
-    const int stage = t & 1;
+    const int stage = t % S;
     const int64_t tb = wbeg + (int64_t)t * K::TW;
 #pragma unroll
     for (int i = 0; i < K::LH; ++i) {
@@ -259,19 +284,17 @@ __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kern
   uint32_t kx, kx2;
   RF::keys(g, col, kx, kx2);
 
-  issue(0);
+  for (int t = 0; t < S - 1 && t < ntiles; ++t) issue(t);
   for (int t = 0; t < ntiles; ++t) {
-    const int stage = t & 1;
-    if (t + 1 < ntiles) {
-      issue(t + 1);          // into the stage every wavefront finished reading before the
-      if (K::NH == 0 || wave < K::NH)  // last barrier; then this wavefront's copies of tile t are in
-        wait_vmcnt<K::LTH>();
-      else
-        wait_vmcnt<K::LTL>();
-    } else {
-      wait_vmcnt<0>();
-    }
-    __syncthreads();         // ... and every wavefront's
+    const int stage = t % S;
+    // this wavefront's copies of tile t: later tiles issued so far are t+1 .. t+S-2
+    const int later = min(S - 2, ntiles - 1 - t);
+    if (K::NH == 0 || wave < K::NH)
+      wait_tiles<K::LTH, S>(later);
+    else
+      wait_tiles<K::LTL, S>(later);
+    __syncthreads();  // every wavefront's copies of tile t; stage (t-1) % S is read
+    if (t + S - 1 < ntiles) issue(t + S - 1);
     f32x16 acc[K::NF][1];
 #pragma unroll
     for (int f = 0; f < K::NF; ++f) acc[f][0] = f32x16{};
@@ -285,20 +308,29 @@ __global__ __launch_bounds__((ThrK<PREC, KR>::THREADS)) void threshold_scan_kern
       const float sc = side[stage][1][wave][col];
       sj2 = sc * sc;
     }
+    float F[K::NF][8];
+    float fmax = 0.f;
 #pragma unroll
     for (int f = 0; f < K::NF; ++f)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const float re = acc[f][0][2 * q], im = acc[f][0][2 * q + 1];
-        const int slot = wave * K::NF * 16 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
-        const float F = (re * re + im * im) * (rsq[slot] * sj2);
-        if (colok && F > 0.f && F >= cut) {
-          const int64_t r = read0 + slot;
-          const unsigned long long p = atomicAdd(pool_n, 1ull);
-          if (p < pool_cap) pool[p] = ((uint64_t)r << 32) | (uint64_t)(uint32_t)j;
-        }
+        F[f][q] = fmaf(re, re, im * im);
+        if constexpr (kFp8) F[f][q] *= rsq[f][q] * sj2;
+        fmax = fmaxf(fmax, F[f][q]);
       }
-    __syncthreads();         // stage `stage` is refilled by the next iteration's copies
+    if (colok && fmax > 0.f && fmax >= cut) {  // rare
+#pragma unroll
+      for (int f = 0; f < K::NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (F[f][q] > 0.f && F[f][q] >= cut) {
+            const int slot = wave * K::NF * 16 + f * 16 + 4 * (q >> 1) + 2 * g + (q & 1);
+            const int64_t r = read0 + slot;
+            const unsigned long long p = atomicAdd(pool_n, 1ull);
+            if (p < pool_cap) pool[p] = ((uint64_t)r << 32) | (uint64_t)(uint32_t)j;
+          }
+    }
   }
 }
 
