@@ -289,7 +289,7 @@ def main():
                                ("value", "unit", "ms_per_step", "steps", "config",
                                 "window_scores_per_s", "reads_per_s_prebuilt_index_eager",
                                 "breakdown_ms_eager", "accuracy", "roofline", "fp8_path",
-                                "fp32_path") if key in b}
+                                "fp8_letter_sum_path", "fp32_path") if key in b}
     print(json.dumps(out), flush=True)
 
 
@@ -393,7 +393,7 @@ def run_map(args, w, ref, reads, precision, k, k_fetch, stride, radius, tok, ste
             "accuracy": acc, "roofline": roofline}
 
 
-def _batched_pass(ref, reads, k, k_fetch, precision, steps, warmup):
+def _batched_pass(ref, reads, k, k_fetch, precision, steps, warmup, reduced=None):
     """Bucket indexes, the autotuned grouped persistent scoring launch, and the
     whole step (index builds, read heads, product + top-k, FP32 rescore)
     captured in a HIP graph and replayed `steps` times; returns the mapper (to
@@ -401,7 +401,7 @@ def _batched_pass(ref, reads, k, k_fetch, precision, steps, warmup):
     import torch
     from paper_2603_22245_amd import mapper
     bm = mapper.BatchMapper(ref, reads.seq, reads.offsets, k=k, k_fetch=k_fetch,
-                            precision=precision)
+                            precision=precision, reduced=reduced)
     stream = torch.cuda.Stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     with torch.cuda.stream(stream):
@@ -502,18 +502,26 @@ def bench_batching(args, fp32: bool = None, low=None):
     }
     prebuilt = {precision: parts[1] + parts[2] + parts[3]}
     step_ms = {precision: ms_per_step}
+    # further low-precision legs: (precision, row form, output key)
+    legs = []
     if low is not None and len(low) > 1:
-        p2 = low[1]
-        bm2, ms2, parts2, best2 = _batched_pass(ref, reads, k, k_fetch, p2, args.steps, 1)
+        legs.append((low[1], None, f"{low[1]}_path"))
+        if low[1] == "fp8" and not getattr(args, "no_fp8_letter_sum", False):
+            legs.append(("fp8", True, "fp8_letter_sum_path"))
+    for p2, red2, key2 in legs:
+        bm2, ms2, parts2, best2 = _batched_pass(ref, reads, k, k_fetch, p2, args.steps, 1,
+                                                reduced=red2)
         flops2 = sum(b.reads.n * b.index.n_windows * 4 * b.index.real_dim for b in bm2.buckets)
+        rr2 = sorted({b.index.real_dim for b in bm2.buckets})
         ids2, sc2 = bm2.results()
         acc2 = batching_accuracy(ref, reads, bm2, ids2, sc2, k)
         bm2.close()
         del bm2
         torch.cuda.empty_cache()
-        prebuilt[p2] = parts2[1] + parts2[2] + parts2[3]
-        step_ms[p2] = ms2
-        out[f"{p2}_path"] = {
+        name2 = key2[:-len("_path")]
+        prebuilt[name2] = parts2[1] + parts2[2] + parts2[3]
+        step_ms[name2] = ms2
+        out[key2] = {
             "value": round(R / (ms2 / 1e3), 1), "unit": "reads/s", "ms_per_step": round(ms2, 3),
             "reads_per_s_prebuilt_index_eager": round(R / (prebuilt[p2] / 1e3), 1),
             "breakdown_ms_eager": {"encode_references": round(parts2[0], 3),
@@ -526,7 +534,9 @@ def bench_batching(args, fp32: bool = None, low=None):
                          "peak": PEAK_TFLOPS[p2], "unit": "TFLOP/s",
                          "frac": round(flops2 / (parts2[2] / 1e3) / 1e12 / PEAK_TFLOPS[p2], 4),
                          "traffic": None},
-            "note": f"the same graph-replayed step with {p2} indexes and read heads "
+            "row_reals": rr2,
+            "note": f"the same graph-replayed step with {p2} indexes and read heads"
+                    f"{' in the letter-sum form' if red2 else ''} "
                     f"(tuning read_tile={best2.read_tile}, chunk_tiles={best2.chunk_tiles})"}
     if fp32 and precision != "fp32":
         bm32, ms32, parts32, best32 = _batched_pass(ref, reads, k, k_fetch, "fp32", 1, 1)

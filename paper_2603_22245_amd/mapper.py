@@ -385,11 +385,12 @@ class BatchMapper:
     """Reads of uneven length: one index per head length (bucket), every bucket's
     reads scored against its index in one persistent launch (rm_score_topk_groups),
     then FP32 rescore per bucket.  Buckets without reads are skipped; reads shorter
-    than the smallest bucket are left unmapped (id -1)."""
+    than the smallest bucket are left unmapped (id -1).  `reduced` picks the row
+    form of the indexes as in build_index (None: the precision's default)."""
 
     def __init__(self, ref: np.ndarray, seq: np.ndarray, offsets: np.ndarray, k: int = 8,
                  k_fetch: int = 16, precision: str = "fp16", buckets=BUCKETS,
-                 stride_div: int = 100, device="cuda"):
+                 stride_div: int = 100, device="cuda", reduced=None):
         torch = _torch()
         self.k, self.k_fetch, self.precision = k, k_fetch, precision
         self.n_reads = int(offsets.shape[0] - 1)
@@ -403,7 +404,7 @@ class BatchMapper:
                 continue
             stride = max(1, n_b // stride_div)
             index = build_index(d_ref, window_len=n_b, stride=stride, precision=precision,
-                                device=device)
+                                device=device, reduced=reduced)
             # this bucket's reads, concatenated (each keeps all its letters)
             lens = offsets[ids + 1] - offsets[ids]
             off = np.zeros(ids.size + 1, dtype=np.int64)

@@ -29,9 +29,10 @@ def plain_data():
     return ref, reads, mapping.read_heads(reads.seq, reads.offsets, 150)
 
 
-def _index(ref, precision="fp32", N=150, stride=1):
+def _index(ref, precision="fp32", N=150, stride=1, reduced=None):
     from paper_2603_22245_amd import mapper
-    return mapper.build_index(ref, window_len=N, stride=stride, precision=precision)
+    return mapper.build_index(ref, window_len=N, stride=stride, precision=precision,
+                              reduced=reduced)
 
 
 @pytest.mark.parametrize("N,stride,err,copies,rank", [(150, 1, 0.05, 16, 1), (150, 3, 0.3, 8, 0),
@@ -78,8 +79,9 @@ def _check_regime(hits, F, cut):
     return n_hits
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp8"])
-def test_threshold_regime_matches_oracle(precision, plain_data):
+@pytest.mark.parametrize("precision,reduced", [("fp32", None), ("fp16", None), ("fp8", None),
+                                               ("fp32", True), ("fp16", False), ("fp8", True)])
+def test_threshold_regime_matches_oracle(precision, reduced, plain_data):
     """The plain workload (200 reads, 19,851 windows) with seeded synthetic
     thresholds: most windows cut at 0.3-0.9, 1 % at 0.005 (so that every read
     passes about 200 windows: lists far longer than any top-k), a floor of
@@ -99,7 +101,7 @@ def test_threshold_regime_matches_oracle(precision, plain_data):
     seq = seq[keep]
     off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
     heads = mapping.read_heads(seq, off, 150)
-    index = _index(ref, precision)
+    index = _index(ref, precision, reduced=reduced)
     W = index.n_windows
     rng = np.random.default_rng(81)
     thr = rng.uniform(0.3, 0.9, W).astype(np.float32)
