@@ -16,6 +16,7 @@
 // mid + lo) and the indicators are exact in bfloat16, so three bf16 MFMAs with
 // FP32 accumulation reproduce the FP32 direct sums up to the order of FP32
 // additions; each table row is read once per read instead of once per string.
+#include "rm_bf16.h"
 #include "rm_internal.h"
 #include "rm_tokens.h"
 
@@ -89,24 +90,6 @@ __device__ __forceinline__ void sort_and_write(uint64_t key, int lane, int64_t r
   if (lane < k) write_list_entry(key, &top_idx[r * k + lane], &top_score[r * k + lane]);
 }
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Exact split of an FP32 value into three bfloat16 bit patterns, x = hi + mid +
-// lo: hi keeps the sign, exponent and top 7 stored mantissa bits of x
-// (truncated), so x - hi is exact and has at most 16 significant bits; mid
-// keeps the top 8 of those, and the exact remainder has at most 8 (bfloat16
-// has the exponent range of FP32, so no part underflows).
-__device__ __forceinline__ void split_bf16x3(float x, uint32_t& hi, uint32_t& mid, uint32_t& lo) {
-  const uint32_t h = __float_as_uint(x) & 0xffff0000u;
-  const float r1 = x - __uint_as_float(h);
-  const uint32_t m = __float_as_uint(r1) & 0xffff0000u;
-  const float r2 = r1 - __uint_as_float(m);
-  hi = h >> 16;
-  mid = m >> 16;
-  lo = __float_as_uint(r2) >> 16;
-}
-
 // Plain rescore, one wavefront per read (four per block).  Strings: s = 0 is
 // the read head, s = 1 .. k_fetch the candidates, taken in passes of 8 RB:
 // RB blocks of 32 rows hold the rows (s, L), row = 4 (s - s0) + L, of the
@@ -157,26 +140,7 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
 
     for (int pb = 0; pb < N; pb += 64) {
       __syncthreads();  // the previous chunk's table parts and letters are read
-      // table parts: thread t builds the fragments (column block cb, positions
-      // 8 pg .. 8 pg + 7, column col) for two (cb, pg) pairs
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int f = (threadIdx.x >> 5) + 8 * u;  // 0..15
-        const int cb = f >> 3, pg = f & 7, c = threadIdx.x & 31;
-        uint32_t hi[8], mid[8], lo[8];
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-          const int pos = pb + 8 * pg + jj;
-          const float x = pos < N ? tab[(int64_t)pos * (2 * kM) + cb * 32 + c] : 0.f;
-          split_bf16x3(x, hi[jj], mid[jj], lo[jj]);
-        }
-        tparts[0][cb][pg][c] = u32x4{hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16,
-                                     hi[6] | hi[7] << 16};
-        tparts[1][cb][pg][c] = u32x4{mid[0] | mid[1] << 16, mid[2] | mid[3] << 16,
-                                     mid[4] | mid[5] << 16, mid[6] | mid[7] << 16};
-        tparts[2][cb][pg][c] = u32x4{lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16,
-                                     lo[6] | lo[7] << 16};
-      }
+      stage_table_parts(tab, pb, N, tparts, threadIdx.x, 256);
       // this wavefront's strings: the 64 letters at positions pb .. pb+63
       if (active) {
         for (int sl = 0; sl < SMAX; ++sl) {
@@ -208,11 +172,7 @@ __global__ __launch_bounds__(256) void rescore_mfma_kernel(
           for (int rb = 0; rb < RB; ++rb) {
             // row rb*32 + col: string rb*8 + col/4, letter col & 3
             const uint2 w = *reinterpret_cast<const uint2*>(&letters[rb * 8 + (col >> 2)][16 * st + 8 * half]);
-            const uint32_t h0 = __builtin_amdgcn_perm(0u, onehot_tab, w.x);  // 4 bytes 0x40 / 0
-            const uint32_t h1 = __builtin_amdgcn_perm(0u, onehot_tab, w.y);
-            const u32x4 av{__builtin_amdgcn_perm(0u, h0, 0x010c000cu), __builtin_amdgcn_perm(0u, h0, 0x030c020cu),
-                           __builtin_amdgcn_perm(0u, h1, 0x010c000cu), __builtin_amdgcn_perm(0u, h1, 0x030c020cu)};
-            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+            const bf16x8 a = onehot_fragment(w, onehot_tab);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll

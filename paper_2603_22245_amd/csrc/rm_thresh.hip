@@ -26,6 +26,7 @@
 // keeps those with F >= max(thr_j, floor) and F > 0, and writes them ranked by
 // (F desc, window id asc).
 
+#include "rm_bf16.h"
 #include "rm_score_kernel.h"
 
 namespace rm {
@@ -155,6 +156,155 @@ __global__ __launch_bounds__(64 * kThrWaves) void window_thresholds_kernel(
 }
 
 // ---- the regime's product pass
+
+// The same thresholds with the strings' vectors from one MFMA product: each
+// wavefront writes the letters of its window (string 0) and of its copies
+// (strings 1..copies) into LDS, drawing the copies exactly as
+// window_thresholds_kernel does, then the block multiplies the one-hot
+// (string, letter) rows of its four windows with the FP32 table split into
+// three bfloat16 parts (rm_bf16.h), in passes of 8 RB strings and chunks of
+// 64 positions, and each wavefront takes the fidelities of its copies with
+// its window from the product.  `np` is N rounded up to 64, `sp` the strings
+// rounded up to whole passes; letters past a string's end are 4 (none).
+template <int RB>
+__global__ __launch_bounds__(64 * kThrWaves) void window_thresholds_mfma_kernel(
+    const uint8_t* __restrict__ ref, int64_t G, int64_t W, int N, int np, int stride,
+    const float* __restrict__ tab, uint32_t T1, int copies, int sp, int rank, uint32_t seed,
+    int max_steps, float* __restrict__ thr) {
+  constexpr int SMAX = 8 * RB;
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  extern __shared__ __attribute__((aligned(16))) uint8_t letters_dyn[];  // [waves][sp][np]
+  __shared__ u32x4 tparts[3][2][8][32];
+  __shared__ float mat_all[kThrWaves][32][2 * kM + 1];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t j = (int64_t)blockIdx.x * kThrWaves + wave;
+  const bool active = j < W;  // inactive wavefronts still stage the table
+  uint8_t* letters = letters_dyn + (size_t)wave * sp * np;
+  float(*mat)[2 * kM + 1] = mat_all[wave];
+  const int S = 1 + copies;
+  const int half = lane >> 5, col = lane & 31;
+  const int kf = lane >> 1, h = lane & 1;
+
+  // ---- letters of the window and its copies (4 for none)
+  if (active) {
+    const int64_t start = j * stride;
+    for (int s = 0; s < sp; ++s)
+      for (int p = lane; p < np; p += 64)
+        letters[s * np + p] = (s == 0 && p < N) ? (uint8_t)min((int)ref[start + p], 4) : (uint8_t)4;
+    __builtin_amdgcn_wave_barrier();
+    for (int c = 0; c < copies; ++c) {
+      uint8_t* out = letters + (size_t)(c + 1) * np;
+      int64_t pos = start;  // next reference letter
+      int n = 0;            // letters emitted
+      for (int t0 = 0; t0 < max_steps && n < N; t0 += 64) {
+        const int t = t0 + lane;
+        const Words4 d = philox4x32_10((uint32_t)j, (uint32_t)(j >> 32), (uint32_t)c, (uint32_t)t,
+                                       seed, 0u);
+        const bool live = t < max_steps;
+        // 0 insertion, 1 deletion, 2 substitution, 3 match
+        int kind = d.x < T1 ? 0 : d.x < 2u * T1 ? 1 : d.x < 3u * T1 ? 2 : 3;
+        const uint64_t consume = __ballot(live && kind != 0);
+        const int64_t p = pos + lanes_below(consume);
+        if (p >= G) kind = 0;
+        const bool emit = live && kind != 1;
+        const uint64_t em = __ballot(emit);
+        const int q = lanes_below(em);  // this step's output index in the group
+        if (emit && n + q < N) {
+          int L;
+          if (kind == 0) {
+            L = (int)(d.y & 3u);
+          } else {
+            const int R0 = ref[p];
+            L = (kind == 3 || R0 > 3) ? R0 : (R0 + 1 + (int)(d.z % 3u)) & 3;
+          }
+          out[n + q] = (uint8_t)min(L, 4);
+        }
+        n += min(__popcll(em), N - n);
+        pos += __popcll(__ballot(live && kind != 0));
+      }
+    }
+  }
+
+  float2 x0 = make_float2(0.f, 0.f), x1 = make_float2(0.f, 0.f);  // the window
+  float X = 0.f;
+  float mine = 3.0e38f;  // lane c keeps copy c's fidelity
+  const uint32_t onehot_tab = 0x40u << (8 * (col & 3));
+  for (int s0 = 0; s0 < S; s0 += SMAX) {
+    const int SP = min(SMAX, S - s0);
+    f32x16 acc[RB][2];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = f32x16{};
+    for (int pb = 0; pb < N; pb += 64) {
+      __syncthreads();  // the previous chunk's table parts are read (and the letters written)
+      stage_table_parts(tab, pb, N, tparts, threadIdx.x, 64 * kThrWaves);
+      __syncthreads();
+      if (active) {
+        const int steps = min(4, (N - pb + 15) >> 4);
+        for (int st = 0; st < steps; ++st) {
+          bf16x8 b[3][2];
+#pragma unroll
+          for (int pt = 0; pt < 3; ++pt)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              b[pt][cb] = __builtin_bit_cast(bf16x8, tparts[pt][cb][2 * st + half][col]);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const int s = s0 + rb * 8 + (col >> 2);  // < sp
+            const uint2 w =
+                *reinterpret_cast<const uint2*>(&letters[(size_t)s * np + pb + 16 * st + 8 * half]);
+            const bf16x8 a = onehot_fragment(w, onehot_tab);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+              for (int pt = 2; pt >= 0; --pt)  // small parts first
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[pt][cb], acc[rb][cb], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (!active) continue;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          mat[8 * (v >> 2) + 4 * half + (v & 3)][cb * 32 + col] = 0.5f * acc[rb][cb][v];
+      __builtin_amdgcn_wave_barrier();
+      for (int sl = 0; sl < 8; ++sl) {
+        const int sx = s0 + rb * 8 + sl;
+        if (rb * 8 + sl >= SP) break;
+        const float2 c0 = make_float2(mat[4 * sl + 2 * h][2 * kf], mat[4 * sl + 2 * h][2 * kf + 1]);
+        const float2 c1 = make_float2(mat[4 * sl + 2 * h + 1][2 * kf], mat[4 * sl + 2 * h + 1][2 * kf + 1]);
+        const float Y = wave_sum(c0.x * c0.x + c0.y * c0.y + c1.x * c1.x + c1.y * c1.y);
+        if (sx == 0) {
+          x0 = c0;
+          x1 = c1;
+          X = Y;
+          continue;
+        }
+        const float F = fidelity32(x0, x1, X, c0, c1, Y, N);
+        if (lane == sx - 1) mine = F;
+      }
+      __builtin_amdgcn_wave_barrier();  // before the next block overwrites mat
+    }
+  }
+  if (!active) return;
+  // ascending bitonic sort of the copies' fidelities over the 64 lanes
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+    for (int dd = kk >> 1; dd > 0; dd >>= 1) {
+      const float other = __shfl_xor(mine, dd, 64);
+      const bool up = (lane & kk) == 0;
+      const bool lower = (lane & dd) == 0;
+      const float lo = fminf(mine, other), hi = fmaxf(mine, other);
+      mine = (lower == up) ? lo : hi;
+    }
+  }
+  if (lane == rank) thr[j] = mine;
+}
 
 template <int PREC, int KR>
 struct ThrK {
@@ -457,6 +607,23 @@ hipError_t launch_window_thresholds(const rm_index& idx, const uint8_t* ref, flo
   const uint32_t T1 = (uint32_t)floor((double)err / 3.0 * 4294967296.0);
   const int N = idx.p.window_len;
   const int64_t blocks = (idx.n_windows + kThrWaves - 1) / kThrWaves;
+  // the product form while the letters of a block's strings fit in 64 KB of LDS
+  const int S = 1 + copies;
+  const int rb = min(5, (S + 7) / 8);
+  const int sp = (S + 8 * rb - 1) / (8 * rb) * (8 * rb);
+  const int np = (N + 63) / 64 * 64;
+  const size_t lds = (size_t)kThrWaves * sp * np;
+  if (copies <= 64 && lds <= 65536) {
+    auto kern = rb <= 1 ? window_thresholds_mfma_kernel<1>
+              : rb == 2 ? window_thresholds_mfma_kernel<2>
+              : rb == 3 ? window_thresholds_mfma_kernel<3>
+              : rb == 4 ? window_thresholds_mfma_kernel<4> : window_thresholds_mfma_kernel<5>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kThrWaves), lds, s, ref, idx.ref_len,
+                       idx.n_windows, N, np, idx.p.stride,
+                       reinterpret_cast<const float*>(idx.d_phase32), T1, copies, sp, rank, seed,
+                       8 * N + 64, thr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(window_thresholds_kernel, dim3((unsigned)blocks), dim3(64 * kThrWaves), 0, s,
                      ref, idx.ref_len, idx.n_windows, N, idx.p.stride,
                      reinterpret_cast<const float2*>(idx.d_phase32), T1, copies, rank, seed,
