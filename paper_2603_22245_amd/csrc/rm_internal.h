@@ -262,6 +262,8 @@ struct ScoreGroup {
   int64_t chunk_windows;
   int32_t P;                 // window chunks
   int32_t item_begin;        // first work item of this group
+  int32_t thin;              // 1: read tiles of half the block's reads (a group whose
+                             // reads would leave most of a full tile empty)
   uint64_t* lists;           // [R][P][kp] keys
   uint32_t* gthr;            // [R] shared k-th-best per read
   uint64_t* gslot;           // [R][kScoreSlots] keys of finished chunks (slot = id mod kScoreSlots)
@@ -281,6 +283,7 @@ struct Tuning {
 
 struct GroupPlan {
   int read_tiles;
+  int thin;  // read tiles of half the launch's read tile
   int chunks;
   int64_t chunk_windows;
   size_t lists_offset;

@@ -133,6 +133,17 @@ ScorePlan plan_score(int precision, int n_groups, const int64_t* W, const int32_
   for (int i = 0; i < n_groups; ++i) {
     GroupPlan& gp = p.g[i];
     gp.read_tiles = (int)(((int64_t)R[i] + rt - 1) / rt);
+    // 256-read tiles run two fragments per wavefront; a group that would leave
+    // a quarter or more of its padded reads empty takes 128-read tiles (one
+    // fragment per wavefront, half the work per tile) in the same launch
+    gp.thin = 0;
+    if (rt == 256) {
+      const int64_t t128 = ((int64_t)R[i] + 127) / 128;
+      if (4 * 128 * t128 <= 3 * 256 * (int64_t)gp.read_tiles) {
+        gp.thin = 1;
+        gp.read_tiles = (int)t128;
+      }
+    }
     int64_t tiles = (W[i] + kPlanW - 1) / kPlanW;
     int64_t ct = t.chunk_tiles;
     if (ct <= 0) {
@@ -193,6 +204,7 @@ hipError_t launch_score_topk(const rm_index* idx, const ScorePlan& plan,
     G.chunk_windows = gp.chunk_windows;
     G.P = gp.chunks;
     G.item_begin = item;
+    G.thin = gp.thin;
     G.lists = reinterpret_cast<uint64_t*>(base + gp.lists_offset);
     G.gthr = reinterpret_cast<uint32_t*>(base + gp.thr_offset);
     G.gslot = reinterpret_cast<uint64_t*>(base + gp.slot_offset);

@@ -800,7 +800,8 @@ __device__ __forceinline__ void score_item(const ScoreGroup& G, int chunk, int t
 // (group, chunk, read tile) from a device counter until all are done.  Items
 // are numbered chunk-major within each group, so concurrently running blocks
 // stream the same windows.  Every block leaves the loop once the counter has
-// passed the last item.
+// passed the last item.  With two fragments per wavefront, a thin group's
+// items run with one (half the reads per tile, half the work per tile).
 template <int PREC, int NF, int WAVES, int KP, int ENT, int STAGES, int NB, int KR>
 __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
   using K = ScoreKernel<PREC, NF, WAVES, KP, ENT, STAGES, NB, KR>;
@@ -822,6 +823,14 @@ __global__ __launch_bounds__(WAVES * 64) void score_topk_kernel(ScoreLaunch L) {
     while (gi + 1 < L.n_groups && item >= L.g[gi + 1].item_begin) ++gi;
     const ScoreGroup& G = L.g[gi];
     const int local = item - G.item_begin;
+    if constexpr (NF == 2) {
+      if (G.thin) {  // half-size read tiles: one fragment per wavefront
+        score_item<PREC, 1, WAVES, KP, ENT, STAGES, NB, KR>(G, local / G.read_tiles,
+                                                         local % G.read_tiles, ring, ring_scale,
+                                                         lst, cnt, thr, rsq);
+        continue;
+      }
+    }
     score_item<PREC, NF, WAVES, KP, ENT, STAGES, NB, KR>(G, local / G.read_tiles,
                                                       local % G.read_tiles, ring, ring_scale, lst,
                                                       cnt, thr, rsq);

@@ -282,6 +282,44 @@ def test_score_topk_and_rescore(precision, k_fetch, reduced, plain_data, plain_o
     assert_lists_exact(exact, rec, k_fetch, k, precision)
 
 
+@pytest.mark.parametrize("precision,n_reads", [("fp16", 40), ("fp8", 40), ("fp16", 300),
+                                               ("fp8", 300)])
+def test_thin_read_tiles(precision, n_reads, plain_data, plain_oracle):
+    """Batches that would leave a quarter or more of their 256-read tiles empty
+    (40 reads: one tile; 300 reads: two) run with 128-read tiles in the
+    256-read launch: candidates within the product's tolerance, rescored lists
+    equal to the oracle's up to ties."""
+    torch = torch_cuda()
+    ref, reads, heads = plain_data
+    _, _, _, F = plain_oracle
+    n = min(n_reads, reads.n)
+    sub = synth.Reads(reads.seq[:reads.offsets[n]], reads.offsets[:n + 1], reads.truth[:n])
+    F = F[:n]
+    if n_reads > reads.n:  # repeat the plain reads to reach the batch size
+        reps = -(-n_reads // reads.n)
+        seq = np.concatenate([reads.seq] * reps)
+        lens = np.tile(np.diff(reads.offsets), reps)[:n_reads]
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        sub = synth.Reads(seq[:off[-1]], off, np.tile(reads.truth, reps)[:n_reads])
+        F = np.tile(plain_oracle[3], (reps, 1))[:n_reads]
+    index = _build(ref, precision)
+    k, k_fetch = 8, 16
+    rb, bufs = _map(index, sub, k, k_fetch)
+    cidx = bufs.cand_idx.cpu().numpy()
+    csc = bufs.cand_score.cpu().numpy()
+    _check_candidates(cidx, csc, F, TOL[precision], absolute=precision == "fp8")
+    W = F.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(W), F.shape), -F), axis=1)
+    o_idx = order[:, :k]
+    o_F = np.take_along_axis(F, o_idx, 1)
+    tidx = bufs.top_idx.cpu().numpy()
+    top_F = np.take_along_axis(F, tidx, 1)
+    rec = mapping.recall_at_k(tidx, o_idx, o_F, top_F)
+    exact = mapping.same_up_to_ties(tidx, o_F, top_F)
+    print(f"{precision} {n_reads} reads: rescored recall@8 {rec:.4f}, exact lists {exact.mean():.4f}")
+    assert_lists_exact(exact, rec, k_fetch, k, precision)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "fp8"])
 def test_sixty_four_candidates_and_long_lists(precision, plain_data, plain_oracle):
     """64 product candidates (lists of 64 keys per chunk, merged two keys per
