@@ -523,7 +523,7 @@ def bench_batching(args, fp32: bool = None, low=None):
         step_ms[name2] = ms2
         out[key2] = {
             "value": round(R / (ms2 / 1e3), 1), "unit": "reads/s", "ms_per_step": round(ms2, 3),
-            "reads_per_s_prebuilt_index_eager": round(R / (prebuilt[p2] / 1e3), 1),
+            "reads_per_s_prebuilt_index_eager": round(R / (prebuilt[name2] / 1e3), 1),
             "breakdown_ms_eager": {"encode_references": round(parts2[0], 3),
                                    "encode_reads": round(parts2[1], 3),
                                    "score_topk_grouped": round(parts2[2], 3),

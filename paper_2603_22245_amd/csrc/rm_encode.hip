@@ -14,10 +14,13 @@
 // a block at a time: E_{j+1} = omega^(-f s) (E_j - O_j + omega^(f N) I_j), where
 // O_j and I_j add omega^(f q) over the s letters leaving (starts j s + q) and
 // entering (j s + N + q), q < s -- one turn per window instead of one per
-// letter.  Longer strides slide letter by letter.  Each wavefront walks a
+// letter; with integer factors and strides of 4 or more the block sums come
+// from bf16 MFMA products of signed one-hot rows with the phase table.
+// Longer strides slide letter by letter.  Each wavefront walks a
 // segment of consecutive windows; at the segment start the state is computed
 // directly from the letters in FP64 (the re-anchor), then rolled in FP32.
 // Each window is normalised (§2.3) and written in the index precision.
+#include "rm_bf16.h"
 #include "rm_internal.h"
 #include "rm_tokens.h"
 
@@ -174,7 +177,11 @@ __device__ __forceinline__ void letter_sum_rows(float2 u0, float2 u1, int h, Row
 // Write the lane's three reals of a letter-sum row (reals 3 lane .. 3 lane + 2)
 // in the requested precision; FP8 codes and the returned scale as for
 // store_row, the scale making the dequantised row exactly as long as the
-// FP32 row.
+// FP32 row.  A window row (WINDOW) is the projection of a unit vector whose
+// all-letters part is zero (the form is used only on references of letters
+// only), so its length is 1 up to rounding and the dequantised row is made
+// unit length, as store_row does; a read head may hold other codes, whose
+// all-letters part the projection drops, so its length is summed.
 template <int PREC, bool WINDOW = false>
 __device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, Row3 x) {
   if constexpr (PREC == RM_FP32) {
@@ -210,8 +217,12 @@ __device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, R
     dst[2] = (uint8_t)w2;
     const float2 d01 = unpack_fp8x2(w01), d2 = unpack_fp8x2(w2);
     const float q2 = wave_total(d01.x * d01.x + d01.y * d01.y + d2.x * d2.x);
-    const float y2 = wave_total(x.v[0] * x.v[0] + x.v[1] * x.v[1] + x.v[2] * x.v[2]);
-    return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) * sqrtf(y2) : s;
+    if constexpr (WINDOW) {
+      return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) : s;  // 1 ulp
+    } else {
+      const float y2 = wave_total(x.v[0] * x.v[0] + x.v[1] * x.v[1] + x.v[2] * x.v[2]);
+      return q2 > 0.f ? __builtin_amdgcn_rsqf(q2) * sqrtf(y2) : s;
+    }
   }
 }
 
@@ -436,6 +447,188 @@ __device__ __forceinline__ void roll(const uint8_t* __restrict__ ref, int64_t s0
     off_l = off_next;
   }
   st = RollState{c0, c1, j};
+}
+
+// ---- block rolling on the matrix cores (integer factors, strides kMfmaStrideMin
+// .. kBlockMax, at most N)
+//
+// With omega^(f N) = 1 the block update is E_{j+1} = omega^(-f s) (E_j + D_j),
+// D_j[k][L] = sum_{q < s} omega^(f_k q) ([ref[j s + N + q] = L] - [ref[j s + q] = L]):
+// the product of signed one-hot (window, letter) rows with the table [q][64
+// reals] of omega^(f_k q).  Eight windows at a time, the wavefront forms it on
+// 32x32x16 bf16 MFMAs (rows 4 w + L, columns 2 k + re/im, 16 positions per
+// instruction): the indicators are exact in bfloat16 and the FP32 table splits
+// exactly into three bfloat16 parts, so with FP32 accumulation D_j is the
+// FP32 block sum up to the order of the additions.  D goes through LDS into
+// the lane layout of the rolling state; the turn and the window's emission
+// stay as in the letter-by-letter path.
+constexpr int kMfmaStrideMin = 4;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Eight letter codes at positions pos .. pos+7 (little-endian bytes of the
+// pair), 4 for positions outside [0, len).
+__device__ __forceinline__ uint2 letters8_bytes(const uint8_t* __restrict__ ref, int64_t pos,
+                                                int64_t len) {
+  uint32_t w[2] = {0u, 0u};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t p = pos + i;
+    const uint32_t c = (p >= 0 && p < len) ? (uint32_t)ref[p] : 4u;
+    w[i >> 2] |= c << (8 * (i & 3));
+  }
+  return make_uint2(w[0], w[1]);
+}
+
+// The eight letters leaving (positions po ..) and entering (pi ..) as
+// letters8_bytes gives them: where the aligned dwords around both runs lie
+// inside the string, three dword loads each (issued together) and two byte
+// alignments; bytewise otherwise.
+__device__ __forceinline__ void letters8_pair(const uint8_t* __restrict__ ref, int64_t po,
+                                              int64_t pi, int64_t len, uint2& out, uint2& in) {
+  const uint32_t mis = (uint32_t)(reinterpret_cast<uintptr_t>(ref) & 3);
+  const uint32_t so = (uint32_t)(po + mis) & 3, si = (uint32_t)(pi + mis) & 3;
+  const int64_t bo = po - so, bi = pi - si;  // offsets of 4-byte aligned addresses
+  if (bo >= 0 && bo + 12 <= len && bi >= 0 && bi + 12 <= len) {
+    const uint32_t* d = reinterpret_cast<const uint32_t*>(ref + bo);
+    const uint32_t* e = reinterpret_cast<const uint32_t*>(ref + bi);
+    const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
+    const uint32_t e0 = e[0], e1 = e[1], e2 = e[2];
+    out = make_uint2(__builtin_amdgcn_alignbyte(d1, d0, so), __builtin_amdgcn_alignbyte(d2, d1, so));
+    in = make_uint2(__builtin_amdgcn_alignbyte(e1, e0, si), __builtin_amdgcn_alignbyte(e2, e1, si));
+  } else {
+    out = letters8_bytes(ref, po, len);
+    in = letters8_bytes(ref, pi, len);
+  }
+}
+
+// Bytes of `w` clamped to at most 4 (codes above 3 are no letter).
+__device__ __forceinline__ uint32_t clamp_codes(uint32_t w) {
+  typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+  const u16x2 four{4, 4};
+  const u16x2 ev = __builtin_elementwise_min(__builtin_bit_cast(u16x2, w & 0x00ff00ffu), four);
+  const u16x2 od = __builtin_elementwise_min(__builtin_bit_cast(u16x2, (w >> 8) & 0x00ff00ffu), four);
+  return __builtin_bit_cast(uint32_t, ev) | (__builtin_bit_cast(uint32_t, od) << 8);
+}
+
+// A fragment of eight positions of a signed (window, letter) row: bf16 2.0
+// where only the entering letter is the row's letter, -2.0 where only the
+// leaving one is, 0 otherwise (byte 0x40 / 0xc0 as the high byte; sums come out
+// doubled).  `tab` has byte L = 0x40 for the row's letter L.
+__device__ __forceinline__ bf16x8 signed_onehot(uint2 in, uint2 out, uint32_t tab) {
+  uint32_t v[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const uint32_t bi = __builtin_amdgcn_perm(0u, tab, clamp_codes(i ? in.y : in.x));
+    const uint32_t bo = __builtin_amdgcn_perm(0u, tab, clamp_codes(i ? out.y : out.x));
+    const uint32_t x = bi ^ bo;
+    v[i] = x | ((bo & x) << 1);  // 0x40 -> 0xc0 where the leaving letter matched
+  }
+  const u32x4 av{__builtin_amdgcn_perm(0u, v[0], 0x010c000cu), __builtin_amdgcn_perm(0u, v[0], 0x030c020cu),
+                 __builtin_amdgcn_perm(0u, v[1], 0x010c000cu), __builtin_amdgcn_perm(0u, v[1], 0x030c020cu)};
+  return __builtin_bit_cast(bf16x8, av);
+}
+
+// NS = 16-position steps covering the stride (1, 2 or 4).
+template <int PREC, bool RED, int NS>
+__global__ __launch_bounds__(256) void encode_reference_mfma_kernel(
+    const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,
+    const double2* __restrict__ phase64, void* __restrict__ emb, float* __restrict__ scale,
+    float* __restrict__ norm2) {
+  __shared__ float dbuf[4][8][64][4];  // per wavefront: D of 8 windows [w][column][letter], doubled
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  if (seg >= n_seg) return;
+  const int k = lane >> 1, h = lane & 1;
+  const int64_t j0 = seg * seg_len;
+  const int64_t j1 = min(W, j0 + seg_len);
+  const int64_t len = (W - 1) * (int64_t)stride + N;  // letters the windows cover
+
+  // B fragments: column 32 cb + (lane & 31) = real (factor c >> 1, part c & 1),
+  // positions 16 t + 8 (lane >> 5) + i, zero at and past the stride
+  bf16x8 b[NS][3][2];
+#pragma unroll
+  for (int t = 0; t < NS; ++t)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int c = 32 * cb + (lane & 31);
+      uint32_t hi[8], mid[8], lo[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int q = 16 * t + 8 * (lane >> 5) + i;
+        float x = 0.f;
+        if (q < stride) {
+          const double2 e = phase64[(int64_t)q * kM + (c >> 1)];
+          x = (float)((c & 1) ? e.y : e.x);
+        }
+        split_bf16x3(x, hi[i], mid[i], lo[i]);
+      }
+      const u32x4 vh{hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16, hi[6] | hi[7] << 16};
+      const u32x4 vm{mid[0] | mid[1] << 16, mid[2] | mid[3] << 16, mid[4] | mid[5] << 16,
+                     mid[6] | mid[7] << 16};
+      const u32x4 vl{lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16, lo[6] | lo[7] << 16};
+      b[t][0][cb] = __builtin_bit_cast(bf16x8, vh);
+      b[t][1][cb] = __builtin_bit_cast(bf16x8, vm);
+      b[t][2][cb] = __builtin_bit_cast(bf16x8, vl);
+    }
+  // omega^(-f stride), rounded once from FP64 (the table holds rows below N)
+  const double2 ws = stride < N ? phase64[(int64_t)stride * kM + k]
+                                : cmul64(phase64[(int64_t)(N - 1) * kM + k], phase64[kM + k]);
+  const float2 rot = make_float2((float)ws.x, -(float)ws.y);
+
+  // Re-anchor: the first window of the segment, directly, in FP64.
+  double2 a0, a1;
+  direct_sum(ref + j0 * stride, N, phase64, lane, a0, a1);
+  float2 c0 = make_float2((float)a0.x, (float)a0.y);
+  float2 c1 = make_float2((float)a1.x, (float)a1.y);
+  SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
+  emit_window<PREC, RED>(j0, lane, N, c0, c1, emb, side, scale, norm2);
+
+  // A role: row lane & 31 = 4 w + L (window jc + w, letter L), positions
+  // 8 (lane >> 5) .. + 7 of each 16-position step
+  const int aw = (lane & 31) >> 2, aL = lane & 3;
+  const uint32_t tab = 0x40u << (8 * aL);
+  float(*db)[64][4] = dbuf[wv];
+  for (int64_t jc = j0; jc < j1 - 1; jc += 8) {
+    f32x16 acc[2] = {f32x16{}, f32x16{}};
+    const int64_t sw = (jc + aw) * (int64_t)stride;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int q0 = 16 * t + 8 * (lane >> 5);
+      bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+      if (q0 < stride) {
+        uint2 lo, li;
+        letters8_pair(ref, sw + q0, sw + N + q0, len, lo, li);
+        a = signed_onehot(li, lo, tab);
+      }
+#pragma unroll
+      for (int pt = 2; pt >= 0; --pt) {
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t][pt][0], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t][pt][1], acc[1], 0, 0, 0);
+      }
+    }
+    // D rows 8 g + 4 (lane >> 5) + L: window 2 g + (lane >> 5), letter L
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int L = 0; L < 4; ++L) db[2 * g + (lane >> 5)][32 * cb + (lane & 31)][L] = acc[cb][4 * g + L];
+    __builtin_amdgcn_wave_barrier();
+    const int nw = (int)min<int64_t>(8, j1 - 1 - jc);
+    for (int w = 0; w < nw; ++w) {
+      // letters 2h, 2h+1 of the real parts (column 2k) and imaginary parts (2k+1)
+      const float* dre = &db[w][2 * k][2 * h];
+      const float* dim = &db[w][2 * k + 1][2 * h];
+      c0 = make_float2(fmaf(0.5f, dre[0], c0.x), fmaf(0.5f, dim[0], c0.y));
+      c1 = make_float2(fmaf(0.5f, dre[1], c1.x), fmaf(0.5f, dim[1], c1.y));
+      c0 = cmul(c0, rot);
+      c1 = cmul(c1, rot);
+      emit_window<PREC, RED>(jc + w + 1, lane, N, c0, c1, emb, side, scale, norm2);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  side_finish(side, lane, norm2, scale);
 }
 
 template <int PREC, bool RED>
@@ -802,13 +995,20 @@ __global__ __launch_bounds__(256) void encode_reads_tokens_kernel(
 hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_params& p,
                                    const double* phase64, const float* step32, void* emb,
                                    float* scale, float* norm2, hipStream_t s) {
+  const bool blockwise = p.stride > 1 && p.stride <= kBlockMax && p.stride <= p.window_len;
+  const int unit_z = p.schedule == RM_SCHED_DEFAULT ? 1 : 0;
+  const bool on_mfma = blockwise && unit_z && p.stride >= kMfmaStrideMin;
   // Segment = window starts between two FP64 re-anchors: the caller's value,
-  // or enough segments for the chip (about 8192) with at most 4096 starts each.
+  // or W / 4096 clamped to 256 .. 512 (at least about 4096 wavefronts where W
+  // allows; longer segments leave a ragged last round of blocks, shorter ones
+  // repeat the N-letter FP64 re-anchor more often).  Rolling on the matrix
+  // cores makes a window cheap next to the re-anchor (N >= 4 stride letters):
+  // W / 2048 clamped to 256 .. 2048 there.
   int64_t seg = p.reanchor;
   if (seg <= 0) {
-    seg = (W + 8191) / 8192;
+    seg = on_mfma ? W / 2048 : W / 4096;
     if (seg < 256) seg = 256;
-    if (seg > 4096) seg = 4096;
+    if (seg > (on_mfma ? 2048 : 512)) seg = on_mfma ? 2048 : 512;
   }
   int64_t n_seg = (W + seg - 1) / seg;
   const int waves = 4;
@@ -823,9 +1023,36 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
                      : encode_reference_kernel<RM_FP8_E4M3, false>;
   // block rolling (stride 2 .. kBlockMax, at most N) takes the table of
   // omega^(f q), q < stride, in LDS; integer factors make omega^(f N) = 1
-  const bool blockwise = p.stride > 1 && p.stride <= kBlockMax && p.stride <= p.window_len;
   const size_t lds = blockwise ? (size_t)p.stride * kM * sizeof(float2) : 0;
-  const int unit_z = p.schedule == RM_SCHED_DEFAULT ? 1 : 0;
+  if (on_mfma) {
+    const int ns = p.stride <= 16 ? 1 : p.stride <= 32 ? 2 : 4;
+    auto pick = [&](auto k1, auto k2, auto k4) { return ns == 1 ? k1 : ns == 2 ? k2 : k4; };
+    decltype(&encode_reference_mfma_kernel<RM_FP32, false, 1>) mk;
+    if (p.precision == RM_FP16)
+      mk = p.reduced ? pick(encode_reference_mfma_kernel<RM_FP16, true, 1>,
+                            encode_reference_mfma_kernel<RM_FP16, true, 2>,
+                            encode_reference_mfma_kernel<RM_FP16, true, 4>)
+                     : pick(encode_reference_mfma_kernel<RM_FP16, false, 1>,
+                            encode_reference_mfma_kernel<RM_FP16, false, 2>,
+                            encode_reference_mfma_kernel<RM_FP16, false, 4>);
+    else if (p.precision == RM_FP8_E4M3)
+      mk = p.reduced ? pick(encode_reference_mfma_kernel<RM_FP8_E4M3, true, 1>,
+                            encode_reference_mfma_kernel<RM_FP8_E4M3, true, 2>,
+                            encode_reference_mfma_kernel<RM_FP8_E4M3, true, 4>)
+                     : pick(encode_reference_mfma_kernel<RM_FP8_E4M3, false, 1>,
+                            encode_reference_mfma_kernel<RM_FP8_E4M3, false, 2>,
+                            encode_reference_mfma_kernel<RM_FP8_E4M3, false, 4>);
+    else
+      mk = p.reduced ? pick(encode_reference_mfma_kernel<RM_FP32, true, 1>,
+                            encode_reference_mfma_kernel<RM_FP32, true, 2>,
+                            encode_reference_mfma_kernel<RM_FP32, true, 4>)
+                     : pick(encode_reference_mfma_kernel<RM_FP32, false, 1>,
+                            encode_reference_mfma_kernel<RM_FP32, false, 2>,
+                            encode_reference_mfma_kernel<RM_FP32, false, 4>);
+    hipLaunchKernelGGL(mk, dim3((unsigned)blocks), dim3(64 * waves), 0, s, ref, W, p.window_len,
+                       p.stride, seg, n_seg, ph, emb, scale, norm2);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, s, ref, W, p.window_len,
                      p.stride, unit_z, seg, n_seg, ph, st, emb, scale, norm2);
   return hipGetLastError();

@@ -96,6 +96,62 @@ def test_rolling_encoder_fp32(N, stride, sched):
     assert np.max(np.abs(gn2[ok] - n2[ok]) / n2[ok]) < 1e-4
 
 
+@pytest.mark.parametrize("N,stride,reanchor", [(100, 4, 0), (150, 16, 300), (300, 17, 0),
+                                               (400, 32, 77), (500, 33, 0), (6400, 64, 0),
+                                               (64, 64, 5), (200, 5, 9)])
+def test_block_rolling_on_matrix_cores_fp32(N, stride, reanchor):
+    """Strides 4..64 with integer factors roll on the matrix cores (block
+    sums as signed one-hot rows times the phase table, 16 positions per step:
+    one, two and four steps); segments of lengths that are not multiples of
+    the eight windows per product, a block of N letters, and codes other than
+    A, C, G, T (4 and 255) in the reference, which add nothing."""
+    torch = torch_cuda()
+    ref = synth.make_reference(60_000, gc=0.45, repeat_frac=0.05, seed=17)
+    rng = np.random.default_rng(17)
+    pos = rng.choice(ref.shape[0], 400, replace=False)
+    ref[pos[:200]] = 4
+    ref[pos[200:]] = 255
+    index = _build(ref, "fp32", window_len=N, stride=stride, reanchor=reanchor)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    Cn, n2 = oracle_windows(ref, N, stride)
+    assert got.shape == Cn.shape
+    ok = n2 >= 1e-3 * N
+    err = np.max(np.abs(got[ok] - Cn[ok]))
+    print(f"N={N} stride={stride} reanchor={reanchor}: W={got.shape[0]}, max |d| {err:.2e}")
+    assert err < 5e-5, err
+    gn2 = index.norms2().cpu().numpy()
+    assert np.max(np.abs(gn2[ok] - n2[ok]) / n2[ok]) < 1e-4
+
+
+@pytest.mark.parametrize("precision,reduced,N,stride", [("fp16", True, 400, 4), ("fp16", True, 1600, 16),
+                                                        ("fp8", False, 3200, 32), ("fp8", True, 6400, 64)])
+def test_block_rolling_on_matrix_cores_quantised(precision, reduced, N, stride):
+    """The batching buckets' shapes (N = 100 stride) in FP16 and FP8 rows, both
+    forms: stored rows within the rounding bounds of the oracle's vectors."""
+    torch = torch_cuda()
+    ref = synth.make_reference(80_000, gc=0.45, repeat_frac=0.08, seed=18)
+    index = _build(ref, precision, window_len=N, stride=stride, reduced=reduced)
+    torch.cuda.synchronize()
+    assert bool(index.params.reduced) == reduced
+    got = emb_to_complex(index, torch)
+    Cn, _ = oracle_windows(ref, N, stride)
+    Cn = stored_form(Cn, index)
+    assert got.shape == Cn.shape
+    if precision == "fp16":
+        bound_re = 2.0 ** -11 * np.abs(Cn.real) + 2e-5
+        bound_im = 2.0 ** -11 * np.abs(Cn.imag) + 2e-5
+    else:
+        scale = index.scales().cpu().numpy()
+        sc = np.exp2(np.round(np.log2(scale)))[:, None]
+        bound_re = fp8_bound(np.abs(Cn.real), sc) + 0.05 * np.abs(Cn.real)
+        bound_im = fp8_bound(np.abs(Cn.imag), sc) + 0.05 * np.abs(Cn.imag)
+        nz = np.abs(got).sum(axis=1) > 0
+        assert np.max(np.abs(np.linalg.norm(got[nz], axis=1) - 1)) < 1e-5
+    assert np.all(np.abs(got.real - Cn.real) <= bound_re)
+    assert np.all(np.abs(got.imag - Cn.imag) <= bound_im)
+
+
 def test_rolling_drift_over_long_segments():
     # 65,536 starts per FP64 re-anchor: the FP32 recurrence's error after the
     # longest segment stays far below FP16 rounding of a unit vector.
