@@ -20,6 +20,9 @@
 // segment of consecutive windows; at the segment start the state is computed
 // directly from the letters in FP64 (the re-anchor), then rolled in FP32.
 // Each window is normalised (§2.3) and written in the index precision.
+#include <mutex>
+#include <unordered_map>
+
 #include "rm_bf16.h"
 #include "rm_internal.h"
 #include "rm_tokens.h"
@@ -995,36 +998,12 @@ __global__ __launch_bounds__(256) void encode_reads_tokens_kernel(
 hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_params& p,
                                    const double* phase64, const float* step32, void* emb,
                                    float* scale, float* norm2, hipStream_t s) {
-  const bool blockwise = p.stride > 1 && p.stride <= kBlockMax && p.stride <= p.window_len;
-  const int unit_z = p.schedule == RM_SCHED_DEFAULT ? 1 : 0;
-  const bool on_mfma = blockwise && unit_z && p.stride >= kMfmaStrideMin;
-  // Segment = window starts between two FP64 re-anchors: the caller's value,
-  // or W / 4096 clamped to 256 .. 512 (at least about 4096 wavefronts where W
-  // allows; longer segments leave a ragged last round of blocks, shorter ones
-  // repeat the N-letter FP64 re-anchor more often).  Rolling on the matrix
-  // cores makes a window cheap next to the re-anchor (N >= 4 stride letters):
-  // W / 2048 clamped to 256 .. 2048 there.
-  int64_t seg = p.reanchor;
-  if (seg <= 0) {
-    seg = on_mfma ? W / 2048 : W / 4096;
-    if (seg < 256) seg = 256;
-    if (seg > (on_mfma ? 2048 : 512)) seg = on_mfma ? 2048 : 512;
-  }
-  int64_t n_seg = (W + seg - 1) / seg;
   const int waves = 4;
-  int64_t blocks = (n_seg + waves - 1) / waves;
   auto* ph = reinterpret_cast<const double2*>(phase64);
   auto* st = reinterpret_cast<const float4*>(step32);
-  auto kern = p.reduced ? encode_reference_kernel<RM_FP32, true> : encode_reference_kernel<RM_FP32, false>;
-  if (p.precision == RM_FP16)
-    kern = p.reduced ? encode_reference_kernel<RM_FP16, true> : encode_reference_kernel<RM_FP16, false>;
-  else if (p.precision == RM_FP8_E4M3)
-    kern = p.reduced ? encode_reference_kernel<RM_FP8_E4M3, true>
-                     : encode_reference_kernel<RM_FP8_E4M3, false>;
-  // block rolling (stride 2 .. kBlockMax, at most N) takes the table of
-  // omega^(f q), q < stride, in LDS; integer factors make omega^(f N) = 1
-  const size_t lds = blockwise ? (size_t)p.stride * kM * sizeof(float2) : 0;
-  if (on_mfma) {
+  const bool blockwise = p.stride > 1 && p.stride <= kBlockMax && p.stride <= p.window_len;
+  const int unit_z = p.schedule == RM_SCHED_DEFAULT ? 1 : 0;
+  if (blockwise && unit_z && p.stride >= kMfmaStrideMin) {
     const int ns = p.stride <= 16 ? 1 : p.stride <= 32 ? 2 : 4;
     auto pick = [&](auto k1, auto k2, auto k4) { return ns == 1 ? k1 : ns == 2 ? k2 : k4; };
     decltype(&encode_reference_mfma_kernel<RM_FP32, false, 1>) mk;
@@ -1049,10 +1028,70 @@ hipError_t launch_encode_reference(const uint8_t* ref, int64_t W, const rm_param
                      : pick(encode_reference_mfma_kernel<RM_FP32, false, 1>,
                             encode_reference_mfma_kernel<RM_FP32, false, 2>,
                             encode_reference_mfma_kernel<RM_FP32, false, 4>);
+    // Segments: the caller's value, or as few rounds of resident blocks as
+    // keep a segment within 2048 starts, each round full (a window is cheap
+    // here next to the segment's N-letter FP64 re-anchor, and a block left
+    // over for a round of its own costs a whole segment's time), at least 256
+    // starts.
+    int64_t seg = p.reanchor;
+    if (seg <= 0) {
+      // resident blocks per CU of this instantiation, queried once (the
+      // launch may be captured into a graph)
+      static std::mutex mu;
+      static std::unordered_map<const void*, int> per_cu_of;
+      int per_cu = 0, dev = 0, cus = 0;
+      {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = per_cu_of.find(reinterpret_cast<const void*>(mk));
+        if (it != per_cu_of.end()) {
+          per_cu = it->second;
+        } else {
+          if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mk, 64 * waves, 0) != hipSuccess ||
+              per_cu < 1)
+            per_cu = 1;
+          per_cu_of[reinterpret_cast<const void*>(mk)] = per_cu;
+        }
+      }
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          cus < 1)
+        cus = 256;
+      const int64_t resident = (int64_t)per_cu * cus * waves;  // wavefronts in one round
+      int64_t rounds = 1;
+      seg = (W + resident - 1) / resident;
+      while (seg > 2048) {
+        ++rounds;
+        seg = (W + rounds * resident - 1) / (rounds * resident);
+      }
+      if (seg < 256) seg = 256;
+    }
+    const int64_t n_seg = (W + seg - 1) / seg;
+    const int64_t blocks = (n_seg + waves - 1) / waves;
     hipLaunchKernelGGL(mk, dim3((unsigned)blocks), dim3(64 * waves), 0, s, ref, W, p.window_len,
                        p.stride, seg, n_seg, ph, emb, scale, norm2);
     return hipGetLastError();
   }
+  // Segment = window starts between two FP64 re-anchors: the caller's value,
+  // or W / 4096 clamped to 256 .. 512 (at least about 4096 wavefronts where W
+  // allows; longer segments leave a ragged last round of blocks, shorter ones
+  // repeat the N-letter FP64 re-anchor more often).
+  int64_t seg = p.reanchor;
+  if (seg <= 0) {
+    seg = W / 4096;
+    if (seg < 256) seg = 256;
+    if (seg > 512) seg = 512;
+  }
+  const int64_t n_seg = (W + seg - 1) / seg;
+  const int64_t blocks = (n_seg + waves - 1) / waves;
+  auto kern = p.reduced ? encode_reference_kernel<RM_FP32, true> : encode_reference_kernel<RM_FP32, false>;
+  if (p.precision == RM_FP16)
+    kern = p.reduced ? encode_reference_kernel<RM_FP16, true> : encode_reference_kernel<RM_FP16, false>;
+  else if (p.precision == RM_FP8_E4M3)
+    kern = p.reduced ? encode_reference_kernel<RM_FP8_E4M3, true>
+                     : encode_reference_kernel<RM_FP8_E4M3, false>;
+  // block rolling (stride 2 .. kBlockMax, at most N) takes the table of
+  // omega^(f q), q < stride, in LDS; integer factors make omega^(f N) = 1
+  const size_t lds = blockwise ? (size_t)p.stride * kM * sizeof(float2) : 0;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, s, ref, W, p.window_len,
                      p.stride, unit_z, seg, n_seg, ph, st, emb, scale, norm2);
   return hipGetLastError();
