@@ -67,14 +67,28 @@ __device__ __forceinline__ float wave_total(float v) {
 struct LetterMul {
   float m0, m1;
 };
+//
+// The letter-sum form (RED) keeps the rolling state in the letter-sum basis
+// instead: per factor the coordinates on the orthonormal letter weights
+// w_0 = (1,1,1,1)/2 (all letters), w_1 = (1,1,-1,-1)/2, w_2 = (1,-1,1,-1)/2,
+// w_3 = (1,-1,-1,1)/2 over (A,C,G,T), lane h holding coordinates 2h and
+// 2h + 1; a letter L then adds w_m[L] = +-1/2 of its term to every coordinate.
+__device__ __forceinline__ float letter_weight(int m, int L) {
+  if (L >= 4) return 0.f;
+  const int neg = (m == 1 && L >= 2) || (m == 2 && (L & 1)) || (m == 3 && (L == 1 || L == 2));
+  return neg ? -0.5f : 0.5f;
+}
+template <bool RED = false>
 __device__ __forceinline__ LetterMul letter_mul_entry(int hh, int L) {
+  if constexpr (RED) return LetterMul{letter_weight(2 * hh, L), letter_weight(2 * hh + 1, L)};
   return LetterMul{(L < 4 && L == 2 * hh) ? 1.f : 0.f, (L < 4 && L == 2 * hh + 1) ? 1.f : 0.f};
 }
 // With omega^(f N) = 1 (integer factors) a step adds the incoming letter's term
 // and removes the outgoing one's with the same factor, so one entry serves both:
 // [h][5 min(out, 4) + min(in, 4)] = multipliers of `in` minus those of `out`.
+template <bool RED = false>
 __device__ __forceinline__ LetterMul letter_pair_entry(int hh, int out, int in) {
-  const LetterMul a = letter_mul_entry(hh, out), b = letter_mul_entry(hh, in);
+  const LetterMul a = letter_mul_entry<RED>(hh, out), b = letter_mul_entry<RED>(hh, in);
   return LetterMul{b.m0 - a.m0, b.m1 - a.m1};
 }
 __device__ __forceinline__ int letter_pair_index(int packed) {  // out | in << 8
@@ -235,7 +249,9 @@ __device__ __forceinline__ float store_row3(void* base, int64_t row, int lane, R
 // with omega^(f_k) (at most 63 products, relative error below 2^-45).  The
 // letter is the same for the whole wavefront, so each position adds the phase
 // to one of four per-letter sums by a uniform branch; the lane keeps the two
-// sums of its own letters.  Codes above 3 add nothing.
+// sums of its own letters (RED: its two letter-sum coordinates, formed from
+// the four sums).  Codes above 3 add nothing.
+template <bool RED = false>
 __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int n,
                                            const double2* __restrict__ phase64, int lane,
                                            double2& a0, double2& a1) {
@@ -264,8 +280,17 @@ __device__ __forceinline__ void direct_sum(const uint8_t* __restrict__ str, int 
       t = make_double2(t.x * w.x - t.y * w.y, t.x * w.y + t.y * w.x);
     }
   }
-  a0 = h ? s2 : s0;
-  a1 = h ? s3 : s1;
+  if constexpr (RED) {
+    // h = 0: w_0, w_1 (s0 + s1 +- (s2 + s3)); h = 1: w_2, w_3 (s0 - s1 +- (s2 - s3))
+    const double sg = h ? -1.0 : 1.0;
+    const double2 u = make_double2(s0.x + sg * s1.x, s0.y + sg * s1.y);
+    const double2 v = make_double2(s2.x + sg * s3.x, s2.y + sg * s3.y);
+    a0 = make_double2(0.5 * (u.x + v.x), 0.5 * (u.y + v.y));
+    a1 = make_double2(0.5 * (u.x - v.x), 0.5 * (u.y - v.y));
+  } else {
+    a0 = h ? s2 : s0;
+    a1 = h ? s3 : s1;
+  }
 }
 
 // A window's squared norm and scale wait in lane registers (lane j - jb
@@ -310,19 +335,15 @@ __device__ __forceinline__ void emit_window(int64_t j, int lane, int N, float2 c
   const float inv = deg ? 0.f : __builtin_amdgcn_rsqf(n2);  // 1 ulp
   float s;
   if constexpr (RED) {
-    // The letter-sum row of the normalised vector: the combinations of
-    // letter_sum_rows taken on (c0, c1), the basis' factor 1/2 folded into
-    // the normalisation.
-    const float g = 0.5f * inv;
-    const float2 sm = make_float2(c0.x + c1.x, c0.y + c1.y);
-    const float2 df = make_float2(c0.x - c1.x, c0.y - c1.y);
-    const float spx = mdpp<0xB1>(sm.x), spy = mdpp<0xB1>(sm.y);  // partner lane (lane ^ 1)
-    const float dpx = mdpp<0xB1>(df.x), dpy = mdpp<0xB1>(df.y);
+    // The state is in the letter-sum basis: lane h = 0 holds (w_0, w_1) =
+    // (all letters, y1), h = 1 holds (y2, y3); the row's reals are (y1.re,
+    // y1.im, y2.re) for h = 0 and (y2.im, y3.re, y3.im) for h = 1.
+    const float p = mdpp<0xB1>(c0.x);  // the partner's (lane ^ 1) c0.x: y2.re for h = 0
     Row3 y;
-    if (lane & 1)  // (y2.im, y3.re, y3.im)
-      y = Row3{{g * (df.y + dpy), g * (dpx - df.x), g * (dpy - df.y)}};
-    else           // (y1.re, y1.im, y2.re)
-      y = Row3{{g * (sm.x - spx), g * (sm.y - spy), g * (df.x + dpx)}};
+    if (lane & 1)
+      y = Row3{{inv * c0.y, inv * c1.x, inv * c1.y}};
+    else
+      y = Row3{{inv * c1.x, inv * c1.y, inv * p}};
     s = store_row3<PREC, true>(emb, j, lane, y);
   } else {
     Row4 x{{c0.x * inv, c0.y * inv, c1.x * inv, c1.y * inv}};
@@ -531,7 +552,21 @@ __device__ __forceinline__ bf16x8 signed_onehot(uint2 in, uint2 out, uint32_t ta
   return __builtin_bit_cast(bf16x8, av);
 }
 
-// NS = 16-position steps covering the stride (1, 2 or 4).
+// A fragment of eight positions of a (window, coordinate) row of the
+// letter-sum form: byte L of `tab` is 0x40 or 0xc0 (bf16 +-2.0 = 4 w_m[L]) for
+// the letters, codes above 3 give 0.
+__device__ __forceinline__ bf16x8 weight_fragment(uint2 w, uint32_t tab) {
+  const uint32_t b0 = __builtin_amdgcn_perm(0u, tab, clamp_codes(w.x));
+  const uint32_t b1 = __builtin_amdgcn_perm(0u, tab, clamp_codes(w.y));
+  const u32x4 av{__builtin_amdgcn_perm(0u, b0, 0x010c000cu), __builtin_amdgcn_perm(0u, b0, 0x030c020cu),
+                 __builtin_amdgcn_perm(0u, b1, 0x010c000cu), __builtin_amdgcn_perm(0u, b1, 0x030c020cu)};
+  return __builtin_bit_cast(bf16x8, av);
+}
+
+// NS = 16-position steps covering the stride (1, 2 or 4).  RED: rows are
+// (window, letter-sum coordinate m) and the state is in that basis; the
+// entering letters' rows (+4 w_m) and the leaving ones' (-4 w_m) go through
+// the product separately, which returns 4 D.
 template <int PREC, bool RED, int NS>
 __global__ __launch_bounds__(256) void encode_reference_mfma_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,
@@ -581,16 +616,19 @@ __global__ __launch_bounds__(256) void encode_reference_mfma_kernel(
 
   // Re-anchor: the first window of the segment, directly, in FP64.
   double2 a0, a1;
-  direct_sum(ref + j0 * stride, N, phase64, lane, a0, a1);
+  direct_sum<RED>(ref + j0 * stride, N, phase64, lane, a0, a1);
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
   SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
   emit_window<PREC, RED>(j0, lane, N, c0, c1, emb, side, scale, norm2);
 
-  // A role: row lane & 31 = 4 w + L (window jc + w, letter L), positions
-  // 8 (lane >> 5) .. + 7 of each 16-position step
+  // A role: row lane & 31 = 4 w + L (window jc + w, letter L, or letter-sum
+  // coordinate L), positions 8 (lane >> 5) .. + 7 of each 16-position step
   const int aw = (lane & 31) >> 2, aL = lane & 3;
-  const uint32_t tab = 0x40u << (8 * aL);
+  const uint32_t tab = RED ? (aL == 0 ? 0x40404040u : aL == 1 ? 0xc0c04040u
+                              : aL == 2 ? 0xc040c040u : 0x40c0c040u)
+                           : 0x40u << (8 * aL);
+  const float dscale = RED ? 0.25f : 0.5f;  // the product returns 4 D (RED) or 2 D
   float(*db)[64][4] = dbuf[wv];
   for (int64_t jc = j0; jc < j1 - 1; jc += 8) {
     f32x16 acc[2] = {f32x16{}, f32x16{}};
@@ -598,16 +636,25 @@ __global__ __launch_bounds__(256) void encode_reference_mfma_kernel(
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       const int q0 = 16 * t + 8 * (lane >> 5);
-      bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+      bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u}), ao = a;
       if (q0 < stride) {
         uint2 lo, li;
         letters8_pair(ref, sw + q0, sw + N + q0, len, lo, li);
-        a = signed_onehot(li, lo, tab);
+        if constexpr (RED) {
+          a = weight_fragment(li, tab);
+          ao = weight_fragment(lo, tab ^ 0x80808080u);
+        } else {
+          a = signed_onehot(li, lo, tab);
+        }
       }
 #pragma unroll
       for (int pt = 2; pt >= 0; --pt) {
         acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t][pt][0], acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t][pt][1], acc[1], 0, 0, 0);
+        if constexpr (RED) {
+          acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ao, b[t][pt][0], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ao, b[t][pt][1], acc[1], 0, 0, 0);
+        }
       }
     }
     // D rows 8 g + 4 (lane >> 5) + L: window 2 g + (lane >> 5), letter L
@@ -620,11 +667,12 @@ __global__ __launch_bounds__(256) void encode_reference_mfma_kernel(
     __builtin_amdgcn_wave_barrier();
     const int nw = (int)min<int64_t>(8, j1 - 1 - jc);
     for (int w = 0; w < nw; ++w) {
-      // letters 2h, 2h+1 of the real parts (column 2k) and imaginary parts (2k+1)
+      // rows 2h, 2h+1 (letters or coordinates) of the real parts (column 2k)
+      // and imaginary parts (2k+1)
       const float* dre = &db[w][2 * k][2 * h];
       const float* dim = &db[w][2 * k + 1][2 * h];
-      c0 = make_float2(fmaf(0.5f, dre[0], c0.x), fmaf(0.5f, dim[0], c0.y));
-      c1 = make_float2(fmaf(0.5f, dre[1], c1.x), fmaf(0.5f, dim[1], c1.y));
+      c0 = make_float2(fmaf(dscale, dre[0], c0.x), fmaf(dscale, dim[0], c0.y));
+      c1 = make_float2(fmaf(dscale, dre[1], c1.x), fmaf(dscale, dim[1], c1.y));
       c0 = cmul(c0, rot);
       c1 = cmul(c1, rot);
       emit_window<PREC, RED>(jc + w + 1, lane, N, c0, c1, emb, side, scale, norm2);
@@ -649,10 +697,11 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
       tq[v] = make_float2((float)e.x, (float)e.y);
     }
   }
-  if (threadIdx.x < 10) ltab[threadIdx.x / 5][threadIdx.x % 5] = letter_mul_entry(threadIdx.x / 5, threadIdx.x % 5);
+  if (threadIdx.x < 10)
+    ltab[threadIdx.x / 5][threadIdx.x % 5] = letter_mul_entry<RED>(threadIdx.x / 5, threadIdx.x % 5);
   if (threadIdx.x < 50) {
     const int hh = threadIdx.x / 25, e = threadIdx.x % 25;
-    ptab[hh][e] = letter_pair_entry(hh, e / 5, e % 5);
+    ptab[hh][e] = letter_pair_entry<RED>(hh, e / 5, e % 5);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -666,7 +715,7 @@ __global__ __launch_bounds__(256) void encode_reference_kernel(
 
   // Re-anchor: the first window of the segment, directly, in FP64.
   double2 a0, a1;
-  direct_sum(ref + j0 * stride, N, phase64, lane, a0, a1);
+  direct_sum<RED>(ref + j0 * stride, N, phase64, lane, a0, a1);
   float2 c0 = make_float2((float)a0.x, (float)a0.y);
   float2 c1 = make_float2((float)a1.x, (float)a1.y);
   SideBuf side{j0, 0, 0.f, 0.f, PREC == RM_FP8_E4M3 ? scale + W : nullptr, 0.f};
