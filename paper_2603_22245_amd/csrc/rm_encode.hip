@@ -572,7 +572,9 @@ __global__ __launch_bounds__(256) void encode_reference_mfma_kernel(
     const uint8_t* __restrict__ ref, int64_t W, int N, int stride, int64_t seg_len, int64_t n_seg,
     const double2* __restrict__ phase64, void* __restrict__ emb, float* __restrict__ scale,
     float* __restrict__ norm2) {
-  __shared__ float dbuf[4][8][64][4];  // per wavefront: D of 8 windows [w][column][letter], doubled
+  // per wavefront: D of 8 windows [w][column][letter, or coordinate (RED)],
+  // times 2 (letters) or 4 (RED)
+  __shared__ float dbuf[4][8][64][4];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t seg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
