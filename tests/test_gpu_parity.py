@@ -300,6 +300,28 @@ def _check_candidates(idx, score, F, tol, absolute=False):
     return frac
 
 
+@pytest.mark.parametrize("reduced", [False, True])
+def test_block_rolling_drift_over_long_segments(reduced):
+    """65,536 starts per FP64 re-anchor at stride 4 (block sums on the matrix
+    cores, in the letter basis or the letter-sum basis): the FP32 recurrence's
+    error after the longest segment stays far below FP16 rounding of a unit
+    vector, and the next segment starts re-anchored."""
+    torch = torch_cuda()
+    N, stride = 150, 4
+    ref = synth.make_reference(4 * 70_000 + N, seed=9, uniform=True)
+    index = _build(ref, "fp32", window_len=N, stride=stride, reanchor=65_536, reduced=reduced)
+    torch.cuda.synchronize()
+    got = emb_to_complex(index, torch)
+    Cn, _ = oracle_windows(ref, N, stride)
+    Cn = stored_form(Cn, index)
+    err = np.abs(got - Cn).max(axis=1)
+    first, last = err[:1000].max(), err[64_000:65_536].max()
+    print(f"stride {stride} reduced={reduced}: max |d| first 1000 starts {first:.2e}, "
+          f"starts 64000-65535 {last:.2e}, start 65536 {err[65_536]:.2e}")
+    assert last < 2e-4
+    assert err[65_536] < 1e-5                               # re-anchored
+
+
 @pytest.mark.parametrize("precision,k_fetch,reduced", [
     ("fp32", 8, None), ("fp16", 8, None), ("fp16", 16, None), ("fp16", 32, None), ("fp8", 16, None),
     ("fp8", 32, None), ("fp32", 32, None), ("fp16", 16, False), ("fp16", 32, False),
